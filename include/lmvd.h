@@ -1,0 +1,202 @@
+/*
+ * lmvd.h -- C ABI of the MI355X library for one explicit RK2 substep of the
+ * pseudospectral low-Mach, variable-density method of Reuter, Oliver & Moser
+ * ("A pseudospectral method for direct numerical simulation of low-Mach,
+ * variable-density, turbulent flows").
+ *
+ * The operation (Section 4, "Time advance", Algorithm time_advanceDNS): given
+ * the state S = (phi2, Omega2, z, <m>1, <m>3) at stage s, the right-hand sides
+ * stored from the previous stage, and the z history, apply one substep
+ * s -> s+1:
+ *   1. finalize m^d (eqs. phi_poisson, md_recon, potential-matching rows of
+ *      eq. bc_both);
+ *   2. evaluate R_z (Section 2.1) and the BDF-like guess of dz/dt
+ *      (eq. dzdt_guesses, beta^n and beta' of Appendix A);
+ *   3. k_f fixed-point iterations z_t^k = L(z) z_t^{k-1} + R_z (eq. y_k,
+ *      Section 3.2), L applied matrix-free (Section 4.3), then m^c
+ *      (eqs. COM_fourier, CF_fourier, mc_recon, mc_mean);
+ *   4. rho = f(z) (equation of state of Section 5);
+ *   5. RHS of Omega2, phi2 (eqs. om, phi, with the body force -rho g delta_i2)
+ *      and of <m>1, <m>3 (eq. mean_m1m3);
+ *   6. explicit midpoint RK2, low-storage form:
+ *      stage n:  X' = X^n + dt/2 R^n;   stage ':  X^{n+1} = X' + dt (R' - R^n/2).
+ *
+ * Discretisation: Fourier in x1, x3 with the Nyquist modes excluded (eq.
+ * disc_f), nonlinear products on the 3/2-rule M1 x M3 grid; B-splines of
+ * order p (B) and p+1 (B*, for m2) on clamped knots in x2 (Appendix C),
+ * collocated at Greville points; Dirichlet rows for phi2, Omega2, Neumann
+ * rows for z, <m>1, <m>3, Robin (potential-matching) rows for m2, and
+ * <m2>(+L2/2) = 0 (Section 4.5).
+ *
+ * Array layout.  A spectral field ("S-field") is complex128 (interleaved
+ * re, im doubles), shape [ny][N3-1][N1/2], index [j][n_idx][l], l fastest:
+ * ny = n2 for fields in B, n2+1 for fields in B*; l = 0..N1/2-1; n_idx runs
+ * over n = 0..N3/2-1 then n = -(N3/2-1)..-1.  The l = 0 column must be
+ * Hermitian in n (f_{0,-n} = conj f_{0,n}) and is kept so.  The plane means
+ * <m>1, <m>3 and their RHS are real double [n2].  The (0,0) entries of phi2
+ * and Omega2 are ignored on input and their RHS are written as zero.
+ *
+ * Ownership.  Every state, output and workspace buffer is device memory owned
+ * by the caller.  A plan owns only its constant tables.  lmvd_substep
+ * allocates nothing, does not synchronise the host and only enqueues work on
+ * the given stream.
+ *
+ * Errors.  Every entry point returns an lmvd_status; no exceptions cross
+ * the ABI.  LMVD_EINVAL: bad configuration, null or misaligned (not 16-byte)
+ * pointer, or a bad argument value.  LMVD_EUNSUPPORTED: a grid size outside
+ * what the kernels handle (M1/2 and M3 must be products of 2s and 3s with
+ * M3 <= 1024 and M1/2 <= 768, N1/2 <= M1/2, N3-1 <= M3, order <= 9).  LMVD_ENOMEM:
+ * host or device allocation failed in lmvd_plan_create.  LMVD_EHIP: a HIP
+ * call failed.  LMVD_ENUMERIC: a factorisation without pivoting met a
+ * near-zero pivot at plan creation.
+ */
+#ifndef LMVD_H
+#define LMVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lmvd_plan_s* lmvd_plan;
+
+typedef enum {
+  LMVD_OK = 0,
+  LMVD_EINVAL = -1,
+  LMVD_ENOMEM = -2,
+  LMVD_EHIP = -3,
+  LMVD_EUNSUPPORTED = -4,
+  LMVD_ENUMERIC = -5
+} lmvd_status;
+
+/* Problem definition.  Symbols follow the paper. */
+typedef struct {
+  int32_t n1, n3;        /* Fourier modes, even; retained |l| <= n1/2-1, |n| <= n3/2-1 (eq. disc_f) */
+  int32_t n2;            /* number of B coefficients (order-p B-splines); m2 uses n2+1 of order p+1 */
+  int32_t order;         /* p (App. C); 3 <= p <= 9                                                  */
+  int32_t m1, m3;        /* physical x1, x3 grid; 3/2 rule: m = 3n/2; m1 >= n1, m3 >= n3            */
+  double L1, L2, L3;     /* domain [0,L1] x [-L2/2, L2/2] x [0,L3] (Section 4)                        */
+  const double* breakpoints; /* host array of n2-order+2 strictly increasing values, ends -+L2/2     */
+  double dt;             /* time step (fixed per plan: the BDF-like guesses assume a uniform dt)      */
+  double mu;             /* dynamic viscosity, constant                                               */
+  double rhoD;           /* rho D_z, constant                                                         */
+  double g;              /* gravity along -x2 (body force -rho g delta_i2)                           */
+  double rho_l, rho_h;   /* light / heavy density of the mixture EOS rho = rl rh / (rh - (rh - rl) z) */
+  double beta_n, beta_p; /* free parameters of the BDF-like guesses (paper: 0, -4)                    */
+  int32_t kf;            /* default number of fixed-point iterations                                  */
+  int32_t plane_batch;   /* y-planes per physical-space batch (0 = all planes at once)               */
+} lmvd_config;
+
+/* Arguments of one substep.  All pointers are device pointers.  Pointers that
+ * are optional may be NULL. */
+typedef struct {
+  int32_t stage;          /* 0 = stage n, 1 = stage ' (Section 3.2)                                    */
+  int32_t kf;             /* iterations for this call; -1 = the plan's kf                               */
+  int32_t guess_mode;     /* 0 = BDF-like guess from z_hist; 1 = zero guess (startup without history)  */
+  /* state at stage s (inputs) */
+  const void* phi2;       /* S-field (B)                                                               */
+  const void* omega2;     /* S-field (B)                                                               */
+  const void* z;          /* S-field (B)                                                               */
+  const double* m1bar;    /* [n2]                                                                       */
+  const double* m3bar;    /* [n2]                                                                       */
+  /* state at stage s+1 (outputs).  phi2_out, omega2_out, m1bar_out, m3bar_out
+   * may alias their inputs; z_out must not alias z (z^s is read to the end). */
+  void* phi2_out;
+  void* omega2_out;
+  void* z_out;
+  double* m1bar_out;
+  double* m3bar_out;
+  /* stage ' only: data stored at stage n */
+  const void* rhs_phi2_prev;
+  const void* rhs_omega2_prev;
+  const void* zt_prev;    /* z_t^{n, k_f}                                                              */
+  const double* rhs_m1_prev;
+  const double* rhs_m3_prev;
+  /* this stage's RHS and z_t^{s, k_f} (outputs; required at stage n, optional at stage ') */
+  void* rhs_phi2;
+  void* rhs_omega2;
+  void* zt;
+  double* rhs_m1;
+  double* rhs_m3;
+  /* z coefficients of the previous three stages, most recent first
+   * (stage n: z^{n-1,'}, z^{n-1}, z^{n-2,'}; stage ': z^n, z^{n-1,'}, z^{n-1});
+   * read only with guess_mode 0.  z_out may alias z_hist[2]. */
+  const void* z_hist[3];
+  /* optional diagnostics: m^d = (m1 in B, m2 in B*, m3 in B), m^c likewise */
+  void* md[3];
+  void* mc[3];
+} lmvd_substep_args;
+
+const char* lmvd_status_string(lmvd_status s);
+
+/* Build the plan: host tables (knots, Greville points, collocation and
+ * derivative matrices, no-pivot LU of the shared projections, FFT twiddles)
+ * and their upload to the current device.  Host-synchronous. */
+lmvd_status lmvd_plan_create(const lmvd_config* cfg, lmvd_plan* out);
+lmvd_status lmvd_plan_destroy(lmvd_plan plan);
+
+/* Element counts of an S-field in B (n2 rows) and in B* (n2+1 rows), and the
+ * workspace size in bytes that lmvd_substep needs (256-byte aligned pointer). */
+lmvd_status lmvd_sizes(lmvd_plan plan, size_t* sfield_elems, size_t* sfield_star_elems,
+                       size_t* workspace_bytes);
+
+/* One substep (Algorithm time_advanceDNS) on `stream` (a hipStream_t; NULL =
+ * the null stream).  Asynchronous.  Not reentrant: one plan must not run on two
+ * streams at once, and concurrent calls must use distinct workspaces. */
+lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* args, void* workspace,
+                         void* stream);
+
+/* ---- operator entry points (same conventions), one per stage of the path ----
+ * They expose the steps of the substep individually for verification. */
+
+/* Inverse transform (eq. disc_f at the 3/2 grid): spectral values at the
+ * Greville points (S-field of values, n2 rows) -> real physical field
+ * double [n2][m3][m1], index [j][b][a] at x = a L1/m1, z = b L3/m3. */
+lmvd_status lmvd_to_physical(lmvd_plan plan, const void* values, double* phys,
+                             void* workspace, void* stream);
+/* Forward transform: physical double [n2][m3][m1] -> values on the retained
+ * modes, (1/(m1 m3)) sum u e^{-i(k1 x + k3 z)}. */
+lmvd_status lmvd_to_spectral(lmvd_plan plan, const double* phys, void* values,
+                             void* workspace, void* stream);
+/* Projection values -> B coefficients: kind 0 = interpolation, 1 = Dirichlet
+ * end rows, 2 = Neumann end rows (the end values are replaced by zero). */
+lmvd_status lmvd_project(lmvd_plan plan, int32_t kind, const void* values, void* coeffs,
+                         void* stream);
+/* Evaluation B coefficients -> values at the Greville points: deriv 0, 1, 2.
+ * With star = 1 the input is a B* S-field (n2+1 rows) and deriv must be 0. */
+lmvd_status lmvd_evaluate(lmvd_plan plan, int32_t deriv, int32_t star, const void* coeffs,
+                          void* values, void* stream);
+/* m^d from (phi2, Omega2, <m>1, <m>3): writes m1 (B), m2 (B*), m3 (B). */
+lmvd_status lmvd_md(lmvd_plan plan, const void* phi2, const void* omega2,
+                    const double* m1bar, const double* m3bar, void* m1, void* m2, void* m3,
+                    void* workspace, void* stream);
+/* m^c from the B coefficients of rho_t: writes m1 (B), m2 (B*), m3 (B). */
+lmvd_status lmvd_mc(lmvd_plan plan, const void* rhot, void* m1, void* m2, void* m3,
+                    void* workspace, void* stream);
+
+/* Timing hook for measurements: while active, every launch of one kernel
+ * class is bracketed by two HIP events recorded on the stream it is launched
+ * on.  Classes: 0 evaluation at the Greville points + inverse z-FFT,
+ * 1 x-pass (inverse x-FFT, pointwise products, forward x-FFT), 2 forward
+ * z-FFT + truncation, 3 shared-LU projection, 4 per-wavenumber A(k) solve,
+ * 5 RHS assembly + projection + RK2.  lmvd_profile_start creates
+ * `max_launches` event pairs on the host (launches beyond that are not
+ * timed); lmvd_profile_stop waits for the events and returns the summed
+ * elapsed milliseconds, the number of timed launches and their algorithmic
+ * HBM bytes (each input read once, each output written once). */
+lmvd_status lmvd_profile_start(lmvd_plan plan, int32_t cls, int32_t max_launches);
+lmvd_status lmvd_profile_stop(lmvd_plan plan, double* total_ms, int64_t* launches, double* alg_bytes);
+
+/* Host-only view of the plan's y-discretisation (for inspection; no GPU use):
+ * Greville points tau [n2] and tau* [n2+1], and the dense matrices
+ * E_d (d = 0,1,2; n2 x n2, row-major) of the B-splines at tau.
+ * Any output pointer may be NULL. */
+lmvd_status lmvd_host_tables(const lmvd_config* cfg, double* tau, double* tau_star,
+                             double* E0, double* E1, double* E2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMVD_H */

@@ -1,0 +1,1443 @@
+// MI355X (gfx950) implementation of one explicit RK2 substep of the
+// low-Mach variable-density pseudospectral method (Algorithm
+// time_advanceDNS of Reuter, Oliver & Moser), behind the C ABI of lmvd.h.
+//
+// Data never leaves the plane-major spectral layout [j][n_idx][l]:
+//  * "column" work (banded y-operations per wavenumber pair) runs one thread
+//    per (l, n) column and sweeps j; neighbouring threads touch neighbouring
+//    l, so every access of a sweep is coalesced and no transpose is needed;
+//  * "plane" work (3/2-rule transforms and pointwise products) runs per
+//    y-plane in three kernels: evaluation at the Greville point + inverse
+//    z-FFT (k_eval_zinv), inverse x-FFT + products + forward x-FFT
+//    (k_xpass), forward z-FFT + truncation (k_zfwd).  Physical fields exist
+//    only in registers inside k_xpass.
+// Everything is float64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lmvd.h"
+#include "fft_lds.h"
+#include "plan_host.h"
+
+namespace lmvd {
+
+constexpr int kMaxIn = 13;
+constexpr int kMaxOut = 6;
+constexpr int kThreads = 256;
+constexpr int kZMaxE = 12;    // elements per thread in the z-FFT kernels
+constexpr int kXSlots = 3;    // complex slots per thread per line set in k_xpass
+constexpr int kNumEv = 4;     // E0, E1, E2 (B at tau), F0 (B* at tau)
+
+enum EvalKind { EV_E0 = 0, EV_E1 = 1, EV_E2 = 2, EV_F0 = 3, EV_LAP = 4, EV_IDENT = 5 };
+enum Mult { MU_ONE = 0, MU_IK1 = 1, MU_IK3 = 2, MU_K1K = 3, MU_K3K = 4 };
+enum Phase { PH_RZ = 0, PH_RHOT = 1, PH_L = 2, PH_VEL = 3, PH_FLUX = 4, PH_TOPHYS = 5, PH_FROMPHYS = 6 };
+enum Epi { EPI_STORE = 0, EPI_ADD = 1, EPI_ADD_ZUPDATE = 2 };
+
+struct DevPlan {
+  int n2, p, nl, nn, n3, m1, m3, hx;
+  double dt, mu, rhoD, g, rho_l, rho_h, inv_rlrh, drho;
+  // row tables
+  const int* ev_lo;        // [kNumEv][n2]
+  const double* ev_w;      // [kNumEv][n2][kMaxW]
+  const int* gs_lo;        // [2][n2+1]   G0, G1 at tau*
+  const double* gs_w;
+  const int* es_lo;        // [3][n2+1]   E*_0, E*_1, E*_2 at tau*
+  const double* es_w;
+  const double* dstar;     // [n2]
+  const double* lu_l;      // [3][n2][kMaxBand]
+  const double* lu_u;      // [3][n2][kMaxBand+1]
+  const double* lu_uinv;   // [3][n2]
+  const double* k1;        // [nl]
+  const double* k3;        // [nn]
+  FftDev fz, fx;
+  const double2* xtw;      // [hx] exp(-2 pi i k / m1)
+};
+
+struct EvalIn {
+  const double2* a;
+  const double2* b;
+  int kind;
+  int ma;
+  int mb;
+  int pad;
+};
+struct EvalArgs {
+  EvalIn in[kMaxIn];
+};
+struct OutPtrs {
+  double2* v[kMaxOut];
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double2 fma2(double s, double2 a, double2 acc) {
+  return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
+}
+__device__ __forceinline__ double2 times_i(double2 z) { return make_double2(-z.y, z.x); }
+
+// spectral multiplier of a column
+__device__ __forceinline__ double2 apply_mult(int m, double k1, double k3, double2 v) {
+  switch (m) {
+    case MU_IK1: return make_double2(-k1 * v.y, k1 * v.x);
+    case MU_IK3: return make_double2(-k3 * v.y, k3 * v.x);
+    case MU_K1K:
+    case MU_K3K: {
+      double ksq = k1 * k1 + k3 * k3;
+      if (ksq == 0.0) return zero2();
+      double s = ((m == MU_K1K) ? k1 : k3) / sqrt(ksq);
+      return cscale(v, s);
+    }
+    default: return v;
+  }
+}
+
+// value at tau_j of column (ni, l) of a spectral coefficient array
+__device__ __forceinline__ double2 eval_at(const DevPlan& P, int kind, const double2* __restrict__ src,
+                                           int j, size_t col, size_t ncol, double ksq) {
+  if (kind == EV_IDENT) return src[size_t(j) * ncol + col];
+  const int rows = (kind == EV_F0) ? P.n2 + 1 : P.n2;
+  const int kk = (kind == EV_LAP) ? EV_E2 : kind;
+  const int lo = P.ev_lo[kk * P.n2 + j];
+  const double* w = P.ev_w + (size_t(kk) * P.n2 + j) * kMaxW;
+  const double* w0 = P.ev_w + (size_t(EV_E0) * P.n2 + j) * kMaxW;
+  double2 acc = zero2(), acc0 = zero2();
+#pragma unroll
+  for (int q = 0; q < kMaxW; ++q) {
+    const int r = lo + q;
+    if (r < rows && (w[q] != 0.0 || (kind == EV_LAP && w0[q] != 0.0))) {
+      const double2 s = src[size_t(r) * ncol + col];
+      acc = fma2(w[q], s, acc);
+      if (kind == EV_LAP) acc0 = fma2(w0[q], s, acc0);
+    }
+  }
+  if (kind == EV_LAP) acc = make_double2(acc.x - ksq * acc0.x, acc.y - ksq * acc0.y);
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// plane kernel 1: evaluation at tau_j, spectral multiplier, inverse z-FFT
+// grid (ceil(nl/LG), planes, nin); output zbuf[f][jj][b][l]
+
+__global__ void __launch_bounds__(kThreads) k_eval_zinv(DevPlan P, EvalArgs A, double2* __restrict__ zbuf,
+                                                        int j0, int pb, int LG) {
+  extern __shared__ double2 lds[];
+  const int f = blockIdx.z, jj = blockIdx.y, j = j0 + jj, l0 = blockIdx.x * LG;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int M3 = P.m3, nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = M3 - nn;
+  const EvalIn in = A.in[f];
+  const size_t ncol = size_t(nn) * nl;
+  // zero the padded (dealiasing) positions
+  for (int idx = tid; idx < LG * pad; idx += nth) {
+    const int ll = idx % LG, q = idx / LG;
+    lds[ll * M3 + h3 + q] = zero2();
+  }
+  // retained modes
+  for (int idx = tid; idx < LG * nn; idx += nth) {
+    const int ll = idx % LG, ni = idx / LG, l = l0 + ll;
+    double2 v = zero2();
+    if (l < nl) {
+      const double k1 = P.k1[l], k3 = P.k3[ni];
+      const double ksq = k1 * k1 + k3 * k3;
+      const size_t col = size_t(ni) * nl + l;
+      v = apply_mult(in.ma, k1, k3, eval_at(P, in.kind, in.a, j, col, ncol, ksq));
+      if (in.b) {
+        const double2 w = apply_mult(in.mb, k1, k3, eval_at(P, in.kind, in.b, j, col, ncol, ksq));
+        v = cadd(v, w);
+      }
+    }
+    const int pos = (ni < h3) ? ni : ni + pad;
+    lds[ll * M3 + pos] = v;
+  }
+  __syncthreads();
+  fft_lines<1, kZMaxE>(lds, M3, LG, P.fz, tid, nth);
+  double2* out = zbuf + (size_t(f) * pb + jj) * size_t(M3) * nl;
+  for (int idx = tid; idx < LG * M3; idx += nth) {
+    const int ll = idx % LG, b = idx / LG;
+    if (l0 + ll < nl) out[size_t(b) * nl + l0 + ll] = lds[ll * M3 + b];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pointwise products on the physical grid
+
+template <int PH>
+struct Op;
+
+template <>
+struct Op<PH_RZ> {  // R_z = (1/rho)(-m^d . grad z + rho D lap z)
+  static constexpr int NIN = 8, NOUT = 1;
+  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
+    const double ir = (P.rho_h - P.drho * x[0]) * P.inv_rlrh;
+    y[0] = (P.rhoD * x[4] - (x[5] * x[1] + x[6] * x[2] + x[7] * x[3])) * ir;
+  }
+};
+template <>
+struct Op<PH_RHOT> {  // rho_t = f'(z) z_t = rho^2 (rh - rl)/(rl rh) z_t
+  static constexpr int NIN = 2, NOUT = 1;
+  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
+    const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x[0]);
+    y[0] = rho * rho * P.drho * P.inv_rlrh * x[1];
+  }
+};
+template <>
+struct Op<PH_L> {  // L z_t = -(1/rho) grad z . m^c
+  static constexpr int NIN = 7, NOUT = 1;
+  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
+    const double ir = (P.rho_h - P.drho * x[0]) * P.inv_rlrh;
+    y[0] = -(x[1] * x[4] + x[2] * x[5] + x[3] * x[6]) * ir;
+  }
+};
+template <>
+struct Op<PH_VEL> {  // u = m / rho, and rho
+  static constexpr int NIN = 4, NOUT = 4;
+  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
+    const double den = P.rho_h - P.drho * x[0];
+    const double ir = den * P.inv_rlrh;
+    y[0] = x[1] * ir;
+    y[1] = x[2] * ir;
+    y[2] = x[3] * ir;
+    y[3] = (P.rho_l * P.rho_h) / den;
+  }
+};
+template <>
+struct Op<PH_FLUX> {  // T_ij = -m_i m_j / rho + mu (d_j u_i + d_i u_j) - 2/3 mu theta delta_ij
+  static constexpr int NIN = 13, NOUT = 6;
+  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
+    const double ir = (P.rho_h - P.drho * x[0]) * P.inv_rlrh;
+    const double m1 = x[1], m2 = x[2], m3 = x[3];
+    const double* d = x + 4;  // d[3*i + j] = d u_i / d x_j
+    const double mu = P.mu;
+    const double th = (2.0 / 3.0) * mu * (d[0] + d[4] + d[8]);
+    y[0] = -m1 * m1 * ir + mu * (d[0] + d[0]) - th;
+    y[1] = -m1 * m2 * ir + mu * (d[1] + d[3]);
+    y[2] = -m1 * m3 * ir + mu * (d[2] + d[6]);
+    y[3] = -m2 * m2 * ir + mu * (d[4] + d[4]) - th;
+    y[4] = -m2 * m3 * ir + mu * (d[5] + d[7]);
+    y[5] = -m3 * m3 * ir + mu * (d[8] + d[8]) - th;
+  }
+};
+template <>
+struct Op<PH_TOPHYS> {
+  static constexpr int NIN = 1, NOUT = 0;
+  __device__ static void apply(const DevPlan&, const double*, double*) {}
+};
+template <>
+struct Op<PH_FROMPHYS> {
+  static constexpr int NIN = 0, NOUT = 1;
+  __device__ static void apply(const DevPlan&, const double*, double*) {}
+};
+
+// ---------------------------------------------------------------------------
+// plane kernel 2: per (plane, group of z lines): inverse real x-FFT of every
+// input (length m1 via a complex FFT of m1/2), products, forward real x-FFT
+// of every output.  grid (ceil(m3/BG), planes).
+
+template <int PH>
+__global__ void __launch_bounds__(kThreads) k_xpass(DevPlan P, const double2* __restrict__ zbuf,
+                                                    double2* __restrict__ obuf, int pb, int BG,
+                                                    double* phys_out, const double* phys_in, int j0) {
+  using O = Op<PH>;
+  constexpr int NIN = O::NIN, NOUT = O::NOUT;
+  constexpr int NINA = NIN > 0 ? NIN : 1, NOUTA = NOUT > 0 ? NOUT : 1;
+  extern __shared__ double2 lds[];
+  const int jj = blockIdx.y, b0 = blockIdx.x * BG;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int H = P.hx, nl = P.nl, M3 = P.m3, M1 = P.m1;
+  const int nlines = min(BG, M3 - b0);
+  const int nel = nlines * H;
+  double2 ph[NINA][kXSlots];
+  double2 res[NOUTA][kXSlots];
+
+#pragma unroll
+  for (int f = 0; f < NIN; ++f) {
+    const double2* X0 = zbuf + ((size_t(f) * pb + jj) * M3 + b0) * nl;
+    for (int idx = tid; idx < nel; idx += nth) {
+      const int line = idx / H, k = idx - line * H;
+      const double2* X = X0 + size_t(line) * nl;
+      const double2 a = (k < nl) ? X[k] : zero2();
+      const double2 c = (k > 0 && H - k < nl) ? cconj(X[H - k]) : zero2();
+      const double2 s = cadd(a, c), d = csub(a, c);
+      const double2 w = cconj(P.xtw[k]);  // exp(+2 pi i k / m1)
+      lds[idx] = cadd(s, times_i(cmul(w, d)));
+    }
+    __syncthreads();
+    fft_lines<1, 6>(lds, H, nlines, P.fx, tid, nth);
+#pragma unroll
+    for (int s = 0; s < kXSlots; ++s) {
+      const int idx = tid + s * nth;
+      ph[f][s] = (idx < nel) ? lds[idx] : zero2();
+    }
+    if constexpr (PH == PH_TOPHYS) {
+      double* dst = phys_out + (size_t(j0 + jj) * M3 + b0) * M1;
+#pragma unroll
+      for (int s = 0; s < kXSlots; ++s) {
+        const int idx = tid + s * nth;
+        if (idx < nel) {
+          const int line = idx / H, m = idx - line * H;
+          dst[size_t(line) * M1 + 2 * m] = ph[f][s].x;
+          dst[size_t(line) * M1 + 2 * m + 1] = ph[f][s].y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (PH == PH_FROMPHYS) {
+    const double* src = phys_in + (size_t(j0 + jj) * M3 + b0) * M1;
+#pragma unroll
+    for (int s = 0; s < kXSlots; ++s) {
+      const int idx = tid + s * nth;
+      if (idx < nel) {
+        const int line = idx / H, m = idx - line * H;
+        res[0][s] = make_double2(src[size_t(line) * M1 + 2 * m], src[size_t(line) * M1 + 2 * m + 1]);
+      }
+    }
+  } else if constexpr (NOUT > 0) {
+#pragma unroll
+    for (int s = 0; s < kXSlots; ++s) {
+      double xi[NINA], yo[NOUTA], xj[NINA], yp[NOUTA];
+#pragma unroll
+      for (int f = 0; f < NIN; ++f) {
+        xi[f] = ph[f][s].x;
+        xj[f] = ph[f][s].y;
+      }
+      O::apply(P, xi, yo);
+      O::apply(P, xj, yp);
+#pragma unroll
+      for (int g = 0; g < NOUT; ++g) res[g][s] = make_double2(yo[g], yp[g]);
+    }
+  }
+  const double scale = 1.0 / (double(M1) * double(M3));
+#pragma unroll
+  for (int g = 0; g < NOUT; ++g) {
+#pragma unroll
+    for (int s = 0; s < kXSlots; ++s) {
+      const int idx = tid + s * nth;
+      if (idx < nel) lds[idx] = res[g][s];
+    }
+    __syncthreads();
+    fft_lines<-1, 6>(lds, H, nlines, P.fx, tid, nth);
+    double2* Y0 = obuf + ((size_t(g) * pb + jj) * M3 + b0) * nl;
+    for (int idx = tid; idx < nlines * nl; idx += nth) {
+      const int line = idx / nl, l = idx - line * nl;
+      const double2 Yk = lds[line * H + l];
+      const double2 Yc = cconj(lds[line * H + ((H - l) % H)]);
+      const double2 E = cscale(cadd(Yk, Yc), 0.5);
+      const double2 D = csub(Yk, Yc);
+      const double2 O = make_double2(0.5 * D.y, -0.5 * D.x);  // (Yk - conj Y_{H-k}) / (2i)
+      const double2 Xt = cadd(E, cmul(P.xtw[l], O));
+      Y0[size_t(line) * nl + l] = cscale(Xt, scale);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plane kernel 3: forward z-FFT, keep the retained n.  grid (ceil(nl/LG), planes, nout)
+
+__global__ void __launch_bounds__(kThreads) k_zfwd(DevPlan P, const double2* __restrict__ obuf, OutPtrs V,
+                                                   int j0, int pb, int LG) {
+  extern __shared__ double2 lds[];
+  const int g = blockIdx.z, jj = blockIdx.y, l0 = blockIdx.x * LG;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int M3 = P.m3, nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = M3 - nn;
+  const double2* in = obuf + (size_t(g) * pb + jj) * size_t(M3) * nl;
+  for (int idx = tid; idx < LG * M3; idx += nth) {
+    const int ll = idx % LG, b = idx / LG;
+    lds[ll * M3 + b] = (l0 + ll < nl) ? in[size_t(b) * nl + l0 + ll] : zero2();
+  }
+  __syncthreads();
+  fft_lines<-1, kZMaxE>(lds, M3, LG, P.fz, tid, nth);
+  double2* out = V.v[g] + size_t(j0 + jj) * nn * nl;
+  for (int idx = tid; idx < LG * nn; idx += nth) {
+    const int ll = idx % LG, ni = idx / LG;
+    if (l0 + ll < nl) out[size_t(ni) * nl + l0 + ll] = lds[ll * M3 + ((ni < h3) ? ni : ni + pad)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column kernel: projection values -> B coefficients with a shared no-pivot LU
+// (kind 0 interpolation, 1 Dirichlet rows, 2 Neumann rows).  One thread per
+// column; forward sweep stores L^{-1} b in `out`, backward sweep overwrites it.
+
+template <int EPI>
+__global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const double2* in, double2* out,
+                                                   const double2* __restrict__ add, const double2* __restrict__ z,
+                                                   const double2* __restrict__ zt_prev, double2* __restrict__ z_out,
+                                                   double2* __restrict__ zt_copy, int stage, int ncol) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int n2 = P.n2;
+  const double* L = P.lu_l + size_t(kind) * n2 * kMaxBand;
+  const double* U = P.lu_u + size_t(kind) * n2 * (kMaxBand + 1);
+  const double* Ui = P.lu_uinv + size_t(kind) * n2;
+  double2 ring[kMaxBand];
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+  for (int i = 0; i < n2; ++i) {
+    double2 b = (kind != 0 && (i == 0 || i == n2 - 1)) ? zero2() : in[size_t(i) * ncol + c];
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) b = fma2(-L[i * kMaxBand + m], ring[m], b);
+    out[size_t(i) * ncol + c] = b;
+#pragma unroll
+    for (int m = kMaxBand - 1; m > 0; --m) ring[m] = ring[m - 1];
+    ring[0] = b;
+  }
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+  for (int i = n2 - 1; i >= 0; --i) {
+    double2 y = out[size_t(i) * ncol + c];
+#pragma unroll
+    for (int q = 0; q < kMaxBand; ++q) y = fma2(-U[i * (kMaxBand + 1) + q + 1], ring[q], y);
+    const double2 x = cscale(y, Ui[i]);
+#pragma unroll
+    for (int q = kMaxBand - 1; q > 0; --q) ring[q] = ring[q - 1];
+    ring[0] = x;
+    const size_t e = size_t(i) * ncol + c;
+    if (EPI == EPI_STORE) {
+      out[e] = x;
+    } else {
+      const double2 zt = cadd(x, add[e]);
+      out[e] = zt;
+      if (EPI == EPI_ADD_ZUPDATE) {
+        const double2 z0 = z[e];
+        double2 zn;
+        if (stage == 0) {
+          zn = fma2(0.5 * P.dt, zt, z0);
+        } else {
+          const double2 dz = make_double2(zt.x - 0.5 * zt_prev[e].x, zt.y - 0.5 * zt_prev[e].y);
+          zn = fma2(P.dt, dz, z0);
+        }
+        z_out[e] = zn;
+        if (zt_copy) zt_copy[e] = zt;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column kernel: the per-wavenumber systems A(k) c = r,
+//   A(k) = E*_2 - k^2 E*_0 at the interior tau*, Robin rows
+//   k m2 - m2' = 0 (bottom), k m2 + m2' = 0 (top) (eqs. phi_poisson, bc_both),
+// LU without pivoting formed on the fly in the forward sweep; the U rows go to
+// a scratch array, read back by the backward sweep.  One thread solves the
+// pair (l, n), (l, -n), which share k.  The backward sweep emits the
+// reconstructions:
+//   MODE 0 (m^d):  r = G0 phi2;      m1 = (i k1 D*c - i k3 Omega2)/k^2,
+//                                    m3 = (i k3 D*c + i k1 Omega2)/k^2  (eq. md_recon)
+//   MODE 1 (m^c):  r = -G1 rho_t;    m_par = (i/k)(rho_t + D*c)        (eqs. COM_fourier, CF_fourier)
+// The (0,0) thread handles the plane mean: m^d = (<m>1, 0, <m>3); for m^c
+// D*c = -<rho_t>, c_top = 0 (eq. mc_mean with <m2>(+L2/2) = 0).
+
+template <int MODE, int LO, int UP>
+__global__ void __launch_bounds__(kThreads) k_solveA(DevPlan P, const double2* __restrict__ in1,
+                                                     const double2* __restrict__ in2, const double* __restrict__ m1bar,
+                                                     const double* __restrict__ m3bar, double2* __restrict__ c2,
+                                                     double2* __restrict__ o1, double2* __restrict__ o3,
+                                                     double* __restrict__ uscr) {
+  const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
+  const int half = (nn + 1) / 2;
+  const int npairs = nl * half;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= npairs) return;
+  const int l = t % nl, pp = t / nl;
+  const size_t ncol = size_t(nn) * nl;
+  const size_t cA = size_t(pp) * nl + l;
+  const bool two = pp > 0;
+  const size_t cB = two ? size_t(nn - pp) * nl + l : cA;
+  const double k1 = P.k1[l], k3 = P.k3[pp];
+  const double ksq = k1 * k1 + k3 * k3;
+  if (ksq == 0.0) {
+    // plane mean
+    if (MODE == 0) {
+      for (int i = 0; i < N; ++i) c2[size_t(i) * ncol] = zero2();
+      for (int i = 0; i < n2; ++i) {
+        o1[size_t(i) * ncol] = make_double2(m1bar[i], 0.0);
+        o3[size_t(i) * ncol] = make_double2(m3bar[i], 0.0);
+      }
+    } else {
+      double2 c = zero2();
+      c2[size_t(n2) * ncol] = c;
+      for (int i = n2 - 1; i >= 0; --i) {
+        const double2 r = in1[size_t(i) * ncol];
+        c = make_double2(c.x + r.x / P.dstar[i], c.y + r.y / P.dstar[i]);
+        c2[size_t(i) * ncol] = c;
+        o1[size_t(i) * ncol] = zero2();
+      }
+    }
+    return;
+  }
+  const double k = sqrt(ksq);
+  constexpr int W = LO + UP + 1;
+  double uw[LO][UP];       // U rows i-1..i-LO, entries for columns r+1..r+UP
+  double uinvw[LO];
+  double2 ya[LO], yb[LO];
+#pragma unroll
+  for (int m = 0; m < LO; ++m) {
+    uinvw[m] = 0.0;
+    ya[m] = yb[m] = zero2();
+#pragma unroll
+    for (int q = 0; q < UP; ++q) uw[m][q] = 0.0;
+  }
+  const int* elo = P.es_lo;
+  const double* ew = P.es_w;
+  const int Ns = n2 + 1;
+  const double* Gw = P.gs_w + (MODE == 0 ? 0 : size_t(Ns) * kMaxW);
+  const int* Glo = P.gs_lo + (MODE == 0 ? 0 : Ns);
+  const double gsign = (MODE == 0) ? 1.0 : -1.0;
+  const size_t ustride = size_t(npairs);
+  for (int i = 0; i < N; ++i) {
+    double a[W];
+    const int lo0 = elo[i], lo1 = elo[Ns + i], lo2 = elo[2 * Ns + i];
+    const bool robin = (i == 0 || i == n2);
+    const double sg = (i == 0) ? -1.0 : 1.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int col = i - LO + w;
+      const int q0 = col - lo0, q1 = col - lo1, q2 = col - lo2;
+      const double e0 = (q0 >= 0 && q0 < kMaxW) ? ew[(size_t(i)) * kMaxW + q0] : 0.0;
+      if (robin) {
+        const double e1 = (q1 >= 0 && q1 < kMaxW) ? ew[(size_t(Ns) + i) * kMaxW + q1] : 0.0;
+        a[w] = k * e0 + sg * e1;
+      } else {
+        const double e2 = (q2 >= 0 && q2 < kMaxW) ? ew[(size_t(2 * Ns) + i) * kMaxW + q2] : 0.0;
+        a[w] = e2 - ksq * e0;
+      }
+    }
+    double2 ra = zero2(), rb = zero2();
+    if (!robin) {
+      const int glo = Glo[i];
+      const double* gw = Gw + size_t(i) * kMaxW;
+#pragma unroll
+      for (int q = 0; q < kMaxW; ++q) {
+        const int r = glo + q;
+        if (gw[q] != 0.0 && r < n2) {
+          ra = fma2(gsign * gw[q], in1[size_t(r) * ncol + cA], ra);
+          if (two) rb = fma2(gsign * gw[q], in1[size_t(r) * ncol + cB], rb);
+        }
+      }
+    }
+    // eliminate columns i-LO .. i-1 with the stored pivot rows
+#pragma unroll
+    for (int m = LO; m >= 1; --m) {
+      const double lm = a[LO - m] * uinvw[m - 1];
+#pragma unroll
+      for (int q = 1; q <= UP; ++q) {
+        if (LO - m + q < W) a[LO - m + q] -= lm * uw[m - 1][q - 1];
+      }
+      ra = fma2(-lm, ya[m - 1], ra);
+      rb = fma2(-lm, yb[m - 1], rb);
+    }
+    const double uinv = 1.0 / a[LO];
+    double* us = uscr + size_t(i) * (UP + 1) * ustride + t;
+    us[0] = uinv;
+#pragma unroll
+    for (int q = 1; q <= UP; ++q) us[q * ustride] = a[LO + q];
+    c2[size_t(i) * ncol + cA] = ra;
+    if (two) c2[size_t(i) * ncol + cB] = rb;
+#pragma unroll
+    for (int m = LO - 1; m > 0; --m) {
+      uinvw[m] = uinvw[m - 1];
+      ya[m] = ya[m - 1];
+      yb[m] = yb[m - 1];
+#pragma unroll
+      for (int q = 0; q < UP; ++q) uw[m][q] = uw[m - 1][q];
+    }
+    uinvw[0] = uinv;
+    ya[0] = ra;
+    yb[0] = rb;
+#pragma unroll
+    for (int q = 0; q < UP; ++q) uw[0][q] = a[LO + 1 + q];
+  }
+  // backward sweep
+  double2 xa[UP], xb[UP];
+#pragma unroll
+  for (int q = 0; q < UP; ++q) xa[q] = xb[q] = zero2();
+  const double ik = 1.0 / k, iksq = 1.0 / ksq;
+  for (int i = N - 1; i >= 0; --i) {
+    const double* us = uscr + size_t(i) * (UP + 1) * ustride + t;
+    double2 ya_ = c2[size_t(i) * ncol + cA];
+    double2 yb_ = two ? c2[size_t(i) * ncol + cB] : zero2();
+#pragma unroll
+    for (int q = 1; q <= UP; ++q) {
+      const double u = us[q * ustride];
+      ya_ = fma2(-u, xa[q - 1], ya_);
+      yb_ = fma2(-u, xb[q - 1], yb_);
+    }
+    const double uinv = us[0];
+    const double2 xA = cscale(ya_, uinv), xB = cscale(yb_, uinv);
+    c2[size_t(i) * ncol + cA] = xA;
+    if (two) c2[size_t(i) * ncol + cB] = xB;
+    if (i < n2) {
+      const double ds = P.dstar[i];
+      // (D* c)_i = dstar_i (c_{i+1} - c_i); c_{i+1} = xa[0] before the shift
+      const double2 DA = make_double2(ds * (xa[0].x - xA.x), ds * (xa[0].y - xA.y));
+      const double2 DB = make_double2(ds * (xb[0].x - xB.x), ds * (xb[0].y - xB.y));
+      const size_t eA = size_t(i) * ncol + cA, eB = size_t(i) * ncol + cB;
+      if (MODE == 0) {
+        const double2 OA = in2[eA];
+        // (i k1 D - i k3 Omega)/k^2, (i k3 D + i k1 Omega)/k^2
+        o1[eA] = cscale(times_i(make_double2(k1 * DA.x - k3 * OA.x, k1 * DA.y - k3 * OA.y)), iksq);
+        o3[eA] = cscale(times_i(make_double2(k3 * DA.x + k1 * OA.x, k3 * DA.y + k1 * OA.y)), iksq);
+        if (two) {
+          const double2 OB = in2[eB];
+          const double k3b = -k3;
+          o1[eB] = cscale(times_i(make_double2(k1 * DB.x - k3b * OB.x, k1 * DB.y - k3b * OB.y)), iksq);
+          o3[eB] = cscale(times_i(make_double2(k3b * DB.x + k1 * OB.x, k3b * DB.y + k1 * OB.y)), iksq);
+        }
+      } else {
+        const double2 RA = in1[eA];
+        o1[eA] = cscale(times_i(cadd(RA, DA)), ik);
+        if (two) o1[eB] = cscale(times_i(cadd(in1[eB], DB)), ik);
+      }
+    }
+#pragma unroll
+    for (int q = UP - 1; q > 0; --q) {
+      xa[q] = xa[q - 1];
+      xb[q] = xb[q - 1];
+    }
+    xa[0] = xA;
+    xb[0] = xB;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column kernel: RHS of Omega2 and phi2 from the projected T_ij, Dirichlet-row
+// projection, RK2 update (eqs. om, phi with the body force; R17 form
+// RHS_phi2 = -k^2 N2 - d/dy(i k1 N1 + i k3 N3) + k^2 g rho).
+
+__global__ void __launch_bounds__(kThreads) k_rhs_fluct(
+    DevPlan P, const double2* __restrict__ T11, const double2* __restrict__ T12, const double2* __restrict__ T13,
+    const double2* __restrict__ T22, const double2* __restrict__ T23, const double2* __restrict__ T33,
+    const double2* __restrict__ rhov, const double2* phi, const double2* om, const double2* __restrict__ rphi_prev,
+    const double2* __restrict__ rom_prev, double2* phi_out, double2* om_out, double2* __restrict__ rphi_out,
+    double2* __restrict__ rom_out, double2* __restrict__ yphi, double2* __restrict__ yom, int stage) {
+  const int nl = P.nl, nn = P.nn, n2 = P.n2;
+  const int ncol = nn * nl;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int l = c % nl, ni = c / nl;
+  const double k1 = P.k1[l], k3 = P.k3[ni], ksq = k1 * k1 + k3 * k3;
+  const double* L = P.lu_l + size_t(1) * n2 * kMaxBand;
+  const double* U = P.lu_u + size_t(1) * n2 * (kMaxBand + 1);
+  const double* Ui = P.lu_uinv + size_t(1) * n2;
+  double2 rp[kMaxBand], ro[kMaxBand];
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) rp[m] = ro[m] = zero2();
+  for (int i = 0; i < n2; ++i) {
+    double2 bp = zero2(), bo = zero2();
+    if (i > 0 && i < n2 - 1) {
+      const int lo = P.ev_lo[i];
+      const double* w0 = P.ev_w + (size_t(0) * n2 + i) * kMaxW;
+      const double* w1 = P.ev_w + (size_t(1) * n2 + i) * kMaxW;
+      const double* w2 = P.ev_w + (size_t(2) * n2 + i) * kMaxW;
+      double2 e0_11 = zero2(), e1_11 = zero2(), e0_12 = zero2(), e1_12 = zero2(), e2_12 = zero2();
+      double2 e0_13 = zero2(), e1_13 = zero2(), e1_22 = zero2(), e0_23 = zero2(), e1_23 = zero2();
+      double2 e2_23 = zero2(), e0_33 = zero2(), e1_33 = zero2();
+#pragma unroll
+      for (int q = 0; q < kMaxW; ++q) {
+        const int r = lo + q;
+        if (r < n2 && (w0[q] != 0.0 || w1[q] != 0.0 || w2[q] != 0.0)) {
+          const size_t e = size_t(r) * ncol + c;
+          const double2 t11 = T11[e], t12 = T12[e], t13 = T13[e], t22 = T22[e], t23 = T23[e], t33 = T33[e];
+          e0_11 = fma2(w0[q], t11, e0_11);
+          e1_11 = fma2(w1[q], t11, e1_11);
+          e0_12 = fma2(w0[q], t12, e0_12);
+          e1_12 = fma2(w1[q], t12, e1_12);
+          e2_12 = fma2(w2[q], t12, e2_12);
+          e0_13 = fma2(w0[q], t13, e0_13);
+          e1_13 = fma2(w1[q], t13, e1_13);
+          e1_22 = fma2(w1[q], t22, e1_22);
+          e0_23 = fma2(w0[q], t23, e0_23);
+          e1_23 = fma2(w1[q], t23, e1_23);
+          e2_23 = fma2(w2[q], t23, e2_23);
+          e0_33 = fma2(w0[q], t33, e0_33);
+          e1_33 = fma2(w1[q], t33, e1_33);
+        }
+      }
+      // N_i = i k1 T_i1 + d/dy T_i2 + i k3 T_i3 ;  dN_i = its y-derivative
+      const double2 N1 = cadd(cadd(times_i(cscale(e0_11, k1)), e1_12), times_i(cscale(e0_13, k3)));
+      const double2 N2 = cadd(cadd(times_i(cscale(e0_12, k1)), e1_22), times_i(cscale(e0_23, k3)));
+      const double2 N3 = cadd(cadd(times_i(cscale(e0_13, k1)), e1_23), times_i(cscale(e0_33, k3)));
+      const double2 dN1 = cadd(cadd(times_i(cscale(e1_11, k1)), e2_12), times_i(cscale(e1_13, k3)));
+      const double2 dN3 = cadd(cadd(times_i(cscale(e1_13, k1)), e2_23), times_i(cscale(e1_33, k3)));
+      bo = csub(times_i(cscale(N1, k3)), times_i(cscale(N3, k1)));
+      const double2 g = cadd(times_i(cscale(dN1, k1)), times_i(cscale(dN3, k3)));
+      const double2 rv = rhov[size_t(i) * ncol + c];
+      bp = make_double2(-ksq * N2.x - g.x + ksq * P.g * rv.x, -ksq * N2.y - g.y + ksq * P.g * rv.y);
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) {
+      const double lm = L[i * kMaxBand + m];
+      bp = fma2(-lm, rp[m], bp);
+      bo = fma2(-lm, ro[m], bo);
+    }
+    yphi[size_t(i) * ncol + c] = bp;
+    yom[size_t(i) * ncol + c] = bo;
+#pragma unroll
+    for (int m = kMaxBand - 1; m > 0; --m) {
+      rp[m] = rp[m - 1];
+      ro[m] = ro[m - 1];
+    }
+    rp[0] = bp;
+    ro[0] = bo;
+  }
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) rp[m] = ro[m] = zero2();
+  for (int i = n2 - 1; i >= 0; --i) {
+    const size_t e = size_t(i) * ncol + c;
+    double2 yp = yphi[e], yo = yom[e];
+#pragma unroll
+    for (int q = 0; q < kMaxBand; ++q) {
+      const double u = U[i * (kMaxBand + 1) + q + 1];
+      yp = fma2(-u, rp[q], yp);
+      yo = fma2(-u, ro[q], yo);
+    }
+    const double2 xp = cscale(yp, Ui[i]), xo = cscale(yo, Ui[i]);
+#pragma unroll
+    for (int q = kMaxBand - 1; q > 0; --q) {
+      rp[q] = rp[q - 1];
+      ro[q] = ro[q - 1];
+    }
+    rp[0] = xp;
+    ro[0] = xo;
+    if (rphi_out) rphi_out[e] = xp;
+    if (rom_out) rom_out[e] = xo;
+    const double2 p0 = phi[e], o0 = om[e];
+    if (stage == 0) {
+      phi_out[e] = fma2(0.5 * P.dt, xp, p0);
+      om_out[e] = fma2(0.5 * P.dt, xo, o0);
+    } else {
+      const double2 pp = rphi_prev[e], op = rom_prev[e];
+      phi_out[e] = fma2(P.dt, make_double2(xp.x - 0.5 * pp.x, xp.y - 0.5 * pp.y), p0);
+      om_out[e] = fma2(P.dt, make_double2(xo.x - 0.5 * op.x, xo.y - 0.5 * op.y), o0);
+    }
+  }
+}
+
+// plane means <m>1, <m>3: RHS = d/dy <T12>, d/dy <T32> at tau, Neumann rows,
+// RK2 (eq. mean_m1m3).  Two threads, one per component.
+__global__ void k_rhs_mean(DevPlan P, const double2* __restrict__ T12, const double2* __restrict__ T23,
+                           const double* m1, const double* m3, const double* __restrict__ r1p,
+                           const double* __restrict__ r3p, double* m1o, double* m3o, double* __restrict__ r1o,
+                           double* __restrict__ r3o, double* __restrict__ ytmp, int stage) {
+  const int comp = threadIdx.x;
+  if (comp > 1) return;
+  const int n2 = P.n2;
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const double2* T = comp == 0 ? T12 : T23;
+  const double* m = comp == 0 ? m1 : m3;
+  const double* rprev = comp == 0 ? r1p : r3p;
+  double* mo = comp == 0 ? m1o : m3o;
+  double* ro = comp == 0 ? r1o : r3o;
+  double* y = ytmp + comp * n2;
+  const double* L = P.lu_l + size_t(2) * n2 * kMaxBand;
+  const double* U = P.lu_u + size_t(2) * n2 * (kMaxBand + 1);
+  const double* Ui = P.lu_uinv + size_t(2) * n2;
+  for (int i = 0; i < n2; ++i) {
+    double b = 0.0;
+    if (i > 0 && i < n2 - 1) {
+      const int lo = P.ev_lo[n2 + i];
+      const double* w1 = P.ev_w + (size_t(1) * n2 + i) * kMaxW;
+      for (int q = 0; q < kMaxW; ++q)
+        if (lo + q < n2 && w1[q] != 0.0) b += w1[q] * T[size_t(lo + q) * ncol].x;
+    }
+    for (int mm = 1; mm <= kMaxBand && i - mm >= 0; ++mm) b -= L[i * kMaxBand + mm - 1] * y[i - mm];
+    y[i] = b;
+  }
+  for (int i = n2 - 1; i >= 0; --i) {
+    double s = y[i];
+    for (int q = 1; q <= kMaxBand && i + q < n2; ++q) s -= U[i * (kMaxBand + 1) + q] * y[i + q];
+    y[i] = s * Ui[i];
+  }
+  for (int i = 0; i < n2; ++i) {
+    const double x = y[i];
+    if (ro) ro[i] = x;
+    mo[i] = (stage == 0) ? m[i] + 0.5 * P.dt * x : m[i] + P.dt * (x - 0.5 * rprev[i]);
+  }
+}
+
+// BDF-like guess dt z_t^0 = a1 z + a2 h1 + a3 h2 + a4 h3 (eq. dzdt_guesses)
+__global__ void k_guess(const double2* __restrict__ z, const double2* __restrict__ h1, const double2* __restrict__ h2,
+                        const double2* __restrict__ h3, double a1, double a2, double a3, double a4, double dt,
+                        double2* __restrict__ out, size_t n, int zero) {
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  if (zero) {
+    out[e] = zero2();
+    return;
+  }
+  const double2 a = z[e], b = h1[e], c = h2[e], d = h3[e];
+  out[e] = make_double2((a1 * a.x + a2 * b.x + a3 * c.x + a4 * d.x) / dt, (a1 * a.y + a2 * b.y + a3 * c.y + a4 * d.y) / dt);
+}
+
+// z update from a given z_t (used when k_f = 0)
+__global__ void k_zupdate(const double2* __restrict__ z, const double2* __restrict__ zt,
+                          const double2* __restrict__ ztp, double2* __restrict__ zo, double dt, int stage, size_t n) {
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double2 a = z[e], t = zt[e];
+  if (stage == 0) {
+    zo[e] = make_double2(a.x + 0.5 * dt * t.x, a.y + 0.5 * dt * t.y);
+  } else {
+    const double2 p = ztp[e];
+    zo[e] = make_double2(a.x + dt * (t.x - 0.5 * p.x), a.y + dt * (t.y - 0.5 * p.y));
+  }
+}
+
+// plain evaluation (operator entry point)
+__global__ void k_evaluate(DevPlan P, int kind, const double2* __restrict__ src, double2* __restrict__ dst) {
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= ncol * P.n2) return;
+  const int j = int(e / ncol);
+  const size_t col = e - size_t(j) * ncol;
+  dst[e] = eval_at(P, kind, src, j, col, ncol, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+#define HIP_OK(x)                                    \
+  do {                                               \
+    if ((x) != hipSuccess) return LMVD_EHIP;         \
+  } while (0)
+
+struct Workspace {
+  size_t bytes = 0;
+  size_t off_md1, off_md3, off_c2d, off_mpar, off_c2c, off_rz, off_zta, off_ztb, off_rhot, off_vals[kMaxOut];
+  size_t off_u[3], off_T[6], off_rhov, off_yphi, off_yom, off_uscr, off_zbuf, off_obuf, off_mean;
+};
+
+}  // namespace lmvd
+
+struct lmvd_prof {
+  int cls = -1;                 // kernel class being timed, -1 = off
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  int used = 0;                 // pairs recorded
+  double bytes = 0.0;           // algorithmic bytes of the recorded launches
+};
+
+struct lmvd_plan_s {
+  lmvd::HostTables H;
+  lmvd_prof prof;
+  lmvd::DevPlan D{};
+  std::vector<void*> allocs;
+  lmvd::Workspace ws;
+  int pb = 0;       // planes per batch
+  int lgz = 1;      // l-lines per z-FFT block
+  int bgx = 1;      // z-lines per x-pass block
+  int device = 0;
+};
+
+namespace lmvd {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static void layout_workspace(lmvd_plan_s* p) {
+  const HostTables& H = p->H;
+  const size_t ncol = size_t(H.nn) * H.nl;
+  const size_t sB = ncol * H.n2 * 16, sS = ncol * (H.n2 + 1) * 16;
+  const int UPA = 8;  // widest instantiation of k_solveA (band 8, 8)
+  size_t o = 0;
+  Workspace& w = p->ws;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+  w.off_md1 = take(sB);
+  w.off_md3 = take(sB);
+  w.off_c2d = take(sS);
+  w.off_mpar = take(sB);
+  w.off_c2c = take(sS);
+  w.off_rz = take(sB);
+  w.off_zta = take(sB);
+  w.off_ztb = take(sB);
+  w.off_rhot = take(sB);
+  for (int g = 0; g < kMaxOut; ++g) w.off_vals[g] = take(sB);
+  for (int i = 0; i < 3; ++i) w.off_u[i] = take(sB);
+  for (int i = 0; i < 6; ++i) w.off_T[i] = take(sB);
+  w.off_rhov = take(sB);
+  w.off_yphi = take(sB);
+  w.off_yom = take(sB);
+  const size_t npairs = size_t(H.nl) * ((H.nn + 1) / 2);
+  w.off_uscr = take(size_t(H.n2 + 1) * (UPA + 1) * npairs * 8);
+  const size_t plane = size_t(H.cfg.m3) * H.nl * 16;
+  w.off_zbuf = take(size_t(kMaxIn) * p->pb * plane);
+  w.off_obuf = take(size_t(kMaxOut) * p->pb * plane);
+  w.off_mean = take(size_t(2) * H.n2 * 8);
+  w.bytes = o;
+}
+
+template <typename T>
+static lmvd_status upload(lmvd_plan_s* p, const std::vector<T>& v, const T** dst) {
+  void* d = nullptr;
+  size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+  if (hipMalloc(&d, bytes) != hipSuccess) return LMVD_ENOMEM;
+  p->allocs.push_back(d);
+  if (!v.empty() && hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return LMVD_EHIP;
+  *dst = static_cast<const T*>(d);
+  return LMVD_OK;
+}
+
+static void cat_rows(const RowTable* t, int count, std::vector<int>& lo, std::vector<double>& w) {
+  for (int k = 0; k < count; ++k) {
+    lo.insert(lo.end(), t[k].lo.begin(), t[k].lo.end());
+    w.insert(w.end(), t[k].w.begin(), t[k].w.end());
+  }
+}
+
+static void fill_fft(const FftPlan& f, FftDev& d) {
+  d.n = f.n;
+  d.nstages = f.nstages;
+  for (int s = 0; s < kMaxStagesDev; ++s) {
+    d.radix[s] = s < f.nstages ? f.radix[s] : 0;
+    d.ns[s] = s < f.nstages ? f.ns[s] : 0;
+  }
+}
+
+// choose launch shapes
+static void choose_shapes(lmvd_plan_s* p) {
+  const HostTables& H = p->H;
+  const int M3 = H.cfg.m3;
+  // l-lines per z-FFT block: at most 64 KiB of LDS and kZMaxE elements per thread
+  int lg = std::max(1, std::min(4096, kZMaxE * kThreads) / M3);  // kZMaxE * kThreads = 3072
+  int pw = 1;
+  while (pw * 2 <= lg) pw *= 2;
+  lg = std::min(pw, H.nl);
+  p->lgz = lg;
+  int bg = std::max(1, (kXSlots * kThreads) / H.hx);
+  bg = std::min(bg, M3);
+  p->bgx = bg;
+}
+
+static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::string& msg) {
+  if (!cfg || !out) return LMVD_EINVAL;
+  lmvd_plan_s* p = new (std::nothrow) lmvd_plan_s();
+  if (!p) return LMVD_ENOMEM;
+  lmvd_status st = build_host_tables(*cfg, p->H, msg);
+  if (st != LMVD_OK) {
+    delete p;
+    return st;
+  }
+  HostTables& H = p->H;
+  // k_xpass stages one x-line of m1/2 complex values in kXSlots * kThreads slots
+  if (H.nl > H.hx || H.nn > cfg->m3 || H.hx > kXSlots * kThreads) {
+    delete p;
+    return LMVD_EUNSUPPORTED;
+  }
+  if (H.a_lower > 8 || H.a_upper > 8) {
+    delete p;
+    return LMVD_EUNSUPPORTED;
+  }
+  if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
+  p->pb = (cfg->plane_batch > 0) ? std::min(cfg->plane_batch, H.n2) : H.n2;
+  choose_shapes(p);
+  DevPlan& D = p->D;
+  D.n2 = H.n2;
+  D.p = H.p;
+  D.nl = H.nl;
+  D.nn = H.nn;
+  D.n3 = cfg->n3;
+  D.m1 = cfg->m1;
+  D.m3 = cfg->m3;
+  D.hx = H.hx;
+  D.dt = cfg->dt;
+  D.mu = cfg->mu;
+  D.rhoD = cfg->rhoD;
+  D.g = cfg->g;
+  D.rho_l = cfg->rho_l;
+  D.rho_h = cfg->rho_h;
+  D.inv_rlrh = 1.0 / (cfg->rho_l * cfg->rho_h);
+  D.drho = cfg->rho_h - cfg->rho_l;
+  std::vector<int> lo;
+  std::vector<double> w;
+  RowTable ev[kNumEv] = {H.E[0], H.E[1], H.E[2], H.F0};
+  cat_rows(ev, kNumEv, lo, w);
+#define UP_OR_FAIL(vec, dst)                \
+  do {                                      \
+    st = upload(p, vec, dst);               \
+    if (st != LMVD_OK) {                    \
+      lmvd_plan_destroy(p);                 \
+      return st;                            \
+    }                                       \
+  } while (0)
+  UP_OR_FAIL(lo, &D.ev_lo);
+  UP_OR_FAIL(w, &D.ev_w);
+  lo.clear();
+  w.clear();
+  cat_rows(H.G, 2, lo, w);
+  UP_OR_FAIL(lo, &D.gs_lo);
+  UP_OR_FAIL(w, &D.gs_w);
+  lo.clear();
+  w.clear();
+  cat_rows(H.Es, 3, lo, w);
+  UP_OR_FAIL(lo, &D.es_lo);
+  UP_OR_FAIL(w, &D.es_w);
+  UP_OR_FAIL(H.dstar, &D.dstar);
+  std::vector<double> L, U, Ui;
+  for (int k = 0; k < 3; ++k) {
+    L.insert(L.end(), H.proj[k].lmul.begin(), H.proj[k].lmul.end());
+    U.insert(U.end(), H.proj[k].u.begin(), H.proj[k].u.end());
+    Ui.insert(Ui.end(), H.proj[k].uinv.begin(), H.proj[k].uinv.end());
+  }
+  UP_OR_FAIL(L, &D.lu_l);
+  UP_OR_FAIL(U, &D.lu_u);
+  UP_OR_FAIL(Ui, &D.lu_uinv);
+  UP_OR_FAIL(H.k1, &D.k1);
+  UP_OR_FAIL(H.k3, &D.k3);
+  const double* tw = nullptr;
+  UP_OR_FAIL(H.fz.tw, &tw);
+  fill_fft(H.fz, D.fz);
+  D.fz.tw = reinterpret_cast<const double2*>(tw);
+  UP_OR_FAIL(H.fx.tw, &tw);
+  fill_fft(H.fx, D.fx);
+  D.fx.tw = reinterpret_cast<const double2*>(tw);
+  UP_OR_FAIL(H.xtw, &tw);
+  D.xtw = reinterpret_cast<const double2*>(tw);
+#undef UP_OR_FAIL
+  layout_workspace(p);
+  *out = p;
+  return LMVD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+struct Ctx {
+  lmvd_plan_s* p;
+  char* ws;
+  hipStream_t s;
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+};
+
+static size_t ncols(const lmvd_plan_s* p) { return size_t(p->H.nn) * p->H.nl; }
+
+// kernel classes of the timing hook
+enum KClass { KC_EVAL = 0, KC_XPASS = 1, KC_ZFWD = 2, KC_PROJ = 3, KC_SOLVEA = 4, KC_RHS = 5, KC_COUNT = 6 };
+
+// Bracket one launch of class `cls` with events when that class is timed.
+struct ProfScope {
+  lmvd_plan_s* p;
+  hipStream_t s;
+  bool on;
+  ProfScope(lmvd_plan_s* p_, int cls, hipStream_t s_, double bytes) : p(p_), s(s_) {
+    lmvd_prof& f = p->prof;
+    on = (f.cls == cls) && (2 * f.used + 1 < int(f.ev.size()));
+    if (on) {
+      (void)hipEventRecord(f.ev[2 * f.used], s);
+      f.bytes += bytes;
+    }
+  }
+  ~ProfScope() {
+    if (on) {
+      (void)hipEventRecord(p->prof.ev[2 * p->prof.used + 1], s);
+      ++p->prof.used;
+    }
+  }
+};
+
+static EvalIn ev(const void* a, int kind, int ma = MU_ONE, const void* b = nullptr, int mb = MU_ONE) {
+  EvalIn e;
+  e.a = static_cast<const double2*>(a);
+  e.b = static_cast<const double2*>(b);
+  e.kind = kind;
+  e.ma = ma;
+  e.mb = mb;
+  e.pad = 0;
+  return e;
+}
+
+template <int PH>
+static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, const std::vector<double2*>& outs,
+                               double* phys_out = nullptr, const double* phys_in = nullptr) {
+  lmvd_plan_s* p = c.p;
+  const HostTables& H = p->H;
+  const int M3 = H.cfg.m3, nl = H.nl;
+  EvalArgs A{};
+  for (size_t i = 0; i < ins.size(); ++i) A.in[i] = ins[i];
+  OutPtrs V{};
+  for (size_t g = 0; g < outs.size(); ++g) V.v[g] = outs[g];
+  double2* zbuf = c.at<double2>(p->ws.off_zbuf);
+  double2* obuf = c.at<double2>(p->ws.off_obuf);
+  const int lg = p->lgz, bg = p->bgx;
+  const size_t lds_z = size_t(lg) * M3 * sizeof(double2);
+  const size_t lds_x = size_t(bg) * H.hx * sizeof(double2);
+  for (int j0 = 0; j0 < H.n2; j0 += p->pb) {
+    const int nb = std::min(p->pb, H.n2 - j0);
+    const double zplane = double(M3) * nl * 16.0, splane = double(ncols(p)) * 16.0;
+    const double nin = double(ins.size()), nout = double(outs.size());
+    if (!ins.empty()) {
+      double terms = 0;
+      for (const EvalIn& e : ins) terms += e.b ? 2 : 1;
+      ProfScope ps(p, KC_EVAL, c.s, nb * (terms * splane + nin * zplane));
+      dim3 g1((nl + lg - 1) / lg, nb, int(ins.size()));
+      hipLaunchKernelGGL(k_eval_zinv, g1, dim3(kThreads), lds_z, c.s, p->D, A, zbuf, j0, p->pb, lg);
+    }
+    {
+      ProfScope ps(p, KC_XPASS, c.s, nb * (nin + nout) * zplane);
+      dim3 g2((M3 + bg - 1) / bg, nb);
+      hipLaunchKernelGGL(k_xpass<PH>, g2, dim3(kThreads), lds_x, c.s, p->D, zbuf, obuf, p->pb, bg, phys_out,
+                         phys_in, j0);
+    }
+    if (!outs.empty()) {
+      ProfScope ps(p, KC_ZFWD, c.s, nb * nout * (zplane + splane));
+      dim3 g3((nl + lg - 1) / lg, nb, int(outs.size()));
+      hipLaunchKernelGGL(k_zfwd, g3, dim3(kThreads), lds_z, c.s, p->D, obuf, V, j0, p->pb, lg);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+static void proj(const Ctx& c, int kind, const double2* in, double2* out) {
+  const int n = int(ncols(c.p));
+  ProfScope ps(c.p, KC_PROJ, c.s, 2.0 * 16.0 * n * c.p->H.n2);
+  hipLaunchKernelGGL(k_proj<EPI_STORE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, c.s, c.p->D, kind,
+                     in, out, nullptr, nullptr, nullptr, nullptr, nullptr, 0, n);
+}
+
+template <int MODE>
+static void solveA(const Ctx& c, const double2* in1, const double2* in2, const double* m1bar, const double* m3bar,
+                   double2* c2, double2* o1, double2* o3) {
+  const HostTables& H = c.p->H;
+  const int npairs = H.nl * ((H.nn + 1) / 2);
+  dim3 grid((npairs + kThreads - 1) / kThreads);
+  double* uscr = c.at<double>(c.p->ws.off_uscr);
+  const double sB = 16.0 * ncols(c.p) * H.n2, sS = 16.0 * ncols(c.p) * (H.n2 + 1);
+  ProfScope ps(c.p, KC_SOLVEA, c.s, MODE == 0 ? 4.0 * sB + sS : 2.0 * sB + sS);
+  // the U scratch stride is (a_upper + 1); kernels are instantiated for the band of the plan
+  if (H.a_lower <= 7 && H.a_upper <= 7)
+    hipLaunchKernelGGL((k_solveA<MODE, 7, 7>), grid, dim3(kThreads), 0, c.s, c.p->D, in1, in2, m1bar, m3bar, c2, o1,
+                       o3, uscr);
+  else
+    hipLaunchKernelGGL((k_solveA<MODE, 8, 8>), grid, dim3(kThreads), 0, c.s, c.p->D, in1, in2, m1bar, m3bar, c2, o1,
+                       o3, uscr);
+}
+
+static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void* workspace, hipStream_t s) {
+  const HostTables& H = p->H;
+  Ctx c{p, static_cast<char*>(workspace), s};
+  const Workspace& W = p->ws;
+  const size_t ncol = ncols(p);
+  const size_t nB = ncol * H.n2;
+  const int kf = (a->kf < 0) ? H.cfg.kf : a->kf;
+  double2* md1 = c.at<double2>(W.off_md1);
+  double2* md3 = c.at<double2>(W.off_md3);
+  double2* c2d = c.at<double2>(W.off_c2d);
+  double2* mpar = c.at<double2>(W.off_mpar);
+  double2* c2c = c.at<double2>(W.off_c2c);
+  double2* rz = c.at<double2>(W.off_rz);
+  double2* zta = c.at<double2>(W.off_zta);
+  double2* ztb = c.at<double2>(W.off_ztb);
+  double2* rhot = c.at<double2>(W.off_rhot);
+  double2* vals[kMaxOut];
+  for (int g = 0; g < kMaxOut; ++g) vals[g] = c.at<double2>(W.off_vals[g]);
+  double2* u[3];
+  for (int i = 0; i < 3; ++i) u[i] = c.at<double2>(W.off_u[i]);
+  double2* T[6];
+  for (int i = 0; i < 6; ++i) T[i] = c.at<double2>(W.off_T[i]);
+  double2* rhov = c.at<double2>(W.off_rhov);
+  const double2* z = static_cast<const double2*>(a->z);
+  const double2* phi2 = static_cast<const double2*>(a->phi2);
+  const double2* om2 = static_cast<const double2*>(a->omega2);
+  double2* user_zt = static_cast<double2*>(a->zt);
+  lmvd_status st;
+
+  // 1. m^d
+  solveA<0>(c, phi2, om2, a->m1bar, a->m3bar, c2d, md1, md3);
+  // 2. R_z
+  st = plane_phase<PH_RZ>(c,
+                          {ev(z, EV_E0), ev(z, EV_E0, MU_IK1), ev(z, EV_E1), ev(z, EV_E0, MU_IK3), ev(z, EV_LAP),
+                           ev(md1, EV_E0), ev(c2d, EV_F0), ev(md3, EV_E0)},
+                          {vals[0]});
+  if (st != LMVD_OK) return st;
+  proj(c, 2, vals[0], rz);
+  // guess
+  {
+    const double bn = H.cfg.beta_n, bp = H.cfg.beta_p;
+    double co[4];
+    if (a->stage == 0) {
+      co[0] = 2.0; co[1] = -2.0 - 0.5 * bn; co[2] = bn; co[3] = -0.5 * bn;
+    } else {
+      co[0] = 4.0 + bp; co[1] = -5.0 - 2.0 * bp; co[2] = bp; co[3] = 1.0;
+    }
+    double2* gdst = (kf == 0 && user_zt) ? user_zt : zta;
+    const int zero = (a->guess_mode == 1) ? 1 : 0;
+    hipLaunchKernelGGL(k_guess, dim3((nB + kThreads - 1) / kThreads), dim3(kThreads), 0, s, z,
+                       static_cast<const double2*>(a->z_hist[0]), static_cast<const double2*>(a->z_hist[1]),
+                       static_cast<const double2*>(a->z_hist[2]), co[0], co[1], co[2], co[3], H.cfg.dt, gdst, nB,
+                       zero);
+    if (kf == 0) {
+      hipLaunchKernelGGL(k_zupdate, dim3((nB + kThreads - 1) / kThreads), dim3(kThreads), 0, s, z, gdst,
+                         static_cast<const double2*>(a->zt_prev), static_cast<double2*>(a->z_out), H.cfg.dt, a->stage,
+                         nB);
+    }
+  }
+  double2* cur = (kf == 0 && user_zt) ? user_zt : zta;
+  // 3. fixed-point iterations
+  for (int it = 0; it < kf; ++it) {
+    const bool last = (it == kf - 1);
+    st = plane_phase<PH_RHOT>(c, {ev(z, EV_E0), ev(cur, EV_E0)}, {vals[0]});
+    if (st != LMVD_OK) return st;
+    proj(c, 0, vals[0], rhot);
+    solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
+    st = plane_phase<PH_L>(c,
+                           {ev(z, EV_E0), ev(z, EV_E0, MU_IK1), ev(z, EV_E1), ev(z, EV_E0, MU_IK3),
+                            ev(mpar, EV_E0, MU_K1K), ev(c2c, EV_F0), ev(mpar, EV_E0, MU_K3K)},
+                           {vals[0]});
+    if (st != LMVD_OK) return st;
+    double2* next = (last && user_zt) ? user_zt : (cur == zta ? ztb : zta);
+    const int n = int(ncol);
+    ProfScope ps(p, KC_PROJ, s, (last ? (a->stage ? 6.0 : 5.0) : 3.0) * 16.0 * nB);
+    if (last) {
+      hipLaunchKernelGGL(k_proj<EPI_ADD_ZUPDATE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
+                         vals[0], next, rz, z, static_cast<const double2*>(a->zt_prev),
+                         static_cast<double2*>(a->z_out), nullptr, a->stage, n);
+    } else {
+      hipLaunchKernelGGL(k_proj<EPI_ADD>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
+                         vals[0], next, rz, nullptr, nullptr, nullptr, nullptr, a->stage, n);
+    }
+    cur = next;
+  }
+  // m^c of the stage from z_t^{k_f}
+  st = plane_phase<PH_RHOT>(c, {ev(z, EV_E0), ev(cur, EV_E0)}, {vals[0]});
+  if (st != LMVD_OK) return st;
+  proj(c, 0, vals[0], rhot);
+  solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
+  // 4./5. velocities, density, fluxes
+  const EvalIn m1 = ev(md1, EV_E0, MU_ONE, mpar, MU_K1K);
+  const EvalIn m2 = ev(c2d, EV_F0, MU_ONE, c2c, MU_ONE);
+  const EvalIn m3 = ev(md3, EV_E0, MU_ONE, mpar, MU_K3K);
+  st = plane_phase<PH_VEL>(c, {ev(z, EV_E0), m1, m2, m3}, {vals[0], vals[1], vals[2], rhov});
+  if (st != LMVD_OK) return st;
+  for (int i = 0; i < 3; ++i) proj(c, 0, vals[i], u[i]);
+  std::vector<EvalIn> fin = {ev(z, EV_E0), m1, m2, m3};
+  for (int i = 0; i < 3; ++i) {
+    fin.push_back(ev(u[i], EV_E0, MU_IK1));
+    fin.push_back(ev(u[i], EV_E1));
+    fin.push_back(ev(u[i], EV_E0, MU_IK3));
+  }
+  st = plane_phase<PH_FLUX>(c, fin, {vals[0], vals[1], vals[2], vals[3], vals[4], vals[5]});
+  if (st != LMVD_OK) return st;
+  for (int i = 0; i < 6; ++i) proj(c, 0, vals[i], T[i]);
+  // RHS and RK2
+  {
+    const int n = int(ncol);
+    {
+    ProfScope ps(p, KC_RHS, s, 16.0 * nB * (a->stage ? 11.0 : 9.0) + 16.0 * nB * ((a->rhs_phi2 ? 2 : 0) + 2));
+    hipLaunchKernelGGL(k_rhs_fluct, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, T[0], T[1],
+                       T[2], T[3], T[4], T[5], rhov, phi2, om2, static_cast<const double2*>(a->rhs_phi2_prev),
+                       static_cast<const double2*>(a->rhs_omega2_prev), static_cast<double2*>(a->phi2_out),
+                       static_cast<double2*>(a->omega2_out), static_cast<double2*>(a->rhs_phi2),
+                       static_cast<double2*>(a->rhs_omega2), c.at<double2>(W.off_yphi), c.at<double2>(W.off_yom),
+                       a->stage);
+    }
+    hipLaunchKernelGGL(k_rhs_mean, dim3(1), dim3(64), 0, s, p->D, T[1], T[4], a->m1bar, a->m3bar, a->rhs_m1_prev,
+                       a->rhs_m3_prev, a->m1bar_out, a->m3bar_out, a->rhs_m1, a->rhs_m3, c.at<double>(W.off_mean),
+                       a->stage);
+  }
+  // optional diagnostics
+  const size_t sB = nB * 16, sS = ncol * (H.n2 + 1) * 16;
+  if (a->md[0]) HIP_OK(hipMemcpyAsync(a->md[0], md1, sB, hipMemcpyDeviceToDevice, s));
+  if (a->md[1]) HIP_OK(hipMemcpyAsync(a->md[1], c2d, sS, hipMemcpyDeviceToDevice, s));
+  if (a->md[2]) HIP_OK(hipMemcpyAsync(a->md[2], md3, sB, hipMemcpyDeviceToDevice, s));
+  if (a->mc[1]) HIP_OK(hipMemcpyAsync(a->mc[1], c2c, sS, hipMemcpyDeviceToDevice, s));
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+__global__ void k_mc13(DevPlan P, const double2* __restrict__ mpar, double2* __restrict__ m1, double2* __restrict__ m3) {
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= ncol * P.n2) return;
+  const size_t col = e % ncol;
+  const int l = int(col % P.nl), ni = int(col / P.nl);
+  const double k1 = P.k1[l], k3 = P.k3[ni];
+  if (m1) m1[e] = apply_mult(MU_K1K, k1, k3, mpar[e]);
+  if (m3) m3[e] = apply_mult(MU_K3K, k1, k3, mpar[e]);
+}
+
+static bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; }
+
+}  // namespace lmvd
+
+using namespace lmvd;
+
+extern "C" {
+
+const char* lmvd_status_string(lmvd_status s) {
+  switch (s) {
+    case LMVD_OK: return "ok";
+    case LMVD_EINVAL: return "invalid argument";
+    case LMVD_ENOMEM: return "out of memory";
+    case LMVD_EHIP: return "HIP error";
+    case LMVD_EUNSUPPORTED: return "unsupported size";
+    case LMVD_ENUMERIC: return "numerical failure (pivot)";
+  }
+  return "unknown status";
+}
+
+lmvd_status lmvd_plan_create(const lmvd_config* cfg, lmvd_plan* out) {
+  std::string msg;
+  lmvd_status st = create_plan(cfg, out, msg);
+  if (st != LMVD_OK && !msg.empty()) fprintf(stderr, "lmvd_plan_create: %s\n", msg.c_str());
+  return st;
+}
+
+lmvd_status lmvd_plan_destroy(lmvd_plan plan) {
+  if (!plan) return LMVD_EINVAL;
+  for (hipEvent_t e : plan->prof.ev) (void)hipEventDestroy(e);
+  for (void* d : plan->allocs) (void)hipFree(d);
+  delete plan;
+  return LMVD_OK;
+}
+
+lmvd_status lmvd_sizes(lmvd_plan plan, size_t* se, size_t* ss, size_t* wb) {
+  if (!plan) return LMVD_EINVAL;
+  const size_t ncol = size_t(plan->H.nn) * plan->H.nl;
+  if (se) *se = ncol * plan->H.n2;
+  if (ss) *ss = ncol * (plan->H.n2 + 1);
+  if (wb) *wb = plan->ws.bytes;
+  return LMVD_OK;
+}
+
+lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* a, void* workspace, void* stream) {
+  if (!plan || !a || !workspace) return LMVD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
+  if (a->stage != 0 && a->stage != 1) return LMVD_EINVAL;
+  if (a->guess_mode != 0 && a->guess_mode != 1) return LMVD_EINVAL;
+  const void* req[] = {a->phi2, a->omega2, a->z, a->m1bar, a->m3bar, a->phi2_out, a->omega2_out, a->z_out,
+                       a->m1bar_out, a->m3bar_out};
+  for (const void* q : req)
+    if (!q || !aligned(q)) return LMVD_EINVAL;
+  if (a->z_out == a->z) return LMVD_EINVAL;
+  if (a->stage == 0 && (!a->rhs_phi2 || !a->rhs_omega2 || !a->zt || !a->rhs_m1 || !a->rhs_m3)) return LMVD_EINVAL;
+  if (a->stage == 1 && (!a->rhs_phi2_prev || !a->rhs_omega2_prev || !a->zt_prev || !a->rhs_m1_prev ||
+                        !a->rhs_m3_prev))
+    return LMVD_EINVAL;
+  if (a->guess_mode == 0 && (!a->z_hist[0] || !a->z_hist[1] || !a->z_hist[2])) return LMVD_EINVAL;
+  if (a->kf < -1 || a->kf > 10000) return LMVD_EINVAL;
+  if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lmvd_status st = run_substep(plan, a, workspace, s);
+  if (st != LMVD_OK) return st;
+  if (a->mc[0] || a->mc[2]) {
+    const size_t n = size_t(plan->H.nn) * plan->H.nl * plan->H.n2;
+    hipLaunchKernelGGL(k_mc13, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, plan->D,
+                       reinterpret_cast<const double2*>(static_cast<char*>(workspace) + plan->ws.off_mpar),
+                       static_cast<double2*>(a->mc[0]), static_cast<double2*>(a->mc[2]));
+  }
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_to_physical(lmvd_plan plan, const void* values, double* phys, void* workspace, void* stream) {
+  if (!plan || !values || !phys || !workspace) return LMVD_EINVAL;
+  Ctx c{plan, static_cast<char*>(workspace), static_cast<hipStream_t>(stream)};
+  return plane_phase<PH_TOPHYS>(c, {ev(values, EV_IDENT)}, {}, phys, nullptr);
+}
+
+lmvd_status lmvd_to_spectral(lmvd_plan plan, const double* phys, void* values, void* workspace, void* stream) {
+  if (!plan || !values || !phys || !workspace) return LMVD_EINVAL;
+  Ctx c{plan, static_cast<char*>(workspace), static_cast<hipStream_t>(stream)};
+  return plane_phase<PH_FROMPHYS>(c, {}, {static_cast<double2*>(values)}, nullptr, phys);
+}
+
+lmvd_status lmvd_project(lmvd_plan plan, int32_t kind, const void* values, void* coeffs, void* stream) {
+  if (!plan || !values || !coeffs || kind < 0 || kind > 2) return LMVD_EINVAL;
+  Ctx c{plan, nullptr, static_cast<hipStream_t>(stream)};
+  proj(c, kind, static_cast<const double2*>(values), static_cast<double2*>(coeffs));
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_evaluate(lmvd_plan plan, int32_t deriv, int32_t star, const void* coeffs, void* values,
+                          void* stream) {
+  if (!plan || !coeffs || !values || deriv < 0 || deriv > 2 || (star && deriv != 0)) return LMVD_EINVAL;
+  const size_t n = size_t(plan->H.nn) * plan->H.nl * plan->H.n2;
+  const int kind = star ? EV_F0 : deriv;
+  hipLaunchKernelGGL(k_evaluate, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     static_cast<hipStream_t>(stream), plan->D, kind, static_cast<const double2*>(coeffs),
+                     static_cast<double2*>(values));
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_md(lmvd_plan plan, const void* phi2, const void* omega2, const double* m1bar, const double* m3bar,
+                    void* m1, void* m2, void* m3, void* workspace, void* stream) {
+  if (!plan || !phi2 || !omega2 || !m1bar || !m3bar || !m1 || !m2 || !m3 || !workspace) return LMVD_EINVAL;
+  Ctx c{plan, static_cast<char*>(workspace), static_cast<hipStream_t>(stream)};
+  solveA<0>(c, static_cast<const double2*>(phi2), static_cast<const double2*>(omega2), m1bar, m3bar,
+            static_cast<double2*>(m2), static_cast<double2*>(m1), static_cast<double2*>(m3));
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_mc(lmvd_plan plan, const void* rhot, void* m1, void* m2, void* m3, void* workspace, void* stream) {
+  if (!plan || !rhot || !m1 || !m2 || !m3 || !workspace) return LMVD_EINVAL;
+  Ctx c{plan, static_cast<char*>(workspace), static_cast<hipStream_t>(stream)};
+  double2* mpar = c.at<double2>(plan->ws.off_mpar);
+  solveA<1>(c, static_cast<const double2*>(rhot), nullptr, nullptr, nullptr, static_cast<double2*>(m2), mpar,
+            nullptr);
+  const size_t n = size_t(plan->H.nn) * plan->H.nl * plan->H.n2;
+  hipLaunchKernelGGL(k_mc13, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, c.s, plan->D, mpar,
+                     static_cast<double2*>(m1), static_cast<double2*>(m3));
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_profile_start(lmvd_plan plan, int32_t cls, int32_t max_launches) {
+  if (!plan || cls < 0 || cls >= KC_COUNT || max_launches < 1 || max_launches > (1 << 20)) return LMVD_EINVAL;
+  lmvd_prof& f = plan->prof;
+  for (hipEvent_t e : f.ev) (void)hipEventDestroy(e);
+  f.ev.assign(size_t(2) * max_launches, nullptr);
+  for (auto& e : f.ev)
+    if (hipEventCreate(&e) != hipSuccess) return LMVD_EHIP;
+  f.used = 0;
+  f.bytes = 0.0;
+  f.cls = cls;
+  return LMVD_OK;
+}
+
+lmvd_status lmvd_profile_stop(lmvd_plan plan, double* total_ms, int64_t* launches, double* alg_bytes) {
+  if (!plan) return LMVD_EINVAL;
+  lmvd_prof& f = plan->prof;
+  double tot = 0.0;
+  for (int i = 0; i < f.used; ++i) {
+    if (hipEventSynchronize(f.ev[2 * i + 1]) != hipSuccess) return LMVD_EHIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, f.ev[2 * i], f.ev[2 * i + 1]) != hipSuccess) return LMVD_EHIP;
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = f.used;
+  if (alg_bytes) *alg_bytes = f.bytes;
+  for (hipEvent_t e : f.ev) (void)hipEventDestroy(e);
+  f.ev.clear();
+  f.cls = -1;
+  f.used = 0;
+  return LMVD_OK;
+}
+
+lmvd_status lmvd_host_tables(const lmvd_config* cfg, double* tau, double* tau_star, double* E0, double* E1,
+                             double* E2) {
+  if (!cfg) return LMVD_EINVAL;
+  HostTables H;
+  std::string msg;
+  lmvd_status st = build_host_tables(*cfg, H, msg);
+  if (st != LMVD_OK) return st;
+  if (tau) std::copy(H.tau.begin(), H.tau.end(), tau);
+  if (tau_star) std::copy(H.tau_s.begin(), H.tau_s.end(), tau_star);
+  double* outs[3] = {E0, E1, E2};
+  for (int d = 0; d < 3; ++d)
+    if (outs[d]) {
+      std::vector<double> D = dense(H.E[d]);
+      std::copy(D.begin(), D.end(), outs[d]);
+    }
+  return LMVD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,339 @@
+// Host tables of the y-discretisation (App. C) and of the x-z transforms.
+//
+// B-spline values and derivatives at a point come from the triangular
+// "nonzero functions of one knot span" evaluation with its derivative table
+// (Piegl & Tiller, The NURBS Book, algorithm A2.3), written here for
+// clamped knot vectors.  Collocation rows are stored band-packed.
+#include "plan_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <random>
+
+namespace lmvd {
+namespace {
+
+std::vector<double> clamped(const std::vector<double>& xi, int order) {
+  std::vector<double> t;
+  t.insert(t.end(), order - 1, xi.front());
+  t.insert(t.end(), xi.begin(), xi.end());
+  t.insert(t.end(), order - 1, xi.back());
+  return t;
+}
+
+std::vector<double> greville_points(const std::vector<double>& t, int order) {
+  int n = int(t.size()) - order;
+  std::vector<double> g(n);
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int q = 1; q < order; ++q) s += t[i + q];
+    g[i] = s / double(order - 1);
+  }
+  return g;
+}
+
+// Knot span s with t[s] <= x < t[s+1]; the right end belongs to the last span.
+int span_of(const std::vector<double>& t, int order, double x) {
+  int n = int(t.size()) - order;
+  if (x >= t[n]) return n - 1;
+  int lo = order - 1, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (x < t[mid]) hi = mid; else lo = mid;
+  }
+  return lo;
+}
+
+// Nonzero functions N_{s-deg+r} (r = 0..deg) of degree `deg` at x in span s
+// and their first `nd` derivatives: ders[k][r].
+void span_basis(const std::vector<double>& t, int deg, int s, double x, int nd,
+                double ders[3][kMaxW]) {
+  double ndu[kMaxW][kMaxW], left[kMaxW], right[kMaxW], a[2][kMaxW];
+  ndu[0][0] = 1.0;
+  for (int j = 1; j <= deg; ++j) {
+    left[j] = x - t[s + 1 - j];
+    right[j] = t[s + j] - x;
+    double saved = 0.0;
+    for (int r = 0; r < j; ++r) {
+      ndu[j][r] = right[r + 1] + left[j - r];
+      double temp = ndu[r][j - 1] / ndu[j][r];
+      ndu[r][j] = saved + right[r + 1] * temp;
+      saved = left[j - r] * temp;
+    }
+    ndu[j][j] = saved;
+  }
+  for (int j = 0; j <= deg; ++j) ders[0][j] = ndu[j][deg];
+  for (int r = 0; r <= deg; ++r) {
+    int s1 = 0, s2 = 1;
+    a[0][0] = 1.0;
+    for (int k = 1; k <= nd; ++k) {
+      double d = 0.0;
+      int rk = r - k, pk = deg - k;
+      if (r >= k) {
+        a[s2][0] = a[s1][0] / ndu[pk + 1][rk];
+        d = a[s2][0] * ndu[rk][pk];
+      }
+      int j1 = (rk >= -1) ? 1 : -rk;
+      int j2 = (r - 1 <= pk) ? k - 1 : deg - r;
+      for (int j = j1; j <= j2; ++j) {
+        a[s2][j] = (a[s1][j] - a[s1][j - 1]) / ndu[pk + 1][rk + j];
+        d += a[s2][j] * ndu[rk + j][pk];
+      }
+      if (r <= pk) {
+        a[s2][k] = -a[s1][k - 1] / ndu[pk + 1][r];
+        d += a[s2][k] * ndu[r][pk];
+      }
+      ders[k][r] = d;
+      std::swap(s1, s2);
+    }
+  }
+  double f = deg;
+  for (int k = 1; k <= nd; ++k) {
+    for (int j = 0; j <= deg; ++j) ders[k][j] *= f;
+    f *= double(deg - k);
+  }
+}
+
+// Row tables of derivatives 0..nd of the order-`order` basis on knots t at pts.
+void rows_at(const std::vector<double>& t, int order, const std::vector<double>& pts, int nd,
+             RowTable* out) {
+  int n = int(t.size()) - order;
+  for (int d = 0; d <= nd; ++d) {
+    out[d].rows = int(pts.size());
+    out[d].cols = n;
+    out[d].lo.assign(pts.size(), 0);
+    out[d].w.assign(pts.size() * kMaxW, 0.0);
+  }
+  for (size_t i = 0; i < pts.size(); ++i) {
+    int s = span_of(t, order, pts[i]);
+    double ders[3][kMaxW] = {{0}};
+    span_basis(t, order - 1, s, pts[i], nd, ders);
+    for (int d = 0; d <= nd; ++d) {
+      out[d].lo[i] = s - order + 1;
+      for (int r = 0; r < order; ++r) out[d].w[i * kMaxW + r] = ders[d][r];
+    }
+  }
+}
+
+// No-pivot LU of a dense n x n matrix (row-major), returned band-packed.
+lmvd_status band_lu(std::vector<double> A, int n, BandLU& lu, std::string& msg) {
+  int lower = 0, upper = 0;
+  double amax = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (A[size_t(i) * n + j] != 0.0) {
+        lower = std::max(lower, i - j);
+        upper = std::max(upper, j - i);
+        amax = std::max(amax, std::fabs(A[size_t(i) * n + j]));
+      }
+  if (lower > kMaxBand || upper > kMaxBand) {
+    msg = "bandwidth exceeds the LU table limit";
+    return LMVD_EUNSUPPORTED;
+  }
+  std::vector<double> Aorig = A;
+  for (int k = 0; k < n; ++k) {
+    double piv = A[size_t(k) * n + k];
+    if (!(std::fabs(piv) > 1e-12 * amax)) {
+      msg = "near-zero pivot in a no-pivot LU";
+      return LMVD_ENUMERIC;
+    }
+    for (int i = k + 1; i < std::min(n, k + lower + 1); ++i) {
+      double m = A[size_t(i) * n + k] / piv;
+      A[size_t(i) * n + k] = m;
+      for (int j = k + 1; j < std::min(n, k + upper + 1); ++j) A[size_t(i) * n + j] -= m * A[size_t(k) * n + j];
+    }
+  }
+  lu.n = n;
+  lu.lower = lower;
+  lu.upper = upper;
+  lu.lmul.assign(size_t(n) * kMaxBand, 0.0);
+  lu.u.assign(size_t(n) * (kMaxBand + 1), 0.0);
+  lu.uinv.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    for (int m = 1; m <= lower && i - m >= 0; ++m) lu.lmul[size_t(i) * kMaxBand + m - 1] = A[size_t(i) * n + i - m];
+    for (int q = 1; q <= upper && i + q < n; ++q) lu.u[size_t(i) * (kMaxBand + 1) + q] = A[size_t(i) * n + i + q];
+    lu.uinv[i] = 1.0 / A[size_t(i) * n + i];
+    lu.u[size_t(i) * (kMaxBand + 1)] = A[size_t(i) * n + i];
+  }
+  // residual check of the factorisation on a random vector
+  std::mt19937_64 rng(12345);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  std::vector<double> x(n), b(n, 0.0), y(n);
+  for (auto& v : x) v = U(rng);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) b[i] += Aorig[size_t(i) * n + j] * x[j];
+  for (int i = 0; i < n; ++i) {
+    double s = b[i];
+    for (int m = 1; m <= lower && i - m >= 0; ++m) s -= lu.lmul[size_t(i) * kMaxBand + m - 1] * y[i - m];
+    y[i] = s;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = y[i];
+    for (int q = 1; q <= upper && i + q < n; ++q) s -= lu.u[size_t(i) * (kMaxBand + 1) + q] * y[i + q];
+    y[i] = s * lu.uinv[i];
+  }
+  double err = 0.0, xm = 0.0;
+  for (int i = 0; i < n; ++i) {
+    err = std::max(err, std::fabs(y[i] - x[i]));
+    xm = std::max(xm, std::fabs(x[i]));
+  }
+  if (!(err <= 1e-9 * xm)) {
+    msg = "no-pivot LU is inaccurate";
+    return LMVD_ENUMERIC;
+  }
+  return LMVD_OK;
+}
+
+bool factor23(int n, FftPlan& f) {
+  if (n < 1) return false;
+  int a = 0, b = 0, m = n;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  while (m % 3 == 0) { m /= 3; ++b; }
+  if (m != 1) return false;
+  f.n = n;
+  f.nstages = 0;
+  while (a >= 3) { f.radix[f.nstages++] = 8; a -= 3; }
+  if (a == 2) f.radix[f.nstages++] = 4;
+  if (a == 1) f.radix[f.nstages++] = 2;
+  for (int i = 0; i < b; ++i) f.radix[f.nstages++] = 3;
+  if (f.nstages == 0) f.radix[f.nstages++] = 1;
+  int ns = 1;
+  for (int s = 0; s < f.nstages; ++s) {
+    f.ns[s] = ns;
+    ns *= f.radix[s];
+  }
+  f.tw.resize(size_t(2) * n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int t = 0; t < n; ++t) {
+    long double ang = -2.0L * pi * (long double)t / (long double)n;
+    f.tw[2 * t] = double(cosl(ang));
+    f.tw[2 * t + 1] = double(sinl(ang));
+  }
+  return true;
+}
+
+}  // namespace
+
+std::vector<double> dense(const RowTable& r) {
+  std::vector<double> D(size_t(r.rows) * r.cols, 0.0);
+  for (int i = 0; i < r.rows; ++i)
+    for (int q = 0; q < kMaxW; ++q) {
+      int j = r.lo[i] + q;
+      if (j >= 0 && j < r.cols) D[size_t(i) * r.cols + j] = r.w[size_t(i) * kMaxW + q];
+    }
+  return D;
+}
+
+lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& H, std::string& msg) {
+  H.cfg = cfg;
+  const int p = cfg.order;
+  if (p < 3 || p > 9) { msg = "order must be in 3..9"; return LMVD_EUNSUPPORTED; }
+  if (cfg.n1 < 2 || cfg.n3 < 2 || cfg.n1 % 2 || cfg.n3 % 2) { msg = "n1, n3 must be even >= 2"; return LMVD_EINVAL; }
+  if (cfg.n2 < p) { msg = "n2 must be >= order"; return LMVD_EINVAL; }
+  if (cfg.m1 < cfg.n1 || cfg.m3 < cfg.n3 || cfg.m1 % 2) { msg = "m1 >= n1 (even) and m3 >= n3 required"; return LMVD_EINVAL; }
+  if (!(cfg.L1 > 0 && cfg.L2 > 0 && cfg.L3 > 0 && cfg.dt > 0 && cfg.rho_l > 0 && cfg.rho_h > 0)) {
+    msg = "lengths, dt and densities must be positive";
+    return LMVD_EINVAL;
+  }
+  if (cfg.kf < 0 || cfg.plane_batch < 0) { msg = "kf and plane_batch must be >= 0"; return LMVD_EINVAL; }
+  if (!cfg.breakpoints) { msg = "breakpoints is NULL"; return LMVD_EINVAL; }
+  const int nb = cfg.n2 - p + 2;
+  H.breakpoints.assign(cfg.breakpoints, cfg.breakpoints + nb);
+  for (int i = 1; i < nb; ++i)
+    if (!(H.breakpoints[i] > H.breakpoints[i - 1])) { msg = "breakpoints must increase"; return LMVD_EINVAL; }
+  if (std::fabs(H.breakpoints.front() + 0.5 * cfg.L2) > 1e-12 * cfg.L2 ||
+      std::fabs(H.breakpoints.back() - 0.5 * cfg.L2) > 1e-12 * cfg.L2) {
+    msg = "breakpoints must end at -L2/2 and +L2/2";
+    return LMVD_EINVAL;
+  }
+  H.n2 = cfg.n2;
+  H.p = p;
+  H.nl = cfg.n1 / 2;
+  H.nn = cfg.n3 - 1;
+  H.hx = cfg.m1 / 2;
+  H.t = clamped(H.breakpoints, p);
+  H.ts = clamped(H.breakpoints, p + 1);
+  H.tau = greville_points(H.t, p);
+  H.tau_s = greville_points(H.ts, p + 1);
+  rows_at(H.t, p, H.tau, 2, H.E);
+  rows_at(H.ts, p + 1, H.tau, 0, &H.F0);
+  rows_at(H.t, p, H.tau_s, 1, H.G);
+  rows_at(H.ts, p + 1, H.tau_s, 2, H.Es);
+  H.dstar.resize(H.n2);
+  for (int j = 0; j < H.n2; ++j) H.dstar[j] = double(p) / (H.ts[j + p + 1] - H.ts[j + 1]);
+
+  // shared projections (values -> coefficients), end rows replaced
+  const int n2 = H.n2;
+  std::vector<double> E0 = dense(H.E[0]), E1 = dense(H.E[1]);
+  for (int kind = 0; kind < 3; ++kind) {
+    std::vector<double> A = E0;
+    if (kind > 0) {
+      for (int end : {0, n2 - 1}) {
+        for (int j = 0; j < n2; ++j) {
+          double v = (kind == 1) ? (j == end ? 1.0 : 0.0) : E1[size_t(end) * n2 + j];
+          A[size_t(end) * n2 + j] = v;
+        }
+      }
+    }
+    lmvd_status st = band_lu(A, n2, H.proj[kind], msg);
+    if (st != LMVD_OK) return st;
+  }
+
+  // band of A(k): union of E*_0, E*_1, E*_2 row supports
+  {
+    int lower = 0, upper = 0;
+    for (int i = 0; i <= n2; ++i)
+      for (int d = 0; d < 3; ++d)
+        for (int q = 0; q < kMaxW; ++q) {
+          int j = H.Es[d].lo[i] + q;
+          if (j < 0 || j > n2 || H.Es[d].w[size_t(i) * kMaxW + q] == 0.0) continue;
+          lower = std::max(lower, i - j);
+          upper = std::max(upper, j - i);
+        }
+    H.a_lower = lower;
+    H.a_upper = upper;
+    if (lower > 8 || upper > 8) { msg = "A(k) bandwidth exceeds 8"; return LMVD_EUNSUPPORTED; }
+    // no-pivot stability of A(k) over the range of k of this grid
+    double kmax = std::sqrt(std::pow(2 * M_PI * (H.nl - 1) / cfg.L1, 2) +
+                            std::pow(2 * M_PI * (cfg.n3 / 2 - 1) / cfg.L3, 2));
+    double kmin = 2 * M_PI / std::max(cfg.L1, cfg.L3);
+    std::vector<double> ks;
+    for (int s = 0; s <= 6; ++s) ks.push_back(kmin * std::pow(kmax / kmin, s / 6.0));
+    std::vector<double> Es0 = dense(H.Es[0]), Es1 = dense(H.Es[1]), Es2 = dense(H.Es[2]);
+    const int n = n2 + 1;
+    for (double k : ks) {
+      if (!(k > 0)) continue;
+      std::vector<double> A(size_t(n) * n);
+      for (size_t e = 0; e < A.size(); ++e) A[e] = Es2[e] - k * k * Es0[e];
+      for (int j = 0; j < n; ++j) {
+        A[j] = k * Es0[j] - Es1[j];
+        A[size_t(n2) * n + j] = k * Es0[size_t(n2) * n + j] + Es1[size_t(n2) * n + j];
+      }
+      BandLU tmp;
+      lmvd_status st = band_lu(A, n, tmp, msg);
+      if (st != LMVD_OK) { msg = "A(k): " + msg; return st; }
+    }
+  }
+
+  H.k1.resize(H.nl);
+  H.k3.resize(H.nn);
+  for (int l = 0; l < H.nl; ++l) H.k1[l] = 2.0 * M_PI * l / cfg.L1;
+  for (int i = 0; i < H.nn; ++i) {
+    int n = (i < cfg.n3 / 2) ? i : i - (cfg.n3 - 1);
+    H.k3[i] = 2.0 * M_PI * n / cfg.L3;
+  }
+  if (!factor23(cfg.m3, H.fz) || !factor23(H.hx, H.fx) || cfg.m3 > 1024 || H.hx > 1024) {
+    msg = "m3 and m1/2 must be 2^a 3^b <= 1024";
+    return LMVD_EUNSUPPORTED;
+  }
+  H.xtw.resize(size_t(2) * H.hx);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < H.hx; ++k) {
+    long double ang = -2.0L * pi * (long double)k / (long double)cfg.m1;
+    H.xtw[2 * k] = double(cosl(ang));
+    H.xtw[2 * k + 1] = double(sinl(ang));
+  }
+  return LMVD_OK;
+}
+
+}  // namespace lmvd

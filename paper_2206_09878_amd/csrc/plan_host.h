@@ -1,0 +1,75 @@
+// Host-side tables of the y-discretisation and the x-z transforms.
+//
+// Everything here runs on the CPU at plan creation; the device kernels read
+// the uploaded copies.  B-splines (App. C of the paper): order p on clamped
+// knots for every field except m2, order p+1 for m2; collocation at the
+// Greville abscissae.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lmvd.h"
+
+namespace lmvd {
+
+constexpr int kMaxW = 10;       // nonzeros of one collocation row (order <= 9 -> <= 10)
+constexpr int kMaxBand = 9;     // half-bandwidth limit of the no-pivot LU tables
+constexpr int kMaxStages = 12;  // FFT passes
+
+// A banded row table: row i has nonzeros in columns lo[i] .. lo[i]+kMaxW-1
+// (zero-padded); w[i*kMaxW + q] multiplies column lo[i]+q.
+struct RowTable {
+  std::vector<int32_t> lo;
+  std::vector<double> w;
+  int rows = 0;
+  int cols = 0;
+  double at(int i, int j) const {
+    int q = j - lo[i];
+    return (q >= 0 && q < kMaxW) ? w[size_t(i) * kMaxW + q] : 0.0;
+  }
+};
+
+// No-pivot banded LU of a shared (k-independent) matrix: row i of L has
+// multipliers lmul[i*kMaxBand + (m-1)] for row i-m (m = 1..lower), row i of
+// U has entries u[i*(kMaxBand+1) + q] for column i+q (q = 1..upper) and
+// uinv[i] = 1/U_ii.
+struct BandLU {
+  int n = 0, lower = 0, upper = 0;
+  std::vector<double> lmul, u, uinv;
+};
+
+struct FftPlan {
+  int n = 0;
+  int nstages = 0;
+  int radix[kMaxStages] = {0};
+  int ns[kMaxStages] = {0};
+  std::vector<double> tw;  // tw[2t], tw[2t+1] = cos, sin of -2 pi t / n
+};
+
+struct HostTables {
+  lmvd_config cfg{};
+  std::vector<double> breakpoints;
+  int n2 = 0, p = 0, nl = 0, nn = 0, hx = 0;
+  std::vector<double> t, ts;         // knots of B (order p) and B* (order p+1)
+  std::vector<double> tau, tau_s;    // Greville points
+  RowTable E[3];                     // d^d B_j (tau_i)
+  RowTable F0;                       // B*_j (tau_i)
+  RowTable G[2];                     // d^d B_j (tau*_i)
+  RowTable Es[3];                    // d^d B*_j (tau*_i)
+  std::vector<double> dstar;         // (D* c)_j = dstar[j] (c_{j+1} - c_j)
+  BandLU proj[3];                    // interpolation, Dirichlet rows, Neumann rows
+  int a_lower = 0, a_upper = 0;      // band of A(k) = E*_2 - k^2 E*_0 with Robin rows
+  std::vector<double> k1, k3;        // k1[l], k3[n_idx]
+  FftPlan fz, fx;                    // complex FFTs of size m3 and m1/2
+  std::vector<double> xtw;           // cos, sin of -2 pi k / m1, k < m1/2
+};
+
+// Build all host tables.  Returns LMVD_OK or an error with `msg` set.
+lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& out, std::string& msg);
+
+// Dense copy of a row table (row-major rows x cols).
+std::vector<double> dense(const RowTable& r);
+
+}  // namespace lmvd

@@ -1,0 +1,298 @@
+"""Python binding of the HIP library (ctypes; argument marshalling only).
+
+Every step of the substep runs in the library's kernels; torch supplies device
+memory and the current stream.  The binding loads the in-tree
+``_lmvd.so`` and raises if it is missing: there is no CPU fallback.
+
+Spectral arrays are torch.complex128 tensors of shape [ny, N3-1, N1/2]
+(index [j, n_idx, l]) on the GPU; plane means are float64 [n2].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_lmvd.so")
+_lib = None
+
+
+class LmvdError(RuntimeError):
+    pass
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n1", ctypes.c_int32), ("n3", ctypes.c_int32), ("n2", ctypes.c_int32), ("order", ctypes.c_int32),
+        ("m1", ctypes.c_int32), ("m3", ctypes.c_int32),
+        ("L1", ctypes.c_double), ("L2", ctypes.c_double), ("L3", ctypes.c_double),
+        ("breakpoints", ctypes.POINTER(ctypes.c_double)),
+        ("dt", ctypes.c_double), ("mu", ctypes.c_double), ("rhoD", ctypes.c_double), ("g", ctypes.c_double),
+        ("rho_l", ctypes.c_double), ("rho_h", ctypes.c_double),
+        ("beta_n", ctypes.c_double), ("beta_p", ctypes.c_double),
+        ("kf", ctypes.c_int32), ("plane_batch", ctypes.c_int32),
+    ]
+
+
+class SubstepArgs(ctypes.Structure):
+    _fields_ = [
+        ("stage", ctypes.c_int32), ("kf", ctypes.c_int32), ("guess_mode", ctypes.c_int32),
+        ("phi2", ctypes.c_void_p), ("omega2", ctypes.c_void_p), ("z", ctypes.c_void_p),
+        ("m1bar", ctypes.c_void_p), ("m3bar", ctypes.c_void_p),
+        ("phi2_out", ctypes.c_void_p), ("omega2_out", ctypes.c_void_p), ("z_out", ctypes.c_void_p),
+        ("m1bar_out", ctypes.c_void_p), ("m3bar_out", ctypes.c_void_p),
+        ("rhs_phi2_prev", ctypes.c_void_p), ("rhs_omega2_prev", ctypes.c_void_p), ("zt_prev", ctypes.c_void_p),
+        ("rhs_m1_prev", ctypes.c_void_p), ("rhs_m3_prev", ctypes.c_void_p),
+        ("rhs_phi2", ctypes.c_void_p), ("rhs_omega2", ctypes.c_void_p), ("zt", ctypes.c_void_p),
+        ("rhs_m1", ctypes.c_void_p), ("rhs_m3", ctypes.c_void_p),
+        ("z_hist", ctypes.c_void_p * 3),
+        ("md", ctypes.c_void_p * 3), ("mc", ctypes.c_void_p * 3),
+    ]
+
+
+EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_sizes", "lmvd_substep",
+           "lmvd_to_physical", "lmvd_to_spectral", "lmvd_project", "lmvd_evaluate", "lmvd_md", "lmvd_mc",
+           "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop"]
+
+
+def library():
+    """Load the built library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise LmvdError(f"HIP library not built: {_LIB_PATH} (run python -m paper_2206_09878_amd.build)")
+        lib = ctypes.CDLL(_LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        lib.lmvd_status_string.restype = ctypes.c_char_p
+        lib.lmvd_status_string.argtypes = [ctypes.c_int]
+        lib.lmvd_plan_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(vp)]
+        lib.lmvd_plan_destroy.argtypes = [vp]
+        lib.lmvd_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_size_t)]
+        lib.lmvd_substep.argtypes = [vp, ctypes.POINTER(SubstepArgs), vp, vp]
+        lib.lmvd_to_physical.argtypes = [vp, vp, vp, vp, vp]
+        lib.lmvd_to_spectral.argtypes = [vp, vp, vp, vp, vp]
+        lib.lmvd_project.argtypes = [vp, i32, vp, vp, vp]
+        lib.lmvd_evaluate.argtypes = [vp, i32, i32, vp, vp, vp]
+        lib.lmvd_md.argtypes = [vp] * 8 + [vp, vp]
+        lib.lmvd_mc.argtypes = [vp] * 7
+        lib.lmvd_host_tables.argtypes = [ctypes.POINTER(Config), vp, vp, vp, vp, vp]
+        lib.lmvd_profile_start.argtypes = [vp, i32, i32]
+        lib.lmvd_profile_stop.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_double)]
+        for name in EXPORTS:
+            if name != "lmvd_status_string":
+                getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        msg = library().lmvd_status_string(st).decode()
+        raise LmvdError(f"{what}: {msg} ({st})")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_config(w, plane_batch: int = 0):
+    """ctypes Config from a workload (paper_2206_09878_amd.workloads.Workload).
+    The returned object keeps its breakpoint buffer alive."""
+    bp = np.ascontiguousarray(w.breakpoints, dtype=np.float64)
+    c = Config(w.n1, w.n3, w.n2, w.order, w.m1, w.m3, w.L1, w.L2, w.L3,
+               bp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), w.dt, w.mu, w.rhoD, w.g,
+               w.rho_l, w.rho_h, w.beta_n, w.beta_p, w.kf, plane_batch)
+    c._bp = bp
+    return c
+
+
+def host_tables(w):
+    """Greville points and E_d matrices of the plan builder (host only)."""
+    cfg = make_config(w)
+    n2 = w.n2
+    tau = np.zeros(n2)
+    taus = np.zeros(n2 + 1)
+    E = [np.zeros((n2, n2)) for _ in range(3)]
+    st = library().lmvd_host_tables(ctypes.byref(cfg), tau.ctypes.data, taus.ctypes.data,
+                                    E[0].ctypes.data, E[1].ctypes.data, E[2].ctypes.data)
+    _check(st, "lmvd_host_tables")
+    return tau, taus, E
+
+
+class Plan:
+    """A plan plus its workspace on the current GPU."""
+
+    def __init__(self, w, plane_batch: int = 0):
+        import torch
+        self.torch = torch
+        self.w = w
+        self.cfg = make_config(w, plane_batch)
+        h = ctypes.c_void_p()
+        _check(library().lmvd_plan_create(ctypes.byref(self.cfg), ctypes.byref(h)), "lmvd_plan_create")
+        self.handle = h
+        se, ss, wb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(library().lmvd_sizes(h, ctypes.byref(se), ctypes.byref(ss), ctypes.byref(wb)), "lmvd_sizes")
+        self.sfield_elems, self.sfield_star_elems, self.workspace_bytes = se.value, ss.value, wb.value
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device="cuda")
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off:off + self.workspace_bytes]
+        self.shape = w.shape
+        self.shape_star = w.shape_star
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                library().lmvd_plan_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------------
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def empty(self, star=False):
+        return self.torch.empty(self.shape_star if star else self.shape, dtype=self.torch.complex128,
+                                device="cuda")
+
+    def to_dev(self, a):
+        t = self.torch.from_numpy(np.ascontiguousarray(a))
+        return t.to("cuda")
+
+    @staticmethod
+    def _req(t, dtype):
+        if t is None or not t.is_cuda or not t.is_contiguous() or t.dtype != dtype:
+            raise LmvdError("expected a contiguous CUDA tensor of dtype %s" % dtype)
+
+    # -- the substep -------------------------------------------------------------
+    def substep(self, stage, phi2, omega2, z, m1bar, m3bar, *, z_out, phi2_out=None, omega2_out=None,
+                m1bar_out=None, m3bar_out=None, hist=None, kf=-1, guess_mode=0, rhs_prev=None, zt_prev=None,
+                rhs_out=None, zt_out=None, md=None, mc=None):
+        """One substep; see lmvd.h.  rhs_prev / rhs_out are dicts with keys
+        phi2, omega2, m1bar, m3bar.  Outputs default to in-place (except z_out)."""
+        torch = self.torch
+        c128, f64 = torch.complex128, torch.float64
+        for t in (phi2, omega2, z, z_out):
+            self._req(t, c128)
+        for t in (m1bar, m3bar):
+            self._req(t, f64)
+        a = SubstepArgs()
+        a.stage, a.kf, a.guess_mode = stage, kf, guess_mode
+        a.phi2, a.omega2, a.z = _ptr(phi2), _ptr(omega2), _ptr(z)
+        a.m1bar, a.m3bar = _ptr(m1bar), _ptr(m3bar)
+        a.phi2_out = _ptr(phi2_out if phi2_out is not None else phi2)
+        a.omega2_out = _ptr(omega2_out if omega2_out is not None else omega2)
+        a.z_out = _ptr(z_out)
+        a.m1bar_out = _ptr(m1bar_out if m1bar_out is not None else m1bar)
+        a.m3bar_out = _ptr(m3bar_out if m3bar_out is not None else m3bar)
+        if rhs_prev is not None:
+            a.rhs_phi2_prev, a.rhs_omega2_prev = _ptr(rhs_prev["phi2"]), _ptr(rhs_prev["omega2"])
+            a.rhs_m1_prev, a.rhs_m3_prev = _ptr(rhs_prev["m1bar"]), _ptr(rhs_prev["m3bar"])
+        a.zt_prev = _ptr(zt_prev)
+        if rhs_out is not None:
+            a.rhs_phi2, a.rhs_omega2 = _ptr(rhs_out["phi2"]), _ptr(rhs_out["omega2"])
+            a.rhs_m1, a.rhs_m3 = _ptr(rhs_out["m1bar"]), _ptr(rhs_out["m3bar"])
+        a.zt = _ptr(zt_out)
+        if hist is not None:
+            for i in range(3):
+                a.z_hist[i] = hist[i].data_ptr()
+        if md is not None:
+            for i in range(3):
+                a.md[i] = md[i].data_ptr()
+        if mc is not None:
+            for i in range(3):
+                a.mc[i] = mc[i].data_ptr()
+        _check(library().lmvd_substep(self.handle, ctypes.byref(a), _ptr(self.ws), self._stream()),
+               "lmvd_substep")
+
+    # -- timing hook -----------------------------------------------------------------
+    KERNEL_CLASSES = ("eval_zinv", "xpass", "zfwd", "proj", "solveA", "rhs")
+
+    def profile_start(self, cls: int, max_launches: int = 65536):
+        _check(library().lmvd_profile_start(self.handle, cls, max_launches), "lmvd_profile_start")
+
+    def profile_stop(self):
+        """(total_ms, launches, algorithmic_bytes) of the timed kernel class."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(library().lmvd_profile_stop(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
+               "lmvd_profile_stop")
+        return ms.value, n.value, b.value
+
+    # -- operator entry points ------------------------------------------------------
+    def to_physical(self, values):
+        w = self.w
+        out = self.torch.empty((w.n2, w.m3, w.m1), dtype=self.torch.float64, device="cuda")
+        _check(library().lmvd_to_physical(self.handle, _ptr(values), _ptr(out), _ptr(self.ws), self._stream()),
+               "lmvd_to_physical")
+        return out
+
+    def to_spectral(self, phys):
+        out = self.empty()
+        _check(library().lmvd_to_spectral(self.handle, _ptr(phys), _ptr(out), _ptr(self.ws), self._stream()),
+               "lmvd_to_spectral")
+        return out
+
+    def project(self, kind, values):
+        out = self.empty()
+        _check(library().lmvd_project(self.handle, kind, _ptr(values), _ptr(out), self._stream()), "lmvd_project")
+        return out
+
+    def evaluate(self, deriv, coeffs, star=False):
+        out = self.empty()
+        _check(library().lmvd_evaluate(self.handle, deriv, int(star), _ptr(coeffs), _ptr(out), self._stream()),
+               "lmvd_evaluate")
+        return out
+
+    def md(self, phi2, omega2, m1bar, m3bar):
+        m1, m2, m3 = self.empty(), self.empty(True), self.empty()
+        _check(library().lmvd_md(self.handle, _ptr(phi2), _ptr(omega2), _ptr(m1bar), _ptr(m3bar), _ptr(m1),
+                                 _ptr(m2), _ptr(m3), _ptr(self.ws), self._stream()), "lmvd_md")
+        return m1, m2, m3
+
+    def mc(self, rhot):
+        m1, m2, m3 = self.empty(), self.empty(True), self.empty()
+        _check(library().lmvd_mc(self.handle, _ptr(rhot), _ptr(m1), _ptr(m2), _ptr(m3), _ptr(self.ws),
+                                 self._stream()), "lmvd_mc")
+        return m1, m2, m3
+
+
+class Stepper:
+    """Holds the device state of one simulation and advances it by substeps
+    (the z history ring, stored RHS and z_t between the two stages)."""
+
+    def __init__(self, plan: Plan, inputs: dict, stage: int = 0):
+        torch = plan.torch
+        self.p = plan
+        dev = plan.to_dev
+        self.phi2, self.omega2 = dev(inputs["phi2"]), dev(inputs["omega2"])
+        self.z = dev(inputs["z"])
+        self.m1bar, self.m3bar = dev(inputs["m1bar"]), dev(inputs["m3bar"])
+        self.hist = [dev(h) for h in inputs["hist"]]
+        self.stage = stage
+        self.rhs = {k: (plan.empty() if k in ("phi2", "omega2") else torch.empty(plan.w.n2, dtype=torch.float64,
+                                                                                     device="cuda"))
+                    for k in ("phi2", "omega2", "m1bar", "m3bar")}
+        self.zt = plan.empty()
+        if stage == 1:
+            rp = inputs["rhs_prev"]
+            for k in self.rhs:
+                self.rhs[k].copy_(dev(rp[k]))
+            self.zt.copy_(dev(inputs["zt_prev"]))
+        self.zt_next = plan.empty()
+
+    def substep(self, kf=-1):
+        p = self.p
+        z_new = self.hist[2]          # the oldest history slot is free after this substep
+        if self.stage == 0:
+            p.substep(0, self.phi2, self.omega2, self.z, self.m1bar, self.m3bar, z_out=z_new, hist=self.hist,
+                      kf=kf, rhs_out=self.rhs, zt_out=self.zt)
+        else:
+            p.substep(1, self.phi2, self.omega2, self.z, self.m1bar, self.m3bar, z_out=z_new, hist=self.hist,
+                      kf=kf, rhs_prev=self.rhs, zt_prev=self.zt, zt_out=self.zt_next)
+        self.hist = [self.z, self.hist[0], self.hist[1]]
+        self.z = z_new
+        self.stage = 1 - self.stage

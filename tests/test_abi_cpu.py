@@ -1,0 +1,75 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, validates configurations, and its host plan builder (own B-spline
+code) agrees with the oracle's spline spaces."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2206_09878_amd import lmvd
+from paper_2206_09878_amd.workloads import workload
+from oracle.bspline import SplineSpaces
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "lmvd.h")).read()
+    return sorted(set(re.findall(r"\b(lmvd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lmvd.library()
+    syms = declared_symbols()
+    assert "lmvd_substep" in syms and len(syms) >= 10
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) <= set(lmvd.EXPORTS)
+
+
+def test_status_strings():
+    lib = lmvd.library()
+    assert lib.lmvd_status_string(0) == b"ok"
+    assert b"invalid" in lib.lmvd_status_string(-1)
+
+
+@pytest.mark.parametrize("name,n,n2", [("small", None, None), ("small", 16, 25), ("mixing128", 48, 65)])
+def test_host_tables_match_oracle(name, n, n2):
+    w = workload(name, n=n, n2=n2)
+    tau, taus, E = lmvd.host_tables(w)
+    sp = SplineSpaces(w.breakpoints, w.order)
+    assert np.abs(tau - sp.tau).max() < 1e-14 * w.L2
+    assert np.abs(taus - sp.tau_s).max() < 1e-14 * w.L2
+    for d in range(3):
+        scale = np.abs(sp.E[d]).max()
+        assert np.abs(E[d] - sp.E[d]).max() < 1e-12 * scale, d
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n1", 31, -1),          # odd
+    ("m1", 20, -1),          # m1 < n1
+    ("order", 12, -4),       # unsupported order
+    ("dt", -1.0, -1),
+    ("m3", 5 * 48, None),    # m3 not 2^a 3^b -> unsupported
+])
+def test_plan_create_rejects_bad_configs(field, value, status):
+    w = workload("small")
+    cfg = lmvd.make_config(w)
+    setattr(cfg, field, value)
+    h = ctypes.c_void_p()
+    st = lmvd.library().lmvd_plan_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert st != 0
+    if status is not None:
+        assert st == status
+
+
+def test_bad_breakpoints_rejected():
+    w = workload("small")
+    cfg = lmvd.make_config(w)
+    bp = np.array(w.breakpoints)
+    bp[3], bp[4] = bp[4], bp[3]
+    cfg.breakpoints = bp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    assert lmvd.library().lmvd_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == -1

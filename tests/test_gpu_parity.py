@@ -1,0 +1,209 @@
+"""GPU parity: the HIP library against the oracle, element by element, on the
+same seeded inputs.  Bar: relative max-norm difference per field <= 1e-11.
+
+Every call goes through the C ABI (ctypes binding)."""
+import numpy as np
+import pytest
+
+from oracle.fourier import to_physical, to_spectral
+from oracle.lmvd import Plan as OPlan, apply, curl_free_momentum, divergence_free_momentum, substep
+from paper_2206_09878_amd.workloads import make_inputs, workload
+from tests.conftest import oracle_config
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def gplan(w, **kw):
+    from paper_2206_09878_amd.lmvd import Plan
+    return Plan(w, **kw)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def hermitian(rng, shape):
+    V = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    nn = shape[1]
+    for ni in range(1, (nn + 1) // 2):
+        V[:, nn - ni, 0] = np.conj(V[:, ni, 0])
+    V[:, 0, 0] = V[:, 0, 0].real
+    return V
+
+
+GRIDS = [("small", None, None), ("small", 48, 17), ("small", 64, 33), ("mixing128", 128, 17),
+         ("rt512", 512, 9)]
+
+
+@pytest.mark.parametrize("name,n,n2", GRIDS)
+def test_transforms(torch, name, n, n2):
+    w = workload(name, n=n, n2=n2)
+    p = gplan(w)
+    rng = np.random.default_rng(1)
+    V = hermitian(rng, w.shape)
+    ref = to_physical(V, w.m1, w.m3)
+    got = host(p.to_physical(p.to_dev(V)))
+    assert rel(got, ref) < TOL
+    u = rng.standard_normal((w.n2, w.m3, w.m1))
+    refV = to_spectral(u, w.n1, w.n3)
+    gotV = host(p.to_spectral(p.to_dev(u)))
+    assert rel(gotV, refV) < TOL
+
+
+@pytest.mark.parametrize("name,n,n2", [("small", None, None), ("small", 48, 49)])
+def test_evaluate_and_project(torch, name, n, n2):
+    w = workload(name, n=n, n2=n2)
+    p = gplan(w)
+    op = OPlan(oracle_config(w))
+    rng = np.random.default_rng(2)
+    C = hermitian(rng, w.shape)
+    Cs = hermitian(rng, w.shape_star)
+    for d in range(3):
+        assert rel(host(p.evaluate(d, p.to_dev(C))), apply(op.sp.E[d], C)) < TOL
+    assert rel(host(p.evaluate(0, p.to_dev(Cs), star=True)), apply(op.sp.F[0], Cs)) < TOL
+    for kind, name_ in enumerate(("plain", "dirichlet", "neumann")):
+        assert rel(host(p.project(kind, p.to_dev(C))), op.project(C, name_)) < TOL
+
+
+@pytest.mark.parametrize("name,n,n2", [("small", None, None), ("small", 48, 49), ("mixing128", 64, 65)])
+def test_md_mc(torch, name, n, n2):
+    w = workload(name, n=n, n2=n2)
+    p = gplan(w)
+    op = OPlan(oracle_config(w))
+    inp = make_inputs(w, seed=3)
+    ref = divergence_free_momentum(op, inp["phi2"], inp["omega2"], inp["m1bar"], inp["m3bar"])
+    got = p.md(p.to_dev(inp["phi2"]), p.to_dev(inp["omega2"]), p.to_dev(inp["m1bar"]), p.to_dev(inp["m3bar"]))
+    for g, r in zip(got, ref):
+        assert rel(host(g), r) < TOL
+    rng = np.random.default_rng(4)
+    rhot = hermitian(rng, w.shape)
+    ref = curl_free_momentum(op, rhot)
+    got = p.mc(p.to_dev(rhot))
+    for g, r in zip(got, ref[:3]):
+        assert rel(host(g), r) < TOL
+
+
+def run_pair(w, stage, seed=0, kf=None, guess_mode=0, plane_batch=0):
+    """One substep on the GPU and in the oracle from the same inputs."""
+    import torch
+    p = gplan(w, plane_batch=plane_batch)
+    op = OPlan(oracle_config(w))
+    inp = make_inputs(w, seed=seed, stage=stage)
+    st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
+    kw = {}
+    if stage == 1:
+        kw = dict(rhs_prev=inp["rhs_prev"], zt_prev=inp["zt_prev"])
+    ref = substep(op, st, stage, hist=inp["hist"], kf=kf, guess="zero" if guess_mode else "bdf",
+                  diagnostics=True, **kw)
+    d = {k: p.to_dev(v) for k, v in st.items()}
+    hist = [p.to_dev(h) for h in inp["hist"]]
+    z_out = p.empty()
+    rhs = {"phi2": p.empty(), "omega2": p.empty(),
+           "m1bar": torch.empty(w.n2, dtype=torch.float64, device="cuda"),
+           "m3bar": torch.empty(w.n2, dtype=torch.float64, device="cuda")}
+    zt = p.empty()
+    md = [p.empty(), p.empty(True), p.empty()]
+    mc = [p.empty(), p.empty(True), p.empty()]
+    args = dict(z_out=z_out, hist=hist, kf=-1 if kf is None else kf, guess_mode=guess_mode, rhs_out=rhs,
+                zt_out=zt, md=md, mc=mc)
+    if stage == 1:
+        args["rhs_prev"] = {k: p.to_dev(v) for k, v in inp["rhs_prev"].items()}
+        args["zt_prev"] = p.to_dev(inp["zt_prev"])
+    p.substep(stage, d["phi2"], d["omega2"], d["z"], d["m1bar"], d["m3bar"], **args)
+    torch.cuda.synchronize()
+    got = dict(phi2=host(d["phi2"]), omega2=host(d["omega2"]), z=host(z_out), m1bar=host(d["m1bar"]),
+               m3bar=host(d["m3bar"]), zt=host(zt), rhs={k: host(v) for k, v in rhs.items()},
+               md=[host(x) for x in md], mc=[host(x) for x in mc])
+    return got, ref
+
+
+class scipy_fft_in_oracle:
+    """Run the oracle with scipy.fft in place of numpy.fft: the same sums with
+    a different rounding.  The spread between the two oracle runs measures how
+    much float64 rounding the quantity itself amplifies."""
+
+    def __enter__(self):
+        import types
+        import scipy.fft as sf
+        import oracle.fourier as F
+        self.F, self.np = F, F.np
+        shim = types.SimpleNamespace(**{k: getattr(np, k) for k in dir(np) if not k.startswith("__")})
+        shim.fft = types.SimpleNamespace(ifft2=lambda x, axes: sf.ifft2(x, axes=axes),
+                                         fft2=lambda x, axes: sf.fft2(x, axes=axes))
+        F.np = shim
+        return self
+
+    def __exit__(self, *exc):
+        self.F.np = self.np
+
+
+def rhs_tolerances(w, stage, seed, kf=None, ref=None):
+    """Per-field bound for the stage RHS outputs: 1e-11, or 4x the oracle's own
+    numpy-vs-scipy FFT spread where derivatives amplify rounding more."""
+    op = OPlan(oracle_config(w))
+    inp = make_inputs(w, seed=seed, stage=stage)
+    st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
+    kw = dict(rhs_prev=inp["rhs_prev"], zt_prev=inp["zt_prev"]) if stage == 1 else {}
+    with scipy_fft_in_oracle():
+        alt = substep(op, st, stage, hist=inp["hist"], kf=kf, **kw)
+    return {k: max(TOL, 4.0 * rel(alt["rhs"][k], ref["rhs"][k])) for k in alt["rhs"]}
+
+
+def check_pair(got, ref, tol=TOL, rhs_tol=None):
+    errs = {}
+    for k in ("phi2", "omega2", "z", "m1bar", "m3bar"):
+        errs[k] = rel(got[k], ref["state"][k])
+    errs["zt"] = rel(got["zt"], ref["zt"])
+    for k in ("phi2", "omega2", "m1bar", "m3bar"):
+        errs["rhs_" + k] = rel(got["rhs"][k], ref["rhs"][k])
+    for i in range(3):
+        errs[f"md{i}"] = rel(got["md"][i], ref["diag"]["md"][i])
+        errs[f"mc{i}"] = rel(got["mc"][i], ref["diag"]["mc"][i])
+    tols = {k: tol for k in errs}
+    if rhs_tol:
+        for k, v in rhs_tol.items():
+            tols["rhs_" + k] = v
+    bad = {k: (v, tols[k]) for k, v in errs.items() if not v < tols[k]}
+    assert not bad, (bad, errs)
+    return errs
+
+
+@pytest.mark.parametrize("stage", [0, 1])
+def test_substep_small(torch, stage):
+    w = workload("small")
+    got, ref = run_pair(w, stage)
+    check_pair(got, ref)
+
+
+@pytest.mark.parametrize("kf,guess_mode", [(0, 0), (1, 0), (3, 1)])
+def test_substep_iteration_counts(torch, kf, guess_mode):
+    w = workload("small", n=16, n2=25)
+    got, ref = run_pair(w, 0, seed=5, kf=kf, guess_mode=guess_mode)
+    check_pair(got, ref)
+
+
+def test_substep_ragged_plane_batches(torch):
+    w = workload("small", n=24, n2=33)       # M = 36: radices 2, 3, 3 / 2, 9
+    got, ref = run_pair(w, 1, seed=6, plane_batch=7)
+    check_pair(got, ref)
+
+
+@pytest.mark.parametrize("name,n,n2", [("mixing128", 64, 65), ("adjoint96", 96, 97)])
+def test_substep_mid(torch, name, n, n2):
+    w = workload(name, n=n, n2=n2)
+    got, ref = run_pair(w, 0, seed=7)
+    check_pair(got, ref, rhs_tol=rhs_tolerances(w, 0, 7, ref=ref))
