@@ -1,0 +1,251 @@
+// Register-resident line FFTs with compile-time sizes.
+//
+// A line of N complex points is held by T threads, E = N/T points each.  The
+// transform is a Stockham decomposition N = R0 R1 R2 R3 (R = 1 for unused
+// stages) in which every radix divides E, so each thread owns whole
+// butterflies in every stage: stage s, radix R, span Ns = R0...R_{s-1};
+// thread tl owns butterflies j = tl + T c (c < E/R), whose inputs are
+// x[j + r N/R] and whose outputs go to y[(j/Ns) Ns R + j%Ns + r Ns] after the
+// twiddle W_{Ns R}^{r (j%Ns)}.  Between stages the data crosses LDS once, as
+// separate real and imaginary planes of doubles.
+//
+// Register order: v[c*R + r] is input r of butterfly c of the current stage
+// (stage 0: v[r] = x[tl + T r]); after run(), v[c*Rl + r] is output r of
+// butterfly c of the last stage, at position tl + T c + r N/Rl (the last
+// stage has Ns Rl = N).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+
+namespace lmvd {
+namespace rf {
+
+// ---- small DFTs in registers -------------------------------------------------
+
+template <int R, int DIR>
+struct Dft;
+
+template <int DIR>
+struct Dft<1, DIR> {
+  __device__ __forceinline__ static void run(double2*) {}
+};
+template <int DIR>
+struct Dft<2, DIR> {
+  __device__ __forceinline__ static void run(double2* v) { small_dft<2, -1>(v); }
+};
+template <int DIR>
+struct Dft<3, DIR> {
+  __device__ __forceinline__ static void run(double2* v) { dft3<DIR>(v); }
+};
+template <int DIR>
+struct Dft<4, DIR> {
+  __device__ __forceinline__ static void run(double2* v) { dft4<DIR>(v[0], v[1], v[2], v[3]); }
+};
+template <int DIR>
+struct Dft<8, DIR> {
+  __device__ __forceinline__ static void run(double2* v) { dft8<DIR>(v); }
+};
+
+constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
+// Prime-factor (Good-Thomas) composition for coprime A, B: no inner twiddles.
+// x[(n1 B + n2 A) mod AB] -> a[n1][n2]; DFT_B along n2, DFT_A along n1;
+// X[(k1 B tB + k2 A tA) mod AB] = a[k1][k2], tB = B^{-1} mod A, tA = A^{-1} mod B.
+template <int A, int B, int DIR>
+__device__ __forceinline__ void dft_pfa(double2* v) {
+  constexpr int N = A * B;
+  constexpr int tB = inv_mod(B % A, A), tA = inv_mod(A % B, B);
+  double2 a[A][B];
+#pragma unroll
+  for (int n1 = 0; n1 < A; ++n1)
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) a[n1][n2] = v[(n1 * B + n2 * A) % N];
+#pragma unroll
+  for (int n1 = 0; n1 < A; ++n1) Dft<B, DIR>::run(a[n1]);
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) {
+    double2 col[A];
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) col[n1] = a[n1][k2];
+    Dft<A, DIR>::run(col);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) a[k1][k2] = col[k1];
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < A; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) v[(k1 * B * tB + k2 * A * tA) % N] = a[k1][k2];
+}
+
+template <int DIR>
+struct Dft<6, DIR> {
+  __device__ __forceinline__ static void run(double2* v) { dft_pfa<2, 3, DIR>(v); }
+};
+template <int DIR>
+struct Dft<12, DIR> {
+  __device__ __forceinline__ static void run(double2* v) { dft_pfa<4, 3, DIR>(v); }
+};
+template <int DIR>
+struct Dft<24, DIR> {
+  __device__ __forceinline__ static void run(double2* v) { dft_pfa<8, 3, DIR>(v); }
+};
+
+// ---- stages --------------------------------------------------------------------
+
+template <int N, int T, int R, int NS>
+__device__ __forceinline__ int out_pos(int tl, int c, int r) {
+  const int j = tl + T * c;
+  return (j / NS) * NS * R + (j % NS) + r * NS;
+}
+template <int N, int T, int R>
+__device__ __forceinline__ int in_pos(int tl, int c, int r) {
+  return tl + T * c + r * (N / R);
+}
+
+// twiddle + DFT of every butterfly of one stage (tw[t] = exp(-2 pi i t / N))
+template <int N, int T, int DIR, int R, int NS>
+__device__ __forceinline__ void stage(double2* v, int tl, const double2* __restrict__ tw) {
+  constexpr int E = N / T;
+  constexpr int NB = E / R;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (NS > 1) {
+      const int jm = (tl + T * c) % NS;
+      const int step = jm * (N / (NS * R));
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        double2 w = tw[r * step];
+        if (DIR > 0) w.y = -w.y;
+        v[c * R + r] = cmul(v[c * R + r], w);
+      }
+    }
+    Dft<R, DIR>::run(v + c * R);
+  }
+}
+
+// LDS addressing of position p of the line owned by this thread group
+template <int PADDIV>
+__device__ __forceinline__ int padded(int p) {
+  return PADDIV > 0 ? p + p / PADDIV : p;
+}
+
+// Move stage outputs (radix Ra, span NSa) to the next stage's inputs (radix Rb)
+// through LDS, real then imaginary part.  `base` is this line's LDS offset.
+template <int N, int T, int Ra, int NSa, int Rb, int PADDIV>
+__device__ __forceinline__ void exchange(double2* v, double* lds, int base, int tl) {
+  constexpr int E = N / T;
+  double tmp[E];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < E / Ra; ++c)
+#pragma unroll
+    for (int r = 0; r < Ra; ++r) lds[base + padded<PADDIV>(out_pos<N, T, Ra, NSa>(tl, c, r))] = v[c * Ra + r].x;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < E / Rb; ++c)
+#pragma unroll
+    for (int r = 0; r < Rb; ++r) tmp[c * Rb + r] = lds[base + padded<PADDIV>(in_pos<N, T, Rb>(tl, c, r))];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < E / Ra; ++c)
+#pragma unroll
+    for (int r = 0; r < Ra; ++r) lds[base + padded<PADDIV>(out_pos<N, T, Ra, NSa>(tl, c, r))] = v[c * Ra + r].y;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < E / Rb; ++c)
+#pragma unroll
+    for (int r = 0; r < Rb; ++r) {
+      const int k = c * Rb + r;
+      v[k] = make_double2(tmp[k], lds[base + padded<PADDIV>(in_pos<N, T, Rb>(tl, c, r))]);
+    }
+}
+
+// Ordering point between LDS writes and reads of one wavefront.  LDS
+// operations of a wave are performed in issue order, so threads of one wave
+// exchanging through LDS need only keep the compiler from reordering.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ordering for a line of T consecutive threads: wave-level when every line
+// lies within one wavefront (T divides 64), else a block barrier.
+template <int T>
+__device__ __forceinline__ void line_sync() {
+  if constexpr (64 % T == 0) wave_sync();
+  else __syncthreads();
+}
+
+// Exchange for lines of T consecutive threads: complex values.
+template <int N, int T, int Ra, int NSa, int Rb, int PADDIV>
+__device__ __forceinline__ void exchange_wave(double2* v, double2* lds, int base, int tl) {
+  constexpr int E = N / T;
+  line_sync<T>();
+#pragma unroll
+  for (int c = 0; c < E / Ra; ++c)
+#pragma unroll
+    for (int r = 0; r < Ra; ++r) lds[base + padded<PADDIV>(out_pos<N, T, Ra, NSa>(tl, c, r))] = v[c * Ra + r];
+  line_sync<T>();
+#pragma unroll
+  for (int c = 0; c < E / Rb; ++c)
+#pragma unroll
+    for (int r = 0; r < Rb; ++r) v[c * Rb + r] = lds[base + padded<PADDIV>(in_pos<N, T, Rb>(tl, c, r))];
+}
+
+template <int N, int T, int DIR, int R0, int R1, int R2, int R3, int PADDIV>
+__device__ __forceinline__ void run_wave(double2* v, double2* lds, int base, int tl, const double2* __restrict__ tw) {
+  static_assert(R0 * R1 * R2 * R3 == N, "radices must multiply to N");
+  constexpr int NS1 = R0, NS2 = R0 * R1, NS3 = R0 * R1 * R2;
+  stage<N, T, DIR, R0, 1>(v, tl, tw);
+  if constexpr (R1 > 1) {
+    exchange_wave<N, T, R0, 1, R1, PADDIV>(v, lds, base, tl);
+    stage<N, T, DIR, R1, NS1>(v, tl, tw);
+  }
+  if constexpr (R2 > 1) {
+    exchange_wave<N, T, R1, NS1, R2, PADDIV>(v, lds, base, tl);
+    stage<N, T, DIR, R2, NS2>(v, tl, tw);
+  }
+  if constexpr (R3 > 1) {
+    exchange_wave<N, T, R2, NS2, R3, PADDIV>(v, lds, base, tl);
+    stage<N, T, DIR, R3, NS3>(v, tl, tw);
+  }
+}
+
+// Full transform.  Ends with the last stage's outputs in registers; the
+// caller must not write `lds` before a __syncthreads().
+template <int N, int T, int DIR, int R0, int R1, int R2, int R3, int PADDIV>
+__device__ __forceinline__ void run(double2* v, double* lds, int base, int tl, const double2* __restrict__ tw) {
+  static_assert(R0 * R1 * R2 * R3 == N, "radices must multiply to N");
+  static_assert((N / T) % R0 == 0 && (N / T) % R1 == 0 && (N / T) % R2 == 0 && (N / T) % R3 == 0,
+                "every radix must divide N/T");
+  constexpr int NS1 = R0, NS2 = R0 * R1, NS3 = R0 * R1 * R2;
+  stage<N, T, DIR, R0, 1>(v, tl, tw);
+  if constexpr (R1 > 1) {
+    exchange<N, T, R0, 1, R1, PADDIV>(v, lds, base, tl);
+    stage<N, T, DIR, R1, NS1>(v, tl, tw);
+  }
+  if constexpr (R2 > 1) {
+    exchange<N, T, R1, NS1, R2, PADDIV>(v, lds, base, tl);
+    stage<N, T, DIR, R2, NS2>(v, tl, tw);
+  }
+  if constexpr (R3 > 1) {
+    exchange<N, T, R2, NS2, R3, PADDIV>(v, lds, base, tl);
+    stage<N, T, DIR, R3, NS3>(v, tl, tw);
+  }
+}
+
+// radix of the last stage
+template <int R0, int R1, int R2, int R3>
+struct Last {
+  static constexpr int value = R3 > 1 ? R3 : (R2 > 1 ? R2 : (R1 > 1 ? R1 : R0));
+};
+
+}  // namespace rf
+}  // namespace lmvd

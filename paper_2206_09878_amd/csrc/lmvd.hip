@@ -24,12 +24,13 @@
 
 #include "../../include/lmvd.h"
 #include "fft_lds.h"
+#include "fft_reg.h"
 #include "plan_host.h"
 
 namespace lmvd {
 
 constexpr int kMaxIn = 13;
-constexpr int kMaxOut = 6;
+constexpr int kMaxOut = 10;
 constexpr int kThreads = 256;
 constexpr int kZMaxE = 12;    // elements per thread in the z-FFT kernels
 constexpr int kXSlots = 3;    // complex slots per thread per line set in k_xpass
@@ -37,7 +38,7 @@ constexpr int kNumEv = 4;     // E0, E1, E2 (B at tau), F0 (B* at tau)
 
 enum EvalKind { EV_E0 = 0, EV_E1 = 1, EV_E2 = 2, EV_F0 = 3, EV_LAP = 4, EV_IDENT = 5 };
 enum Mult { MU_ONE = 0, MU_IK1 = 1, MU_IK3 = 2, MU_K1K = 3, MU_K3K = 4 };
-enum Phase { PH_RZ = 0, PH_RHOT = 1, PH_L = 2, PH_VEL = 3, PH_FLUX = 4, PH_TOPHYS = 5, PH_FROMPHYS = 6 };
+enum Phase { PH_RZ = 0, PH_RHOT = 1, PH_L = 2, PH_VEL = 3, PH_TOPHYS = 5, PH_FROMPHYS = 6 };
 enum Epi { EPI_STORE = 0, EPI_ADD = 1, EPI_ADD_ZUPDATE = 2 };
 
 struct DevPlan {
@@ -56,6 +57,8 @@ struct DevPlan {
   const double* lu_uinv;   // [3][n2]
   const double* k1;        // [nl]
   const double* k3;        // [nn]
+  const int* emit_first;   // [n2] first E0 row whose band starts at row i
+  const int* emit_cnt;     // [n2] number of such rows
   FftDev fz, fx;
   const double2* xtw;      // [hx] exp(-2 pi i k / m1)
 };
@@ -173,11 +176,11 @@ template <int PH>
 struct Op;
 
 template <>
-struct Op<PH_RZ> {  // R_z = (1/rho)(-m^d . grad z + rho D lap z)
+struct Op<PH_RZ> {  // R_z = (1/rho)(-m^d . grad z + rho D lap z); inputs lap z, z1, m1, z2, m2, z3, m3, z
   static constexpr int NIN = 8, NOUT = 1;
   __device__ static void apply(const DevPlan& P, const double* x, double* y) {
-    const double ir = (P.rho_h - P.drho * x[0]) * P.inv_rlrh;
-    y[0] = (P.rhoD * x[4] - (x[5] * x[1] + x[6] * x[2] + x[7] * x[3])) * ir;
+    const double ir = (P.rho_h - P.drho * x[7]) * P.inv_rlrh;
+    y[0] = (P.rhoD * x[0] - (x[1] * x[2] + x[3] * x[4] + x[5] * x[6])) * ir;
   }
 };
 template <>
@@ -189,40 +192,30 @@ struct Op<PH_RHOT> {  // rho_t = f'(z) z_t = rho^2 (rh - rl)/(rl rh) z_t
   }
 };
 template <>
-struct Op<PH_L> {  // L z_t = -(1/rho) grad z . m^c
+struct Op<PH_L> {  // L z_t = -(1/rho) grad z . m^c; inputs z1, m1c, z2, m2c, z3, m3c, z
   static constexpr int NIN = 7, NOUT = 1;
   __device__ static void apply(const DevPlan& P, const double* x, double* y) {
-    const double ir = (P.rho_h - P.drho * x[0]) * P.inv_rlrh;
-    y[0] = -(x[1] * x[4] + x[2] * x[5] + x[3] * x[6]) * ir;
+    const double ir = (P.rho_h - P.drho * x[6]) * P.inv_rlrh;
+    y[0] = -(x[0] * x[1] + x[2] * x[3] + x[4] * x[5]) * ir;
   }
 };
 template <>
-struct Op<PH_VEL> {  // u = m / rho, and rho
-  static constexpr int NIN = 4, NOUT = 4;
+struct Op<PH_VEL> {  // u = m / rho, rho, and C_ij = -m_i m_j / rho (i <= j)
+  static constexpr int NIN = 4, NOUT = 10;
   __device__ static void apply(const DevPlan& P, const double* x, double* y) {
     const double den = P.rho_h - P.drho * x[0];
     const double ir = den * P.inv_rlrh;
-    y[0] = x[1] * ir;
-    y[1] = x[2] * ir;
-    y[2] = x[3] * ir;
+    const double u1 = x[1] * ir, u2 = x[2] * ir, u3 = x[3] * ir;
+    y[0] = u1;
+    y[1] = u2;
+    y[2] = u3;
     y[3] = (P.rho_l * P.rho_h) / den;
-  }
-};
-template <>
-struct Op<PH_FLUX> {  // T_ij = -m_i m_j / rho + mu (d_j u_i + d_i u_j) - 2/3 mu theta delta_ij
-  static constexpr int NIN = 13, NOUT = 6;
-  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
-    const double ir = (P.rho_h - P.drho * x[0]) * P.inv_rlrh;
-    const double m1 = x[1], m2 = x[2], m3 = x[3];
-    const double* d = x + 4;  // d[3*i + j] = d u_i / d x_j
-    const double mu = P.mu;
-    const double th = (2.0 / 3.0) * mu * (d[0] + d[4] + d[8]);
-    y[0] = -m1 * m1 * ir + mu * (d[0] + d[0]) - th;
-    y[1] = -m1 * m2 * ir + mu * (d[1] + d[3]);
-    y[2] = -m1 * m3 * ir + mu * (d[2] + d[6]);
-    y[3] = -m2 * m2 * ir + mu * (d[4] + d[4]) - th;
-    y[4] = -m2 * m3 * ir + mu * (d[5] + d[7]);
-    y[5] = -m3 * m3 * ir + mu * (d[8] + d[8]) - th;
+    y[4] = -x[1] * u1;
+    y[5] = -x[1] * u2;
+    y[6] = -x[1] * u3;
+    y[7] = -x[2] * u2;
+    y[8] = -x[2] * u3;
+    y[9] = -x[3] * u3;
   }
 };
 template <>
@@ -364,6 +357,521 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(DevPlan P, const double2* __r
 }
 
 // ---------------------------------------------------------------------------
+// column kernels: values at the Greville points tau_j of spectral coefficient
+// fields (one thread per (l, n) column, ascending sweep with a register
+// window of coefficient rows, so every coefficient is read once).
+
+struct RowWindow {
+  double2 w[kMaxW];
+  int base;
+  __device__ __forceinline__ void init(const double2* __restrict__ src, size_t ncol, size_t c, int rows) {
+    base = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q) w[q] = (q < rows) ? src[size_t(q) * ncol + c] : zero2();
+  }
+  __device__ __forceinline__ void advance(const double2* __restrict__ src, size_t ncol, size_t c, int rows, int lo) {
+    while (base < lo) {
+#pragma unroll
+      for (int q = 0; q < kMaxW - 1; ++q) w[q] = w[q + 1];
+      const int r = base + kMaxW;
+      w[kMaxW - 1] = (r < rows) ? src[size_t(r) * ncol + c] : zero2();
+      ++base;
+    }
+  }
+  __device__ __forceinline__ double2 dot(const double* __restrict__ wt) const {
+    double2 acc = zero2();
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q) acc = fma2(wt[q], w[q], acc);
+    return acc;
+  }
+};
+
+// z -> E0 z, E1 z, (E2 - k^2 E0) z at tau
+__global__ void __launch_bounds__(kThreads) k_values_z(DevPlan P, const double2* __restrict__ z, double2* __restrict__ V0,
+                                                       double2* __restrict__ V1, double2* __restrict__ VL) {
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int n2 = P.n2;
+  const double k1 = P.k1[c % P.nl], k3 = P.k3[c / P.nl], ksq = k1 * k1 + k3 * k3;
+  RowWindow rw;
+  rw.init(z, ncol, c, n2);
+  for (int i = 0; i < n2; ++i) {
+    rw.advance(z, ncol, c, n2, P.ev_lo[i]);
+    const double2 a0 = rw.dot(P.ev_w + size_t(i) * kMaxW);
+    const double2 a1 = rw.dot(P.ev_w + (size_t(n2) + i) * kMaxW);
+    const double2 a2 = rw.dot(P.ev_w + (size_t(2 * n2) + i) * kMaxW);
+    const size_t e = size_t(i) * ncol + c;
+    V0[e] = a0;
+    V1[e] = a1;
+    VL[e] = make_double2(a2.x - ksq * a0.x, a2.y - ksq * a0.y);
+  }
+}
+
+// up to two B fields -> E0 values; one B* field -> F0 values (any pointer may be null)
+__global__ void __launch_bounds__(kThreads) k_values(DevPlan P, const double2* __restrict__ a, double2* __restrict__ Va,
+                                                     const double2* __restrict__ b, double2* __restrict__ Vb,
+                                                     const double2* __restrict__ cs, double2* __restrict__ Vc) {
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int n2 = P.n2;
+  RowWindow wa, wb, wc;
+  if (a) wa.init(a, ncol, c, n2);
+  if (b) wb.init(b, ncol, c, n2);
+  if (cs) wc.init(cs, ncol, c, n2 + 1);
+  for (int i = 0; i < n2; ++i) {
+    const size_t e = size_t(i) * ncol + c;
+    const double* w0 = P.ev_w + size_t(i) * kMaxW;
+    if (a) {
+      wa.advance(a, ncol, c, n2, P.ev_lo[i]);
+      Va[e] = wa.dot(w0);
+    }
+    if (b) {
+      wb.advance(b, ncol, c, n2, P.ev_lo[i]);
+      Vb[e] = wb.dot(w0);
+    }
+    if (cs) {
+      wc.advance(cs, ncol, c, n2 + 1, P.ev_lo[3 * n2 + i]);
+      Vc[e] = wc.dot(P.ev_w + (size_t(3 * n2) + i) * kMaxW);
+    }
+  }
+}
+
+// BDF-like guess dt z_t^0 = a1 z + a2 h1 + a3 h2 + a4 h3 (eq. dzdt_guesses)
+// (or zero) as coefficients, and its E0 values at tau
+__global__ void __launch_bounds__(kThreads) k_guess_v(DevPlan P, const double2* __restrict__ z,
+                                                      const double2* __restrict__ h1, const double2* __restrict__ h2,
+                                                      const double2* __restrict__ h3, double a1, double a2, double a3,
+                                                      double a4, double dt, int zero, double2* __restrict__ zt,
+                                                      double2* __restrict__ V) {
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int n2 = P.n2;
+  auto coef = [&](int r) -> double2 {
+    if (zero || r >= n2) return zero2();
+    const size_t e = size_t(r) * ncol + c;
+    const double2 A = z[e], B = h1[e], C = h2[e], D = h3[e];
+    return make_double2((a1 * A.x + a2 * B.x + a3 * C.x + a4 * D.x) / dt,
+                        (a1 * A.y + a2 * B.y + a3 * C.y + a4 * D.y) / dt);
+  };
+  double2 w[kMaxW];
+#pragma unroll
+  for (int q = 0; q < kMaxW; ++q) {
+    w[q] = coef(q);
+    if (q < n2) zt[size_t(q) * ncol + c] = w[q];
+  }
+  int base = 0;
+  for (int i = 0; i < n2; ++i) {
+    const int lo = P.ev_lo[i];
+    while (base < lo) {
+#pragma unroll
+      for (int q = 0; q < kMaxW - 1; ++q) w[q] = w[q + 1];
+      const int r = base + kMaxW;
+      w[kMaxW - 1] = coef(r);
+      if (r < n2) zt[size_t(r) * ncol + c] = w[kMaxW - 1];
+      ++base;
+    }
+    const double* w0 = P.ev_w + size_t(i) * kMaxW;
+    double2 acc = zero2();
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q) acc = fma2(w0[q], w[q], acc);
+    V[size_t(i) * ncol + c] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Register-FFT plane kernels for the sizes of the workloads.  Line size N,
+// T threads per line, radices R0..R3 (every radix divides N/T), PAD: one
+// LDS pad slot every PAD positions.
+
+template <int N>
+struct LinePlan;
+#define LMVD_LINEPLAN(N_, T_, R0_, R1_, R2_, R3_, PAD_)                                              \
+  template <>                                                                                        \
+  struct LinePlan<N_> {                                                                              \
+    static constexpr int T = T_, R0 = R0_, R1 = R1_, R2 = R2_, R3 = R3_, PAD = PAD_;                 \
+    static constexpr int E = N_ / T_;                                                                \
+    static constexpr int RL = rf::Last<R0_, R1_, R2_, R3_>::value;                                   \
+  };
+LMVD_LINEPLAN(768, 32, 24, 8, 4, 1, 24)
+LMVD_LINEPLAN(384, 32, 12, 4, 4, 2, 12)
+LMVD_LINEPLAN(192, 16, 12, 4, 4, 1, 12)
+LMVD_LINEPLAN(144, 12, 12, 12, 1, 1, 12)
+LMVD_LINEPLAN(96, 8, 12, 4, 2, 1, 12)
+LMVD_LINEPLAN(72, 6, 12, 6, 1, 1, 12)
+LMVD_LINEPLAN(48, 4, 12, 4, 1, 1, 12)
+LMVD_LINEPLAN(36, 3, 12, 3, 1, 1, 12)
+LMVD_LINEPLAN(24, 2, 12, 2, 1, 1, 12)
+#undef LMVD_LINEPLAN
+
+// lines per block and LDS line stride (doubles) of the z kernels (lines = l, lane-fastest)
+template <int N>
+struct ZShape {
+  static constexpr int T = LinePlan<N>::T;
+  static constexpr int LG = kThreads / T;
+  static constexpr int BASE = N + N / LinePlan<N>::PAD;
+  // 8 lines: stride = 2 mod 32 keeps two neighbouring threads of each of the
+  // 8 lines on distinct banks; otherwise an odd stride
+  static constexpr int STRIDE = (LG == 8) ? (BASE + ((2 - BASE % 32) + 32) % 32) : (BASE | 1);
+};
+// lines per block and LDS line stride of the x kernels (threads of a line lane-fastest)
+template <int N>
+struct XShape {
+  static constexpr int T = LinePlan<N>::T;
+  static constexpr int BG = kThreads / T;
+  static constexpr int STRIDE = N + N / LinePlan<N>::PAD;
+};
+
+// band row of the evaluation at tau_j, hoisted out of the per-mode loop
+struct BandRow {
+  int lo, rows, kind;
+  double w[kMaxW], w0[kMaxW];
+};
+__device__ __forceinline__ BandRow band_row(const DevPlan& P, int kind, int j) {
+  BandRow b;
+  b.kind = kind;
+  b.rows = (kind == EV_F0) ? P.n2 + 1 : P.n2;
+  const int kk = (kind == EV_LAP) ? EV_E2 : (kind == EV_IDENT ? EV_E0 : kind);
+  b.lo = P.ev_lo[kk * P.n2 + j];
+  const double* w = P.ev_w + (size_t(kk) * P.n2 + j) * kMaxW;
+  const double* w0 = P.ev_w + size_t(j) * kMaxW;
+#pragma unroll
+  for (int q = 0; q < kMaxW; ++q) {
+    b.w[q] = w[q];
+    b.w0[q] = (kind == EV_LAP) ? w0[q] : 0.0;
+  }
+  if (kind == EV_IDENT) b.lo = j;
+  return b;
+}
+__device__ __forceinline__ double2 band_apply(const BandRow& b, const double2* __restrict__ src, size_t col,
+                                              size_t ncol, double ksq) {
+  if (b.kind == EV_IDENT) return src[size_t(b.lo) * ncol + col];
+  double2 acc = zero2(), acc0 = zero2();
+#pragma unroll
+  for (int q = 0; q < kMaxW; ++q) {
+    const int r = b.lo + q;
+    if (r < b.rows && (b.w[q] != 0.0 || b.w0[q] != 0.0)) {
+      const double2 s = src[size_t(r) * ncol + col];
+      acc = fma2(b.w[q], s, acc);
+      acc0 = fma2(b.w0[q], s, acc0);
+    }
+  }
+  if (b.kind == EV_LAP) acc = make_double2(acc.x - ksq * acc0.x, acc.y - ksq * acc0.y);
+  return acc;
+}
+
+// evaluation at tau_j + spectral multiplier + inverse z-FFT of size N = m3.
+// grid (ceil(nl/LG), planes, nin), block LG*T (line index lane-fastest).
+template <int N>
+__global__ void __launch_bounds__(kThreads) k_zinv_r(DevPlan P, EvalArgs A, double2* __restrict__ zbuf, int j0,
+                                                    int pb) {
+  using LP = LinePlan<N>;
+  using ZS = ZShape<N>;
+  constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL;
+  extern __shared__ double lds_d[];
+  const int tid = threadIdx.x;
+  const int ll = tid % LG, tl = tid / LG;
+  const int f = blockIdx.z, jj = blockIdx.y, j = j0 + jj, l = blockIdx.x * LG + ll;
+  const int nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = N - nn;
+  const EvalIn in = A.in[f];
+  const bool lok = l < nl;
+  const size_t ncol = size_t(nn) * nl;
+  const BandRow br = band_row(P, in.kind, j);
+  const double k1 = lok ? P.k1[l] : 0.0;
+  double2 v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int pos = tl + T * r;
+    double2 val = zero2();
+    if (lok && (pos < h3 || pos >= h3 + pad)) {
+      const int ni = pos < h3 ? pos : pos - pad;
+      const double k3 = P.k3[ni];
+      const double ksq = k1 * k1 + k3 * k3;
+      const size_t col = size_t(ni) * nl + l;
+      val = apply_mult(in.ma, k1, k3, band_apply(br, in.a, col, ncol, ksq));
+      if (in.b) val = cadd(val, apply_mult(in.mb, k1, k3, band_apply(br, in.b, col, ncol, ksq)));
+    }
+    v[r] = val;
+  }
+  rf::run<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, ll * ZS::STRIDE, tl, P.fz.tw);
+  if (lok) {
+    double2* out = zbuf + (size_t(f) * pb + jj) * size_t(N) * nl + l;
+#pragma unroll
+    for (int c = 0; c < E / RL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) out[size_t(tl + T * c + r * (N / RL)) * nl] = v[c * RL + r];
+  }
+}
+
+// forward z-FFT of size N = m3 and truncation to the retained n.
+template <int N>
+__global__ void __launch_bounds__(kThreads) k_zfwd_r(DevPlan P, const double2* __restrict__ obuf, OutPtrs V, int j0,
+                                                    int pb) {
+  using LP = LinePlan<N>;
+  using ZS = ZShape<N>;
+  constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL;
+  extern __shared__ double lds_d[];
+  const int tid = threadIdx.x;
+  const int ll = tid % LG, tl = tid / LG;
+  const int g = blockIdx.z, jj = blockIdx.y, l = blockIdx.x * LG + ll;
+  const int nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = N - nn;
+  const bool lok = l < nl;
+  const double2* in = obuf + (size_t(g) * pb + jj) * size_t(N) * nl + l;
+  double2 v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = lok ? in[size_t(tl + T * r) * nl] : zero2();
+  rf::run<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, ll * ZS::STRIDE, tl, P.fz.tw);
+  if (lok) {
+    double2* out = V.v[g] + size_t(j0 + jj) * nn * nl + l;
+#pragma unroll
+    for (int c = 0; c < E / RL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int pos = tl + T * c + r * (N / RL);
+        if (pos < h3) out[size_t(pos) * nl] = v[c * RL + r];
+        else if (pos >= h3 + pad) out[size_t(pos - pad) * nl] = v[c * RL + r];
+      }
+  }
+}
+
+// Pointwise products, streamed: each input field updates a few per-point
+// accumulators as soon as its physical values exist; outputs are formed from
+// the accumulators.  Inputs are consumed in the order of the phase's input
+// list.  in<F>/out<G> act on one physical point.
+template <int PH>
+struct Stream;
+
+template <>
+struct Stream<PH_RZ> {  // inputs lap z, z1, m1, z2, m2, z3, m3, z (R_z)
+  static constexpr int NIN = 8, NOUT = 1, NST = 2;
+  template <int F>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x) {
+    if constexpr (F == 0) s[0] = P.rhoD * x;
+    else if constexpr (F == 1 || F == 3 || F == 5) s[1] = x;
+    else if constexpr (F == 7) s[0] *= (P.rho_h - P.drho * x) * P.inv_rlrh;
+    else s[0] -= s[1] * x;
+  }
+  template <int G>
+  __device__ __forceinline__ static double out(const DevPlan&, const double* s) { return s[0]; }
+};
+template <>
+struct Stream<PH_L> {  // inputs z1, m1c, z2, m2c, z3, m3c, z (L z_t)
+  static constexpr int NIN = 7, NOUT = 1, NST = 2;
+  template <int F>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x) {
+    if constexpr (F == 0 || F == 2 || F == 4) s[1] = x;
+    else if constexpr (F == 1) s[0] = -(s[1] * x);
+    else if constexpr (F == 6) s[0] *= (P.rho_h - P.drho * x) * P.inv_rlrh;
+    else s[0] -= s[1] * x;
+  }
+  template <int G>
+  __device__ __forceinline__ static double out(const DevPlan&, const double* s) { return s[0]; }
+};
+template <>
+struct Stream<PH_RHOT> {  // inputs z, z_t (rho_t = f'(z) z_t)
+  static constexpr int NIN = 2, NOUT = 1, NST = 1;
+  template <int F>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x) {
+    if constexpr (F == 0) {
+      const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x);
+      s[0] = rho * rho * P.drho * P.inv_rlrh;
+    } else {
+      s[0] = s[0] * x;
+    }
+  }
+  template <int G>
+  __device__ __forceinline__ static double out(const DevPlan&, const double* s) { return s[0]; }
+};
+template <>
+struct Stream<PH_VEL> {  // inputs z, m1, m2, m3 -> u1, u2, u3, rho, C11, C12, C13, C22, C23, C33
+  static constexpr int NIN = 4, NOUT = 10, NST = 4;
+  template <int F>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x) {
+    s[F] = (F == 0) ? (P.rho_h - P.drho * x) : x;
+  }
+  template <int G>
+  __device__ __forceinline__ static double out(const DevPlan& P, const double* s) {
+    const double ir = s[0] * P.inv_rlrh;
+    if constexpr (G == 0) return s[1] * ir;
+    else if constexpr (G == 1) return s[2] * ir;
+    else if constexpr (G == 2) return s[3] * ir;
+    else if constexpr (G == 3) return (P.rho_l * P.rho_h) / s[0];
+    else if constexpr (G == 4) return -s[1] * (s[1] * ir);
+    else if constexpr (G == 5) return -s[1] * (s[2] * ir);
+    else if constexpr (G == 6) return -s[1] * (s[3] * ir);
+    else if constexpr (G == 7) return -s[2] * (s[2] * ir);
+    else if constexpr (G == 8) return -s[2] * (s[3] * ir);
+    else return -s[3] * (s[3] * ir);
+  }
+};
+template <>
+struct Stream<PH_TOPHYS> {
+  static constexpr int NIN = 1, NOUT = 0, NST = 1;
+  template <int F>
+  __device__ __forceinline__ static void in(const DevPlan&, double*, double) {}
+  template <int G>
+  __device__ __forceinline__ static double out(const DevPlan&, const double*) { return 0.0; }
+};
+template <>
+struct Stream<PH_FROMPHYS> {
+  static constexpr int NIN = 0, NOUT = 1, NST = 1;
+  template <int F>
+  __device__ __forceinline__ static void in(const DevPlan&, double*, double) {}
+  template <int G>
+  __device__ __forceinline__ static double out(const DevPlan&, const double* s) { return s[0]; }
+};
+
+// apply input F to every point of the thread: point pair q of register slot
+// v[c*RL + r] has q = c + r*EL
+template <class S, int F, int E, int RL, int NST>
+__device__ __forceinline__ void stream_in(const DevPlan& P, double (&st)[NST][2 * E], const double2* v) {
+  constexpr int EL = E / RL;
+#pragma unroll
+  for (int c = 0; c < EL; ++c)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int q = c + r * EL;
+      double sa[NST], sb[NST];
+#pragma unroll
+      for (int k = 0; k < NST; ++k) {
+        sa[k] = st[k][2 * q];
+        sb[k] = st[k][2 * q + 1];
+      }
+      S::template in<F>(P, sa, v[c * RL + r].x);
+      S::template in<F>(P, sb, v[c * RL + r].y);
+#pragma unroll
+      for (int k = 0; k < NST; ++k) {
+        st[k][2 * q] = sa[k];
+        st[k][2 * q + 1] = sb[k];
+      }
+    }
+}
+template <class S, int F, int E, int RL, int NST>
+__device__ __forceinline__ void stream_in_dispatch(const DevPlan& P, int f, double (&st)[NST][2 * E],
+                                                   const double2* v) {
+  if constexpr (F < S::NIN) {
+    if (f == F) stream_in<S, F, E, RL, NST>(P, st, v);
+    else stream_in_dispatch<S, F + 1, E, RL, NST>(P, f, st, v);
+  }
+}
+template <class S, int G, int E, int NST>
+__device__ __forceinline__ void stream_out(const DevPlan& P, const double (&st)[NST][2 * E], double2* v) {
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    double sa[NST], sb[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+      sa[k] = st[k][2 * q];
+      sb[k] = st[k][2 * q + 1];
+    }
+    v[q] = make_double2(S::template out<G>(P, sa), S::template out<G>(P, sb));
+  }
+}
+template <class S, int G, int E, int NST>
+__device__ __forceinline__ void stream_out_dispatch(const DevPlan& P, int g, const double (&st)[NST][2 * E],
+                                                    double2* v) {
+  if constexpr (G < S::NOUT) {
+    if (g == G) stream_out<S, G, E, NST>(P, st, v);
+    else stream_out_dispatch<S, G + 1, E, NST>(P, g, st, v);
+  }
+}
+
+// x-pass with register FFTs of size N = m1/2.  grid (ceil(m3/BG), planes),
+// block BG*T; the T threads of a line are consecutive lanes, so where T
+// divides 64 the LDS exchanges of a line need only wave-level ordering.
+template <int PH, int N>
+__global__ void __launch_bounds__(kThreads) k_xpass_r(DevPlan P, const double2* __restrict__ zbuf,
+                                                     double2* __restrict__ obuf, int pb, double* phys_out,
+                                                     const double* phys_in, int j0) {
+  using LP = LinePlan<N>;
+  using XS = XShape<N>;
+  using S = Stream<PH>;
+  constexpr int T = LP::T, E = LP::E, RL = LP::RL, EL = E / RL;
+  extern __shared__ double2 lds_c[];
+  const int tid = threadIdx.x;
+  const int tl = tid % T, line = tid / T;
+  const int jj = blockIdx.y, b = blockIdx.x * XS::BG + line;
+  const int nl = P.nl, M3 = P.m3, M1 = P.m1;
+  const bool bok = b < M3;
+  const int base = line * XS::STRIDE;
+  double st[S::NST][2 * E];
+#pragma unroll
+  for (int k = 0; k < S::NST; ++k)
+#pragma unroll
+    for (int q = 0; q < 2 * E; ++q) st[k][q] = 0.0;
+  double2 v[E];
+#pragma unroll 1
+  for (int f = 0; f < S::NIN; ++f) {
+    const double2* X = zbuf + ((size_t(f) * pb + jj) * M3 + (bok ? b : 0)) * nl;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int k = tl + T * r;
+      const double2 a = (bok && k < nl) ? X[k] : zero2();
+      const double2 cj = (bok && k > 0 && N - k < nl) ? cconj(X[N - k]) : zero2();
+      const double2 w = cconj(P.xtw[k]);  // exp(+2 pi i k / m1)
+      v[r] = cadd(cadd(a, cj), times_i(cmul(w, csub(a, cj))));
+    }
+    rf::run_wave<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_c, base, tl, P.fx.tw);
+    // v[c*RL + r] holds the sample pair m = tl + T (c + r EL)
+    if constexpr (PH == PH_TOPHYS) {
+#pragma unroll
+      for (int c = 0; c < EL; ++c)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const int q = c + r * EL;
+          if (bok) {
+            double* dst = phys_out + (size_t(j0 + jj) * M3 + b) * M1 + 2 * (tl + T * q);
+            dst[0] = v[c * RL + r].x;
+            dst[1] = v[c * RL + r].y;
+          }
+        }
+    } else {
+      stream_in_dispatch<S, 0, E, RL, S::NST>(P, f, st, v);
+    }
+  }
+  if constexpr (PH == PH_FROMPHYS) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const double* src = phys_in + (size_t(j0 + jj) * M3 + (bok ? b : 0)) * M1 + 2 * (tl + T * q);
+      st[0][2 * q] = bok ? src[0] : 0.0;
+      st[0][2 * q + 1] = bok ? src[1] : 0.0;
+    }
+  }
+  const double scale = 1.0 / (double(M1) * double(M3));
+#pragma unroll 1
+  for (int g = 0; g < S::NOUT; ++g) {
+    stream_out_dispatch<S, 0, E, S::NST>(P, g, st, v);
+    rf::run_wave<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_c, base, tl, P.fx.tw);
+    // Y at k = tl + T (c + r EL); the real-signal unpacking needs Y_k and Y_{(N-k) mod N}
+    rf::line_sync<T>();
+#pragma unroll
+    for (int c = 0; c < EL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) lds_c[base + rf::padded<LP::PAD>(tl + T * (c + r * EL))] = v[c * RL + r];
+    rf::line_sync<T>();
+    double2* Y0 = obuf + ((size_t(g) * pb + jj) * M3 + (bok ? b : 0)) * nl;
+#pragma unroll
+    for (int c = 0; c < EL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int q = c + r * EL;
+        const int k = tl + T * q;
+        const double2 Yp = lds_c[base + rf::padded<LP::PAD>((N - k) % N)];
+        if (bok && k < nl) {
+          const double2 Yk = v[c * RL + r];
+          const double2 Yc = cconj(Yp);
+          const double2 Ev = cscale(cadd(Yk, Yc), 0.5);
+          const double2 D = csub(Yk, Yc);
+          const double2 O = make_double2(0.5 * D.y, -0.5 * D.x);
+          Y0[k] = cscale(cadd(Ev, cmul(P.xtw[k], O)), scale);
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column kernel: projection values -> B coefficients with a shared no-pivot LU
 // (kind 0 interpolation, 1 Dirichlet rows, 2 Neumann rows).  One thread per
 // column; forward sweep stores L^{-1} b in `out`, backward sweep overwrites it.
@@ -372,7 +880,7 @@ template <int EPI>
 __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const double2* in, double2* out,
                                                    const double2* __restrict__ add, const double2* __restrict__ z,
                                                    const double2* __restrict__ zt_prev, double2* __restrict__ z_out,
-                                                   double2* __restrict__ zt_copy, int stage, int ncol) {
+                                                   double2* __restrict__ vals_out, int stage, int ncol) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const int n2 = P.n2;
@@ -393,6 +901,10 @@ __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const do
   }
 #pragma unroll
   for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+  // window of the final output rows i .. i+kMaxW-1 for the E0 values (vals_out)
+  double2 win[kMaxW];
+#pragma unroll
+  for (int q = 0; q < kMaxW; ++q) win[q] = zero2();
   for (int i = n2 - 1; i >= 0; --i) {
     double2 y = out[size_t(i) * ncol + c];
 #pragma unroll
@@ -407,6 +919,19 @@ __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const do
     } else {
       const double2 zt = cadd(x, add[e]);
       out[e] = zt;
+      if (vals_out) {
+#pragma unroll
+        for (int q = kMaxW - 1; q > 0; --q) win[q] = win[q - 1];
+        win[0] = zt;
+        const int first = P.emit_first[i], cnt = P.emit_cnt[i];
+        for (int t = 0; t < cnt; ++t) {
+          const double* w0 = P.ev_w + size_t(first + t) * kMaxW;
+          double2 acc = zero2();
+#pragma unroll
+          for (int q = 0; q < kMaxW; ++q) acc = fma2(w0[q], win[q], acc);
+          vals_out[size_t(first + t) * ncol + c] = acc;
+        }
+      }
       if (EPI == EPI_ADD_ZUPDATE) {
         const double2 z0 = z[e];
         double2 zn;
@@ -417,9 +942,123 @@ __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const do
           zn = fma2(P.dt, dz, z0);
         }
         z_out[e] = zn;
-        if (zt_copy) zt_copy[e] = zt;
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column kernel: T_ij = C_ij + tau_ij at the Greville points and its
+// interpolation (plain projection).  tau_ij = mu (d_j u_i + d_i u_j)
+// - 2/3 mu theta delta_ij is linear in u, so its values follow from the
+// projected velocity u_hat directly (i k1, d/dy, i k3): the same numbers
+// the 3/2-grid round trip of the derivative fields would give, since the
+// forward transform inverts the inverse one on the retained modes.
+// GROUP 0 produces T11, T12, T13; GROUP 1 produces T22, T23, T33.
+
+template <int GROUP>
+__global__ void __launch_bounds__(kThreads) k_proj_T(DevPlan P, const double2* __restrict__ Ca,
+                                                     const double2* __restrict__ Cb, const double2* __restrict__ Cc,
+                                                     const double2* __restrict__ u1, const double2* __restrict__ u2,
+                                                     const double2* __restrict__ u3, double2* __restrict__ Ta,
+                                                     double2* __restrict__ Tb, double2* __restrict__ Tc) {
+  const int nl = P.nl, nn = P.nn, n2 = P.n2;
+  const int ncol = nn * nl;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int l = c % nl, ni = c / nl;
+  const double k1 = P.k1[l], k3 = P.k3[ni];
+  const double mu = P.mu, th = (2.0 / 3.0) * P.mu;
+  const double* L = P.lu_l;
+  const double* U = P.lu_u;
+  const double* Ui = P.lu_uinv;
+  double2 ra[kMaxBand], rb[kMaxBand], rc[kMaxBand];
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) ra[m] = rb[m] = rc[m] = zero2();
+  for (int i = 0; i < n2; ++i) {
+    const int lo = P.ev_lo[i];
+    const double* w0 = P.ev_w + size_t(i) * kMaxW;
+    const double* w1 = P.ev_w + (size_t(n2) + i) * kMaxW;
+    double2 s0[3] = {zero2(), zero2(), zero2()}, s1[3] = {zero2(), zero2(), zero2()};
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q) {
+      const int r = lo + q;
+      if (r < n2 && (w0[q] != 0.0 || w1[q] != 0.0)) {
+        const size_t e = size_t(r) * ncol + c;
+        const double2 a = u1[e], b = u2[e], d = u3[e];
+        s0[0] = fma2(w0[q], a, s0[0]);
+        s1[0] = fma2(w1[q], a, s1[0]);
+        s0[1] = fma2(w0[q], b, s0[1]);
+        s1[1] = fma2(w1[q], b, s1[1]);
+        s0[2] = fma2(w0[q], d, s0[2]);
+        s1[2] = fma2(w1[q], d, s1[2]);
+      }
+    }
+    // d[a][b] = d u_a / d x_b at tau_i
+    double2 d[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      d[a][0] = times_i(cscale(s0[a], k1));
+      d[a][1] = s1[a];
+      d[a][2] = times_i(cscale(s0[a], k3));
+    }
+    const double2 theta = cadd(cadd(d[0][0], d[1][1]), d[2][2]);
+    const size_t e = size_t(i) * ncol + c;
+    double2 ba, bb, bc;
+    if (GROUP == 0) {
+      ba = cadd(Ca[e], make_double2(2 * mu * d[0][0].x - th * theta.x, 2 * mu * d[0][0].y - th * theta.y));
+      bb = cadd(Cb[e], cscale(cadd(d[0][1], d[1][0]), mu));
+      bc = cadd(Cc[e], cscale(cadd(d[0][2], d[2][0]), mu));
+    } else {
+      ba = cadd(Ca[e], make_double2(2 * mu * d[1][1].x - th * theta.x, 2 * mu * d[1][1].y - th * theta.y));
+      bb = cadd(Cb[e], cscale(cadd(d[1][2], d[2][1]), mu));
+      bc = cadd(Cc[e], make_double2(2 * mu * d[2][2].x - th * theta.x, 2 * mu * d[2][2].y - th * theta.y));
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) {
+      const double lm = L[i * kMaxBand + m];
+      ba = fma2(-lm, ra[m], ba);
+      bb = fma2(-lm, rb[m], bb);
+      bc = fma2(-lm, rc[m], bc);
+    }
+    Ta[e] = ba;
+    Tb[e] = bb;
+    Tc[e] = bc;
+#pragma unroll
+    for (int m = kMaxBand - 1; m > 0; --m) {
+      ra[m] = ra[m - 1];
+      rb[m] = rb[m - 1];
+      rc[m] = rc[m - 1];
+    }
+    ra[0] = ba;
+    rb[0] = bb;
+    rc[0] = bc;
+  }
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) ra[m] = rb[m] = rc[m] = zero2();
+  for (int i = n2 - 1; i >= 0; --i) {
+    const size_t e = size_t(i) * ncol + c;
+    double2 ya = Ta[e], yb = Tb[e], yc = Tc[e];
+#pragma unroll
+    for (int q = 0; q < kMaxBand; ++q) {
+      const double u = U[i * (kMaxBand + 1) + q + 1];
+      ya = fma2(-u, ra[q], ya);
+      yb = fma2(-u, rb[q], yb);
+      yc = fma2(-u, rc[q], yc);
+    }
+    const double2 xa = cscale(ya, Ui[i]), xb = cscale(yb, Ui[i]), xc = cscale(yc, Ui[i]);
+#pragma unroll
+    for (int q = kMaxBand - 1; q > 0; --q) {
+      ra[q] = ra[q - 1];
+      rb[q] = rb[q - 1];
+      rc[q] = rc[q - 1];
+    }
+    ra[0] = xa;
+    rb[0] = xb;
+    rc[0] = xc;
+    Ta[e] = xa;
+    Tb[e] = xb;
+    Tc[e] = xc;
   }
 }
 
@@ -815,6 +1454,8 @@ struct Workspace {
   size_t bytes = 0;
   size_t off_md1, off_md3, off_c2d, off_mpar, off_c2c, off_rz, off_zta, off_ztb, off_rhot, off_vals[kMaxOut];
   size_t off_u[3], off_T[6], off_rhov, off_yphi, off_yom, off_uscr, off_zbuf, off_obuf, off_mean;
+  // values at the Greville points
+  size_t off_vz0, off_vz1, off_vzl, off_vmd1, off_vmd3, off_vc2d, off_vmpar, off_vc2c, off_vzt;
 };
 
 }  // namespace lmvd
@@ -836,6 +1477,7 @@ struct lmvd_plan_s {
   int lgz = 1;      // l-lines per z-FFT block
   int bgx = 1;      // z-lines per x-pass block
   int device = 0;
+  bool use_reg = true;  // register-FFT kernels for the specialised sizes
 };
 
 namespace lmvd {
@@ -871,6 +1513,15 @@ static void layout_workspace(lmvd_plan_s* p) {
   w.off_zbuf = take(size_t(kMaxIn) * p->pb * plane);
   w.off_obuf = take(size_t(kMaxOut) * p->pb * plane);
   w.off_mean = take(size_t(2) * H.n2 * 8);
+  w.off_vz0 = take(sB);
+  w.off_vz1 = take(sB);
+  w.off_vzl = take(sB);
+  w.off_vmd1 = take(sB);
+  w.off_vmd3 = take(sB);
+  w.off_vc2d = take(sB);
+  w.off_vmpar = take(sB);
+  w.off_vc2c = take(sB);
+  w.off_vzt = take(sB);
   w.bytes = o;
 }
 
@@ -992,6 +1643,8 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   UP_OR_FAIL(Ui, &D.lu_uinv);
   UP_OR_FAIL(H.k1, &D.k1);
   UP_OR_FAIL(H.k3, &D.k3);
+  UP_OR_FAIL(H.emit_first, &D.emit_first);
+  UP_OR_FAIL(H.emit_cnt, &D.emit_cnt);
   const double* tw = nullptr;
   UP_OR_FAIL(H.fz.tw, &tw);
   fill_fft(H.fz, D.fz);
@@ -1057,6 +1710,58 @@ static EvalIn ev(const void* a, int kind, int ma = MU_ONE, const void* b = nullp
   return e;
 }
 
+// register-FFT launches for the specialised sizes; false if the size has none
+template <int N>
+static void launch_zinv_t(lmvd_plan_s* p, hipStream_t s, const EvalArgs& A, double2* zbuf, int j0, int nb, int nin) {
+  using ZS = ZShape<N>;
+  const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nin);
+  const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
+  hipLaunchKernelGGL(k_zinv_r<N>, g, dim3(ZS::LG * ZS::T), lds, s, p->D, A, zbuf, j0, p->pb);
+}
+template <int N>
+static void launch_zfwd_t(lmvd_plan_s* p, hipStream_t s, const double2* obuf, const OutPtrs& V, int j0, int nb,
+                          int nout) {
+  using ZS = ZShape<N>;
+  const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nout);
+  const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
+  hipLaunchKernelGGL(k_zfwd_r<N>, g, dim3(ZS::LG * ZS::T), lds, s, p->D, obuf, V, j0, p->pb);
+}
+template <int PH, int N>
+static void launch_xpass_t(lmvd_plan_s* p, hipStream_t s, const double2* zbuf, double2* obuf, double* phys_out,
+                           const double* phys_in, int j0, int nb) {
+  using XS = XShape<N>;
+  const dim3 g((p->H.cfg.m3 + XS::BG - 1) / XS::BG, nb);
+  const size_t lds = size_t(XS::BG) * XS::STRIDE * sizeof(double2);
+  hipLaunchKernelGGL((k_xpass_r<PH, N>), g, dim3(XS::BG * XS::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out,
+                     phys_in, j0);
+}
+static bool zreg_size(int n) {
+  return n == 768 || n == 192 || n == 144 || n == 96 || n == 72 || n == 48;
+}
+static bool xreg_size(int n) {
+  return n == 384 || n == 96 || n == 72 || n == 48 || n == 36 || n == 24;
+}
+#define LMVD_ZSWITCH(n, CALL) \
+  switch (n) {                \
+    case 768: CALL(768); break; \
+    case 192: CALL(192); break; \
+    case 144: CALL(144); break; \
+    case 96: CALL(96); break;   \
+    case 72: CALL(72); break;   \
+    case 48: CALL(48); break;   \
+    default: break;             \
+  }
+#define LMVD_XSWITCH(n, CALL) \
+  switch (n) {                \
+    case 384: CALL(384); break; \
+    case 96: CALL(96); break;   \
+    case 72: CALL(72); break;   \
+    case 48: CALL(48); break;   \
+    case 36: CALL(36); break;   \
+    case 24: CALL(24); break;   \
+    default: break;             \
+  }
+
 template <int PH>
 static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, const std::vector<double2*>& outs,
                                double* phys_out = nullptr, const double* phys_in = nullptr) {
@@ -1076,23 +1781,42 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
     const int nb = std::min(p->pb, H.n2 - j0);
     const double zplane = double(M3) * nl * 16.0, splane = double(ncols(p)) * 16.0;
     const double nin = double(ins.size()), nout = double(outs.size());
+    const bool zr = p->use_reg && zreg_size(M3), xr = p->use_reg && xreg_size(H.hx);
     if (!ins.empty()) {
       double terms = 0;
       for (const EvalIn& e : ins) terms += e.b ? 2 : 1;
       ProfScope ps(p, KC_EVAL, c.s, nb * (terms * splane + nin * zplane));
-      dim3 g1((nl + lg - 1) / lg, nb, int(ins.size()));
-      hipLaunchKernelGGL(k_eval_zinv, g1, dim3(kThreads), lds_z, c.s, p->D, A, zbuf, j0, p->pb, lg);
+      if (zr) {
+#define CALLZ(N) launch_zinv_t<N>(p, c.s, A, zbuf, j0, nb, int(ins.size()))
+        LMVD_ZSWITCH(M3, CALLZ)
+#undef CALLZ
+      } else {
+        dim3 g1((nl + lg - 1) / lg, nb, int(ins.size()));
+        hipLaunchKernelGGL(k_eval_zinv, g1, dim3(kThreads), lds_z, c.s, p->D, A, zbuf, j0, p->pb, lg);
+      }
     }
     {
       ProfScope ps(p, KC_XPASS, c.s, nb * (nin + nout) * zplane);
-      dim3 g2((M3 + bg - 1) / bg, nb);
-      hipLaunchKernelGGL(k_xpass<PH>, g2, dim3(kThreads), lds_x, c.s, p->D, zbuf, obuf, p->pb, bg, phys_out,
-                         phys_in, j0);
+      if (xr) {
+#define CALLX(N) launch_xpass_t<PH, N>(p, c.s, zbuf, obuf, phys_out, phys_in, j0, nb)
+        LMVD_XSWITCH(H.hx, CALLX)
+#undef CALLX
+      } else {
+        dim3 g2((M3 + bg - 1) / bg, nb);
+        hipLaunchKernelGGL(k_xpass<PH>, g2, dim3(kThreads), lds_x, c.s, p->D, zbuf, obuf, p->pb, bg, phys_out,
+                           phys_in, j0);
+      }
     }
     if (!outs.empty()) {
       ProfScope ps(p, KC_ZFWD, c.s, nb * nout * (zplane + splane));
-      dim3 g3((nl + lg - 1) / lg, nb, int(outs.size()));
-      hipLaunchKernelGGL(k_zfwd, g3, dim3(kThreads), lds_z, c.s, p->D, obuf, V, j0, p->pb, lg);
+      if (zr) {
+#define CALLF(N) launch_zfwd_t<N>(p, c.s, obuf, V, j0, nb, int(outs.size()))
+        LMVD_ZSWITCH(M3, CALLF)
+#undef CALLF
+      } else {
+        dim3 g3((nl + lg - 1) / lg, nb, int(outs.size()));
+        hipLaunchKernelGGL(k_zfwd, g3, dim3(kThreads), lds_z, c.s, p->D, obuf, V, j0, p->pb, lg);
+      }
     }
   }
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
@@ -1152,16 +1876,37 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   double2* user_zt = static_cast<double2*>(a->zt);
   lmvd_status st;
 
-  // 1. m^d
+  double2* vz0 = c.at<double2>(W.off_vz0);
+  double2* vz1 = c.at<double2>(W.off_vz1);
+  double2* vzl = c.at<double2>(W.off_vzl);
+  double2* vmd1 = c.at<double2>(W.off_vmd1);
+  double2* vmd3 = c.at<double2>(W.off_vmd3);
+  double2* vc2d = c.at<double2>(W.off_vc2d);
+  double2* vmpar = c.at<double2>(W.off_vmpar);
+  double2* vc2c = c.at<double2>(W.off_vc2c);
+  double2* vzt = c.at<double2>(W.off_vzt);
+  const dim3 cgrid((unsigned)((ncol + kThreads - 1) / kThreads));
+  auto values = [&](const double2* a1, double2* v1, const double2* a2, double2* v2, const double2* a3, double2* v3) {
+    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * ((a1 ? 2 : 0) + (a2 ? 2 : 0) + (a3 ? 2 : 0)));
+    hipLaunchKernelGGL(k_values, cgrid, dim3(kThreads), 0, s, p->D, a1, v1, a2, v2, a3, v3);
+  };
+
+  // 1. m^d and its values at tau
   solveA<0>(c, phi2, om2, a->m1bar, a->m3bar, c2d, md1, md3);
+  values(md1, vmd1, md3, vmd3, c2d, vc2d);
+  // values of z and its y-derivatives (z is fixed during the substep)
+  {
+    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * 4);
+    hipLaunchKernelGGL(k_values_z, cgrid, dim3(kThreads), 0, s, p->D, z, vz0, vz1, vzl);
+  }
   // 2. R_z
   st = plane_phase<PH_RZ>(c,
-                          {ev(z, EV_E0), ev(z, EV_E0, MU_IK1), ev(z, EV_E1), ev(z, EV_E0, MU_IK3), ev(z, EV_LAP),
-                           ev(md1, EV_E0), ev(c2d, EV_F0), ev(md3, EV_E0)},
+                          {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT),
+                           ev(vc2d, EV_IDENT), ev(vz0, EV_IDENT, MU_IK3), ev(vmd3, EV_IDENT), ev(vz0, EV_IDENT)},
                           {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
-  // guess
+  // guess (coefficients and values)
   {
     const double bn = H.cfg.beta_n, bp = H.cfg.beta_p;
     double co[4];
@@ -1172,10 +1917,12 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     }
     double2* gdst = (kf == 0 && user_zt) ? user_zt : zta;
     const int zero = (a->guess_mode == 1) ? 1 : 0;
-    hipLaunchKernelGGL(k_guess, dim3((nB + kThreads - 1) / kThreads), dim3(kThreads), 0, s, z,
-                       static_cast<const double2*>(a->z_hist[0]), static_cast<const double2*>(a->z_hist[1]),
-                       static_cast<const double2*>(a->z_hist[2]), co[0], co[1], co[2], co[3], H.cfg.dt, gdst, nB,
-                       zero);
+    {
+      ProfScope ps(p, KC_PROJ, s, 16.0 * nB * (zero ? 2 : 6));
+      hipLaunchKernelGGL(k_guess_v, cgrid, dim3(kThreads), 0, s, p->D, z, static_cast<const double2*>(a->z_hist[0]),
+                         static_cast<const double2*>(a->z_hist[1]), static_cast<const double2*>(a->z_hist[2]), co[0],
+                         co[1], co[2], co[3], H.cfg.dt, zero, gdst, vzt);
+    }
     if (kf == 0) {
       hipLaunchKernelGGL(k_zupdate, dim3((nB + kThreads - 1) / kThreads), dim3(kThreads), 0, s, z, gdst,
                          static_cast<const double2*>(a->zt_prev), static_cast<double2*>(a->z_out), H.cfg.dt, a->stage,
@@ -1183,52 +1930,59 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     }
   }
   double2* cur = (kf == 0 && user_zt) ? user_zt : zta;
-  // 3. fixed-point iterations
+  // 3. fixed-point iterations z_t^k = L(z) z_t^{k-1} + R_z
   for (int it = 0; it < kf; ++it) {
     const bool last = (it == kf - 1);
-    st = plane_phase<PH_RHOT>(c, {ev(z, EV_E0), ev(cur, EV_E0)}, {vals[0]});
+    st = plane_phase<PH_RHOT>(c, {ev(vz0, EV_IDENT), ev(vzt, EV_IDENT)}, {vals[0]});
     if (st != LMVD_OK) return st;
     proj(c, 0, vals[0], rhot);
     solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
+    values(mpar, vmpar, nullptr, nullptr, c2c, vc2c);
     st = plane_phase<PH_L>(c,
-                           {ev(z, EV_E0), ev(z, EV_E0, MU_IK1), ev(z, EV_E1), ev(z, EV_E0, MU_IK3),
-                            ev(mpar, EV_E0, MU_K1K), ev(c2c, EV_F0), ev(mpar, EV_E0, MU_K3K)},
+                           {ev(vz0, EV_IDENT, MU_IK1), ev(vmpar, EV_IDENT, MU_K1K), ev(vz1, EV_IDENT),
+                            ev(vc2c, EV_IDENT), ev(vz0, EV_IDENT, MU_IK3), ev(vmpar, EV_IDENT, MU_K3K),
+                            ev(vz0, EV_IDENT)},
                            {vals[0]});
     if (st != LMVD_OK) return st;
     double2* next = (last && user_zt) ? user_zt : (cur == zta ? ztb : zta);
     const int n = int(ncol);
-    ProfScope ps(p, KC_PROJ, s, (last ? (a->stage ? 6.0 : 5.0) : 3.0) * 16.0 * nB);
+    ProfScope ps(p, KC_PROJ, s, (last ? (a->stage ? 7.0 : 6.0) : 4.0) * 16.0 * nB);
     if (last) {
       hipLaunchKernelGGL(k_proj<EPI_ADD_ZUPDATE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
                          vals[0], next, rz, z, static_cast<const double2*>(a->zt_prev),
-                         static_cast<double2*>(a->z_out), nullptr, a->stage, n);
+                         static_cast<double2*>(a->z_out), vzt, a->stage, n);
     } else {
       hipLaunchKernelGGL(k_proj<EPI_ADD>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
-                         vals[0], next, rz, nullptr, nullptr, nullptr, nullptr, a->stage, n);
+                         vals[0], next, rz, nullptr, nullptr, nullptr, vzt, a->stage, n);
     }
     cur = next;
   }
   // m^c of the stage from z_t^{k_f}
-  st = plane_phase<PH_RHOT>(c, {ev(z, EV_E0), ev(cur, EV_E0)}, {vals[0]});
+  st = plane_phase<PH_RHOT>(c, {ev(vz0, EV_IDENT), ev(vzt, EV_IDENT)}, {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 0, vals[0], rhot);
   solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
+  values(mpar, vmpar, nullptr, nullptr, c2c, vc2c);
   // 4./5. velocities, density, fluxes
-  const EvalIn m1 = ev(md1, EV_E0, MU_ONE, mpar, MU_K1K);
-  const EvalIn m2 = ev(c2d, EV_F0, MU_ONE, c2c, MU_ONE);
-  const EvalIn m3 = ev(md3, EV_E0, MU_ONE, mpar, MU_K3K);
-  st = plane_phase<PH_VEL>(c, {ev(z, EV_E0), m1, m2, m3}, {vals[0], vals[1], vals[2], rhov});
+  const EvalIn m1 = ev(vmd1, EV_IDENT, MU_ONE, vmpar, MU_K1K);
+  const EvalIn m2 = ev(vc2d, EV_IDENT, MU_ONE, vc2c, MU_ONE);
+  const EvalIn m3 = ev(vmd3, EV_IDENT, MU_ONE, vmpar, MU_K3K);
+  // u = m/rho, rho and C_ij = -m_i m_j/rho on the physical grid; u_hat by interpolation;
+  // T_ij = C_ij + tau_ij(u_hat) projected
+  double2* cv[6] = {vals[4], vals[5], vals[6], vals[7], vals[8], vals[9]};
+  st = plane_phase<PH_VEL>(c, {ev(vz0, EV_IDENT), m1, m2, m3},
+                           {vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]});
   if (st != LMVD_OK) return st;
   for (int i = 0; i < 3; ++i) proj(c, 0, vals[i], u[i]);
-  std::vector<EvalIn> fin = {ev(z, EV_E0), m1, m2, m3};
-  for (int i = 0; i < 3; ++i) {
-    fin.push_back(ev(u[i], EV_E0, MU_IK1));
-    fin.push_back(ev(u[i], EV_E1));
-    fin.push_back(ev(u[i], EV_E0, MU_IK3));
+  {
+    const int n = int(ncol);
+    const dim3 grid((n + kThreads - 1) / kThreads);
+    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * 15.0);
+    hipLaunchKernelGGL(k_proj_T<0>, grid, dim3(kThreads), 0, s, p->D, cv[0], cv[1], cv[2], u[0], u[1], u[2], T[0],
+                       T[1], T[2]);
+    hipLaunchKernelGGL(k_proj_T<1>, grid, dim3(kThreads), 0, s, p->D, cv[3], cv[4], cv[5], u[0], u[1], u[2], T[3],
+                       T[4], T[5]);
   }
-  st = plane_phase<PH_FLUX>(c, fin, {vals[0], vals[1], vals[2], vals[3], vals[4], vals[5]});
-  if (st != LMVD_OK) return st;
-  for (int i = 0; i < 6; ++i) proj(c, 0, vals[i], T[i]);
   // RHS and RK2
   {
     const int n = int(ncol);

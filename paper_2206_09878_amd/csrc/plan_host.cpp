@@ -326,6 +326,14 @@ lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& H, std::string
     msg = "m3 and m1/2 must be 2^a 3^b <= 1024";
     return LMVD_EUNSUPPORTED;
   }
+  H.emit_first.assign(H.n2, 0);
+  H.emit_cnt.assign(H.n2, 0);
+  for (int i = H.n2 - 1; i >= 0; --i) {
+    const int lo = H.E[0].lo[i];
+    if (lo < 0 || lo >= H.n2) { msg = "E0 band start out of range"; return LMVD_ENUMERIC; }
+    H.emit_first[lo] = i;  // the smallest i with this lo, after the descending loop
+    H.emit_cnt[lo] += 1;
+  }
   H.xtw.resize(size_t(2) * H.hx);
   const long double pi = 3.141592653589793238462643383279502884L;
   for (int k = 0; k < H.hx; ++k) {

@@ -64,6 +64,8 @@ struct HostTables {
   std::vector<double> k1, k3;        // k1[l], k3[n_idx]
   FftPlan fz, fx;                    // complex FFTs of size m3 and m1/2
   std::vector<double> xtw;           // cos, sin of -2 pi k / m1, k < m1/2
+  // rows i' of E_0 whose band starts at row i (lo(i') = i): emit_first[i], emit_cnt[i]
+  std::vector<int32_t> emit_first, emit_cnt;
 };
 
 // Build all host tables.  Returns LMVD_OK or an error with `msg` set.
