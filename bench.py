@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--workload", default="rt512")
     ap.add_argument("--plane-batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-class", choices=CLASS_NAMES, default=None,
+                    help="time this kernel class instead of detecting the dominant one")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs the substep on one GPU only; multi-GPU sharding is a design "
@@ -95,12 +97,15 @@ def main():
 
     # dominant kernel class: one untimed substep per class with its launches timed
     totals = {}
-    for cls in range(len(CLASS_NAMES)):
-        plan.profile_start(cls)
-        stepper.substep()
-        ms, n, b = plan.profile_stop()
-        totals[cls] = ms
-    dom = max(totals, key=totals.get)
+    if args.kernel_class is None:
+        for cls in range(len(CLASS_NAMES)):
+            plan.profile_start(cls)
+            stepper.substep()
+            ms, n, b = plan.profile_stop()
+            totals[cls] = ms
+        dom = max(totals, key=totals.get)
+    else:
+        dom = CLASS_NAMES.index(args.kernel_class)
     torch.cuda.synchronize()
 
     # timed region
@@ -135,7 +140,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "launches": klaunch, "avg_launch_ms": kms / max(klaunch, 1),
-                     "share_of_substep": totals[dom] / sum(totals.values())},
+                     "share_of_substep": (totals[dom] / sum(totals.values())) if totals else None},
         "substep_roofline": {"model_bytes_per_substep": model,
                              "frac": model * value / (HBM_PEAK_GBS * 1e9)},
         "kernel_class_ms_per_substep": {CLASS_NAMES[c]: totals[c] for c in totals},

@@ -386,9 +386,10 @@ struct RowWindow {
   }
 };
 
-// z -> E0 z, E1 z, (E2 - k^2 E0) z at tau
+// z -> E0 z, E1 z, (E2 - k^2 E0) z and i k3 E0 z at tau
 __global__ void __launch_bounds__(kThreads) k_values_z(DevPlan P, const double2* __restrict__ z, double2* __restrict__ V0,
-                                                       double2* __restrict__ V1, double2* __restrict__ VL) {
+                                                       double2* __restrict__ V1, double2* __restrict__ VL,
+                                                       double2* __restrict__ V3) {
   const size_t ncol = size_t(P.nn) * P.nl;
   const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
@@ -405,6 +406,7 @@ __global__ void __launch_bounds__(kThreads) k_values_z(DevPlan P, const double2*
     V0[e] = a0;
     V1[e] = a1;
     VL[e] = make_double2(a2.x - ksq * a0.x, a2.y - ksq * a0.y);
+    V3[e] = times_i(cscale(a0, k3));
   }
 }
 
@@ -435,6 +437,41 @@ __global__ void __launch_bounds__(kThreads) k_values(DevPlan P, const double2* _
       wc.advance(cs, ncol, c, n2 + 1, P.ev_lo[3 * n2 + i]);
       Vc[e] = wc.dot(P.ev_w + (size_t(3 * n2) + i) * kMaxW);
     }
+  }
+}
+
+// m^c values at tau from (m_par in B, m2 in B*): m1 = (k1/k) E0 m_par,
+// m3 = (k3/k) E0 m_par, m2 = F0 c2; with md values given, the totals m^d + m^c
+__global__ void __launch_bounds__(kThreads) k_values_mc(DevPlan P, const double2* __restrict__ mpar,
+                                                        const double2* __restrict__ c2, const double2* __restrict__ d1,
+                                                        const double2* __restrict__ d2, const double2* __restrict__ d3,
+                                                        double2* __restrict__ V1, double2* __restrict__ V2,
+                                                        double2* __restrict__ V3) {
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int n2 = P.n2;
+  const double k1 = P.k1[c % P.nl], k3 = P.k3[c / P.nl], ksq = k1 * k1 + k3 * k3;
+  const double ik = (ksq > 0.0) ? 1.0 / sqrt(ksq) : 0.0;
+  const double f1 = k1 * ik, f3 = k3 * ik;
+  RowWindow wa, wc;
+  wa.init(mpar, ncol, c, n2);
+  wc.init(c2, ncol, c, n2 + 1);
+  for (int i = 0; i < n2; ++i) {
+    const size_t e = size_t(i) * ncol + c;
+    wa.advance(mpar, ncol, c, n2, P.ev_lo[i]);
+    wc.advance(c2, ncol, c, n2 + 1, P.ev_lo[3 * n2 + i]);
+    const double2 a = wa.dot(P.ev_w + size_t(i) * kMaxW);
+    const double2 b = wc.dot(P.ev_w + (size_t(3 * n2) + i) * kMaxW);
+    double2 m1 = cscale(a, f1), m3 = cscale(a, f3), m2 = b;
+    if (d1) {
+      m1 = cadd(m1, d1[e]);
+      m2 = cadd(m2, d2[e]);
+      m3 = cadd(m3, d3[e]);
+    }
+    V1[e] = m1;
+    V2[e] = m2;
+    V3[e] = m3;
   }
 }
 
@@ -562,38 +599,46 @@ __device__ __forceinline__ double2 band_apply(const BandRow& b, const double2* _
   return acc;
 }
 
-// evaluation at tau_j + spectral multiplier + inverse z-FFT of size N = m3.
+// inverse z-FFT of size N = m3 of values at tau_j (optionally times i k1, the
+// only multiplier that stays here: it is constant along a z line).
 // grid (ceil(nl/LG), planes, nin), block LG*T (line index lane-fastest).
-template <int N>
+// EXACT: nn = 2N/3 - 1 (3/2 grid), so the zero-padded positions are known
+// at compile time.
+template <int N, bool EXACT>
 __global__ void __launch_bounds__(kThreads) k_zinv_r(DevPlan P, EvalArgs A, double2* __restrict__ zbuf, int j0,
                                                     int pb) {
   using LP = LinePlan<N>;
   using ZS = ZShape<N>;
   constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL;
+  constexpr int NNX = 2 * N / 3 - 1, H3X = (NNX + 1) / 2, PADX = N - NNX;
   extern __shared__ double lds_d[];
   const int tid = threadIdx.x;
   const int ll = tid % LG, tl = tid / LG;
   const int f = blockIdx.z, jj = blockIdx.y, j = j0 + jj, l = blockIdx.x * LG + ll;
-  const int nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = N - nn;
+  const int nn = EXACT ? NNX : P.nn, nl = P.nl;
+  const int h3 = EXACT ? H3X : (nn + 1) / 2, pad = EXACT ? PADX : N - nn;
   const EvalIn in = A.in[f];
   const bool lok = l < nl;
   const size_t ncol = size_t(nn) * nl;
-  const BandRow br = band_row(P, in.kind, j);
-  const double k1 = lok ? P.k1[l] : 0.0;
+  const double k1 = (lok && in.ma == MU_IK1) ? P.k1[l] : 0.0;
+  const double2* src = in.a + size_t(j) * ncol + (lok ? l : 0);
   double2 v[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int pos = tl + T * r;
+    // compile-time zero when the whole r-slice lies in the padding
+    const bool always_pad = EXACT && (T * r >= H3X) && (T * r + T - 1 < H3X + PADX);
     double2 val = zero2();
-    if (lok && (pos < h3 || pos >= h3 + pad)) {
+    if (!always_pad && lok && (pos < h3 || pos >= h3 + pad)) {
       const int ni = pos < h3 ? pos : pos - pad;
-      const double k3 = P.k3[ni];
-      const double ksq = k1 * k1 + k3 * k3;
-      const size_t col = size_t(ni) * nl + l;
-      val = apply_mult(in.ma, k1, k3, band_apply(br, in.a, col, ncol, ksq));
-      if (in.b) val = cadd(val, apply_mult(in.mb, k1, k3, band_apply(br, in.b, col, ncol, ksq)));
+      val = src[size_t(ni) * nl];
+      if (in.b) val = cadd(val, in.b[size_t(j) * ncol + size_t(ni) * nl + l]);
     }
     v[r] = val;
+  }
+  if (in.ma == MU_IK1) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = make_double2(-k1 * v[r].y, k1 * v[r].x);
   }
   rf::run<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, ll * ZS::STRIDE, tl, P.fz.tw);
   if (lok) {
@@ -804,16 +849,20 @@ __global__ void __launch_bounds__(kThreads) k_xpass_r(DevPlan P, const double2* 
   double2 v[E];
 #pragma unroll 1
   for (int f = 0; f < S::NIN; ++f) {
+    // opaque per iteration: keeps the compiler from hoisting every LDS address
+    // and twiddle index of the transform out of the loop (register pressure)
+    int tlx = tl, basex = base;
+    asm volatile("" : "+v"(tlx), "+v"(basex));
     const double2* X = zbuf + ((size_t(f) * pb + jj) * M3 + (bok ? b : 0)) * nl;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      const int k = tl + T * r;
+      const int k = tlx + T * r;
       const double2 a = (bok && k < nl) ? X[k] : zero2();
       const double2 cj = (bok && k > 0 && N - k < nl) ? cconj(X[N - k]) : zero2();
       const double2 w = cconj(P.xtw[k]);  // exp(+2 pi i k / m1)
       v[r] = cadd(cadd(a, cj), times_i(cmul(w, csub(a, cj))));
     }
-    rf::run_wave<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_c, base, tl, P.fx.tw);
+    rf::run_wave<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_c, basex, tlx, P.fx.tw);
     // v[c*RL + r] holds the sample pair m = tl + T (c + r EL)
     if constexpr (PH == PH_TOPHYS) {
 #pragma unroll
@@ -842,14 +891,16 @@ __global__ void __launch_bounds__(kThreads) k_xpass_r(DevPlan P, const double2* 
   const double scale = 1.0 / (double(M1) * double(M3));
 #pragma unroll 1
   for (int g = 0; g < S::NOUT; ++g) {
+    int tlx = tl, basex = base;
+    asm volatile("" : "+v"(tlx), "+v"(basex));
     stream_out_dispatch<S, 0, E, S::NST>(P, g, st, v);
-    rf::run_wave<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_c, base, tl, P.fx.tw);
+    rf::run_wave<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_c, basex, tlx, P.fx.tw);
     // Y at k = tl + T (c + r EL); the real-signal unpacking needs Y_k and Y_{(N-k) mod N}
     rf::line_sync<T>();
 #pragma unroll
     for (int c = 0; c < EL; ++c)
 #pragma unroll
-      for (int r = 0; r < RL; ++r) lds_c[base + rf::padded<LP::PAD>(tl + T * (c + r * EL))] = v[c * RL + r];
+      for (int r = 0; r < RL; ++r) lds_c[basex + rf::padded<LP::PAD>(tlx + T * (c + r * EL))] = v[c * RL + r];
     rf::line_sync<T>();
     double2* Y0 = obuf + ((size_t(g) * pb + jj) * M3 + (bok ? b : 0)) * nl;
 #pragma unroll
@@ -857,8 +908,8 @@ __global__ void __launch_bounds__(kThreads) k_xpass_r(DevPlan P, const double2* 
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int q = c + r * EL;
-        const int k = tl + T * q;
-        const double2 Yp = lds_c[base + rf::padded<LP::PAD>((N - k) % N)];
+        const int k = tlx + T * q;
+        const double2 Yp = lds_c[basex + rf::padded<LP::PAD>((N - k) % N)];
         if (bok && k < nl) {
           const double2 Yk = v[c * RL + r];
           const double2 Yc = cconj(Yp);
@@ -880,7 +931,8 @@ template <int EPI>
 __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const double2* in, double2* out,
                                                    const double2* __restrict__ add, const double2* __restrict__ z,
                                                    const double2* __restrict__ zt_prev, double2* __restrict__ z_out,
-                                                   double2* __restrict__ vals_out, int stage, int ncol) {
+                                                   double2* __restrict__ vals_out, double2* __restrict__ vals_out1,
+                                                   int stage, int ncol) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const int n2 = P.n2;
@@ -914,24 +966,30 @@ __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const do
     for (int q = kMaxBand - 1; q > 0; --q) ring[q] = ring[q - 1];
     ring[0] = x;
     const size_t e = size_t(i) * ncol + c;
-    if (EPI == EPI_STORE) {
-      out[e] = x;
-    } else {
-      const double2 zt = cadd(x, add[e]);
-      out[e] = zt;
-      if (vals_out) {
+    const double2 fin = (EPI == EPI_STORE) ? x : cadd(x, add[e]);
+    out[e] = fin;
+    if (vals_out) {
 #pragma unroll
-        for (int q = kMaxW - 1; q > 0; --q) win[q] = win[q - 1];
-        win[0] = zt;
-        const int first = P.emit_first[i], cnt = P.emit_cnt[i];
-        for (int t = 0; t < cnt; ++t) {
-          const double* w0 = P.ev_w + size_t(first + t) * kMaxW;
-          double2 acc = zero2();
+      for (int q = kMaxW - 1; q > 0; --q) win[q] = win[q - 1];
+      win[0] = fin;
+      const int first = P.emit_first[i], cnt = P.emit_cnt[i];
+      for (int t = 0; t < cnt; ++t) {
+        const double* w0 = P.ev_w + size_t(first + t) * kMaxW;
+        double2 acc = zero2();
 #pragma unroll
-          for (int q = 0; q < kMaxW; ++q) acc = fma2(w0[q], win[q], acc);
-          vals_out[size_t(first + t) * ncol + c] = acc;
+        for (int q = 0; q < kMaxW; ++q) acc = fma2(w0[q], win[q], acc);
+        vals_out[size_t(first + t) * ncol + c] = acc;
+        if (vals_out1) {
+          const double* w1 = P.ev_w + (size_t(n2) + first + t) * kMaxW;
+          double2 acc1 = zero2();
+#pragma unroll
+          for (int q = 0; q < kMaxW; ++q) acc1 = fma2(w1[q], win[q], acc1);
+          vals_out1[size_t(first + t) * ncol + c] = acc1;
         }
       }
+    }
+    if (EPI != EPI_STORE) {
+      const double2 zt = fin;
       if (EPI == EPI_ADD_ZUPDATE) {
         const double2 z0 = z[e];
         double2 zn;
@@ -1455,7 +1513,7 @@ struct Workspace {
   size_t off_md1, off_md3, off_c2d, off_mpar, off_c2c, off_rz, off_zta, off_ztb, off_rhot, off_vals[kMaxOut];
   size_t off_u[3], off_T[6], off_rhov, off_yphi, off_yom, off_uscr, off_zbuf, off_obuf, off_mean;
   // values at the Greville points
-  size_t off_vz0, off_vz1, off_vzl, off_vmd1, off_vmd3, off_vc2d, off_vmpar, off_vc2c, off_vzt;
+  size_t off_vz0, off_vz1, off_vzl, off_vz3, off_vmd1, off_vmd3, off_vc2d, off_vm1c, off_vm2c, off_vm3c, off_vzt;
 };
 
 }  // namespace lmvd
@@ -1516,11 +1574,13 @@ static void layout_workspace(lmvd_plan_s* p) {
   w.off_vz0 = take(sB);
   w.off_vz1 = take(sB);
   w.off_vzl = take(sB);
+  w.off_vz3 = take(sB);
   w.off_vmd1 = take(sB);
   w.off_vmd3 = take(sB);
   w.off_vc2d = take(sB);
-  w.off_vmpar = take(sB);
-  w.off_vc2c = take(sB);
+  w.off_vm1c = take(sB);
+  w.off_vm2c = take(sB);
+  w.off_vm3c = take(sB);
   w.off_vzt = take(sB);
   w.bytes = o;
 }
@@ -1716,7 +1776,10 @@ static void launch_zinv_t(lmvd_plan_s* p, hipStream_t s, const EvalArgs& A, doub
   using ZS = ZShape<N>;
   const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nin);
   const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
-  hipLaunchKernelGGL(k_zinv_r<N>, g, dim3(ZS::LG * ZS::T), lds, s, p->D, A, zbuf, j0, p->pb);
+  if (p->H.nn == 2 * N / 3 - 1)
+    hipLaunchKernelGGL((k_zinv_r<N, true>), g, dim3(ZS::LG * ZS::T), lds, s, p->D, A, zbuf, j0, p->pb);
+  else
+    hipLaunchKernelGGL((k_zinv_r<N, false>), g, dim3(ZS::LG * ZS::T), lds, s, p->D, A, zbuf, j0, p->pb);
 }
 template <int N>
 static void launch_zfwd_t(lmvd_plan_s* p, hipStream_t s, const double2* obuf, const OutPtrs& V, int j0, int nb,
@@ -1781,7 +1844,10 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
     const int nb = std::min(p->pb, H.n2 - j0);
     const double zplane = double(M3) * nl * 16.0, splane = double(ncols(p)) * 16.0;
     const double nin = double(ins.size()), nout = double(outs.size());
-    const bool zr = p->use_reg && zreg_size(M3), xr = p->use_reg && xreg_size(H.hx);
+    bool inputs_plain = true;  // the register z kernel takes values with multiplier 1 or i k1 only
+    for (const EvalIn& e : ins)
+      if (e.kind != EV_IDENT || (e.ma != MU_ONE && e.ma != MU_IK1) || (e.b && e.mb != MU_ONE)) inputs_plain = false;
+    const bool zr = p->use_reg && zreg_size(M3) && inputs_plain, xr = p->use_reg && xreg_size(H.hx);
     if (!ins.empty()) {
       double terms = 0;
       for (const EvalIn& e : ins) terms += e.b ? 2 : 1;
@@ -1809,7 +1875,7 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
     }
     if (!outs.empty()) {
       ProfScope ps(p, KC_ZFWD, c.s, nb * nout * (zplane + splane));
-      if (zr) {
+      if (p->use_reg && zreg_size(M3)) {
 #define CALLF(N) launch_zfwd_t<N>(p, c.s, obuf, V, j0, nb, int(outs.size()))
         LMVD_ZSWITCH(M3, CALLF)
 #undef CALLF
@@ -1822,11 +1888,12 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
 }
 
-static void proj(const Ctx& c, int kind, const double2* in, double2* out) {
+static void proj(const Ctx& c, int kind, const double2* in, double2* out, double2* v0 = nullptr,
+                 double2* v1 = nullptr) {
   const int n = int(ncols(c.p));
   ProfScope ps(c.p, KC_PROJ, c.s, 2.0 * 16.0 * n * c.p->H.n2);
   hipLaunchKernelGGL(k_proj<EPI_STORE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, c.s, c.p->D, kind,
-                     in, out, nullptr, nullptr, nullptr, nullptr, nullptr, 0, n);
+                     in, out, nullptr, nullptr, nullptr, nullptr, v0, v1, 0, n);
 }
 
 template <int MODE>
@@ -1879,13 +1946,20 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   double2* vz0 = c.at<double2>(W.off_vz0);
   double2* vz1 = c.at<double2>(W.off_vz1);
   double2* vzl = c.at<double2>(W.off_vzl);
+  double2* vz3 = c.at<double2>(W.off_vz3);
   double2* vmd1 = c.at<double2>(W.off_vmd1);
   double2* vmd3 = c.at<double2>(W.off_vmd3);
   double2* vc2d = c.at<double2>(W.off_vc2d);
-  double2* vmpar = c.at<double2>(W.off_vmpar);
-  double2* vc2c = c.at<double2>(W.off_vc2c);
+  double2* vm1 = c.at<double2>(W.off_vm1c);
+  double2* vm2 = c.at<double2>(W.off_vm2c);
+  double2* vm3 = c.at<double2>(W.off_vm3c);
   double2* vzt = c.at<double2>(W.off_vzt);
   const dim3 cgrid((unsigned)((ncol + kThreads - 1) / kThreads));
+  auto values_mc = [&](bool total) {
+    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * (total ? 8 : 5));
+    hipLaunchKernelGGL(k_values_mc, cgrid, dim3(kThreads), 0, s, p->D, mpar, c2c, total ? vmd1 : nullptr,
+                       total ? vc2d : nullptr, total ? vmd3 : nullptr, vm1, vm2, vm3);
+  };
   auto values = [&](const double2* a1, double2* v1, const double2* a2, double2* v2, const double2* a3, double2* v3) {
     ProfScope ps(p, KC_PROJ, s, 16.0 * nB * ((a1 ? 2 : 0) + (a2 ? 2 : 0) + (a3 ? 2 : 0)));
     hipLaunchKernelGGL(k_values, cgrid, dim3(kThreads), 0, s, p->D, a1, v1, a2, v2, a3, v3);
@@ -1896,13 +1970,13 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   values(md1, vmd1, md3, vmd3, c2d, vc2d);
   // values of z and its y-derivatives (z is fixed during the substep)
   {
-    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * 4);
-    hipLaunchKernelGGL(k_values_z, cgrid, dim3(kThreads), 0, s, p->D, z, vz0, vz1, vzl);
+    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * 5);
+    hipLaunchKernelGGL(k_values_z, cgrid, dim3(kThreads), 0, s, p->D, z, vz0, vz1, vzl, vz3);
   }
   // 2. R_z
   st = plane_phase<PH_RZ>(c,
                           {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT),
-                           ev(vc2d, EV_IDENT), ev(vz0, EV_IDENT, MU_IK3), ev(vmd3, EV_IDENT), ev(vz0, EV_IDENT)},
+                           ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT), ev(vz0, EV_IDENT)},
                           {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
@@ -1937,11 +2011,10 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     if (st != LMVD_OK) return st;
     proj(c, 0, vals[0], rhot);
     solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
-    values(mpar, vmpar, nullptr, nullptr, c2c, vc2c);
+    values_mc(false);
     st = plane_phase<PH_L>(c,
-                           {ev(vz0, EV_IDENT, MU_IK1), ev(vmpar, EV_IDENT, MU_K1K), ev(vz1, EV_IDENT),
-                            ev(vc2c, EV_IDENT), ev(vz0, EV_IDENT, MU_IK3), ev(vmpar, EV_IDENT, MU_K3K),
-                            ev(vz0, EV_IDENT)},
+                           {ev(vz0, EV_IDENT, MU_IK1), ev(vm1, EV_IDENT), ev(vz1, EV_IDENT), ev(vm2, EV_IDENT),
+                            ev(vz3, EV_IDENT), ev(vm3, EV_IDENT), ev(vz0, EV_IDENT)},
                            {vals[0]});
     if (st != LMVD_OK) return st;
     double2* next = (last && user_zt) ? user_zt : (cur == zta ? ztb : zta);
@@ -1950,10 +2023,10 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     if (last) {
       hipLaunchKernelGGL(k_proj<EPI_ADD_ZUPDATE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
                          vals[0], next, rz, z, static_cast<const double2*>(a->zt_prev),
-                         static_cast<double2*>(a->z_out), vzt, a->stage, n);
+                         static_cast<double2*>(a->z_out), vzt, nullptr, a->stage, n);
     } else {
       hipLaunchKernelGGL(k_proj<EPI_ADD>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
-                         vals[0], next, rz, nullptr, nullptr, nullptr, vzt, a->stage, n);
+                         vals[0], next, rz, nullptr, nullptr, nullptr, vzt, nullptr, a->stage, n);
     }
     cur = next;
   }
@@ -1962,11 +2035,11 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   if (st != LMVD_OK) return st;
   proj(c, 0, vals[0], rhot);
   solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
-  values(mpar, vmpar, nullptr, nullptr, c2c, vc2c);
+  values_mc(true);  // m = m^d + m^c values
   // 4./5. velocities, density, fluxes
-  const EvalIn m1 = ev(vmd1, EV_IDENT, MU_ONE, vmpar, MU_K1K);
-  const EvalIn m2 = ev(vc2d, EV_IDENT, MU_ONE, vc2c, MU_ONE);
-  const EvalIn m3 = ev(vmd3, EV_IDENT, MU_ONE, vmpar, MU_K3K);
+  const EvalIn m1 = ev(vm1, EV_IDENT);
+  const EvalIn m2 = ev(vm2, EV_IDENT);
+  const EvalIn m3 = ev(vm3, EV_IDENT);
   // u = m/rho, rho and C_ij = -m_i m_j/rho on the physical grid; u_hat by interpolation;
   // T_ij = C_ij + tau_ij(u_hat) projected
   double2* cv[6] = {vals[4], vals[5], vals[6], vals[7], vals[8], vals[9]};
