@@ -241,6 +241,86 @@ __device__ __forceinline__ void run(double2* v, double* lds, int base, int tl, c
   }
 }
 
+// ---- lines of one wavefront (or less) with LDS twiddles ------------------------
+//
+// Variant for kernels whose LDS budget is tight: the exchange moves real and
+// imaginary planes of doubles one after the other, and the stage twiddles come
+// from a table twl[t] = exp(-2 pi i t / N), t < N/2, held in LDS.  Only the
+// first power w of a butterfly is read; w^r follows by repeated products
+// (rounding grows like r ulp, far below the transform's own error).
+
+template <int N, int T, int DIR, int R, int NS>
+__device__ __forceinline__ void stage_lt(double2* v, int tl, const double2* twl) {
+  constexpr int E = N / T;
+  constexpr int NB = E / R;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if constexpr (NS > 1) {
+      const int jm = (tl + T * c) % NS;
+      double2 w1 = twl[jm * (N / (NS * R))];
+      if (DIR > 0) w1.y = -w1.y;
+      double2 w = w1;
+      v[c * R + 1] = cmul(v[c * R + 1], w1);
+#pragma unroll
+      for (int r = 2; r < R; ++r) {
+        w = cmul(w, w1);
+        v[c * R + r] = cmul(v[c * R + r], w);
+      }
+    }
+    Dft<R, DIR>::run(v + c * R);
+  }
+}
+
+template <int N, int T, int Ra, int NSa, int Rb, int PADDIV>
+__device__ __forceinline__ void exchange_split(double2* v, double* lds, int base, int tl) {
+  constexpr int E = N / T;
+  double tmp[E];
+  line_sync<T>();
+#pragma unroll
+  for (int c = 0; c < E / Ra; ++c)
+#pragma unroll
+    for (int r = 0; r < Ra; ++r) lds[base + padded<PADDIV>(out_pos<N, T, Ra, NSa>(tl, c, r))] = v[c * Ra + r].x;
+  line_sync<T>();
+#pragma unroll
+  for (int c = 0; c < E / Rb; ++c)
+#pragma unroll
+    for (int r = 0; r < Rb; ++r) tmp[c * Rb + r] = lds[base + padded<PADDIV>(in_pos<N, T, Rb>(tl, c, r))];
+  line_sync<T>();
+#pragma unroll
+  for (int c = 0; c < E / Ra; ++c)
+#pragma unroll
+    for (int r = 0; r < Ra; ++r) lds[base + padded<PADDIV>(out_pos<N, T, Ra, NSa>(tl, c, r))] = v[c * Ra + r].y;
+  line_sync<T>();
+#pragma unroll
+  for (int c = 0; c < E / Rb; ++c)
+#pragma unroll
+    for (int r = 0; r < Rb; ++r) {
+      const int k = c * Rb + r;
+      v[k] = make_double2(tmp[k], lds[base + padded<PADDIV>(in_pos<N, T, Rb>(tl, c, r))]);
+    }
+}
+
+template <int N, int T, int DIR, int R0, int R1, int R2, int R3, int PADDIV>
+__device__ __forceinline__ void run_split(double2* v, double* lds, int base, int tl, const double2* twl) {
+  static_assert(R0 * R1 * R2 * R3 == N, "radices must multiply to N");
+  static_assert((N / T) % R0 == 0 && (N / T) % R1 == 0 && (N / T) % R2 == 0 && (N / T) % R3 == 0,
+                "every radix must divide N/T");
+  constexpr int NS1 = R0, NS2 = R0 * R1, NS3 = R0 * R1 * R2;
+  stage_lt<N, T, DIR, R0, 1>(v, tl, twl);
+  if constexpr (R1 > 1) {
+    exchange_split<N, T, R0, 1, R1, PADDIV>(v, lds, base, tl);
+    stage_lt<N, T, DIR, R1, NS1>(v, tl, twl);
+  }
+  if constexpr (R2 > 1) {
+    exchange_split<N, T, R1, NS1, R2, PADDIV>(v, lds, base, tl);
+    stage_lt<N, T, DIR, R2, NS2>(v, tl, twl);
+  }
+  if constexpr (R3 > 1) {
+    exchange_split<N, T, R2, NS2, R3, PADDIV>(v, lds, base, tl);
+    stage_lt<N, T, DIR, R3, NS3>(v, tl, twl);
+  }
+}
+
 // radix of the last stage
 template <int R0, int R1, int R2, int R3>
 struct Last {

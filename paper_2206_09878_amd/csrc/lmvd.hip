@@ -176,11 +176,11 @@ template <int PH>
 struct Op;
 
 template <>
-struct Op<PH_RZ> {  // R_z = (1/rho)(-m^d . grad z + rho D lap z); inputs lap z, z1, m1, z2, m2, z3, m3, z
+struct Op<PH_RZ> {  // R_z = (1/rho)(-m^d . grad z + rho D lap z); inputs z1, m1, z2, m2, z3, m3, lap z, z
   static constexpr int NIN = 8, NOUT = 1;
   __device__ static void apply(const DevPlan& P, const double* x, double* y) {
     const double ir = (P.rho_h - P.drho * x[7]) * P.inv_rlrh;
-    y[0] = (P.rhoD * x[0] - (x[1] * x[2] + x[3] * x[4] + x[5] * x[6])) * ir;
+    y[0] = (P.rhoD * x[6] - (x[0] * x[1] + x[2] * x[3] + x[4] * x[5])) * ir;
   }
 };
 template <>
@@ -553,51 +553,25 @@ struct ZShape {
   // 8 lines on distinct banks; otherwise an odd stride
   static constexpr int STRIDE = (LG == 8) ? (BASE + ((2 - BASE % 32) + 32) % 32) : (BASE | 1);
 };
-// lines per block and LDS line stride of the x kernels (threads of a line lane-fastest)
+// x-line plans: full-length complex FFTs of m1 points, E = 12 per thread
 template <int N>
-struct XShape {
-  static constexpr int T = LinePlan<N>::T;
-  static constexpr int BG = kThreads / T;
-  static constexpr int STRIDE = N + N / LinePlan<N>::PAD;
-};
-
-// band row of the evaluation at tau_j, hoisted out of the per-mode loop
-struct BandRow {
-  int lo, rows, kind;
-  double w[kMaxW], w0[kMaxW];
-};
-__device__ __forceinline__ BandRow band_row(const DevPlan& P, int kind, int j) {
-  BandRow b;
-  b.kind = kind;
-  b.rows = (kind == EV_F0) ? P.n2 + 1 : P.n2;
-  const int kk = (kind == EV_LAP) ? EV_E2 : (kind == EV_IDENT ? EV_E0 : kind);
-  b.lo = P.ev_lo[kk * P.n2 + j];
-  const double* w = P.ev_w + (size_t(kk) * P.n2 + j) * kMaxW;
-  const double* w0 = P.ev_w + size_t(j) * kMaxW;
-#pragma unroll
-  for (int q = 0; q < kMaxW; ++q) {
-    b.w[q] = w[q];
-    b.w0[q] = (kind == EV_LAP) ? w0[q] : 0.0;
-  }
-  if (kind == EV_IDENT) b.lo = j;
-  return b;
-}
-__device__ __forceinline__ double2 band_apply(const BandRow& b, const double2* __restrict__ src, size_t col,
-                                              size_t ncol, double ksq) {
-  if (b.kind == EV_IDENT) return src[size_t(b.lo) * ncol + col];
-  double2 acc = zero2(), acc0 = zero2();
-#pragma unroll
-  for (int q = 0; q < kMaxW; ++q) {
-    const int r = b.lo + q;
-    if (r < b.rows && (b.w[q] != 0.0 || b.w0[q] != 0.0)) {
-      const double2 s = src[size_t(r) * ncol + col];
-      acc = fma2(b.w[q], s, acc);
-      acc0 = fma2(b.w0[q], s, acc0);
-    }
-  }
-  if (b.kind == EV_LAP) acc = make_double2(acc.x - ksq * acc0.x, acc.y - ksq * acc0.y);
-  return acc;
-}
+struct XPlan;
+#define LMVD_XPLAN(N_, T_, R0_, R1_, R2_, R3_, PAD_)                                                 \
+  template <>                                                                                        \
+  struct XPlan<N_> {                                                                                 \
+    static constexpr int T = T_, R0 = R0_, R1 = R1_, R2 = R2_, R3 = R3_, PAD = PAD_;                 \
+    static constexpr int E = N_ / T_;                                                                \
+    static constexpr int RL = rf::Last<R0_, R1_, R2_, R3_>::value;                                   \
+    static constexpr int BG = kThreads / T_;                     /* lines per block */               \
+    static constexpr int STRIDE = ((N_ + N_ / PAD_) + 1) / 2 * 2; /* doubles per line, even */        \
+  };
+LMVD_XPLAN(768, 64, 12, 4, 4, 4, 12)
+LMVD_XPLAN(192, 16, 12, 4, 4, 1, 12)
+LMVD_XPLAN(144, 12, 12, 12, 1, 1, 12)
+LMVD_XPLAN(96, 8, 12, 4, 2, 1, 12)
+LMVD_XPLAN(72, 6, 12, 6, 1, 1, 12)
+LMVD_XPLAN(48, 4, 12, 4, 1, 1, 12)
+#undef LMVD_XPLAN
 
 // inverse z-FFT of size N = m3 of values at tau_j (optionally times i k1, the
 // only multiplier that stays here: it is constant along a z line).
@@ -681,244 +655,291 @@ __global__ void __launch_bounds__(kThreads) k_zfwd_r(DevPlan P, const double2* _
   }
 }
 
-// Pointwise products, streamed: each input field updates a few per-point
-// accumulators as soon as its physical values exist; outputs are formed from
-// the accumulators.  Inputs are consumed in the order of the phase's input
-// list.  in<F>/out<G> act on one physical point.
+// Pointwise products of the x-pass.  Two real fields x, y travel through one
+// complex FFT as x + i y, so a product of the pair needs no carried state.
+// Input FFT I carries fields fa(I) and fb(I) (fb < 0: a single field, y = 0);
+// in<I> folds the point values into the state s; output FFT Q carries
+// fields ga(Q) and gb(Q) formed by out<Q>.
 template <int PH>
-struct Stream;
+struct Pair;
 
 template <>
-struct Stream<PH_RZ> {  // inputs lap z, z1, m1, z2, m2, z3, m3, z (R_z)
-  static constexpr int NIN = 8, NOUT = 1, NST = 2;
-  template <int F>
-  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x) {
-    if constexpr (F == 0) s[0] = P.rhoD * x;
-    else if constexpr (F == 1 || F == 3 || F == 5) s[1] = x;
-    else if constexpr (F == 7) s[0] *= (P.rho_h - P.drho * x) * P.inv_rlrh;
-    else s[0] -= s[1] * x;
+struct Pair<PH_RZ> {  // inputs z1, m1, z2, m2, z3, m3, lap z, z:  R_z = (1/rho)(-m^d . grad z + rho D lap z)
+  static constexpr int NP = 4, NQ = 1, NST = 1;
+  __device__ static constexpr int fa(int i) { return 2 * i; }
+  __device__ static constexpr int fb(int i) { return 2 * i + 1; }
+  __device__ static constexpr int ga(int q) { return q; }
+  __device__ static constexpr int gb(int) { return -1; }
+  template <int I>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y) {
+    if constexpr (I == 0) s[0] = -(x * y);
+    else if constexpr (I < 3) s[0] -= x * y;
+    else s[0] = (s[0] + P.rhoD * x) * ((P.rho_h - P.drho * y) * P.inv_rlrh);
   }
-  template <int G>
-  __device__ __forceinline__ static double out(const DevPlan&, const double* s) { return s[0]; }
+  template <int Q>
+  __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
 };
 template <>
-struct Stream<PH_L> {  // inputs z1, m1c, z2, m2c, z3, m3c, z (L z_t)
-  static constexpr int NIN = 7, NOUT = 1, NST = 2;
-  template <int F>
-  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x) {
-    if constexpr (F == 0 || F == 2 || F == 4) s[1] = x;
-    else if constexpr (F == 1) s[0] = -(s[1] * x);
-    else if constexpr (F == 6) s[0] *= (P.rho_h - P.drho * x) * P.inv_rlrh;
-    else s[0] -= s[1] * x;
+struct Pair<PH_L> {  // inputs z1, m1c, z2, m2c, z3, m3c, z:  L z_t = -(1/rho) grad z . m^c
+  static constexpr int NP = 4, NQ = 1, NST = 1;
+  __device__ static constexpr int fa(int i) { return 2 * i; }
+  __device__ static constexpr int fb(int i) { return i < 3 ? 2 * i + 1 : -1; }
+  __device__ static constexpr int ga(int q) { return q; }
+  __device__ static constexpr int gb(int) { return -1; }
+  template <int I>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y) {
+    if constexpr (I == 0) s[0] = -(x * y);
+    else if constexpr (I < 3) s[0] -= x * y;
+    else s[0] *= (P.rho_h - P.drho * x) * P.inv_rlrh;
   }
-  template <int G>
-  __device__ __forceinline__ static double out(const DevPlan&, const double* s) { return s[0]; }
+  template <int Q>
+  __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
 };
 template <>
-struct Stream<PH_RHOT> {  // inputs z, z_t (rho_t = f'(z) z_t)
-  static constexpr int NIN = 2, NOUT = 1, NST = 1;
-  template <int F>
-  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x) {
-    if constexpr (F == 0) {
-      const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x);
-      s[0] = rho * rho * P.drho * P.inv_rlrh;
+struct Pair<PH_RHOT> {  // inputs z, z_t:  rho_t = f'(z) z_t = rho^2 (rh - rl)/(rl rh) z_t
+  static constexpr int NP = 1, NQ = 1, NST = 1;
+  __device__ static constexpr int fa(int) { return 0; }
+  __device__ static constexpr int fb(int) { return 1; }
+  __device__ static constexpr int ga(int q) { return q; }
+  __device__ static constexpr int gb(int) { return -1; }
+  template <int I>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y) {
+    const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x);
+    s[0] = rho * rho * P.drho * P.inv_rlrh * y;
+  }
+  template <int Q>
+  __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
+};
+template <>
+struct Pair<PH_VEL> {  // inputs z, m1, m2, m3 -> u1, u2, u3, rho, C11, C12, C13, C22, C23, C33
+  static constexpr int NP = 2, NQ = 5, NST = 4;
+  __device__ static constexpr int fa(int i) { return 2 * i; }
+  __device__ static constexpr int fb(int i) { return 2 * i + 1; }
+  __device__ static constexpr int ga(int q) { return 2 * q; }
+  __device__ static constexpr int gb(int q) { return 2 * q + 1; }
+  template <int I>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y) {
+    if constexpr (I == 0) {
+      s[0] = P.rho_h - P.drho * x;  // rl rh / rho
+      s[1] = y;
     } else {
-      s[0] = s[0] * x;
+      s[2] = x;
+      s[3] = y;
     }
   }
-  template <int G>
-  __device__ __forceinline__ static double out(const DevPlan&, const double* s) { return s[0]; }
-};
-template <>
-struct Stream<PH_VEL> {  // inputs z, m1, m2, m3 -> u1, u2, u3, rho, C11, C12, C13, C22, C23, C33
-  static constexpr int NIN = 4, NOUT = 10, NST = 4;
-  template <int F>
-  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x) {
-    s[F] = (F == 0) ? (P.rho_h - P.drho * x) : x;
-  }
-  template <int G>
-  __device__ __forceinline__ static double out(const DevPlan& P, const double* s) {
+  template <int Q>
+  __device__ __forceinline__ static double2 out(const DevPlan& P, const double* s) {
     const double ir = s[0] * P.inv_rlrh;
-    if constexpr (G == 0) return s[1] * ir;
-    else if constexpr (G == 1) return s[2] * ir;
-    else if constexpr (G == 2) return s[3] * ir;
-    else if constexpr (G == 3) return (P.rho_l * P.rho_h) / s[0];
-    else if constexpr (G == 4) return -s[1] * (s[1] * ir);
-    else if constexpr (G == 5) return -s[1] * (s[2] * ir);
-    else if constexpr (G == 6) return -s[1] * (s[3] * ir);
-    else if constexpr (G == 7) return -s[2] * (s[2] * ir);
-    else if constexpr (G == 8) return -s[2] * (s[3] * ir);
-    else return -s[3] * (s[3] * ir);
+    if constexpr (Q == 0) return make_double2(s[1] * ir, s[2] * ir);
+    else if constexpr (Q == 1) return make_double2(s[3] * ir, (P.rho_l * P.rho_h) / s[0]);
+    else if constexpr (Q == 2) return make_double2(-s[1] * (s[1] * ir), -s[1] * (s[2] * ir));
+    else if constexpr (Q == 3) return make_double2(-s[1] * (s[3] * ir), -s[2] * (s[2] * ir));
+    else return make_double2(-s[2] * (s[3] * ir), -s[3] * (s[3] * ir));
   }
 };
 template <>
-struct Stream<PH_TOPHYS> {
-  static constexpr int NIN = 1, NOUT = 0, NST = 1;
-  template <int F>
-  __device__ __forceinline__ static void in(const DevPlan&, double*, double) {}
-  template <int G>
-  __device__ __forceinline__ static double out(const DevPlan&, const double*) { return 0.0; }
+struct Pair<PH_TOPHYS> {  // one input, written out on the physical grid
+  static constexpr int NP = 1, NQ = 0, NST = 1;
+  __device__ static constexpr int fa(int) { return 0; }
+  __device__ static constexpr int fb(int) { return -1; }
+  __device__ static constexpr int ga(int q) { return q; }
+  __device__ static constexpr int gb(int) { return -1; }
+  template <int I>
+  __device__ __forceinline__ static void in(const DevPlan&, double*, double, double) {}
+  template <int Q>
+  __device__ __forceinline__ static double2 out(const DevPlan&, const double*) { return zero2(); }
 };
 template <>
-struct Stream<PH_FROMPHYS> {
-  static constexpr int NIN = 0, NOUT = 1, NST = 1;
-  template <int F>
-  __device__ __forceinline__ static void in(const DevPlan&, double*, double) {}
-  template <int G>
-  __device__ __forceinline__ static double out(const DevPlan&, const double* s) { return s[0]; }
+struct Pair<PH_FROMPHYS> {  // one output, read from the physical grid
+  static constexpr int NP = 0, NQ = 1, NST = 1;
+  __device__ static constexpr int fa(int) { return 0; }
+  __device__ static constexpr int fb(int) { return -1; }
+  __device__ static constexpr int ga(int q) { return q; }
+  __device__ static constexpr int gb(int) { return -1; }
+  template <int I>
+  __device__ __forceinline__ static void in(const DevPlan&, double*, double, double) {}
+  template <int Q>
+  __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
 };
 
-// apply input F to every point of the thread: point pair q of register slot
-// v[c*RL + r] has q = c + r*EL
-template <class S, int F, int E, int RL, int NST>
-__device__ __forceinline__ void stream_in(const DevPlan& P, double (&st)[NST][2 * E], const double2* v) {
-  constexpr int EL = E / RL;
+// state update of input FFT I (runtime index i) on every point of the thread;
+// point q of the line (position tl + T q) sits in register slot
+// v[c*RL + r] with q = c + r*EL after an inverse transform
+template <class S, int I, int E, int RL, int NST>
+__device__ __forceinline__ void pair_in(const DevPlan& P, int i, double (&st)[NST][E], const double2* v) {
+  if constexpr (I < S::NP) {
+    if (i == I) {
+      constexpr int EL = E / RL;
 #pragma unroll
-  for (int c = 0; c < EL; ++c)
+      for (int c = 0; c < EL; ++c)
 #pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      const int q = c + r * EL;
-      double sa[NST], sb[NST];
+        for (int r = 0; r < RL; ++r) {
+          const int q = c + r * EL;
+          double s[NST];
 #pragma unroll
-      for (int k = 0; k < NST; ++k) {
-        sa[k] = st[k][2 * q];
-        sb[k] = st[k][2 * q + 1];
-      }
-      S::template in<F>(P, sa, v[c * RL + r].x);
-      S::template in<F>(P, sb, v[c * RL + r].y);
+          for (int k = 0; k < NST; ++k) s[k] = st[k][q];
+          S::template in<I>(P, s, v[c * RL + r].x, v[c * RL + r].y);
 #pragma unroll
-      for (int k = 0; k < NST; ++k) {
-        st[k][2 * q] = sa[k];
-        st[k][2 * q + 1] = sb[k];
-      }
+          for (int k = 0; k < NST; ++k) st[k][q] = s[k];
+        }
+    } else {
+      pair_in<S, I + 1, E, RL, NST>(P, i, st, v);
     }
-}
-template <class S, int F, int E, int RL, int NST>
-__device__ __forceinline__ void stream_in_dispatch(const DevPlan& P, int f, double (&st)[NST][2 * E],
-                                                   const double2* v) {
-  if constexpr (F < S::NIN) {
-    if (f == F) stream_in<S, F, E, RL, NST>(P, st, v);
-    else stream_in_dispatch<S, F + 1, E, RL, NST>(P, f, st, v);
   }
 }
-template <class S, int G, int E, int NST>
-__device__ __forceinline__ void stream_out(const DevPlan& P, const double (&st)[NST][2 * E], double2* v) {
+template <class S, int Q, int E, int NST>
+__device__ __forceinline__ void pair_out(const DevPlan& P, int q, const double (&st)[NST][E], double2* v) {
+  if constexpr (Q < S::NQ) {
+    if (q == Q) {
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    double sa[NST], sb[NST];
+      for (int e = 0; e < E; ++e) {
+        double s[NST];
 #pragma unroll
-    for (int k = 0; k < NST; ++k) {
-      sa[k] = st[k][2 * q];
-      sb[k] = st[k][2 * q + 1];
+        for (int k = 0; k < NST; ++k) s[k] = st[k][e];
+        v[e] = S::template out<Q>(P, s);
+      }
+    } else {
+      pair_out<S, Q + 1, E, NST>(P, q, st, v);
     }
-    v[q] = make_double2(S::template out<G>(P, sa), S::template out<G>(P, sb));
-  }
-}
-template <class S, int G, int E, int NST>
-__device__ __forceinline__ void stream_out_dispatch(const DevPlan& P, int g, const double (&st)[NST][2 * E],
-                                                    double2* v) {
-  if constexpr (G < S::NOUT) {
-    if (g == G) stream_out<S, G, E, NST>(P, st, v);
-    else stream_out_dispatch<S, G + 1, E, NST>(P, g, st, v);
   }
 }
 
-// x-pass with register FFTs of size N = m1/2.  grid (ceil(m3/BG), planes),
-// block BG*T; the T threads of a line are consecutive lanes, so where T
-// divides 64 the LDS exchanges of a line need only wave-level ordering.
+// x-pass: per (plane, z line b) inverse x-FFTs of the inputs, products,
+// forward x-FFTs of the outputs, m1 = N points, retained modes l < N/3.
+// Spectral line X_l (l < N/3) of a real field; a pair X, Y enters one
+// transform as Z_l = X_l + i Y_l, Z_{N-l} = conj(X_l) + i conj(Y_l), with
+// the real parts of X_0, Y_0 (what the Hermitian extension keeps).  An
+// output pair u + i v with transform W splits as U_k = (W_k + conj W_{N-k})/2,
+// V_k = (W_k - conj W_{N-k})/(2i).  grid (ceil(m3/BG), planes), block BG*T.
 template <int PH, int N>
-__global__ void __launch_bounds__(kThreads) k_xpass_r(DevPlan P, const double2* __restrict__ zbuf,
-                                                     double2* __restrict__ obuf, int pb, double* phys_out,
-                                                     const double* phys_in, int j0) {
-  using LP = LinePlan<N>;
-  using XS = XShape<N>;
-  using S = Stream<PH>;
-  constexpr int T = LP::T, E = LP::E, RL = LP::RL, EL = E / RL;
-  extern __shared__ double2 lds_c[];
+__global__ void __launch_bounds__(kThreads) k_xpair(DevPlan P, const double2* __restrict__ zbuf,
+                                                   double2* __restrict__ obuf, int pb, double* phys_out,
+                                                   const double* phys_in, int j0) {
+  using LP = XPlan<N>;
+  using S = Pair<PH>;
+  constexpr int T = LP::T, E = LP::E, RL = LP::RL, EL = E / RL, BG = LP::BG, NL = N / 3;
+  static_assert(E == 12 && NL % T == 0, "x plans hold 12 points per thread, N/3 retained modes");
+  constexpr int QL = NL / T;  // points q < QL hold retained modes k = tl + T q < N/3
+  extern __shared__ double lds_d[];
+  double2* twl = reinterpret_cast<double2*>(lds_d + BG * LP::STRIDE);
   const int tid = threadIdx.x;
   const int tl = tid % T, line = tid / T;
-  const int jj = blockIdx.y, b = blockIdx.x * XS::BG + line;
-  const int nl = P.nl, M3 = P.m3, M1 = P.m1;
+  const int jj = blockIdx.y, b = blockIdx.x * BG + line;
+  const int M3 = P.m3;
   const bool bok = b < M3;
-  const int base = line * XS::STRIDE;
-  double st[S::NST][2 * E];
+  const int bb = bok ? b : 0;
+  for (int t = tid; t < N / 2; t += BG * T) twl[t] = P.xtw[t];
+  __syncthreads();
+  const int base = line * LP::STRIDE;
+  double st[S::NST][E];
 #pragma unroll
   for (int k = 0; k < S::NST; ++k)
 #pragma unroll
-    for (int q = 0; q < 2 * E; ++q) st[k][q] = 0.0;
+    for (int q = 0; q < E; ++q) st[k][q] = 0.0;
   double2 v[E];
 #pragma unroll 1
-  for (int f = 0; f < S::NIN; ++f) {
+  for (int i = 0; i < S::NP; ++i) {
     // opaque per iteration: keeps the compiler from hoisting every LDS address
-    // and twiddle index of the transform out of the loop (register pressure)
+    // and twiddle of the transform out of the loop (register pressure)
     int tlx = tl, basex = base;
     asm volatile("" : "+v"(tlx), "+v"(basex));
-    const double2* X = zbuf + ((size_t(f) * pb + jj) * M3 + (bok ? b : 0)) * nl;
+    const int fa = S::fa(i), fb = S::fb(i);
+    const double2* XA = zbuf + ((size_t(fa) * pb + jj) * M3 + bb) * NL;
+    const double2* XB = zbuf + ((size_t(fb < 0 ? fa : fb) * pb + jj) * M3 + bb) * NL;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      const int k = tlx + T * r;
-      const double2 a = (bok && k < nl) ? X[k] : zero2();
-      const double2 cj = (bok && k > 0 && N - k < nl) ? cconj(X[N - k]) : zero2();
-      const double2 w = cconj(P.xtw[k]);  // exp(+2 pi i k / m1)
-      v[r] = cadd(cadd(a, cj), times_i(cmul(w, csub(a, cj))));
+      double2 z = zero2();
+      if (!(T * r >= NL && T * r + T - 1 <= N - NL) && bok) {
+        const int pos = tlx + T * r;
+        if (pos < NL) {
+          double2 xa = XA[pos];
+          double2 xb = fb >= 0 ? XB[pos] : zero2();
+          if (pos == 0) {
+            xa.y = 0.0;
+            xb.y = 0.0;
+          }
+          z = make_double2(xa.x - xb.y, xa.y + xb.x);
+        } else if (pos > N - NL) {
+          const double2 xa = XA[N - pos];
+          const double2 xb = fb >= 0 ? XB[N - pos] : zero2();
+          z = make_double2(xa.x + xb.y, xb.x - xa.y);
+        }
+      }
+      v[r] = z;
     }
-    rf::run_wave<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_c, basex, tlx, P.fx.tw);
-    // v[c*RL + r] holds the sample pair m = tl + T (c + r EL)
+    rf::run_split<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, basex, tlx, twl);
     if constexpr (PH == PH_TOPHYS) {
 #pragma unroll
       for (int c = 0; c < EL; ++c)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
           const int q = c + r * EL;
-          if (bok) {
-            double* dst = phys_out + (size_t(j0 + jj) * M3 + b) * M1 + 2 * (tl + T * q);
-            dst[0] = v[c * RL + r].x;
-            dst[1] = v[c * RL + r].y;
-          }
+          if (bok) phys_out[(size_t(j0 + jj) * M3 + b) * P.m1 + tl + T * q] = v[c * RL + r].x;
         }
     } else {
-      stream_in_dispatch<S, 0, E, RL, S::NST>(P, f, st, v);
+      pair_in<S, 0, E, RL, S::NST>(P, i, st, v);
     }
   }
   if constexpr (PH == PH_FROMPHYS) {
+    const double* src = phys_in + (size_t(j0 + jj) * M3 + bb) * P.m1 + tl;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const double* src = phys_in + (size_t(j0 + jj) * M3 + (bok ? b : 0)) * M1 + 2 * (tl + T * q);
-      st[0][2 * q] = bok ? src[0] : 0.0;
-      st[0][2 * q + 1] = bok ? src[1] : 0.0;
-    }
+    for (int q = 0; q < E; ++q) st[0][q] = bok ? src[T * q] : 0.0;
   }
-  const double scale = 1.0 / (double(M1) * double(M3));
+  const double scale = 1.0 / (double(P.m1) * double(M3));
 #pragma unroll 1
-  for (int g = 0; g < S::NOUT; ++g) {
+  for (int q = 0; q < S::NQ; ++q) {
     int tlx = tl, basex = base;
     asm volatile("" : "+v"(tlx), "+v"(basex));
-    stream_out_dispatch<S, 0, E, S::NST>(P, g, st, v);
-    rf::run_wave<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_c, basex, tlx, P.fx.tw);
-    // Y at k = tl + T (c + r EL); the real-signal unpacking needs Y_k and Y_{(N-k) mod N}
-    rf::line_sync<T>();
+    pair_out<S, 0, E, S::NST>(P, q, st, v);
+    rf::run_split<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, basex, tlx, twl);
+    // W at point q' = c + r EL (k = tl + T q')
+    const int ga = S::ga(q), gb = S::gb(q);
+    double2* YA = obuf + ((size_t(ga) * pb + jj) * M3 + bb) * NL;
+    if (gb < 0) {
 #pragma unroll
-    for (int c = 0; c < EL; ++c)
+      for (int c = 0; c < EL; ++c)
 #pragma unroll
-      for (int r = 0; r < RL; ++r) lds_c[basex + rf::padded<LP::PAD>(tlx + T * (c + r * EL))] = v[c * RL + r];
-    rf::line_sync<T>();
-    double2* Y0 = obuf + ((size_t(g) * pb + jj) * M3 + (bok ? b : 0)) * nl;
+        for (int r = 0; r < RL; ++r)
+          if (c + r * EL < QL && bok) YA[tlx + T * (c + r * EL)] = cscale(v[c * RL + r], scale);
+    } else {
+      double2* YB = obuf + ((size_t(gb) * pb + jj) * M3 + bb) * NL;
+      // partners W_{N-k} of the retained k sit at point 0 and the points above N - N/3
+      double pre[QL], pim[QL];
+      rf::line_sync<T>();
 #pragma unroll
-    for (int c = 0; c < EL; ++c)
+      for (int c = 0; c < EL; ++c)
 #pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int q = c + r * EL;
-        const int k = tlx + T * q;
-        const double2 Yp = lds_c[basex + rf::padded<LP::PAD>((N - k) % N)];
-        if (bok && k < nl) {
-          const double2 Yk = v[c * RL + r];
-          const double2 Yc = cconj(Yp);
-          const double2 Ev = cscale(cadd(Yk, Yc), 0.5);
-          const double2 D = csub(Yk, Yc);
-          const double2 O = make_double2(0.5 * D.y, -0.5 * D.x);
-          Y0[k] = cscale(cadd(Ev, cmul(P.xtw[k], O)), scale);
+        for (int r = 0; r < RL; ++r) {
+          const int qq = c + r * EL;
+          if (qq == 0 || T * qq + T - 1 > N - NL) lds_d[basex + rf::padded<LP::PAD>(tlx + T * qq)] = v[c * RL + r].x;
         }
-      }
+      rf::line_sync<T>();
+#pragma unroll
+      for (int qq = 0; qq < QL; ++qq) pre[qq] = lds_d[basex + rf::padded<LP::PAD>((N - tlx - T * qq) % N)];
+      rf::line_sync<T>();
+#pragma unroll
+      for (int c = 0; c < EL; ++c)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const int qq = c + r * EL;
+          if (qq == 0 || T * qq + T - 1 > N - NL) lds_d[basex + rf::padded<LP::PAD>(tlx + T * qq)] = v[c * RL + r].y;
+        }
+      rf::line_sync<T>();
+#pragma unroll
+      for (int qq = 0; qq < QL; ++qq) pim[qq] = lds_d[basex + rf::padded<LP::PAD>((N - tlx - T * qq) % N)];
+#pragma unroll
+      for (int c = 0; c < EL; ++c)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const int qq = c + r * EL;
+          if (qq < QL && bok) {
+            const double2 w = v[c * RL + r];
+            const double hs = 0.5 * scale;
+            YA[tlx + T * qq] = make_double2(hs * (w.x + pre[qq]), hs * (w.y - pim[qq]));
+            YB[tlx + T * qq] = make_double2(hs * (w.y + pim[qq]), -hs * (w.x - pre[qq]));
+          }
+        }
+    }
   }
 }
 
@@ -1792,17 +1813,18 @@ static void launch_zfwd_t(lmvd_plan_s* p, hipStream_t s, const double2* obuf, co
 template <int PH, int N>
 static void launch_xpass_t(lmvd_plan_s* p, hipStream_t s, const double2* zbuf, double2* obuf, double* phys_out,
                            const double* phys_in, int j0, int nb) {
-  using XS = XShape<N>;
-  const dim3 g((p->H.cfg.m3 + XS::BG - 1) / XS::BG, nb);
-  const size_t lds = size_t(XS::BG) * XS::STRIDE * sizeof(double2);
-  hipLaunchKernelGGL((k_xpass_r<PH, N>), g, dim3(XS::BG * XS::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out,
-                     phys_in, j0);
+  using LP = XPlan<N>;
+  const dim3 g((p->H.cfg.m3 + LP::BG - 1) / LP::BG, nb);
+  const size_t lds = size_t(LP::BG) * LP::STRIDE * sizeof(double) + size_t(N / 2) * sizeof(double2);
+  hipLaunchKernelGGL((k_xpair<PH, N>), g, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out, phys_in,
+                     j0);
 }
 static bool zreg_size(int n) {
   return n == 768 || n == 192 || n == 144 || n == 96 || n == 72 || n == 48;
 }
-static bool xreg_size(int n) {
-  return n == 384 || n == 96 || n == 72 || n == 48 || n == 36 || n == 24;
+// full-length x plans; the retained x-modes must be exactly m1/3
+static bool xreg_size(int m1, int nl) {
+  return (m1 == 768 || m1 == 192 || m1 == 144 || m1 == 96 || m1 == 72 || m1 == 48) && 3 * nl == m1;
 }
 #define LMVD_ZSWITCH(n, CALL) \
   switch (n) {                \
@@ -1816,12 +1838,12 @@ static bool xreg_size(int n) {
   }
 #define LMVD_XSWITCH(n, CALL) \
   switch (n) {                \
-    case 384: CALL(384); break; \
+    case 768: CALL(768); break; \
+    case 192: CALL(192); break; \
+    case 144: CALL(144); break; \
     case 96: CALL(96); break;   \
     case 72: CALL(72); break;   \
     case 48: CALL(48); break;   \
-    case 36: CALL(36); break;   \
-    case 24: CALL(24); break;   \
     default: break;             \
   }
 
@@ -1847,7 +1869,7 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
     bool inputs_plain = true;  // the register z kernel takes values with multiplier 1 or i k1 only
     for (const EvalIn& e : ins)
       if (e.kind != EV_IDENT || (e.ma != MU_ONE && e.ma != MU_IK1) || (e.b && e.mb != MU_ONE)) inputs_plain = false;
-    const bool zr = p->use_reg && zreg_size(M3) && inputs_plain, xr = p->use_reg && xreg_size(H.hx);
+    const bool zr = p->use_reg && zreg_size(M3) && inputs_plain, xr = p->use_reg && xreg_size(H.cfg.m1, nl);
     if (!ins.empty()) {
       double terms = 0;
       for (const EvalIn& e : ins) terms += e.b ? 2 : 1;
@@ -1865,7 +1887,7 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
       ProfScope ps(p, KC_XPASS, c.s, nb * (nin + nout) * zplane);
       if (xr) {
 #define CALLX(N) launch_xpass_t<PH, N>(p, c.s, zbuf, obuf, phys_out, phys_in, j0, nb)
-        LMVD_XSWITCH(H.hx, CALLX)
+        LMVD_XSWITCH(H.cfg.m1, CALLX)
 #undef CALLX
       } else {
         dim3 g2((M3 + bg - 1) / bg, nb);
@@ -1975,8 +1997,8 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   }
   // 2. R_z
   st = plane_phase<PH_RZ>(c,
-                          {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT),
-                           ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT), ev(vz0, EV_IDENT)},
+                          {ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT),
+                           ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT), ev(vzl, EV_IDENT), ev(vz0, EV_IDENT)},
                           {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
