@@ -245,19 +245,48 @@ __device__ __forceinline__ void run(double2* v, double* lds, int base, int tl, c
 //
 // Variant for kernels whose LDS budget is tight: the exchange moves real and
 // imaginary planes of doubles one after the other, and the stage twiddles come
-// from a table twl[t] = exp(-2 pi i t / N), t < N/2, held in LDS.  Only the
-// first power w of a butterfly is read; w^r follows by repeated products
-// (rounding grows like r ulp, far below the transform's own error).
+// from LDS tables, one per stage s >= 1, of NS_s entries
+// tws[m] = exp(-2 pi i m / (NS_s R_s)), so that the lanes of a wave read
+// consecutive entries.  Only the first power w of a butterfly is read; w^r
+// follows by repeated products (rounding grows like r ulp, far below the
+// transform's own error).
+
+template <int R0, int R1, int R2, int R3>
+struct StageTw {
+  static constexpr int NS1 = R0, NS2 = R0 * R1, NS3 = R0 * R1 * R2;
+  static constexpr int OFF1 = 0, OFF2 = (R1 > 1 ? NS1 : 0), OFF3 = OFF2 + (R2 > 1 ? NS2 : 0);
+  static constexpr int SIZE = OFF3 + (R3 > 1 ? NS3 : 0);
+};
+
+// fill the stage tables from tw[t] = exp(-2 pi i t / N), t < N/2
+template <int N, int R0, int R1, int R2, int R3>
+__device__ __forceinline__ void fill_stage_tw(double2* twl, const double2* __restrict__ tw, int tid, int nthreads) {
+  using ST = StageTw<R0, R1, R2, R3>;
+  for (int t = tid; t < ST::SIZE; t += nthreads) {
+    int m, step;
+    if (t < ST::OFF2 || (R2 == 1 && R3 == 1)) {
+      m = t - ST::OFF1;
+      step = N / (ST::NS1 * R1);
+    } else if (t < ST::OFF3 || R3 == 1) {
+      m = t - ST::OFF2;
+      step = N / (ST::NS2 * R2);
+    } else {
+      m = t - ST::OFF3;
+      step = N / (ST::NS3 * (R3 > 1 ? R3 : 1));
+    }
+    twl[t] = tw[m * step];
+  }
+}
 
 template <int N, int T, int DIR, int R, int NS>
-__device__ __forceinline__ void stage_lt(double2* v, int tl, const double2* twl) {
+__device__ __forceinline__ void stage_lt(double2* v, int tl, const double2* tws) {
   constexpr int E = N / T;
   constexpr int NB = E / R;
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if constexpr (NS > 1) {
       const int jm = (tl + T * c) % NS;
-      double2 w1 = twl[jm * (N / (NS * R))];
+      double2 w1 = tws[jm];
       if (DIR > 0) w1.y = -w1.y;
       double2 w = w1;
       v[c * R + 1] = cmul(v[c * R + 1], w1);
@@ -305,19 +334,19 @@ __device__ __forceinline__ void run_split(double2* v, double* lds, int base, int
   static_assert(R0 * R1 * R2 * R3 == N, "radices must multiply to N");
   static_assert((N / T) % R0 == 0 && (N / T) % R1 == 0 && (N / T) % R2 == 0 && (N / T) % R3 == 0,
                 "every radix must divide N/T");
-  constexpr int NS1 = R0, NS2 = R0 * R1, NS3 = R0 * R1 * R2;
+  using ST = StageTw<R0, R1, R2, R3>;
   stage_lt<N, T, DIR, R0, 1>(v, tl, twl);
   if constexpr (R1 > 1) {
     exchange_split<N, T, R0, 1, R1, PADDIV>(v, lds, base, tl);
-    stage_lt<N, T, DIR, R1, NS1>(v, tl, twl);
+    stage_lt<N, T, DIR, R1, ST::NS1>(v, tl, twl + ST::OFF1);
   }
   if constexpr (R2 > 1) {
-    exchange_split<N, T, R1, NS1, R2, PADDIV>(v, lds, base, tl);
-    stage_lt<N, T, DIR, R2, NS2>(v, tl, twl);
+    exchange_split<N, T, R1, ST::NS1, R2, PADDIV>(v, lds, base, tl);
+    stage_lt<N, T, DIR, R2, ST::NS2>(v, tl, twl + ST::OFF2);
   }
   if constexpr (R3 > 1) {
-    exchange_split<N, T, R2, NS2, R3, PADDIV>(v, lds, base, tl);
-    stage_lt<N, T, DIR, R3, NS3>(v, tl, twl);
+    exchange_split<N, T, R2, ST::NS2, R3, PADDIV>(v, lds, base, tl);
+    stage_lt<N, T, DIR, R3, ST::NS3>(v, tl, twl + ST::OFF3);
   }
 }
 

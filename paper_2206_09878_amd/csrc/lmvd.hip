@@ -29,8 +29,9 @@
 
 namespace lmvd {
 
-constexpr int kMaxIn = 13;
+constexpr int kMaxIn = 8;
 constexpr int kMaxOut = 10;
+constexpr int kNumAux = 4;   // physical-grid fields fixed during a substep
 constexpr int kThreads = 256;
 constexpr int kZMaxE = 12;    // elements per thread in the z-FFT kernels
 constexpr int kXSlots = 3;    // complex slots per thread per line set in k_xpass
@@ -175,34 +176,40 @@ __global__ void __launch_bounds__(kThreads) k_eval_zinv(DevPlan P, EvalArgs A, d
 template <int PH>
 struct Op;
 
+// Fields fixed during a substep live on the physical grid (aux, field stride
+// fs): g_i = -(1/rho) d_i z (i = 1..3) and f'(z) = rho^2 (rh - rl)/(rl rh),
+// written by the R_z phase and read by every L and rho_t phase.
 template <>
-struct Op<PH_RZ> {  // R_z = (1/rho)(-m^d . grad z + rho D lap z); inputs z1, m1, z2, m2, z3, m3, lap z, z
+struct Op<PH_RZ> {  // R_z = (1/rho)(-m^d . grad z + rho D lap z); inputs lap z, z, z1, m1, z2, m2, z3, m3
   static constexpr int NIN = 8, NOUT = 1;
-  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
-    const double ir = (P.rho_h - P.drho * x[7]) * P.inv_rlrh;
-    y[0] = (P.rhoD * x[6] - (x[0] * x[1] + x[2] * x[3] + x[4] * x[5])) * ir;
+  __device__ static void apply(const DevPlan& P, const double* x, double* y, double* a, size_t fs) {
+    const double ir = (P.rho_h - P.drho * x[1]) * P.inv_rlrh;
+    const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x[1]);
+    a[0] = -ir * x[2];
+    a[fs] = -ir * x[4];
+    a[2 * fs] = -ir * x[6];
+    a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
+    y[0] = (P.rhoD * x[0] - (x[2] * x[3] + x[4] * x[5] + x[6] * x[7])) * ir;
   }
 };
 template <>
-struct Op<PH_RHOT> {  // rho_t = f'(z) z_t = rho^2 (rh - rl)/(rl rh) z_t
-  static constexpr int NIN = 2, NOUT = 1;
-  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
-    const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x[0]);
-    y[0] = rho * rho * P.drho * P.inv_rlrh * x[1];
+struct Op<PH_RHOT> {  // rho_t = f'(z) z_t; input z_t
+  static constexpr int NIN = 1, NOUT = 1;
+  __device__ static void apply(const DevPlan&, const double* x, double* y, double* a, size_t fs) {
+    y[0] = a[3 * fs] * x[0];
   }
 };
 template <>
-struct Op<PH_L> {  // L z_t = -(1/rho) grad z . m^c; inputs z1, m1c, z2, m2c, z3, m3c, z
-  static constexpr int NIN = 7, NOUT = 1;
-  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
-    const double ir = (P.rho_h - P.drho * x[6]) * P.inv_rlrh;
-    y[0] = -(x[0] * x[1] + x[2] * x[3] + x[4] * x[5]) * ir;
+struct Op<PH_L> {  // L z_t = -(1/rho) grad z . m^c = g . m^c; inputs m1c, m2c, m3c
+  static constexpr int NIN = 3, NOUT = 1;
+  __device__ static void apply(const DevPlan&, const double* x, double* y, double* a, size_t fs) {
+    y[0] = a[0] * x[0] + a[fs] * x[1] + a[2 * fs] * x[2];
   }
 };
 template <>
 struct Op<PH_VEL> {  // u = m / rho, rho, and C_ij = -m_i m_j / rho (i <= j)
   static constexpr int NIN = 4, NOUT = 10;
-  __device__ static void apply(const DevPlan& P, const double* x, double* y) {
+  __device__ static void apply(const DevPlan& P, const double* x, double* y, double*, size_t) {
     const double den = P.rho_h - P.drho * x[0];
     const double ir = den * P.inv_rlrh;
     const double u1 = x[1] * ir, u2 = x[2] * ir, u3 = x[3] * ir;
@@ -221,12 +228,12 @@ struct Op<PH_VEL> {  // u = m / rho, rho, and C_ij = -m_i m_j / rho (i <= j)
 template <>
 struct Op<PH_TOPHYS> {
   static constexpr int NIN = 1, NOUT = 0;
-  __device__ static void apply(const DevPlan&, const double*, double*) {}
+  __device__ static void apply(const DevPlan&, const double*, double*, double*, size_t) {}
 };
 template <>
 struct Op<PH_FROMPHYS> {
   static constexpr int NIN = 0, NOUT = 1;
-  __device__ static void apply(const DevPlan&, const double*, double*) {}
+  __device__ static void apply(const DevPlan&, const double*, double*, double*, size_t) {}
 };
 
 // ---------------------------------------------------------------------------
@@ -237,7 +244,8 @@ struct Op<PH_FROMPHYS> {
 template <int PH>
 __global__ void __launch_bounds__(kThreads) k_xpass(DevPlan P, const double2* __restrict__ zbuf,
                                                     double2* __restrict__ obuf, int pb, int BG,
-                                                    double* phys_out, const double* phys_in, int j0) {
+                                                    double* phys_out, const double* phys_in, int j0,
+                                                    double* __restrict__ aux) {
   using O = Op<PH>;
   constexpr int NIN = O::NIN, NOUT = O::NOUT;
   constexpr int NINA = NIN > 0 ? NIN : 1, NOUTA = NOUT > 0 ? NOUT : 1;
@@ -302,8 +310,18 @@ __global__ void __launch_bounds__(kThreads) k_xpass(DevPlan P, const double2* __
         xi[f] = ph[f][s].x;
         xj[f] = ph[f][s].y;
       }
-      O::apply(P, xi, yo);
-      O::apply(P, xj, yp);
+      const int idx = tid + s * nth;
+      const int line = idx / H, m = idx - line * H;
+      const size_t fs = size_t(P.n2) * M3 * M1;
+      double* ap = aux ? aux + (size_t(j0 + jj) * M3 + b0 + (idx < nel ? line : 0)) * M1 + 2 * (idx < nel ? m : 0)
+                       : nullptr;
+      if (idx < nel) {
+        O::apply(P, xi, yo, ap, fs);
+        O::apply(P, xj, yp, ap ? ap + 1 : nullptr, fs);
+      } else {
+#pragma unroll
+        for (int g = 0; g < NOUTA; ++g) yo[g] = yp[g] = 0.0;
+      }
 #pragma unroll
       for (int g = 0; g < NOUT; ++g) res[g][s] = make_double2(yo[g], yp[g]);
     }
@@ -565,7 +583,7 @@ struct XPlan;
     static constexpr int BG = kThreads / T_;                     /* lines per block */               \
     static constexpr int STRIDE = ((N_ + N_ / PAD_) + 1) / 2 * 2; /* doubles per line, even */        \
   };
-LMVD_XPLAN(768, 64, 12, 4, 4, 4, 12)
+LMVD_XPLAN(768, 64, 12, 4, 4, 4, 96)
 LMVD_XPLAN(192, 16, 12, 4, 4, 1, 12)
 LMVD_XPLAN(144, 12, 12, 12, 1, 1, 12)
 LMVD_XPLAN(96, 8, 12, 4, 2, 1, 12)
@@ -664,48 +682,55 @@ template <int PH>
 struct Pair;
 
 template <>
-struct Pair<PH_RZ> {  // inputs z1, m1, z2, m2, z3, m3, lap z, z:  R_z = (1/rho)(-m^d . grad z + rho D lap z)
-  static constexpr int NP = 4, NQ = 1, NST = 1;
+struct Pair<PH_RZ> {  // inputs lap z, z, z1, m1, z2, m2, z3, m3:  R_z = (1/rho)(-m^d . grad z + rho D lap z)
+  static constexpr int NP = 4, NQ = 1, NST = 2;
   __device__ static constexpr int fa(int i) { return 2 * i; }
   __device__ static constexpr int fb(int i) { return 2 * i + 1; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
-  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y) {
-    if constexpr (I == 0) s[0] = -(x * y);
-    else if constexpr (I < 3) s[0] -= x * y;
-    else s[0] = (s[0] + P.rhoD * x) * ((P.rho_h - P.drho * y) * P.inv_rlrh);
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y, double* a, size_t fs) {
+    // a == nullptr on lines past the grid edge: nothing is written there
+    if constexpr (I == 0) {
+      const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * y);
+      s[0] = (P.rho_h - P.drho * y) * P.inv_rlrh;  // 1/rho
+      s[1] = P.rhoD * x;
+      if (a) a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
+    } else {
+      s[1] -= x * y;
+      if (a) a[(I - 1) * fs] = -s[0] * x;
+    }
   }
   template <int Q>
-  __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
+  __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) {
+    return make_double2(s[1] * s[0], 0.0);
+  }
 };
 template <>
-struct Pair<PH_L> {  // inputs z1, m1c, z2, m2c, z3, m3c, z:  L z_t = -(1/rho) grad z . m^c
-  static constexpr int NP = 4, NQ = 1, NST = 1;
+struct Pair<PH_L> {  // inputs m1c, m2c, m3c:  L z_t = -(1/rho) grad z . m^c = g . m^c
+  static constexpr int NP = 2, NQ = 1, NST = 1;
   __device__ static constexpr int fa(int i) { return 2 * i; }
-  __device__ static constexpr int fb(int i) { return i < 3 ? 2 * i + 1 : -1; }
+  __device__ static constexpr int fb(int i) { return i == 0 ? 1 : -1; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
-  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y) {
-    if constexpr (I == 0) s[0] = -(x * y);
-    else if constexpr (I < 3) s[0] -= x * y;
-    else s[0] *= (P.rho_h - P.drho * x) * P.inv_rlrh;
+  __device__ __forceinline__ static void in(const DevPlan&, double* s, double x, double y, double* a, size_t fs) {
+    if constexpr (I == 0) s[0] = a[0] * x + a[fs] * y;
+    else s[0] += a[2 * fs] * x;
   }
   template <int Q>
   __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
 };
 template <>
-struct Pair<PH_RHOT> {  // inputs z, z_t:  rho_t = f'(z) z_t = rho^2 (rh - rl)/(rl rh) z_t
+struct Pair<PH_RHOT> {  // input z_t:  rho_t = f'(z) z_t
   static constexpr int NP = 1, NQ = 1, NST = 1;
   __device__ static constexpr int fa(int) { return 0; }
-  __device__ static constexpr int fb(int) { return 1; }
+  __device__ static constexpr int fb(int) { return -1; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
-  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y) {
-    const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x);
-    s[0] = rho * rho * P.drho * P.inv_rlrh * y;
+  __device__ __forceinline__ static void in(const DevPlan&, double* s, double x, double, double* a, size_t fs) {
+    s[0] = a[3 * fs] * x;
   }
   template <int Q>
   __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
@@ -718,7 +743,7 @@ struct Pair<PH_VEL> {  // inputs z, m1, m2, m3 -> u1, u2, u3, rho, C11, C12, C13
   __device__ static constexpr int ga(int q) { return 2 * q; }
   __device__ static constexpr int gb(int q) { return 2 * q + 1; }
   template <int I>
-  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y) {
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y, double*, size_t) {
     if constexpr (I == 0) {
       s[0] = P.rho_h - P.drho * x;  // rl rh / rho
       s[1] = y;
@@ -745,7 +770,7 @@ struct Pair<PH_TOPHYS> {  // one input, written out on the physical grid
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
-  __device__ __forceinline__ static void in(const DevPlan&, double*, double, double) {}
+  __device__ __forceinline__ static void in(const DevPlan&, double*, double, double, double*, size_t) {}
   template <int Q>
   __device__ __forceinline__ static double2 out(const DevPlan&, const double*) { return zero2(); }
 };
@@ -757,7 +782,7 @@ struct Pair<PH_FROMPHYS> {  // one output, read from the physical grid
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
-  __device__ __forceinline__ static void in(const DevPlan&, double*, double, double) {}
+  __device__ __forceinline__ static void in(const DevPlan&, double*, double, double, double*, size_t) {}
   template <int Q>
   __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
 };
@@ -765,8 +790,9 @@ struct Pair<PH_FROMPHYS> {  // one output, read from the physical grid
 // state update of input FFT I (runtime index i) on every point of the thread;
 // point q of the line (position tl + T q) sits in register slot
 // v[c*RL + r] with q = c + r*EL after an inverse transform
-template <class S, int I, int E, int RL, int NST>
-__device__ __forceinline__ void pair_in(const DevPlan& P, int i, double (&st)[NST][E], const double2* v) {
+template <class S, int I, int E, int RL, int NST, int T>
+__device__ __forceinline__ void pair_in(const DevPlan& P, int i, double (&st)[NST][E], const double2* v, double* ap,
+                                        size_t fs) {
   if constexpr (I < S::NP) {
     if (i == I) {
       constexpr int EL = E / RL;
@@ -778,12 +804,12 @@ __device__ __forceinline__ void pair_in(const DevPlan& P, int i, double (&st)[NS
           double s[NST];
 #pragma unroll
           for (int k = 0; k < NST; ++k) s[k] = st[k][q];
-          S::template in<I>(P, s, v[c * RL + r].x, v[c * RL + r].y);
+          S::template in<I>(P, s, v[c * RL + r].x, v[c * RL + r].y, ap + T * q, fs);
 #pragma unroll
           for (int k = 0; k < NST; ++k) st[k][q] = s[k];
         }
     } else {
-      pair_in<S, I + 1, E, RL, NST>(P, i, st, v);
+      pair_in<S, I + 1, E, RL, NST, T>(P, i, st, v, ap, fs);
     }
   }
 }
@@ -814,7 +840,7 @@ __device__ __forceinline__ void pair_out(const DevPlan& P, int q, const double (
 template <int PH, int N>
 __global__ void __launch_bounds__(kThreads) k_xpair(DevPlan P, const double2* __restrict__ zbuf,
                                                    double2* __restrict__ obuf, int pb, double* phys_out,
-                                                   const double* phys_in, int j0) {
+                                                   const double* phys_in, int j0, double* __restrict__ aux) {
   using LP = XPlan<N>;
   using S = Pair<PH>;
   constexpr int T = LP::T, E = LP::E, RL = LP::RL, EL = E / RL, BG = LP::BG, NL = N / 3;
@@ -828,7 +854,7 @@ __global__ void __launch_bounds__(kThreads) k_xpair(DevPlan P, const double2* __
   const int M3 = P.m3;
   const bool bok = b < M3;
   const int bb = bok ? b : 0;
-  for (int t = tid; t < N / 2; t += BG * T) twl[t] = P.xtw[t];
+  rf::fill_stage_tw<N, LP::R0, LP::R1, LP::R2, LP::R3>(twl, P.xtw, tid, BG * T);
   __syncthreads();
   const int base = line * LP::STRIDE;
   double st[S::NST][E];
@@ -877,7 +903,9 @@ __global__ void __launch_bounds__(kThreads) k_xpair(DevPlan P, const double2* __
           if (bok) phys_out[(size_t(j0 + jj) * M3 + b) * P.m1 + tl + T * q] = v[c * RL + r].x;
         }
     } else {
-      pair_in<S, 0, E, RL, S::NST>(P, i, st, v);
+      // aux point q of this thread: ap[T q], fields fs apart
+      double* ap = (aux && (bok || PH != PH_RZ)) ? aux + (size_t(j0 + jj) * M3 + bb) * P.m1 + tl : nullptr;
+      pair_in<S, 0, E, RL, S::NST, T>(P, i, st, v, ap, size_t(P.n2) * M3 * P.m1);
     }
   }
   if constexpr (PH == PH_FROMPHYS) {
@@ -1532,7 +1560,7 @@ __global__ void k_evaluate(DevPlan P, int kind, const double2* __restrict__ src,
 struct Workspace {
   size_t bytes = 0;
   size_t off_md1, off_md3, off_c2d, off_mpar, off_c2c, off_rz, off_zta, off_ztb, off_rhot, off_vals[kMaxOut];
-  size_t off_u[3], off_T[6], off_rhov, off_yphi, off_yom, off_uscr, off_zbuf, off_obuf, off_mean;
+  size_t off_u[3], off_T[6], off_rhov, off_yphi, off_yom, off_uscr, off_zbuf, off_obuf, off_mean, off_aux;
   // values at the Greville points
   size_t off_vz0, off_vz1, off_vzl, off_vz3, off_vmd1, off_vmd3, off_vc2d, off_vm1c, off_vm2c, off_vm3c, off_vzt;
 };
@@ -1592,6 +1620,7 @@ static void layout_workspace(lmvd_plan_s* p) {
   w.off_zbuf = take(size_t(kMaxIn) * p->pb * plane);
   w.off_obuf = take(size_t(kMaxOut) * p->pb * plane);
   w.off_mean = take(size_t(2) * H.n2 * 8);
+  w.off_aux = take(size_t(kNumAux) * H.n2 * H.cfg.m3 * H.cfg.m1 * 8);
   w.off_vz0 = take(sB);
   w.off_vz1 = take(sB);
   w.off_vzl = take(sB);
@@ -1812,12 +1841,13 @@ static void launch_zfwd_t(lmvd_plan_s* p, hipStream_t s, const double2* obuf, co
 }
 template <int PH, int N>
 static void launch_xpass_t(lmvd_plan_s* p, hipStream_t s, const double2* zbuf, double2* obuf, double* phys_out,
-                           const double* phys_in, int j0, int nb) {
+                           const double* phys_in, int j0, int nb, double* aux) {
   using LP = XPlan<N>;
   const dim3 g((p->H.cfg.m3 + LP::BG - 1) / LP::BG, nb);
-  const size_t lds = size_t(LP::BG) * LP::STRIDE * sizeof(double) + size_t(N / 2) * sizeof(double2);
+  const size_t lds = size_t(LP::BG) * LP::STRIDE * sizeof(double) +
+                     size_t(rf::StageTw<LP::R0, LP::R1, LP::R2, LP::R3>::SIZE) * sizeof(double2);
   hipLaunchKernelGGL((k_xpair<PH, N>), g, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out, phys_in,
-                     j0);
+                     j0, aux);
 }
 static bool zreg_size(int n) {
   return n == 768 || n == 192 || n == 144 || n == 96 || n == 72 || n == 48;
@@ -1859,6 +1889,9 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
   for (size_t g = 0; g < outs.size(); ++g) V.v[g] = outs[g];
   double2* zbuf = c.at<double2>(p->ws.off_zbuf);
   double2* obuf = c.at<double2>(p->ws.off_obuf);
+  double* aux = c.at<double>(p->ws.off_aux);
+  // physical aux fields each phase writes (R_z) or reads (L, rho_t)
+  const double naux = (PH == PH_RZ) ? 4.0 : (PH == PH_L) ? 3.0 : (PH == PH_RHOT) ? 1.0 : 0.0;
   const int lg = p->lgz, bg = p->bgx;
   const size_t lds_z = size_t(lg) * M3 * sizeof(double2);
   const size_t lds_x = size_t(bg) * H.hx * sizeof(double2);
@@ -1884,15 +1917,15 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
       }
     }
     {
-      ProfScope ps(p, KC_XPASS, c.s, nb * (nin + nout) * zplane);
+      ProfScope ps(p, KC_XPASS, c.s, nb * ((nin + nout) * zplane + naux * double(M3) * H.cfg.m1 * 8.0));
       if (xr) {
-#define CALLX(N) launch_xpass_t<PH, N>(p, c.s, zbuf, obuf, phys_out, phys_in, j0, nb)
+#define CALLX(N) launch_xpass_t<PH, N>(p, c.s, zbuf, obuf, phys_out, phys_in, j0, nb, aux)
         LMVD_XSWITCH(H.cfg.m1, CALLX)
 #undef CALLX
       } else {
         dim3 g2((M3 + bg - 1) / bg, nb);
         hipLaunchKernelGGL(k_xpass<PH>, g2, dim3(kThreads), lds_x, c.s, p->D, zbuf, obuf, p->pb, bg, phys_out,
-                           phys_in, j0);
+                           phys_in, j0, aux);
       }
     }
     if (!outs.empty()) {
@@ -1997,8 +2030,8 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   }
   // 2. R_z
   st = plane_phase<PH_RZ>(c,
-                          {ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT),
-                           ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT), ev(vzl, EV_IDENT), ev(vz0, EV_IDENT)},
+                          {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT),
+                           ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
                           {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
@@ -2029,14 +2062,13 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   // 3. fixed-point iterations z_t^k = L(z) z_t^{k-1} + R_z
   for (int it = 0; it < kf; ++it) {
     const bool last = (it == kf - 1);
-    st = plane_phase<PH_RHOT>(c, {ev(vz0, EV_IDENT), ev(vzt, EV_IDENT)}, {vals[0]});
+    st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
     if (st != LMVD_OK) return st;
     proj(c, 0, vals[0], rhot);
     solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
     values_mc(false);
     st = plane_phase<PH_L>(c,
-                           {ev(vz0, EV_IDENT, MU_IK1), ev(vm1, EV_IDENT), ev(vz1, EV_IDENT), ev(vm2, EV_IDENT),
-                            ev(vz3, EV_IDENT), ev(vm3, EV_IDENT), ev(vz0, EV_IDENT)},
+                           {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
                            {vals[0]});
     if (st != LMVD_OK) return st;
     double2* next = (last && user_zt) ? user_zt : (cur == zta ? ztb : zta);
@@ -2053,7 +2085,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     cur = next;
   }
   // m^c of the stage from z_t^{k_f}
-  st = plane_phase<PH_RHOT>(c, {ev(vz0, EV_IDENT), ev(vzt, EV_IDENT)}, {vals[0]});
+  st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 0, vals[0], rhot);
   solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
