@@ -60,6 +60,12 @@ struct DevPlan {
   const double* k3;        // [nn]
   const int* emit_first;   // [n2] first E0 row whose band starts at row i
   const int* emit_cnt;     // [n2] number of such rows
+  const int* g1e_first;    // [n2] first interior tau* row whose G1 band starts at B row j
+  const int* g1e_cnt;      // [n2]
+  const int* asc_first;    // [n2+1] first tau row whose last F0/F1 column is B* row j
+  const int* asc_cnt;      // [n2+1]
+  const double* asc_w;     // [2][n2][kMaxW] F0, F1 weights of c_{last - q}
+  const double* fac;       // bottom-up factors of A(k) per (l, |n|) pair: [n2+1][slots][npairs]
   FftDev fz, fx;
   const double2* xtw;      // [hx] exp(-2 pi i k / m1)
 };
@@ -455,41 +461,6 @@ __global__ void __launch_bounds__(kThreads) k_values(DevPlan P, const double2* _
       wc.advance(cs, ncol, c, n2 + 1, P.ev_lo[3 * n2 + i]);
       Vc[e] = wc.dot(P.ev_w + (size_t(3 * n2) + i) * kMaxW);
     }
-  }
-}
-
-// m^c values at tau from (m_par in B, m2 in B*): m1 = (k1/k) E0 m_par,
-// m3 = (k3/k) E0 m_par, m2 = F0 c2; with md values given, the totals m^d + m^c
-__global__ void __launch_bounds__(kThreads) k_values_mc(DevPlan P, const double2* __restrict__ mpar,
-                                                        const double2* __restrict__ c2, const double2* __restrict__ d1,
-                                                        const double2* __restrict__ d2, const double2* __restrict__ d3,
-                                                        double2* __restrict__ V1, double2* __restrict__ V2,
-                                                        double2* __restrict__ V3) {
-  const size_t ncol = size_t(P.nn) * P.nl;
-  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= ncol) return;
-  const int n2 = P.n2;
-  const double k1 = P.k1[c % P.nl], k3 = P.k3[c / P.nl], ksq = k1 * k1 + k3 * k3;
-  const double ik = (ksq > 0.0) ? 1.0 / sqrt(ksq) : 0.0;
-  const double f1 = k1 * ik, f3 = k3 * ik;
-  RowWindow wa, wc;
-  wa.init(mpar, ncol, c, n2);
-  wc.init(c2, ncol, c, n2 + 1);
-  for (int i = 0; i < n2; ++i) {
-    const size_t e = size_t(i) * ncol + c;
-    wa.advance(mpar, ncol, c, n2, P.ev_lo[i]);
-    wc.advance(c2, ncol, c, n2 + 1, P.ev_lo[3 * n2 + i]);
-    const double2 a = wa.dot(P.ev_w + size_t(i) * kMaxW);
-    const double2 b = wc.dot(P.ev_w + (size_t(3 * n2) + i) * kMaxW);
-    double2 m1 = cscale(a, f1), m3 = cscale(a, f3), m2 = b;
-    if (d1) {
-      m1 = cadd(m1, d1[e]);
-      m2 = cadd(m2, d2[e]);
-      m3 = cadd(m3, d3[e]);
-    }
-    V1[e] = m1;
-    V2[e] = m2;
-    V3[e] = m3;
   }
 }
 
@@ -1356,6 +1327,265 @@ __global__ void __launch_bounds__(kThreads) k_solveA(DevPlan P, const double2* _
 }
 
 // ---------------------------------------------------------------------------
+// A(k) factors, computed once per plan: bottom-up elimination without
+// pivoting (rows n2 .. 0), one thread per pair (l, +-n) (A depends on k only).
+// Row i keeps UA multipliers (of rows i+1 .. i+UA), its LA entries left of
+// the diagonal and 1/pivot, stored at fac[((n2 - i) * S + slot) * npairs + t],
+// S = UA + LA + 1.  A(k) = E*_2 - k^2 E*_0 at interior tau*, Robin rows
+// k m2 - m2' (bottom), k m2 + m2' (top) (eqs. phi_poisson, bc_both).
+template <int LA, int UA>
+__global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __restrict__ fac) {
+  const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
+  const int npairs = nl * ((nn + 1) / 2);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= npairs) return;
+  const int l = t % nl, pp = t / nl;
+  const double k1 = P.k1[l], k3 = P.k3[pp];
+  const double ksq = k1 * k1 + k3 * k3;
+  constexpr int W = LA + UA + 1, S = UA + LA + 1;
+  if (ksq == 0.0) {
+    for (int i = 0; i < N; ++i)
+      for (int q = 0; q < S; ++q) fac[(size_t(i) * S + q) * npairs + t] = 0.0;
+    return;
+  }
+  const double k = sqrt(ksq);
+  const int Ns = n2 + 1;
+  const int* elo = P.es_lo;
+  const double* ew = P.es_w;
+  double piv[UA][LA];  // entries left of the diagonal of pivot rows i+1 .. i+UA
+  double pinv[UA];
+#pragma unroll
+  for (int m = 0; m < UA; ++m) {
+    pinv[m] = 0.0;
+#pragma unroll
+    for (int q = 0; q < LA; ++q) piv[m][q] = 0.0;
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    double a[W];  // a[w] = A[i][i - LA + w]
+    const int lo0 = elo[i], lo1 = elo[Ns + i], lo2 = elo[2 * Ns + i];
+    const bool robin = (i == 0 || i == n2);
+    const double sg = (i == 0) ? -1.0 : 1.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int col = i - LA + w;
+      const int q0 = col - lo0, q1 = col - lo1, q2 = col - lo2;
+      const double e0 = (q0 >= 0 && q0 < kMaxW) ? ew[size_t(i) * kMaxW + q0] : 0.0;
+      if (robin) {
+        const double e1 = (q1 >= 0 && q1 < kMaxW) ? ew[(size_t(Ns) + i) * kMaxW + q1] : 0.0;
+        a[w] = k * e0 + sg * e1;
+      } else {
+        const double e2 = (q2 >= 0 && q2 < kMaxW) ? ew[(size_t(2 * Ns) + i) * kMaxW + q2] : 0.0;
+        a[w] = e2 - ksq * e0;
+      }
+    }
+    double* f = fac + size_t(N - 1 - i) * S * npairs + t;
+    // eliminate columns i+UA .. i+1 with pivot rows i+UA .. i+1 (farthest first)
+#pragma unroll
+    for (int m = UA; m >= 1; --m) {
+      const double lm = a[LA + m] * pinv[m - 1];
+#pragma unroll
+      for (int q = 1; q <= LA; ++q) a[LA + m - q] -= lm * piv[m - 1][q - 1];
+      f[size_t(m - 1) * npairs] = lm;
+    }
+    const double dinv = 1.0 / a[LA];
+#pragma unroll
+    for (int q = 1; q <= LA; ++q) f[size_t(UA + q - 1) * npairs] = a[LA - q];
+    f[size_t(UA + LA) * npairs] = dinv;
+#pragma unroll
+    for (int m = UA - 1; m > 0; --m) {
+      pinv[m] = pinv[m - 1];
+#pragma unroll
+      for (int q = 0; q < LA; ++q) piv[m][q] = piv[m - 1][q];
+    }
+    pinv[0] = dinv;
+#pragma unroll
+    for (int q = 1; q <= LA; ++q) piv[0][q - 1] = a[LA - q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column kernel: m^c of one fixed-point iterate from the rho_t values at tau
+// (eqs. COM_fourier, CF_fourier, mc_mean), one thread per column; the two
+// columns (l, n), (l, -n) of a pair are neighbouring lanes and share the
+// factors of A(k).
+//   1. interpolation rho_t = P0 (values): ascending L sweep (scratch yp),
+//   2. descending U sweep; every interior tau* row i whose G1 band starts at
+//      the current row gets r_i = -G1 rho_t at once and enters the bottom-up
+//      forward sweep of A(k) c = r (scratch yt); Robin rows have r = 0,
+//   3. ascending back substitution for c (the B* coefficients of m2); every
+//      tau row whose F0/F1 band is complete emits the values
+//        m2 = F0 c,  m_par = (i/k)(rho_t + F1 c),  m1 = (k1/k) m_par,  m3 = (k3/k) m_par
+//      (F1 = E0 D*, so F1 c = E0 D* c and E0 rho_t is the input value itself).
+// Plane mean (k = 0): D* c = -<rho_t>, c_top = 0, m1 = m3 = 0.
+// With d1 (final iterate) the m^d values are added and the coefficients
+// c2 = c, mparc = (i/k)(rho_t + D* c) and rhoc = rho_t are written.
+template <int LA, int UA>
+__global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __restrict__ vals, double2* yp,
+                                                double2* yt, const double2* __restrict__ d1,
+                                                const double2* __restrict__ d2, const double2* __restrict__ d3,
+                                                double2* __restrict__ V1, double2* __restrict__ V2,
+                                                double2* __restrict__ V3, double2* rhoc, double2* __restrict__ c2,
+                                                double2* __restrict__ mparc) {
+  const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
+  const int half = (nn + 1) / 2, npairs = nl * half;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pr = t >> 1, side = t & 1;
+  if (pr >= npairs) return;
+  const int l = pr % nl, pp = pr / nl;
+  if (side == 1 && pp == 0) return;
+  const int ni = side ? nn - pp : pp;
+  const size_t ncol = size_t(nn) * nl, c = size_t(ni) * nl + l;
+  const double k1 = P.k1[l], k3 = P.k3[ni], ksq = k1 * k1 + k3 * k3;
+  const bool mean = (ksq == 0.0);
+  const double ik = mean ? 0.0 : 1.0 / sqrt(ksq);
+  constexpr int S = UA + LA + 1;
+  const double* fac = P.fac + pr;
+  // Every sweep loads the operands of its next row one step ahead: the loads
+  // do not depend on the recurrence, so their latency overlaps the current row.
+  // 1. ascending sweep of the interpolation projection
+  {
+    double2 ring[kMaxBand];
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+    double2 bn = vals[c];
+    for (int i = 0; i < n2; ++i) {
+      double2 b = bn;
+      if (i + 1 < n2) bn = vals[size_t(i + 1) * ncol + c];
+#pragma unroll
+      for (int m = 0; m < kMaxBand; ++m) b = fma2(-P.lu_l[i * kMaxBand + m], ring[m], b);
+      yp[size_t(i) * ncol + c] = b;
+#pragma unroll
+      for (int m = kMaxBand - 1; m > 0; --m) ring[m] = ring[m - 1];
+      ring[0] = b;
+    }
+  }
+  // 2. descending sweep: rho_t coefficients, r = -G1 rho_t, bottom-up forward sweep of A(k)
+  {
+    double2 win[kMaxW];  // rho_t coefficients of rows j .. j+kMaxW-1
+    double2 yr[UA];      // forward-sweep results of rows i+1 .. i+UA
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q) win[q] = zero2();
+#pragma unroll
+    for (int m = 0; m < UA; ++m) yr[m] = zero2();
+    double2 cm = zero2();  // mean column: c_{j+1}
+    yt[size_t(n2) * ncol + c] = zero2();  // Robin row n2: r = 0, nothing above it
+    const double* G1w = P.gs_w + size_t(N) * kMaxW;
+    // multipliers of the next row of the bottom-up sweep (rows n2-1, n2-2, ..., 0 in turn)
+    int inext = n2 - 1;
+    double fm[UA];
+#pragma unroll
+    for (int m = 0; m < UA; ++m) fm[m] = mean ? 0.0 : fac[(size_t(n2 - inext) * S + m) * npairs];
+    double2 ypn = yp[size_t(n2 - 1) * ncol + c];
+    for (int j = n2 - 1; j >= 0; --j) {
+      double2 y = ypn;
+      if (j > 0) ypn = yp[size_t(j - 1) * ncol + c];
+#pragma unroll
+      for (int q = 0; q < kMaxBand; ++q) y = fma2(-P.lu_u[j * (kMaxBand + 1) + q + 1], win[q], y);
+      const double2 x = cscale(y, P.lu_uinv[j]);
+#pragma unroll
+      for (int q = kMaxW - 1; q > 0; --q) win[q] = win[q - 1];
+      win[0] = x;
+      if (rhoc) rhoc[size_t(j) * ncol + c] = x;
+      if (mean) {
+        cm = make_double2(cm.x + x.x / P.dstar[j], cm.y + x.y / P.dstar[j]);
+        yt[size_t(j) * ncol + c] = cm;
+        continue;
+      }
+      const int first = P.g1e_first[j], cnt = P.g1e_cnt[j];
+      for (int e = cnt - 1; e >= 0; --e) {
+        const int i = first + e;  // == inext
+        const double* g = G1w + size_t(i) * kMaxW;
+        double2 r = zero2();
+#pragma unroll
+        for (int q = 0; q < kMaxW; ++q) r = fma2(-g[q], win[q], r);
+#pragma unroll
+        for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
+        --inext;
+#pragma unroll
+        for (int m = 0; m < UA; ++m) fm[m] = fac[(size_t(n2 - inext) * S + m) * npairs];
+        yt[size_t(i) * ncol + c] = r;
+#pragma unroll
+        for (int m = UA - 1; m > 0; --m) yr[m] = yr[m - 1];
+        yr[0] = r;
+      }
+    }
+    if (!mean) {  // Robin row 0 (inext == 0): r = 0
+      double2 r = zero2();
+#pragma unroll
+      for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
+      yt[c] = r;
+    }
+  }
+  // 3. ascending back substitution and emission of the values at tau
+  {
+    double2 cw[kMaxW];  // c_i, c_{i-1}, ...
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q) cw[q] = zero2();
+    double fs[LA + 1];
+    double2 ytn = yt[c];
+#pragma unroll
+    for (int q = 0; q <= LA; ++q) fs[q] = mean ? 0.0 : fac[(size_t(n2) * S + UA + q) * npairs];
+    for (int i = 0; i < N; ++i) {
+      double2 x = ytn;
+      double fc[LA + 1];
+#pragma unroll
+      for (int q = 0; q <= LA; ++q) fc[q] = fs[q];
+      if (i + 1 < N) {
+        ytn = yt[size_t(i + 1) * ncol + c];
+        if (!mean) {
+#pragma unroll
+          for (int q = 0; q <= LA; ++q) fs[q] = fac[(size_t(n2 - i - 1) * S + UA + q) * npairs];
+        }
+      }
+      if (!mean) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) x = fma2(-fc[q], cw[q], x);
+        x = cscale(x, fc[LA]);
+      }
+#pragma unroll
+      for (int q = kMaxW - 1; q > 0; --q) cw[q] = cw[q - 1];
+      cw[0] = x;
+      if (c2) {
+        c2[size_t(i) * ncol + c] = x;
+        if (i > 0) {
+          const size_t e = size_t(i - 1) * ncol + c;
+          const double ds = P.dstar[i - 1];
+          const double2 dc = make_double2(ds * (cw[0].x - cw[1].x), ds * (cw[0].y - cw[1].y));
+          mparc[e] = mean ? zero2() : cscale(times_i(cadd(rhoc[e], dc)), ik);
+        }
+      }
+      const int first = P.asc_first[i], cnt = P.asc_cnt[i];
+      for (int e = 0; e < cnt; ++e) {
+        const int row = first + e;
+        const double* w0 = P.asc_w + size_t(row) * kMaxW;
+        const double* w1 = P.asc_w + (size_t(n2) + row) * kMaxW;
+        double2 m2 = zero2(), f1 = zero2();
+#pragma unroll
+        for (int q = 0; q < kMaxW; ++q) {
+          m2 = fma2(w0[q], cw[q], m2);
+          f1 = fma2(w1[q], cw[q], f1);
+        }
+        const size_t o = size_t(row) * ncol + c;
+        double2 m1 = zero2(), m3 = zero2();
+        if (!mean) {
+          const double2 mp = cscale(times_i(cadd(vals[o], f1)), ik);
+          m1 = cscale(mp, k1 * ik);
+          m3 = cscale(mp, k3 * ik);
+        }
+        if (d1) {
+          m1 = cadd(m1, d1[o]);
+          m2 = cadd(m2, d2[o]);
+          m3 = cadd(m3, d3[o]);
+        }
+        V1[o] = m1;
+        V2[o] = m2;
+        V3[o] = m3;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column kernel: RHS of Omega2 and phi2 from the projected T_ij, Dirichlet-row
 // projection, RK2 update (eqs. om, phi with the body force; R17 form
 // RHS_phi2 = -k^2 N2 - d/dy(i k1 N1 + i k3 N3) + k^2 g rho).
@@ -1561,6 +1791,7 @@ struct Workspace {
   size_t bytes = 0;
   size_t off_md1, off_md3, off_c2d, off_mpar, off_c2c, off_rz, off_zta, off_ztb, off_rhot, off_vals[kMaxOut];
   size_t off_u[3], off_T[6], off_rhov, off_yphi, off_yom, off_uscr, off_zbuf, off_obuf, off_mean, off_aux;
+  size_t off_yp, off_yt;  // scratch of the m^c column kernel
   // values at the Greville points
   size_t off_vz0, off_vz1, off_vzl, off_vz3, off_vmd1, off_vmd3, off_vc2d, off_vm1c, off_vm2c, off_vm3c, off_vzt;
 };
@@ -1585,6 +1816,9 @@ struct lmvd_plan_s {
   int bgx = 1;      // z-lines per x-pass block
   int device = 0;
   bool use_reg = true;  // register-FFT kernels for the specialised sizes
+  double* fac = nullptr;    // A(k) factors (plan memory), filled on first use
+  bool fac_ready = false;
+  int fac_la = 7, fac_ua = 7;  // instantiated band of the factor kernels
 };
 
 namespace lmvd {
@@ -1620,6 +1854,8 @@ static void layout_workspace(lmvd_plan_s* p) {
   w.off_zbuf = take(size_t(kMaxIn) * p->pb * plane);
   w.off_obuf = take(size_t(kMaxOut) * p->pb * plane);
   w.off_mean = take(size_t(2) * H.n2 * 8);
+  w.off_yp = take(sB);
+  w.off_yt = take(sS);
   w.off_aux = take(size_t(kNumAux) * H.n2 * H.cfg.m3 * H.cfg.m1 * 8);
   w.off_vz0 = take(sB);
   w.off_vz1 = take(sB);
@@ -1755,6 +1991,24 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   UP_OR_FAIL(H.k3, &D.k3);
   UP_OR_FAIL(H.emit_first, &D.emit_first);
   UP_OR_FAIL(H.emit_cnt, &D.emit_cnt);
+  UP_OR_FAIL(H.g1e_first, &D.g1e_first);
+  UP_OR_FAIL(H.g1e_cnt, &D.g1e_cnt);
+  UP_OR_FAIL(H.asc_first, &D.asc_first);
+  UP_OR_FAIL(H.asc_cnt, &D.asc_cnt);
+  UP_OR_FAIL(H.asc_w, &D.asc_w);
+  {
+    p->fac_la = p->fac_ua = (H.a_lower <= 7 && H.a_upper <= 7) ? 7 : 8;
+    const size_t npairs = size_t(H.nl) * ((H.nn + 1) / 2);
+    const size_t bytes = size_t(H.n2 + 1) * (p->fac_la + p->fac_ua + 1) * npairs * sizeof(double);
+    void* d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) {
+      lmvd_plan_destroy(p);
+      return LMVD_ENOMEM;
+    }
+    p->allocs.push_back(d);
+    p->fac = static_cast<double*>(d);
+    D.fac = p->fac;
+  }
   const double* tw = nullptr;
   UP_OR_FAIL(H.fz.tw, &tw);
   fill_fft(H.fz, D.fz);
@@ -2010,10 +2264,32 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   double2* vm3 = c.at<double2>(W.off_vm3c);
   double2* vzt = c.at<double2>(W.off_vzt);
   const dim3 cgrid((unsigned)((ncol + kThreads - 1) / kThreads));
-  auto values_mc = [&](bool total) {
-    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * (total ? 8 : 5));
-    hipLaunchKernelGGL(k_values_mc, cgrid, dim3(kThreads), 0, s, p->D, mpar, c2c, total ? vmd1 : nullptr,
-                       total ? vc2d : nullptr, total ? vmd3 : nullptr, vm1, vm2, vm3);
+  // m^c values (and, for the final iterate, m = m^d + m^c and the coefficients) from the rho_t values
+  auto mc_step = [&](bool final_it) {
+    if (!p->fac_ready) {
+      const int npairs = H.nl * ((H.nn + 1) / 2);
+      const dim3 g((npairs + kThreads - 1) / kThreads);
+      if (p->fac_la == 7)
+        hipLaunchKernelGGL((k_factor_ul<7, 7>), g, dim3(kThreads), 0, s, p->D, p->fac);
+      else
+        hipLaunchKernelGGL((k_factor_ul<8, 8>), g, dim3(kThreads), 0, s, p->D, p->fac);
+      p->fac_ready = true;
+    }
+    const int nth = 2 * H.nl * ((H.nn + 1) / 2);
+    const dim3 g((nth + kThreads - 1) / kThreads);
+    const int S = p->fac_la + p->fac_ua + 1;
+    ProfScope ps(p, KC_SOLVEA, s,
+                 16.0 * nB * (final_it ? 14.0 : 8.0) + 16.0 * ncol * 2.0 + 8.0 * S * (H.n2 + 1) * (nth / 2));
+    double2* yp = c.at<double2>(W.off_yp);
+    double2* yt = c.at<double2>(W.off_yt);
+    if (p->fac_la == 7)
+      hipLaunchKernelGGL((k_mc<7, 7>), g, dim3(kThreads), 0, s, p->D, vals[0], yp, yt, final_it ? vmd1 : nullptr,
+                         final_it ? vc2d : nullptr, final_it ? vmd3 : nullptr, vm1, vm2, vm3,
+                         final_it ? rhot : nullptr, final_it ? c2c : nullptr, final_it ? mpar : nullptr);
+    else
+      hipLaunchKernelGGL((k_mc<8, 8>), g, dim3(kThreads), 0, s, p->D, vals[0], yp, yt, final_it ? vmd1 : nullptr,
+                         final_it ? vc2d : nullptr, final_it ? vmd3 : nullptr, vm1, vm2, vm3,
+                         final_it ? rhot : nullptr, final_it ? c2c : nullptr, final_it ? mpar : nullptr);
   };
   auto values = [&](const double2* a1, double2* v1, const double2* a2, double2* v2, const double2* a3, double2* v3) {
     ProfScope ps(p, KC_PROJ, s, 16.0 * nB * ((a1 ? 2 : 0) + (a2 ? 2 : 0) + (a3 ? 2 : 0)));
@@ -2064,9 +2340,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     const bool last = (it == kf - 1);
     st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
     if (st != LMVD_OK) return st;
-    proj(c, 0, vals[0], rhot);
-    solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
-    values_mc(false);
+    mc_step(false);
     st = plane_phase<PH_L>(c,
                            {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
                            {vals[0]});
@@ -2087,9 +2361,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   // m^c of the stage from z_t^{k_f}
   st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
   if (st != LMVD_OK) return st;
-  proj(c, 0, vals[0], rhot);
-  solveA<1>(c, rhot, nullptr, nullptr, nullptr, c2c, mpar, nullptr);
-  values_mc(true);  // m = m^d + m^c values
+  mc_step(true);  // m = m^d + m^c values
   // 4./5. velocities, density, fluxes
   const EvalIn m1 = ev(vm1, EV_IDENT);
   const EvalIn m2 = ev(vm2, EV_IDENT);

@@ -312,6 +312,12 @@ lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& H, std::string
       BandLU tmp;
       lmvd_status st = band_lu(A, n, tmp, msg);
       if (st != LMVD_OK) { msg = "A(k): " + msg; return st; }
+      // the m^c solve eliminates from the last row upwards: LU of the reversed matrix
+      std::vector<double> Ar(A.size());
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ar[size_t(i) * n + j] = A[size_t(n - 1 - i) * n + (n - 1 - j)];
+      st = band_lu(Ar, n, tmp, msg);
+      if (st != LMVD_OK) { msg = "A(k) reversed: " + msg; return st; }
     }
   }
 
@@ -333,6 +339,50 @@ lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& H, std::string
     if (lo < 0 || lo >= H.n2) { msg = "E0 band start out of range"; return LMVD_ENUMERIC; }
     H.emit_first[lo] = i;  // the smallest i with this lo, after the descending loop
     H.emit_cnt[lo] += 1;
+  }
+  // G_1 rows at interior tau*, emitted by the descending sweep of a projection
+  H.g1e_first.assign(H.n2, 0);
+  H.g1e_cnt.assign(H.n2, 0);
+  for (int i = H.n2 - 1; i >= 1; --i) {
+    const int lo = H.G[1].lo[i];
+    if (lo < 0 || lo >= H.n2) { msg = "G1 band start out of range"; return LMVD_ENUMERIC; }
+    if (i < H.n2 - 1 && lo > H.G[1].lo[i + 1]) { msg = "G1 band starts not monotone"; return LMVD_ENUMERIC; }
+    H.g1e_first[lo] = i;
+    H.g1e_cnt[lo] += 1;
+  }
+  // F_0 (B* at tau) and F_1 = E_0 D* (derivative of a B* spline at tau), emitted by an
+  // ascending sweep over B* coefficients once their last column is known
+  {
+    const int ns = H.n2 + 1;
+    std::vector<double> F0d = dense(H.F0), E0d = dense(H.E[0]);
+    H.asc_first.assign(ns, 0);
+    H.asc_cnt.assign(ns, 0);
+    H.asc_w.assign(size_t(2) * H.n2 * kMaxW, 0.0);
+    int prev_last = -1;
+    for (int i = 0; i < H.n2; ++i) {
+      std::vector<double> f1(ns, 0.0);
+      for (int j = 0; j < ns; ++j) {
+        double v = 0.0;
+        if (j >= 1) v += E0d[size_t(i) * H.n2 + j - 1] * H.dstar[j - 1];
+        if (j < H.n2) v -= E0d[size_t(i) * H.n2 + j] * H.dstar[j];
+        f1[j] = v;
+      }
+      int first = ns, last = -1;
+      for (int j = 0; j < ns; ++j)
+        if (F0d[size_t(i) * ns + j] != 0.0 || f1[j] != 0.0) {
+          first = std::min(first, j);
+          last = std::max(last, j);
+        }
+      if (last < 0 || last - first >= kMaxW) { msg = "F0/F1 row support exceeds the window"; return LMVD_ENUMERIC; }
+      if (last < prev_last) { msg = "F0/F1 row ends not monotone"; return LMVD_ENUMERIC; }
+      prev_last = last;
+      if (H.asc_cnt[last] == 0) H.asc_first[last] = i;
+      H.asc_cnt[last] += 1;
+      for (int q = 0; q < kMaxW && last - q >= 0; ++q) {
+        H.asc_w[size_t(i) * kMaxW + q] = F0d[size_t(i) * ns + last - q];
+        H.asc_w[(size_t(H.n2) + i) * kMaxW + q] = f1[last - q];
+      }
+    }
   }
   H.xtw.resize(size_t(2) * H.hx);
   const long double pi = 3.141592653589793238462643383279502884L;

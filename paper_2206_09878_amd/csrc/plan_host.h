@@ -66,6 +66,12 @@ struct HostTables {
   std::vector<double> xtw;           // cos, sin of -2 pi k / m1, k < m1/2
   // rows i' of E_0 whose band starts at row i (lo(i') = i): emit_first[i], emit_cnt[i]
   std::vector<int32_t> emit_first, emit_cnt;
+  // interior tau* rows i' (1..n2-1) of G_1 whose band starts at B row j: g1e_first[j], g1e_cnt[j]
+  std::vector<int32_t> g1e_first, g1e_cnt;
+  // tau rows i' whose last B* column (F_0 and F_1 = E_0 D* rows) is c row j: asc_first[j], asc_cnt[j]
+  // (j = 0..n2); asc_w[(d n2 + i') kMaxW + q] multiplies c_{last(i') - q}, d = 0 (F_0), 1 (F_1)
+  std::vector<int32_t> asc_first, asc_cnt;
+  std::vector<double> asc_w;
 };
 
 // Build all host tables.  Returns LMVD_OK or an error with `msg` set.
