@@ -1026,117 +1026,184 @@ __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const do
 }
 
 // ---------------------------------------------------------------------------
-// column kernel: T_ij = C_ij + tau_ij at the Greville points and its
-// interpolation (plain projection).  tau_ij = mu (d_j u_i + d_i u_j)
+// column kernel: T_ij = C_ij + tau_ij at the Greville points, their
+// interpolation, and their share of the right-hand sides of Omega2 and phi2
+// (eqs. om, phi with the body force).  tau_ij = mu (d_j u_i + d_i u_j)
 // - 2/3 mu theta delta_ij is linear in u, so its values follow from the
-// projected velocity u_hat directly (i k1, d/dy, i k3): the same numbers
-// the 3/2-grid round trip of the derivative fields would give, since the
-// forward transform inverts the inverse one on the retained modes.
-// GROUP 0 produces T11, T12, T13; GROUP 1 produces T22, T23, T33.
+// projected velocity u_hat directly (i k1, d/dy, i k3): the same numbers the
+// 3/2-grid round trip of the derivative fields would give, since the forward
+// transform inverts the inverse one on the retained modes.
+// With N_i = i k1 T_i1 + d/dy T_i2 + i k3 T_i3 (T symmetric):
+//   RHS_Omega2 = i k3 N1 - i k1 N3
+//   RHS_phi2   = -k^2 N2 - d/dy (i k1 N1 + i k3 N3) + k^2 g rho
+// GROUP 0 (T11, T12, T13) writes its part of both at tau; GROUP 1 (T22, T23,
+// T33) adds its part and the buoyancy term.  The ascending sweep reads u_hat
+// through register windows (every coefficient once) and forms the L solve of
+// the interpolation; the descending U solve keeps a window of T_hat rows and
+// emits every tau row whose band starts at the current row.  Only the
+// (0, 0) column keeps T12 / T23 coefficients (for the plane means).
+// W: register window (>= B-spline order), LB: band of the interpolation LU.
+template <int W>
+struct RowWin {
+  double2 w[W];
+  int base;
+  __device__ __forceinline__ void init(const double2* __restrict__ src, size_t ncol, size_t c, int rows) {
+    base = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) w[q] = (q < rows) ? src[size_t(q) * ncol + c] : zero2();
+  }
+  __device__ __forceinline__ void advance(const double2* __restrict__ src, size_t ncol, size_t c, int rows, int lo) {
+    while (base < lo) {
+#pragma unroll
+      for (int q = 0; q < W - 1; ++q) w[q] = w[q + 1];
+      const int r = base + W;
+      w[W - 1] = (r < rows) ? src[size_t(r) * ncol + c] : zero2();
+      ++base;
+    }
+  }
+  __device__ __forceinline__ double2 dot(const double* __restrict__ wt) const {
+    double2 acc = zero2();
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc = fma2(wt[q], w[q], acc);
+    return acc;
+  }
+};
 
-template <int GROUP>
-__global__ void __launch_bounds__(kThreads) k_proj_T(DevPlan P, const double2* __restrict__ Ca,
-                                                     const double2* __restrict__ Cb, const double2* __restrict__ Cc,
-                                                     const double2* __restrict__ u1, const double2* __restrict__ u2,
-                                                     const double2* __restrict__ u3, double2* __restrict__ Ta,
-                                                     double2* __restrict__ Tb, double2* __restrict__ Tc) {
+template <int GROUP, int W, int LB>
+__global__ void __launch_bounds__(kThreads) k_flux(DevPlan P, const double2* __restrict__ Ca,
+                                                   const double2* __restrict__ Cb, const double2* __restrict__ Cc,
+                                                   const double2* __restrict__ u1, const double2* __restrict__ u2,
+                                                   const double2* __restrict__ u3, double2* Ta, double2* Tb,
+                                                   double2* Tc, double2* RO, double2* RP,
+                                                   const double2* __restrict__ rhov) {
   const int nl = P.nl, nn = P.nn, n2 = P.n2;
-  const int ncol = nn * nl;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t ncol = size_t(nn) * nl;
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
-  const int l = c % nl, ni = c / nl;
-  const double k1 = P.k1[l], k3 = P.k3[ni];
+  const double k1 = P.k1[c % nl], k3 = P.k3[c / nl], ksq = k1 * k1 + k3 * k3;
   const double mu = P.mu, th = (2.0 / 3.0) * P.mu;
   const double* L = P.lu_l;
   const double* U = P.lu_u;
   const double* Ui = P.lu_uinv;
-  double2 ra[kMaxBand], rb[kMaxBand], rc[kMaxBand];
+  {
+    RowWin<W> w1, w2, w3;
+    w1.init(u1, ncol, c, n2);
+    w2.init(u2, ncol, c, n2);
+    w3.init(u3, ncol, c, n2);
+    double2 ra[LB], rb[LB], rc[LB];
 #pragma unroll
-  for (int m = 0; m < kMaxBand; ++m) ra[m] = rb[m] = rc[m] = zero2();
-  for (int i = 0; i < n2; ++i) {
-    const int lo = P.ev_lo[i];
-    const double* w0 = P.ev_w + size_t(i) * kMaxW;
-    const double* w1 = P.ev_w + (size_t(n2) + i) * kMaxW;
-    double2 s0[3] = {zero2(), zero2(), zero2()}, s1[3] = {zero2(), zero2(), zero2()};
+    for (int m = 0; m < LB; ++m) ra[m] = rb[m] = rc[m] = zero2();
+    for (int i = 0; i < n2; ++i) {
+      const int lo = P.ev_lo[i];
+      w1.advance(u1, ncol, c, n2, lo);
+      w2.advance(u2, ncol, c, n2, lo);
+      w3.advance(u3, ncol, c, n2, lo);
+      const double* e0 = P.ev_w + size_t(i) * kMaxW;
+      const double* e1 = P.ev_w + (size_t(n2) + i) * kMaxW;
+      double2 s0[3] = {w1.dot(e0), w2.dot(e0), w3.dot(e0)};
+      double2 s1[3] = {w1.dot(e1), w2.dot(e1), w3.dot(e1)};
+      // d[a][b] = d u_a / d x_b at tau_i
+      double2 d[3][3];
 #pragma unroll
-    for (int q = 0; q < kMaxW; ++q) {
-      const int r = lo + q;
-      if (r < n2 && (w0[q] != 0.0 || w1[q] != 0.0)) {
-        const size_t e = size_t(r) * ncol + c;
-        const double2 a = u1[e], b = u2[e], d = u3[e];
-        s0[0] = fma2(w0[q], a, s0[0]);
-        s1[0] = fma2(w1[q], a, s1[0]);
-        s0[1] = fma2(w0[q], b, s0[1]);
-        s1[1] = fma2(w1[q], b, s1[1]);
-        s0[2] = fma2(w0[q], d, s0[2]);
-        s1[2] = fma2(w1[q], d, s1[2]);
+      for (int a = 0; a < 3; ++a) {
+        d[a][0] = times_i(cscale(s0[a], k1));
+        d[a][1] = s1[a];
+        d[a][2] = times_i(cscale(s0[a], k3));
       }
-    }
-    // d[a][b] = d u_a / d x_b at tau_i
-    double2 d[3][3];
+      const double2 theta = cadd(cadd(d[0][0], d[1][1]), d[2][2]);
+      const size_t e = size_t(i) * ncol + c;
+      double2 ba, bb, bc;
+      if (GROUP == 0) {
+        ba = cadd(Ca[e], make_double2(2 * mu * d[0][0].x - th * theta.x, 2 * mu * d[0][0].y - th * theta.y));
+        bb = cadd(Cb[e], cscale(cadd(d[0][1], d[1][0]), mu));
+        bc = cadd(Cc[e], cscale(cadd(d[0][2], d[2][0]), mu));
+      } else {
+        ba = cadd(Ca[e], make_double2(2 * mu * d[1][1].x - th * theta.x, 2 * mu * d[1][1].y - th * theta.y));
+        bb = cadd(Cb[e], cscale(cadd(d[1][2], d[2][1]), mu));
+        bc = cadd(Cc[e], make_double2(2 * mu * d[2][2].x - th * theta.x, 2 * mu * d[2][2].y - th * theta.y));
+      }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      d[a][0] = times_i(cscale(s0[a], k1));
-      d[a][1] = s1[a];
-      d[a][2] = times_i(cscale(s0[a], k3));
-    }
-    const double2 theta = cadd(cadd(d[0][0], d[1][1]), d[2][2]);
-    const size_t e = size_t(i) * ncol + c;
-    double2 ba, bb, bc;
-    if (GROUP == 0) {
-      ba = cadd(Ca[e], make_double2(2 * mu * d[0][0].x - th * theta.x, 2 * mu * d[0][0].y - th * theta.y));
-      bb = cadd(Cb[e], cscale(cadd(d[0][1], d[1][0]), mu));
-      bc = cadd(Cc[e], cscale(cadd(d[0][2], d[2][0]), mu));
-    } else {
-      ba = cadd(Ca[e], make_double2(2 * mu * d[1][1].x - th * theta.x, 2 * mu * d[1][1].y - th * theta.y));
-      bb = cadd(Cb[e], cscale(cadd(d[1][2], d[2][1]), mu));
-      bc = cadd(Cc[e], make_double2(2 * mu * d[2][2].x - th * theta.x, 2 * mu * d[2][2].y - th * theta.y));
-    }
+      for (int m = 0; m < LB; ++m) {
+        const double lm = L[i * kMaxBand + m];
+        ba = fma2(-lm, ra[m], ba);
+        bb = fma2(-lm, rb[m], bb);
+        bc = fma2(-lm, rc[m], bc);
+      }
+      Ta[e] = ba;
+      Tb[e] = bb;
+      Tc[e] = bc;
 #pragma unroll
-    for (int m = 0; m < kMaxBand; ++m) {
-      const double lm = L[i * kMaxBand + m];
-      ba = fma2(-lm, ra[m], ba);
-      bb = fma2(-lm, rb[m], bb);
-      bc = fma2(-lm, rc[m], bc);
+      for (int m = LB - 1; m > 0; --m) {
+        ra[m] = ra[m - 1];
+        rb[m] = rb[m - 1];
+        rc[m] = rc[m - 1];
+      }
+      ra[0] = ba;
+      rb[0] = bb;
+      rc[0] = bc;
     }
-    Ta[e] = ba;
-    Tb[e] = bb;
-    Tc[e] = bc;
-#pragma unroll
-    for (int m = kMaxBand - 1; m > 0; --m) {
-      ra[m] = ra[m - 1];
-      rb[m] = rb[m - 1];
-      rc[m] = rc[m - 1];
-    }
-    ra[0] = ba;
-    rb[0] = bb;
-    rc[0] = bc;
   }
+  double2 wa[W], wb[W], wc[W];  // T_hat rows i .. i+W-1
 #pragma unroll
-  for (int m = 0; m < kMaxBand; ++m) ra[m] = rb[m] = rc[m] = zero2();
+  for (int q = 0; q < W; ++q) wa[q] = wb[q] = wc[q] = zero2();
+  const double k1k3 = k1 * k3;
   for (int i = n2 - 1; i >= 0; --i) {
     const size_t e = size_t(i) * ncol + c;
     double2 ya = Ta[e], yb = Tb[e], yc = Tc[e];
 #pragma unroll
-    for (int q = 0; q < kMaxBand; ++q) {
+    for (int q = 0; q < LB; ++q) {
       const double u = U[i * (kMaxBand + 1) + q + 1];
-      ya = fma2(-u, ra[q], ya);
-      yb = fma2(-u, rb[q], yb);
-      yc = fma2(-u, rc[q], yc);
+      ya = fma2(-u, wa[q], ya);
+      yb = fma2(-u, wb[q], yb);
+      yc = fma2(-u, wc[q], yc);
     }
-    const double2 xa = cscale(ya, Ui[i]), xb = cscale(yb, Ui[i]), xc = cscale(yc, Ui[i]);
 #pragma unroll
-    for (int q = kMaxBand - 1; q > 0; --q) {
-      ra[q] = ra[q - 1];
-      rb[q] = rb[q - 1];
-      rc[q] = rc[q - 1];
+    for (int q = W - 1; q > 0; --q) {
+      wa[q] = wa[q - 1];
+      wb[q] = wb[q - 1];
+      wc[q] = wc[q - 1];
     }
-    ra[0] = xa;
-    rb[0] = xb;
-    rc[0] = xc;
-    Ta[e] = xa;
-    Tb[e] = xb;
-    Tc[e] = xc;
+    wa[0] = cscale(ya, Ui[i]);
+    wb[0] = cscale(yb, Ui[i]);
+    wc[0] = cscale(yc, Ui[i]);
+    if (c == 0) Tb[e] = wb[0];
+    const int first = P.emit_first[i], cnt = P.emit_cnt[i];
+    for (int t = 0; t < cnt; ++t) {
+      const int r = first + t;
+      const double* e0 = P.ev_w + size_t(r) * kMaxW;
+      const double* e1 = P.ev_w + (size_t(n2) + r) * kMaxW;
+      const double* e2 = P.ev_w + (size_t(2 * n2) + r) * kMaxW;
+      double2 a0 = zero2(), a1 = zero2(), b0 = zero2(), b1 = zero2(), b2 = zero2(), c0 = zero2(), c1 = zero2();
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        a0 = fma2(e0[q], wa[q], a0);
+        a1 = fma2(e1[q], wa[q], a1);
+        b0 = fma2(e0[q], wb[q], b0);
+        b1 = fma2(e1[q], wb[q], b1);
+        b2 = fma2(e2[q], wb[q], b2);
+        c0 = fma2(e0[q], wc[q], c0);
+        c1 = fma2(e1[q], wc[q], c1);
+      }
+      const size_t o = size_t(r) * ncol + c;
+      double2 om, ph;
+      if (GROUP == 0) {  // a = T11, b = T12, c = T13
+        // -k1 k3 E0 T11 + i k3 E1 T12 + (k1^2 - k3^2) E0 T13
+        om = cadd(cadd(cscale(a0, -k1k3), times_i(cscale(b1, k3))), cscale(c0, k1 * k1 - k3 * k3));
+        // k1^2 E1 T11 - i k1 (k^2 E0 T12 + E2 T12) + 2 k1 k3 E1 T13
+        const double2 t12 = make_double2(ksq * b0.x + b2.x, ksq * b0.y + b2.y);
+        ph = cadd(csub(cscale(a1, k1 * k1), times_i(cscale(t12, k1))), cscale(c1, 2.0 * k1k3));
+      } else {  // a = T22, b = T23, c = T33
+        // -i k1 E1 T23 + k1 k3 E0 T33
+        om = cadd(RO[o], csub(cscale(c0, k1k3), times_i(cscale(b1, k1))));
+        // -k^2 E1 T22 - i k3 (k^2 E0 T23 + E2 T23) + k3^2 E1 T33 + k^2 g rho
+        const double2 t23 = make_double2(ksq * b0.x + b2.x, ksq * b0.y + b2.y);
+        const double2 rv = rhov[o];
+        ph = cadd(RP[o], cadd(csub(cscale(c1, k3 * k3), times_i(cscale(t23, k3))),
+                              make_double2(ksq * (P.g * rv.x - a1.x), ksq * (P.g * rv.y - a1.y))));
+      }
+      RO[o] = om;
+      RP[o] = ph;
+    }
   }
 }
 
@@ -1586,22 +1653,19 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
 }
 
 // ---------------------------------------------------------------------------
-// column kernel: RHS of Omega2 and phi2 from the projected T_ij, Dirichlet-row
-// projection, RK2 update (eqs. om, phi with the body force; R17 form
-// RHS_phi2 = -k^2 N2 - d/dy(i k1 N1 + i k3 N3) + k^2 g rho).
+// column kernel: the right-hand sides of Omega2 and phi2 at tau (from the
+// flux kernels) -> coefficients with Dirichlet end rows, RK2 update.
 
 __global__ void __launch_bounds__(kThreads) k_rhs_fluct(
-    DevPlan P, const double2* __restrict__ T11, const double2* __restrict__ T12, const double2* __restrict__ T13,
-    const double2* __restrict__ T22, const double2* __restrict__ T23, const double2* __restrict__ T33,
-    const double2* __restrict__ rhov, const double2* phi, const double2* om, const double2* __restrict__ rphi_prev,
-    const double2* __restrict__ rom_prev, double2* phi_out, double2* om_out, double2* __restrict__ rphi_out,
-    double2* __restrict__ rom_out, double2* __restrict__ yphi, double2* __restrict__ yom, int stage) {
+    DevPlan P, const double2* __restrict__ RO, const double2* __restrict__ RP, const double2* phi,
+    const double2* om, const double2* __restrict__ rphi_prev, const double2* __restrict__ rom_prev, double2* phi_out,
+    double2* om_out, double2* __restrict__ rphi_out, double2* __restrict__ rom_out, double2* __restrict__ yphi,
+    double2* __restrict__ yom, int stage) {
   const int nl = P.nl, nn = P.nn, n2 = P.n2;
   const int ncol = nn * nl;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
-  const int l = c % nl, ni = c / nl;
-  const double k1 = P.k1[l], k3 = P.k3[ni], ksq = k1 * k1 + k3 * k3;
+  (void)nl;
   const double* L = P.lu_l + size_t(1) * n2 * kMaxBand;
   const double* U = P.lu_u + size_t(1) * n2 * (kMaxBand + 1);
   const double* Ui = P.lu_uinv + size_t(1) * n2;
@@ -1611,44 +1675,8 @@ __global__ void __launch_bounds__(kThreads) k_rhs_fluct(
   for (int i = 0; i < n2; ++i) {
     double2 bp = zero2(), bo = zero2();
     if (i > 0 && i < n2 - 1) {
-      const int lo = P.ev_lo[i];
-      const double* w0 = P.ev_w + (size_t(0) * n2 + i) * kMaxW;
-      const double* w1 = P.ev_w + (size_t(1) * n2 + i) * kMaxW;
-      const double* w2 = P.ev_w + (size_t(2) * n2 + i) * kMaxW;
-      double2 e0_11 = zero2(), e1_11 = zero2(), e0_12 = zero2(), e1_12 = zero2(), e2_12 = zero2();
-      double2 e0_13 = zero2(), e1_13 = zero2(), e1_22 = zero2(), e0_23 = zero2(), e1_23 = zero2();
-      double2 e2_23 = zero2(), e0_33 = zero2(), e1_33 = zero2();
-#pragma unroll
-      for (int q = 0; q < kMaxW; ++q) {
-        const int r = lo + q;
-        if (r < n2 && (w0[q] != 0.0 || w1[q] != 0.0 || w2[q] != 0.0)) {
-          const size_t e = size_t(r) * ncol + c;
-          const double2 t11 = T11[e], t12 = T12[e], t13 = T13[e], t22 = T22[e], t23 = T23[e], t33 = T33[e];
-          e0_11 = fma2(w0[q], t11, e0_11);
-          e1_11 = fma2(w1[q], t11, e1_11);
-          e0_12 = fma2(w0[q], t12, e0_12);
-          e1_12 = fma2(w1[q], t12, e1_12);
-          e2_12 = fma2(w2[q], t12, e2_12);
-          e0_13 = fma2(w0[q], t13, e0_13);
-          e1_13 = fma2(w1[q], t13, e1_13);
-          e1_22 = fma2(w1[q], t22, e1_22);
-          e0_23 = fma2(w0[q], t23, e0_23);
-          e1_23 = fma2(w1[q], t23, e1_23);
-          e2_23 = fma2(w2[q], t23, e2_23);
-          e0_33 = fma2(w0[q], t33, e0_33);
-          e1_33 = fma2(w1[q], t33, e1_33);
-        }
-      }
-      // N_i = i k1 T_i1 + d/dy T_i2 + i k3 T_i3 ;  dN_i = its y-derivative
-      const double2 N1 = cadd(cadd(times_i(cscale(e0_11, k1)), e1_12), times_i(cscale(e0_13, k3)));
-      const double2 N2 = cadd(cadd(times_i(cscale(e0_12, k1)), e1_22), times_i(cscale(e0_23, k3)));
-      const double2 N3 = cadd(cadd(times_i(cscale(e0_13, k1)), e1_23), times_i(cscale(e0_33, k3)));
-      const double2 dN1 = cadd(cadd(times_i(cscale(e1_11, k1)), e2_12), times_i(cscale(e1_13, k3)));
-      const double2 dN3 = cadd(cadd(times_i(cscale(e1_13, k1)), e2_23), times_i(cscale(e1_33, k3)));
-      bo = csub(times_i(cscale(N1, k3)), times_i(cscale(N3, k1)));
-      const double2 g = cadd(times_i(cscale(dN1, k1)), times_i(cscale(dN3, k3)));
-      const double2 rv = rhov[size_t(i) * ncol + c];
-      bp = make_double2(-ksq * N2.x - g.x + ksq * P.g * rv.x, -ksq * N2.y - g.y + ksq * P.g * rv.y);
+      bp = RP[size_t(i) * ncol + c];
+      bo = RO[size_t(i) * ncol + c];
     }
 #pragma unroll
     for (int m = 0; m < kMaxBand; ++m) {
@@ -2373,22 +2401,33 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
                            {vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]});
   if (st != LMVD_OK) return st;
   for (int i = 0; i < 3; ++i) proj(c, 0, vals[i], u[i]);
+  // fluxes and their share of the RHS values at tau (RO: Omega2, RP: phi2)
+  double2* RO = vals[0];
+  double2* RP = vals[1];
   {
     const int n = int(ncol);
     const dim3 grid((n + kThreads - 1) / kThreads);
-    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * 15.0);
-    hipLaunchKernelGGL(k_proj_T<0>, grid, dim3(kThreads), 0, s, p->D, cv[0], cv[1], cv[2], u[0], u[1], u[2], T[0],
-                       T[1], T[2]);
-    hipLaunchKernelGGL(k_proj_T<1>, grid, dim3(kThreads), 0, s, p->D, cv[3], cv[4], cv[5], u[0], u[1], u[2], T[3],
-                       T[4], T[5]);
+    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * 25.0);
+    const bool narrow = H.p <= 8 && H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
+    if (narrow) {
+      hipLaunchKernelGGL((k_flux<0, 8, 6>), grid, dim3(kThreads), 0, s, p->D, cv[0], cv[1], cv[2], u[0], u[1], u[2],
+                         T[0], T[1], T[2], RO, RP, rhov);
+      hipLaunchKernelGGL((k_flux<1, 8, 6>), grid, dim3(kThreads), 0, s, p->D, cv[3], cv[4], cv[5], u[0], u[1], u[2],
+                         T[3], T[4], T[5], RO, RP, rhov);
+    } else {
+      hipLaunchKernelGGL((k_flux<0, kMaxW, kMaxBand>), grid, dim3(kThreads), 0, s, p->D, cv[0], cv[1], cv[2], u[0],
+                         u[1], u[2], T[0], T[1], T[2], RO, RP, rhov);
+      hipLaunchKernelGGL((k_flux<1, kMaxW, kMaxBand>), grid, dim3(kThreads), 0, s, p->D, cv[3], cv[4], cv[5], u[0],
+                         u[1], u[2], T[3], T[4], T[5], RO, RP, rhov);
+    }
   }
   // RHS and RK2
   {
     const int n = int(ncol);
     {
-    ProfScope ps(p, KC_RHS, s, 16.0 * nB * (a->stage ? 11.0 : 9.0) + 16.0 * nB * ((a->rhs_phi2 ? 2 : 0) + 2));
-    hipLaunchKernelGGL(k_rhs_fluct, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, T[0], T[1],
-                       T[2], T[3], T[4], T[5], rhov, phi2, om2, static_cast<const double2*>(a->rhs_phi2_prev),
+    ProfScope ps(p, KC_RHS, s, 16.0 * nB * (a->stage ? 12.0 : 10.0) + 16.0 * nB * (a->rhs_phi2 ? 2 : 0));
+    hipLaunchKernelGGL(k_rhs_fluct, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, RO, RP, phi2,
+                       om2, static_cast<const double2*>(a->rhs_phi2_prev),
                        static_cast<const double2*>(a->rhs_omega2_prev), static_cast<double2*>(a->phi2_out),
                        static_cast<double2*>(a->omega2_out), static_cast<double2*>(a->rhs_phi2),
                        static_cast<double2*>(a->rhs_omega2), c.at<double2>(W.off_yphi), c.at<double2>(W.off_yom),
