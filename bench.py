@@ -9,7 +9,7 @@ seeded synthetic fields (no dataset).  A step is one substep of the method
 alternate n, ', n, ...  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line with substeps/s, the roofline of the dominant kernel
-class (HIP events on the library's stream over the timed region) and the CPU
+(HIP events on the library's stream over the timed region) and the CPU
 oracle baseline.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
@@ -17,9 +17,11 @@ oracle baseline.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import resource
 import sys
 import time
 
@@ -27,46 +29,84 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-CLASS_NAMES = ("eval_zinv", "xpass", "zfwd", "proj", "solveA", "rhs")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2206_09878_amd", "csrc", "lmvd.hip")
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+
+
+def class_names():
+    from paper_2206_09878_amd.lmvd import Plan
+    return Plan.KERNEL_CLASSES
+
+
+def kernel_symbol(cls: str, w) -> str:
+    """Kernel symbol a class launches on the register-FFT sizes (as rocprofv3 names it)."""
+    m1, m3 = w.m1, w.m3
+    return {
+        "zinv": f"k_zinv_r<{m3}, true>", "zfwd": f"k_zfwd_r<{m3}>",
+        "xpass_rz": f"k_xpair<0, {m1}>", "xpass_rhot": f"k_xpair<1, {m1}>", "xpass_l": f"k_xpair<2, {m1}>",
+        "xpass_vel": f"k_xpair<3, {m1}>", "mc": "k_mc<7, 7>", "md": "k_solveA<0, 7, 7>", "proj": "k_proj<0>",
+        "proj_zt": "k_proj<1>, k_proj<2>", "values": "k_values, k_values_z, k_guess_v",
+        "flux": "k_flux<0, 8, 6>, k_flux<1, 8, 6>", "rhs": "k_rhs_fluct, k_rhs_mean",
+    }.get(cls, cls)
+
+
+def source_digest() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def counter_traffic(cls: str, w):
+    """HBM bytes per launch of `cls` from the committed rocprofv3 counter summary, or None when
+    there is none for this class and workload or the kernel source changed since it was taken."""
+    path = os.path.join(TRAFFIC_DIR, f"traffic_{cls}_{w.name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != source_digest():
+        return None
+    return t["fetch_kib_per_dispatch"] * 1024.0 * t["fetch_scale"] + \
+        t["write_kib_per_dispatch"] * 1024.0 * t["write_scale"]
 
 
 def substep_model_bytes(w, kf):
-    """Algorithmic HBM bytes of one substep under the dataflow model of the
-    method: (87 + 16 k_f) spectral-field passes of N1/2 (N3-1) n2 complex128."""
+    """HBM bytes of one substep under the reference dataflow of the method:
+    (87 + 16 k_f) spectral-field passes of N1/2 (N3-1) n2 complex128."""
     s = (w.n1 // 2) * (w.n3 - 1) * w.n2 * 16.0
     return (87 + 16 * kf) * s
 
 
-def cpu_baseline(full):
+def cpu_baseline(full, n=128, n2=129):
     """The oracle, untouched, on a bounded sample: one substep of the same
-    workload recipe at 128 x 97 x 128 (192 x 192 grid), scaled to the full
-    size by the ratio of transform work N1 N3 n2 log2(M1 M3)."""
-    from threadpoolctl import threadpool_info
-
+    workload recipe at n x n2 x n, scaled to the full size by the ratio of
+    transform work N1 N3 n2 log2(M1 M3)."""
     from oracle.lmvd import Config, Plan as OPlan, substep
     from paper_2206_09878_amd.workloads import make_inputs, workload
-    w = workload(full.name, n=128, n2=97)
+    w = workload(full.name, n=n, n2=n2)
     inp = make_inputs(w, seed=2)
     st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
     cfg = Config(w.n1, w.n3, w.n2, w.order, w.m1, w.m3, w.L1, w.L2, w.L3, w.breakpoints, w.dt, w.mu,
                  w.rhoD, w.g, w.rho_l, w.rho_h, w.beta_n, w.beta_p, w.kf)
     op = OPlan(cfg)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
     substep(op, st, 0, hist=inp["hist"])
     t = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
 
     def work(x):
         return x.n1 * x.n3 * x.n2 * math.log2(x.m1 * x.m3)
 
     ratio = work(full) / work(w)
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": 1.0 / (t * ratio), "unit": "substeps/s", "cores": threads, "kind": "oracle",
-            "sample": f"one oracle substep of the {full.name} recipe at 128x97x128 (192x192 grid): "
-                      f"{t:.1f} s, scaled by the transform-work ratio {ratio:.1f} to "
-                      f"{full.n1}x{full.n2}x{full.n3}"}
+    return {"value": 1.0 / (t * ratio), "unit": "substeps/s", "cores": max(1, round(cpu / t)), "kind": "oracle",
+            "sample": f"one oracle substep (stage n, k_f={w.kf}) of the {full.name} recipe at "
+                      f"{w.n1}x{w.n2}x{w.n3} ({w.m1}x{w.m3} grid): {t:.1f} s wall, {cpu:.1f} s CPU; scaled by "
+                      f"the transform-work ratio {ratio:.1f} to {full.n1}x{full.n2}x{full.n3}"}
 
 
 def main():
+    names = class_names()
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -74,12 +114,26 @@ def main():
     ap.add_argument("--workload", default="rt512")
     ap.add_argument("--plane-batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-class", choices=CLASS_NAMES, default=None,
+    ap.add_argument("--kernel-class", choices=names, default=None,
                     help="time this kernel class instead of detecting the dominant one")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only copy a GIB-sized device buffer three times (reference kernel for the HBM "
+                         "byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = int(args.copy_calibration * 2**30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": 8 * n, "dispatches": 3}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs the substep on one GPU only; multi-GPU sharding is a design "
-              "(see the design notes), not a run. Use --gpus 1.", file=sys.stderr)
+        print("bench.py: this build runs the substep on one GPU only; sharding across GPUs is a design, "
+              "not a run. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -98,17 +152,19 @@ def main():
     # dominant kernel class: one untimed substep per class with its launches timed
     totals = {}
     if args.kernel_class is None:
-        for cls in range(len(CLASS_NAMES)):
+        for cls in range(len(names)):
+            if names[cls] == "xpass_io":
+                continue
             plan.profile_start(cls)
             stepper.substep()
             ms, n, b = plan.profile_stop()
             totals[cls] = ms
         dom = max(totals, key=totals.get)
     else:
-        dom = CLASS_NAMES.index(args.kernel_class)
+        dom = names.index(args.kernel_class)
     torch.cuda.synchronize()
 
-    # timed region
+    # timed region: the dominant class is timed with events on the library's stream
     plan.profile_start(dom)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -119,7 +175,9 @@ def main():
     kms, klaunch, kbytes = plan.profile_stop()
 
     value = args.steps / elapsed
-    achieved = kbytes / (kms * 1e-3) / 1e9
+    avg_ms = kms / max(klaunch, 1)
+    achieved = (kbytes / max(klaunch, 1)) / (avg_ms * 1e-3) / 1e9
+    traffic = counter_traffic(names[dom], w)
     model = substep_model_bytes(w, w.kf)
     out = {
         "metric": "RK substeps/s at 512x385x512 FP64",
@@ -137,13 +195,14 @@ def main():
         "config": {"workload": f"{w.name}: Rayleigh-Taylor At=0.925, {w.n1}x{w.n2}x{w.n3} modes, "
                                f"{w.m1}x{w.m3} dealiased x-z grid, k_f={w.kf}, stages n/' alternating",
                    "kf": w.kf, "plane_batch": args.plane_batch or w.n2},
-        "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "launches": klaunch, "avg_launch_ms": kms / max(klaunch, 1),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel_class": names[dom], "kernel": kernel_symbol(names[dom], w),
+                     "launches": klaunch, "avg_launch_ms": avg_ms, "bytes_per_launch": kbytes / max(klaunch, 1),
                      "share_of_substep": (totals[dom] / sum(totals.values())) if totals else None},
         "substep_roofline": {"model_bytes_per_substep": model,
                              "frac": model * value / (HBM_PEAK_GBS * 1e9)},
-        "kernel_class_ms_per_substep": {CLASS_NAMES[c]: totals[c] for c in totals},
+        "kernel_class_ms_per_substep": {names[c]: totals[c] for c in totals},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

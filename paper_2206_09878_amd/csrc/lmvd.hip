@@ -2068,7 +2068,28 @@ struct Ctx {
 static size_t ncols(const lmvd_plan_s* p) { return size_t(p->H.nn) * p->H.nl; }
 
 // kernel classes of the timing hook
-enum KClass { KC_EVAL = 0, KC_XPASS = 1, KC_ZFWD = 2, KC_PROJ = 3, KC_SOLVEA = 4, KC_RHS = 5, KC_COUNT = 6 };
+// Each class is one kernel (one symbol on the rt512-like sizes); the bytes a
+// launch reports are its compulsory traffic: inputs read once, outputs written
+// once, the factor tables, and the stored intermediate of a two-sweep banded
+// solve (written by the first sweep, read by the second).  Re-reads through
+// the caches are not counted.
+enum KClass {
+  KC_ZINV = 0,       // inverse z transforms (all phases)
+  KC_XPASS_RZ = 1,   // x-pass of R_z (also writes the physical aux fields)
+  KC_XPASS_L = 2,    // x-pass of L z_t
+  KC_XPASS_RHOT = 3, // x-pass of rho_t
+  KC_XPASS_VEL = 4,  // x-pass of u, rho, C_ij
+  KC_ZFWD = 5,       // forward z transforms (all phases)
+  KC_MC = 6,         // fused m^c column kernel
+  KC_MD = 7,         // m^d solve
+  KC_PROJ = 8,       // projection with plain store (u_hat, R_z)
+  KC_PROJ_ZT = 9,    // projection + R_z add (+ z update) of the fixed-point iterate
+  KC_VALUES = 10,    // values at tau of fixed fields (m^d, z, guess)
+  KC_FLUX = 11,      // T_ij projection and RHS emission (both groups)
+  KC_RHS = 12,       // RHS projection, RK2 update, plane means
+  KC_XPASS_IO = 13,  // x-pass of the transform entry points
+  KC_COUNT = 14
+};
 
 // Bracket one launch of class `cls` with events when that class is timed.
 struct ProfScope {
@@ -2188,7 +2209,7 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
     if (!ins.empty()) {
       double terms = 0;
       for (const EvalIn& e : ins) terms += e.b ? 2 : 1;
-      ProfScope ps(p, KC_EVAL, c.s, nb * (terms * splane + nin * zplane));
+        ProfScope ps(p, KC_ZINV, c.s, nb * (terms * splane + nin * zplane));
       if (zr) {
 #define CALLZ(N) launch_zinv_t<N>(p, c.s, A, zbuf, j0, nb, int(ins.size()))
         LMVD_ZSWITCH(M3, CALLZ)
@@ -2199,7 +2220,9 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
       }
     }
     {
-      ProfScope ps(p, KC_XPASS, c.s, nb * ((nin + nout) * zplane + naux * double(M3) * H.cfg.m1 * 8.0));
+      constexpr int xcls = (PH == PH_RZ) ? KC_XPASS_RZ : (PH == PH_L) ? KC_XPASS_L : (PH == PH_RHOT) ? KC_XPASS_RHOT
+                           : (PH == PH_VEL) ? KC_XPASS_VEL : KC_XPASS_IO;
+      ProfScope ps(p, xcls, c.s, nb * ((nin + nout) * zplane + naux * double(M3) * H.cfg.m1 * 8.0));
       if (xr) {
 #define CALLX(N) launch_xpass_t<PH, N>(p, c.s, zbuf, obuf, phys_out, phys_in, j0, nb, aux)
         LMVD_XSWITCH(H.cfg.m1, CALLX)
@@ -2228,7 +2251,8 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
 static void proj(const Ctx& c, int kind, const double2* in, double2* out, double2* v0 = nullptr,
                  double2* v1 = nullptr) {
   const int n = int(ncols(c.p));
-  ProfScope ps(c.p, KC_PROJ, c.s, 2.0 * 16.0 * n * c.p->H.n2);
+  // values in, L-sweep intermediate out and back, coefficients out, optional emitted values
+  ProfScope ps(c.p, KC_PROJ, c.s, (4.0 + (v0 ? 1.0 : 0.0) + (v1 ? 1.0 : 0.0)) * 16.0 * n * c.p->H.n2);
   hipLaunchKernelGGL(k_proj<EPI_STORE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, c.s, c.p->D, kind,
                      in, out, nullptr, nullptr, nullptr, nullptr, v0, v1, 0, n);
 }
@@ -2241,7 +2265,9 @@ static void solveA(const Ctx& c, const double2* in1, const double2* in2, const d
   dim3 grid((npairs + kThreads - 1) / kThreads);
   double* uscr = c.at<double>(c.p->ws.off_uscr);
   const double sB = 16.0 * ncols(c.p) * H.n2, sS = 16.0 * ncols(c.p) * (H.n2 + 1);
-  ProfScope ps(c.p, KC_SOLVEA, c.s, MODE == 0 ? 4.0 * sB + sS : 2.0 * sB + sS);
+  // MODE 0: phi2, Omega2 in, m1, m3 out, c (B*) forward store + read back + final store, U rows stored and read
+  const double uscr_bytes = 2.0 * 8.0 * (H.a_upper + 1) * (H.n2 + 1) * double(npairs);
+  ProfScope ps(c.p, MODE == 0 ? KC_MD : KC_MC, c.s, (MODE == 0 ? 4.0 * sB : 2.0 * sB) + 3.0 * sS + uscr_bytes);
   // the U scratch stride is (a_upper + 1); kernels are instantiated for the band of the plan
   if (H.a_lower <= 7 && H.a_upper <= 7)
     hipLaunchKernelGGL((k_solveA<MODE, 7, 7>), grid, dim3(kThreads), 0, c.s, c.p->D, in1, in2, m1bar, m3bar, c2, o1,
@@ -2306,8 +2332,11 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     const int nth = 2 * H.nl * ((H.nn + 1) / 2);
     const dim3 g((nth + kThreads - 1) / kThreads);
     const int S = p->fac_la + p->fac_ua + 1;
-    ProfScope ps(p, KC_SOLVEA, s,
-                 16.0 * nB * (final_it ? 14.0 : 8.0) + 16.0 * ncol * 2.0 + 8.0 * S * (H.n2 + 1) * (nth / 2));
+    // values in, L-sweep intermediate out and back, 3 value fields out, A(k) sweep intermediate out and back,
+    // the factors once per pair; the final iterate also reads m^d values and writes rho_t, m_par, c2
+    ProfScope ps(p, KC_MC, s,
+                 16.0 * nB * (final_it ? 11.0 : 6.0) + 16.0 * ncol * (H.n2 + 1) * (final_it ? 3.0 : 2.0) +
+                     8.0 * S * (H.n2 + 1) * (nth / 2));
     double2* yp = c.at<double2>(W.off_yp);
     double2* yt = c.at<double2>(W.off_yt);
     if (p->fac_la == 7)
@@ -2320,7 +2349,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
                          final_it ? rhot : nullptr, final_it ? c2c : nullptr, final_it ? mpar : nullptr);
   };
   auto values = [&](const double2* a1, double2* v1, const double2* a2, double2* v2, const double2* a3, double2* v3) {
-    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * ((a1 ? 2 : 0) + (a2 ? 2 : 0) + (a3 ? 2 : 0)));
+    ProfScope ps(p, KC_VALUES, s, 16.0 * nB * ((a1 ? 2 : 0) + (a2 ? 2 : 0) + (a3 ? 2 : 0)));
     hipLaunchKernelGGL(k_values, cgrid, dim3(kThreads), 0, s, p->D, a1, v1, a2, v2, a3, v3);
   };
 
@@ -2329,7 +2358,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   values(md1, vmd1, md3, vmd3, c2d, vc2d);
   // values of z and its y-derivatives (z is fixed during the substep)
   {
-    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * 5);
+    ProfScope ps(p, KC_VALUES, s, 16.0 * nB * 5);
     hipLaunchKernelGGL(k_values_z, cgrid, dim3(kThreads), 0, s, p->D, z, vz0, vz1, vzl, vz3);
   }
   // 2. R_z
@@ -2351,7 +2380,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     double2* gdst = (kf == 0 && user_zt) ? user_zt : zta;
     const int zero = (a->guess_mode == 1) ? 1 : 0;
     {
-      ProfScope ps(p, KC_PROJ, s, 16.0 * nB * (zero ? 2 : 6));
+      ProfScope ps(p, KC_VALUES, s, 16.0 * nB * (zero ? 2 : 6));
       hipLaunchKernelGGL(k_guess_v, cgrid, dim3(kThreads), 0, s, p->D, z, static_cast<const double2*>(a->z_hist[0]),
                          static_cast<const double2*>(a->z_hist[1]), static_cast<const double2*>(a->z_hist[2]), co[0],
                          co[1], co[2], co[3], H.cfg.dt, zero, gdst, vzt);
@@ -2375,7 +2404,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     if (st != LMVD_OK) return st;
     double2* next = (last && user_zt) ? user_zt : (cur == zta ? ztb : zta);
     const int n = int(ncol);
-    ProfScope ps(p, KC_PROJ, s, (last ? (a->stage ? 7.0 : 6.0) : 4.0) * 16.0 * nB);
+    ProfScope ps(p, KC_PROJ_ZT, s, (last ? (a->stage ? 9.0 : 8.0) : 6.0) * 16.0 * nB);
     if (last) {
       hipLaunchKernelGGL(k_proj<EPI_ADD_ZUPDATE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
                          vals[0], next, rz, z, static_cast<const double2*>(a->zt_prev),
@@ -2407,7 +2436,9 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   {
     const int n = int(ncol);
     const dim3 grid((n + kThreads - 1) / kThreads);
-    ProfScope ps(p, KC_PROJ, s, 16.0 * nB * 25.0);
+    // per group: C_ij and u_hat in, L-sweep intermediates out and back, RHS values out (group 1 also
+    // reads them and rho)
+    ProfScope ps(p, KC_FLUX, s, 16.0 * nB * 31.0);
     const bool narrow = H.p <= 8 && H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
     if (narrow) {
       hipLaunchKernelGGL((k_flux<0, 8, 6>), grid, dim3(kThreads), 0, s, p->D, cv[0], cv[1], cv[2], u[0], u[1], u[2],
