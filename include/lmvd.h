@@ -37,9 +37,10 @@
  * and Omega2 are ignored on input and their RHS are written as zero.
  *
  * Ownership.  Every state, output and workspace buffer is device memory owned
- * by the caller.  A plan owns only its constant tables.  lmvd_substep
- * allocates nothing, does not synchronise the host and only enqueues work on
- * the given stream.
+ * by the caller.  A plan owns only its constant tables, among them the
+ * factors of A(k) for every (l, |n|) pair, which the first lmvd_substep of
+ * the plan computes on its stream.  lmvd_substep allocates nothing, does not
+ * synchronise the host and only enqueues work on the given stream.
  *
  * Errors.  Every entry point returns an lmvd_status; no exceptions cross
  * the ABI.  LMVD_EINVAL: bad configuration, null or misaligned (not 16-byte)
