@@ -1,0 +1,185 @@
+"""Parity at the full benchmark size: 512 x 385 x 512 modes on the 768 x 768
+grid, in the launch configuration the benchmark times (all planes in one
+batch), through the C ABI.
+
+The oracle cannot run a whole substep at this size, so the checks are
+  (a) properties that hold at any size, on every coefficient:
+      the RK2 stage-n update, the divergence-free and Omega2-reproducing m^d
+      (eq. md_recon), the curl-free direction of m^c (eq. mc_recon);
+  (b) values the oracle's own building blocks compute one by one on sampled
+      columns and points: the collocated A(k) system of m^c with its Robin
+      rows (eqs. phi_poisson, bc_both, CF_fourier) on sampled (l, n) columns,
+      and inverse transforms as direct sums at sampled grid points.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.bspline import SplineSpaces
+from paper_2206_09878_amd.workloads import make_inputs, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b, scale=None):
+    s = scale if scale is not None else np.abs(b).max()
+    return float(np.abs(a - b).max() / max(s, 1e-300))
+
+
+def hermitian(a):
+    nn = a.shape[1]
+    for ni in range(1, (nn + 1) // 2):
+        a[:, nn - ni, 0] = np.conj(a[:, ni, 0])
+    a[:, 0, 0] = a[:, 0, 0].real
+    return a
+
+
+def wavenumbers(w):
+    h = w.n3 // 2
+    n = np.concatenate([np.arange(0, h), np.arange(-(h - 1), 0)])
+    l = np.arange(w.n1 // 2)
+    return 2 * math.pi * l / w.L1, 2 * math.pi * n / w.L3, n, l
+
+
+@pytest.fixture(scope="module")
+def full():
+    import torch
+    from paper_2206_09878_amd.lmvd import Plan
+    assert torch.cuda.is_available()
+    w = workload("rt512")
+    p = Plan(w)
+    inp = make_inputs(w, seed=2, stage=0)
+    # the Rayleigh-Taylor initial state has m^d = 0; add a small broadband phi2, Omega2
+    rng = np.random.default_rng(11)
+    k1, k3, n, l = wavenumbers(w)
+    kap = np.sqrt(n[:, None] ** 2 + l[None, :] ** 2)
+    amp = np.where((kap >= 1) & (kap <= 32), np.maximum(kap, 1.0) ** (-5.0 / 3.0), 0.0)
+    prof = np.exp(-np.linspace(-2.0, 2.0, w.n2) ** 2)
+    prof[0] = prof[-1] = 0.0
+    def field():
+        xi = rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape)
+        return hermitian(1e-3 * xi * amp[None] * prof[:, None, None])
+    phi2, omega2 = field(), field()
+    z, m1bar, m3bar = inp["z"], inp["m1bar"], inp["m3bar"]
+    d = dict(phi2=p.to_dev(phi2), omega2=p.to_dev(omega2), z=p.to_dev(z), m1bar=p.to_dev(m1bar),
+             m3bar=p.to_dev(m3bar))
+    hist = [p.to_dev(h) for h in inp["hist"]]
+    z_out = p.empty()
+    rhs = {"phi2": p.empty(), "omega2": p.empty(),
+           "m1bar": torch.empty(w.n2, dtype=torch.float64, device="cuda"),
+           "m3bar": torch.empty(w.n2, dtype=torch.float64, device="cuda")}
+    zt = p.empty()
+    md = [p.empty(), p.empty(True), p.empty()]
+    mc = [p.empty(), p.empty(True), p.empty()]
+    print("rt512 full-size substep, stage n", flush=True)
+    p.substep(0, d["phi2"], d["omega2"], d["z"], d["m1bar"], d["m3bar"], z_out=z_out, hist=hist, rhs_out=rhs,
+              zt_out=zt, md=md, mc=mc)
+    torch.cuda.synchronize()
+    h = lambda t: t.detach().cpu().numpy()
+    out = dict(w=w, plan=p, phi2=phi2, omega2=omega2, z=z, m1bar=m1bar, m3bar=m3bar,
+               phi2_out=h(d["phi2"]), omega2_out=h(d["omega2"]), z_out=h(z_out), m1bar_out=h(d["m1bar"]),
+               m3bar_out=h(d["m3bar"]), zt=h(zt), rhs={k: h(v) for k, v in rhs.items()},
+               md=[h(x) for x in md], mc=[h(x) for x in mc], sp=SplineSpaces(w.breakpoints, w.order))
+    del d, hist, z_out, rhs, zt, md, mc
+    torch.cuda.empty_cache()
+    return out
+
+
+def test_outputs_finite(full):
+    for k in ("phi2_out", "omega2_out", "z_out", "zt", "m1bar_out", "m3bar_out"):
+        assert np.isfinite(full[k]).all(), k
+
+
+def test_rk2_stage_n_update(full):
+    """X' = X^n + dt/2 R^n for every state field (explicit midpoint, first stage)."""
+    w = full["w"]
+    hdt = 0.5 * w.dt
+    assert rel(full["z_out"], full["z"] + hdt * full["zt"]) < 1e-14
+    for k in ("phi2", "omega2"):
+        a = full[k + "_out"].copy()
+        b = full[k] + hdt * full["rhs"][k]
+        a[:, 0, 0] = b[:, 0, 0] = 0.0   # (0,0) of phi2 and Omega2 is not part of the state
+        assert rel(a, b) < 1e-14, k
+    for k in ("m1bar", "m3bar"):
+        assert rel(full[k + "_out"], full[k] + hdt * full["rhs"][k]) < 1e-14, k
+
+
+def test_md_divergence_free_and_vorticity(full):
+    """i k1 m1 + D* c + i k3 m3 = 0 and i k3 m1 - i k1 m3 = Omega2 on every coefficient (k != 0)."""
+    w, sp = full["w"], full["sp"]
+    m1, c, m3 = full["md"]
+    k1, k3, _, _ = wavenumbers(w)
+    K1 = k1[None, None, :]
+    K3 = k3[None, :, None]
+    Dc = np.tensordot(sp.Dstar, c, axes=(1, 0))
+    div = 1j * K1 * m1 + Dc + 1j * K3 * m3
+    scale = np.abs(1j * K1 * m1).max() + np.abs(Dc).max()
+    div[:, 0, 0] = 0.0
+    assert np.abs(div).max() / scale < 1e-12
+    om = 1j * K3 * m1 - 1j * K1 * m3
+    om[:, 0, 0] = full["omega2"][:, 0, 0]
+    assert rel(om, full["omega2"]) < 1e-12
+    # plane mean: (<m>1, 0, <m>3)
+    assert rel(m1[:, 0, 0].real, full["m1bar"]) < 1e-15 and np.abs(c[:, 0, 0]).max() == 0.0
+
+
+def test_mc_collocated_system_on_sampled_columns(full):
+    """m^c direction k3 m1 = k1 m3 everywhere; on sampled columns, rho_t recovered
+    from the exact mass equation makes c solve A(k) c = -G1 rho_t with Robin rows."""
+    w, sp = full["w"], full["sp"]
+    m1, c, m3 = full["mc"]
+    k1, k3, n, l = wavenumbers(w)
+    K1 = k1[None, None, :]
+    K3 = k3[None, :, None]
+    cur = K3 * m1 - K1 * m3
+    assert np.abs(cur).max() / max(np.abs(K1 * m1).max(), 1e-300) < 1e-13
+    rng = np.random.default_rng(5)
+    cols = [(1, 0), (0, 1), (0, w.n3 - 2), (w.n1 // 2 - 1, w.n3 // 2 - 1), (w.n1 // 2 - 1, w.n3 // 2),
+            (7, 3)] + [(int(rng.integers(0, w.n1 // 2)), int(rng.integers(0, w.n3 - 1))) for _ in range(40)]
+    Es0, Es1, Es2 = sp.Es
+    G1 = sp.G[1]
+    n2 = w.n2
+    worst = 0.0
+    for (li, ni) in cols:
+        a, b = k1[li], k3[ni]
+        k = math.hypot(a, b)
+        if k == 0.0:
+            continue
+        mpar = (a * m1[:, ni, li] + b * m3[:, ni, li]) / k
+        cc = c[:, ni, li]
+        rhot = -(1j * k * mpar + sp.Dstar @ cc)
+        A = Es2 - k * k * Es0
+        lhs = A @ cc
+        rhs = -(G1 @ rhot)
+        res = np.abs(lhs[1:n2] - rhs[1:n2]).max() / (np.abs(A).max() * np.abs(cc).max() + np.abs(rhs).max())
+        rob0 = abs(k * Es0[0] @ cc - Es1[0] @ cc) / (k * np.abs(cc).max() + 1e-300)
+        rob1 = abs(k * Es0[n2] @ cc + Es1[n2] @ cc) / (k * np.abs(cc).max() + 1e-300)
+        worst = max(worst, res, rob0, rob1)
+    assert worst < 1e-11, worst
+    # plane mean: no m1, m3; <m2>(+L2/2) = 0
+    assert np.abs(m1[:, 0, 0]).max() == 0.0 and np.abs(m3[:, 0, 0]).max() == 0.0
+    assert abs(c[-1, 0, 0]) == 0.0
+
+
+def test_inverse_transform_direct_sums_and_round_trip(full):
+    """Physical values on all 385 planes at sampled grid points equal the direct
+    Fourier sums of the retained modes; the forward transform returns the modes."""
+    import torch
+    w, p = full["w"], full["plan"]
+    rng = np.random.default_rng(3)
+    V = hermitian(rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape))
+    phys = p.to_physical(p.to_dev(V))
+    back = p.to_spectral(phys)
+    torch.cuda.synchronize()
+    P = phys.cpu().numpy()
+    assert rel(back.cpu().numpy(), V) < 1e-12
+    _, _, n, l = wavenumbers(w)
+    wl = np.where(l == 0, 1.0, 2.0)
+    worst = 0.0
+    for _ in range(24):
+        j, b, a = int(rng.integers(0, w.n2)), int(rng.integers(0, w.m3)), int(rng.integers(0, w.m1))
+        ph = np.exp(2j * math.pi * (n[:, None] * b / w.m3 + l[None, :] * a / w.m1))
+        val = float(np.sum(wl[None, :] * (V[j] * ph).real))
+        worst = max(worst, abs(P[j, b, a] - val) / np.abs(V[j]).sum())
+    assert worst < 1e-13, worst
