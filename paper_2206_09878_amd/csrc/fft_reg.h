@@ -300,26 +300,34 @@ __device__ __forceinline__ void stage_lt(double2* v, int tl, const double2* tws)
   }
 }
 
-template <int N, int T, int Ra, int NSa, int Rb, int PADDIV>
+// BLK: the T threads of a line are spread over the block (not consecutive
+// lanes), so every ordering point is a block barrier.
+template <bool BLK, int T>
+__device__ __forceinline__ void xsync() {
+  if constexpr (BLK) __syncthreads();
+  else line_sync<T>();
+}
+
+template <int N, int T, int Ra, int NSa, int Rb, int PADDIV, bool BLK = false>
 __device__ __forceinline__ void exchange_split(double2* v, double* lds, int base, int tl) {
   constexpr int E = N / T;
   double tmp[E];
-  line_sync<T>();
+  xsync<BLK, T>();
 #pragma unroll
   for (int c = 0; c < E / Ra; ++c)
 #pragma unroll
     for (int r = 0; r < Ra; ++r) lds[base + padded<PADDIV>(out_pos<N, T, Ra, NSa>(tl, c, r))] = v[c * Ra + r].x;
-  line_sync<T>();
+  xsync<BLK, T>();
 #pragma unroll
   for (int c = 0; c < E / Rb; ++c)
 #pragma unroll
     for (int r = 0; r < Rb; ++r) tmp[c * Rb + r] = lds[base + padded<PADDIV>(in_pos<N, T, Rb>(tl, c, r))];
-  line_sync<T>();
+  xsync<BLK, T>();
 #pragma unroll
   for (int c = 0; c < E / Ra; ++c)
 #pragma unroll
     for (int r = 0; r < Ra; ++r) lds[base + padded<PADDIV>(out_pos<N, T, Ra, NSa>(tl, c, r))] = v[c * Ra + r].y;
-  line_sync<T>();
+  xsync<BLK, T>();
 #pragma unroll
   for (int c = 0; c < E / Rb; ++c)
 #pragma unroll
@@ -329,7 +337,7 @@ __device__ __forceinline__ void exchange_split(double2* v, double* lds, int base
     }
 }
 
-template <int N, int T, int DIR, int R0, int R1, int R2, int R3, int PADDIV>
+template <int N, int T, int DIR, int R0, int R1, int R2, int R3, int PADDIV, bool BLK = false>
 __device__ __forceinline__ void run_split(double2* v, double* lds, int base, int tl, const double2* twl) {
   static_assert(R0 * R1 * R2 * R3 == N, "radices must multiply to N");
   static_assert((N / T) % R0 == 0 && (N / T) % R1 == 0 && (N / T) % R2 == 0 && (N / T) % R3 == 0,
@@ -337,15 +345,15 @@ __device__ __forceinline__ void run_split(double2* v, double* lds, int base, int
   using ST = StageTw<R0, R1, R2, R3>;
   stage_lt<N, T, DIR, R0, 1>(v, tl, twl);
   if constexpr (R1 > 1) {
-    exchange_split<N, T, R0, 1, R1, PADDIV>(v, lds, base, tl);
+    exchange_split<N, T, R0, 1, R1, PADDIV, BLK>(v, lds, base, tl);
     stage_lt<N, T, DIR, R1, ST::NS1>(v, tl, twl + ST::OFF1);
   }
   if constexpr (R2 > 1) {
-    exchange_split<N, T, R1, ST::NS1, R2, PADDIV>(v, lds, base, tl);
+    exchange_split<N, T, R1, ST::NS1, R2, PADDIV, BLK>(v, lds, base, tl);
     stage_lt<N, T, DIR, R2, ST::NS2>(v, tl, twl + ST::OFF2);
   }
   if constexpr (R3 > 1) {
-    exchange_split<N, T, R2, ST::NS2, R3, PADDIV>(v, lds, base, tl);
+    exchange_split<N, T, R2, ST::NS2, R3, PADDIV, BLK>(v, lds, base, tl);
     stage_lt<N, T, DIR, R3, ST::NS3>(v, tl, twl + ST::OFF3);
   }
 }

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lmvd.h"
@@ -42,29 +43,37 @@ enum Mult { MU_ONE = 0, MU_IK1 = 1, MU_IK3 = 2, MU_K1K = 3, MU_K3K = 4 };
 enum Phase { PH_RZ = 0, PH_RHOT = 1, PH_L = 2, PH_VEL = 3, PH_TOPHYS = 5, PH_FROMPHYS = 6 };
 enum Epi { EPI_STORE = 0, EPI_ADD = 1, EPI_ADD_ZUPDATE = 2 };
 
+// Read-only plan tables live in the constant address space: the kernels read
+// them with indices that are uniform across a wavefront (row numbers), which
+// lets the compiler use scalar loads for them.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+inline cptr<T> to_cptr(const void* p) { return (cptr<T>)(p); }
+
 struct DevPlan {
   int n2, p, nl, nn, n3, m1, m3, hx;
   double dt, mu, rhoD, g, rho_l, rho_h, inv_rlrh, drho;
   // row tables
-  const int* ev_lo;        // [kNumEv][n2]
-  const double* ev_w;      // [kNumEv][n2][kMaxW]
-  const int* gs_lo;        // [2][n2+1]   G0, G1 at tau*
-  const double* gs_w;
-  const int* es_lo;        // [3][n2+1]   E*_0, E*_1, E*_2 at tau*
-  const double* es_w;
-  const double* dstar;     // [n2]
-  const double* lu_l;      // [3][n2][kMaxBand]
-  const double* lu_u;      // [3][n2][kMaxBand+1]
-  const double* lu_uinv;   // [3][n2]
+  cptr<int> ev_lo;        // [kNumEv][n2]
+  cptr<double> ev_w;      // [kNumEv][n2][kMaxW]
+  cptr<int> gs_lo;        // [2][n2+1]   G0, G1 at tau*
+  cptr<double> gs_w;
+  cptr<int> es_lo;        // [3][n2+1]   E*_0, E*_1, E*_2 at tau*
+  cptr<double> es_w;
+  cptr<double> dstar;     // [n2]
+  cptr<double> lu_l;      // [3][n2][kMaxBand]
+  cptr<double> lu_u;      // [3][n2][kMaxBand+1]
+  cptr<double> lu_uinv;   // [3][n2]
   const double* k1;        // [nl]
   const double* k3;        // [nn]
-  const int* emit_first;   // [n2] first E0 row whose band starts at row i
-  const int* emit_cnt;     // [n2] number of such rows
-  const int* g1e_first;    // [n2] first interior tau* row whose G1 band starts at B row j
-  const int* g1e_cnt;      // [n2]
-  const int* asc_first;    // [n2+1] first tau row whose last F0/F1 column is B* row j
-  const int* asc_cnt;      // [n2+1]
-  const double* asc_w;     // [2][n2][kMaxW] F0, F1 weights of c_{last - q}
+  cptr<int> emit_first;   // [n2] first E0 row whose band starts at row i
+  cptr<int> emit_cnt;     // [n2] number of such rows
+  cptr<int> g1e_first;    // [n2] first interior tau* row whose G1 band starts at B row j
+  cptr<int> g1e_cnt;      // [n2]
+  cptr<int> asc_first;    // [n2+1] first tau row whose last F0/F1 column is B* row j
+  cptr<int> asc_cnt;      // [n2+1]
+  cptr<double> asc_w;     // [2][n2][kMaxW] F0, F1 weights of c_{last - q}
   const double* fac;       // bottom-up factors of A(k) per (l, |n|) pair: [n2+1][slots][npairs]
   FftDev fz, fx;
   const double2* xtw;      // [hx] exp(-2 pi i k / m1)
@@ -117,8 +126,8 @@ __device__ __forceinline__ double2 eval_at(const DevPlan& P, int kind, const dou
   const int rows = (kind == EV_F0) ? P.n2 + 1 : P.n2;
   const int kk = (kind == EV_LAP) ? EV_E2 : kind;
   const int lo = P.ev_lo[kk * P.n2 + j];
-  const double* w = P.ev_w + (size_t(kk) * P.n2 + j) * kMaxW;
-  const double* w0 = P.ev_w + (size_t(EV_E0) * P.n2 + j) * kMaxW;
+  const auto w = P.ev_w + (size_t(kk) * P.n2 + j) * kMaxW;
+  const auto w0 = P.ev_w + (size_t(EV_E0) * P.n2 + j) * kMaxW;
   double2 acc = zero2(), acc0 = zero2();
 #pragma unroll
   for (int q = 0; q < kMaxW; ++q) {
@@ -402,7 +411,7 @@ struct RowWindow {
       ++base;
     }
   }
-  __device__ __forceinline__ double2 dot(const double* __restrict__ wt) const {
+  __device__ __forceinline__ double2 dot(cptr<double> wt) const {
     double2 acc = zero2();
 #pragma unroll
     for (int q = 0; q < kMaxW; ++q) acc = fma2(wt[q], w[q], acc);
@@ -448,7 +457,7 @@ __global__ void __launch_bounds__(kThreads) k_values(DevPlan P, const double2* _
   if (cs) wc.init(cs, ncol, c, n2 + 1);
   for (int i = 0; i < n2; ++i) {
     const size_t e = size_t(i) * ncol + c;
-    const double* w0 = P.ev_w + size_t(i) * kMaxW;
+    const auto w0 = P.ev_w + size_t(i) * kMaxW;
     if (a) {
       wa.advance(a, ncol, c, n2, P.ev_lo[i]);
       Va[e] = wa.dot(w0);
@@ -499,7 +508,7 @@ __global__ void __launch_bounds__(kThreads) k_guess_v(DevPlan P, const double2* 
       if (r < n2) zt[size_t(r) * ncol + c] = w[kMaxW - 1];
       ++base;
     }
-    const double* w0 = P.ev_w + size_t(i) * kMaxW;
+    const auto w0 = P.ev_w + size_t(i) * kMaxW;
     double2 acc = zero2();
 #pragma unroll
     for (int q = 0; q < kMaxW; ++q) acc = fma2(w0[q], w[q], acc);
@@ -631,6 +640,100 @@ __global__ void __launch_bounds__(kThreads) k_zfwd_r(DevPlan P, const double2* _
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = lok ? in[size_t(tl + T * r) * nl] : zero2();
   rf::run<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, ll * ZS::STRIDE, tl, P.fz.tw);
+  if (lok) {
+    double2* out = V.v[g] + size_t(j0 + jj) * nn * nl + l;
+#pragma unroll
+    for (int c = 0; c < E / RL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int pos = tl + T * c + r * (N / RL);
+        if (pos < h3) out[size_t(pos) * nl] = v[c * RL + r];
+        else if (pos >= h3 + pad) out[size_t(pos - pad) * nl] = v[c * RL + r];
+      }
+  }
+}
+
+// z kernels with one 64-thread group per line (12 points per thread) and 8
+// lines per 512-thread block, the line index lane-fastest so that loads and
+// stores of a wavefront cover 8 consecutive l (coalesced); exchanges move real
+// and imaginary planes through LDS under block barriers, stage twiddles come
+// from per-stage LDS tables.  Only the 768-point line has such a plan.
+constexpr int kZWThreads = 512;
+template <int N>
+struct ZPlanW;
+template <>
+struct ZPlanW<768> {
+  static constexpr int T = 64, R0 = 12, R1 = 4, R2 = 4, R3 = 4, PAD = 12, LG = 8;
+  static constexpr int E = 768 / 64, RL = 4;
+  static constexpr int STRIDE = 834;  // doubles per line: 768 + 768/12 padded to 2 mod 32
+};
+
+template <int N, bool EXACT>
+__global__ void __launch_bounds__(kZWThreads) k_zinv_w(DevPlan P, EvalArgs A, double2* __restrict__ zbuf, int j0,
+                                                      int pb) {
+  using ZP = ZPlanW<N>;
+  constexpr int T = ZP::T, E = ZP::E, LG = ZP::LG, RL = ZP::RL;
+  constexpr int NNX = 2 * N / 3 - 1, H3X = (NNX + 1) / 2, PADX = N - NNX;
+  extern __shared__ double lds_d[];
+  double2* twl = reinterpret_cast<double2*>(lds_d + LG * ZP::STRIDE);
+  const int tid = threadIdx.x;
+  const int ll = tid % LG, tl = tid / LG;
+  const int f = blockIdx.z, jj = blockIdx.y, j = j0 + jj, l = blockIdx.x * LG + ll;
+  const int nn = EXACT ? NNX : P.nn, nl = P.nl;
+  const int h3 = EXACT ? H3X : (nn + 1) / 2, pad = EXACT ? PADX : N - nn;
+  rf::fill_stage_tw<N, ZP::R0, ZP::R1, ZP::R2, ZP::R3>(twl, P.fz.tw, tid, kZWThreads);
+  const EvalIn in = A.in[f];
+  const bool lok = l < nl;
+  const size_t ncol = size_t(nn) * nl;
+  const double k1 = (lok && in.ma == MU_IK1) ? P.k1[l] : 0.0;
+  const double2* src = in.a + size_t(j) * ncol + (lok ? l : 0);
+  double2 v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int pos = tl + T * r;
+    const bool always_pad = EXACT && (T * r >= H3X) && (T * r + T - 1 < H3X + PADX);
+    double2 val = zero2();
+    if (!always_pad && lok && (pos < h3 || pos >= h3 + pad)) {
+      const int ni = pos < h3 ? pos : pos - pad;
+      val = src[size_t(ni) * nl];
+      if (in.b) val = cadd(val, in.b[size_t(j) * ncol + size_t(ni) * nl + l]);
+    }
+    v[r] = val;
+  }
+  if (in.ma == MU_IK1) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = make_double2(-k1 * v[r].y, k1 * v[r].x);
+  }
+  __syncthreads();  // twiddle tables
+  rf::run_split<N, T, 1, ZP::R0, ZP::R1, ZP::R2, ZP::R3, ZP::PAD, true>(v, lds_d, ll * ZP::STRIDE, tl, twl);
+  if (lok) {
+    double2* out = zbuf + (size_t(f) * pb + jj) * size_t(N) * nl + l;
+#pragma unroll
+    for (int c = 0; c < E / RL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) out[size_t(tl + T * c + r * (N / RL)) * nl] = v[c * RL + r];
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kZWThreads) k_zfwd_w(DevPlan P, const double2* __restrict__ obuf, OutPtrs V,
+                                                      int j0, int pb) {
+  using ZP = ZPlanW<N>;
+  constexpr int T = ZP::T, E = ZP::E, LG = ZP::LG, RL = ZP::RL;
+  extern __shared__ double lds_d[];
+  double2* twl = reinterpret_cast<double2*>(lds_d + LG * ZP::STRIDE);
+  const int tid = threadIdx.x;
+  const int ll = tid % LG, tl = tid / LG;
+  const int g = blockIdx.z, jj = blockIdx.y, l = blockIdx.x * LG + ll;
+  const int nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = N - nn;
+  rf::fill_stage_tw<N, ZP::R0, ZP::R1, ZP::R2, ZP::R3>(twl, P.fz.tw, tid, kZWThreads);
+  const bool lok = l < nl;
+  const double2* in = obuf + (size_t(g) * pb + jj) * size_t(N) * nl + (lok ? l : 0);
+  double2 v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = lok ? in[size_t(tl + T * r) * nl] : zero2();
+  __syncthreads();  // twiddle tables
+  rf::run_split<N, T, -1, ZP::R0, ZP::R1, ZP::R2, ZP::R3, ZP::PAD, true>(v, lds_d, ll * ZP::STRIDE, tl, twl);
   if (lok) {
     double2* out = V.v[g] + size_t(j0 + jj) * nn * nl + l;
 #pragma unroll
@@ -809,9 +912,9 @@ __device__ __forceinline__ void pair_out(const DevPlan& P, int q, const double (
 // output pair u + i v with transform W splits as U_k = (W_k + conj W_{N-k})/2,
 // V_k = (W_k - conj W_{N-k})/(2i).  grid (ceil(m3/BG), planes), block BG*T.
 template <int PH, int N>
-__global__ void __launch_bounds__(kThreads) k_xpair(DevPlan P, const double2* __restrict__ zbuf,
-                                                   double2* __restrict__ obuf, int pb, double* phys_out,
-                                                   const double* phys_in, int j0, double* __restrict__ aux) {
+__device__ __forceinline__ void xpair_body(const DevPlan& P, const double2* __restrict__ zbuf,
+                                           double2* __restrict__ obuf, int pb, double* phys_out,
+                                           const double* phys_in, int j0, double* __restrict__ aux) {
   using LP = XPlan<N>;
   using S = Pair<PH>;
   constexpr int T = LP::T, E = LP::E, RL = LP::RL, EL = E / RL, BG = LP::BG, NL = N / 3;
@@ -942,6 +1045,22 @@ __global__ void __launch_bounds__(kThreads) k_xpair(DevPlan P, const double2* __
   }
 }
 
+// Kernels of the x-pass.  The u, rho, C_ij pass keeps four values per point
+// across five output transforms; its register budget is capped at two waves
+// per SIMD (the rest spills), which measured faster than one wave per SIMD.
+template <int PH, int N>
+__global__ void __launch_bounds__(kThreads) k_xpair(DevPlan P, const double2* __restrict__ zbuf,
+                                                   double2* __restrict__ obuf, int pb, double* phys_out,
+                                                   const double* phys_in, int j0, double* __restrict__ aux) {
+  xpair_body<PH, N>(P, zbuf, obuf, pb, phys_out, phys_in, j0, aux);
+}
+template <int PH, int N>
+__global__ void __launch_bounds__(kThreads, 2) k_xpair_w2(DevPlan P, const double2* __restrict__ zbuf,
+                                                         double2* __restrict__ obuf, int pb, double* phys_out,
+                                                         const double* phys_in, int j0, double* __restrict__ aux) {
+  xpair_body<PH, N>(P, zbuf, obuf, pb, phys_out, phys_in, j0, aux);
+}
+
 // ---------------------------------------------------------------------------
 // column kernel: projection values -> B coefficients with a shared no-pivot LU
 // (kind 0 interpolation, 1 Dirichlet rows, 2 Neumann rows).  One thread per
@@ -956,9 +1075,9 @@ __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const do
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const int n2 = P.n2;
-  const double* L = P.lu_l + size_t(kind) * n2 * kMaxBand;
-  const double* U = P.lu_u + size_t(kind) * n2 * (kMaxBand + 1);
-  const double* Ui = P.lu_uinv + size_t(kind) * n2;
+  const auto L = P.lu_l + size_t(kind) * n2 * kMaxBand;
+  const auto U = P.lu_u + size_t(kind) * n2 * (kMaxBand + 1);
+  const auto Ui = P.lu_uinv + size_t(kind) * n2;
   double2 ring[kMaxBand];
 #pragma unroll
   for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
@@ -994,13 +1113,13 @@ __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const do
       win[0] = fin;
       const int first = P.emit_first[i], cnt = P.emit_cnt[i];
       for (int t = 0; t < cnt; ++t) {
-        const double* w0 = P.ev_w + size_t(first + t) * kMaxW;
+        const auto w0 = P.ev_w + size_t(first + t) * kMaxW;
         double2 acc = zero2();
 #pragma unroll
         for (int q = 0; q < kMaxW; ++q) acc = fma2(w0[q], win[q], acc);
         vals_out[size_t(first + t) * ncol + c] = acc;
         if (vals_out1) {
-          const double* w1 = P.ev_w + (size_t(n2) + first + t) * kMaxW;
+          const auto w1 = P.ev_w + (size_t(n2) + first + t) * kMaxW;
           double2 acc1 = zero2();
 #pragma unroll
           for (int q = 0; q < kMaxW; ++q) acc1 = fma2(w1[q], win[q], acc1);
@@ -1061,7 +1180,7 @@ struct RowWin {
       ++base;
     }
   }
-  __device__ __forceinline__ double2 dot(const double* __restrict__ wt) const {
+  __device__ __forceinline__ double2 dot(cptr<double> wt) const {
     double2 acc = zero2();
 #pragma unroll
     for (int q = 0; q < W; ++q) acc = fma2(wt[q], w[q], acc);
@@ -1082,9 +1201,9 @@ __global__ void __launch_bounds__(kThreads) k_flux(DevPlan P, const double2* __r
   if (c >= ncol) return;
   const double k1 = P.k1[c % nl], k3 = P.k3[c / nl], ksq = k1 * k1 + k3 * k3;
   const double mu = P.mu, th = (2.0 / 3.0) * P.mu;
-  const double* L = P.lu_l;
-  const double* U = P.lu_u;
-  const double* Ui = P.lu_uinv;
+  const auto L = P.lu_l;
+  const auto U = P.lu_u;
+  const auto Ui = P.lu_uinv;
   {
     RowWin<W> w1, w2, w3;
     w1.init(u1, ncol, c, n2);
@@ -1098,8 +1217,8 @@ __global__ void __launch_bounds__(kThreads) k_flux(DevPlan P, const double2* __r
       w1.advance(u1, ncol, c, n2, lo);
       w2.advance(u2, ncol, c, n2, lo);
       w3.advance(u3, ncol, c, n2, lo);
-      const double* e0 = P.ev_w + size_t(i) * kMaxW;
-      const double* e1 = P.ev_w + (size_t(n2) + i) * kMaxW;
+      const auto e0 = P.ev_w + size_t(i) * kMaxW;
+      const auto e1 = P.ev_w + (size_t(n2) + i) * kMaxW;
       double2 s0[3] = {w1.dot(e0), w2.dot(e0), w3.dot(e0)};
       double2 s1[3] = {w1.dot(e1), w2.dot(e1), w3.dot(e1)};
       // d[a][b] = d u_a / d x_b at tau_i
@@ -1170,9 +1289,9 @@ __global__ void __launch_bounds__(kThreads) k_flux(DevPlan P, const double2* __r
     const int first = P.emit_first[i], cnt = P.emit_cnt[i];
     for (int t = 0; t < cnt; ++t) {
       const int r = first + t;
-      const double* e0 = P.ev_w + size_t(r) * kMaxW;
-      const double* e1 = P.ev_w + (size_t(n2) + r) * kMaxW;
-      const double* e2 = P.ev_w + (size_t(2 * n2) + r) * kMaxW;
+      const auto e0 = P.ev_w + size_t(r) * kMaxW;
+      const auto e1 = P.ev_w + (size_t(n2) + r) * kMaxW;
+      const auto e2 = P.ev_w + (size_t(2 * n2) + r) * kMaxW;
       double2 a0 = zero2(), a1 = zero2(), b0 = zero2(), b1 = zero2(), b2 = zero2(), c0 = zero2(), c1 = zero2();
 #pragma unroll
       for (int q = 0; q < W; ++q) {
@@ -1271,11 +1390,11 @@ __global__ void __launch_bounds__(kThreads) k_solveA(DevPlan P, const double2* _
 #pragma unroll
     for (int q = 0; q < UP; ++q) uw[m][q] = 0.0;
   }
-  const int* elo = P.es_lo;
-  const double* ew = P.es_w;
+  const auto elo = P.es_lo;
+  const auto ew = P.es_w;
   const int Ns = n2 + 1;
-  const double* Gw = P.gs_w + (MODE == 0 ? 0 : size_t(Ns) * kMaxW);
-  const int* Glo = P.gs_lo + (MODE == 0 ? 0 : Ns);
+  const auto Gw = P.gs_w + (MODE == 0 ? 0 : size_t(Ns) * kMaxW);
+  const auto Glo = P.gs_lo + (MODE == 0 ? 0 : Ns);
   const double gsign = (MODE == 0) ? 1.0 : -1.0;
   const size_t ustride = size_t(npairs);
   for (int i = 0; i < N; ++i) {
@@ -1299,7 +1418,7 @@ __global__ void __launch_bounds__(kThreads) k_solveA(DevPlan P, const double2* _
     double2 ra = zero2(), rb = zero2();
     if (!robin) {
       const int glo = Glo[i];
-      const double* gw = Gw + size_t(i) * kMaxW;
+      const auto gw = Gw + size_t(i) * kMaxW;
 #pragma unroll
       for (int q = 0; q < kMaxW; ++q) {
         const int r = glo + q;
@@ -1417,8 +1536,8 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
   }
   const double k = sqrt(ksq);
   const int Ns = n2 + 1;
-  const int* elo = P.es_lo;
-  const double* ew = P.es_w;
+  const auto elo = P.es_lo;
+  const auto ew = P.es_w;
   double piv[UA][LA];  // entries left of the diagonal of pivot rows i+1 .. i+UA
   double pinv[UA];
 #pragma unroll
@@ -1536,7 +1655,7 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
     for (int m = 0; m < UA; ++m) yr[m] = zero2();
     double2 cm = zero2();  // mean column: c_{j+1}
     yt[size_t(n2) * ncol + c] = zero2();  // Robin row n2: r = 0, nothing above it
-    const double* G1w = P.gs_w + size_t(N) * kMaxW;
+    const auto G1w = P.gs_w + size_t(N) * kMaxW;
     // multipliers of the next row of the bottom-up sweep (rows n2-1, n2-2, ..., 0 in turn)
     int inext = n2 - 1;
     double fm[UA];
@@ -1561,7 +1680,7 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
       const int first = P.g1e_first[j], cnt = P.g1e_cnt[j];
       for (int e = cnt - 1; e >= 0; --e) {
         const int i = first + e;  // == inext
-        const double* g = G1w + size_t(i) * kMaxW;
+        const auto g = G1w + size_t(i) * kMaxW;
         double2 r = zero2();
 #pragma unroll
         for (int q = 0; q < kMaxW; ++q) r = fma2(-g[q], win[q], r);
@@ -1624,8 +1743,8 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
       const int first = P.asc_first[i], cnt = P.asc_cnt[i];
       for (int e = 0; e < cnt; ++e) {
         const int row = first + e;
-        const double* w0 = P.asc_w + size_t(row) * kMaxW;
-        const double* w1 = P.asc_w + (size_t(n2) + row) * kMaxW;
+        const auto w0 = P.asc_w + size_t(row) * kMaxW;
+        const auto w1 = P.asc_w + (size_t(n2) + row) * kMaxW;
         double2 m2 = zero2(), f1 = zero2();
 #pragma unroll
         for (int q = 0; q < kMaxW; ++q) {
@@ -1666,9 +1785,9 @@ __global__ void __launch_bounds__(kThreads) k_rhs_fluct(
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   (void)nl;
-  const double* L = P.lu_l + size_t(1) * n2 * kMaxBand;
-  const double* U = P.lu_u + size_t(1) * n2 * (kMaxBand + 1);
-  const double* Ui = P.lu_uinv + size_t(1) * n2;
+  const auto L = P.lu_l + size_t(1) * n2 * kMaxBand;
+  const auto U = P.lu_u + size_t(1) * n2 * (kMaxBand + 1);
+  const auto Ui = P.lu_uinv + size_t(1) * n2;
   double2 rp[kMaxBand], ro[kMaxBand];
 #pragma unroll
   for (int m = 0; m < kMaxBand; ++m) rp[m] = ro[m] = zero2();
@@ -1743,14 +1862,14 @@ __global__ void k_rhs_mean(DevPlan P, const double2* __restrict__ T12, const dou
   double* mo = comp == 0 ? m1o : m3o;
   double* ro = comp == 0 ? r1o : r3o;
   double* y = ytmp + comp * n2;
-  const double* L = P.lu_l + size_t(2) * n2 * kMaxBand;
-  const double* U = P.lu_u + size_t(2) * n2 * (kMaxBand + 1);
-  const double* Ui = P.lu_uinv + size_t(2) * n2;
+  const auto L = P.lu_l + size_t(2) * n2 * kMaxBand;
+  const auto U = P.lu_u + size_t(2) * n2 * (kMaxBand + 1);
+  const auto Ui = P.lu_uinv + size_t(2) * n2;
   for (int i = 0; i < n2; ++i) {
     double b = 0.0;
     if (i > 0 && i < n2 - 1) {
       const int lo = P.ev_lo[n2 + i];
-      const double* w1 = P.ev_w + (size_t(1) * n2 + i) * kMaxW;
+      const auto w1 = P.ev_w + (size_t(1) * n2 + i) * kMaxW;
       for (int q = 0; q < kMaxW; ++q)
         if (lo + q < n2 && w1[q] != 0.0) b += w1[q] * T[size_t(lo + q) * ncol].x;
     }
@@ -1993,37 +2112,44 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
       return st;                            \
     }                                       \
   } while (0)
-  UP_OR_FAIL(lo, &D.ev_lo);
-  UP_OR_FAIL(w, &D.ev_w);
+  // tables read through the constant address space
+#define UP_TABLE(vec, member)                                      \
+  do {                                                             \
+    const std::remove_reference_t<decltype(vec[0])>* tmp_ = nullptr; \
+    UP_OR_FAIL(vec, &tmp_);                                        \
+    member = (decltype(member))(tmp_);                             \
+  } while (0)
+  UP_TABLE(lo, D.ev_lo);
+  UP_TABLE(w, D.ev_w);
   lo.clear();
   w.clear();
   cat_rows(H.G, 2, lo, w);
-  UP_OR_FAIL(lo, &D.gs_lo);
-  UP_OR_FAIL(w, &D.gs_w);
+  UP_TABLE(lo, D.gs_lo);
+  UP_TABLE(w, D.gs_w);
   lo.clear();
   w.clear();
   cat_rows(H.Es, 3, lo, w);
-  UP_OR_FAIL(lo, &D.es_lo);
-  UP_OR_FAIL(w, &D.es_w);
-  UP_OR_FAIL(H.dstar, &D.dstar);
+  UP_TABLE(lo, D.es_lo);
+  UP_TABLE(w, D.es_w);
+  UP_TABLE(H.dstar, D.dstar);
   std::vector<double> L, U, Ui;
   for (int k = 0; k < 3; ++k) {
     L.insert(L.end(), H.proj[k].lmul.begin(), H.proj[k].lmul.end());
     U.insert(U.end(), H.proj[k].u.begin(), H.proj[k].u.end());
     Ui.insert(Ui.end(), H.proj[k].uinv.begin(), H.proj[k].uinv.end());
   }
-  UP_OR_FAIL(L, &D.lu_l);
-  UP_OR_FAIL(U, &D.lu_u);
-  UP_OR_FAIL(Ui, &D.lu_uinv);
+  UP_TABLE(L, D.lu_l);
+  UP_TABLE(U, D.lu_u);
+  UP_TABLE(Ui, D.lu_uinv);
   UP_OR_FAIL(H.k1, &D.k1);
   UP_OR_FAIL(H.k3, &D.k3);
-  UP_OR_FAIL(H.emit_first, &D.emit_first);
-  UP_OR_FAIL(H.emit_cnt, &D.emit_cnt);
-  UP_OR_FAIL(H.g1e_first, &D.g1e_first);
-  UP_OR_FAIL(H.g1e_cnt, &D.g1e_cnt);
-  UP_OR_FAIL(H.asc_first, &D.asc_first);
-  UP_OR_FAIL(H.asc_cnt, &D.asc_cnt);
-  UP_OR_FAIL(H.asc_w, &D.asc_w);
+  UP_TABLE(H.emit_first, D.emit_first);
+  UP_TABLE(H.emit_cnt, D.emit_cnt);
+  UP_TABLE(H.g1e_first, D.g1e_first);
+  UP_TABLE(H.g1e_cnt, D.g1e_cnt);
+  UP_TABLE(H.asc_first, D.asc_first);
+  UP_TABLE(H.asc_cnt, D.asc_cnt);
+  UP_TABLE(H.asc_w, D.asc_w);
   {
     p->fac_la = p->fac_ua = (H.a_lower <= 7 && H.a_upper <= 7) ? 7 : 8;
     const size_t npairs = size_t(H.nl) * ((H.nn + 1) / 2);
@@ -2046,6 +2172,7 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   D.fx.tw = reinterpret_cast<const double2*>(tw);
   UP_OR_FAIL(H.xtw, &tw);
   D.xtw = reinterpret_cast<const double2*>(tw);
+#undef UP_TABLE
 #undef UP_OR_FAIL
   layout_workspace(p);
   *out = p;
@@ -2126,6 +2253,17 @@ static EvalIn ev(const void* a, int kind, int ma = MU_ONE, const void* b = nullp
 // register-FFT launches for the specialised sizes; false if the size has none
 template <int N>
 static void launch_zinv_t(lmvd_plan_s* p, hipStream_t s, const EvalArgs& A, double2* zbuf, int j0, int nb, int nin) {
+  if constexpr (N == 768) {
+    using ZP = ZPlanW<N>;
+    const dim3 g((p->H.nl + ZP::LG - 1) / ZP::LG, nb, nin);
+    const size_t lds = size_t(ZP::LG) * ZP::STRIDE * sizeof(double) +
+                       size_t(rf::StageTw<ZP::R0, ZP::R1, ZP::R2, ZP::R3>::SIZE) * sizeof(double2);
+    if (p->H.nn == 2 * N / 3 - 1)
+      hipLaunchKernelGGL((k_zinv_w<N, true>), g, dim3(kZWThreads), lds, s, p->D, A, zbuf, j0, p->pb);
+    else
+      hipLaunchKernelGGL((k_zinv_w<N, false>), g, dim3(kZWThreads), lds, s, p->D, A, zbuf, j0, p->pb);
+    return;
+  }
   using ZS = ZShape<N>;
   const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nin);
   const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
@@ -2137,6 +2275,14 @@ static void launch_zinv_t(lmvd_plan_s* p, hipStream_t s, const EvalArgs& A, doub
 template <int N>
 static void launch_zfwd_t(lmvd_plan_s* p, hipStream_t s, const double2* obuf, const OutPtrs& V, int j0, int nb,
                           int nout) {
+  if constexpr (N == 768) {
+    using ZP = ZPlanW<N>;
+    const dim3 g((p->H.nl + ZP::LG - 1) / ZP::LG, nb, nout);
+    const size_t lds = size_t(ZP::LG) * ZP::STRIDE * sizeof(double) +
+                       size_t(rf::StageTw<ZP::R0, ZP::R1, ZP::R2, ZP::R3>::SIZE) * sizeof(double2);
+    hipLaunchKernelGGL(k_zfwd_w<N>, g, dim3(kZWThreads), lds, s, p->D, obuf, V, j0, p->pb);
+    return;
+  }
   using ZS = ZShape<N>;
   const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nout);
   const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
@@ -2149,8 +2295,12 @@ static void launch_xpass_t(lmvd_plan_s* p, hipStream_t s, const double2* zbuf, d
   const dim3 g((p->H.cfg.m3 + LP::BG - 1) / LP::BG, nb);
   const size_t lds = size_t(LP::BG) * LP::STRIDE * sizeof(double) +
                      size_t(rf::StageTw<LP::R0, LP::R1, LP::R2, LP::R3>::SIZE) * sizeof(double2);
-  hipLaunchKernelGGL((k_xpair<PH, N>), g, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out, phys_in,
-                     j0, aux);
+  if constexpr (PH == PH_VEL)
+    hipLaunchKernelGGL((k_xpair_w2<PH, N>), g, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out,
+                       phys_in, j0, aux);
+  else
+    hipLaunchKernelGGL((k_xpair<PH, N>), g, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out, phys_in,
+                       j0, aux);
 }
 static bool zreg_size(int n) {
   return n == 768 || n == 192 || n == 144 || n == 96 || n == 72 || n == 48;
