@@ -1045,6 +1045,165 @@ __device__ __forceinline__ void xpair_body(const DevPlan& P, const double2* __re
   }
 }
 
+// x-pass with line pairing, for phases whose inputs are products of one field
+// with physical aux fields (L z_t and rho_t): every transform carries one
+// field on two neighbouring z lines b0, b1 as x(b0) + i x(b1), so a single
+// field costs half a transform.  Traits: input I is field I; in<I> folds the
+// point value x into the point state s (aux a, field stride fs); output Q is
+// field Q, formed by out<Q>.
+template <int PH>
+struct LineOp;
+template <>
+struct LineOp<PH_L> {  // inputs m1c, m2c, m3c:  L z_t = g . m^c (aux fields g1, g2, g3)
+  static constexpr int NP = 3, NQ = 1;
+  __device__ static constexpr int aux_field(int i) { return i; }
+  template <int I>
+  __device__ __forceinline__ static void in(double& s, double x, double a) {
+    if constexpr (I == 0) s = a * x;
+    else s += a * x;
+  }
+};
+template <>
+struct LineOp<PH_RHOT> {  // input z_t:  rho_t = f'(z) z_t (aux field f')
+  static constexpr int NP = 1, NQ = 1;
+  __device__ static constexpr int aux_field(int) { return 3; }
+  template <int I>
+  __device__ __forceinline__ static void in(double& s, double x, double a) {
+    s = a * x;
+  }
+};
+
+// a0, a1: the aux field of input i at point 0 of lines b0, b1 (point q at T q)
+template <class S, int I, int E, int RL, int T>
+__device__ __forceinline__ void line_in(int i, double (&s0)[E], double (&s1)[E], const double2* v,
+                                        const double* __restrict__ a0, const double* __restrict__ a1) {
+  if constexpr (I < S::NP) {
+    if (i == I) {
+      constexpr int EL = E / RL;
+#pragma unroll
+      for (int c = 0; c < EL; ++c)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const int q = c + r * EL;
+          S::template in<I>(s0[q], v[c * RL + r].x, a0[T * q]);
+          S::template in<I>(s1[q], v[c * RL + r].y, a1[T * q]);
+        }
+    } else {
+      line_in<S, I + 1, E, RL, T>(i, s0, s1, v, a0, a1);
+    }
+  }
+}
+
+template <int PH, int N>
+__global__ void __launch_bounds__(kThreads) k_xline(DevPlan P, const double2* __restrict__ zbuf,
+                                                   double2* __restrict__ obuf, int pb, int j0,
+                                                   const double* __restrict__ aux) {
+  using LP = XPlan<N>;
+  using S = LineOp<PH>;
+  constexpr int T = LP::T, E = LP::E, RL = LP::RL, EL = E / RL, BG = LP::BG, NL = N / 3;
+  static_assert(E == 12 && NL % T == 0, "x plans hold 12 points per thread, N/3 retained modes");
+  constexpr int QL = NL / T;
+  extern __shared__ double lds_d[];
+  double2* twl = reinterpret_cast<double2*>(lds_d + BG * LP::STRIDE);
+  const int tid = threadIdx.x;
+  const int tl = tid % T, grp = tid / T;
+  const int jj = blockIdx.y;
+  const int b0 = 2 * (blockIdx.x * BG + grp), b1 = b0 + 1;
+  const int M3 = P.m3;
+  const bool ok0 = b0 < M3, ok1 = b1 < M3;
+  const int c0 = ok0 ? b0 : 0, c1 = ok1 ? b1 : 0;
+  rf::fill_stage_tw<N, LP::R0, LP::R1, LP::R2, LP::R3>(twl, P.xtw, tid, BG * T);
+  __syncthreads();
+  const int base = grp * LP::STRIDE;
+  const size_t fs = size_t(P.n2) * M3 * P.m1;
+  const double* a0 = aux + (size_t(j0 + jj) * M3 + c0) * P.m1 + tl;
+  const double* a1 = aux + (size_t(j0 + jj) * M3 + c1) * P.m1 + tl;
+  double s0[E], s1[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) s0[q] = s1[q] = 0.0;
+  double2 v[E];
+#pragma unroll 1
+  for (int i = 0; i < S::NP; ++i) {
+    int tlx = tl, basex = base;
+    asm volatile("" : "+v"(tlx), "+v"(basex));
+    const double2* XA = zbuf + ((size_t(i) * pb + jj) * M3 + c0) * NL;
+    const double2* XB = zbuf + ((size_t(i) * pb + jj) * M3 + c1) * NL;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      double2 z = zero2();
+      if (!(T * r >= NL && T * r + T - 1 <= N - NL)) {
+        const int pos = tlx + T * r;
+        if (pos < NL) {
+          double2 xa = ok0 ? XA[pos] : zero2();
+          double2 xb = ok1 ? XB[pos] : zero2();
+          if (pos == 0) {
+            xa.y = 0.0;
+            xb.y = 0.0;
+          }
+          z = make_double2(xa.x - xb.y, xa.y + xb.x);
+        } else if (pos > N - NL) {
+          const double2 xa = ok0 ? XA[N - pos] : zero2();
+          const double2 xb = ok1 ? XB[N - pos] : zero2();
+          z = make_double2(xa.x + xb.y, xb.x - xa.y);
+        }
+      }
+      v[r] = z;
+    }
+    rf::run_split<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, basex, tlx, twl);
+    const double* ai0 = a0 + S::aux_field(i) * fs;
+    const double* ai1 = a1 + S::aux_field(i) * fs;
+    asm volatile("" : "+v"(ai0), "+v"(ai1));
+    line_in<S, 0, E, RL, T>(i, s0, s1, v, ai0, ai1);
+  }
+  const double scale = 1.0 / (double(P.m1) * double(M3));
+#pragma unroll 1
+  for (int q = 0; q < S::NQ; ++q) {
+    int tlx = tl, basex = base;
+    asm volatile("" : "+v"(tlx), "+v"(basex));
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = make_double2(s0[e], s1[e]);
+    rf::run_split<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, basex, tlx, twl);
+    double2* YA = obuf + ((size_t(q) * pb + jj) * M3 + c0) * NL;
+    double2* YB = obuf + ((size_t(q) * pb + jj) * M3 + c1) * NL;
+    // partners W_{N-k} of the retained k sit at point 0 and the points above N - N/3
+    double pre[QL], pim[QL];
+    rf::line_sync<T>();
+#pragma unroll
+    for (int c = 0; c < EL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int qq = c + r * EL;
+        if (qq == 0 || T * qq + T - 1 > N - NL) lds_d[basex + rf::padded<LP::PAD>(tlx + T * qq)] = v[c * RL + r].x;
+      }
+    rf::line_sync<T>();
+#pragma unroll
+    for (int qq = 0; qq < QL; ++qq) pre[qq] = lds_d[basex + rf::padded<LP::PAD>((N - tlx - T * qq) % N)];
+    rf::line_sync<T>();
+#pragma unroll
+    for (int c = 0; c < EL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int qq = c + r * EL;
+        if (qq == 0 || T * qq + T - 1 > N - NL) lds_d[basex + rf::padded<LP::PAD>(tlx + T * qq)] = v[c * RL + r].y;
+      }
+    rf::line_sync<T>();
+#pragma unroll
+    for (int qq = 0; qq < QL; ++qq) pim[qq] = lds_d[basex + rf::padded<LP::PAD>((N - tlx - T * qq) % N)];
+#pragma unroll
+    for (int c = 0; c < EL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int qq = c + r * EL;
+        if (qq < QL) {
+          const double2 w = v[c * RL + r];
+          const double hs = 0.5 * scale;
+          if (ok0) YA[tlx + T * qq] = make_double2(hs * (w.x + pre[qq]), hs * (w.y - pim[qq]));
+          if (ok1) YB[tlx + T * qq] = make_double2(hs * (w.y + pim[qq]), -hs * (w.x - pre[qq]));
+        }
+      }
+  }
+}
+
 // Kernels of the x-pass.  The u, rho, C_ij pass keeps four values per point
 // across five output transforms; its register budget is capped at two waves
 // per SIMD (the rest spills), which measured faster than one wave per SIMD.
@@ -2295,7 +2454,10 @@ static void launch_xpass_t(lmvd_plan_s* p, hipStream_t s, const double2* zbuf, d
   const dim3 g((p->H.cfg.m3 + LP::BG - 1) / LP::BG, nb);
   const size_t lds = size_t(LP::BG) * LP::STRIDE * sizeof(double) +
                      size_t(rf::StageTw<LP::R0, LP::R1, LP::R2, LP::R3>::SIZE) * sizeof(double2);
-  if constexpr (PH == PH_VEL)
+  if constexpr (PH == PH_L || PH == PH_RHOT) {
+    const dim3 g2((p->H.cfg.m3 + 2 * LP::BG - 1) / (2 * LP::BG), nb);
+    hipLaunchKernelGGL((k_xline<PH, N>), g2, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, j0, aux);
+  } else if constexpr (PH == PH_VEL)
     hipLaunchKernelGGL((k_xpair_w2<PH, N>), g, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out,
                        phys_in, j0, aux);
   else
