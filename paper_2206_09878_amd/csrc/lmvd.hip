@@ -74,7 +74,10 @@ struct DevPlan {
   cptr<int> asc_first;    // [n2+1] first tau row whose last F0/F1 column is B* row j
   cptr<int> asc_cnt;      // [n2+1]
   cptr<double> asc_w;     // [2][n2][kMaxW] F0, F1 weights of c_{last - q}
-  const double* fac;       // bottom-up factors of A(k) per (l, |n|) pair: [n2+1][slots][npairs]
+  const double* fac;       // bottom-up factors of A(k) per (l, |n|) pair: row i at slot fac_off[i], [slots][npairs]
+  cptr<int> fac_nm;       // [n2+1] multipliers of row i (rows i+1 .. i+nm)
+  cptr<int> fac_ns;       // [n2+1] entries of row i left of its diagonal
+  cptr<int> fac_off;      // [n2+1] first slot of row i
   FftDev fz, fx;
   const double2* xtw;      // [hx] exp(-2 pi i k / m1)
 };
@@ -1674,9 +1677,9 @@ __global__ void __launch_bounds__(kThreads) k_solveA(DevPlan P, const double2* _
 // ---------------------------------------------------------------------------
 // A(k) factors, computed once per plan: bottom-up elimination without
 // pivoting (rows n2 .. 0), one thread per pair (l, +-n) (A depends on k only).
-// Row i keeps UA multipliers (of rows i+1 .. i+UA), its LA entries left of
-// the diagonal and 1/pivot, stored at fac[((n2 - i) * S + slot) * npairs + t],
-// S = UA + LA + 1.  A(k) = E*_2 - k^2 E*_0 at interior tau*, Robin rows
+// Row i keeps nm_i <= UA multipliers (of rows i+1 .. i+nm_i), its ns_i <= LA
+// entries left of the diagonal and 1/pivot (nm_i, ns_i: the structure of A,
+// from the plan), at fac[(fac_off[i] + slot) * npairs + t].  A(k) = E*_2 - k^2 E*_0 at interior tau*, Robin rows
 // k m2 - m2' (bottom), k m2 + m2' (top) (eqs. phi_poisson, bc_both).
 template <int LA, int UA>
 __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __restrict__ fac) {
@@ -1687,10 +1690,12 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
   const int l = t % nl, pp = t / nl;
   const double k1 = P.k1[l], k3 = P.k3[pp];
   const double ksq = k1 * k1 + k3 * k3;
-  constexpr int W = LA + UA + 1, S = UA + LA + 1;
+  constexpr int W = LA + UA + 1;
   if (ksq == 0.0) {
-    for (int i = 0; i < N; ++i)
-      for (int q = 0; q < S; ++q) fac[(size_t(i) * S + q) * npairs + t] = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const int ns = P.fac_nm[i] + P.fac_ns[i] + 1;
+      for (int q = 0; q < ns; ++q) fac[(size_t(P.fac_off[i]) + q) * npairs + t] = 0.0;
+    }
     return;
   }
   const double k = sqrt(ksq);
@@ -1723,19 +1728,21 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
         a[w] = e2 - ksq * e0;
       }
     }
-    double* f = fac + size_t(N - 1 - i) * S * npairs + t;
+    const int nm = P.fac_nm[i], ns = P.fac_ns[i];
+    double* f = fac + size_t(P.fac_off[i]) * npairs + t;
     // eliminate columns i+UA .. i+1 with pivot rows i+UA .. i+1 (farthest first)
 #pragma unroll
     for (int m = UA; m >= 1; --m) {
       const double lm = a[LA + m] * pinv[m - 1];
 #pragma unroll
       for (int q = 1; q <= LA; ++q) a[LA + m - q] -= lm * piv[m - 1][q - 1];
-      f[size_t(m - 1) * npairs] = lm;
+      if (m <= nm) f[size_t(m - 1) * npairs] = lm;
     }
     const double dinv = 1.0 / a[LA];
 #pragma unroll
-    for (int q = 1; q <= LA; ++q) f[size_t(UA + q - 1) * npairs] = a[LA - q];
-    f[size_t(UA + LA) * npairs] = dinv;
+    for (int q = 1; q <= LA; ++q)
+      if (q <= ns) f[size_t(nm + q - 1) * npairs] = a[LA - q];
+    f[size_t(nm + ns) * npairs] = dinv;
 #pragma unroll
     for (int m = UA - 1; m > 0; --m) {
       pinv[m] = pinv[m - 1];
@@ -1764,7 +1771,7 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
 // Plane mean (k = 0): D* c = -<rho_t>, c_top = 0, m1 = m3 = 0.
 // With d1 (final iterate) the m^d values are added and the coefficients
 // c2 = c, mparc = (i/k)(rho_t + D* c) and rhoc = rho_t are written.
-template <int LA, int UA>
+template <int LA, int UA, int LB>
 __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __restrict__ vals, double2* yp,
                                                 double2* yt, const double2* __restrict__ d1,
                                                 const double2* __restrict__ d2, const double2* __restrict__ d3,
@@ -1783,24 +1790,23 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
   const double k1 = P.k1[l], k3 = P.k3[ni], ksq = k1 * k1 + k3 * k3;
   const bool mean = (ksq == 0.0);
   const double ik = mean ? 0.0 : 1.0 / sqrt(ksq);
-  constexpr int S = UA + LA + 1;
   const double* fac = P.fac + pr;
   // Every sweep loads the operands of its next row one step ahead: the loads
   // do not depend on the recurrence, so their latency overlaps the current row.
   // 1. ascending sweep of the interpolation projection
   {
-    double2 ring[kMaxBand];
+    double2 ring[LB];
 #pragma unroll
-    for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+    for (int m = 0; m < LB; ++m) ring[m] = zero2();
     double2 bn = vals[c];
     for (int i = 0; i < n2; ++i) {
       double2 b = bn;
       if (i + 1 < n2) bn = vals[size_t(i + 1) * ncol + c];
 #pragma unroll
-      for (int m = 0; m < kMaxBand; ++m) b = fma2(-P.lu_l[i * kMaxBand + m], ring[m], b);
+      for (int m = 0; m < LB; ++m) b = fma2(-P.lu_l[i * kMaxBand + m], ring[m], b);
       yp[size_t(i) * ncol + c] = b;
 #pragma unroll
-      for (int m = kMaxBand - 1; m > 0; --m) ring[m] = ring[m - 1];
+      for (int m = LB - 1; m > 0; --m) ring[m] = ring[m - 1];
       ring[0] = b;
     }
   }
@@ -1818,14 +1824,23 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
     // multipliers of the next row of the bottom-up sweep (rows n2-1, n2-2, ..., 0 in turn)
     int inext = n2 - 1;
     double fm[UA];
+    auto load_mult = [&](int row) {
+      const int nm = P.fac_nm[row], off = P.fac_off[row];
 #pragma unroll
-    for (int m = 0; m < UA; ++m) fm[m] = mean ? 0.0 : fac[(size_t(n2 - inext) * S + m) * npairs];
+      for (int m = 0; m < UA; ++m) fm[m] = (m < nm) ? fac[(size_t(off) + m) * npairs] : 0.0;
+    };
+    if (mean) {
+#pragma unroll
+      for (int m = 0; m < UA; ++m) fm[m] = 0.0;
+    } else {
+      load_mult(inext);
+    }
     double2 ypn = yp[size_t(n2 - 1) * ncol + c];
     for (int j = n2 - 1; j >= 0; --j) {
       double2 y = ypn;
       if (j > 0) ypn = yp[size_t(j - 1) * ncol + c];
 #pragma unroll
-      for (int q = 0; q < kMaxBand; ++q) y = fma2(-P.lu_u[j * (kMaxBand + 1) + q + 1], win[q], y);
+      for (int q = 0; q < LB; ++q) y = fma2(-P.lu_u[j * (kMaxBand + 1) + q + 1], win[q], y);
       const double2 x = cscale(y, P.lu_uinv[j]);
 #pragma unroll
       for (int q = kMaxW - 1; q > 0; --q) win[q] = win[q - 1];
@@ -1846,8 +1861,7 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
 #pragma unroll
         for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
         --inext;
-#pragma unroll
-        for (int m = 0; m < UA; ++m) fm[m] = fac[(size_t(n2 - inext) * S + m) * npairs];
+        load_mult(inext);
         yt[size_t(i) * ncol + c] = r;
 #pragma unroll
         for (int m = UA - 1; m > 0; --m) yr[m] = yr[m - 1];
@@ -1866,10 +1880,18 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
     double2 cw[kMaxW];  // c_i, c_{i-1}, ...
 #pragma unroll
     for (int q = 0; q < kMaxW; ++q) cw[q] = zero2();
+    // entries left of the diagonal (fs[0 .. LA-1]) and 1/pivot (fs[LA]) of a row
     double fs[LA + 1];
-    double2 ytn = yt[c];
+    auto load_sub = [&](int row) {
+      const int nm = P.fac_nm[row], ns = P.fac_ns[row], off = P.fac_off[row];
 #pragma unroll
-    for (int q = 0; q <= LA; ++q) fs[q] = mean ? 0.0 : fac[(size_t(n2) * S + UA + q) * npairs];
+      for (int q = 0; q < LA; ++q) fs[q] = (q < ns) ? fac[(size_t(off) + nm + q) * npairs] : 0.0;
+      fs[LA] = fac[(size_t(off) + nm + ns) * npairs];
+    };
+#pragma unroll
+    for (int q = 0; q <= LA; ++q) fs[q] = 0.0;
+    double2 ytn = yt[c];
+    if (!mean) load_sub(0);
     for (int i = 0; i < N; ++i) {
       double2 x = ytn;
       double fc[LA + 1];
@@ -1877,10 +1899,7 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
       for (int q = 0; q <= LA; ++q) fc[q] = fs[q];
       if (i + 1 < N) {
         ytn = yt[size_t(i + 1) * ncol + c];
-        if (!mean) {
-#pragma unroll
-          for (int q = 0; q <= LA; ++q) fs[q] = fac[(size_t(n2 - i - 1) * S + UA + q) * npairs];
-        }
+        if (!mean) load_sub(i + 1);
       }
       if (!mean) {
 #pragma unroll
@@ -2309,10 +2328,13 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   UP_TABLE(H.asc_first, D.asc_first);
   UP_TABLE(H.asc_cnt, D.asc_cnt);
   UP_TABLE(H.asc_w, D.asc_w);
+  UP_TABLE(H.fac_nm, D.fac_nm);
+  UP_TABLE(H.fac_ns, D.fac_ns);
+  UP_TABLE(H.fac_off, D.fac_off);
   {
     p->fac_la = p->fac_ua = (H.a_lower <= 7 && H.a_upper <= 7) ? 7 : 8;
     const size_t npairs = size_t(H.nl) * ((H.nn + 1) / 2);
-    const size_t bytes = size_t(H.n2 + 1) * (p->fac_la + p->fac_ua + 1) * npairs * sizeof(double);
+    const size_t bytes = size_t(H.fac_slots) * npairs * sizeof(double);
     void* d = nullptr;
     if (hipMalloc(&d, bytes) != hipSuccess) {
       lmvd_plan_destroy(p);
@@ -2643,22 +2665,25 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     }
     const int nth = 2 * H.nl * ((H.nn + 1) / 2);
     const dim3 g((nth + kThreads - 1) / kThreads);
-    const int S = p->fac_la + p->fac_ua + 1;
     // values in, L-sweep intermediate out and back, 3 value fields out, A(k) sweep intermediate out and back,
     // the factors once per pair; the final iterate also reads m^d values and writes rho_t, m_par, c2
     ProfScope ps(p, KC_MC, s,
                  16.0 * nB * (final_it ? 11.0 : 6.0) + 16.0 * ncol * (H.n2 + 1) * (final_it ? 3.0 : 2.0) +
-                     8.0 * S * (H.n2 + 1) * (nth / 2));
+                     8.0 * H.fac_slots * (nth / 2));
+    const bool narrow = H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
     double2* yp = c.at<double2>(W.off_yp);
     double2* yt = c.at<double2>(W.off_yt);
-    if (p->fac_la == 7)
-      hipLaunchKernelGGL((k_mc<7, 7>), g, dim3(kThreads), 0, s, p->D, vals[0], yp, yt, final_it ? vmd1 : nullptr,
-                         final_it ? vc2d : nullptr, final_it ? vmd3 : nullptr, vm1, vm2, vm3,
-                         final_it ? rhot : nullptr, final_it ? c2c : nullptr, final_it ? mpar : nullptr);
+#define LMVD_MC(LA_, LB_)                                                                                      \
+  hipLaunchKernelGGL((k_mc<LA_, LA_, LB_>), g, dim3(kThreads), 0, s, p->D, vals[0], yp, yt,                     \
+                     final_it ? vmd1 : nullptr, final_it ? vc2d : nullptr, final_it ? vmd3 : nullptr, vm1, vm2,   \
+                     vm3, final_it ? rhot : nullptr, final_it ? c2c : nullptr, final_it ? mpar : nullptr)
+    if (p->fac_la == 7 && narrow)
+      LMVD_MC(7, 6);
+    else if (p->fac_la == 7)
+      LMVD_MC(7, kMaxBand);
     else
-      hipLaunchKernelGGL((k_mc<8, 8>), g, dim3(kThreads), 0, s, p->D, vals[0], yp, yt, final_it ? vmd1 : nullptr,
-                         final_it ? vc2d : nullptr, final_it ? vmd3 : nullptr, vm1, vm2, vm3,
-                         final_it ? rhot : nullptr, final_it ? c2c : nullptr, final_it ? mpar : nullptr);
+      LMVD_MC(8, kMaxBand);
+#undef LMVD_MC
   };
   auto values = [&](const double2* a1, double2* v1, const double2* a2, double2* v2, const double2* a3, double2* v3) {
     ProfScope ps(p, KC_VALUES, s, 16.0 * nB * ((a1 ? 2 : 0) + (a2 ? 2 : 0) + (a3 ? 2 : 0)));

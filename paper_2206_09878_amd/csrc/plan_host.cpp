@@ -293,6 +293,8 @@ lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& H, std::string
     H.a_lower = lower;
     H.a_upper = upper;
     if (lower > 8 || upper > 8) { msg = "A(k) bandwidth exceeds 8"; return LMVD_EUNSUPPORTED; }
+    H.fac_nm.assign(n2 + 1, 0);
+    H.fac_ns.assign(n2 + 1, 0);
     // no-pivot stability of A(k) over the range of k of this grid
     double kmax = std::sqrt(std::pow(2 * M_PI * (H.nl - 1) / cfg.L1, 2) +
                             std::pow(2 * M_PI * (cfg.n3 / 2 - 1) / cfg.L3, 2));
@@ -318,7 +320,31 @@ lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& H, std::string
         for (int j = 0; j < n; ++j) Ar[size_t(i) * n + j] = A[size_t(n - 1 - i) * n + (n - 1 - j)];
       st = band_lu(Ar, n, tmp, msg);
       if (st != LMVD_OK) { msg = "A(k) reversed: " + msg; return st; }
+      // nonzero structure of the bottom-up elimination
+      std::vector<double> a = A;
+      for (int i = n - 1; i >= 0; --i) {
+        for (int m = upper; m >= 1; --m) {
+          if (i + m >= n) continue;
+          const double e = a[size_t(i) * n + i + m];
+          if (e == 0.0) continue;
+          H.fac_nm[i] = std::max(H.fac_nm[i], m);
+          const double lm = e / a[size_t(i + m) * n + i + m];
+          for (int j = std::max(0, i + m - lower - upper); j <= i + m; ++j)
+            a[size_t(i) * n + j] -= lm * a[size_t(i + m) * n + j];
+          a[size_t(i) * n + i + m] = 0.0;
+        }
+        for (int q = 1; q <= i; ++q)
+          if (a[size_t(i) * n + i - q] != 0.0) H.fac_ns[i] = std::max(H.fac_ns[i], q);
+      }
     }
+    H.fac_off.assign(n, 0);
+    int off = 0;
+    for (int i = n - 1; i >= 0; --i) {  // in the order of the bottom-up sweep
+      if (H.fac_nm[i] > upper || H.fac_ns[i] > lower) { msg = "A(k) elimination exceeds its band"; return LMVD_ENUMERIC; }
+      H.fac_off[i] = off;
+      off += H.fac_nm[i] + H.fac_ns[i] + 1;
+    }
+    H.fac_slots = off;
   }
 
   H.k1.resize(H.nl);

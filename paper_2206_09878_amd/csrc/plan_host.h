@@ -72,6 +72,12 @@ struct HostTables {
   // (j = 0..n2); asc_w[(d n2 + i') kMaxW + q] multiplies c_{last(i') - q}, d = 0 (F_0), 1 (F_1)
   std::vector<int32_t> asc_first, asc_cnt;
   std::vector<double> asc_w;
+  // bottom-up elimination of A(k) (rows n2 .. 0): per row i the number of
+  // multipliers (rows i+1 .. i+nm) and of entries left of the diagonal
+  // (columns i-1 .. i-ns) that can be nonzero (structure of A, union over
+  // sampled k), and the offset of the row's nm + ns + 1 factor slots
+  std::vector<int32_t> fac_nm, fac_ns, fac_off;
+  int fac_slots = 0;
 };
 
 // Build all host tables.  Returns LMVD_OK or an error with `msg` set.
