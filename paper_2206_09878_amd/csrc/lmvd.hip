@@ -1950,6 +1950,161 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
 }
 
 // ---------------------------------------------------------------------------
+// column kernel: m^d and its values at tau (eqs. phi_poisson, bc_both,
+// md_recon), one thread per column, pairs (l, +-n) on neighbouring lanes.
+//   1. descending sweep: r_i = G0 phi2 at the interior tau* rows (phi2 read
+//      through a register window of W = p rows, every coefficient once),
+//      bottom-up forward sweep of A(k) c = r (per-plan factors, Robin rows r = 0);
+//   2. ascending back substitution for c (B* coefficients of m2); every tau
+//      row whose F0/F1 band is complete emits
+//        m2 = F0 c,  m1 = (i k1 F1 c - i k3 E0 Omega2)/k^2,  m3 = (i k3 F1 c + i k1 E0 Omega2)/k^2
+//      (F1 = E0 D*, Omega2 read through a second window).
+// Plane mean: m^d = (<m>1, 0, <m>3).  With c2o the coefficients are written too.
+template <int LA, int UA, int W>
+__global__ void __launch_bounds__(kThreads) k_md(DevPlan P, const double2* __restrict__ phi,
+                                                const double2* __restrict__ om, const double* __restrict__ m1bar,
+                                                const double* __restrict__ m3bar, double2* yt,
+                                                double2* __restrict__ V1, double2* __restrict__ V2,
+                                                double2* __restrict__ V3, double2* __restrict__ c2o,
+                                                double2* __restrict__ m1o, double2* __restrict__ m3o) {
+  const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
+  const int half = (nn + 1) / 2, npairs = nl * half;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pr = t >> 1, side = t & 1;
+  if (pr >= npairs) return;
+  const int l = pr % nl, pp = pr / nl;
+  if (side == 1 && pp == 0) return;
+  const int ni = side ? nn - pp : pp;
+  const size_t ncol = size_t(nn) * nl, c = size_t(ni) * nl + l;
+  const double k1 = P.k1[l], k3 = P.k3[ni], ksq = k1 * k1 + k3 * k3;
+  if (ksq == 0.0) {
+    for (int i = 0; i < n2; ++i) {
+      const int lo = P.ev_lo[i];
+      double a1 = 0.0, a3 = 0.0;
+      for (int q = 0; q < kMaxW; ++q)
+        if (lo + q < n2) {
+          a1 += P.ev_w[size_t(i) * kMaxW + q] * m1bar[lo + q];
+          a3 += P.ev_w[size_t(i) * kMaxW + q] * m3bar[lo + q];
+        }
+      V1[size_t(i) * ncol] = make_double2(a1, 0.0);
+      V2[size_t(i) * ncol] = zero2();
+      V3[size_t(i) * ncol] = make_double2(a3, 0.0);
+    }
+    if (c2o) {
+      for (int i = 0; i < N; ++i) c2o[size_t(i) * ncol] = zero2();
+      for (int i = 0; i < n2; ++i) {
+        m1o[size_t(i) * ncol] = make_double2(m1bar[i], 0.0);
+        m3o[size_t(i) * ncol] = make_double2(m3bar[i], 0.0);
+      }
+    }
+    return;
+  }
+  const double iksq = 1.0 / ksq;
+  const double* fac = P.fac + pr;
+  // 1. descending: r = G0 phi2, bottom-up forward sweep
+  {
+    double2 wp[W];  // phi2 rows base .. base+W-1
+    int base = n2 - W;
+#pragma unroll
+    for (int q = 0; q < W; ++q) wp[q] = phi[size_t(base + q) * ncol + c];
+    double2 yr[UA];
+#pragma unroll
+    for (int m = 0; m < UA; ++m) yr[m] = zero2();
+    double fm[UA];
+    auto load_mult = [&](int row) {
+      const int nm = P.fac_nm[row], off = P.fac_off[row];
+#pragma unroll
+      for (int m = 0; m < UA; ++m) fm[m] = (m < nm) ? fac[(size_t(off) + m) * npairs] : 0.0;
+    };
+    yt[size_t(n2) * ncol + c] = zero2();  // Robin row n2: r = 0
+    load_mult(n2 - 1);
+    for (int i = n2 - 1; i >= 1; --i) {
+      const int lo = P.gs_lo[i];
+      while (base > lo) {
+#pragma unroll
+        for (int q = W - 1; q > 0; --q) wp[q] = wp[q - 1];
+        --base;
+        wp[0] = phi[size_t(base) * ncol + c];
+      }
+      double2 r = zero2();
+#pragma unroll
+      for (int q = 0; q < W; ++q) r = fma2(P.gs_w[size_t(i) * kMaxW + q], wp[q], r);
+#pragma unroll
+      for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
+      load_mult(i - 1);
+      yt[size_t(i) * ncol + c] = r;
+#pragma unroll
+      for (int m = UA - 1; m > 0; --m) yr[m] = yr[m - 1];
+      yr[0] = r;
+    }
+    double2 r = zero2();  // Robin row 0
+#pragma unroll
+    for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
+    yt[c] = r;
+  }
+  // 2. ascending back substitution, emission of the values at tau
+  {
+    double2 cw[kMaxW];
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q) cw[q] = zero2();
+    RowWin<W> wo;
+    wo.init(om, ncol, c, n2);
+    double fs[LA + 1];
+    auto load_sub = [&](int row) {
+      const int nm = P.fac_nm[row], ns = P.fac_ns[row], off = P.fac_off[row];
+#pragma unroll
+      for (int q = 0; q < LA; ++q) fs[q] = (q < ns) ? fac[(size_t(off) + nm + q) * npairs] : 0.0;
+      fs[LA] = fac[(size_t(off) + nm + ns) * npairs];
+    };
+    double2 ytn = yt[c];
+    load_sub(0);
+    for (int i = 0; i < N; ++i) {
+      double2 x = ytn;
+      double fc[LA + 1];
+#pragma unroll
+      for (int q = 0; q <= LA; ++q) fc[q] = fs[q];
+      if (i + 1 < N) {
+        ytn = yt[size_t(i + 1) * ncol + c];
+        load_sub(i + 1);
+      }
+#pragma unroll
+      for (int q = 0; q < LA; ++q) x = fma2(-fc[q], cw[q], x);
+      x = cscale(x, fc[LA]);
+#pragma unroll
+      for (int q = kMaxW - 1; q > 0; --q) cw[q] = cw[q - 1];
+      cw[0] = x;
+      if (c2o) {
+        c2o[size_t(i) * ncol + c] = x;
+        if (i > 0) {
+          const size_t e = size_t(i - 1) * ncol + c;
+          const double ds = P.dstar[i - 1];
+          const double2 D = make_double2(ds * (cw[0].x - cw[1].x), ds * (cw[0].y - cw[1].y));
+          const double2 O = om[e];
+          m1o[e] = cscale(times_i(make_double2(k1 * D.x - k3 * O.x, k1 * D.y - k3 * O.y)), iksq);
+          m3o[e] = cscale(times_i(make_double2(k3 * D.x + k1 * O.x, k3 * D.y + k1 * O.y)), iksq);
+        }
+      }
+      const int first = P.asc_first[i], cnt = P.asc_cnt[i];
+      for (int e = 0; e < cnt; ++e) {
+        const int row = first + e;
+        double2 f0 = zero2(), f1 = zero2();
+#pragma unroll
+        for (int q = 0; q < kMaxW; ++q) {
+          f0 = fma2(P.asc_w[size_t(row) * kMaxW + q], cw[q], f0);
+          f1 = fma2(P.asc_w[(size_t(n2) + row) * kMaxW + q], cw[q], f1);
+        }
+        wo.advance(om, ncol, c, n2, P.ev_lo[row]);
+        const double2 oe = wo.dot(P.ev_w + size_t(row) * kMaxW);
+        const size_t o = size_t(row) * ncol + c;
+        V1[o] = cscale(times_i(make_double2(k1 * f1.x - k3 * oe.x, k1 * f1.y - k3 * oe.y)), iksq);
+        V2[o] = f0;
+        V3[o] = cscale(times_i(make_double2(k3 * f1.x + k1 * oe.x, k3 * f1.y + k1 * oe.y)), iksq);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column kernel: the right-hand sides of Omega2 and phi2 at tau (from the
 // flux kernels) -> coefficients with Dirichlet end rows, RK2 update.
 
@@ -2611,6 +2766,18 @@ static void solveA(const Ctx& c, const double2* in1, const double2* in2, const d
                        o3, uscr);
 }
 
+// the plan's A(k) factors, computed on the stream of the first substep that needs them
+static void ensure_factors(lmvd_plan_s* p, hipStream_t s) {
+  if (p->fac_ready) return;
+  const int npairs = p->H.nl * ((p->H.nn + 1) / 2);
+  const dim3 g((npairs + kThreads - 1) / kThreads);
+  if (p->fac_la == 7)
+    hipLaunchKernelGGL((k_factor_ul<7, 7>), g, dim3(kThreads), 0, s, p->D, p->fac);
+  else
+    hipLaunchKernelGGL((k_factor_ul<8, 8>), g, dim3(kThreads), 0, s, p->D, p->fac);
+  p->fac_ready = true;
+}
+
 static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void* workspace, hipStream_t s) {
   const HostTables& H = p->H;
   Ctx c{p, static_cast<char*>(workspace), s};
@@ -2654,15 +2821,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   const dim3 cgrid((unsigned)((ncol + kThreads - 1) / kThreads));
   // m^c values (and, for the final iterate, m = m^d + m^c and the coefficients) from the rho_t values
   auto mc_step = [&](bool final_it) {
-    if (!p->fac_ready) {
-      const int npairs = H.nl * ((H.nn + 1) / 2);
-      const dim3 g((npairs + kThreads - 1) / kThreads);
-      if (p->fac_la == 7)
-        hipLaunchKernelGGL((k_factor_ul<7, 7>), g, dim3(kThreads), 0, s, p->D, p->fac);
-      else
-        hipLaunchKernelGGL((k_factor_ul<8, 8>), g, dim3(kThreads), 0, s, p->D, p->fac);
-      p->fac_ready = true;
-    }
+    ensure_factors(p, s);
     const int nth = 2 * H.nl * ((H.nn + 1) / 2);
     const dim3 g((nth + kThreads - 1) / kThreads);
     // values in, L-sweep intermediate out and back, 3 value fields out, A(k) sweep intermediate out and back,
@@ -2691,8 +2850,27 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   };
 
   // 1. m^d and its values at tau
-  solveA<0>(c, phi2, om2, a->m1bar, a->m3bar, c2d, md1, md3);
-  values(md1, vmd1, md3, vmd3, c2d, vc2d);
+  if (H.p == 8) {
+    ensure_factors(p, s);
+    const int nth = 2 * H.nl * ((H.nn + 1) / 2);
+    const bool diag = a->md[0] || a->md[1] || a->md[2];
+    // phi2, Omega2 in, 3 value fields out, A(k) sweep intermediate out and back, factors once per pair
+    // (+ the coefficients when requested)
+    ProfScope ps(p, KC_MD, s,
+                 16.0 * nB * (diag ? 7.0 : 5.0) + 16.0 * ncol * (H.n2 + 1) * (diag ? 3.0 : 2.0) +
+                     8.0 * H.fac_slots * (nth / 2));
+    const dim3 g((nth + kThreads - 1) / kThreads);
+    double2* yt = c.at<double2>(W.off_yt);
+    if (p->fac_la == 7)
+      hipLaunchKernelGGL((k_md<7, 7, 8>), g, dim3(kThreads), 0, s, p->D, phi2, om2, a->m1bar, a->m3bar, yt, vmd1,
+                         vc2d, vmd3, diag ? c2d : nullptr, diag ? md1 : nullptr, diag ? md3 : nullptr);
+    else
+      hipLaunchKernelGGL((k_md<8, 8, 8>), g, dim3(kThreads), 0, s, p->D, phi2, om2, a->m1bar, a->m3bar, yt, vmd1,
+                         vc2d, vmd3, diag ? c2d : nullptr, diag ? md1 : nullptr, diag ? md3 : nullptr);
+  } else {
+    solveA<0>(c, phi2, om2, a->m1bar, a->m3bar, c2d, md1, md3);
+    values(md1, vmd1, md3, vmd3, c2d, vc2d);
+  }
   // values of z and its y-derivatives (z is fixed during the substep)
   {
     ProfScope ps(p, KC_VALUES, s, 16.0 * nB * 5);
