@@ -44,7 +44,7 @@ def kernel_symbol(cls: str, w) -> str:
     return {
         "zinv": f"k_zinv_r<{m3}, true>", "zfwd": f"k_zfwd_r<{m3}>",
         "xpass_rz": f"k_xpair<0, {m1}>", "xpass_rhot": f"k_xpair<1, {m1}>", "xpass_l": f"k_xpair<2, {m1}>",
-        "xpass_vel": f"k_xpair<3, {m1}>", "mc": "k_mc<7, 7, 6>", "md": "k_solveA<0, 7, 7>", "proj": "k_proj<0>",
+        "xpass_vel": f"k_xpair<3, {m1}>", "mc": "k_mc<7, 7, 6, true>", "md": "k_solveA<0, 7, 7>", "proj": "k_proj<0>",
         "proj_zt": "k_proj<1>, k_proj<2>", "values": "k_values, k_values_z, k_guess_v",
         "flux": "k_flux<0, 8, 6>, k_flux<1, 8, 6>", "rhs": "k_rhs_fluct, k_rhs_mean",
     }.get(cls, cls)

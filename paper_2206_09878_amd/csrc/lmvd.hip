@@ -33,6 +33,7 @@ namespace lmvd {
 constexpr int kMaxIn = 8;
 constexpr int kMaxOut = 10;
 constexpr int kNumAux = 4;   // physical-grid fields fixed during a substep
+constexpr int kPre = 3;      // rows loaded ahead by the sequential column sweeps
 constexpr int kThreads = 256;
 constexpr int kZMaxE = 12;    // elements per thread in the z-FFT kernels
 constexpr int kXSlots = 3;    // complex slots per thread per line set in k_xpass
@@ -1268,7 +1269,8 @@ __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const do
     ring[0] = x;
     const size_t e = size_t(i) * ncol + c;
     const double2 fin = (EPI == EPI_STORE) ? x : cadd(x, add[e]);
-    out[e] = fin;
+    // a non-final fixed-point iterate (EPI_ADD) is consumed only through its emitted values
+    if (EPI != EPI_ADD) out[e] = fin;
     if (vals_out) {
 #pragma unroll
       for (int q = kMaxW - 1; q > 0; --q) win[q] = win[q - 1];
@@ -1771,37 +1773,62 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
 // Plane mean (k = 0): D* c = -<rho_t>, c_top = 0, m1 = m3 = 0.
 // With d1 (final iterate) the m^d values are added and the coefficients
 // c2 = c, mparc = (i/k)(rho_t + D* c) and rhoc = rho_t are written.
-template <int LA, int UA, int LB>
+// LDS layout of the tables a sweep of k_mc reads (doubles, then ints), per
+// phase; phase 2: U rows of the interpolation (LB), 1/pivots, G1 rows,
+// G1 emission starts and counts, factor row counts and offsets; phase 3:
+// F0/F1 emission weights, emission starts and counts, factor row structure.
+struct McLds {
+  int n2, N, lb;
+  __host__ __device__ int p2_doubles() const { return n2 * lb + n2 + N * kMaxW + n2; }
+  __host__ __device__ int p2_ints() const { return 2 * n2 + 2 * N; }
+  __host__ __device__ int p3_doubles() const { return 2 * n2 * kMaxW + n2; }
+  __host__ __device__ int p3_ints() const { return 2 * N + 3 * N; }
+  __host__ __device__ size_t bytes() const {
+    const size_t a = size_t(p2_doubles()) * 8 + size_t(p2_ints()) * 4;
+    const size_t b = size_t(p3_doubles()) * 8 + size_t(p3_ints()) * 4;
+    return a > b ? a : b;
+  }
+};
+
+// STAGE: the row tables of phases 2 and 3 are copied to LDS at the start of
+// each phase (every row of every column reads them with the same index, so
+// LDS latency replaces a scalar-cache miss per row); threads without a
+// column still take part in the copies and barriers.
+template <int LA, int UA, int LB, bool STAGE>
 __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __restrict__ vals, double2* yp,
                                                 double2* yt, const double2* __restrict__ d1,
                                                 const double2* __restrict__ d2, const double2* __restrict__ d3,
                                                 double2* __restrict__ V1, double2* __restrict__ V2,
                                                 double2* __restrict__ V3, double2* rhoc, double2* __restrict__ c2,
                                                 double2* __restrict__ mparc) {
+  extern __shared__ double lds_d[];
   const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
   const int half = (nn + 1) / 2, npairs = nl * half;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int pr = t >> 1, side = t & 1;
-  if (pr >= npairs) return;
   const int l = pr % nl, pp = pr / nl;
-  if (side == 1 && pp == 0) return;
-  const int ni = side ? nn - pp : pp;
-  const size_t ncol = size_t(nn) * nl, c = size_t(ni) * nl + l;
-  const double k1 = P.k1[l], k3 = P.k3[ni], ksq = k1 * k1 + k3 * k3;
+  const bool active = pr < npairs && !(side == 1 && pp == 0);
+  if (!STAGE && !active) return;
+  const int ni = active ? (side ? nn - pp : pp) : 0;
+  const size_t ncol = size_t(nn) * nl, c = size_t(ni) * nl + (active ? l : 0);
+  const double k1 = active ? P.k1[l] : 1.0, k3 = P.k3[ni], ksq = k1 * k1 + k3 * k3;
   const bool mean = (ksq == 0.0);
   const double ik = mean ? 0.0 : 1.0 / sqrt(ksq);
-  const double* fac = P.fac + pr;
-  // Every sweep loads the operands of its next row one step ahead: the loads
-  // do not depend on the recurrence, so their latency overlaps the current row.
-  // 1. ascending sweep of the interpolation projection
-  {
+  const double* fac = P.fac + (active ? pr : 0);
+  const McLds lay{n2, N, LB};
+  // 1. ascending sweep of the interpolation projection (rows loaded kPre ahead)
+  if (active) {
     double2 ring[LB];
 #pragma unroll
     for (int m = 0; m < LB; ++m) ring[m] = zero2();
-    double2 bn = vals[c];
+    double2 pf[kPre];
+#pragma unroll
+    for (int d = 0; d < kPre; ++d) pf[d] = (d < n2) ? vals[size_t(d) * ncol + c] : zero2();
     for (int i = 0; i < n2; ++i) {
-      double2 b = bn;
-      if (i + 1 < n2) bn = vals[size_t(i + 1) * ncol + c];
+      double2 b = pf[0];
+#pragma unroll
+      for (int d = 0; d < kPre - 1; ++d) pf[d] = pf[d + 1];
+      if (i + kPre < n2) pf[kPre - 1] = vals[size_t(i + kPre) * ncol + c];
 #pragma unroll
       for (int m = 0; m < LB; ++m) b = fma2(-P.lu_l[i * kMaxBand + m], ring[m], b);
       yp[size_t(i) * ncol + c] = b;
@@ -1812,138 +1839,207 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
   }
   // 2. descending sweep: rho_t coefficients, r = -G1 rho_t, bottom-up forward sweep of A(k)
   {
-    double2 win[kMaxW];  // rho_t coefficients of rows j .. j+kMaxW-1
-    double2 yr[UA];      // forward-sweep results of rows i+1 .. i+UA
-#pragma unroll
-    for (int q = 0; q < kMaxW; ++q) win[q] = zero2();
-#pragma unroll
-    for (int m = 0; m < UA; ++m) yr[m] = zero2();
-    double2 cm = zero2();  // mean column: c_{j+1}
-    yt[size_t(n2) * ncol + c] = zero2();  // Robin row n2: r = 0, nothing above it
-    const auto G1w = P.gs_w + size_t(N) * kMaxW;
-    // multipliers of the next row of the bottom-up sweep (rows n2-1, n2-2, ..., 0 in turn)
-    int inext = n2 - 1;
-    double fm[UA];
-    auto load_mult = [&](int row) {
-      const int nm = P.fac_nm[row], off = P.fac_off[row];
-#pragma unroll
-      for (int m = 0; m < UA; ++m) fm[m] = (m < nm) ? fac[(size_t(off) + m) * npairs] : 0.0;
+    double* su = lds_d;                 // [n2][LB]
+    double* sui = su + n2 * LB;         // [n2]
+    double* sg = sui + n2;              // [N][kMaxW] G1 rows
+    double* sds = sg + N * kMaxW;       // [n2] dstar
+    int* sgf = reinterpret_cast<int*>(sds + n2);  // [n2] G1 emission starts
+    int* sgc = sgf + n2;                // [n2]
+    int* snm = sgc + n2;                // [N]
+    int* sof = snm + N;                 // [N]
+    if constexpr (STAGE) {
+      for (int e = threadIdx.x; e < n2 * LB; e += blockDim.x) su[e] = P.lu_u[(e / LB) * (kMaxBand + 1) + e % LB + 1];
+      for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+        sui[e] = P.lu_uinv[e];
+        sds[e] = P.dstar[e];
+        sgf[e] = P.g1e_first[e];
+        sgc[e] = P.g1e_cnt[e];
+      }
+      for (int e = threadIdx.x; e < N * kMaxW; e += blockDim.x) sg[e] = P.gs_w[size_t(N) * kMaxW + e];
+      for (int e = threadIdx.x; e < N; e += blockDim.x) {
+        snm[e] = P.fac_nm[e];
+        sof[e] = P.fac_off[e];
+      }
+      __syncthreads();
+    }
+    auto U_ = [&](int j, int q) -> double {
+      if constexpr (STAGE) return su[j * LB + q]; else return P.lu_u[j * (kMaxBand + 1) + q + 1];
     };
-    if (mean) {
+    auto Ui_ = [&](int j) -> double { if constexpr (STAGE) return sui[j]; else return P.lu_uinv[j]; };
+    auto G_ = [&](int i, int q) -> double {
+      if constexpr (STAGE) return sg[i * kMaxW + q]; else return P.gs_w[(size_t(N) + i) * kMaxW + q];
+    };
+    auto ds_ = [&](int j) -> double { if constexpr (STAGE) return sds[j]; else return P.dstar[j]; };
+    auto gf_ = [&](int j) -> int { if constexpr (STAGE) return sgf[j]; else return P.g1e_first[j]; };
+    auto gc_ = [&](int j) -> int { if constexpr (STAGE) return sgc[j]; else return P.g1e_cnt[j]; };
+    auto nm_ = [&](int r) -> int { if constexpr (STAGE) return snm[r]; else return P.fac_nm[r]; };
+    auto of_ = [&](int r) -> int { if constexpr (STAGE) return sof[r]; else return P.fac_off[r]; };
+    if (active) {
+      double2 win[kMaxW];  // rho_t coefficients of rows j .. j+kMaxW-1
+      double2 yr[UA];      // forward-sweep results of rows i+1 .. i+UA
+#pragma unroll
+      for (int q = 0; q < kMaxW; ++q) win[q] = zero2();
+#pragma unroll
+      for (int m = 0; m < UA; ++m) yr[m] = zero2();
+      double2 cm = zero2();  // mean column: c_{j+1}
+      yt[size_t(n2) * ncol + c] = zero2();  // Robin row n2: r = 0, nothing above it
+      // multipliers of the next row of the bottom-up sweep (rows n2-1, n2-2, ..., 0 in turn)
+      int inext = n2 - 1;
+      double fm[UA];
+      auto load_mult = [&](int row) {
+        const int nm = nm_(row), off = of_(row);
+#pragma unroll
+        for (int m = 0; m < UA; ++m) fm[m] = (m < nm) ? fac[(size_t(off) + m) * npairs] : 0.0;
+      };
 #pragma unroll
       for (int m = 0; m < UA; ++m) fm[m] = 0.0;
-    } else {
-      load_mult(inext);
-    }
-    double2 ypn = yp[size_t(n2 - 1) * ncol + c];
-    for (int j = n2 - 1; j >= 0; --j) {
-      double2 y = ypn;
-      if (j > 0) ypn = yp[size_t(j - 1) * ncol + c];
+      if (!mean) load_mult(inext);
+      double2 pf[kPre];  // rows j-1 .. j-kPre of the L-sweep result, loaded ahead
 #pragma unroll
-      for (int q = 0; q < LB; ++q) y = fma2(-P.lu_u[j * (kMaxBand + 1) + q + 1], win[q], y);
-      const double2 x = cscale(y, P.lu_uinv[j]);
+      for (int d = 0; d < kPre; ++d) pf[d] = (n2 - 1 - d >= 0) ? yp[size_t(n2 - 1 - d) * ncol + c] : zero2();
+      for (int j = n2 - 1; j >= 0; --j) {
+        double2 y = pf[0];
 #pragma unroll
-      for (int q = kMaxW - 1; q > 0; --q) win[q] = win[q - 1];
-      win[0] = x;
-      if (rhoc) rhoc[size_t(j) * ncol + c] = x;
-      if (mean) {
-        cm = make_double2(cm.x + x.x / P.dstar[j], cm.y + x.y / P.dstar[j]);
-        yt[size_t(j) * ncol + c] = cm;
-        continue;
+        for (int d = 0; d < kPre - 1; ++d) pf[d] = pf[d + 1];
+        if (j - kPre >= 0) pf[kPre - 1] = yp[size_t(j - kPre) * ncol + c];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) y = fma2(-U_(j, q), win[q], y);
+        const double2 x = cscale(y, Ui_(j));
+#pragma unroll
+        for (int q = kMaxW - 1; q > 0; --q) win[q] = win[q - 1];
+        win[0] = x;
+        if (rhoc) rhoc[size_t(j) * ncol + c] = x;
+        if (mean) {
+          cm = make_double2(cm.x + x.x / ds_(j), cm.y + x.y / ds_(j));
+          yt[size_t(j) * ncol + c] = cm;
+          continue;
+        }
+        const int first = gf_(j), cnt = gc_(j);
+        for (int e = cnt - 1; e >= 0; --e) {
+          const int i = first + e;  // == inext
+          double2 r = zero2();
+#pragma unroll
+          for (int q = 0; q < kMaxW; ++q) r = fma2(-G_(i, q), win[q], r);
+#pragma unroll
+          for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
+          --inext;
+          load_mult(inext);
+          yt[size_t(i) * ncol + c] = r;
+#pragma unroll
+          for (int m = UA - 1; m > 0; --m) yr[m] = yr[m - 1];
+          yr[0] = r;
+        }
       }
-      const int first = P.g1e_first[j], cnt = P.g1e_cnt[j];
-      for (int e = cnt - 1; e >= 0; --e) {
-        const int i = first + e;  // == inext
-        const auto g = G1w + size_t(i) * kMaxW;
+      if (!mean) {  // Robin row 0 (inext == 0): r = 0
         double2 r = zero2();
 #pragma unroll
-        for (int q = 0; q < kMaxW; ++q) r = fma2(-g[q], win[q], r);
-#pragma unroll
         for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
-        --inext;
-        load_mult(inext);
-        yt[size_t(i) * ncol + c] = r;
-#pragma unroll
-        for (int m = UA - 1; m > 0; --m) yr[m] = yr[m - 1];
-        yr[0] = r;
+        yt[c] = r;
       }
-    }
-    if (!mean) {  // Robin row 0 (inext == 0): r = 0
-      double2 r = zero2();
-#pragma unroll
-      for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
-      yt[c] = r;
     }
   }
   // 3. ascending back substitution and emission of the values at tau
   {
-    double2 cw[kMaxW];  // c_i, c_{i-1}, ...
-#pragma unroll
-    for (int q = 0; q < kMaxW; ++q) cw[q] = zero2();
-    // entries left of the diagonal (fs[0 .. LA-1]) and 1/pivot (fs[LA]) of a row
-    double fs[LA + 1];
-    auto load_sub = [&](int row) {
-      const int nm = P.fac_nm[row], ns = P.fac_ns[row], off = P.fac_off[row];
-#pragma unroll
-      for (int q = 0; q < LA; ++q) fs[q] = (q < ns) ? fac[(size_t(off) + nm + q) * npairs] : 0.0;
-      fs[LA] = fac[(size_t(off) + nm + ns) * npairs];
+    double* sw = lds_d;                  // [2][n2][kMaxW] F0, F1 emission weights
+    double* sds = sw + 2 * n2 * kMaxW;   // [n2] dstar
+    int* saf = reinterpret_cast<int*>(sds + n2);  // [N] emission starts
+    int* sac = saf + N;                  // [N]
+    int* snm = sac + N;                  // [N]
+    int* sns = snm + N;                  // [N]
+    int* sof = sns + N;                  // [N]
+    if constexpr (STAGE) {
+      __syncthreads();  // phase-2 tables no longer read
+      for (int e = threadIdx.x; e < 2 * n2 * kMaxW; e += blockDim.x) sw[e] = P.asc_w[e];
+      for (int e = threadIdx.x; e < n2; e += blockDim.x) sds[e] = P.dstar[e];
+      for (int e = threadIdx.x; e < N; e += blockDim.x) {
+        saf[e] = P.asc_first[e];
+        sac[e] = P.asc_cnt[e];
+        snm[e] = P.fac_nm[e];
+        sns[e] = P.fac_ns[e];
+        sof[e] = P.fac_off[e];
+      }
+      __syncthreads();
+    }
+    (void)lay;
+    auto W_ = [&](int d, int row, int q) -> double {
+      if constexpr (STAGE) return sw[(d * n2 + row) * kMaxW + q];
+      else return P.asc_w[(size_t(d) * n2 + row) * kMaxW + q];
     };
+    auto ds_ = [&](int j) -> double { if constexpr (STAGE) return sds[j]; else return P.dstar[j]; };
+    auto af_ = [&](int j) -> int { if constexpr (STAGE) return saf[j]; else return P.asc_first[j]; };
+    auto ac_ = [&](int j) -> int { if constexpr (STAGE) return sac[j]; else return P.asc_cnt[j]; };
+    auto nm_ = [&](int r) -> int { if constexpr (STAGE) return snm[r]; else return P.fac_nm[r]; };
+    auto ns_ = [&](int r) -> int { if constexpr (STAGE) return sns[r]; else return P.fac_ns[r]; };
+    auto of_ = [&](int r) -> int { if constexpr (STAGE) return sof[r]; else return P.fac_off[r]; };
+    if (active) {
+      double2 cw[kMaxW];  // c_i, c_{i-1}, ...
 #pragma unroll
-    for (int q = 0; q <= LA; ++q) fs[q] = 0.0;
-    double2 ytn = yt[c];
-    if (!mean) load_sub(0);
-    for (int i = 0; i < N; ++i) {
-      double2 x = ytn;
-      double fc[LA + 1];
+      for (int q = 0; q < kMaxW; ++q) cw[q] = zero2();
+      // entries left of the diagonal (fs[0 .. LA-1]) and 1/pivot (fs[LA]) of a row
+      double fs[LA + 1];
+      auto load_sub = [&](int row) {
+        const int nm = nm_(row), ns = ns_(row), off = of_(row);
 #pragma unroll
-      for (int q = 0; q <= LA; ++q) fc[q] = fs[q];
-      if (i + 1 < N) {
-        ytn = yt[size_t(i + 1) * ncol + c];
-        if (!mean) load_sub(i + 1);
-      }
-      if (!mean) {
+        for (int q = 0; q < LA; ++q) fs[q] = (q < ns) ? fac[(size_t(off) + nm + q) * npairs] : 0.0;
+        fs[LA] = fac[(size_t(off) + nm + ns) * npairs];
+      };
 #pragma unroll
-        for (int q = 0; q < LA; ++q) x = fma2(-fc[q], cw[q], x);
-        x = cscale(x, fc[LA]);
-      }
+      for (int q = 0; q <= LA; ++q) fs[q] = 0.0;
+      double2 pf[kPre];  // rows i .. i+kPre-1 of the A(k) forward-sweep result, loaded ahead
 #pragma unroll
-      for (int q = kMaxW - 1; q > 0; --q) cw[q] = cw[q - 1];
-      cw[0] = x;
-      if (c2) {
-        c2[size_t(i) * ncol + c] = x;
-        if (i > 0) {
-          const size_t e = size_t(i - 1) * ncol + c;
-          const double ds = P.dstar[i - 1];
-          const double2 dc = make_double2(ds * (cw[0].x - cw[1].x), ds * (cw[0].y - cw[1].y));
-          mparc[e] = mean ? zero2() : cscale(times_i(cadd(rhoc[e], dc)), ik);
-        }
-      }
-      const int first = P.asc_first[i], cnt = P.asc_cnt[i];
-      for (int e = 0; e < cnt; ++e) {
-        const int row = first + e;
-        const auto w0 = P.asc_w + size_t(row) * kMaxW;
-        const auto w1 = P.asc_w + (size_t(n2) + row) * kMaxW;
-        double2 m2 = zero2(), f1 = zero2();
+      for (int d = 0; d < kPre; ++d) pf[d] = (d < N) ? yt[size_t(d) * ncol + c] : zero2();
+      if (!mean) load_sub(0);
+      for (int i = 0; i < N; ++i) {
+        double2 x = pf[0];
 #pragma unroll
-        for (int q = 0; q < kMaxW; ++q) {
-          m2 = fma2(w0[q], cw[q], m2);
-          f1 = fma2(w1[q], cw[q], f1);
-        }
-        const size_t o = size_t(row) * ncol + c;
-        double2 m1 = zero2(), m3 = zero2();
+        for (int d = 0; d < kPre - 1; ++d) pf[d] = pf[d + 1];
+        if (i + kPre < N) pf[kPre - 1] = yt[size_t(i + kPre) * ncol + c];
+        double fc[LA + 1];
+#pragma unroll
+        for (int q = 0; q <= LA; ++q) fc[q] = fs[q];
+        if (i + 1 < N && !mean) load_sub(i + 1);
         if (!mean) {
-          const double2 mp = cscale(times_i(cadd(vals[o], f1)), ik);
-          m1 = cscale(mp, k1 * ik);
-          m3 = cscale(mp, k3 * ik);
+#pragma unroll
+          for (int q = 0; q < LA; ++q) x = fma2(-fc[q], cw[q], x);
+          x = cscale(x, fc[LA]);
         }
-        if (d1) {
-          m1 = cadd(m1, d1[o]);
-          m2 = cadd(m2, d2[o]);
-          m3 = cadd(m3, d3[o]);
+#pragma unroll
+        for (int q = kMaxW - 1; q > 0; --q) cw[q] = cw[q - 1];
+        cw[0] = x;
+        if (c2) {
+          c2[size_t(i) * ncol + c] = x;
+          if (i > 0) {
+            const size_t e = size_t(i - 1) * ncol + c;
+            const double ds = ds_(i - 1);
+            const double2 dc = make_double2(ds * (cw[0].x - cw[1].x), ds * (cw[0].y - cw[1].y));
+            mparc[e] = mean ? zero2() : cscale(times_i(cadd(rhoc[e], dc)), ik);
+          }
         }
-        V1[o] = m1;
-        V2[o] = m2;
-        V3[o] = m3;
+        const int first = af_(i), cnt = ac_(i);
+        for (int e = 0; e < cnt; ++e) {
+          const int row = first + e;
+          double2 m2 = zero2(), f1 = zero2();
+#pragma unroll
+          for (int q = 0; q < kMaxW; ++q) {
+            m2 = fma2(W_(0, row, q), cw[q], m2);
+            f1 = fma2(W_(1, row, q), cw[q], f1);
+          }
+          const size_t o = size_t(row) * ncol + c;
+          double2 m1 = zero2(), m3 = zero2();
+          if (!mean) {
+            const double2 mp = cscale(times_i(cadd(vals[o], f1)), ik);
+            m1 = cscale(mp, k1 * ik);
+            m3 = cscale(mp, k3 * ik);
+          }
+          if (d1) {
+            m1 = cadd(m1, d1[o]);
+            m2 = cadd(m2, d2[o]);
+            m3 = cadd(m3, d3[o]);
+          }
+          V1[o] = m1;
+          V2[o] = m2;
+          V3[o] = m3;
+        }
       }
     }
   }
@@ -2832,16 +2928,21 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     const bool narrow = H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
     double2* yp = c.at<double2>(W.off_yp);
     double2* yt = c.at<double2>(W.off_yt);
-#define LMVD_MC(LA_, LB_)                                                                                      \
-  hipLaunchKernelGGL((k_mc<LA_, LA_, LB_>), g, dim3(kThreads), 0, s, p->D, vals[0], yp, yt,                     \
+#define LMVD_MC(LA_, LB_, ST_)                                                                                 \
+  hipLaunchKernelGGL((k_mc<LA_, LA_, LB_, ST_>), g, dim3(kThreads), ST_ ? lay.bytes() : 0, s, p->D, vals[0], yp, yt,  \
                      final_it ? vmd1 : nullptr, final_it ? vc2d : nullptr, final_it ? vmd3 : nullptr, vm1, vm2,   \
                      vm3, final_it ? rhot : nullptr, final_it ? c2c : nullptr, final_it ? mpar : nullptr)
-    if (p->fac_la == 7 && narrow)
-      LMVD_MC(7, 6);
+    // the staged tables must leave room for two blocks per compute unit
+    const McLds lay{H.n2, H.n2 + 1, narrow ? 6 : kMaxBand};
+    const bool stage = lay.bytes() <= 72 * 1024;
+    if (p->fac_la == 7 && narrow && stage)
+      LMVD_MC(7, 6, true);
+    else if (p->fac_la == 7 && narrow)
+      LMVD_MC(7, 6, false);
     else if (p->fac_la == 7)
-      LMVD_MC(7, kMaxBand);
+      LMVD_MC(7, kMaxBand, false);
     else
-      LMVD_MC(8, kMaxBand);
+      LMVD_MC(8, kMaxBand, false);
 #undef LMVD_MC
   };
   auto values = [&](const double2* a1, double2* v1, const double2* a2, double2* v2, const double2* a3, double2* v3) {
@@ -2919,7 +3020,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     if (st != LMVD_OK) return st;
     double2* next = (last && user_zt) ? user_zt : (cur == zta ? ztb : zta);
     const int n = int(ncol);
-    ProfScope ps(p, KC_PROJ_ZT, s, (last ? (a->stage ? 9.0 : 8.0) : 6.0) * 16.0 * nB);
+    ProfScope ps(p, KC_PROJ_ZT, s, (last ? (a->stage ? 9.0 : 8.0) : 5.0) * 16.0 * nB);
     if (last) {
       hipLaunchKernelGGL(k_proj<EPI_ADD_ZUPDATE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
                          vals[0], next, rz, z, static_cast<const double2*>(a->zt_prev),
