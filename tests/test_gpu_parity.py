@@ -207,3 +207,26 @@ def test_substep_mid(torch, name, n, n2):
     w = workload(name, n=n, n2=n2)
     got, ref = run_pair(w, 0, seed=7)
     check_pair(got, ref, rhs_tol=rhs_tolerances(w, 0, 7, ref=ref))
+
+
+def test_trajectory_three_substeps_small(torch):
+    """Config 0 trajectory: substeps n, ', n, each side free-running on its own
+    outputs (history rotation, stored RHS and z_t between the stages), from the
+    same seeded state and synthetic history; every state field within 1e-11."""
+    from oracle.lmvd import Integrator
+    from paper_2206_09878_amd.lmvd import Stepper
+    w = workload("small")
+    p = gplan(w)
+    op = OPlan(oracle_config(w))
+    inp = make_inputs(w, seed=0, stage=0)
+    st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
+    it = Integrator(op, st, hist=inp["hist"])
+    it.step()                                   # substeps n and '
+    ref = substep(op, it.state, 0, hist=it.hist)["state"]   # substep n of the next step
+    s = Stepper(p, inp, stage=0)
+    for _ in range(3):
+        s.substep()
+    torch.cuda.synchronize()
+    got = dict(phi2=host(s.phi2), omega2=host(s.omega2), z=host(s.z), m1bar=host(s.m1bar), m3bar=host(s.m3bar))
+    errs = {k: rel(got[k], ref[k]) for k in got}
+    assert all(v < TOL for v in errs.values()), errs
