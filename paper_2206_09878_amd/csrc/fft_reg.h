@@ -98,10 +98,11 @@ struct Dft<24, DIR> {
 
 // ---- stages --------------------------------------------------------------------
 
+// positions are unsigned: divisions by the constant spans then need no sign fix-ups
 template <int N, int T, int R, int NS>
 __device__ __forceinline__ int out_pos(int tl, int c, int r) {
-  const int j = tl + T * c;
-  return (j / NS) * NS * R + (j % NS) + r * NS;
+  const unsigned j = unsigned(tl) + unsigned(T * c);
+  return int((j / unsigned(NS)) * unsigned(NS * R) + (j % unsigned(NS)) + unsigned(r * NS));
 }
 template <int N, int T, int R>
 __device__ __forceinline__ int in_pos(int tl, int c, int r) {
@@ -132,7 +133,7 @@ __device__ __forceinline__ void stage(double2* v, int tl, const double2* __restr
 // LDS addressing of position p of the line owned by this thread group
 template <int PADDIV>
 __device__ __forceinline__ int padded(int p) {
-  return PADDIV > 0 ? p + p / PADDIV : p;
+  return PADDIV > 0 ? int(unsigned(p) + unsigned(p) / unsigned(PADDIV)) : p;
 }
 
 // Move stage outputs (radix Ra, span NSa) to the next stage's inputs (radix Rb)
@@ -285,7 +286,7 @@ __device__ __forceinline__ void stage_lt(double2* v, int tl, const double2* tws)
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if constexpr (NS > 1) {
-      const int jm = (tl + T * c) % NS;
+      const int jm = int((unsigned(tl) + unsigned(T * c)) % unsigned(NS));
       double2 w1 = tws[jm];
       if (DIR > 0) w1.y = -w1.y;
       double2 w = w1;

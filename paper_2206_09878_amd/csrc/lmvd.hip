@@ -567,7 +567,7 @@ struct XPlan;
     static constexpr int BG = kThreads / T_;                     /* lines per block */               \
     static constexpr int STRIDE = ((N_ + N_ / PAD_) + 1) / 2 * 2; /* doubles per line, even */        \
   };
-LMVD_XPLAN(768, 64, 12, 4, 4, 4, 96)
+LMVD_XPLAN(768, 64, 12, 4, 4, 4, 64)
 LMVD_XPLAN(192, 16, 12, 4, 4, 1, 12)
 LMVD_XPLAN(144, 12, 12, 12, 1, 1, 12)
 LMVD_XPLAN(96, 8, 12, 4, 2, 1, 12)
