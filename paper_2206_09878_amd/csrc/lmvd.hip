@@ -814,12 +814,14 @@ struct Pair<PH_RHOT> {  // input z_t:  rho_t = f'(z) z_t
   __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
 };
 template <>
-struct Pair<PH_VEL> {  // inputs z, m1, m2, m3 -> u1, u2, u3, rho, C11, C12, C13, C22, C23, C33
+struct Pair<PH_VEL> {  // inputs z, m1, m2, m3 -> u1, u2, u3, rho, C11, C12, C13, C22, C23, C33 (fields 0..9)
   static constexpr int NP = 2, NQ = 5, NST = 4;
   __device__ static constexpr int fa(int i) { return 2 * i; }
   __device__ static constexpr int fb(int i) { return 2 * i + 1; }
-  __device__ static constexpr int ga(int q) { return 2 * q; }
-  __device__ static constexpr int gb(int q) { return 2 * q + 1; }
+  // output pairs ordered so that m1, then m2, then m3 is last used early
+  // (the transforms are unrolled): (C11, C12), (C13, u1), (C22, C23), (u2, rho), (C33, u3)
+  __device__ static constexpr int ga(int q) { return q == 0 ? 4 : q == 1 ? 6 : q == 2 ? 7 : q == 3 ? 1 : 9; }
+  __device__ static constexpr int gb(int q) { return q == 0 ? 5 : q == 1 ? 0 : q == 2 ? 8 : q == 3 ? 3 : 2; }
   template <int I>
   __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y, double*, size_t) {
     if constexpr (I == 0) {
@@ -833,11 +835,11 @@ struct Pair<PH_VEL> {  // inputs z, m1, m2, m3 -> u1, u2, u3, rho, C11, C12, C13
   template <int Q>
   __device__ __forceinline__ static double2 out(const DevPlan& P, const double* s) {
     const double ir = s[0] * P.inv_rlrh;
-    if constexpr (Q == 0) return make_double2(s[1] * ir, s[2] * ir);
-    else if constexpr (Q == 1) return make_double2(s[3] * ir, (P.rho_l * P.rho_h) / s[0]);
-    else if constexpr (Q == 2) return make_double2(-s[1] * (s[1] * ir), -s[1] * (s[2] * ir));
-    else if constexpr (Q == 3) return make_double2(-s[1] * (s[3] * ir), -s[2] * (s[2] * ir));
-    else return make_double2(-s[2] * (s[3] * ir), -s[3] * (s[3] * ir));
+    if constexpr (Q == 0) return make_double2(-s[1] * (s[1] * ir), -s[1] * (s[2] * ir));
+    else if constexpr (Q == 1) return make_double2(-s[1] * (s[3] * ir), s[1] * ir);
+    else if constexpr (Q == 2) return make_double2(-s[2] * (s[2] * ir), -s[2] * (s[3] * ir));
+    else if constexpr (Q == 3) return make_double2(s[2] * ir, (P.rho_l * P.rho_h) / s[0]);
+    else return make_double2(-s[3] * (s[3] * ir), s[3] * ir);
   }
 };
 template <>
@@ -992,7 +994,8 @@ __device__ __forceinline__ void xpair_body(const DevPlan& P, const double2* __re
     for (int q = 0; q < E; ++q) st[0][q] = bok ? src[T * q] : 0.0;
   }
   const double scale = 1.0 / (double(P.m1) * double(M3));
-#pragma unroll 1
+  // unrolled: with several outputs the state of a point dies output by output
+#pragma unroll
   for (int q = 0; q < S::NQ; ++q) {
     int tlx = tl, basex = base;
     asm volatile("" : "+v"(tlx), "+v"(basex));
