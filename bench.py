@@ -42,9 +42,10 @@ def kernel_symbol(cls: str, w) -> str:
     """Kernel symbol a class launches on the register-FFT sizes (as rocprofv3 names it)."""
     m1, m3 = w.m1, w.m3
     return {
-        "zinv": f"k_zinv_r<{m3}, true>", "zfwd": f"k_zfwd_r<{m3}>",
-        "xpass_rz": f"k_xpair<0, {m1}>", "xpass_rhot": f"k_xpair<1, {m1}>", "xpass_l": f"k_xpair<2, {m1}>",
-        "xpass_vel": f"k_xpair<3, {m1}>", "mc": "k_mc<7, 7, 6, true>", "md": "k_solveA<0, 7, 7>", "proj": "k_proj<0>",
+        "zinv": f"k_zinv_w<{m3}, true>" if m3 == 768 else f"k_zinv_r<{m3}, true>",
+        "zfwd": f"k_zfwd_w<{m3}>" if m3 == 768 else f"k_zfwd_r<{m3}>",
+        "xpass_rz": f"k_xpair<0, {m1}>", "xpass_rhot": f"k_xline<1, {m1}>", "xpass_l": f"k_xline<2, {m1}>",
+        "xpass_vel": f"k_xpair_w2<3, {m1}>", "mc": "k_mc<7, 7, 6, true>", "md": "k_md<7, 7, 8>", "proj": "k_proj<0>",
         "proj_zt": "k_proj<1>, k_proj<2>", "values": "k_values, k_values_z, k_guess_v",
         "flux": "k_flux<0, 8, 6>, k_flux<1, 8, 6>", "rhs": "k_rhs_fluct, k_rhs_mean",
     }.get(cls, cls)
@@ -150,7 +151,7 @@ def main():
     torch.cuda.synchronize()
 
     # dominant kernel class: one untimed substep per class with its launches timed
-    totals = {}
+    totals, tbytes = {}, {}
     if args.kernel_class is None:
         for cls in range(len(names)):
             if names[cls] == "xpass_io":
@@ -159,6 +160,7 @@ def main():
             stepper.substep()
             ms, n, b = plan.profile_stop()
             totals[cls] = ms
+            tbytes[cls] = b
         dom = max(totals, key=totals.get)
     else:
         dom = names.index(args.kernel_class)
@@ -203,6 +205,8 @@ def main():
         "substep_roofline": {"model_bytes_per_substep": model,
                              "frac": model * value / (HBM_PEAK_GBS * 1e9)},
         "kernel_class_ms_per_substep": {names[c]: totals[c] for c in totals},
+        "kernel_class_tbps": {names[c]: tbytes[c] / (totals[c] * 1e-3) / 1e12 for c in totals if totals[c] > 0},
+        "compulsory_bytes_per_substep": sum(tbytes.values()) if tbytes else None,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
