@@ -45,8 +45,8 @@ def kernel_symbol(cls: str, w) -> str:
         "zinv": f"k_zinv_w<{m3}, true>" if m3 == 768 else f"k_zinv_r<{m3}, true>",
         "zfwd": f"k_zfwd_w<{m3}>" if m3 == 768 else f"k_zfwd_r<{m3}>",
         "xpass_rz": f"k_xpair<0, {m1}>", "xpass_rhot": f"k_xline<1, {m1}>", "xpass_l": f"k_xline<2, {m1}>",
-        "xpass_vel": f"k_xpair_w2<3, {m1}>", "mc": "k_mc<7, 7, 6, true>", "md": "k_md<7, 7, 8>", "proj": "k_proj<0>",
-        "proj_zt": "k_proj<1>, k_proj<2>", "values": "k_values, k_values_z, k_guess_v",
+        "xpass_vel": f"k_xpair_w2<3, {m1}>", "mc": "k_mc<7, 7, 6, true>", "md": "k_prologue<7, 7, 8>", "proj": "k_proj<0>, k_proj3",
+        "proj_zt": "k_proj<1>, k_proj<2>", "values": "k_values",
         "flux": "k_flux<0, 8, 6>, k_flux<1, 8, 6>", "rhs": "k_rhs_fluct, k_rhs_mean",
     }.get(cls, cls)
 

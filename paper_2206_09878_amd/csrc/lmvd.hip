@@ -424,11 +424,17 @@ struct RowWindow {
 };
 
 // z -> E0 z, E1 z, (E2 - k^2 E0) z and i k3 E0 z at tau
-__global__ void __launch_bounds__(kThreads) k_values_z(DevPlan P, const double2* __restrict__ z, double2* __restrict__ V0,
-                                                       double2* __restrict__ V1, double2* __restrict__ VL,
-                                                       double2* __restrict__ V3) {
+struct ValuesZArgs {
+  const double2* z;
+  double2 *V0, *V1, *VL, *V3;
+};
+__device__ __forceinline__ void values_z_body(const DevPlan& P, size_t c, const ValuesZArgs& A) {
+  const double2* __restrict__ z = A.z;
+  double2* __restrict__ V0 = A.V0;
+  double2* __restrict__ V1 = A.V1;
+  double2* __restrict__ VL = A.VL;
+  double2* __restrict__ V3 = A.V3;
   const size_t ncol = size_t(P.nn) * P.nl;
-  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const int n2 = P.n2;
   const double k1 = P.k1[c % P.nl], k3 = P.k3[c / P.nl], ksq = k1 * k1 + k3 * k3;
@@ -479,13 +485,22 @@ __global__ void __launch_bounds__(kThreads) k_values(DevPlan P, const double2* _
 
 // BDF-like guess dt z_t^0 = a1 z + a2 h1 + a3 h2 + a4 h3 (eq. dzdt_guesses)
 // (or zero) as coefficients, and its E0 values at tau
-__global__ void __launch_bounds__(kThreads) k_guess_v(DevPlan P, const double2* __restrict__ z,
-                                                      const double2* __restrict__ h1, const double2* __restrict__ h2,
-                                                      const double2* __restrict__ h3, double a1, double a2, double a3,
-                                                      double a4, double dt, int zero, double2* __restrict__ zt,
-                                                      double2* __restrict__ V) {
+struct GuessArgs {
+  const double2 *z, *h1, *h2, *h3;
+  double a1, a2, a3, a4, dt;
+  int zero;
+  double2 *zt, *V;
+};
+__device__ __forceinline__ void guess_body(const DevPlan& P, size_t c, const GuessArgs& G) {
+  const double2* __restrict__ z = G.z;
+  const double2* __restrict__ h1 = G.h1;
+  const double2* __restrict__ h2 = G.h2;
+  const double2* __restrict__ h3 = G.h3;
+  const double a1 = G.a1, a2 = G.a2, a3 = G.a3, a4 = G.a4, dt = G.dt;
+  const int zero = G.zero;
+  double2* __restrict__ zt = G.zt;
+  double2* __restrict__ V = G.V;
   const size_t ncol = size_t(P.nn) * P.nl;
-  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const int n2 = P.n2;
   auto coef = [&](int r) -> double2 {
@@ -1233,12 +1248,11 @@ __global__ void __launch_bounds__(kThreads, 2) k_xpair_w2(DevPlan P, const doubl
 // column; forward sweep stores L^{-1} b in `out`, backward sweep overwrites it.
 
 template <int EPI>
-__global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const double2* in, double2* out,
-                                                   const double2* __restrict__ add, const double2* __restrict__ z,
-                                                   const double2* __restrict__ zt_prev, double2* __restrict__ z_out,
-                                                   double2* __restrict__ vals_out, double2* __restrict__ vals_out1,
-                                                   int stage, int ncol) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void proj_body(const DevPlan& P, int c, int kind, const double2* in, double2* out,
+                                          const double2* __restrict__ add, const double2* __restrict__ z,
+                                          const double2* __restrict__ zt_prev, double2* __restrict__ z_out,
+                                          double2* __restrict__ vals_out, double2* __restrict__ vals_out1,
+                                          int stage, int ncol) {
   if (c >= ncol) return;
   const int n2 = P.n2;
   const auto L = P.lu_l + size_t(kind) * n2 * kMaxBand;
@@ -1309,6 +1323,27 @@ __global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const do
       }
     }
   }
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(kThreads) k_proj(DevPlan P, int kind, const double2* in, double2* out,
+                                                   const double2* __restrict__ add, const double2* __restrict__ z,
+                                                   const double2* __restrict__ zt_prev, double2* __restrict__ z_out,
+                                                   double2* __restrict__ vals_out, double2* __restrict__ vals_out1,
+                                                   int stage, int ncol) {
+  proj_body<EPI>(P, int(blockIdx.x * blockDim.x + threadIdx.x), kind, in, out, add, z, zt_prev, z_out, vals_out,
+                 vals_out1, stage, ncol);
+}
+
+// Independent plain projections of the same kind in one launch (field blockIdx.y).
+struct ProjBatch {
+  const double2* in[3];
+  double2* out[3];
+};
+__global__ void __launch_bounds__(kThreads) k_proj3(DevPlan P, int kind, ProjBatch B, int ncol) {
+  const int f = blockIdx.y;
+  proj_body<EPI_STORE>(P, int(blockIdx.x * blockDim.x + threadIdx.x), kind, B.in[f], B.out[f], nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, 0, ncol);
 }
 
 // ---------------------------------------------------------------------------
@@ -2059,16 +2094,26 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
 //        m2 = F0 c,  m1 = (i k1 F1 c - i k3 E0 Omega2)/k^2,  m3 = (i k3 F1 c + i k1 E0 Omega2)/k^2
 //      (F1 = E0 D*, Omega2 read through a second window).
 // Plane mean: m^d = (<m>1, 0, <m>3).  With c2o the coefficients are written too.
+struct MdArgs {
+  const double2 *phi, *om;
+  const double *m1bar, *m3bar;
+  double2 *yt, *V1, *V2, *V3, *c2o, *m1o, *m3o;
+};
 template <int LA, int UA, int W>
-__global__ void __launch_bounds__(kThreads) k_md(DevPlan P, const double2* __restrict__ phi,
-                                                const double2* __restrict__ om, const double* __restrict__ m1bar,
-                                                const double* __restrict__ m3bar, double2* yt,
-                                                double2* __restrict__ V1, double2* __restrict__ V2,
-                                                double2* __restrict__ V3, double2* __restrict__ c2o,
-                                                double2* __restrict__ m1o, double2* __restrict__ m3o) {
+__device__ __forceinline__ void md_body(const DevPlan& P, int t, const MdArgs& A) {
+  const double2* __restrict__ phi = A.phi;
+  const double2* __restrict__ om = A.om;
+  const double* __restrict__ m1bar = A.m1bar;
+  const double* __restrict__ m3bar = A.m3bar;
+  double2* yt = A.yt;
+  double2* __restrict__ V1 = A.V1;
+  double2* __restrict__ V2 = A.V2;
+  double2* __restrict__ V3 = A.V3;
+  double2* __restrict__ c2o = A.c2o;
+  double2* __restrict__ m1o = A.m1o;
+  double2* __restrict__ m3o = A.m3o;
   const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
   const int half = (nn + 1) / 2, npairs = nl * half;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int pr = t >> 1, side = t & 1;
   if (pr >= npairs) return;
   const int l = pr % nl, pp = pr / nl;
@@ -2201,6 +2246,19 @@ __global__ void __launch_bounds__(kThreads) k_md(DevPlan P, const double2* __res
       }
     }
   }
+}
+
+// The substep's first column work in one launch, one job per blockIdx.y (the
+// jobs are independent; together they fill the GPU better than one by one):
+// job 0 m^d and its values (only when `md` is set), then the values of z and
+// the BDF-like guess.
+template <int LA, int UA, int W>
+__global__ void __launch_bounds__(kThreads) k_prologue(DevPlan P, int md, MdArgs M, ValuesZArgs Z, GuessArgs G) {
+  const int job = int(blockIdx.y) + (md ? 0 : 1);
+  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (job == 0) md_body<LA, UA, W>(P, int(t), M);
+  else if (job == 1) values_z_body(P, t, Z);
+  else guess_body(P, t, G);
 }
 
 // ---------------------------------------------------------------------------
@@ -2643,7 +2701,7 @@ enum KClass {
   KC_XPASS_VEL = 4,  // x-pass of u, rho, C_ij
   KC_ZFWD = 5,       // forward z transforms (all phases)
   KC_MC = 6,         // fused m^c column kernel
-  KC_MD = 7,         // m^d solve
+  KC_MD = 7,         // m^d solve with the z values and the guess in the same launch
   KC_PROJ = 8,       // projection with plain store (u_hat, R_z)
   KC_PROJ_ZT = 9,    // projection + R_z add (+ z update) of the fixed-point iterate
   KC_VALUES = 10,    // values at tau of fixed fields (m^d, z, guess)
@@ -2953,32 +3011,43 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     hipLaunchKernelGGL(k_values, cgrid, dim3(kThreads), 0, s, p->D, a1, v1, a2, v2, a3, v3);
   };
 
-  // 1. m^d and its values at tau
+  // guess coefficients of the BDF-like extrapolation
+  const double bn = H.cfg.beta_n, bp = H.cfg.beta_p;
+  double co[4];
+  if (a->stage == 0) {
+    co[0] = 2.0; co[1] = -2.0 - 0.5 * bn; co[2] = bn; co[3] = -0.5 * bn;
+  } else {
+    co[0] = 4.0 + bp; co[1] = -5.0 - 2.0 * bp; co[2] = bp; co[3] = 1.0;
+  }
+  double2* gdst = (kf == 0 && user_zt) ? user_zt : zta;
+  const int zero = (a->guess_mode == 1) ? 1 : 0;
+  const ValuesZArgs zargs{z, vz0, vz1, vzl, vz3};
+  const GuessArgs gargs{z, static_cast<const double2*>(a->z_hist[0]), static_cast<const double2*>(a->z_hist[1]),
+                        static_cast<const double2*>(a->z_hist[2]), co[0], co[1], co[2], co[3], H.cfg.dt, zero,
+                        gdst, vzt};
+  // 1. m^d and its values at tau, the values of z (fixed during the substep) and the guess
   if (H.p == 8) {
     ensure_factors(p, s);
     const int nth = 2 * H.nl * ((H.nn + 1) / 2);
     const bool diag = a->md[0] || a->md[1] || a->md[2];
-    // phi2, Omega2 in, 3 value fields out, A(k) sweep intermediate out and back, factors once per pair
-    // (+ the coefficients when requested)
+    // m^d: phi2, Omega2 in, 3 value fields out, A(k) sweep intermediate out and back, factors once per
+    // pair (+ the coefficients when requested); z values: 1 in, 4 out; guess: 4 (or 1) in, 2 out
     ProfScope ps(p, KC_MD, s,
                  16.0 * nB * (diag ? 7.0 : 5.0) + 16.0 * ncol * (H.n2 + 1) * (diag ? 3.0 : 2.0) +
-                     8.0 * H.fac_slots * (nth / 2));
-    const dim3 g((nth + kThreads - 1) / kThreads);
-    double2* yt = c.at<double2>(W.off_yt);
+                     8.0 * H.fac_slots * (nth / 2) + 16.0 * nB * 5 + 16.0 * nB * (zero ? 2 : 6));
+    const dim3 g((unsigned(std::max<size_t>(nth, ncol)) + kThreads - 1) / kThreads, 3);
+    const MdArgs margs{phi2, om2, a->m1bar, a->m3bar, c.at<double2>(W.off_yt), vmd1, vc2d, vmd3,
+                       diag ? c2d : nullptr, diag ? md1 : nullptr, diag ? md3 : nullptr};
     if (p->fac_la == 7)
-      hipLaunchKernelGGL((k_md<7, 7, 8>), g, dim3(kThreads), 0, s, p->D, phi2, om2, a->m1bar, a->m3bar, yt, vmd1,
-                         vc2d, vmd3, diag ? c2d : nullptr, diag ? md1 : nullptr, diag ? md3 : nullptr);
+      hipLaunchKernelGGL((k_prologue<7, 7, 8>), g, dim3(kThreads), 0, s, p->D, 1, margs, zargs, gargs);
     else
-      hipLaunchKernelGGL((k_md<8, 8, 8>), g, dim3(kThreads), 0, s, p->D, phi2, om2, a->m1bar, a->m3bar, yt, vmd1,
-                         vc2d, vmd3, diag ? c2d : nullptr, diag ? md1 : nullptr, diag ? md3 : nullptr);
+      hipLaunchKernelGGL((k_prologue<8, 8, 8>), g, dim3(kThreads), 0, s, p->D, 1, margs, zargs, gargs);
   } else {
     solveA<0>(c, phi2, om2, a->m1bar, a->m3bar, c2d, md1, md3);
     values(md1, vmd1, md3, vmd3, c2d, vc2d);
-  }
-  // values of z and its y-derivatives (z is fixed during the substep)
-  {
-    ProfScope ps(p, KC_VALUES, s, 16.0 * nB * 5);
-    hipLaunchKernelGGL(k_values_z, cgrid, dim3(kThreads), 0, s, p->D, z, vz0, vz1, vzl, vz3);
+    ProfScope ps(p, KC_VALUES, s, 16.0 * nB * 5 + 16.0 * nB * (zero ? 2 : 6));
+    const MdArgs none{};
+    hipLaunchKernelGGL((k_prologue<8, 8, 8>), dim3(cgrid.x, 2), dim3(kThreads), 0, s, p->D, 0, none, zargs, gargs);
   }
   // 2. R_z
   st = plane_phase<PH_RZ>(c,
@@ -2987,23 +3056,7 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
                           {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
-  // guess (coefficients and values)
   {
-    const double bn = H.cfg.beta_n, bp = H.cfg.beta_p;
-    double co[4];
-    if (a->stage == 0) {
-      co[0] = 2.0; co[1] = -2.0 - 0.5 * bn; co[2] = bn; co[3] = -0.5 * bn;
-    } else {
-      co[0] = 4.0 + bp; co[1] = -5.0 - 2.0 * bp; co[2] = bp; co[3] = 1.0;
-    }
-    double2* gdst = (kf == 0 && user_zt) ? user_zt : zta;
-    const int zero = (a->guess_mode == 1) ? 1 : 0;
-    {
-      ProfScope ps(p, KC_VALUES, s, 16.0 * nB * (zero ? 2 : 6));
-      hipLaunchKernelGGL(k_guess_v, cgrid, dim3(kThreads), 0, s, p->D, z, static_cast<const double2*>(a->z_hist[0]),
-                         static_cast<const double2*>(a->z_hist[1]), static_cast<const double2*>(a->z_hist[2]), co[0],
-                         co[1], co[2], co[3], H.cfg.dt, zero, gdst, vzt);
-    }
     if (kf == 0) {
       hipLaunchKernelGGL(k_zupdate, dim3((nB + kThreads - 1) / kThreads), dim3(kThreads), 0, s, z, gdst,
                          static_cast<const double2*>(a->zt_prev), static_cast<double2*>(a->z_out), H.cfg.dt, a->stage,
@@ -3048,7 +3101,12 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   st = plane_phase<PH_VEL>(c, {ev(vz0, EV_IDENT), m1, m2, m3},
                            {vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]});
   if (st != LMVD_OK) return st;
-  for (int i = 0; i < 3; ++i) proj(c, 0, vals[i], u[i]);
+  {
+    const int n = int(ncol);
+    ProfScope ps(p, KC_PROJ, s, 3 * 4.0 * 16.0 * nB);
+    const ProjBatch B{{vals[0], vals[1], vals[2]}, {u[0], u[1], u[2]}};
+    hipLaunchKernelGGL(k_proj3, dim3((n + kThreads - 1) / kThreads, 3), dim3(kThreads), 0, s, p->D, 0, B, n);
+  }
   // fluxes and their share of the RHS values at tau (RO: Omega2, RP: phi2)
   double2* RO = vals[0];
   double2* RP = vals[1];
