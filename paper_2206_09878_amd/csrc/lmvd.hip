@@ -927,6 +927,49 @@ __device__ __forceinline__ void pair_out(const DevPlan& P, int q, const double (
 
 // x-pass: per (plane, z line b) inverse x-FFTs of the inputs, products,
 // forward x-FFTs of the outputs, m1 = N points, retained modes l < N/3.
+// Transform input Z = X + i Y of a line pair from the N/3 retained modes of
+// X (at XA) and Y (at XB; absent when !HASB): Z_k = X_k + i Y_k for k < N/3
+// (imaginary parts of X_0, Y_0 dropped), Z_{N-k} = conj(X_k) + i conj(Y_k),
+// zero in between.  oka / okb false: that line is absent (its pointer must
+// still be readable).  N/3 and 2N/3 are multiples of T, so the class of each
+// point is known at compile time; every load is issued before any is used.
+template <int N, int T, bool HASB>
+__device__ __forceinline__ void herm_pair_load(double2* v, const double2* __restrict__ XA,
+                                               const double2* __restrict__ XB, int tl, bool oka, bool okb) {
+  constexpr int E = N / T, NL = N / 3;
+  static_assert(NL % T == 0, "retained band must be whole rows of T points");
+  double2 a[E], b[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    a[r] = b[r] = zero2();
+    if (T * r + T <= NL) {
+      a[r] = XA[tl + T * r];
+      if (HASB) b[r] = XB[tl + T * r];
+    } else if (T * r >= N - NL) {
+      const int m = N - T * r - tl;  // in [1, N/3]
+      const int mm = m < NL ? m : 0;
+      a[r] = XA[mm];
+      if (HASB) b[r] = XB[mm];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    double2 xa = oka ? a[r] : zero2();
+    double2 xb = (HASB && okb) ? b[r] : zero2();
+    double2 z = zero2();
+    if (T * r + T <= NL) {
+      if (r == 0 && tl == 0) {
+        xa.y = 0.0;
+        xb.y = 0.0;
+      }
+      z = make_double2(xa.x - xb.y, xa.y + xb.x);
+    } else if (T * r >= N - NL) {
+      if (N - T * r - tl < NL) z = make_double2(xa.x + xb.y, xb.x - xa.y);
+    }
+    v[r] = z;
+  }
+}
+
 // Spectral line X_l (l < N/3) of a real field; a pair X, Y enters one
 // transform as Z_l = X_l + i Y_l, Z_{N-l} = conj(X_l) + i conj(Y_l), with
 // the real parts of X_0, Y_0 (what the Hermitian extension keeps).  An
@@ -944,7 +987,9 @@ __device__ __forceinline__ void xpair_body(const DevPlan& P, const double2* __re
   extern __shared__ double lds_d[];
   double2* twl = reinterpret_cast<double2*>(lds_d + BG * LP::STRIDE);
   const int tid = threadIdx.x;
-  const int tl = tid % T, line = tid / T;
+  // one line per wavefront when T is the wave size: the line index is then
+  // uniform, and so are the line's base addresses (scalar registers)
+  const int tl = tid % T, line = (T == 64) ? __builtin_amdgcn_readfirstlane(tid / T) : tid / T;
   const int jj = blockIdx.y, b = blockIdx.x * BG + line;
   const int M3 = P.m3;
   const bool bok = b < M3;
@@ -967,27 +1012,8 @@ __device__ __forceinline__ void xpair_body(const DevPlan& P, const double2* __re
     const int fa = S::fa(i), fb = S::fb(i);
     const double2* XA = zbuf + ((size_t(fa) * pb + jj) * M3 + bb) * NL;
     const double2* XB = zbuf + ((size_t(fb < 0 ? fa : fb) * pb + jj) * M3 + bb) * NL;
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      double2 z = zero2();
-      if (!(T * r >= NL && T * r + T - 1 <= N - NL) && bok) {
-        const int pos = tlx + T * r;
-        if (pos < NL) {
-          double2 xa = XA[pos];
-          double2 xb = fb >= 0 ? XB[pos] : zero2();
-          if (pos == 0) {
-            xa.y = 0.0;
-            xb.y = 0.0;
-          }
-          z = make_double2(xa.x - xb.y, xa.y + xb.x);
-        } else if (pos > N - NL) {
-          const double2 xa = XA[N - pos];
-          const double2 xb = fb >= 0 ? XB[N - pos] : zero2();
-          z = make_double2(xa.x + xb.y, xb.x - xa.y);
-        }
-      }
-      v[r] = z;
-    }
+    if (fb >= 0) herm_pair_load<N, T, true>(v, XA, XB, tlx, bok, bok);
+    else herm_pair_load<N, T, false>(v, XA, XA, tlx, bok, bok);
     rf::run_split<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, basex, tlx, twl);
     if constexpr (PH == PH_TOPHYS) {
 #pragma unroll
@@ -1128,7 +1154,7 @@ __global__ void __launch_bounds__(kThreads) k_xline(DevPlan P, const double2* __
   extern __shared__ double lds_d[];
   double2* twl = reinterpret_cast<double2*>(lds_d + BG * LP::STRIDE);
   const int tid = threadIdx.x;
-  const int tl = tid % T, grp = tid / T;
+  const int tl = tid % T, grp = (T == 64) ? __builtin_amdgcn_readfirstlane(tid / T) : tid / T;
   const int jj = blockIdx.y;
   const int b0 = 2 * (blockIdx.x * BG + grp), b1 = b0 + 1;
   const int M3 = P.m3;
@@ -1150,27 +1176,7 @@ __global__ void __launch_bounds__(kThreads) k_xline(DevPlan P, const double2* __
     asm volatile("" : "+v"(tlx), "+v"(basex));
     const double2* XA = zbuf + ((size_t(i) * pb + jj) * M3 + c0) * NL;
     const double2* XB = zbuf + ((size_t(i) * pb + jj) * M3 + c1) * NL;
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      double2 z = zero2();
-      if (!(T * r >= NL && T * r + T - 1 <= N - NL)) {
-        const int pos = tlx + T * r;
-        if (pos < NL) {
-          double2 xa = ok0 ? XA[pos] : zero2();
-          double2 xb = ok1 ? XB[pos] : zero2();
-          if (pos == 0) {
-            xa.y = 0.0;
-            xb.y = 0.0;
-          }
-          z = make_double2(xa.x - xb.y, xa.y + xb.x);
-        } else if (pos > N - NL) {
-          const double2 xa = ok0 ? XA[N - pos] : zero2();
-          const double2 xb = ok1 ? XB[N - pos] : zero2();
-          z = make_double2(xa.x + xb.y, xb.x - xa.y);
-        }
-      }
-      v[r] = z;
-    }
+    herm_pair_load<N, T, true>(v, XA, XB, tlx, ok0, ok1);
     rf::run_split<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, basex, tlx, twl);
     const double* ai0 = a0 + S::aux_field(i) * fs;
     const double* ai1 = a1 + S::aux_field(i) * fs;
