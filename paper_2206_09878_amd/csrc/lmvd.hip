@@ -705,20 +705,35 @@ __global__ void __launch_bounds__(kZWThreads) k_zinv_w(DevPlan P, EvalArgs A, do
   const bool lok = l < nl;
   const size_t ncol = size_t(nn) * nl;
   const double k1 = (lok && in.ma == MU_IK1) ? P.k1[l] : 0.0;
-  const double2* src = in.a + size_t(j) * ncol + (lok ? l : 0);
+  const size_t col0 = size_t(j) * ncol + (lok ? l : 0);
   double2 v[E];
+  // all loads issued before any is used: absent points read mode 0 and are
+  // then zeroed; the optional second field is a uniform branch around the batch
+  auto load = [&](auto hasb) {
+    const double2* __restrict__ sa = in.a + col0;
+    const double2* __restrict__ sb = (hasb ? in.b : in.a) + col0;
+    double2 xa[E], xb[E];
 #pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int pos = tl + T * r;
-    const bool always_pad = EXACT && (T * r >= H3X) && (T * r + T - 1 < H3X + PADX);
-    double2 val = zero2();
-    if (!always_pad && lok && (pos < h3 || pos >= h3 + pad)) {
-      const int ni = pos < h3 ? pos : pos - pad;
-      val = src[size_t(ni) * nl];
-      if (in.b) val = cadd(val, in.b[size_t(j) * ncol + size_t(ni) * nl + l]);
+    for (int r = 0; r < E; ++r) {
+      const int pos = tl + T * r;
+      const bool always_pad = EXACT && (T * r >= H3X) && (T * r + T - 1 < H3X + PADX);
+      xa[r] = xb[r] = zero2();
+      if (!always_pad) {
+        const bool ok = lok && (pos < h3 || pos >= h3 + pad);
+        const int ni = !ok ? 0 : (pos < h3 ? pos : pos - pad);
+        xa[r] = sa[size_t(ni) * nl];
+        if (hasb) xb[r] = sb[size_t(ni) * nl];
+      }
     }
-    v[r] = val;
-  }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int pos = tl + T * r;
+      const bool ok = lok && (pos < h3 || pos >= h3 + pad);
+      v[r] = ok ? (hasb ? cadd(xa[r], xb[r]) : xa[r]) : zero2();
+    }
+  };
+  if (in.b) load(std::true_type{});
+  else load(std::false_type{});
   if (in.ma == MU_IK1) {
 #pragma unroll
     for (int r = 0; r < E; ++r) v[r] = make_double2(-k1 * v[r].y, k1 * v[r].x);
