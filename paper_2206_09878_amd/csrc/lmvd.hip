@@ -940,8 +940,19 @@ __device__ __forceinline__ void pair_out(const DevPlan& P, int q, const double (
   }
 }
 
-// x-pass: per (plane, z line b) inverse x-FFTs of the inputs, products,
-// forward x-FFTs of the outputs, m1 = N points, retained modes l < N/3.
+// Restores the range 0 <= t < T of a lane index made opaque to the compiler,
+// so that positions t + (multiple of the padding period) fold to immediate
+// LDS offsets.
+template <int T>
+__device__ __forceinline__ int lane_in_line(int t) {
+  if constexpr ((T & (T - 1)) == 0) {
+    return t & (T - 1);
+  } else {
+    __builtin_assume(t >= 0 && t < T);
+    return t;
+  }
+}
+
 // Transform input Z = X + i Y of a line pair from the N/3 retained modes of
 // X (at XA) and Y (at XB; absent when !HASB): Z_k = X_k + i Y_k for k < N/3
 // (imaginary parts of X_0, Y_0 dropped), Z_{N-k} = conj(X_k) + i conj(Y_k),
@@ -985,6 +996,8 @@ __device__ __forceinline__ void herm_pair_load(double2* v, const double2* __rest
   }
 }
 
+// x-pass: per (plane, z line b) inverse x-FFTs of the inputs, products,
+// forward x-FFTs of the outputs, m1 = N points, retained modes l < N/3.
 // Spectral line X_l (l < N/3) of a real field; a pair X, Y enters one
 // transform as Z_l = X_l + i Y_l, Z_{N-l} = conj(X_l) + i conj(Y_l), with
 // the real parts of X_0, Y_0 (what the Hermitian extension keeps).  An
@@ -1024,6 +1037,7 @@ __device__ __forceinline__ void xpair_body(const DevPlan& P, const double2* __re
     // and twiddle of the transform out of the loop (register pressure)
     int tlx = tl, basex = base;
     asm volatile("" : "+v"(tlx), "+v"(basex));
+    tlx = lane_in_line<T>(tlx);
     const int fa = S::fa(i), fb = S::fb(i);
     const double2* XA = zbuf + ((size_t(fa) * pb + jj) * M3 + bb) * NL;
     const double2* XB = zbuf + ((size_t(fb < 0 ? fa : fb) * pb + jj) * M3 + bb) * NL;
@@ -1055,6 +1069,7 @@ __device__ __forceinline__ void xpair_body(const DevPlan& P, const double2* __re
   for (int q = 0; q < S::NQ; ++q) {
     int tlx = tl, basex = base;
     asm volatile("" : "+v"(tlx), "+v"(basex));
+    tlx = lane_in_line<T>(tlx);
     pair_out<S, 0, E, S::NST>(P, q, st, v);
     rf::run_split<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, basex, tlx, twl);
     // W at point q' = c + r EL (k = tl + T q')
@@ -1189,6 +1204,7 @@ __global__ void __launch_bounds__(kThreads) k_xline(DevPlan P, const double2* __
   for (int i = 0; i < S::NP; ++i) {
     int tlx = tl, basex = base;
     asm volatile("" : "+v"(tlx), "+v"(basex));
+    tlx = lane_in_line<T>(tlx);
     const double2* XA = zbuf + ((size_t(i) * pb + jj) * M3 + c0) * NL;
     const double2* XB = zbuf + ((size_t(i) * pb + jj) * M3 + c1) * NL;
     herm_pair_load<N, T, true>(v, XA, XB, tlx, ok0, ok1);
@@ -1203,6 +1219,7 @@ __global__ void __launch_bounds__(kThreads) k_xline(DevPlan P, const double2* __
   for (int q = 0; q < S::NQ; ++q) {
     int tlx = tl, basex = base;
     asm volatile("" : "+v"(tlx), "+v"(basex));
+    tlx = lane_in_line<T>(tlx);
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = make_double2(s0[e], s1[e]);
     rf::run_split<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, basex, tlx, twl);
@@ -1262,6 +1279,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_xpair_w2(DevPlan P, const doubl
                                                          const double* phys_in, int j0, double* __restrict__ aux) {
   xpair_body<PH, N>(P, zbuf, obuf, pb, phys_out, phys_in, j0, aux);
 }
+
 
 // ---------------------------------------------------------------------------
 // column kernel: projection values -> B coefficients with a shared no-pivot LU
