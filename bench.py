@@ -77,6 +77,34 @@ def substep_model_bytes(w, kf):
     return (87 + 16 * kf) * s
 
 
+def hbm_ceiling(gib, reps=10):
+    """Achieved bandwidth of plain streaming kernels (torch's copy, fill, sum and add) over
+    GIB-sized FP64 buffers, timed with HIP events: the practical ceiling for the substep's kernels."""
+    import torch
+    n = int(gib * 2**30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    nb = 8.0 * n
+    return {"buffer_gib": gib, "unit": "TB/s",
+            "copy_read1_write1": 2 * nb / timed(lambda: c.copy_(a)) / 1e12,
+            "fill_write1": nb / timed(lambda: c.fill_(1.5)) / 1e12,
+            "sum_read1": nb / timed(lambda: a.sum()) / 1e12,
+            "add_read2_write1": 3 * nb / timed(lambda: torch.add(a, b, out=c)) / 1e12}
+
+
 def cpu_baseline(full, n=128, n2=129):
     """The oracle, untouched, on a bounded sample: one substep of the same
     workload recipe at n x n2 x n, scaled to the full size by the ratio of
@@ -120,7 +148,13 @@ def main():
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only copy a GIB-sized device buffer three times (reference kernel for the HBM "
                          "byte counters) and exit")
+    ap.add_argument("--hbm-ceiling", type=float, default=0.0, metavar="GIB",
+                    help="only time plain streaming kernels over GIB-sized buffers (the practical HBM "
+                         "ceiling) and exit")
     args = ap.parse_args()
+    if args.hbm_ceiling > 0:
+        print(json.dumps(hbm_ceiling(args.hbm_ceiling)), flush=True)
+        return
     if args.copy_calibration > 0:
         import torch
         n = int(args.copy_calibration * 2**30) // 8
