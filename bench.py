@@ -13,6 +13,7 @@ Prints one JSON line with substeps/s, the roofline of the dominant kernel
 oracle baseline.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+    python bench.py --workload batch64     (64 small uneven instances, one HIP graph)
 """
 from __future__ import annotations
 
@@ -105,6 +106,53 @@ def hbm_ceiling(gib, reps=10):
             "add_read2_write1": 3 * nb / timed(lambda: torch.add(a, b, out=c)) / 1e12}
 
 
+def bench_batch(args, count=64, nsub=4):
+    """64 independent small instances of uneven sizes: all of them advanced by one
+    HIP graph launch (nsub substeps each), against the same substeps launched one
+    by one on the plain path, instance after instance, on one stream."""
+    import torch
+
+    from paper_2206_09878_amd.lmvd import GraphBatch, Plan, Stepper
+    from paper_2206_09878_amd.workloads import batch_workloads, make_inputs
+    ws = batch_workloads(count)
+    st = [Stepper(Plan(w), make_inputs(w, seed=w.extra["seed"], stage=0), stage=0) for w in ws]
+    t0 = time.perf_counter()
+    g = GraphBatch(st, nsub=nsub)
+    build_s = time.perf_counter() - t0
+
+    def eager():
+        for s in st:
+            for _ in range(nsub):
+                s.substep()
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    for _ in range(max(args.warmup, 1)):
+        g.launch()
+        eager()
+    tg = timed(g.launch, args.steps)
+    te = timed(eager, args.steps)
+    subs = count * nsub * args.steps
+    pts = sum(w.m1 * w.m3 * w.n2 for w in ws) * nsub * args.steps
+    return {"metric": f"instance-substeps/s, {count} uneven instances in one HIP graph", "value": subs / tg,
+            "unit": "instance-substeps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1e3 * tg / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"batch{count}: N1, N3 in {{32,48,64,96}}, n2 in {{33,49,65,97}}, density ratio "
+                                   f"U[2,25], seeds 1000..{999 + count}; a step = one graph launch = {nsub} substeps "
+                                   f"of every instance", "kf": ws[0].kf},
+            "grid_point_substeps_per_s": pts / tg,
+            "one_by_one": {"value": subs / te, "ms_per_step": 1e3 * te / args.steps,
+                           "grid_point_substeps_per_s": pts / te},
+            "graph_speedup": te / tg, "graph_build_s": build_s}
+
+
 def cpu_baseline(full, n=128, n2=129):
     """The oracle, untouched, on a bounded sample: one substep of the same
     workload recipe at n x n2 x n, scaled to the full size by the ratio of
@@ -177,6 +225,9 @@ def main():
     from paper_2206_09878_amd.workloads import make_inputs, workload
 
     torch.cuda.set_device(0)
+    if args.workload == "batch64":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
     w = workload(args.workload)
     plan = Plan(w, plane_batch=args.plane_batch)
     stepper = Stepper(plan, make_inputs(w, seed=2, stage=0), stage=0)

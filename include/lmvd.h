@@ -149,6 +149,35 @@ lmvd_status lmvd_sizes(lmvd_plan plan, size_t* sfield_elems, size_t* sfield_star
 lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* args, void* workspace,
                          void* stream);
 
+/* ---- many independent simulations in one HIP graph ----
+ * For small problems, where one substep is a few dozen short launches, the
+ * substeps of many independent instances (each its own plan, workspace and
+ * state; any sizes the plans support) are captured into one HIP graph whose
+ * instances are independent branches; one lmvd_graph_launch runs `nsub`
+ * substeps of every instance.
+ *
+ * lmvd_graph_create: plans[count], workspaces[count] (one per instance,
+ * distinct), args[count * nsub] with args[i * nsub + k] the k-th substep of
+ * instance i (same rules as lmvd_substep; the diagnostic outputs md, mc must
+ * be NULL).  The argument structs are read during the call only, but every
+ * device pointer in them is baked into the graph: those buffers must stay
+ * allocated, at the same addresses, while the graph exists.  A sequence of
+ * args whose pointers repeat after nsub substeps (a history ring of period
+ * nsub, with the stages alternating) makes repeated launches keep advancing
+ * the simulations.  Computes each plan's A(k) factors first if needed
+ * (synchronously).  No plan may have its timing hook active.  Host-synchronous;
+ * launches nothing else.  Errors: LMVD_EINVAL for bad arguments, LMVD_EHIP if
+ * capture or instantiation fails (nothing is left allocated).
+ * lmvd_graph_launch: asynchronous on `stream`; launches of one graph, and of
+ * lmvd_substep on the same plans, must not overlap.
+ * lmvd_graph_destroy: frees the graph (not the buffers it refers to). */
+typedef struct lmvd_graph_s* lmvd_graph;
+lmvd_status lmvd_graph_create(const lmvd_plan* plans, const lmvd_substep_args* args,
+                              void* const* workspaces, int32_t count, int32_t nsub,
+                              lmvd_graph* out);
+lmvd_status lmvd_graph_launch(lmvd_graph graph, void* stream);
+lmvd_status lmvd_graph_destroy(lmvd_graph graph);
+
 /* ---- operator entry points (same conventions), one per stage of the path ----
  * They expose the steps of the substep individually for verification. */
 

@@ -3210,6 +3210,29 @@ static bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) 
 
 using namespace lmvd;
 
+namespace lmvd {
+// Argument checks of one substep (pointers present and aligned, stage and
+// guess mode valid, the history and the stage's RHS buffers given).
+static lmvd_status check_substep_args(lmvd_plan plan, const lmvd_substep_args* a, const void* workspace) {
+  if (!plan || !a || !workspace) return LMVD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
+  if (a->stage != 0 && a->stage != 1) return LMVD_EINVAL;
+  if (a->guess_mode != 0 && a->guess_mode != 1) return LMVD_EINVAL;
+  const void* req[] = {a->phi2, a->omega2, a->z, a->m1bar, a->m3bar, a->phi2_out, a->omega2_out, a->z_out,
+                       a->m1bar_out, a->m3bar_out};
+  for (const void* q : req)
+    if (!q || !aligned(q)) return LMVD_EINVAL;
+  if (a->z_out == a->z) return LMVD_EINVAL;
+  if (a->stage == 0 && (!a->rhs_phi2 || !a->rhs_omega2 || !a->zt || !a->rhs_m1 || !a->rhs_m3)) return LMVD_EINVAL;
+  if (a->stage == 1 && (!a->rhs_phi2_prev || !a->rhs_omega2_prev || !a->zt_prev || !a->rhs_m1_prev ||
+                        !a->rhs_m3_prev))
+    return LMVD_EINVAL;
+  if (a->guess_mode == 0 && (!a->z_hist[0] || !a->z_hist[1] || !a->z_hist[2])) return LMVD_EINVAL;
+  if (a->kf < -1 || a->kf > 10000) return LMVD_EINVAL;
+  return LMVD_OK;
+}
+}  // namespace lmvd
+
 extern "C" {
 
 const char* lmvd_status_string(lmvd_status s) {
@@ -3249,21 +3272,8 @@ lmvd_status lmvd_sizes(lmvd_plan plan, size_t* se, size_t* ss, size_t* wb) {
 }
 
 lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* a, void* workspace, void* stream) {
-  if (!plan || !a || !workspace) return LMVD_EINVAL;
-  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
-  if (a->stage != 0 && a->stage != 1) return LMVD_EINVAL;
-  if (a->guess_mode != 0 && a->guess_mode != 1) return LMVD_EINVAL;
-  const void* req[] = {a->phi2, a->omega2, a->z, a->m1bar, a->m3bar, a->phi2_out, a->omega2_out, a->z_out,
-                       a->m1bar_out, a->m3bar_out};
-  for (const void* q : req)
-    if (!q || !aligned(q)) return LMVD_EINVAL;
-  if (a->z_out == a->z) return LMVD_EINVAL;
-  if (a->stage == 0 && (!a->rhs_phi2 || !a->rhs_omega2 || !a->zt || !a->rhs_m1 || !a->rhs_m3)) return LMVD_EINVAL;
-  if (a->stage == 1 && (!a->rhs_phi2_prev || !a->rhs_omega2_prev || !a->zt_prev || !a->rhs_m1_prev ||
-                        !a->rhs_m3_prev))
-    return LMVD_EINVAL;
-  if (a->guess_mode == 0 && (!a->z_hist[0] || !a->z_hist[1] || !a->z_hist[2])) return LMVD_EINVAL;
-  if (a->kf < -1 || a->kf > 10000) return LMVD_EINVAL;
+  const lmvd_status ck = lmvd::check_substep_args(plan, a, workspace);
+  if (ck != LMVD_OK) return ck;
   if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   lmvd_status st = run_substep(plan, a, workspace, s);
@@ -3275,6 +3285,102 @@ lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* a, void* works
                        static_cast<double2*>(a->mc[0]), static_cast<double2*>(a->mc[2]));
   }
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+struct lmvd_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+lmvd_status lmvd_graph_create(const lmvd_plan* plans, const lmvd_substep_args* args, void* const* workspaces,
+                              int32_t count, int32_t nsub, lmvd_graph* out) {
+  if (!plans || !args || !workspaces || !out || count < 1 || nsub < 1) return LMVD_EINVAL;
+  *out = nullptr;
+  const int dev = plans[0] ? plans[0]->device : 0;
+  for (int i = 0; i < count; ++i) {
+    lmvd_plan p = plans[i];
+    if (!p || p->device != dev || p->prof.cls >= 0) return LMVD_EINVAL;
+    for (int k = 0; k < nsub; ++k) {
+      const lmvd_substep_args* a = &args[size_t(i) * nsub + k];
+      const lmvd_status ck = lmvd::check_substep_args(p, a, workspaces[i]);
+      if (ck != LMVD_OK) return ck;
+      for (int q = 0; q < 3; ++q)
+        if (a->md[q] || a->mc[q]) return LMVD_EINVAL;
+    }
+  }
+  if (hipSetDevice(dev) != hipSuccess) return LMVD_EHIP;
+  hipStream_t origin = nullptr;
+  if (hipStreamCreateWithFlags(&origin, hipStreamNonBlocking) != hipSuccess) return LMVD_EHIP;
+  std::vector<hipStream_t> br(count, nullptr);
+  std::vector<hipEvent_t> ev(count + 1, nullptr);
+  lmvd_status st = LMVD_OK;
+  auto fail = [&](lmvd_status e) { if (st == LMVD_OK) st = e; };
+  // the A(k) factors are plan state computed on first use: outside the graph
+  for (int i = 0; i < count; ++i) lmvd::ensure_factors(plans[i], origin);
+  if (hipStreamSynchronize(origin) != hipSuccess) fail(LMVD_EHIP);
+  for (int i = 0; i < count && st == LMVD_OK; ++i)
+    if (hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) != hipSuccess) fail(LMVD_EHIP);
+  for (int i = 0; i <= count && st == LMVD_OK; ++i)
+    if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) fail(LMVD_EHIP);
+  hipGraph_t graph = nullptr;
+  if (st == LMVD_OK) {
+    if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      fail(LMVD_EHIP);
+    } else {
+      // fork: every instance is a branch of its own; its substeps stay in order
+      if (hipEventRecord(ev[count], origin) != hipSuccess) fail(LMVD_EHIP);
+      for (int i = 0; i < count && st == LMVD_OK; ++i) {
+        if (hipStreamWaitEvent(br[i], ev[count], 0) != hipSuccess) { fail(LMVD_EHIP); break; }
+        for (int k = 0; k < nsub && st == LMVD_OK; ++k)
+          fail(run_substep(plans[i], &args[size_t(i) * nsub + k], workspaces[i], br[i]));
+        if (hipEventRecord(ev[i], br[i]) != hipSuccess || hipStreamWaitEvent(origin, ev[i], 0) != hipSuccess)
+          fail(LMVD_EHIP);
+      }
+      if (hipGetLastError() != hipSuccess) fail(LMVD_EHIP);
+      // the capture is always ended, also after a failure inside it
+      if (hipStreamEndCapture(origin, &graph) != hipSuccess) fail(LMVD_EHIP);
+    }
+  }
+  lmvd_graph g = nullptr;
+  if (st == LMVD_OK) {
+    g = new (std::nothrow) lmvd_graph_s;
+    if (!g) fail(LMVD_ENOMEM);
+  }
+  if (st == LMVD_OK) {
+    g->graph = graph;
+    g->device = dev;
+    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) fail(LMVD_EHIP);
+  }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t b : br)
+    if (b) (void)hipStreamDestroy(b);
+  (void)hipStreamDestroy(origin);
+  if (st != LMVD_OK) {
+    if (g) {
+      if (g->exec) (void)hipGraphExecDestroy(g->exec);
+      delete g;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  *out = g;
+  return LMVD_OK;
+}
+
+lmvd_status lmvd_graph_launch(lmvd_graph g, void* stream) {
+  if (!g || !g->exec) return LMVD_EINVAL;
+  if (hipSetDevice(g->device) != hipSuccess) return LMVD_EHIP;
+  return hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_graph_destroy(lmvd_graph g) {
+  if (!g) return LMVD_EINVAL;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return LMVD_OK;
 }
 
 lmvd_status lmvd_to_physical(lmvd_plan plan, const void* values, double* phys, void* workspace, void* stream) {

@@ -54,7 +54,8 @@ class SubstepArgs(ctypes.Structure):
 
 EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_sizes", "lmvd_substep",
            "lmvd_to_physical", "lmvd_to_spectral", "lmvd_project", "lmvd_evaluate", "lmvd_md", "lmvd_mc",
-           "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop"]
+           "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop", "lmvd_graph_create",
+           "lmvd_graph_launch", "lmvd_graph_destroy"]
 
 
 def library():
@@ -82,6 +83,10 @@ def library():
         lib.lmvd_profile_start.argtypes = [vp, i32, i32]
         lib.lmvd_profile_stop.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_double)]
+        lib.lmvd_graph_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SubstepArgs), ctypes.POINTER(vp), i32,
+                                          i32, ctypes.POINTER(vp)]
+        lib.lmvd_graph_launch.argtypes = [vp, vp]
+        lib.lmvd_graph_destroy.argtypes = [vp]
         for name in EXPORTS:
             if name != "lmvd_status_string":
                 getattr(lib, name).restype = ctypes.c_int
@@ -169,11 +174,17 @@ class Plan:
             raise LmvdError("expected a contiguous CUDA tensor of dtype %s" % dtype)
 
     # -- the substep -------------------------------------------------------------
-    def substep(self, stage, phi2, omega2, z, m1bar, m3bar, *, z_out, phi2_out=None, omega2_out=None,
-                m1bar_out=None, m3bar_out=None, hist=None, kf=-1, guess_mode=0, rhs_prev=None, zt_prev=None,
-                rhs_out=None, zt_out=None, md=None, mc=None):
+    def substep(self, stage, phi2, omega2, z, m1bar, m3bar, **kw):
         """One substep; see lmvd.h.  rhs_prev / rhs_out are dicts with keys
         phi2, omega2, m1bar, m3bar.  Outputs default to in-place (except z_out)."""
+        a = self.substep_args(stage, phi2, omega2, z, m1bar, m3bar, **kw)
+        _check(library().lmvd_substep(self.handle, ctypes.byref(a), _ptr(self.ws), self._stream()),
+               "lmvd_substep")
+
+    def substep_args(self, stage, phi2, omega2, z, m1bar, m3bar, *, z_out, phi2_out=None, omega2_out=None,
+                     m1bar_out=None, m3bar_out=None, hist=None, kf=-1, guess_mode=0, rhs_prev=None, zt_prev=None,
+                     rhs_out=None, zt_out=None, md=None, mc=None):
+        """The argument struct of one substep (nothing is launched)."""
         torch = self.torch
         c128, f64 = torch.complex128, torch.float64
         for t in (phi2, omega2, z, z_out):
@@ -206,8 +217,7 @@ class Plan:
         if mc is not None:
             for i in range(3):
                 a.mc[i] = mc[i].data_ptr()
-        _check(library().lmvd_substep(self.handle, ctypes.byref(a), _ptr(self.ws), self._stream()),
-               "lmvd_substep")
+        return a
 
     # -- timing hook -----------------------------------------------------------------
     KERNEL_CLASSES = ("zinv", "xpass_rz", "xpass_l", "xpass_rhot", "xpass_vel", "zfwd", "mc", "md", "proj",
@@ -285,15 +295,66 @@ class Stepper:
             self.zt.copy_(dev(inputs["zt_prev"]))
         self.zt_next = plan.empty()
 
-    def substep(self, kf=-1):
+    def next_args(self, kf=-1):
+        """Argument struct of the next substep; advances the state bookkeeping
+        (history ring, stage) without launching anything."""
         p = self.p
         z_new = self.hist[2]          # the oldest history slot is free after this substep
         if self.stage == 0:
-            p.substep(0, self.phi2, self.omega2, self.z, self.m1bar, self.m3bar, z_out=z_new, hist=self.hist,
-                      kf=kf, rhs_out=self.rhs, zt_out=self.zt)
+            a = p.substep_args(0, self.phi2, self.omega2, self.z, self.m1bar, self.m3bar, z_out=z_new,
+                               hist=self.hist, kf=kf, rhs_out=self.rhs, zt_out=self.zt)
         else:
-            p.substep(1, self.phi2, self.omega2, self.z, self.m1bar, self.m3bar, z_out=z_new, hist=self.hist,
-                      kf=kf, rhs_prev=self.rhs, zt_prev=self.zt, zt_out=self.zt_next)
+            a = p.substep_args(1, self.phi2, self.omega2, self.z, self.m1bar, self.m3bar, z_out=z_new,
+                               hist=self.hist, kf=kf, rhs_prev=self.rhs, zt_prev=self.zt, zt_out=self.zt_next)
         self.hist = [self.z, self.hist[0], self.hist[1]]
         self.z = z_new
         self.stage = 1 - self.stage
+        return a
+
+    def substep(self, kf=-1):
+        a = self.next_args(kf)
+        _check(library().lmvd_substep(self.p.handle, ctypes.byref(a), _ptr(self.p.ws), self.p._stream()),
+               "lmvd_substep")
+
+    def state(self):
+        """The state tensors (current z, its history, phi2, Omega2, plane means, stored RHS and z_t)."""
+        return dict(z=self.z, hist=list(self.hist), phi2=self.phi2, omega2=self.omega2, m1bar=self.m1bar,
+                    m3bar=self.m3bar, rhs=dict(self.rhs), zt=self.zt, zt_next=self.zt_next, stage=self.stage)
+
+
+class GraphBatch:
+    """`nsub` substeps of several independent simulations (Steppers, each with
+    its own plan) captured as one HIP graph; launch() advances every one of
+    them by nsub substeps.  nsub must be a multiple of 4: the z history ring
+    and the stage pattern then repeat, so the baked-in pointers stay valid for
+    every launch.  The Steppers must not be advanced otherwise while the graph
+    is in use."""
+
+    def __init__(self, steppers, nsub: int = 4, kf: int = -1):
+        if nsub % 4 != 0 or not steppers:
+            raise LmvdError("GraphBatch: nsub must be a positive multiple of 4")
+        self.steppers = list(steppers)
+        n = len(self.steppers)
+        args = (SubstepArgs * (n * nsub))()
+        for i, st in enumerate(self.steppers):
+            for k in range(nsub):
+                args[i * nsub + k] = st.next_args(kf)
+        plans = (ctypes.c_void_p * n)(*[st.p.handle.value for st in self.steppers])
+        ws = (ctypes.c_void_p * n)(*[st.p.ws.data_ptr() for st in self.steppers])
+        h = ctypes.c_void_p()
+        _check(library().lmvd_graph_create(plans, args, ws, n, nsub, ctypes.byref(h)), "lmvd_graph_create")
+        self.handle = h
+        self.nsub = nsub
+
+    def launch(self):
+        torch = self.steppers[0].p.torch
+        _check(library().lmvd_graph_launch(self.handle, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "lmvd_graph_launch")
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                library().lmvd_graph_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

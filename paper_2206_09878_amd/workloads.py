@@ -16,6 +16,8 @@ Section 5 and Appendix D, and of a mixing layer):
   rt512        512 x 385 x 512 (768 x 768), At = 0.925 (density ratio 25.67),
                Re = 1024, g = 1, interface perturbed by modes 4..64
   adjoint96    96 x 97 x 96 (144 x 144), density ratio 7 layer
+  batch        (batch_workloads) 64 small instances of uneven sizes, N1, N3 in
+               {32, 48, 64, 96}, n2 in {33, 49, 65, 97}, density ratio 2..25
 
 Array layout (all spectral arrays): complex128 [ny, N3-1, N1/2], index
 [j, n_idx, l], with n_idx covering n = 0..N3/2-1 then n = -(N3/2-1)..-1.
@@ -124,6 +126,28 @@ def workload(name: str, n: int | None = None, n2: int | None = None) -> Workload
     return w
 
 
+def batch_workloads(count: int = 64, seed: int = 1000) -> list:
+    """`count` independent small instances of uneven sizes (the batched mode):
+    instance i draws, from default_rng(seed + i), N1 and N3 from {32, 48, 64, 96},
+    n2 from {33, 49, 65, 97} and a density ratio rho_h / rho_l from U[2, 25];
+    everything else as `small` (its inputs come from make_inputs(w, seed + i))."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed + i)
+        n1 = int(rng.choice([32, 48, 64, 96]))
+        n3 = int(rng.choice([32, 48, 64, 96]))
+        n2 = int(rng.choice([33, 49, 65, 97]))
+        ratio = float(rng.uniform(2.0, 25.0))
+        w = workload("small")
+        w.name = f"batch{i}"
+        w.n1, w.n3, w.n2 = n1, n3, n2
+        w.m1, w.m3 = 3 * n1 // 2, 3 * n3 // 2
+        w.rho_l, w.rho_h = 1.0, ratio
+        w.extra = dict(w.extra, means="jet", kmax=min(w.extra["kmax"], min(n1, n3) // 2 - 1), seed=seed + i)
+        out.append(w)
+    return out
+
+
 # ----------------------------------------------------------------------------
 
 
@@ -208,7 +232,7 @@ def make_inputs(w: Workload, seed: int = 0, stage: int = 0) -> dict:
         zenv = np.exp(-(y / (2 * delta)) ** 2)
         z += ex["zpert"] * _random_modes(rng, w, amp, zenv)
         z[:, 0, 0] = 0.5 * (1.0 + np.tanh(y / delta))
-        if w.name != "small":
+        if ex.get("means", "jet" if w.name == "small" else "shear") == "shear":
             # mean shear across the layer: <m>1 ~ rho_mean(y) * dU/2 tanh(y/delta)
             rho_mean = w.rho_l + (w.rho_h - w.rho_l) * 0.5 * (1 + np.tanh(y / delta))
             m1bar = rho_mean * 0.5 * np.tanh(y / delta)
