@@ -2376,25 +2376,21 @@ __global__ void __launch_bounds__(kThreads) k_rhs_fluct(
 }
 
 // plane means <m>1, <m>3: RHS = d/dy <T12>, d/dy <T32> at tau, Neumann rows,
-// RK2 (eq. mean_m1m3).  Two threads, one per component.
-__global__ void k_rhs_mean(DevPlan P, const double2* __restrict__ T12, const double2* __restrict__ T23,
-                           const double* m1, const double* m3, const double* __restrict__ r1p,
-                           const double* __restrict__ r3p, double* m1o, double* m3o, double* __restrict__ r1o,
-                           double* __restrict__ r3o, double* __restrict__ ytmp, int stage) {
-  const int comp = threadIdx.x;
-  if (comp > 1) return;
+// RK2 (eq. mean_m1m3).
+__global__ void __launch_bounds__(256) k_rhs_mean(DevPlan P, const double2* __restrict__ T12,
+                                                  const double2* __restrict__ T23, const double* m1,
+                                                  const double* m3, const double* __restrict__ r1p,
+                                                  const double* __restrict__ r3p, double* m1o, double* m3o,
+                                                  double* __restrict__ r1o, double* __restrict__ r3o, int stage) {
+  // one block: the right-hand sides of both components, all rows in parallel,
+  // then one thread per component runs the two sweeps with the band in
+  // registers (the rows are a dependent chain), then the updates in parallel
+  extern __shared__ double ysh[];  // [2][n2]
   const int n2 = P.n2;
   const size_t ncol = size_t(P.nn) * P.nl;
-  const double2* T = comp == 0 ? T12 : T23;
-  const double* m = comp == 0 ? m1 : m3;
-  const double* rprev = comp == 0 ? r1p : r3p;
-  double* mo = comp == 0 ? m1o : m3o;
-  double* ro = comp == 0 ? r1o : r3o;
-  double* y = ytmp + comp * n2;
-  const auto L = P.lu_l + size_t(2) * n2 * kMaxBand;
-  const auto U = P.lu_u + size_t(2) * n2 * (kMaxBand + 1);
-  const auto Ui = P.lu_uinv + size_t(2) * n2;
-  for (int i = 0; i < n2; ++i) {
+  for (int t = threadIdx.x; t < 2 * n2; t += blockDim.x) {
+    const int comp = t / n2, i = t - comp * n2;
+    const double2* T = comp == 0 ? T12 : T23;
     double b = 0.0;
     if (i > 0 && i < n2 - 1) {
       const int lo = P.ev_lo[n2 + i];
@@ -2402,16 +2398,47 @@ __global__ void k_rhs_mean(DevPlan P, const double2* __restrict__ T12, const dou
       for (int q = 0; q < kMaxW; ++q)
         if (lo + q < n2 && w1[q] != 0.0) b += w1[q] * T[size_t(lo + q) * ncol].x;
     }
-    for (int mm = 1; mm <= kMaxBand && i - mm >= 0; ++mm) b -= L[i * kMaxBand + mm - 1] * y[i - mm];
-    y[i] = b;
+    ysh[t] = b;
   }
-  for (int i = n2 - 1; i >= 0; --i) {
-    double s = y[i];
-    for (int q = 1; q <= kMaxBand && i + q < n2; ++q) s -= U[i * (kMaxBand + 1) + q] * y[i + q];
-    y[i] = s * Ui[i];
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double* y = ysh + threadIdx.x * n2;
+    const auto L = P.lu_l + size_t(2) * n2 * kMaxBand;
+    const auto U = P.lu_u + size_t(2) * n2 * (kMaxBand + 1);
+    const auto Ui = P.lu_uinv + size_t(2) * n2;
+    double ring[kMaxBand];
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) ring[m] = 0.0;
+    for (int i = 0; i < n2; ++i) {  // L (unit lower, zero-padded band): ring[m] = y[i-1-m]
+      double b = y[i];
+#pragma unroll
+      for (int m = 0; m < kMaxBand; ++m) b -= L[i * kMaxBand + m] * ring[m];
+#pragma unroll
+      for (int m = kMaxBand - 1; m > 0; --m) ring[m] = ring[m - 1];
+      ring[0] = b;
+      y[i] = b;
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) ring[m] = 0.0;
+    for (int i = n2 - 1; i >= 0; --i) {  // U: ring[q] = x[i+1+q]
+      double v = y[i];
+#pragma unroll
+      for (int q = 0; q < kMaxBand; ++q) v -= U[i * (kMaxBand + 1) + q + 1] * ring[q];
+      const double x = v * Ui[i];
+#pragma unroll
+      for (int q = kMaxBand - 1; q > 0; --q) ring[q] = ring[q - 1];
+      ring[0] = x;
+      y[i] = x;
+    }
   }
-  for (int i = 0; i < n2; ++i) {
-    const double x = y[i];
+  __syncthreads();
+  for (int t = threadIdx.x; t < 2 * n2; t += blockDim.x) {
+    const int comp = t / n2, i = t - comp * n2;
+    const double x = ysh[t];
+    double* ro = comp == 0 ? r1o : r3o;
+    const double* m = comp == 0 ? m1 : m3;
+    const double* rprev = comp == 0 ? r1p : r3p;
+    double* mo = comp == 0 ? m1o : m3o;
     if (ro) ro[i] = x;
     mo[i] = (stage == 0) ? m[i] + 0.5 * P.dt * x : m[i] + P.dt * (x - 0.5 * rprev[i]);
   }
@@ -2466,7 +2493,7 @@ __global__ void k_evaluate(DevPlan P, int kind, const double2* __restrict__ src,
 struct Workspace {
   size_t bytes = 0;
   size_t off_md1, off_md3, off_c2d, off_mpar, off_c2c, off_rz, off_zta, off_ztb, off_rhot, off_vals[kMaxOut];
-  size_t off_u[3], off_T[6], off_rhov, off_yphi, off_yom, off_uscr, off_zbuf, off_obuf, off_mean, off_aux;
+  size_t off_u[3], off_T[6], off_rhov, off_yphi, off_yom, off_uscr, off_zbuf, off_obuf, off_aux;
   size_t off_yp, off_yt;  // scratch of the m^c column kernel
   // values at the Greville points
   size_t off_vz0, off_vz1, off_vzl, off_vz3, off_vmd1, off_vmd3, off_vc2d, off_vm1c, off_vm2c, off_vm3c, off_vzt;
@@ -2529,7 +2556,6 @@ static void layout_workspace(lmvd_plan_s* p) {
   const size_t plane = size_t(H.cfg.m3) * H.nl * 16;
   w.off_zbuf = take(size_t(kMaxIn) * p->pb * plane);
   w.off_obuf = take(size_t(kMaxOut) * p->pb * plane);
-  w.off_mean = take(size_t(2) * H.n2 * 8);
   w.off_yp = take(sB);
   w.off_yt = take(sS);
   w.off_aux = take(size_t(kNumAux) * H.n2 * H.cfg.m3 * H.cfg.m1 * 8);
@@ -2606,6 +2632,12 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
     return LMVD_EUNSUPPORTED;
   }
   if (H.a_lower > 8 || H.a_upper > 8) {
+    delete p;
+    return LMVD_EUNSUPPORTED;
+  }
+  // the plane-mean kernel keeps both components' rows in 64 KB of LDS
+  if (size_t(2) * H.n2 * sizeof(double) > 65536) {
+    msg = "n2 above 4096 is not supported";
     delete p;
     return LMVD_EUNSUPPORTED;
   }
@@ -3180,9 +3212,12 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
                        static_cast<double2*>(a->rhs_omega2), c.at<double2>(W.off_yphi), c.at<double2>(W.off_yom),
                        a->stage);
     }
-    hipLaunchKernelGGL(k_rhs_mean, dim3(1), dim3(64), 0, s, p->D, T[1], T[4], a->m1bar, a->m3bar, a->rhs_m1_prev,
-                       a->rhs_m3_prev, a->m1bar_out, a->m3bar_out, a->rhs_m1, a->rhs_m3, c.at<double>(W.off_mean),
-                       a->stage);
+    {
+    ProfScope ps(p, KC_RHS, s, 16.0 * 2 * H.n2 + 8.0 * H.n2 * (a->stage ? 8.0 : 6.0));
+    hipLaunchKernelGGL(k_rhs_mean, dim3(1), dim3(256), size_t(2) * H.n2 * sizeof(double), s, p->D, T[1], T[4],
+                       a->m1bar, a->m3bar, a->rhs_m1_prev, a->rhs_m3_prev, a->m1bar_out, a->m3bar_out, a->rhs_m1,
+                       a->rhs_m3, a->stage);
+    }
   }
   // optional diagnostics
   const size_t sB = nB * 16, sS = ncol * (H.n2 + 1) * 16;
