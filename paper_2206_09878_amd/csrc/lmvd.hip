@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1430,15 +1431,14 @@ struct RowWin {
 };
 
 template <int GROUP, int W, int LB>
-__global__ void __launch_bounds__(kThreads) k_flux(DevPlan P, const double2* __restrict__ Ca,
-                                                   const double2* __restrict__ Cb, const double2* __restrict__ Cc,
-                                                   const double2* __restrict__ u1, const double2* __restrict__ u2,
-                                                   const double2* __restrict__ u3, double2* Ta, double2* Tb,
-                                                   double2* Tc, double2* RO, double2* RP,
-                                                   const double2* __restrict__ rhov) {
+__device__ __forceinline__ void flux_body(const DevPlan& P, const unsigned bx, const double2* __restrict__ Ca,
+                                          const double2* __restrict__ Cb, const double2* __restrict__ Cc,
+                                          const double2* __restrict__ u1, const double2* __restrict__ u2,
+                                          const double2* __restrict__ u3, double2* Ta, double2* Tb, double2* Tc,
+                                          double2* RO, double2* RP, const double2* __restrict__ rhov) {
   const int nl = P.nl, nn = P.nn, n2 = P.n2;
   const size_t ncol = size_t(nn) * nl;
-  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t c = size_t(bx) * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const double k1 = P.k1[c % nl], k3 = P.k3[c / nl], ksq = k1 * k1 + k3 * k3;
   const double mu = P.mu, th = (2.0 / 3.0) * P.mu;
@@ -1565,6 +1565,14 @@ __global__ void __launch_bounds__(kThreads) k_flux(DevPlan P, const double2* __r
       RP[o] = ph;
     }
   }
+}
+template <int GROUP, int W, int LB>
+__global__ void __launch_bounds__(kThreads) k_flux(DevPlan P, const double2* __restrict__ Ca,
+                                  const double2* __restrict__ Cb, const double2* __restrict__ Cc,
+                                  const double2* __restrict__ u1, const double2* __restrict__ u2,
+                                  const double2* __restrict__ u3, double2* Ta, double2* Tb, double2* Tc, double2* RO,
+                                  double2* RP, const double2* __restrict__ rhov) {
+  flux_body<GROUP, W, LB>(P, blockIdx.x, Ca, Cb, Cc, u1, u2, u3, Ta, Tb, Tc, RO, RP, rhov);
 }
 
 // ---------------------------------------------------------------------------
@@ -1872,16 +1880,15 @@ struct McLds {
 // LDS latency replaces a scalar-cache miss per row); threads without a
 // column still take part in the copies and barriers.
 template <int LA, int UA, int LB, bool STAGE>
-__global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __restrict__ vals, double2* yp,
-                                                double2* yt, const double2* __restrict__ d1,
-                                                const double2* __restrict__ d2, const double2* __restrict__ d3,
-                                                double2* __restrict__ V1, double2* __restrict__ V2,
-                                                double2* __restrict__ V3, double2* rhoc, double2* __restrict__ c2,
-                                                double2* __restrict__ mparc) {
+__device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, const double2* __restrict__ vals,
+                                        double2* yp, double2* yt, const double2* __restrict__ d1,
+                                        const double2* __restrict__ d2, const double2* __restrict__ d3,
+                                        double2* __restrict__ V1, double2* __restrict__ V2, double2* __restrict__ V3,
+                                        double2* rhoc, double2* __restrict__ c2, double2* __restrict__ mparc) {
   extern __shared__ double lds_d[];
   const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
   const int half = (nn + 1) / 2, npairs = nl * half;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = bx * blockDim.x + threadIdx.x;
   const int pr = t >> 1, side = t & 1;
   const int l = pr % nl, pp = pr / nl;
   const bool active = pr < npairs && !(side == 1 && pp == 0);
@@ -2121,6 +2128,14 @@ __global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __res
     }
   }
 }
+template <int LA, int UA, int LB, bool STAGE>
+__global__ void __launch_bounds__(kThreads) k_mc(DevPlan P, const double2* __restrict__ vals, double2* yp, double2* yt,
+                                  const double2* __restrict__ d1, const double2* __restrict__ d2,
+                                  const double2* __restrict__ d3, double2* __restrict__ V1, double2* __restrict__ V2,
+                                  double2* __restrict__ V3, double2* rhoc, double2* __restrict__ c2,
+                                  double2* __restrict__ mparc) {
+  mc_body<LA, UA, LB, STAGE>(P, blockIdx.x, vals, yp, yt, d1, d2, d3, V1, V2, V3, rhoc, c2, mparc);
+}
 
 // ---------------------------------------------------------------------------
 // column kernel: m^d and its values at tau (eqs. phi_poisson, bc_both,
@@ -2304,14 +2319,15 @@ __global__ void __launch_bounds__(kThreads) k_prologue(DevPlan P, int md, MdArgs
 // column kernel: the right-hand sides of Omega2 and phi2 at tau (from the
 // flux kernels) -> coefficients with Dirichlet end rows, RK2 update.
 
-__global__ void __launch_bounds__(kThreads) k_rhs_fluct(
-    DevPlan P, const double2* __restrict__ RO, const double2* __restrict__ RP, const double2* phi,
-    const double2* om, const double2* __restrict__ rphi_prev, const double2* __restrict__ rom_prev, double2* phi_out,
-    double2* om_out, double2* __restrict__ rphi_out, double2* __restrict__ rom_out, double2* __restrict__ yphi,
-    double2* __restrict__ yom, int stage) {
+__device__ __forceinline__ void rhs_fluct_body(const DevPlan& P, const unsigned bx, const double2* __restrict__ RO,
+                                               const double2* __restrict__ RP, const double2* phi, const double2* om,
+                                               const double2* __restrict__ rphi_prev,
+                                               const double2* __restrict__ rom_prev, double2* phi_out, double2* om_out,
+                                               double2* __restrict__ rphi_out, double2* __restrict__ rom_out,
+                                               double2* __restrict__ yphi, double2* __restrict__ yom, int stage) {
   const int nl = P.nl, nn = P.nn, n2 = P.n2;
   const int ncol = nn * nl;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = bx * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   (void)nl;
   const auto L = P.lu_l + size_t(1) * n2 * kMaxBand;
@@ -2374,14 +2390,23 @@ __global__ void __launch_bounds__(kThreads) k_rhs_fluct(
     }
   }
 }
+__global__ void __launch_bounds__(kThreads) k_rhs_fluct(DevPlan P, const double2* __restrict__ RO,
+                                  const double2* __restrict__ RP, const double2* phi, const double2* om,
+                                  const double2* __restrict__ rphi_prev, const double2* __restrict__ rom_prev,
+                                  double2* phi_out, double2* om_out, double2* __restrict__ rphi_out,
+                                  double2* __restrict__ rom_out, double2* __restrict__ yphi, double2* __restrict__ yom,
+                                  int stage) {
+  rhs_fluct_body(P, blockIdx.x, RO, RP, phi, om, rphi_prev, rom_prev, phi_out, om_out, rphi_out, rom_out, yphi, yom,
+                 stage);
+}
 
 // plane means <m>1, <m>3: RHS = d/dy <T12>, d/dy <T32> at tau, Neumann rows,
 // RK2 (eq. mean_m1m3).
-__global__ void __launch_bounds__(256) k_rhs_mean(DevPlan P, const double2* __restrict__ T12,
-                                                  const double2* __restrict__ T23, const double* m1,
-                                                  const double* m3, const double* __restrict__ r1p,
-                                                  const double* __restrict__ r3p, double* m1o, double* m3o,
-                                                  double* __restrict__ r1o, double* __restrict__ r3o, int stage) {
+__device__ __forceinline__ void rhs_mean_body(const DevPlan& P, const unsigned bx, const double2* __restrict__ T12,
+                                              const double2* __restrict__ T23, const double* m1, const double* m3,
+                                              const double* __restrict__ r1p, const double* __restrict__ r3p,
+                                              double* m1o, double* m3o, double* __restrict__ r1o,
+                                              double* __restrict__ r3o, int stage) {
   // one block: the right-hand sides of both components, all rows in parallel,
   // then one thread per component runs the two sweeps with the band in
   // registers (the rows are a dependent chain), then the updates in parallel
@@ -2443,6 +2468,160 @@ __global__ void __launch_bounds__(256) k_rhs_mean(DevPlan P, const double2* __re
     mo[i] = (stage == 0) ? m[i] + 0.5 * P.dt * x : m[i] + P.dt * (x - 0.5 * rprev[i]);
   }
 }
+__global__ void __launch_bounds__(256) k_rhs_mean(DevPlan P, const double2* __restrict__ T12,
+                                  const double2* __restrict__ T23, const double* m1, const double* m3,
+                                  const double* __restrict__ r1p, const double* __restrict__ r3p, double* m1o,
+                                  double* m3o, double* __restrict__ r1o, double* __restrict__ r3o, int stage) {
+  rhs_mean_body(P, blockIdx.x, T12, T23, m1, m3, r1p, r3p, m1o, m3o, r1o, r3o, stage);
+}
+
+// ---------------------------------------------------------------------------
+// Column kernels as jobs: an argument struct, the body on one instance (its
+// plan, block index and arguments), the named single-instance launch, and one
+// grouped kernel per job that runs the job for many instances (each its own
+// plan and sizes) in a single launch: instance r owns blocks b0 .. b0+nbx-1.
+
+template <class A>
+struct GRec {
+  A a;
+  int inst;
+  unsigned b0, nbx;
+};
+
+template <class Job>
+__global__ void __launch_bounds__(kThreads) k_group(const DevPlan* __restrict__ plans,
+                                                   const GRec<typename Job::Args>* __restrict__ recs, int nrec) {
+  const unsigned bx = blockIdx.x;
+  int lo = 0, hi = nrec - 1;  // the last record with b0 <= bx (records ascend, no gaps)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (recs[mid].b0 <= bx) lo = mid;
+    else hi = mid - 1;
+  }
+  const GRec<typename Job::Args>& R = recs[lo];
+  Job::run(plans[R.inst], bx - R.b0, blockIdx.y, R.a);
+}
+
+template <int LA, int UA, int W>
+struct JobPrologue {
+  struct Args {
+    int md;
+    MdArgs M;
+    ValuesZArgs Z;
+    GuessArgs G;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, const Args& A) {
+    const int job = int(by) + (A.md ? 0 : 1);
+    const size_t t = size_t(bx) * blockDim.x + threadIdx.x;
+    if (job == 0) md_body<LA, UA, W>(P, int(t), A.M);
+    else if (job == 1) values_z_body(P, t, A.Z);
+    else guess_body(P, t, A.G);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
+    hipLaunchKernelGGL((k_prologue<LA, UA, W>), g, dim3(kThreads), lds, s, P, A.md, A.M, A.Z, A.G);
+  }
+};
+
+template <int EPI>
+struct JobProj {
+  struct Args {
+    int kind;
+    const double2* in;
+    double2* out;
+    const double2 *add, *z, *zt_prev;
+    double2 *z_out, *vals_out, *vals_out1;
+    int stage, ncol;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+    proj_body<EPI>(P, int(bx * blockDim.x + threadIdx.x), A.kind, A.in, A.out, A.add, A.z, A.zt_prev, A.z_out,
+                   A.vals_out, A.vals_out1, A.stage, A.ncol);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
+    hipLaunchKernelGGL(k_proj<EPI>, g, dim3(kThreads), lds, s, P, A.kind, A.in, A.out, A.add, A.z, A.zt_prev,
+                       A.z_out, A.vals_out, A.vals_out1, A.stage, A.ncol);
+  }
+};
+
+struct JobProj3 {
+  struct Args {
+    int kind;
+    ProjBatch B;
+    int ncol;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, const Args& A) {
+    proj_body<EPI_STORE>(P, int(bx * blockDim.x + threadIdx.x), A.kind, A.B.in[by], A.B.out[by], nullptr, nullptr,
+                         nullptr, nullptr, nullptr, nullptr, 0, A.ncol);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
+    hipLaunchKernelGGL(k_proj3, g, dim3(kThreads), lds, s, P, A.kind, A.B, A.ncol);
+  }
+};
+
+template <int LA, int UA, int LB, bool STAGE>
+struct JobMc {
+  struct Args {
+    const double2* vals;
+    double2 *yp, *yt;
+    const double2 *d1, *d2, *d3;
+    double2 *V1, *V2, *V3, *rhoc, *c2, *mparc;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+    mc_body<LA, UA, LB, STAGE>(P, bx, A.vals, A.yp, A.yt, A.d1, A.d2, A.d3, A.V1, A.V2, A.V3, A.rhoc, A.c2,
+                               A.mparc);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
+    hipLaunchKernelGGL((k_mc<LA, UA, LB, STAGE>), g, dim3(kThreads), lds, s, P, A.vals, A.yp, A.yt, A.d1, A.d2,
+                       A.d3, A.V1, A.V2, A.V3, A.rhoc, A.c2, A.mparc);
+  }
+};
+
+template <int GROUP, int W, int LB>
+struct JobFlux {
+  struct Args {
+    const double2 *Ca, *Cb, *Cc, *u1, *u2, *u3;
+    double2 *Ta, *Tb, *Tc, *RO, *RP;
+    const double2* rhov;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+    flux_body<GROUP, W, LB>(P, bx, A.Ca, A.Cb, A.Cc, A.u1, A.u2, A.u3, A.Ta, A.Tb, A.Tc, A.RO, A.RP, A.rhov);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
+    hipLaunchKernelGGL((k_flux<GROUP, W, LB>), g, dim3(kThreads), lds, s, P, A.Ca, A.Cb, A.Cc, A.u1, A.u2, A.u3,
+                       A.Ta, A.Tb, A.Tc, A.RO, A.RP, A.rhov);
+  }
+};
+
+struct JobRhsFluct {
+  struct Args {
+    const double2 *RO, *RP, *phi, *om, *rphi_prev, *rom_prev;
+    double2 *phi_out, *om_out, *rphi_out, *rom_out, *yphi, *yom;
+    int stage;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+    rhs_fluct_body(P, bx, A.RO, A.RP, A.phi, A.om, A.rphi_prev, A.rom_prev, A.phi_out, A.om_out, A.rphi_out,
+                   A.rom_out, A.yphi, A.yom, A.stage);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
+    hipLaunchKernelGGL(k_rhs_fluct, g, dim3(kThreads), lds, s, P, A.RO, A.RP, A.phi, A.om, A.rphi_prev,
+                       A.rom_prev, A.phi_out, A.om_out, A.rphi_out, A.rom_out, A.yphi, A.yom, A.stage);
+  }
+};
+
+struct JobRhsMean {
+  struct Args {
+    const double2 *T12, *T23;
+    const double *m1, *m3, *r1p, *r3p;
+    double *m1o, *m3o, *r1o, *r3o;
+    int stage;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+    rhs_mean_body(P, bx, A.T12, A.T23, A.m1, A.m3, A.r1p, A.r3p, A.m1o, A.m3o, A.r1o, A.r3o, A.stage);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
+    hipLaunchKernelGGL(k_rhs_mean, g, dim3(kThreads), lds, s, P, A.T12, A.T23, A.m1, A.m3, A.r1p, A.r3p, A.m1o,
+                       A.m3o, A.r1o, A.r3o, A.stage);
+  }
+};
 
 // BDF-like guess dt z_t^0 = a1 z + a2 h1 + a3 h2 + a4 h3 (eq. dzdt_guesses)
 __global__ void k_guess(const double2* __restrict__ z, const double2* __restrict__ h1, const double2* __restrict__ h2,
@@ -2455,7 +2634,8 @@ __global__ void k_guess(const double2* __restrict__ z, const double2* __restrict
     return;
   }
   const double2 a = z[e], b = h1[e], c = h2[e], d = h3[e];
-  out[e] = make_double2((a1 * a.x + a2 * b.x + a3 * c.x + a4 * d.x) / dt, (a1 * a.y + a2 * b.y + a3 * c.y + a4 * d.y) / dt);
+  out[e] = make_double2((a1 * a.x + a2 * b.x + a3 * c.x + a4 * d.x) / dt,
+                        (a1 * a.y + a2 * b.y + a3 * c.y + a4 * d.y) / dt);
 }
 
 // z update from a given z_t (used when k_f = 0)
@@ -2746,10 +2926,12 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
 // ---------------------------------------------------------------------------
 // launchers
 
+struct Recorder;
 struct Ctx {
   lmvd_plan_s* p;
   char* ws;
   hipStream_t s;
+  Recorder* rec = nullptr;  // set: launches are recorded for a grouped graph, not issued
   template <typename T>
   T* at(size_t off) const {
     return reinterpret_cast<T*>(ws + off);
@@ -2757,6 +2939,82 @@ struct Ctx {
 };
 
 static size_t ncols(const lmvd_plan_s* p) { return size_t(p->H.nn) * p->H.nl; }
+
+// ---------------------------------------------------------------------------
+// Launch routing.  With no recorder a launch happens at once on the context's
+// stream.  With a recorder (the grouped mode of lmvd_graph_create) the
+// substep's launches are collected per instance: column jobs as argument
+// records, to be issued later as one grouped launch over all instances, and
+// everything else (plane phases, per-instance kernels) as functions to run on
+// that instance's stream.
+
+struct JobOps {  // type-erased job: record size, packing, grouped launch
+  size_t rec_size;
+  void (*pack)(void* dst, const void* args, int inst, unsigned b0, unsigned nbx);
+  void (*launch)(const DevPlan* plans, const void* recs, int nrec, dim3 grid, size_t lds, hipStream_t s);
+};
+
+template <class Job>
+struct JobOpsOf {
+  using A = typename Job::Args;
+  static void pack(void* dst, const void* args, int inst, unsigned b0, unsigned nbx) {
+    GRec<A> r;
+    std::memcpy(&r.a, args, sizeof(A));
+    r.inst = inst;
+    r.b0 = b0;
+    r.nbx = nbx;
+    std::memcpy(dst, &r, sizeof(r));
+  }
+  static void launch(const DevPlan* plans, const void* recs, int nrec, dim3 grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(k_group<Job>, grid, dim3(kThreads), lds, s, plans, static_cast<const GRec<A>*>(recs), nrec);
+  }
+  static const JobOps ops;
+};
+template <class Job>
+const JobOps JobOpsOf<Job>::ops = {sizeof(GRec<typename Job::Args>), &JobOpsOf<Job>::pack, &JobOpsOf<Job>::launch};
+
+struct RecOp {
+  const JobOps* job = nullptr;  // column job, or nullptr for a function
+  std::vector<unsigned char> args;
+  dim3 grid;
+  size_t lds = 0;
+  std::function<lmvd_status(hipStream_t)> fn;
+};
+struct Recorder {
+  std::vector<RecOp> ops;
+};
+
+// a column job: launched now, or recorded for a grouped launch
+template <class Job>
+static void col(const Ctx& c, dim3 grid, size_t lds, const typename Job::Args& A) {
+  if (!c.rec) {
+    Job::launch(grid, lds, c.s, c.p->D, A);
+    return;
+  }
+  RecOp op;
+  op.job = &JobOpsOf<Job>::ops;
+  op.args.resize(sizeof(A));
+  std::memcpy(op.args.data(), &A, sizeof(A));
+  op.grid = grid;
+  op.lds = lds;
+  c.rec->ops.push_back(std::move(op));
+}
+
+// anything else: run now, or recorded as a function of the instance's stream
+template <class F>
+static lmvd_status per_instance(const Ctx& c, F&& f) {
+  if (!c.rec) return f(c);
+  const Ctx base{c.p, c.ws, nullptr, nullptr};
+  RecOp op;
+  op.fn = [base, f](hipStream_t s) {
+    Ctx cc = base;
+    cc.s = s;
+    return f(cc);
+  };
+  c.rec->ops.push_back(std::move(op));
+  return LMVD_OK;
+}
+
 
 // kernel classes of the timing hook
 // Each class is one kernel (one symbol on the rt512-like sizes); the bytes a
@@ -2970,8 +3228,8 @@ static void proj(const Ctx& c, int kind, const double2* in, double2* out, double
   const int n = int(ncols(c.p));
   // values in, L-sweep intermediate out and back, coefficients out, optional emitted values
   ProfScope ps(c.p, KC_PROJ, c.s, (4.0 + (v0 ? 1.0 : 0.0) + (v1 ? 1.0 : 0.0)) * 16.0 * n * c.p->H.n2);
-  hipLaunchKernelGGL(k_proj<EPI_STORE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, c.s, c.p->D, kind,
-                     in, out, nullptr, nullptr, nullptr, nullptr, v0, v1, 0, n);
+  col<JobProj<EPI_STORE>>(c, dim3((n + kThreads - 1) / kThreads), 0,
+                          {kind, in, out, nullptr, nullptr, nullptr, nullptr, v0, v1, 0, n});
 }
 
 template <int MODE>
@@ -3006,9 +3264,10 @@ static void ensure_factors(lmvd_plan_s* p, hipStream_t s) {
   p->fac_ready = true;
 }
 
-static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void* workspace, hipStream_t s) {
+static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void* workspace, hipStream_t s,
+                               Recorder* rec = nullptr) {
   const HostTables& H = p->H;
-  Ctx c{p, static_cast<char*>(workspace), s};
+  Ctx c{p, static_cast<char*>(workspace), s, rec};
   const Workspace& W = p->ws;
   const size_t ncol = ncols(p);
   const size_t nB = ncol * H.n2;
@@ -3060,10 +3319,11 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     const bool narrow = H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
     double2* yp = c.at<double2>(W.off_yp);
     double2* yt = c.at<double2>(W.off_yt);
-#define LMVD_MC(LA_, LB_, ST_)                                                                                 \
-  hipLaunchKernelGGL((k_mc<LA_, LA_, LB_, ST_>), g, dim3(kThreads), ST_ ? lay.bytes() : 0, s, p->D, vals[0], yp, yt,  \
-                     final_it ? vmd1 : nullptr, final_it ? vc2d : nullptr, final_it ? vmd3 : nullptr, vm1, vm2,   \
-                     vm3, final_it ? rhot : nullptr, final_it ? c2c : nullptr, final_it ? mpar : nullptr)
+#define LMVD_MC(LA_, LB_, ST_)                                                                               \
+  col<JobMc<LA_, LA_, LB_, ST_>>(c, g, ST_ ? lay.bytes() : 0,                                                \
+                                 {vals[0], yp, yt, final_it ? vmd1 : nullptr, final_it ? vc2d : nullptr,     \
+                                  final_it ? vmd3 : nullptr, vm1, vm2, vm3, final_it ? rhot : nullptr,       \
+                                  final_it ? c2c : nullptr, final_it ? mpar : nullptr})
     // the staged tables must leave room for two blocks per compute unit
     const McLds lay{H.n2, H.n2 + 1, narrow ? 6 : kMaxBand};
     const bool stage = lay.bytes() <= 72 * 1024;
@@ -3079,7 +3339,10 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   };
   auto values = [&](const double2* a1, double2* v1, const double2* a2, double2* v2, const double2* a3, double2* v3) {
     ProfScope ps(p, KC_VALUES, s, 16.0 * nB * ((a1 ? 2 : 0) + (a2 ? 2 : 0) + (a3 ? 2 : 0)));
-    hipLaunchKernelGGL(k_values, cgrid, dim3(kThreads), 0, s, p->D, a1, v1, a2, v2, a3, v3);
+    (void)per_instance(c, [=](const Ctx& cc) {
+      hipLaunchKernelGGL(k_values, cgrid, dim3(kThreads), 0, cc.s, cc.p->D, a1, v1, a2, v2, a3, v3);
+      return LMVD_OK;
+    });
   };
 
   // guess coefficients of the BDF-like extrapolation
@@ -3110,73 +3373,79 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     const MdArgs margs{phi2, om2, a->m1bar, a->m3bar, c.at<double2>(W.off_yt), vmd1, vc2d, vmd3,
                        diag ? c2d : nullptr, diag ? md1 : nullptr, diag ? md3 : nullptr};
     if (p->fac_la == 7)
-      hipLaunchKernelGGL((k_prologue<7, 7, 8>), g, dim3(kThreads), 0, s, p->D, 1, margs, zargs, gargs);
+      col<JobPrologue<7, 7, 8>>(c, g, 0, {1, margs, zargs, gargs});
     else
-      hipLaunchKernelGGL((k_prologue<8, 8, 8>), g, dim3(kThreads), 0, s, p->D, 1, margs, zargs, gargs);
+      col<JobPrologue<8, 8, 8>>(c, g, 0, {1, margs, zargs, gargs});
   } else {
-    solveA<0>(c, phi2, om2, a->m1bar, a->m3bar, c2d, md1, md3);
+    (void)per_instance(c, [=](const Ctx& cc) {
+      solveA<0>(cc, phi2, om2, a->m1bar, a->m3bar, c2d, md1, md3);
+      return LMVD_OK;
+    });
     values(md1, vmd1, md3, vmd3, c2d, vc2d);
     ProfScope ps(p, KC_VALUES, s, 16.0 * nB * 5 + 16.0 * nB * (zero ? 2 : 6));
-    const MdArgs none{};
-    hipLaunchKernelGGL((k_prologue<8, 8, 8>), dim3(cgrid.x, 2), dim3(kThreads), 0, s, p->D, 0, none, zargs, gargs);
+    col<JobPrologue<8, 8, 8>>(c, dim3(cgrid.x, 2), 0, {0, MdArgs{}, zargs, gargs});
   }
   // 2. R_z
-  st = plane_phase<PH_RZ>(c,
-                          {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT),
-                           ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
-                          {vals[0]});
+  st = per_instance(c, [=](const Ctx& cc) {
+    return plane_phase<PH_RZ>(cc,
+                              {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT),
+                               ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
+                              {vals[0]});
+  });
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
-  {
-    if (kf == 0) {
-      hipLaunchKernelGGL(k_zupdate, dim3((nB + kThreads - 1) / kThreads), dim3(kThreads), 0, s, z, gdst,
-                         static_cast<const double2*>(a->zt_prev), static_cast<double2*>(a->z_out), H.cfg.dt, a->stage,
-                         nB);
-    }
+  if (kf == 0) {
+    const double2* ztp = static_cast<const double2*>(a->zt_prev);
+    double2* zo = static_cast<double2*>(a->z_out);
+    const double dt = H.cfg.dt;
+    const int stg = a->stage;
+    (void)per_instance(c, [=](const Ctx& cc) {
+      hipLaunchKernelGGL(k_zupdate, dim3((nB + kThreads - 1) / kThreads), dim3(kThreads), 0, cc.s, z, gdst, ztp, zo,
+                         dt, stg, nB);
+      return LMVD_OK;
+    });
   }
   double2* cur = (kf == 0 && user_zt) ? user_zt : zta;
   // 3. fixed-point iterations z_t^k = L(z) z_t^{k-1} + R_z
   for (int it = 0; it < kf; ++it) {
     const bool last = (it == kf - 1);
-    st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
+    st = per_instance(c, [=](const Ctx& cc) { return plane_phase<PH_RHOT>(cc, {ev(vzt, EV_IDENT)}, {vals[0]}); });
     if (st != LMVD_OK) return st;
     mc_step(false);
-    st = plane_phase<PH_L>(c,
-                           {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
-                           {vals[0]});
+    st = per_instance(c, [=](const Ctx& cc) {
+      return plane_phase<PH_L>(cc, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)}, {vals[0]});
+    });
     if (st != LMVD_OK) return st;
     double2* next = (last && user_zt) ? user_zt : (cur == zta ? ztb : zta);
     const int n = int(ncol);
+    const dim3 g((n + kThreads - 1) / kThreads);
     ProfScope ps(p, KC_PROJ_ZT, s, (last ? (a->stage ? 9.0 : 8.0) : 5.0) * 16.0 * nB);
-    if (last) {
-      hipLaunchKernelGGL(k_proj<EPI_ADD_ZUPDATE>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
-                         vals[0], next, rz, z, static_cast<const double2*>(a->zt_prev),
-                         static_cast<double2*>(a->z_out), vzt, nullptr, a->stage, n);
-    } else {
-      hipLaunchKernelGGL(k_proj<EPI_ADD>, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, 2,
-                         vals[0], next, rz, nullptr, nullptr, nullptr, vzt, nullptr, a->stage, n);
-    }
+    if (last)
+      col<JobProj<EPI_ADD_ZUPDATE>>(c, g, 0,
+                                    {2, vals[0], next, rz, z, static_cast<const double2*>(a->zt_prev),
+                                     static_cast<double2*>(a->z_out), vzt, nullptr, a->stage, n});
+    else
+      col<JobProj<EPI_ADD>>(c, g, 0, {2, vals[0], next, rz, nullptr, nullptr, nullptr, vzt, nullptr, a->stage, n});
     cur = next;
   }
   // m^c of the stage from z_t^{k_f}
-  st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
+  st = per_instance(c, [=](const Ctx& cc) { return plane_phase<PH_RHOT>(cc, {ev(vzt, EV_IDENT)}, {vals[0]}); });
   if (st != LMVD_OK) return st;
   mc_step(true);  // m = m^d + m^c values
   // 4./5. velocities, density, fluxes
-  const EvalIn m1 = ev(vm1, EV_IDENT);
-  const EvalIn m2 = ev(vm2, EV_IDENT);
-  const EvalIn m3 = ev(vm3, EV_IDENT);
   // u = m/rho, rho and C_ij = -m_i m_j/rho on the physical grid; u_hat by interpolation;
   // T_ij = C_ij + tau_ij(u_hat) projected
   double2* cv[6] = {vals[4], vals[5], vals[6], vals[7], vals[8], vals[9]};
-  st = plane_phase<PH_VEL>(c, {ev(vz0, EV_IDENT), m1, m2, m3},
-                           {vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]});
+  st = per_instance(c, [=](const Ctx& cc) {
+    return plane_phase<PH_VEL>(cc, {ev(vz0, EV_IDENT), ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
+                               {vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]});
+  });
   if (st != LMVD_OK) return st;
   {
     const int n = int(ncol);
     ProfScope ps(p, KC_PROJ, s, 3 * 4.0 * 16.0 * nB);
-    const ProjBatch B{{vals[0], vals[1], vals[2]}, {u[0], u[1], u[2]}};
-    hipLaunchKernelGGL(k_proj3, dim3((n + kThreads - 1) / kThreads, 3), dim3(kThreads), 0, s, p->D, 0, B, n);
+    col<JobProj3>(c, dim3((n + kThreads - 1) / kThreads, 3), 0, {0, ProjBatch{{vals[0], vals[1], vals[2]}, {u[0], u[1],
+                  u[2]}}, n});
   }
   // fluxes and their share of the RHS values at tau (RO: Omega2, RP: phi2)
   double2* RO = vals[0];
@@ -3189,46 +3458,47 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     ProfScope ps(p, KC_FLUX, s, 16.0 * nB * 31.0);
     const bool narrow = H.p <= 8 && H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
     if (narrow) {
-      hipLaunchKernelGGL((k_flux<0, 8, 6>), grid, dim3(kThreads), 0, s, p->D, cv[0], cv[1], cv[2], u[0], u[1], u[2],
-                         T[0], T[1], T[2], RO, RP, rhov);
-      hipLaunchKernelGGL((k_flux<1, 8, 6>), grid, dim3(kThreads), 0, s, p->D, cv[3], cv[4], cv[5], u[0], u[1], u[2],
-                         T[3], T[4], T[5], RO, RP, rhov);
+      col<JobFlux<0, 8, 6>>(c, grid, 0, {cv[0], cv[1], cv[2], u[0], u[1], u[2], T[0], T[1], T[2], RO, RP, rhov});
+      col<JobFlux<1, 8, 6>>(c, grid, 0, {cv[3], cv[4], cv[5], u[0], u[1], u[2], T[3], T[4], T[5], RO, RP, rhov});
     } else {
-      hipLaunchKernelGGL((k_flux<0, kMaxW, kMaxBand>), grid, dim3(kThreads), 0, s, p->D, cv[0], cv[1], cv[2], u[0],
-                         u[1], u[2], T[0], T[1], T[2], RO, RP, rhov);
-      hipLaunchKernelGGL((k_flux<1, kMaxW, kMaxBand>), grid, dim3(kThreads), 0, s, p->D, cv[3], cv[4], cv[5], u[0],
-                         u[1], u[2], T[3], T[4], T[5], RO, RP, rhov);
+      col<JobFlux<0, kMaxW, kMaxBand>>(c, grid, 0,
+                                       {cv[0], cv[1], cv[2], u[0], u[1], u[2], T[0], T[1], T[2], RO, RP, rhov});
+      col<JobFlux<1, kMaxW, kMaxBand>>(c, grid, 0,
+                                       {cv[3], cv[4], cv[5], u[0], u[1], u[2], T[3], T[4], T[5], RO, RP, rhov});
     }
   }
   // RHS and RK2
   {
     const int n = int(ncol);
     {
-    ProfScope ps(p, KC_RHS, s, 16.0 * nB * (a->stage ? 12.0 : 10.0) + 16.0 * nB * (a->rhs_phi2 ? 2 : 0));
-    hipLaunchKernelGGL(k_rhs_fluct, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->D, RO, RP, phi2,
-                       om2, static_cast<const double2*>(a->rhs_phi2_prev),
-                       static_cast<const double2*>(a->rhs_omega2_prev), static_cast<double2*>(a->phi2_out),
-                       static_cast<double2*>(a->omega2_out), static_cast<double2*>(a->rhs_phi2),
-                       static_cast<double2*>(a->rhs_omega2), c.at<double2>(W.off_yphi), c.at<double2>(W.off_yom),
-                       a->stage);
+      ProfScope ps(p, KC_RHS, s, 16.0 * nB * (a->stage ? 12.0 : 10.0) + 16.0 * nB * (a->rhs_phi2 ? 2 : 0));
+      col<JobRhsFluct>(c, dim3((n + kThreads - 1) / kThreads), 0,
+                       {RO, RP, phi2, om2, static_cast<const double2*>(a->rhs_phi2_prev),
+                        static_cast<const double2*>(a->rhs_omega2_prev), static_cast<double2*>(a->phi2_out),
+                        static_cast<double2*>(a->omega2_out), static_cast<double2*>(a->rhs_phi2),
+                        static_cast<double2*>(a->rhs_omega2), c.at<double2>(W.off_yphi), c.at<double2>(W.off_yom),
+                        a->stage});
     }
     {
-    ProfScope ps(p, KC_RHS, s, 16.0 * 2 * H.n2 + 8.0 * H.n2 * (a->stage ? 8.0 : 6.0));
-    hipLaunchKernelGGL(k_rhs_mean, dim3(1), dim3(256), size_t(2) * H.n2 * sizeof(double), s, p->D, T[1], T[4],
-                       a->m1bar, a->m3bar, a->rhs_m1_prev, a->rhs_m3_prev, a->m1bar_out, a->m3bar_out, a->rhs_m1,
-                       a->rhs_m3, a->stage);
+      ProfScope ps(p, KC_RHS, s, 16.0 * 2 * H.n2 + 8.0 * H.n2 * (a->stage ? 8.0 : 6.0));
+      col<JobRhsMean>(c, dim3(1), size_t(2) * H.n2 * sizeof(double),
+                      {T[1], T[4], a->m1bar, a->m3bar, a->rhs_m1_prev, a->rhs_m3_prev, a->m1bar_out, a->m3bar_out,
+                       a->rhs_m1, a->rhs_m3, a->stage});
     }
   }
-  // optional diagnostics
-  const size_t sB = nB * 16, sS = ncol * (H.n2 + 1) * 16;
-  if (a->md[0]) HIP_OK(hipMemcpyAsync(a->md[0], md1, sB, hipMemcpyDeviceToDevice, s));
-  if (a->md[1]) HIP_OK(hipMemcpyAsync(a->md[1], c2d, sS, hipMemcpyDeviceToDevice, s));
-  if (a->md[2]) HIP_OK(hipMemcpyAsync(a->md[2], md3, sB, hipMemcpyDeviceToDevice, s));
-  if (a->mc[1]) HIP_OK(hipMemcpyAsync(a->mc[1], c2c, sS, hipMemcpyDeviceToDevice, s));
+  // optional diagnostics (never in a recorded substep)
+  if (!rec) {
+    const size_t sB = nB * 16, sS = ncol * (H.n2 + 1) * 16;
+    if (a->md[0]) HIP_OK(hipMemcpyAsync(a->md[0], md1, sB, hipMemcpyDeviceToDevice, s));
+    if (a->md[1]) HIP_OK(hipMemcpyAsync(a->md[1], c2d, sS, hipMemcpyDeviceToDevice, s));
+    if (a->md[2]) HIP_OK(hipMemcpyAsync(a->md[2], md3, sB, hipMemcpyDeviceToDevice, s));
+    if (a->mc[1]) HIP_OK(hipMemcpyAsync(a->mc[1], c2c, sS, hipMemcpyDeviceToDevice, s));
+  }
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
 }
 
-__global__ void k_mc13(DevPlan P, const double2* __restrict__ mpar, double2* __restrict__ m1, double2* __restrict__ m3) {
+__global__ void k_mc13(DevPlan P, const double2* __restrict__ mpar, double2* __restrict__ m1,
+                       double2* __restrict__ m3) {
   const size_t ncol = size_t(P.nn) * P.nl;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ncol * P.n2) return;
@@ -3325,8 +3595,113 @@ lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* a, void* works
 struct lmvd_graph_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  void* arena = nullptr;  // plans and job records of the grouped launches
   int device = 0;
+  int grouped = 0;
 };
+
+namespace lmvd {
+// Capture of count instances x nsub substeps on `origin`.  Grouped: every
+// column job is one launch over all instances (records in `arena`), and the
+// per-instance work between them (plane phases) runs on one branch stream per
+// instance.  Used when all instances record the same sequence of jobs (same
+// k_f, stage pattern and kernel variants); otherwise every instance is one
+// branch of its own.
+static lmvd_status capture_graph(const lmvd_plan* plans, const lmvd_substep_args* args, void* const* workspaces,
+                                 int count, int nsub, hipStream_t origin, std::vector<hipStream_t>& br,
+                                 std::vector<hipEvent_t>& ev, lmvd_graph_s* g) {
+  std::vector<Recorder> rec(count);
+  for (int i = 0; i < count; ++i)
+    for (int k = 0; k < nsub; ++k) {
+      const lmvd_status st = run_substep(plans[i], &args[size_t(i) * nsub + k], workspaces[i], nullptr, &rec[i]);
+      if (st != LMVD_OK) return st;
+    }
+  const size_t nops = rec[0].ops.size();
+  bool same = true;
+  for (int i = 1; i < count && same; ++i) {
+    if (rec[i].ops.size() != nops) {
+      same = false;
+      break;
+    }
+    for (size_t j = 0; j < nops && same; ++j) {
+      const RecOp &x = rec[0].ops[j], &y = rec[i].ops[j];
+      if (x.job != y.job || (x.job && x.grid.y != y.grid.y)) same = false;
+    }
+  }
+  auto fail_capture = [&](lmvd_status e) {
+    hipGraph_t junk = nullptr;
+    if (hipStreamEndCapture(origin, &junk) == hipSuccess && junk) (void)hipGraphDestroy(junk);
+    return e;
+  };
+  if (!same) {
+    // one branch per instance, its substeps in order
+    if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess) return LMVD_EHIP;
+    if (hipEventRecord(ev[count], origin) != hipSuccess) return fail_capture(LMVD_EHIP);
+    for (int i = 0; i < count; ++i) {
+      if (hipStreamWaitEvent(br[i], ev[count], 0) != hipSuccess) return fail_capture(LMVD_EHIP);
+      for (int k = 0; k < nsub; ++k) {
+        const lmvd_status st = run_substep(plans[i], &args[size_t(i) * nsub + k], workspaces[i], br[i]);
+        if (st != LMVD_OK) return fail_capture(st);
+      }
+      if (hipEventRecord(ev[i], br[i]) != hipSuccess || hipStreamWaitEvent(origin, ev[i], 0) != hipSuccess)
+        return fail_capture(LMVD_EHIP);
+    }
+    if (hipStreamEndCapture(origin, &g->graph) != hipSuccess) return LMVD_EHIP;
+    g->grouped = 0;
+    return LMVD_OK;
+  }
+  // arena: the instances' plans, then per column job the records of all instances
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  std::vector<unsigned char> host(al(size_t(count) * sizeof(DevPlan)));
+  for (int i = 0; i < count; ++i) std::memcpy(host.data() + size_t(i) * sizeof(DevPlan), &plans[i]->D, sizeof(DevPlan));
+  std::vector<size_t> off(nops, 0);
+  std::vector<unsigned> tot(nops, 0);
+  std::vector<size_t> lds(nops, 0);
+  for (size_t j = 0; j < nops; ++j) {
+    const JobOps* job = rec[0].ops[j].job;
+    if (!job) continue;
+    off[j] = host.size();
+    host.resize(al(host.size() + size_t(count) * job->rec_size));
+    unsigned b0 = 0;
+    for (int i = 0; i < count; ++i) {
+      const RecOp& o = rec[i].ops[j];
+      job->pack(host.data() + off[j] + size_t(i) * job->rec_size, o.args.data(), i, b0, o.grid.x);
+      b0 += o.grid.x;
+      lds[j] = std::max(lds[j], o.lds);
+    }
+    tot[j] = b0;
+  }
+  if (hipMalloc(&g->arena, host.size()) != hipSuccess) return LMVD_ENOMEM;
+  if (hipMemcpy(g->arena, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) return LMVD_EHIP;
+  const char* dev = static_cast<const char*>(g->arena);
+  const DevPlan* dplans = reinterpret_cast<const DevPlan*>(dev);
+  if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess) return LMVD_EHIP;
+  for (size_t j = 0; j < nops;) {
+    if (const JobOps* job = rec[0].ops[j].job) {
+      job->launch(dplans, dev + off[j], count, dim3(tot[j], rec[0].ops[j].grid.y), lds[j], origin);
+      ++j;
+      continue;
+    }
+    size_t j2 = j;  // a run of per-instance work: one branch per instance
+    while (j2 < nops && !rec[0].ops[j2].job) ++j2;
+    if (hipEventRecord(ev[count], origin) != hipSuccess) return fail_capture(LMVD_EHIP);
+    for (int i = 0; i < count; ++i) {
+      if (hipStreamWaitEvent(br[i], ev[count], 0) != hipSuccess) return fail_capture(LMVD_EHIP);
+      for (size_t q = j; q < j2; ++q) {
+        const lmvd_status st = rec[i].ops[q].fn(br[i]);
+        if (st != LMVD_OK) return fail_capture(st);
+      }
+      if (hipEventRecord(ev[i], br[i]) != hipSuccess || hipStreamWaitEvent(origin, ev[i], 0) != hipSuccess)
+        return fail_capture(LMVD_EHIP);
+    }
+    j = j2;
+  }
+  if (hipGetLastError() != hipSuccess) return fail_capture(LMVD_EHIP);
+  if (hipStreamEndCapture(origin, &g->graph) != hipSuccess) return LMVD_EHIP;
+  g->grouped = 1;
+  return LMVD_OK;
+}
+}  // namespace lmvd
 
 lmvd_status lmvd_graph_create(const lmvd_plan* plans, const lmvd_substep_args* args, void* const* workspaces,
                               int32_t count, int32_t nsub, lmvd_graph* out) {
@@ -3345,59 +3720,32 @@ lmvd_status lmvd_graph_create(const lmvd_plan* plans, const lmvd_substep_args* a
     }
   }
   if (hipSetDevice(dev) != hipSuccess) return LMVD_EHIP;
+  lmvd_graph g = new (std::nothrow) lmvd_graph_s;
+  if (!g) return LMVD_ENOMEM;
+  g->device = dev;
   hipStream_t origin = nullptr;
-  if (hipStreamCreateWithFlags(&origin, hipStreamNonBlocking) != hipSuccess) return LMVD_EHIP;
   std::vector<hipStream_t> br(count, nullptr);
   std::vector<hipEvent_t> ev(count + 1, nullptr);
   lmvd_status st = LMVD_OK;
-  auto fail = [&](lmvd_status e) { if (st == LMVD_OK) st = e; };
+  if (hipStreamCreateWithFlags(&origin, hipStreamNonBlocking) != hipSuccess) st = LMVD_EHIP;
   // the A(k) factors are plan state computed on first use: outside the graph
-  for (int i = 0; i < count; ++i) lmvd::ensure_factors(plans[i], origin);
-  if (hipStreamSynchronize(origin) != hipSuccess) fail(LMVD_EHIP);
+  if (st == LMVD_OK) {
+    for (int i = 0; i < count; ++i) lmvd::ensure_factors(plans[i], origin);
+    if (hipStreamSynchronize(origin) != hipSuccess) st = LMVD_EHIP;
+  }
   for (int i = 0; i < count && st == LMVD_OK; ++i)
-    if (hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) != hipSuccess) fail(LMVD_EHIP);
+    if (hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) != hipSuccess) st = LMVD_EHIP;
   for (int i = 0; i <= count && st == LMVD_OK; ++i)
-    if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) fail(LMVD_EHIP);
-  hipGraph_t graph = nullptr;
-  if (st == LMVD_OK) {
-    if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      fail(LMVD_EHIP);
-    } else {
-      // fork: every instance is a branch of its own; its substeps stay in order
-      if (hipEventRecord(ev[count], origin) != hipSuccess) fail(LMVD_EHIP);
-      for (int i = 0; i < count && st == LMVD_OK; ++i) {
-        if (hipStreamWaitEvent(br[i], ev[count], 0) != hipSuccess) { fail(LMVD_EHIP); break; }
-        for (int k = 0; k < nsub && st == LMVD_OK; ++k)
-          fail(run_substep(plans[i], &args[size_t(i) * nsub + k], workspaces[i], br[i]));
-        if (hipEventRecord(ev[i], br[i]) != hipSuccess || hipStreamWaitEvent(origin, ev[i], 0) != hipSuccess)
-          fail(LMVD_EHIP);
-      }
-      if (hipGetLastError() != hipSuccess) fail(LMVD_EHIP);
-      // the capture is always ended, also after a failure inside it
-      if (hipStreamEndCapture(origin, &graph) != hipSuccess) fail(LMVD_EHIP);
-    }
-  }
-  lmvd_graph g = nullptr;
-  if (st == LMVD_OK) {
-    g = new (std::nothrow) lmvd_graph_s;
-    if (!g) fail(LMVD_ENOMEM);
-  }
-  if (st == LMVD_OK) {
-    g->graph = graph;
-    g->device = dev;
-    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) fail(LMVD_EHIP);
-  }
+    if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) st = LMVD_EHIP;
+  if (st == LMVD_OK) st = lmvd::capture_graph(plans, args, workspaces, count, nsub, origin, br, ev, g);
+  if (st == LMVD_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) st = LMVD_EHIP;
   for (hipEvent_t e : ev)
     if (e) (void)hipEventDestroy(e);
   for (hipStream_t b : br)
     if (b) (void)hipStreamDestroy(b);
-  (void)hipStreamDestroy(origin);
+  if (origin) (void)hipStreamDestroy(origin);
   if (st != LMVD_OK) {
-    if (g) {
-      if (g->exec) (void)hipGraphExecDestroy(g->exec);
-      delete g;
-    }
-    if (graph) (void)hipGraphDestroy(graph);
+    (void)lmvd_graph_destroy(g);
     return st;
   }
   *out = g;
@@ -3414,6 +3762,7 @@ lmvd_status lmvd_graph_destroy(lmvd_graph g) {
   if (!g) return LMVD_EINVAL;
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->arena) (void)hipFree(g->arena);
   delete g;
   return LMVD_OK;
 }
