@@ -597,8 +597,7 @@ LMVD_XPLAN(48, 4, 12, 4, 1, 1, 12)
 // EXACT: nn = 2N/3 - 1 (3/2 grid), so the zero-padded positions are known
 // at compile time.
 template <int N, bool EXACT>
-__global__ void __launch_bounds__(kThreads) k_zinv_r(DevPlan P, EvalArgs A, double2* __restrict__ zbuf, int j0,
-                                                    int pb) {
+__device__ __forceinline__ void zinv_r_body(const DevPlan& P, const unsigned bx, const unsigned by, const unsigned bz, const EvalArgs& A, double2* __restrict__ zbuf, int j0, int pb) {
   using LP = LinePlan<N>;
   using ZS = ZShape<N>;
   constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL;
@@ -606,7 +605,7 @@ __global__ void __launch_bounds__(kThreads) k_zinv_r(DevPlan P, EvalArgs A, doub
   extern __shared__ double lds_d[];
   const int tid = threadIdx.x;
   const int ll = tid % LG, tl = tid / LG;
-  const int f = blockIdx.z, jj = blockIdx.y, j = j0 + jj, l = blockIdx.x * LG + ll;
+  const int f = bz, jj = by, j = j0 + jj, l = bx * LG + ll;
   const int nn = EXACT ? NNX : P.nn, nl = P.nl;
   const int h3 = EXACT ? H3X : (nn + 1) / 2, pad = EXACT ? PADX : N - nn;
   const EvalIn in = A.in[f];
@@ -641,18 +640,21 @@ __global__ void __launch_bounds__(kThreads) k_zinv_r(DevPlan P, EvalArgs A, doub
       for (int r = 0; r < RL; ++r) out[size_t(tl + T * c + r * (N / RL)) * nl] = v[c * RL + r];
   }
 }
+template <int N, bool EXACT>
+__global__ void __launch_bounds__(kThreads) k_zinv_r(DevPlan P, EvalArgs A, double2* __restrict__ zbuf, int j0, int pb) {
+  zinv_r_body<N, EXACT>(P, blockIdx.x, blockIdx.y, blockIdx.z, A, zbuf, j0, pb);
+}
 
 // forward z-FFT of size N = m3 and truncation to the retained n.
 template <int N>
-__global__ void __launch_bounds__(kThreads) k_zfwd_r(DevPlan P, const double2* __restrict__ obuf, OutPtrs V, int j0,
-                                                    int pb) {
+__device__ __forceinline__ void zfwd_r_body(const DevPlan& P, const unsigned bx, const unsigned by, const unsigned bz, const double2* __restrict__ obuf, const OutPtrs& V, int j0, int pb) {
   using LP = LinePlan<N>;
   using ZS = ZShape<N>;
   constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL;
   extern __shared__ double lds_d[];
   const int tid = threadIdx.x;
   const int ll = tid % LG, tl = tid / LG;
-  const int g = blockIdx.z, jj = blockIdx.y, l = blockIdx.x * LG + ll;
+  const int g = bz, jj = by, l = bx * LG + ll;
   const int nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = N - nn;
   const bool lok = l < nl;
   const double2* in = obuf + (size_t(g) * pb + jj) * size_t(N) * nl + l;
@@ -672,6 +674,10 @@ __global__ void __launch_bounds__(kThreads) k_zfwd_r(DevPlan P, const double2* _
       }
   }
 }
+template <int N>
+__global__ void __launch_bounds__(kThreads) k_zfwd_r(DevPlan P, const double2* __restrict__ obuf, OutPtrs V, int j0, int pb) {
+  zfwd_r_body<N>(P, blockIdx.x, blockIdx.y, blockIdx.z, obuf, V, j0, pb);
+}
 
 // z kernels with one 64-thread group per line (12 points per thread) and 8
 // lines per 512-thread block, the line index lane-fastest so that loads and
@@ -689,8 +695,7 @@ struct ZPlanW<768> {
 };
 
 template <int N, bool EXACT>
-__global__ void __launch_bounds__(kZWThreads) k_zinv_w(DevPlan P, EvalArgs A, double2* __restrict__ zbuf, int j0,
-                                                      int pb) {
+__device__ __forceinline__ void zinv_w_body(const DevPlan& P, const unsigned bx, const unsigned by, const unsigned bz, const EvalArgs& A, double2* __restrict__ zbuf, int j0, int pb) {
   using ZP = ZPlanW<N>;
   constexpr int T = ZP::T, E = ZP::E, LG = ZP::LG, RL = ZP::RL;
   constexpr int NNX = 2 * N / 3 - 1, H3X = (NNX + 1) / 2, PADX = N - NNX;
@@ -698,7 +703,7 @@ __global__ void __launch_bounds__(kZWThreads) k_zinv_w(DevPlan P, EvalArgs A, do
   double2* twl = reinterpret_cast<double2*>(lds_d + LG * ZP::STRIDE);
   const int tid = threadIdx.x;
   const int ll = tid % LG, tl = tid / LG;
-  const int f = blockIdx.z, jj = blockIdx.y, j = j0 + jj, l = blockIdx.x * LG + ll;
+  const int f = bz, jj = by, j = j0 + jj, l = bx * LG + ll;
   const int nn = EXACT ? NNX : P.nn, nl = P.nl;
   const int h3 = EXACT ? H3X : (nn + 1) / 2, pad = EXACT ? PADX : N - nn;
   rf::fill_stage_tw<N, ZP::R0, ZP::R1, ZP::R2, ZP::R3>(twl, P.fz.tw, tid, kZWThreads);
@@ -749,17 +754,20 @@ __global__ void __launch_bounds__(kZWThreads) k_zinv_w(DevPlan P, EvalArgs A, do
       for (int r = 0; r < RL; ++r) out[size_t(tl + T * c + r * (N / RL)) * nl] = v[c * RL + r];
   }
 }
+template <int N, bool EXACT>
+__global__ void __launch_bounds__(kZWThreads) k_zinv_w(DevPlan P, EvalArgs A, double2* __restrict__ zbuf, int j0, int pb) {
+  zinv_w_body<N, EXACT>(P, blockIdx.x, blockIdx.y, blockIdx.z, A, zbuf, j0, pb);
+}
 
 template <int N>
-__global__ void __launch_bounds__(kZWThreads) k_zfwd_w(DevPlan P, const double2* __restrict__ obuf, OutPtrs V,
-                                                      int j0, int pb) {
+__device__ __forceinline__ void zfwd_w_body(const DevPlan& P, const unsigned bx, const unsigned by, const unsigned bz, const double2* __restrict__ obuf, const OutPtrs& V, int j0, int pb) {
   using ZP = ZPlanW<N>;
   constexpr int T = ZP::T, E = ZP::E, LG = ZP::LG, RL = ZP::RL;
   extern __shared__ double lds_d[];
   double2* twl = reinterpret_cast<double2*>(lds_d + LG * ZP::STRIDE);
   const int tid = threadIdx.x;
   const int ll = tid % LG, tl = tid / LG;
-  const int g = blockIdx.z, jj = blockIdx.y, l = blockIdx.x * LG + ll;
+  const int g = bz, jj = by, l = bx * LG + ll;
   const int nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = N - nn;
   rf::fill_stage_tw<N, ZP::R0, ZP::R1, ZP::R2, ZP::R3>(twl, P.fz.tw, tid, kZWThreads);
   const bool lok = l < nl;
@@ -780,6 +788,10 @@ __global__ void __launch_bounds__(kZWThreads) k_zfwd_w(DevPlan P, const double2*
         else if (pos >= h3 + pad) out[size_t(pos - pad) * nl] = v[c * RL + r];
       }
   }
+}
+template <int N>
+__global__ void __launch_bounds__(kZWThreads) k_zfwd_w(DevPlan P, const double2* __restrict__ obuf, OutPtrs V, int j0, int pb) {
+  zfwd_w_body<N>(P, blockIdx.x, blockIdx.y, blockIdx.z, obuf, V, j0, pb);
 }
 
 // Pointwise products of the x-pass.  Two real fields x, y travel through one
@@ -1005,7 +1017,8 @@ __device__ __forceinline__ void herm_pair_load(double2* v, const double2* __rest
 // output pair u + i v with transform W splits as U_k = (W_k + conj W_{N-k})/2,
 // V_k = (W_k - conj W_{N-k})/(2i).  grid (ceil(m3/BG), planes), block BG*T.
 template <int PH, int N>
-__device__ __forceinline__ void xpair_body(const DevPlan& P, const double2* __restrict__ zbuf,
+__device__ __forceinline__ void xpair_body(const DevPlan& P, const unsigned bx, const unsigned by,
+                                           const double2* __restrict__ zbuf,
                                            double2* __restrict__ obuf, int pb, double* phys_out,
                                            const double* phys_in, int j0, double* __restrict__ aux) {
   using LP = XPlan<N>;
@@ -1019,7 +1032,7 @@ __device__ __forceinline__ void xpair_body(const DevPlan& P, const double2* __re
   // one line per wavefront when T is the wave size: the line index is then
   // uniform, and so are the line's base addresses (scalar registers)
   const int tl = tid % T, line = (T == 64) ? __builtin_amdgcn_readfirstlane(tid / T) : tid / T;
-  const int jj = blockIdx.y, b = blockIdx.x * BG + line;
+  const int jj = by, b = bx * BG + line;
   const int M3 = P.m3;
   const bool bok = b < M3;
   const int bb = bok ? b : 0;
@@ -1174,9 +1187,7 @@ __device__ __forceinline__ void line_in(int i, double (&s0)[E], double (&s1)[E],
 }
 
 template <int PH, int N>
-__global__ void __launch_bounds__(kThreads) k_xline(DevPlan P, const double2* __restrict__ zbuf,
-                                                   double2* __restrict__ obuf, int pb, int j0,
-                                                   const double* __restrict__ aux) {
+__device__ __forceinline__ void xline_body(const DevPlan& P, const unsigned bx, const unsigned by, const double2* __restrict__ zbuf, double2* __restrict__ obuf, int pb, int j0, const double* __restrict__ aux) {
   using LP = XPlan<N>;
   using S = LineOp<PH>;
   constexpr int T = LP::T, E = LP::E, RL = LP::RL, EL = E / RL, BG = LP::BG, NL = N / 3;
@@ -1186,8 +1197,8 @@ __global__ void __launch_bounds__(kThreads) k_xline(DevPlan P, const double2* __
   double2* twl = reinterpret_cast<double2*>(lds_d + BG * LP::STRIDE);
   const int tid = threadIdx.x;
   const int tl = tid % T, grp = (T == 64) ? __builtin_amdgcn_readfirstlane(tid / T) : tid / T;
-  const int jj = blockIdx.y;
-  const int b0 = 2 * (blockIdx.x * BG + grp), b1 = b0 + 1;
+  const int jj = by;
+  const int b0 = 2 * (bx * BG + grp), b1 = b0 + 1;
   const int M3 = P.m3;
   const bool ok0 = b0 < M3, ok1 = b1 < M3;
   const int c0 = ok0 ? b0 : 0, c1 = ok1 ? b1 : 0;
@@ -1264,6 +1275,10 @@ __global__ void __launch_bounds__(kThreads) k_xline(DevPlan P, const double2* __
       }
   }
 }
+template <int PH, int N>
+__global__ void __launch_bounds__(kThreads) k_xline(DevPlan P, const double2* __restrict__ zbuf, double2* __restrict__ obuf, int pb, int j0, const double* __restrict__ aux) {
+  xline_body<PH, N>(P, blockIdx.x, blockIdx.y, zbuf, obuf, pb, j0, aux);
+}
 
 // Kernels of the x-pass.  The u, rho, C_ij pass keeps four values per point
 // across five output transforms; its register budget is capped at two waves
@@ -1272,13 +1287,13 @@ template <int PH, int N>
 __global__ void __launch_bounds__(kThreads) k_xpair(DevPlan P, const double2* __restrict__ zbuf,
                                                    double2* __restrict__ obuf, int pb, double* phys_out,
                                                    const double* phys_in, int j0, double* __restrict__ aux) {
-  xpair_body<PH, N>(P, zbuf, obuf, pb, phys_out, phys_in, j0, aux);
+  xpair_body<PH, N>(P, blockIdx.x, blockIdx.y, zbuf, obuf, pb, phys_out, phys_in, j0, aux);
 }
 template <int PH, int N>
 __global__ void __launch_bounds__(kThreads, 2) k_xpair_w2(DevPlan P, const double2* __restrict__ zbuf,
                                                          double2* __restrict__ obuf, int pb, double* phys_out,
                                                          const double* phys_in, int j0, double* __restrict__ aux) {
-  xpair_body<PH, N>(P, zbuf, obuf, pb, phys_out, phys_in, j0, aux);
+  xpair_body<PH, N>(P, blockIdx.x, blockIdx.y, zbuf, obuf, pb, phys_out, phys_in, j0, aux);
 }
 
 
@@ -2485,32 +2500,49 @@ template <class A>
 struct GRec {
   A a;
   int inst;
-  unsigned b0, nbx;
+  unsigned b0, nbx, nby;  // first block, and the x and y extents of the instance's grid
 };
 
 template <class Job>
-__global__ void __launch_bounds__(kThreads) k_group(const DevPlan* __restrict__ plans,
-                                                   const GRec<typename Job::Args>* __restrict__ recs, int nrec) {
-  const unsigned bx = blockIdx.x;
-  int lo = 0, hi = nrec - 1;  // the last record with b0 <= bx (records ascend, no gaps)
+__device__ __forceinline__ void group_dispatch(const DevPlan* __restrict__ plans,
+                                               const GRec<typename Job::Args>* __restrict__ recs, int nrec) {
+  const unsigned bid = blockIdx.x;
+  int lo = 0, hi = nrec - 1;  // the last record with b0 <= bid (records ascend, no gaps)
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (recs[mid].b0 <= bx) lo = mid;
+    if (recs[mid].b0 <= bid) lo = mid;
     else hi = mid - 1;
   }
   const GRec<typename Job::Args>& R = recs[lo];
-  Job::run(plans[R.inst], bx - R.b0, blockIdx.y, R.a);
+  const unsigned loc = bid - R.b0, rest = loc / R.nbx;
+  Job::run(plans[R.inst], loc % R.nbx, rest % R.nby, rest / R.nby, R.a);
+}
+// one grouped kernel per job, with the job's own launch bounds
+template <class Job>
+__global__ void __launch_bounds__(Job::kBound) k_group(const DevPlan* __restrict__ plans,
+                                                       const GRec<typename Job::Args>* __restrict__ recs, int nrec) {
+  group_dispatch<Job>(plans, recs, nrec);
+}
+template <class Job>
+__global__ void __launch_bounds__(Job::kBound, Job::kMinBlocks) k_group_mb(
+    const DevPlan* __restrict__ plans, const GRec<typename Job::Args>* __restrict__ recs, int nrec) {
+  group_dispatch<Job>(plans, recs, nrec);
 }
 
+// column jobs: 256-thread blocks
+struct ColumnJob {
+  static constexpr int kBound = kThreads, kBlock = kThreads, kMinBlocks = 0;
+};
+
 template <int LA, int UA, int W>
-struct JobPrologue {
+struct JobPrologue : ColumnJob {
   struct Args {
     int md;
     MdArgs M;
     ValuesZArgs Z;
     GuessArgs G;
   };
-  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, const Args& A) {
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned, const Args& A) {
     const int job = int(by) + (A.md ? 0 : 1);
     const size_t t = size_t(bx) * blockDim.x + threadIdx.x;
     if (job == 0) md_body<LA, UA, W>(P, int(t), A.M);
@@ -2523,7 +2555,7 @@ struct JobPrologue {
 };
 
 template <int EPI>
-struct JobProj {
+struct JobProj : ColumnJob {
   struct Args {
     int kind;
     const double2* in;
@@ -2532,7 +2564,7 @@ struct JobProj {
     double2 *z_out, *vals_out, *vals_out1;
     int stage, ncol;
   };
-  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, unsigned, const Args& A) {
     proj_body<EPI>(P, int(bx * blockDim.x + threadIdx.x), A.kind, A.in, A.out, A.add, A.z, A.zt_prev, A.z_out,
                    A.vals_out, A.vals_out1, A.stage, A.ncol);
   }
@@ -2542,13 +2574,13 @@ struct JobProj {
   }
 };
 
-struct JobProj3 {
+struct JobProj3 : ColumnJob {
   struct Args {
     int kind;
     ProjBatch B;
     int ncol;
   };
-  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, const Args& A) {
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned, const Args& A) {
     proj_body<EPI_STORE>(P, int(bx * blockDim.x + threadIdx.x), A.kind, A.B.in[by], A.B.out[by], nullptr, nullptr,
                          nullptr, nullptr, nullptr, nullptr, 0, A.ncol);
   }
@@ -2558,14 +2590,14 @@ struct JobProj3 {
 };
 
 template <int LA, int UA, int LB, bool STAGE>
-struct JobMc {
+struct JobMc : ColumnJob {
   struct Args {
     const double2* vals;
     double2 *yp, *yt;
     const double2 *d1, *d2, *d3;
     double2 *V1, *V2, *V3, *rhoc, *c2, *mparc;
   };
-  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, unsigned, const Args& A) {
     mc_body<LA, UA, LB, STAGE>(P, bx, A.vals, A.yp, A.yt, A.d1, A.d2, A.d3, A.V1, A.V2, A.V3, A.rhoc, A.c2,
                                A.mparc);
   }
@@ -2576,13 +2608,13 @@ struct JobMc {
 };
 
 template <int GROUP, int W, int LB>
-struct JobFlux {
+struct JobFlux : ColumnJob {
   struct Args {
     const double2 *Ca, *Cb, *Cc, *u1, *u2, *u3;
     double2 *Ta, *Tb, *Tc, *RO, *RP;
     const double2* rhov;
   };
-  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, unsigned, const Args& A) {
     flux_body<GROUP, W, LB>(P, bx, A.Ca, A.Cb, A.Cc, A.u1, A.u2, A.u3, A.Ta, A.Tb, A.Tc, A.RO, A.RP, A.rhov);
   }
   static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
@@ -2591,13 +2623,13 @@ struct JobFlux {
   }
 };
 
-struct JobRhsFluct {
+struct JobRhsFluct : ColumnJob {
   struct Args {
     const double2 *RO, *RP, *phi, *om, *rphi_prev, *rom_prev;
     double2 *phi_out, *om_out, *rphi_out, *rom_out, *yphi, *yom;
     int stage;
   };
-  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, unsigned, const Args& A) {
     rhs_fluct_body(P, bx, A.RO, A.RP, A.phi, A.om, A.rphi_prev, A.rom_prev, A.phi_out, A.om_out, A.rphi_out,
                    A.rom_out, A.yphi, A.yom, A.stage);
   }
@@ -2607,19 +2639,113 @@ struct JobRhsFluct {
   }
 };
 
-struct JobRhsMean {
+struct JobRhsMean : ColumnJob {
   struct Args {
     const double2 *T12, *T23;
     const double *m1, *m3, *r1p, *r3p;
     double *m1o, *m3o, *r1o, *r3o;
     int stage;
   };
-  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, const Args& A) {
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, unsigned, const Args& A) {
     rhs_mean_body(P, bx, A.T12, A.T23, A.m1, A.m3, A.r1p, A.r3p, A.m1o, A.m3o, A.r1o, A.r3o, A.stage);
   }
   static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
     hipLaunchKernelGGL(k_rhs_mean, g, dim3(kThreads), lds, s, P, A.T12, A.T23, A.m1, A.m3, A.r1p, A.r3p, A.m1o,
                        A.m3o, A.r1o, A.r3o, A.stage);
+  }
+};
+
+// plane jobs (register-FFT kernels; block shape fixed by the transform size)
+template <int N, bool EXACT>
+struct JobZinvR {
+  static constexpr int kBound = kThreads, kBlock = ZShape<N>::LG * ZShape<N>::T, kMinBlocks = 0;
+  struct Args {
+    EvalArgs A;
+    double2* zbuf;
+    int j0, pb;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned bz, const Args& a) {
+    zinv_r_body<N, EXACT>(P, bx, by, bz, a.A, a.zbuf, a.j0, a.pb);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
+    hipLaunchKernelGGL((k_zinv_r<N, EXACT>), g, dim3(kBlock), lds, s, P, a.A, a.zbuf, a.j0, a.pb);
+  }
+};
+template <int N>
+struct JobZfwdR {
+  static constexpr int kBound = kThreads, kBlock = ZShape<N>::LG * ZShape<N>::T, kMinBlocks = 0;
+  struct Args {
+    const double2* obuf;
+    OutPtrs V;
+    int j0, pb;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned bz, const Args& a) {
+    zfwd_r_body<N>(P, bx, by, bz, a.obuf, a.V, a.j0, a.pb);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
+    hipLaunchKernelGGL(k_zfwd_r<N>, g, dim3(kBlock), lds, s, P, a.obuf, a.V, a.j0, a.pb);
+  }
+};
+template <int N, bool EXACT>
+struct JobZinvW {
+  static constexpr int kBound = kZWThreads, kBlock = kZWThreads, kMinBlocks = 0;
+  using Args = typename JobZinvR<N, EXACT>::Args;
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned bz, const Args& a) {
+    zinv_w_body<N, EXACT>(P, bx, by, bz, a.A, a.zbuf, a.j0, a.pb);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
+    hipLaunchKernelGGL((k_zinv_w<N, EXACT>), g, dim3(kBlock), lds, s, P, a.A, a.zbuf, a.j0, a.pb);
+  }
+};
+template <int N>
+struct JobZfwdW {
+  static constexpr int kBound = kZWThreads, kBlock = kZWThreads, kMinBlocks = 0;
+  using Args = typename JobZfwdR<N>::Args;
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned bz, const Args& a) {
+    zfwd_w_body<N>(P, bx, by, bz, a.obuf, a.V, a.j0, a.pb);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
+    hipLaunchKernelGGL(k_zfwd_w<N>, g, dim3(kBlock), lds, s, P, a.obuf, a.V, a.j0, a.pb);
+  }
+};
+template <int PH, int N>
+struct JobXline {
+  static constexpr int kBound = kThreads, kBlock = XPlan<N>::BG * XPlan<N>::T, kMinBlocks = 0;
+  struct Args {
+    const double2* zbuf;
+    double2* obuf;
+    int pb, j0;
+    const double* aux;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned, const Args& a) {
+    xline_body<PH, N>(P, bx, by, a.zbuf, a.obuf, a.pb, a.j0, a.aux);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
+    hipLaunchKernelGGL((k_xline<PH, N>), g, dim3(kBlock), lds, s, P, a.zbuf, a.obuf, a.pb, a.j0, a.aux);
+  }
+};
+template <int PH, int N, int MINB>
+struct JobXpair {
+  static constexpr int kBound = kThreads, kBlock = XPlan<N>::BG * XPlan<N>::T, kMinBlocks = MINB;
+  struct Args {
+    const double2* zbuf;
+    double2* obuf;
+    int pb;
+    double* phys_out;
+    const double* phys_in;
+    int j0;
+    double* aux;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned, const Args& a) {
+    xpair_body<PH, N>(P, bx, by, a.zbuf, a.obuf, a.pb, a.phys_out, a.phys_in, a.j0, a.aux);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
+    if constexpr (MINB == 2)
+      hipLaunchKernelGGL((k_xpair_w2<PH, N>), g, dim3(kBlock), lds, s, P, a.zbuf, a.obuf, a.pb, a.phys_out,
+                         a.phys_in, a.j0, a.aux);
+    else
+      hipLaunchKernelGGL((k_xpair<PH, N>), g, dim3(kBlock), lds, s, P, a.zbuf, a.obuf, a.pb, a.phys_out, a.phys_in,
+                         a.j0, a.aux);
   }
 };
 
@@ -2950,23 +3076,29 @@ static size_t ncols(const lmvd_plan_s* p) { return size_t(p->H.nn) * p->H.nl; }
 
 struct JobOps {  // type-erased job: record size, packing, grouped launch
   size_t rec_size;
-  void (*pack)(void* dst, const void* args, int inst, unsigned b0, unsigned nbx);
-  void (*launch)(const DevPlan* plans, const void* recs, int nrec, dim3 grid, size_t lds, hipStream_t s);
+  void (*pack)(void* dst, const void* args, int inst, unsigned b0, dim3 grid);
+  void (*launch)(const DevPlan* plans, const void* recs, int nrec, unsigned blocks, size_t lds, hipStream_t s);
 };
 
 template <class Job>
 struct JobOpsOf {
   using A = typename Job::Args;
-  static void pack(void* dst, const void* args, int inst, unsigned b0, unsigned nbx) {
+  static void pack(void* dst, const void* args, int inst, unsigned b0, dim3 g) {
     GRec<A> r;
     std::memcpy(&r.a, args, sizeof(A));
     r.inst = inst;
     r.b0 = b0;
-    r.nbx = nbx;
+    r.nbx = g.x;
+    r.nby = g.y;
     std::memcpy(dst, &r, sizeof(r));
   }
-  static void launch(const DevPlan* plans, const void* recs, int nrec, dim3 grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_group<Job>, grid, dim3(kThreads), lds, s, plans, static_cast<const GRec<A>*>(recs), nrec);
+  static void launch(const DevPlan* plans, const void* recs, int nrec, unsigned blocks, size_t lds, hipStream_t s) {
+    if constexpr (Job::kMinBlocks > 0)
+      hipLaunchKernelGGL(k_group_mb<Job>, dim3(blocks), dim3(Job::kBlock), lds, s, plans,
+                         static_cast<const GRec<A>*>(recs), nrec);
+    else
+      hipLaunchKernelGGL(k_group<Job>, dim3(blocks), dim3(Job::kBlock), lds, s, plans,
+                         static_cast<const GRec<A>*>(recs), nrec);
   }
   static const JobOps ops;
 };
@@ -3072,60 +3204,58 @@ static EvalIn ev(const void* a, int kind, int ma = MU_ONE, const void* b = nullp
   return e;
 }
 
-// register-FFT launches for the specialised sizes; false if the size has none
+// register-FFT launches for the specialised sizes
 template <int N>
-static void launch_zinv_t(lmvd_plan_s* p, hipStream_t s, const EvalArgs& A, double2* zbuf, int j0, int nb, int nin) {
+static void launch_zinv_t(const Ctx& c, const EvalArgs& A, double2* zbuf, int j0, int nb, int nin) {
+  lmvd_plan_s* p = c.p;
+  const bool exact = p->H.nn == 2 * N / 3 - 1;
   if constexpr (N == 768) {
     using ZP = ZPlanW<N>;
     const dim3 g((p->H.nl + ZP::LG - 1) / ZP::LG, nb, nin);
     const size_t lds = size_t(ZP::LG) * ZP::STRIDE * sizeof(double) +
                        size_t(rf::StageTw<ZP::R0, ZP::R1, ZP::R2, ZP::R3>::SIZE) * sizeof(double2);
-    if (p->H.nn == 2 * N / 3 - 1)
-      hipLaunchKernelGGL((k_zinv_w<N, true>), g, dim3(kZWThreads), lds, s, p->D, A, zbuf, j0, p->pb);
-    else
-      hipLaunchKernelGGL((k_zinv_w<N, false>), g, dim3(kZWThreads), lds, s, p->D, A, zbuf, j0, p->pb);
+    if (exact) col<JobZinvW<N, true>>(c, g, lds, {A, zbuf, j0, p->pb});
+    else col<JobZinvW<N, false>>(c, g, lds, {A, zbuf, j0, p->pb});
     return;
   }
   using ZS = ZShape<N>;
   const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nin);
   const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
-  if (p->H.nn == 2 * N / 3 - 1)
-    hipLaunchKernelGGL((k_zinv_r<N, true>), g, dim3(ZS::LG * ZS::T), lds, s, p->D, A, zbuf, j0, p->pb);
-  else
-    hipLaunchKernelGGL((k_zinv_r<N, false>), g, dim3(ZS::LG * ZS::T), lds, s, p->D, A, zbuf, j0, p->pb);
+  if (exact) col<JobZinvR<N, true>>(c, g, lds, {A, zbuf, j0, p->pb});
+  else col<JobZinvR<N, false>>(c, g, lds, {A, zbuf, j0, p->pb});
 }
 template <int N>
-static void launch_zfwd_t(lmvd_plan_s* p, hipStream_t s, const double2* obuf, const OutPtrs& V, int j0, int nb,
-                          int nout) {
+static void launch_zfwd_t(const Ctx& c, const double2* obuf, const OutPtrs& V, int j0, int nb, int nout) {
+  lmvd_plan_s* p = c.p;
   if constexpr (N == 768) {
     using ZP = ZPlanW<N>;
     const dim3 g((p->H.nl + ZP::LG - 1) / ZP::LG, nb, nout);
     const size_t lds = size_t(ZP::LG) * ZP::STRIDE * sizeof(double) +
                        size_t(rf::StageTw<ZP::R0, ZP::R1, ZP::R2, ZP::R3>::SIZE) * sizeof(double2);
-    hipLaunchKernelGGL(k_zfwd_w<N>, g, dim3(kZWThreads), lds, s, p->D, obuf, V, j0, p->pb);
+    col<JobZfwdW<N>>(c, g, lds, {obuf, V, j0, p->pb});
     return;
   }
   using ZS = ZShape<N>;
   const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nout);
   const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
-  hipLaunchKernelGGL(k_zfwd_r<N>, g, dim3(ZS::LG * ZS::T), lds, s, p->D, obuf, V, j0, p->pb);
+  col<JobZfwdR<N>>(c, g, lds, {obuf, V, j0, p->pb});
 }
 template <int PH, int N>
-static void launch_xpass_t(lmvd_plan_s* p, hipStream_t s, const double2* zbuf, double2* obuf, double* phys_out,
+static void launch_xpass_t(const Ctx& c, const double2* zbuf, double2* obuf, double* phys_out,
                            const double* phys_in, int j0, int nb, double* aux) {
+  lmvd_plan_s* p = c.p;
   using LP = XPlan<N>;
   const dim3 g((p->H.cfg.m3 + LP::BG - 1) / LP::BG, nb);
   const size_t lds = size_t(LP::BG) * LP::STRIDE * sizeof(double) +
                      size_t(rf::StageTw<LP::R0, LP::R1, LP::R2, LP::R3>::SIZE) * sizeof(double2);
   if constexpr (PH == PH_L || PH == PH_RHOT) {
     const dim3 g2((p->H.cfg.m3 + 2 * LP::BG - 1) / (2 * LP::BG), nb);
-    hipLaunchKernelGGL((k_xline<PH, N>), g2, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, j0, aux);
-  } else if constexpr (PH == PH_VEL)
-    hipLaunchKernelGGL((k_xpair_w2<PH, N>), g, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out,
-                       phys_in, j0, aux);
-  else
-    hipLaunchKernelGGL((k_xpair<PH, N>), g, dim3(LP::BG * LP::T), lds, s, p->D, zbuf, obuf, p->pb, phys_out, phys_in,
-                       j0, aux);
+    col<JobXline<PH, N>>(c, g2, lds, {zbuf, obuf, p->pb, j0, aux});
+  } else if constexpr (PH == PH_VEL) {
+    col<JobXpair<PH, N, 2>>(c, g, lds, {zbuf, obuf, p->pb, phys_out, phys_in, j0, aux});
+  } else {
+    col<JobXpair<PH, N, 0>>(c, g, lds, {zbuf, obuf, p->pb, phys_out, phys_in, j0, aux});
+  }
 }
 static bool zreg_size(int n) {
   return n == 768 || n == 192 || n == 144 || n == 96 || n == 72 || n == 48;
@@ -3186,12 +3316,15 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
       for (const EvalIn& e : ins) terms += e.b ? 2 : 1;
         ProfScope ps(p, KC_ZINV, c.s, nb * (terms * splane + nin * zplane));
       if (zr) {
-#define CALLZ(N) launch_zinv_t<N>(p, c.s, A, zbuf, j0, nb, int(ins.size()))
+#define CALLZ(N) launch_zinv_t<N>(c, A, zbuf, j0, nb, int(ins.size()))
         LMVD_ZSWITCH(M3, CALLZ)
 #undef CALLZ
       } else {
         dim3 g1((nl + lg - 1) / lg, nb, int(ins.size()));
-        hipLaunchKernelGGL(k_eval_zinv, g1, dim3(kThreads), lds_z, c.s, p->D, A, zbuf, j0, p->pb, lg);
+        (void)per_instance(c, [=](const Ctx& cc) {
+          hipLaunchKernelGGL(k_eval_zinv, g1, dim3(kThreads), lds_z, cc.s, cc.p->D, A, zbuf, j0, cc.p->pb, lg);
+          return LMVD_OK;
+        });
       }
     }
     {
@@ -3199,24 +3332,30 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
                            : (PH == PH_VEL) ? KC_XPASS_VEL : KC_XPASS_IO;
       ProfScope ps(p, xcls, c.s, nb * ((nin + nout) * zplane + naux * double(M3) * H.cfg.m1 * 8.0));
       if (xr) {
-#define CALLX(N) launch_xpass_t<PH, N>(p, c.s, zbuf, obuf, phys_out, phys_in, j0, nb, aux)
+#define CALLX(N) launch_xpass_t<PH, N>(c, zbuf, obuf, phys_out, phys_in, j0, nb, aux)
         LMVD_XSWITCH(H.cfg.m1, CALLX)
 #undef CALLX
       } else {
         dim3 g2((M3 + bg - 1) / bg, nb);
-        hipLaunchKernelGGL(k_xpass<PH>, g2, dim3(kThreads), lds_x, c.s, p->D, zbuf, obuf, p->pb, bg, phys_out,
-                           phys_in, j0, aux);
+        (void)per_instance(c, [=](const Ctx& cc) {
+          hipLaunchKernelGGL(k_xpass<PH>, g2, dim3(kThreads), lds_x, cc.s, cc.p->D, zbuf, obuf, cc.p->pb, bg,
+                             phys_out, phys_in, j0, aux);
+          return LMVD_OK;
+        });
       }
     }
     if (!outs.empty()) {
       ProfScope ps(p, KC_ZFWD, c.s, nb * nout * (zplane + splane));
       if (p->use_reg && zreg_size(M3)) {
-#define CALLF(N) launch_zfwd_t<N>(p, c.s, obuf, V, j0, nb, int(outs.size()))
+#define CALLF(N) launch_zfwd_t<N>(c, obuf, V, j0, nb, int(outs.size()))
         LMVD_ZSWITCH(M3, CALLF)
 #undef CALLF
       } else {
         dim3 g3((nl + lg - 1) / lg, nb, int(outs.size()));
-        hipLaunchKernelGGL(k_zfwd, g3, dim3(kThreads), lds_z, c.s, p->D, obuf, V, j0, p->pb, lg);
+        (void)per_instance(c, [=](const Ctx& cc) {
+          hipLaunchKernelGGL(k_zfwd, g3, dim3(kThreads), lds_z, cc.s, cc.p->D, obuf, V, j0, cc.p->pb, lg);
+          return LMVD_OK;
+        });
       }
     }
   }
@@ -3386,12 +3525,10 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     col<JobPrologue<8, 8, 8>>(c, dim3(cgrid.x, 2), 0, {0, MdArgs{}, zargs, gargs});
   }
   // 2. R_z
-  st = per_instance(c, [=](const Ctx& cc) {
-    return plane_phase<PH_RZ>(cc,
-                              {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT),
-                               ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
-                              {vals[0]});
-  });
+  st = plane_phase<PH_RZ>(c,
+                          {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT),
+                           ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
+                          {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
   if (kf == 0) {
@@ -3409,12 +3546,10 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   // 3. fixed-point iterations z_t^k = L(z) z_t^{k-1} + R_z
   for (int it = 0; it < kf; ++it) {
     const bool last = (it == kf - 1);
-    st = per_instance(c, [=](const Ctx& cc) { return plane_phase<PH_RHOT>(cc, {ev(vzt, EV_IDENT)}, {vals[0]}); });
+    st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
     if (st != LMVD_OK) return st;
     mc_step(false);
-    st = per_instance(c, [=](const Ctx& cc) {
-      return plane_phase<PH_L>(cc, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)}, {vals[0]});
-    });
+    st = plane_phase<PH_L>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)}, {vals[0]});
     if (st != LMVD_OK) return st;
     double2* next = (last && user_zt) ? user_zt : (cur == zta ? ztb : zta);
     const int n = int(ncol);
@@ -3429,17 +3564,15 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     cur = next;
   }
   // m^c of the stage from z_t^{k_f}
-  st = per_instance(c, [=](const Ctx& cc) { return plane_phase<PH_RHOT>(cc, {ev(vzt, EV_IDENT)}, {vals[0]}); });
+  st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
   if (st != LMVD_OK) return st;
   mc_step(true);  // m = m^d + m^c values
   // 4./5. velocities, density, fluxes
   // u = m/rho, rho and C_ij = -m_i m_j/rho on the physical grid; u_hat by interpolation;
   // T_ij = C_ij + tau_ij(u_hat) projected
   double2* cv[6] = {vals[4], vals[5], vals[6], vals[7], vals[8], vals[9]};
-  st = per_instance(c, [=](const Ctx& cc) {
-    return plane_phase<PH_VEL>(cc, {ev(vz0, EV_IDENT), ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
-                               {vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]});
-  });
+  st = plane_phase<PH_VEL>(c, {ev(vz0, EV_IDENT), ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
+                           {vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]});
   if (st != LMVD_OK) return st;
   {
     const int n = int(ncol);
@@ -3625,7 +3758,7 @@ static lmvd_status capture_graph(const lmvd_plan* plans, const lmvd_substep_args
     }
     for (size_t j = 0; j < nops && same; ++j) {
       const RecOp &x = rec[0].ops[j], &y = rec[i].ops[j];
-      if (x.job != y.job || (x.job && x.grid.y != y.grid.y)) same = false;
+      if ((x.job == nullptr) != (y.job == nullptr)) same = false;
     }
   }
   auto fail_capture = [&](lmvd_status e) {
@@ -3650,26 +3783,39 @@ static lmvd_status capture_graph(const lmvd_plan* plans, const lmvd_substep_args
     g->grouped = 0;
     return LMVD_OK;
   }
-  // arena: the instances' plans, then per column job the records of all instances
+  // arena: the instances' plans, then for each job op and each distinct job at it (instances of different
+  // sizes run different kernels) the records of the instances that run it
+  struct Launch {
+    const JobOps* job;
+    size_t off;
+    int n;
+    unsigned blocks;
+    size_t lds;
+  };
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   std::vector<unsigned char> host(al(size_t(count) * sizeof(DevPlan)));
   for (int i = 0; i < count; ++i) std::memcpy(host.data() + size_t(i) * sizeof(DevPlan), &plans[i]->D, sizeof(DevPlan));
-  std::vector<size_t> off(nops, 0);
-  std::vector<unsigned> tot(nops, 0);
-  std::vector<size_t> lds(nops, 0);
+  std::vector<std::vector<Launch>> launches(nops);
   for (size_t j = 0; j < nops; ++j) {
-    const JobOps* job = rec[0].ops[j].job;
-    if (!job) continue;
-    off[j] = host.size();
-    host.resize(al(host.size() + size_t(count) * job->rec_size));
-    unsigned b0 = 0;
+    if (!rec[0].ops[j].job) continue;
+    std::vector<const JobOps*> seen;
     for (int i = 0; i < count; ++i) {
-      const RecOp& o = rec[i].ops[j];
-      job->pack(host.data() + off[j] + size_t(i) * job->rec_size, o.args.data(), i, b0, o.grid.x);
-      b0 += o.grid.x;
-      lds[j] = std::max(lds[j], o.lds);
+      const JobOps* job = rec[i].ops[j].job;
+      if (std::find(seen.begin(), seen.end(), job) != seen.end()) continue;
+      seen.push_back(job);
+      Launch L{job, host.size(), 0, 0, 0};
+      for (int q = i; q < count; ++q) {
+        const RecOp& o = rec[q].ops[j];
+        if (o.job != job) continue;
+        host.resize(L.off + size_t(L.n + 1) * job->rec_size);
+        job->pack(host.data() + L.off + size_t(L.n) * job->rec_size, o.args.data(), q, L.blocks, o.grid);
+        L.blocks += o.grid.x * o.grid.y * o.grid.z;
+        L.lds = std::max(L.lds, o.lds);
+        ++L.n;
+      }
+      host.resize(al(host.size()));
+      launches[j].push_back(L);
     }
-    tot[j] = b0;
   }
   if (hipMalloc(&g->arena, host.size()) != hipSuccess) return LMVD_ENOMEM;
   if (hipMemcpy(g->arena, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) return LMVD_EHIP;
@@ -3677,8 +3823,8 @@ static lmvd_status capture_graph(const lmvd_plan* plans, const lmvd_substep_args
   const DevPlan* dplans = reinterpret_cast<const DevPlan*>(dev);
   if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess) return LMVD_EHIP;
   for (size_t j = 0; j < nops;) {
-    if (const JobOps* job = rec[0].ops[j].job) {
-      job->launch(dplans, dev + off[j], count, dim3(tot[j], rec[0].ops[j].grid.y), lds[j], origin);
+    if (rec[0].ops[j].job) {
+      for (const Launch& L : launches[j]) L.job->launch(dplans, dev + L.off, L.n, L.blocks, L.lds, origin);
       ++j;
       continue;
     }
