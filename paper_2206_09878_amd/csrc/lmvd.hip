@@ -3824,7 +3824,19 @@ static lmvd_status capture_graph(const lmvd_plan* plans, const lmvd_substep_args
   if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess) return LMVD_EHIP;
   for (size_t j = 0; j < nops;) {
     if (rec[0].ops[j].job) {
-      for (const Launch& L : launches[j]) L.job->launch(dplans, dev + L.off, L.n, L.blocks, L.lds, origin);
+      const std::vector<Launch>& LS = launches[j];
+      if (LS.size() == 1) {
+        LS[0].job->launch(dplans, dev + LS[0].off, LS[0].n, LS[0].blocks, LS[0].lds, origin);
+      } else {
+        // the launches of one step cover disjoint instances: side by side on branch streams
+        if (hipEventRecord(ev[count], origin) != hipSuccess) return fail_capture(LMVD_EHIP);
+        for (size_t k = 0; k < LS.size(); ++k) {
+          if (hipStreamWaitEvent(br[k], ev[count], 0) != hipSuccess) return fail_capture(LMVD_EHIP);
+          LS[k].job->launch(dplans, dev + LS[k].off, LS[k].n, LS[k].blocks, LS[k].lds, br[k]);
+          if (hipEventRecord(ev[k], br[k]) != hipSuccess || hipStreamWaitEvent(origin, ev[k], 0) != hipSuccess)
+            return fail_capture(LMVD_EHIP);
+        }
+      }
       ++j;
       continue;
     }
