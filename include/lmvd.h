@@ -46,7 +46,7 @@
  * the ABI.  LMVD_EINVAL: bad configuration, null or misaligned (not 16-byte)
  * pointer, or a bad argument value.  LMVD_EUNSUPPORTED: a grid size outside
  * what the kernels handle (M1/2 and M3 must be products of 2s and 3s with
- * M3 <= 1024 and M1/2 <= 768, N1/2 <= M1/2, N3-1 <= M3, order <= 9).  LMVD_ENOMEM:
+ * M3 <= 1024 and M1/2 <= 768, N1/2 <= M1/2, N3-1 <= M3, order <= 9, n2 <= 4096).  LMVD_ENOMEM:
  * host or device allocation failed in lmvd_plan_create.  LMVD_EHIP: a HIP
  * call failed.  LMVD_ENUMERIC: a factorisation without pivoting met a
  * near-zero pivot at plan creation.
@@ -156,6 +156,10 @@ lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* args, void* wo
  * instances are independent branches; one lmvd_graph_launch runs `nsub`
  * substeps of every instance.
  *
+ * Instances whose substeps line up step by step share one grouped launch per
+ * kernel step (one per transform size for the transforms); otherwise every
+ * instance is a graph branch of its own.
+ *
  * lmvd_graph_create: plans[count], workspaces[count] (one per instance,
  * distinct), args[count * nsub] with args[i * nsub + k] the k-th substep of
  * instance i (same rules as lmvd_substep; the diagnostic outputs md, mc must
@@ -177,6 +181,11 @@ lmvd_status lmvd_graph_create(const lmvd_plan* plans, const lmvd_substep_args* a
                               lmvd_graph* out);
 lmvd_status lmvd_graph_launch(lmvd_graph graph, void* stream);
 lmvd_status lmvd_graph_destroy(lmvd_graph graph);
+/* Which form the graph took: 1 = grouped (every kernel step one launch over
+ * the instances that run it; requires the instances' substeps to line up step
+ * by step: same k_f, stage pattern and kernel variants), 0 = one branch per
+ * instance.  Both give the results of the plain path. */
+lmvd_status lmvd_graph_grouped(lmvd_graph graph, int32_t* grouped);
 
 /* ---- operator entry points (same conventions), one per stage of the path ----
  * They expose the steps of the substep individually for verification. */

@@ -3916,6 +3916,12 @@ lmvd_status lmvd_graph_launch(lmvd_graph g, void* stream) {
   return hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? LMVD_OK : LMVD_EHIP;
 }
 
+lmvd_status lmvd_graph_grouped(lmvd_graph g, int32_t* grouped) {
+  if (!g || !grouped) return LMVD_EINVAL;
+  *grouped = g->grouped;
+  return LMVD_OK;
+}
+
 lmvd_status lmvd_graph_destroy(lmvd_graph g) {
   if (!g) return LMVD_EINVAL;
   if (g->exec) (void)hipGraphExecDestroy(g->exec);

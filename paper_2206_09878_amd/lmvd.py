@@ -55,7 +55,7 @@ class SubstepArgs(ctypes.Structure):
 EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_sizes", "lmvd_substep",
            "lmvd_to_physical", "lmvd_to_spectral", "lmvd_project", "lmvd_evaluate", "lmvd_md", "lmvd_mc",
            "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop", "lmvd_graph_create",
-           "lmvd_graph_launch", "lmvd_graph_destroy"]
+           "lmvd_graph_launch", "lmvd_graph_destroy", "lmvd_graph_grouped"]
 
 
 def library():
@@ -87,6 +87,7 @@ def library():
                                           i32, ctypes.POINTER(vp)]
         lib.lmvd_graph_launch.argtypes = [vp, vp]
         lib.lmvd_graph_destroy.argtypes = [vp]
+        lib.lmvd_graph_grouped.argtypes = [vp, ctypes.POINTER(i32)]
         for name in EXPORTS:
             if name != "lmvd_status_string":
                 getattr(lib, name).restype = ctypes.c_int
@@ -330,21 +331,32 @@ class GraphBatch:
     every launch.  The Steppers must not be advanced otherwise while the graph
     is in use."""
 
-    def __init__(self, steppers, nsub: int = 4, kf: int = -1):
+    def __init__(self, steppers, nsub: int = 4, kf=-1):
+        """kf: one k_f for all instances, or one per instance (-1 = the plan's)."""
         if nsub % 4 != 0 or not steppers:
             raise LmvdError("GraphBatch: nsub must be a positive multiple of 4")
         self.steppers = list(steppers)
         n = len(self.steppers)
+        kfs = list(kf) if isinstance(kf, (list, tuple)) else [kf] * n
+        if len(kfs) != n:
+            raise LmvdError("GraphBatch: one kf per instance")
         args = (SubstepArgs * (n * nsub))()
         for i, st in enumerate(self.steppers):
             for k in range(nsub):
-                args[i * nsub + k] = st.next_args(kf)
+                args[i * nsub + k] = st.next_args(kfs[i])
         plans = (ctypes.c_void_p * n)(*[st.p.handle.value for st in self.steppers])
         ws = (ctypes.c_void_p * n)(*[st.p.ws.data_ptr() for st in self.steppers])
         h = ctypes.c_void_p()
         _check(library().lmvd_graph_create(plans, args, ws, n, nsub, ctypes.byref(h)), "lmvd_graph_create")
         self.handle = h
         self.nsub = nsub
+
+    @property
+    def grouped(self) -> bool:
+        """True when every kernel step is one launch over the instances."""
+        v = ctypes.c_int32()
+        _check(library().lmvd_graph_grouped(self.handle, ctypes.byref(v)), "lmvd_graph_grouped")
+        return bool(v.value)
 
     def launch(self):
         torch = self.steppers[0].p.torch

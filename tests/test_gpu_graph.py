@@ -6,6 +6,8 @@ through the C ABI.
     launches with eager work and synchronisations between them.
   * Uneven instances (N1 != N3, n2 = 49 and 97) match the oracle within 1e-11
     on one substep, so the graph's results inherit the parity of the plain path.
+  * Instances whose substeps do not line up (different k_f) take the
+    one-branch-per-instance form of the graph, with the same bit-for-bit result.
   * The entry point rejects diagnostic outputs and a period that breaks the
     history ring.
 """
@@ -45,6 +47,7 @@ def test_graph_replays_equal_eager_substeps(torch):
     print("graph instances:", [(w.n1, w.n2, w.n3) for w in ws], flush=True)
     A, B = steppers(ws), steppers(ws)
     g = GraphBatch(A, nsub=4)
+    assert g.grouped
     for launch in range(3):
         for s in B:
             for _ in range(4):
@@ -73,6 +76,27 @@ def test_graph_eight_substeps_per_launch(torch):
     for a, b in zip(A, B):
         for ta, tb in zip(state_tensors(a), state_tensors(b)):
             assert torch.equal(ta, tb)
+
+
+def test_graph_mixed_iteration_counts_fall_back_to_branches(torch):
+    """Instances whose substeps differ step by step (k_f = 4, 2, 4) cannot share
+    grouped launches; the graph then runs one branch per instance.  Still equal
+    to the plain path, bit for bit, over two launches."""
+    from paper_2206_09878_amd.lmvd import GraphBatch
+    ws = batch_workloads(count=3, seed=3000)
+    kfs = [4, 2, 4]
+    A, B = steppers(ws), steppers(ws)
+    g = GraphBatch(A, nsub=4, kf=kfs)
+    assert not g.grouped
+    for launch in range(2):
+        for s, kf in zip(B, kfs):
+            for _ in range(4):
+                s.substep(kf=kf)
+        g.launch()
+        torch.cuda.synchronize()
+        for a, b in zip(A, B):
+            for ta, tb in zip(state_tensors(a), state_tensors(b)):
+                assert torch.equal(ta, tb), launch
 
 
 @pytest.mark.parametrize("pick", ["n2_49", "n2_97"])
