@@ -49,6 +49,7 @@ def kernel_symbol(cls: str, w) -> str:
         "xpass_vel": f"k_xpair_w2<3, {m1}>", "mc": "k_mc<7, 7, 6, true>", "md": "k_prologue<7, 7, 8>", "proj": "k_proj<0>, k_proj3",
         "proj_zt": "k_proj<1>, k_proj<2>", "values": "k_values",
         "flux": "k_flux<0, 8, 6>, k_flux<1, 8, 6>", "rhs": "k_rhs_fluct, k_rhs_mean",
+        "zfilt": (f"k_zfilt_w<{m3}>" if m3 == 768 else f"k_zfilt_r<{m3}>") + ", k_wall",
     }.get(cls, cls)
 
 

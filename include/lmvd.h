@@ -218,13 +218,15 @@ lmvd_status lmvd_mc(lmvd_plan plan, const void* rhot, void* m1, void* m2, void* 
 /* Timing hook for measurements: while active, every launch of one kernel
  * class is bracketed by two HIP events recorded on the stream it is launched
  * on.  Classes (one kernel each):
- *   0 inverse z-FFT of values at tau          7 m^d solve
+ *   0 inverse z-FFT of values at tau          7 m^d solve, z values and guess
  *   1 x-pass of R_z (+ physical aux fields)   8 projection, plain store
  *   2 x-pass of L z_t                         9 projection + R_z add (+ z update)
  *   3 x-pass of rho_t                        10 values at tau of fixed fields
  *   4 x-pass of u, rho, C_ij                 11 T_ij projection + RHS emission
  *   5 forward z-FFT + truncation             12 RHS projection + RK2 + plane means
  *   6 fused m^c column kernel                13 x-pass of the transform calls
+ *                                            14 z filter + wall planes of the
+ *                                               non-final fixed-point iterates
  * lmvd_profile_start creates `max_launches` event pairs on the host
  * (launches beyond that are not timed); lmvd_profile_stop waits for the
  * events and returns the summed elapsed milliseconds, the number of timed

@@ -82,6 +82,8 @@ struct DevPlan {
   cptr<int> fac_off;      // [n2+1] first slot of row i
   FftDev fz, fx;
   const double2* xtw;      // [hx] exp(-2 pi i k / m1)
+  cptr<double> wall_w;    // weights of the wall rows of E0 P_N (interior values -> wall values)
+  int wall_k0, wall_k1;   // interior planes entering the lower / upper wall value
 };
 
 struct EvalIn {
@@ -793,6 +795,119 @@ template <int N>
 __global__ void __launch_bounds__(kZWThreads) k_zfwd_w(DevPlan P, const double2* __restrict__ obuf, OutPtrs V, int j0, int pb) {
   zfwd_w_body<N>(P, blockIdx.x, blockIdx.y, blockIdx.z, obuf, V, j0, pb);
 }
+
+// z filter of a non-final fixed-point iterate (eqs. y_k, disc_f).  A z line
+// of x-spectral, z-physical values is transformed forward, the z modes
+// outside the retained band are dropped, and it is transformed back: on
+// interior planes these are the values at tau of the truncated, Neumann-
+// projected iterate, because that projection interpolates the interior rows;
+// k_wall then sets the two wall planes.  out = filter(in) + add (add already
+// filtered, or null).  grid (ceil(nl/LG), planes); neither transform scales.
+template <int N>
+__device__ __forceinline__ void zfilt_w_body(const DevPlan& P, const unsigned bx, const unsigned by,
+                                             const double2* __restrict__ in, const double2* __restrict__ add,
+                                             double2* __restrict__ out) {
+  using ZP = ZPlanW<N>;
+  constexpr int T = ZP::T, E = ZP::E, LG = ZP::LG, RL = ZP::RL, EL = E / RL;
+  extern __shared__ double lds_d[];
+  double2* twl = reinterpret_cast<double2*>(lds_d + LG * ZP::STRIDE);
+  const int tid = threadIdx.x;
+  const int ll = tid % LG, tl = tid / LG;
+  const int jj = by, l = bx * LG + ll;
+  const int nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = N - nn;
+  rf::fill_stage_tw<N, ZP::R0, ZP::R1, ZP::R2, ZP::R3>(twl, P.fz.tw, tid, kZWThreads);
+  const bool lok = l < nl;
+  const size_t base = size_t(jj) * N * nl + (lok ? l : 0);
+  double2 v[E], w[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = lok ? in[base + size_t(tl + T * r) * nl] : zero2();
+  __syncthreads();  // twiddle tables
+  rf::run_split<N, T, -1, ZP::R0, ZP::R1, ZP::R2, ZP::R3, ZP::PAD, true>(v, lds_d, ll * ZP::STRIDE, tl, twl);
+  // register c RL + r holds mode tl + T (c + EL r); natural order for the inverse, band only
+#pragma unroll
+  for (int c = 0; c < EL; ++c)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int pos = tl + T * (c + EL * r);
+      w[c + EL * r] = (pos >= h3 && pos < h3 + pad) ? zero2() : v[c * RL + r];
+    }
+  rf::run_split<N, T, 1, ZP::R0, ZP::R1, ZP::R2, ZP::R3, ZP::PAD, true>(w, lds_d, ll * ZP::STRIDE, tl, twl);
+  if (lok) {
+#pragma unroll
+    for (int c = 0; c < EL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const size_t e = base + size_t(tl + T * c + r * (N / RL)) * nl;
+        const double2 x = w[c * RL + r];
+        out[e] = add ? cadd(x, add[e]) : x;
+      }
+  }
+}
+template <int N>
+__global__ void __launch_bounds__(kZWThreads) k_zfilt_w(DevPlan P, const double2* __restrict__ in,
+                                                       const double2* __restrict__ add, double2* __restrict__ out) {
+  zfilt_w_body<N>(P, blockIdx.x, blockIdx.y, in, add, out);
+}
+template <int N>
+__device__ __forceinline__ void zfilt_r_body(const DevPlan& P, const unsigned bx, const unsigned by,
+                                             const double2* __restrict__ in, const double2* __restrict__ add,
+                                             double2* __restrict__ out) {
+  using LP = LinePlan<N>;
+  using ZS = ZShape<N>;
+  constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL, EL = E / RL;
+  extern __shared__ double lds_d[];
+  const int tid = threadIdx.x;
+  const int ll = tid % LG, tl = tid / LG;
+  const int jj = by, l = bx * LG + ll;
+  const int nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = N - nn;
+  const bool lok = l < nl;
+  const size_t base = size_t(jj) * N * nl + (lok ? l : 0);
+  double2 v[E], w[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = lok ? in[base + size_t(tl + T * r) * nl] : zero2();
+  rf::run<N, T, -1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, ll * ZS::STRIDE, tl, P.fz.tw);
+#pragma unroll
+  for (int c = 0; c < EL; ++c)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int pos = tl + T * (c + EL * r);
+      w[c + EL * r] = (pos >= h3 && pos < h3 + pad) ? zero2() : v[c * RL + r];
+    }
+  __syncthreads();  // the forward transform's last LDS reads
+  rf::run<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(w, lds_d, ll * ZS::STRIDE, tl, P.fz.tw);
+  if (lok) {
+#pragma unroll
+    for (int c = 0; c < EL; ++c)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const size_t e = base + size_t(tl + T * c + r * (N / RL)) * nl;
+        const double2 x = w[c * RL + r];
+        out[e] = add ? cadd(x, add[e]) : x;
+      }
+  }
+}
+template <int N>
+__global__ void __launch_bounds__(kThreads) k_zfilt_r(DevPlan P, const double2* __restrict__ in,
+                                                     const double2* __restrict__ add, double2* __restrict__ out) {
+  zfilt_r_body<N>(P, blockIdx.x, blockIdx.y, in, add, out);
+}
+
+// Wall planes of the filtered iterate: the Neumann projection's values at the
+// wall rows are fixed sums of the interior values (weights wall_w, summed
+// planes nearest each wall first).  zt: [n2][m3][nl] (all planes).
+__device__ __forceinline__ void wall_body(const DevPlan& P, const unsigned bx, double2* zt) {
+  const size_t ps = size_t(P.m3) * P.nl;
+  const size_t e = size_t(bx) * blockDim.x + threadIdx.x;
+  if (e >= ps) return;
+  const int n2 = P.n2, k0 = P.wall_k0, k1 = P.wall_k1;
+  const auto w0 = P.wall_w, w1 = P.wall_w + (k0 + 1);
+  double2 a0 = zero2(), a1 = zero2();
+  for (int d = 1; d <= k0; ++d) a0 = fma2(w0[d], zt[size_t(d) * ps + e], a0);
+  for (int d = 1; d <= k1; ++d) a1 = fma2(w1[d], zt[size_t(n2 - 1 - d) * ps + e], a1);
+  zt[e] = a0;
+  zt[size_t(n2 - 1) * ps + e] = a1;
+}
+__global__ void __launch_bounds__(kThreads) k_wall(DevPlan P, double2* zt) { wall_body(P, blockIdx.x, zt); }
 
 // Pointwise products of the x-pass.  Two real fields x, y travel through one
 // complex FFT as x + i y, so a product of the pair needs no carried state.
@@ -2749,6 +2864,41 @@ struct JobXpair {
   }
 };
 
+template <int N>
+struct JobZfiltW {
+  static constexpr int kBound = kZWThreads, kBlock = kZWThreads, kMinBlocks = 0;
+  struct Args {
+    const double2 *in, *add;
+    double2* out;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned, const Args& a) {
+    zfilt_w_body<N>(P, bx, by, a.in, a.add, a.out);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
+    hipLaunchKernelGGL(k_zfilt_w<N>, g, dim3(kBlock), lds, s, P, a.in, a.add, a.out);
+  }
+};
+template <int N>
+struct JobZfiltR {
+  static constexpr int kBound = kThreads, kBlock = ZShape<N>::LG * ZShape<N>::T, kMinBlocks = 0;
+  using Args = typename JobZfiltW<N>::Args;
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned, const Args& a) {
+    zfilt_r_body<N>(P, bx, by, a.in, a.add, a.out);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
+    hipLaunchKernelGGL(k_zfilt_r<N>, g, dim3(kBlock), lds, s, P, a.in, a.add, a.out);
+  }
+};
+struct JobWall : ColumnJob {
+  struct Args {
+    double2* zt;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, unsigned, const Args& a) { wall_body(P, bx, a.zt); }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
+    hipLaunchKernelGGL(k_wall, g, dim3(kThreads), lds, s, P, a.zt);
+  }
+};
+
 // BDF-like guess dt z_t^0 = a1 z + a2 h1 + a3 h2 + a4 h3 (eq. dzdt_guesses)
 __global__ void k_guess(const double2* __restrict__ z, const double2* __restrict__ h1, const double2* __restrict__ h2,
                         const double2* __restrict__ h3, double a1, double a2, double a3, double a4, double dt,
@@ -2803,6 +2953,7 @@ struct Workspace {
   size_t off_yp, off_yt;  // scratch of the m^c column kernel
   // values at the Greville points
   size_t off_vz0, off_vz1, off_vzl, off_vz3, off_vmd1, off_vmd3, off_vc2d, off_vm1c, off_vm2c, off_vm3c, off_vzt;
+  size_t off_szt = 0;  // filtered R_z values, x-spectral and z-physical (elided fixed-point path)
 };
 
 }  // namespace lmvd
@@ -2876,6 +3027,7 @@ static void layout_workspace(lmvd_plan_s* p) {
   w.off_vm2c = take(sB);
   w.off_vm3c = take(sB);
   w.off_vzt = take(sB);
+  if (p->pb == H.n2) w.off_szt = take(plane * H.n2);
   w.bytes = o;
 }
 
@@ -3020,6 +3172,9 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   UP_TABLE(H.fac_nm, D.fac_nm);
   UP_TABLE(H.fac_ns, D.fac_ns);
   UP_TABLE(H.fac_off, D.fac_off);
+  UP_TABLE(H.wall_w, D.wall_w);
+  D.wall_k0 = H.wall_k0;
+  D.wall_k1 = H.wall_k1;
   {
     p->fac_la = p->fac_ua = (H.a_lower <= 7 && H.a_upper <= 7) ? 7 : 8;
     const size_t npairs = size_t(H.nl) * ((H.nn + 1) / 2);
@@ -3169,7 +3324,8 @@ enum KClass {
   KC_FLUX = 11,      // T_ij projection and RHS emission (both groups)
   KC_RHS = 12,       // RHS projection, RK2 update, plane means
   KC_XPASS_IO = 13,  // x-pass of the transform entry points
-  KC_COUNT = 14
+  KC_ZFILT = 14,     // z filter and wall planes of the non-final fixed-point iterates
+  KC_COUNT = 15
 };
 
 // Bracket one launch of class `cls` with events when that class is timed.
@@ -3285,9 +3441,12 @@ static bool xreg_size(int m1, int nl) {
     default: break;             \
   }
 
+// zinv = false: the inputs are already in zbuf (x-spectral, z-physical);
+// zfwd = false: the outputs stay in obuf.
 template <int PH>
 static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, const std::vector<double2*>& outs,
-                               double* phys_out = nullptr, const double* phys_in = nullptr) {
+                               double* phys_out = nullptr, const double* phys_in = nullptr, bool zinv = true,
+                               bool zfwd = true) {
   lmvd_plan_s* p = c.p;
   const HostTables& H = p->H;
   const int M3 = H.cfg.m3, nl = H.nl;
@@ -3311,7 +3470,7 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
     for (const EvalIn& e : ins)
       if (e.kind != EV_IDENT || (e.ma != MU_ONE && e.ma != MU_IK1) || (e.b && e.mb != MU_ONE)) inputs_plain = false;
     const bool zr = p->use_reg && zreg_size(M3) && inputs_plain, xr = p->use_reg && xreg_size(H.cfg.m1, nl);
-    if (!ins.empty()) {
+    if (!ins.empty() && zinv) {
       double terms = 0;
       for (const EvalIn& e : ins) terms += e.b ? 2 : 1;
         ProfScope ps(p, KC_ZINV, c.s, nb * (terms * splane + nin * zplane));
@@ -3344,7 +3503,7 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
         });
       }
     }
-    if (!outs.empty()) {
+    if (!outs.empty() && zfwd) {
       ProfScope ps(p, KC_ZFWD, c.s, nb * nout * (zplane + splane));
       if (p->use_reg && zreg_size(M3)) {
 #define CALLF(N) launch_zfwd_t<N>(c, obuf, V, j0, nb, int(outs.size()))
@@ -3401,6 +3560,36 @@ static void ensure_factors(lmvd_plan_s* p, hipStream_t s) {
   else
     hipLaunchKernelGGL((k_factor_ul<8, 8>), g, dim3(kThreads), 0, s, p->D, p->fac);
   p->fac_ready = true;
+}
+
+// out = filter(in) + add on all planes, then the wall planes of out (see k_zfilt_w, k_wall)
+static void zfilter(const Ctx& c, const double2* in, const double2* add, double2* out) {
+  lmvd_plan_s* p = c.p;
+  const HostTables& H = p->H;
+  const int M3 = H.cfg.m3, n2 = H.n2;
+  const double zf = double(M3) * H.nl * 16.0;
+  ProfScope ps(p, KC_ZFILT, c.s, n2 * zf * (add ? 3.0 : 2.0) + zf * (H.wall_k0 + H.wall_k1 + 2));
+  if (M3 == 768) {
+    using ZP = ZPlanW<768>;
+    const size_t lds = size_t(ZP::LG) * ZP::STRIDE * sizeof(double) +
+                       size_t(rf::StageTw<ZP::R0, ZP::R1, ZP::R2, ZP::R3>::SIZE) * sizeof(double2);
+    col<JobZfiltW<768>>(c, dim3((H.nl + ZP::LG - 1) / ZP::LG, n2), lds, {in, add, out});
+  } else {
+#define LMVD_ZF(N)                                                                                      \
+  col<JobZfiltR<N>>(c, dim3((H.nl + ZShape<N>::LG - 1) / ZShape<N>::LG, n2),                           \
+                    size_t(ZShape<N>::LG) * ZShape<N>::STRIDE * sizeof(double), {in, add, out})
+    switch (M3) {
+      case 192: LMVD_ZF(192); break;
+      case 144: LMVD_ZF(144); break;
+      case 96: LMVD_ZF(96); break;
+      case 72: LMVD_ZF(72); break;
+      case 48: LMVD_ZF(48); break;
+      default: break;
+    }
+#undef LMVD_ZF
+  }
+  const size_t ps_ = size_t(M3) * H.nl;
+  col<JobWall>(c, dim3(unsigned((ps_ + kThreads - 1) / kThreads)), 0, {out});
 }
 
 static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void* workspace, hipStream_t s,
@@ -3531,6 +3720,14 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
                           {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
+  // The iterates before the last one are used only through their values at tau.  With all planes in
+  // one batch and register z transforms, the L x-pass output is z-filtered (plus the filtered R_z
+  // values, computed once here) in place of the forward transform, projection and inverse transform.
+  const bool elide = p->pb == H.n2 && p->use_reg && zreg_size(H.cfg.m3) && kf >= 2 && W.off_szt != 0;
+  double2* szt = c.at<double2>(W.off_szt);
+  double2* zbuf0 = c.at<double2>(p->ws.off_zbuf);
+  double2* obuf0 = c.at<double2>(p->ws.off_obuf);
+  if (elide) zfilter(c, obuf0, nullptr, szt);
   if (kf == 0) {
     const double2* ztp = static_cast<const double2*>(a->zt_prev);
     double2* zo = static_cast<double2*>(a->z_out);
@@ -3544,13 +3741,21 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   }
   double2* cur = (kf == 0 && user_zt) ? user_zt : zta;
   // 3. fixed-point iterations z_t^k = L(z) z_t^{k-1} + R_z
+  bool zt_filtered = false;  // the iterate's values are in zbuf already (z-filtered)
   for (int it = 0; it < kf; ++it) {
     const bool last = (it == kf - 1);
-    st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
+    st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]}, nullptr, nullptr, !zt_filtered);
     if (st != LMVD_OK) return st;
     mc_step(false);
-    st = plane_phase<PH_L>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)}, {vals[0]});
+    const bool filt = elide && !last;
+    st = plane_phase<PH_L>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)}, {vals[0]}, nullptr,
+                           nullptr, true, !filt);
     if (st != LMVD_OK) return st;
+    zt_filtered = filt;
+    if (filt) {
+      zfilter(c, obuf0, szt, zbuf0);
+      continue;
+    }
     double2* next = (last && user_zt) ? user_zt : (cur == zta ? ztb : zta);
     const int n = int(ncol);
     const dim3 g((n + kThreads - 1) / kThreads);

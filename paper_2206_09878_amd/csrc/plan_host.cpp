@@ -410,6 +410,43 @@ lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& H, std::string
       }
     }
   }
+  // wall rows of E_0 P_N: x solves P^T x = e with e = (row 0 or n2-1 of E_0)^T,
+  // P = L U the Neumann matrix (U^T z = e, then L^T x = z)
+  {
+    const BandLU& B = H.proj[2];
+    const int n = H.n2;
+    auto wall = [&](int row, std::vector<double>& x) {
+      std::vector<double> z(n, 0.0);
+      x.assign(n, 0.0);
+      for (int i = 0; i < n; ++i) {
+        double s = H.E[0].at(row, i);
+        for (int q = 1; q <= B.upper && i - q >= 0; ++q) s -= B.u[size_t(i - q) * (kMaxBand + 1) + q] * z[i - q];
+        z[i] = s * B.uinv[i];
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        double s = z[i];
+        for (int m = 1; m <= B.lower && i + m < n; ++m) s -= B.lmul[size_t(i + m) * kMaxBand + (m - 1)] * x[i + m];
+        x[i] = s;
+      }
+    };
+    auto cut = [&](const std::vector<double>& x, bool from_top) {
+      // interior rows by distance d = 1 .. n-2 from the wall; tails summed from the far end
+      std::vector<double> tail(size_t(n), 0.0);  // tail[d] = sum over distances > d
+      for (int d = n - 3; d >= 0; --d) tail[d] = tail[d + 1] + std::fabs(x[from_top ? n - 2 - d : d + 1]);
+      const double tot = tail[0];
+      int k = 0;
+      while (k < n - 2 && tail[k] > std::ldexp(tot, -60)) ++k;
+      return k;
+    };
+    std::vector<double> x0, x1;
+    wall(0, x0);
+    wall(n - 1, x1);
+    H.wall_k0 = cut(x0, false);
+    H.wall_k1 = cut(x1, true);
+    H.wall_w.assign(size_t(H.wall_k0) + H.wall_k1 + 2, 0.0);
+    for (int d = 1; d <= H.wall_k0; ++d) H.wall_w[d] = x0[d];
+    for (int d = 1; d <= H.wall_k1; ++d) H.wall_w[size_t(H.wall_k0) + 1 + d] = x1[n - 1 - d];
+  }
   H.xtw.resize(size_t(2) * H.hx);
   const long double pi = 3.141592653589793238462643383279502884L;
   for (int k = 0; k < H.hx; ++k) {

@@ -78,6 +78,13 @@ struct HostTables {
   // sampled k), and the offset of the row's nm + ns + 1 factor slots
   std::vector<int32_t> fac_nm, fac_ns, fac_off;
   int fac_slots = 0;
+  // Values at the wall rows of the Neumann projection of interior values:
+  // (E_0 P_N v)_0 = sum_{i=1}^{wall_k0} wall_w[i] v_i and
+  // (E_0 P_N v)_{n2-1} = sum_{i=1}^{wall_k1} wall_w[wall_k0 + 1 + i] v_{n2-1-i}
+  // (rows i = 0 and n2-1 of v do not enter P_N); the sums stop where the
+  // remaining weights add up to at most 2^-60 of all of them.
+  std::vector<double> wall_w;
+  int wall_k0 = 0, wall_k1 = 0;
 };
 
 // Build all host tables.  Returns LMVD_OK or an error with `msg` set.

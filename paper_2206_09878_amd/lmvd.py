@@ -222,7 +222,7 @@ class Plan:
 
     # -- timing hook -----------------------------------------------------------------
     KERNEL_CLASSES = ("zinv", "xpass_rz", "xpass_l", "xpass_rhot", "xpass_vel", "zfwd", "mc", "md", "proj",
-                      "proj_zt", "values", "flux", "rhs", "xpass_io")
+                      "proj_zt", "values", "flux", "rhs", "xpass_io", "zfilt")
 
     def profile_start(self, cls: int, max_launches: int = 65536):
         _check(library().lmvd_profile_start(self.handle, cls, max_launches), "lmvd_profile_start")
