@@ -230,3 +230,48 @@ def test_trajectory_three_substeps_small(torch):
     got = dict(phi2=host(s.phi2), omega2=host(s.omega2), z=host(s.z), m1bar=host(s.m1bar), m3bar=host(s.m3bar))
     errs = {k: rel(got[k], ref[k]) for k in got}
     assert all(v < TOL for v in errs.values()), errs
+
+
+def plane_batch_substep(w, plane_batch, seed, stage):
+    """One substep on the GPU only (no diagnostics), returning the host outputs."""
+    import torch
+    p = gplan(w, plane_batch=plane_batch)
+    inp = make_inputs(w, seed=seed, stage=stage)
+    d = {k: p.to_dev(inp[k]) for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
+    hist = [p.to_dev(h) for h in inp["hist"]]
+    z_out, zt = p.empty(), p.empty()
+    rhs = {"phi2": p.empty(), "omega2": p.empty(),
+           "m1bar": torch.empty(w.n2, dtype=torch.float64, device="cuda"),
+           "m3bar": torch.empty(w.n2, dtype=torch.float64, device="cuda")}
+    kw = dict(z_out=z_out, hist=hist, rhs_out=rhs, zt_out=zt)
+    if stage == 1:
+        kw["rhs_prev"] = {k: p.to_dev(v) for k, v in inp["rhs_prev"].items()}
+        kw["zt_prev"] = p.to_dev(inp["zt_prev"])
+    p.substep(stage, d["phi2"], d["omega2"], d["z"], d["m1bar"], d["m3bar"], **kw)
+    torch.cuda.synchronize()
+    out = {k: host(v) for k, v in d.items()}
+    out.update(z_out=host(z_out), zt=host(zt), **{"rhs_" + k: host(v) for k, v in rhs.items()})
+    return out
+
+
+@pytest.mark.parametrize("name,n,n2,stage", [("rt512", 512, 33, 0), ("mixing128", 64, 65, 1)])
+def test_filtered_iterates_match_spectral_path(torch, name, n, n2, stage):
+    """All planes in one batch: the fixed-point iterates before the last are
+    z-filtered on the 3/2 grid with the wall planes from the Neumann
+    projection's wall-row weights.  A plane batch below n2 takes the spectral
+    path (forward transform, projection, values, inverse transform).  The two
+    agree to rounding on every output (768-point filter kernel at rt512 sizes;
+    the register kernels of the smaller sizes are also covered by the oracle
+    parity tests above)."""
+    w = workload(name, n=n, n2=n2)
+    a = plane_batch_substep(w, 0, seed=9, stage=stage)
+    b = plane_batch_substep(w, n2 - 1, seed=9, stage=stage)
+    errs = {k: rel(a[k], b[k]) for k in a}
+    print("filtered vs spectral:", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    # The iterate and the state agree to rounding.  RHS_phi2 (and phi2 = phi2 + dt/2 RHS_phi2) of the
+    # Rayleigh-Taylor state, where m^d = 0, is a small remainder of much larger terms: the oracle itself,
+    # run with numpy's and then scipy's FFT at 512x33x512 (seed 9, stage n), disagrees by 1.7e-9 there
+    # and by 4.0e-12 in RHS_Omega2; the bounds below are about 6x and 2.5x those spreads.
+    tol = {"phi2": 1e-8, "rhs_phi2": 1e-8, "omega2": 1e-11, "rhs_omega2": 1e-11}
+    bad = {k: v for k, v in errs.items() if not v < tol.get(k, 1e-12)}
+    assert not bad, errs
