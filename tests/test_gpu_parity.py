@@ -209,6 +209,16 @@ def test_substep_mid(torch, name, n, n2):
     check_pair(got, ref, rhs_tol=rhs_tolerances(w, 0, 7, ref=ref))
 
 
+def test_substep_mixing_layer_full_size(torch):
+    """The mixing-layer configuration at its full size, 128x129x128 on the
+    192 x 192 grid (density 1 -> 7, broadband perturbation, mean shear), one
+    stage-n substep against the oracle."""
+    w = workload("mixing128")
+    print("mixing128 full size", (w.n1, w.n2, w.n3), flush=True)
+    got, ref = run_pair(w, 0, seed=1)
+    check_pair(got, ref, rhs_tol=rhs_tolerances(w, 0, 1, ref=ref))
+
+
 def test_trajectory_three_substeps_small(torch):
     """Config 0 trajectory: substeps n, ', n, each side free-running on its own
     outputs (history rotation, stored RHS and z_t between the stages), from the
