@@ -918,10 +918,12 @@ template <int PH>
 struct Pair;
 
 template <>
-struct Pair<PH_RZ> {  // inputs lap z, z, z1, m1, z2, m2, z3, m3:  R_z = (1/rho)(-m^d . grad z + rho D lap z)
+struct Pair<PH_RZ> {  // inputs lap z, z, m1, z2, m2, z3, m3:  R_z = (1/rho)(-m^d . grad z + rho D lap z)
   static constexpr int NP = 4, NQ = 1, NST = 2;
-  __device__ static constexpr int fa(int i) { return 2 * i; }
-  __device__ static constexpr int fb(int i) { return 2 * i + 1; }
+  __device__ static constexpr int fa(int i) { return i == 0 ? 0 : 2 * i - 1; }
+  __device__ static constexpr int fb(int i) { return i == 0 ? 1 : 2 * i; }
+  // pair 1 is (d z / d x, m1): the x-derivative of z (input 1) is formed here, mode by mode
+  __device__ static constexpr bool dxa(int i) { return i == 1; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
@@ -947,6 +949,7 @@ struct Pair<PH_L> {  // inputs m1c, m2c, m3c:  L z_t = -(1/rho) grad z . m^c = g
   static constexpr int NP = 2, NQ = 1, NST = 1;
   __device__ static constexpr int fa(int i) { return 2 * i; }
   __device__ static constexpr int fb(int i) { return i == 0 ? 1 : -1; }
+  __device__ static constexpr bool dxa(int) { return false; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
@@ -962,6 +965,7 @@ struct Pair<PH_RHOT> {  // input z_t:  rho_t = f'(z) z_t
   static constexpr int NP = 1, NQ = 1, NST = 1;
   __device__ static constexpr int fa(int) { return 0; }
   __device__ static constexpr int fb(int) { return -1; }
+  __device__ static constexpr bool dxa(int) { return false; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
@@ -976,6 +980,7 @@ struct Pair<PH_VEL> {  // inputs z, m1, m2, m3 -> u1, u2, u3, rho, C11, C12, C13
   static constexpr int NP = 2, NQ = 5, NST = 4;
   __device__ static constexpr int fa(int i) { return 2 * i; }
   __device__ static constexpr int fb(int i) { return 2 * i + 1; }
+  __device__ static constexpr bool dxa(int) { return false; }
   // output pairs ordered so that m1, then m2, then m3 is last used early
   // (the transforms are unrolled): (C11, C12), (C13, u1), (C22, C23), (u2, rho), (C33, u3)
   __device__ static constexpr int ga(int q) { return q == 0 ? 4 : q == 1 ? 6 : q == 2 ? 7 : q == 3 ? 1 : 9; }
@@ -1005,6 +1010,7 @@ struct Pair<PH_TOPHYS> {  // one input, written out on the physical grid
   static constexpr int NP = 1, NQ = 0, NST = 1;
   __device__ static constexpr int fa(int) { return 0; }
   __device__ static constexpr int fb(int) { return -1; }
+  __device__ static constexpr bool dxa(int) { return false; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
@@ -1017,6 +1023,7 @@ struct Pair<PH_FROMPHYS> {  // one output, read from the physical grid
   static constexpr int NP = 0, NQ = 1, NST = 1;
   __device__ static constexpr int fa(int) { return 0; }
   __device__ static constexpr int fb(int) { return -1; }
+  __device__ static constexpr bool dxa(int) { return false; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
@@ -1087,24 +1094,34 @@ __device__ __forceinline__ int lane_in_line(int t) {
 // zero in between.  oka / okb false: that line is absent (its pointer must
 // still be readable).  N/3 and 2N/3 are multiples of T, so the class of each
 // point is known at compile time; every load is issued before any is used.
-template <int N, int T, bool HASB>
+// DXA: X is replaced by its x-derivative, X_k -> i k1[k] X_k (k1: the x wavenumbers).
+template <int N, int T, bool HASB, bool DXA = false>
 __device__ __forceinline__ void herm_pair_load(double2* v, const double2* __restrict__ XA,
-                                               const double2* __restrict__ XB, int tl, bool oka, bool okb) {
+                                               const double2* __restrict__ XB, int tl, bool oka, bool okb,
+                                               const double* __restrict__ k1 = nullptr) {
   constexpr int E = N / T, NL = N / 3;
   static_assert(NL % T == 0, "retained band must be whole rows of T points");
   double2 a[E], b[E];
+  double ka[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     a[r] = b[r] = zero2();
+    ka[r] = 0.0;
     if (T * r + T <= NL) {
       a[r] = XA[tl + T * r];
       if (HASB) b[r] = XB[tl + T * r];
+      if (DXA) ka[r] = k1[tl + T * r];
     } else if (T * r >= N - NL) {
       const int m = N - T * r - tl;  // in [1, N/3]
       const int mm = m < NL ? m : 0;
       a[r] = XA[mm];
       if (HASB) b[r] = XB[mm];
+      if (DXA) ka[r] = k1[mm];
     }
+  }
+  if (DXA) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) a[r] = make_double2(-ka[r] * a[r].y, ka[r] * a[r].x);
   }
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -1170,7 +1187,8 @@ __device__ __forceinline__ void xpair_body(const DevPlan& P, const unsigned bx, 
     const int fa = S::fa(i), fb = S::fb(i);
     const double2* XA = zbuf + ((size_t(fa) * pb + jj) * M3 + bb) * NL;
     const double2* XB = zbuf + ((size_t(fb < 0 ? fa : fb) * pb + jj) * M3 + bb) * NL;
-    if (fb >= 0) herm_pair_load<N, T, true>(v, XA, XB, tlx, bok, bok);
+    if (fb >= 0 && S::dxa(i)) herm_pair_load<N, T, true, true>(v, XA, XB, tlx, bok, bok, P.k1);
+    else if (fb >= 0) herm_pair_load<N, T, true>(v, XA, XB, tlx, bok, bok);
     else herm_pair_load<N, T, false>(v, XA, XA, tlx, bok, bok);
     rf::run_split<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, basex, tlx, twl);
     if constexpr (PH == PH_TOPHYS) {
@@ -3714,10 +3732,17 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     col<JobPrologue<8, 8, 8>>(c, dim3(cgrid.x, 2), 0, {0, MdArgs{}, zargs, gargs});
   }
   // 2. R_z
-  st = plane_phase<PH_RZ>(c,
-                          {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT),
-                           ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
-                          {vals[0]});
+  // the register x-pass forms d z / d x from the z line; the generic one takes it as an input
+  if (p->use_reg && xreg_size(H.cfg.m1, H.nl))
+    st = plane_phase<PH_RZ>(c,
+                            {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT),
+                             ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
+                            {vals[0]});
+  else
+    st = plane_phase<PH_RZ>(c,
+                            {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT),
+                             ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
+                            {vals[0]});
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
   // The iterates before the last one are used only through their values at tau.  With all planes in
