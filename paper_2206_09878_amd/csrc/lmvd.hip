@@ -92,7 +92,7 @@ struct EvalIn {
   int kind;
   int ma;
   int mb;
-  int pad;
+  int slot;  // zbuf slot the inverse z transform writes (-1 before plane_phase: the input's position)
 };
 struct EvalArgs {
   EvalIn in[kMaxIn];
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kThreads) k_eval_zinv(DevPlan P, EvalArgs A, d
   }
   __syncthreads();
   fft_lines<1, kZMaxE>(lds, M3, LG, P.fz, tid, nth);
-  double2* out = zbuf + (size_t(f) * pb + jj) * size_t(M3) * nl;
+  double2* out = zbuf + (size_t(A.in[f].slot) * pb + jj) * size_t(M3) * nl;
   for (int idx = tid; idx < LG * M3; idx += nth) {
     const int ll = idx % LG, b = idx / LG;
     if (l0 + ll < nl) out[size_t(b) * nl + l0 + ll] = lds[ll * M3 + b];
@@ -635,7 +635,7 @@ __device__ __forceinline__ void zinv_r_body(const DevPlan& P, const unsigned bx,
   }
   rf::run<N, T, 1, LP::R0, LP::R1, LP::R2, LP::R3, LP::PAD>(v, lds_d, ll * ZS::STRIDE, tl, P.fz.tw);
   if (lok) {
-    double2* out = zbuf + (size_t(f) * pb + jj) * size_t(N) * nl + l;
+    double2* out = zbuf + (size_t(in.slot) * pb + jj) * size_t(N) * nl + l;
 #pragma unroll
     for (int c = 0; c < E / RL; ++c)
 #pragma unroll
@@ -749,7 +749,7 @@ __device__ __forceinline__ void zinv_w_body(const DevPlan& P, const unsigned bx,
   __syncthreads();  // twiddle tables
   rf::run_split<N, T, 1, ZP::R0, ZP::R1, ZP::R2, ZP::R3, ZP::PAD, true>(v, lds_d, ll * ZP::STRIDE, tl, twl);
   if (lok) {
-    double2* out = zbuf + (size_t(f) * pb + jj) * size_t(N) * nl + l;
+    double2* out = zbuf + (size_t(in.slot) * pb + jj) * size_t(N) * nl + l;
 #pragma unroll
     for (int c = 0; c < E / RL; ++c)
 #pragma unroll
@@ -917,12 +917,15 @@ __global__ void __launch_bounds__(kThreads) k_wall(DevPlan P, double2* zt) { wal
 template <int PH>
 struct Pair;
 
+// inputs (zbuf slots) lap z, m1, z2, m2, z3, m3, z (z in slot 6, which the later phases of the substep
+// leave alone, so the u, rho, C_ij pass reads it again):  R_z = (1/rho)(-m^d . grad z + rho D lap z)
 template <>
-struct Pair<PH_RZ> {  // inputs lap z, z, m1, z2, m2, z3, m3:  R_z = (1/rho)(-m^d . grad z + rho D lap z)
+struct Pair<PH_RZ> {
   static constexpr int NP = 4, NQ = 1, NST = 2;
-  __device__ static constexpr int fa(int i) { return i == 0 ? 0 : 2 * i - 1; }
-  __device__ static constexpr int fb(int i) { return i == 0 ? 1 : 2 * i; }
-  // pair 1 is (d z / d x, m1): the x-derivative of z (input 1) is formed here, mode by mode
+  // pairs (lap z, z), (d z / d x, m1), (z2, m2), (z3, m3)
+  __device__ static constexpr int fa(int i) { return i == 0 ? 0 : i == 1 ? 6 : 2 * i - 2; }
+  __device__ static constexpr int fb(int i) { return i == 0 ? 6 : 2 * i - 1; }
+  // the x-derivative of z is formed here from z's line, mode by mode
   __device__ static constexpr bool dxa(int i) { return i == 1; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
@@ -975,11 +978,13 @@ struct Pair<PH_RHOT> {  // input z_t:  rho_t = f'(z) z_t
   template <int Q>
   __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) { return make_double2(s[0], 0.0); }
 };
+// inputs (zbuf slots) m1, m2, m3, and z in slot 6 -> u1, u2, u3, rho, C11, C12, C13, C22, C23, C33 (fields 0..9)
 template <>
-struct Pair<PH_VEL> {  // inputs z, m1, m2, m3 -> u1, u2, u3, rho, C11, C12, C13, C22, C23, C33 (fields 0..9)
+struct Pair<PH_VEL> {
   static constexpr int NP = 2, NQ = 5, NST = 4;
-  __device__ static constexpr int fa(int i) { return 2 * i; }
-  __device__ static constexpr int fb(int i) { return 2 * i + 1; }
+  // pairs (z, m1), (m2, m3)
+  __device__ static constexpr int fa(int i) { return i == 0 ? 6 : 1; }
+  __device__ static constexpr int fb(int i) { return i == 0 ? 0 : 2; }
   __device__ static constexpr bool dxa(int) { return false; }
   // output pairs ordered so that m1, then m2, then m3 is last used early
   // (the transforms are unrolled): (C11, C12), (C13, u1), (C22, C23), (u2, rho), (C33, u3)
@@ -3374,7 +3379,7 @@ static EvalIn ev(const void* a, int kind, int ma = MU_ONE, const void* b = nullp
   e.kind = kind;
   e.ma = ma;
   e.mb = mb;
-  e.pad = 0;
+  e.slot = -1;
   return e;
 }
 
@@ -3469,7 +3474,10 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
   const HostTables& H = p->H;
   const int M3 = H.cfg.m3, nl = H.nl;
   EvalArgs A{};
-  for (size_t i = 0; i < ins.size(); ++i) A.in[i] = ins[i];
+  for (size_t i = 0; i < ins.size(); ++i) {
+    A.in[i] = ins[i];
+    if (A.in[i].slot < 0) A.in[i].slot = int(i);
+  }
   OutPtrs V{};
   for (size_t g = 0; g < outs.size(); ++g) V.v[g] = outs[g];
   double2* zbuf = c.at<double2>(p->ws.off_zbuf);
@@ -3732,11 +3740,13 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     col<JobPrologue<8, 8, 8>>(c, dim3(cgrid.x, 2), 0, {0, MdArgs{}, zargs, gargs});
   }
   // 2. R_z
-  // the register x-pass forms d z / d x from the z line; the generic one takes it as an input
-  if (p->use_reg && xreg_size(H.cfg.m1, H.nl))
+  // the register x-pass forms d z / d x from the z line and takes z from zbuf slot 6, where it stays for
+  // the u, rho, C_ij pass when all planes are one batch; the generic x-pass takes them as inputs
+  const bool xr = p->use_reg && xreg_size(H.cfg.m1, H.nl);
+  if (xr)
     st = plane_phase<PH_RZ>(c,
-                            {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT),
-                             ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
+                            {ev(vzl, EV_IDENT), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT),
+                             ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT), ev(vz0, EV_IDENT)},
                             {vals[0]});
   else
     st = plane_phase<PH_RZ>(c,
@@ -3801,8 +3811,17 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   // u = m/rho, rho and C_ij = -m_i m_j/rho on the physical grid; u_hat by interpolation;
   // T_ij = C_ij + tau_ij(u_hat) projected
   double2* cv[6] = {vals[4], vals[5], vals[6], vals[7], vals[8], vals[9]};
-  st = plane_phase<PH_VEL>(c, {ev(vz0, EV_IDENT), ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
-                           {vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]});
+  const std::vector<double2*> vel_out{vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]};
+  if (xr && p->pb == H.n2) {  // z still in zbuf slot 6
+    st = plane_phase<PH_VEL>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)}, vel_out);
+  } else if (xr) {
+    EvalIn zin = ev(vz0, EV_IDENT);
+    zin.slot = 6;
+    st = plane_phase<PH_VEL>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT), zin}, vel_out);
+  } else {
+    st = plane_phase<PH_VEL>(c, {ev(vz0, EV_IDENT), ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
+                             vel_out);
+  }
   if (st != LMVD_OK) return st;
   {
     const int n = int(ncol);
