@@ -1,0 +1,59 @@
+"""Single-mode Rayleigh-Taylor validation (Section 5): the GPU integrator's
+bubble velocity in the near-constant, potential-growth phase against the
+closed form of Goncharov, v_b = sqrt(2 At/(1 + At) g/(C k)), C = 1 in 3D.
+
+The paper reports rough agreement: the closed form is an inviscid,
+immiscible potential-flow model, while the computed flow is viscous
+(Re = 1024) and diffusive (Sc = 1).  The GPU test runs the paper's 3D case
+at At = 0.5 on a coarse grid (32 x 129 x 32, dt = 2e-3; the plateau velocity
+agrees with 32 x 257 x 32 at dt = 1e-3 to 0.1 %) and asks for agreement
+within 15 %; the measured difference is +8 %.  The CPU tests check the host
+helpers of the validation tool.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2206_09878_amd.validate_rt import crossing, goncharov_vb, plateau_velocity
+
+
+def test_goncharov_closed_form():
+    # At = 0.5: 2 At/(1 + At) = 2/3, k = 2 pi: v_b^2 = (2/3)/(2 pi)
+    assert abs(goncharov_vb(0.5) - math.sqrt(1.0 / (3.0 * math.pi))) < 1e-15
+    # 2D (C = 3) is sqrt(3) slower
+    assert abs(goncharov_vb(0.5, dim=2) * math.sqrt(3.0) - goncharov_vb(0.5)) < 1e-15
+
+
+def test_crossing_of_a_tanh_profile():
+    y = np.linspace(-2.0, 2.0, 801)
+    for h in (-0.37, 0.0, 0.513):
+        f = 0.5 * (1.0 + np.tanh((y - h) / 0.1))
+        assert abs(crossing(y, f) - h) < 1e-4
+    assert math.isnan(crossing(y, np.zeros_like(y)))
+
+
+def test_plateau_velocity_of_a_linear_rise():
+    at = 0.5
+    tau = np.linspace(0.0, 3.0, 301)
+    t = tau / math.sqrt(at)
+    hb = 0.1 + 0.25 * t
+    r = {"at": at, "tau": tau.tolist(), "h_b": hb.tolist()}
+    assert abs(plateau_velocity(r) - 0.25) < 1e-12
+
+
+@pytest.mark.gpu
+def test_bubble_velocity_matches_potential_theory():
+    import torch
+    from paper_2206_09878_amd.validate_rt import run
+    assert torch.cuda.is_available()
+    print("single-mode RT, At = 0.5, 32 x 129 x 32, dt = 2e-3, to tau = 2.6", flush=True)
+    r = run(at=0.5, n=32, n2=129, dt=2e-3, tau_end=2.6)
+    hb, hs = np.asarray(r["h_b"]), np.asarray(r["h_s"])
+    assert np.isfinite(hb).all() and np.isfinite(hs).all()
+    # after the initial viscous transient the bubble rises and the spike falls (every fifth sample)
+    late = np.asarray(r["tau"]) > 0.5
+    assert (np.diff(hb[late][::5]) > 0).all() and (np.diff(hs[late][::5]) < 0).all()
+    vb = plateau_velocity(r)
+    print("plateau", vb, "Goncharov", r["v_b_goncharov"], flush=True)
+    assert abs(vb / r["v_b_goncharov"] - 1.0) < 0.15
