@@ -38,7 +38,12 @@ Readings of points the paper leaves open (each is listed in the design notes):
   R14 <m2>(+L2/2) = 0
   R15 m^c: mass equation imposed exactly on the coefficients, curl-free
       equation collocated at the interior tau*
-  R16 mu, rho D constant; tau_ij from the projected u = m/rho
+  R16 tau_ij from the projected u = m/rho.  The transport laws mu = g(z) and
+      D_z = h(z) (Section 2) are cubic polynomials in z: g(z) = mu + sum_k
+      mu_z[k] z^(k+1); rho D_z = q(z) or f(z) q(z) with q(z) = rhoD + sum_k
+      rhoD_z[k] z^(k+1) (rhoD_form 0 / 1).  All zero: constant mu, rho D.
+  R16b div(rho D grad z) is expanded by the chain rule, rho D lap z +
+      (rho D)'(z) |grad z|^2, on the physical grid of the R_z product
   R17 RHS_phi2 = -k^2 N2 - d/dy(i k1 N1 + i k3 N3) + k^2 g rho
   R18 gravity uses rho = f(z) on the physical grid, forward-transformed
   R19 advective z equation as printed
@@ -77,6 +82,9 @@ class Config:
     beta_n: float = 0.0
     beta_p: float = -4.0
     kf: int = 4
+    mu_z: tuple = (0.0, 0.0, 0.0)
+    rhoD_z: tuple = (0.0, 0.0, 0.0)
+    rhoD_form: int = 0
 
 
 # ----------------------------------------------------------------------------
@@ -211,6 +219,21 @@ class Plan:
         c = self.cfg
         return rho * rho * (c.rho_h - c.rho_l) / (c.rho_l * c.rho_h)
 
+    # -- transport laws mu = g(z), rho D_z (Section 2; reading R16) -----------
+    def mu_of_z(self, z):
+        c = self.cfg
+        return c.mu + c.mu_z[0] * z + c.mu_z[1] * z ** 2 + c.mu_z[2] * z ** 3
+
+    def rhoD_of_z(self, z):
+        """(rho D_z, d(rho D_z)/dz) at z."""
+        c = self.cfg
+        q = c.rhoD + c.rhoD_z[0] * z + c.rhoD_z[1] * z ** 2 + c.rhoD_z[2] * z ** 3
+        dq = c.rhoD_z[0] + 2.0 * c.rhoD_z[1] * z + 3.0 * c.rhoD_z[2] * z ** 2
+        if c.rhoD_form == 0:
+            return q, dq
+        rho = self.rho_of_z(z)
+        return rho * q, self.drho_dz(rho) * q + rho * dq
+
 
 # ----------------------------------------------------------------------------
 # momentum decomposition
@@ -321,7 +344,9 @@ def substep(plan: Plan, state: dict, stage: int, hist=None, rhs_prev=None,
     # 2. R_z
     def rz(zp, z1, z2, z3, lap, m1, m2, m3):
         rho = plan.rho_of_z(zp)
-        return [(-(m1 * z1 + m2 * z2 + m3 * z3) + c.rhoD * lap) / rho]
+        k, dk = plan.rhoD_of_z(zp)
+        diff = k * lap + dk * (z1 * z1 + z2 * z2 + z3 * z3)      # div(rho D grad z), R16b
+        return [(-(m1 * z1 + m2 * z2 + m3 * z3) + diff) / rho]
 
     (VR,) = plan.plane_phase([Vz] + grad_z + [Vlap, apply(E0, md1), apply(F0, md2),
                                               apply(E0, md3)], rz)
@@ -385,14 +410,15 @@ def substep(plan: Plan, state: dict, stage: int, hist=None, rhs_prev=None,
 
     def fluxes(zp, p1, p2, p3, *g):
         rho = plan.rho_of_z(zp)
+        mu = plan.mu_of_z(zp)
         m = (p1, p2, p3)
         d = [g[0:3], g[3:6], g[6:9]]
         theta = d[0][0] + d[1][1] + d[2][2]
         out = []
         for i, j in pairs:
-            t = -m[i] * m[j] / rho + c.mu * (d[i][j] + d[j][i])
+            t = -m[i] * m[j] / rho + mu * (d[i][j] + d[j][i])
             if i == j:
-                t = t - (2.0 / 3.0) * c.mu * theta
+                t = t - (2.0 / 3.0) * mu * theta
             out.append(t)
         return out
 

@@ -73,6 +73,11 @@ class Workload:
     beta_n: float = 0.0
     beta_p: float = -4.0
     extra: dict = field(default_factory=dict)
+    # transport laws (Section 2): mu(z) = mu + sum_k mu_z[k] z^(k+1);
+    # rho D_z = q(z) (rhoD_form 0) or f(z) q(z) (1), q(z) = rhoD + sum_k rhoD_z[k] z^(k+1)
+    mu_z: tuple = (0.0, 0.0, 0.0)
+    rhoD_z: tuple = (0.0, 0.0, 0.0)
+    rhoD_form: int = 0
 
     @property
     def breakpoints(self) -> np.ndarray:

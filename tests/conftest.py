@@ -19,4 +19,4 @@ def oracle_config(w):
     from oracle.lmvd import Config
     return Config(w.n1, w.n3, w.n2, w.order, w.m1, w.m3, w.L1, w.L2, w.L3,
                   w.breakpoints, w.dt, w.mu, w.rhoD, w.g, w.rho_l, w.rho_h,
-                  w.beta_n, w.beta_p, w.kf)
+                  w.beta_n, w.beta_p, w.kf, tuple(w.mu_z), tuple(w.rhoD_z), w.rhoD_form)
