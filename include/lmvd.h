@@ -81,13 +81,24 @@ typedef struct {
   double L1, L2, L3;     /* domain [0,L1] x [-L2/2, L2/2] x [0,L3] (Section 4)                        */
   const double* breakpoints; /* host array of n2-order+2 strictly increasing values, ends -+L2/2     */
   double dt;             /* time step (fixed per plan: the BDF-like guesses assume a uniform dt)      */
-  double mu;             /* dynamic viscosity, constant                                               */
-  double rhoD;           /* rho D_z, constant                                                         */
+  double mu;             /* dynamic viscosity: constant part of mu(z) (see mu_z)                       */
+  double rhoD;           /* rho D_z: constant part of q(z) (see rhoD_z, rhoD_form)                     */
   double g;              /* gravity along -x2 (body force -rho g delta_i2)                           */
   double rho_l, rho_h;   /* light / heavy density of the mixture EOS rho = rl rh / (rh - (rh - rl) z) */
   double beta_n, beta_p; /* free parameters of the BDF-like guesses (paper: 0, -4)                    */
   int32_t kf;            /* default number of fixed-point iterations                                  */
   int32_t plane_batch;   /* y-planes per physical-space batch (0 = all planes at once)               */
+  /* Transport laws mu = g(z), D_z = h(z) (Section 2, after the stress tensor), as cubics in z:
+   *   mu(z) = mu + mu_z[0] z + mu_z[1] z^2 + mu_z[2] z^3,
+   *   q(z)  = rhoD + rhoD_z[0] z + rhoD_z[1] z^2 + rhoD_z[2] z^3,
+   *   rho D_z = q(z) (rhoD_form 0) or f(z) q(z) (rhoD_form 1, i.e. D_z = q(z)).
+   * All zero (a zero-initialised struct): constant mu and rho D, the fastest path.  A z-dependent
+   * mu adds one physical-grid pass (tau_ij = mu(z) S_ij) per substep; a z-dependent rho D costs
+   * nothing extra: div(rho D grad z) = rho D lap z + (rho D)'(z) |grad z|^2 is formed in the R_z
+   * product.  Non-finite coefficients or another rhoD_form give LMVD_EINVAL. */
+  double mu_z[3];
+  double rhoD_z[3];
+  int32_t rhoD_form;
 } lmvd_config;
 
 /* Arguments of one substep.  All pointers are device pointers.  Pointers that

@@ -42,7 +42,8 @@ constexpr int kNumEv = 4;     // E0, E1, E2 (B at tau), F0 (B* at tau)
 
 enum EvalKind { EV_E0 = 0, EV_E1 = 1, EV_E2 = 2, EV_F0 = 3, EV_LAP = 4, EV_IDENT = 5 };
 enum Mult { MU_ONE = 0, MU_IK1 = 1, MU_IK3 = 2, MU_K1K = 3, MU_K3K = 4 };
-enum Phase { PH_RZ = 0, PH_RHOT = 1, PH_L = 2, PH_VEL = 3, PH_TOPHYS = 5, PH_FROMPHYS = 6 };
+// PH_RZV: R_z with rho D = rho D(z); PH_TAU: tau_ij = mu(z) S_ij (variable transport laws)
+enum Phase { PH_RZ = 0, PH_RHOT = 1, PH_L = 2, PH_VEL = 3, PH_TOPHYS = 5, PH_FROMPHYS = 6, PH_RZV = 7, PH_TAU = 8 };
 enum Epi { EPI_STORE = 0, EPI_ADD = 1, EPI_ADD_ZUPDATE = 2 };
 
 // Read-only plan tables live in the constant address space: the kernels read
@@ -84,6 +85,10 @@ struct DevPlan {
   const double2* xtw;      // [hx] exp(-2 pi i k / m1)
   cptr<double> wall_w;    // weights of the wall rows of E0 P_N (interior values -> wall values)
   int wall_k0, wall_k1;   // interior planes entering the lower / upper wall value
+  // transport laws (Section 2): mu(z) = mu + mu_z . (z, z^2, z^3); q(z) = rhoD + rq_z . (z, z^2, z^3);
+  // rho D_z = q(z) (rq_form 0) or f(z) q(z) (rq_form 1)
+  double mu_z[3], rq_z[3];
+  int rq_form;
 };
 
 struct EvalIn {
@@ -109,6 +114,22 @@ __device__ __forceinline__ double2 fma2(double s, double2 a, double2 acc) {
   return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
 }
 __device__ __forceinline__ double2 times_i(double2 z) { return make_double2(-z.y, z.x); }
+
+// transport laws at a physical point: mu(z), and rho D_z with its z-derivative (rho = f(z) given)
+__device__ __forceinline__ double mu_of(const DevPlan& P, double z) {
+  return fma(fma(fma(P.mu_z[2], z, P.mu_z[1]), z, P.mu_z[0]), z, P.mu);
+}
+__device__ __forceinline__ void rhod_of(const DevPlan& P, double z, double rho, double& k, double& dk) {
+  const double q = fma(fma(fma(P.rq_z[2], z, P.rq_z[1]), z, P.rq_z[0]), z, P.rhoD);
+  const double dq = fma(fma(3.0 * P.rq_z[2], z, 2.0 * P.rq_z[1]), z, P.rq_z[0]);
+  if (P.rq_form == 0) {
+    k = q;
+    dk = dq;
+  } else {  // f'(z) = rho^2 (rh - rl) / (rl rh)
+    k = rho * q;
+    dk = fma(rho * rho * P.drho * P.inv_rlrh, q, rho * dq);
+  }
+}
 
 // spectral multiplier of a column
 __device__ __forceinline__ double2 apply_mult(int m, double k1, double k3, double2 v) {
@@ -212,6 +233,31 @@ struct Op<PH_RZ> {  // R_z = (1/rho)(-m^d . grad z + rho D lap z); inputs lap z,
     a[2 * fs] = -ir * x[6];
     a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
     y[0] = (P.rhoD * x[0] - (x[2] * x[3] + x[4] * x[5] + x[6] * x[7])) * ir;
+  }
+};
+template <>
+struct Op<PH_RZV> {  // R_z = (1/rho)(-m^d . grad z + rho D(z) lap z + (rho D)'(z) |grad z|^2); inputs as PH_RZ
+  static constexpr int NIN = 8, NOUT = 1;
+  __device__ static void apply(const DevPlan& P, const double* x, double* y, double* a, size_t fs) {
+    const double ir = (P.rho_h - P.drho * x[1]) * P.inv_rlrh;
+    const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x[1]);
+    double k, dk;
+    rhod_of(P, x[1], rho, k, dk);
+    a[0] = -ir * x[2];
+    a[fs] = -ir * x[4];
+    a[2 * fs] = -ir * x[6];
+    a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
+    const double g2 = x[2] * x[2] + x[4] * x[4] + x[6] * x[6];
+    y[0] = (k * x[0] + dk * g2 - (x[2] * x[3] + x[4] * x[5] + x[6] * x[7])) * ir;
+  }
+};
+template <>
+struct Op<PH_TAU> {  // tau_ij = mu(z) S_ij; inputs S11, S12, S13, S22, S23, S33, z
+  static constexpr int NIN = 7, NOUT = 6;
+  __device__ static void apply(const DevPlan& P, const double* x, double* y, double*, size_t) {
+    const double mu = mu_of(P, x[6]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) y[q] = mu * x[q];
   }
 };
 template <>
@@ -947,6 +993,62 @@ struct Pair<PH_RZ> {
     return make_double2(s[1] * s[0], 0.0);
   }
 };
+// the same inputs with rho D = rho D(z): + (rho D)'(z) |grad z|^2 (div(rho D grad z) by the chain rule)
+template <>
+struct Pair<PH_RZV> {
+  static constexpr int NP = 4, NQ = 1, NST = 3;
+  __device__ static constexpr int fa(int i) { return Pair<PH_RZ>::fa(i); }
+  __device__ static constexpr int fb(int i) { return Pair<PH_RZ>::fb(i); }
+  __device__ static constexpr bool dxa(int i) { return i == 1; }
+  __device__ static constexpr int ga(int q) { return q; }
+  __device__ static constexpr int gb(int) { return -1; }
+  template <int I>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y, double* a, size_t fs) {
+    if constexpr (I == 0) {
+      const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * y);
+      double k, dk;
+      rhod_of(P, y, rho, k, dk);
+      s[0] = (P.rho_h - P.drho * y) * P.inv_rlrh;  // 1/rho
+      s[1] = k * x;
+      s[2] = dk;
+      if (a) a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
+    } else {
+      s[1] = fma(s[2] * x, x, s[1] - x * y);
+      if (a) a[(I - 1) * fs] = -s[0] * x;
+    }
+  }
+  template <int Q>
+  __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) {
+    return make_double2(s[1] * s[0], 0.0);
+  }
+};
+// inputs (zbuf slots) S11, S12, S13, S22, S23, S33 and z in slot 6 -> tau_ij = mu(z) S_ij (fields 0..5)
+template <>
+struct Pair<PH_TAU> {
+  static constexpr int NP = 4, NQ = 3, NST = 7;
+  // pairs (z, S11), (S12, S13), (S22, S23), (S33)
+  __device__ static constexpr int fa(int i) { return i == 0 ? 6 : 2 * i - 1; }
+  __device__ static constexpr int fb(int i) { return i == 0 ? 0 : i == 3 ? -1 : 2 * i; }
+  __device__ static constexpr bool dxa(int) { return false; }
+  __device__ static constexpr int ga(int q) { return 2 * q; }
+  __device__ static constexpr int gb(int q) { return 2 * q + 1; }
+  template <int I>
+  __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y, double*, size_t) {
+    if constexpr (I == 0) {
+      s[0] = mu_of(P, x);
+      s[1] = s[0] * y;
+    } else if constexpr (I == 3) {
+      s[6] = s[0] * x;
+    } else {
+      s[2 * I] = s[0] * x;
+      s[2 * I + 1] = s[0] * y;
+    }
+  }
+  template <int Q>
+  __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) {
+    return make_double2(s[2 * Q + 1], s[2 * Q + 2]);
+  }
+};
 template <>
 struct Pair<PH_L> {  // inputs m1c, m2c, m3c:  L z_t = -(1/rho) grad z . m^c = g . m^c
   static constexpr int NP = 2, NQ = 1, NST = 1;
@@ -1206,7 +1308,7 @@ __device__ __forceinline__ void xpair_body(const DevPlan& P, const unsigned bx, 
         }
     } else {
       // aux point q of this thread: ap[T q], fields fs apart
-      double* ap = (aux && (bok || PH != PH_RZ)) ? aux + (size_t(j0 + jj) * M3 + bb) * P.m1 + tl : nullptr;
+      double* ap = (aux && (bok || (PH != PH_RZ && PH != PH_RZV))) ? aux + (size_t(j0 + jj) * M3 + bb) * P.m1 + tl : nullptr;
       pair_in<S, 0, E, RL, S::NST, T>(P, i, st, v, ap, size_t(P.n2) * M3 * P.m1);
     }
   }
@@ -1583,7 +1685,9 @@ struct RowWin {
   }
 };
 
-template <int GROUP, int W, int LB>
+// VARMU: mu = mu(z); tau_ij was formed on the physical grid (mu(z) S_ij) and its values at tau are read
+// from Ta, Tb, Tc (which the sweep then overwrites, row by row, with its own intermediates); u is not read.
+template <int GROUP, int W, int LB, bool VARMU = false>
 __device__ __forceinline__ void flux_body(const DevPlan& P, const unsigned bx, const double2* __restrict__ Ca,
                                           const double2* __restrict__ Cb, const double2* __restrict__ Cc,
                                           const double2* __restrict__ u1, const double2* __restrict__ u2,
@@ -1600,40 +1704,48 @@ __device__ __forceinline__ void flux_body(const DevPlan& P, const unsigned bx, c
   const auto Ui = P.lu_uinv;
   {
     RowWin<W> w1, w2, w3;
-    w1.init(u1, ncol, c, n2);
-    w2.init(u2, ncol, c, n2);
-    w3.init(u3, ncol, c, n2);
+    if constexpr (!VARMU) {
+      w1.init(u1, ncol, c, n2);
+      w2.init(u2, ncol, c, n2);
+      w3.init(u3, ncol, c, n2);
+    }
     double2 ra[LB], rb[LB], rc[LB];
 #pragma unroll
     for (int m = 0; m < LB; ++m) ra[m] = rb[m] = rc[m] = zero2();
     for (int i = 0; i < n2; ++i) {
-      const int lo = P.ev_lo[i];
-      w1.advance(u1, ncol, c, n2, lo);
-      w2.advance(u2, ncol, c, n2, lo);
-      w3.advance(u3, ncol, c, n2, lo);
-      const auto e0 = P.ev_w + size_t(i) * kMaxW;
-      const auto e1 = P.ev_w + (size_t(n2) + i) * kMaxW;
-      double2 s0[3] = {w1.dot(e0), w2.dot(e0), w3.dot(e0)};
-      double2 s1[3] = {w1.dot(e1), w2.dot(e1), w3.dot(e1)};
-      // d[a][b] = d u_a / d x_b at tau_i
-      double2 d[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        d[a][0] = times_i(cscale(s0[a], k1));
-        d[a][1] = s1[a];
-        d[a][2] = times_i(cscale(s0[a], k3));
-      }
-      const double2 theta = cadd(cadd(d[0][0], d[1][1]), d[2][2]);
       const size_t e = size_t(i) * ncol + c;
       double2 ba, bb, bc;
-      if (GROUP == 0) {
-        ba = cadd(Ca[e], make_double2(2 * mu * d[0][0].x - th * theta.x, 2 * mu * d[0][0].y - th * theta.y));
-        bb = cadd(Cb[e], cscale(cadd(d[0][1], d[1][0]), mu));
-        bc = cadd(Cc[e], cscale(cadd(d[0][2], d[2][0]), mu));
+      if constexpr (VARMU) {
+        ba = cadd(Ca[e], Ta[e]);
+        bb = cadd(Cb[e], Tb[e]);
+        bc = cadd(Cc[e], Tc[e]);
       } else {
-        ba = cadd(Ca[e], make_double2(2 * mu * d[1][1].x - th * theta.x, 2 * mu * d[1][1].y - th * theta.y));
-        bb = cadd(Cb[e], cscale(cadd(d[1][2], d[2][1]), mu));
-        bc = cadd(Cc[e], make_double2(2 * mu * d[2][2].x - th * theta.x, 2 * mu * d[2][2].y - th * theta.y));
+        const int lo = P.ev_lo[i];
+        w1.advance(u1, ncol, c, n2, lo);
+        w2.advance(u2, ncol, c, n2, lo);
+        w3.advance(u3, ncol, c, n2, lo);
+        const auto e0 = P.ev_w + size_t(i) * kMaxW;
+        const auto e1 = P.ev_w + (size_t(n2) + i) * kMaxW;
+        double2 s0[3] = {w1.dot(e0), w2.dot(e0), w3.dot(e0)};
+        double2 s1[3] = {w1.dot(e1), w2.dot(e1), w3.dot(e1)};
+        // d[a][b] = d u_a / d x_b at tau_i
+        double2 d[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          d[a][0] = times_i(cscale(s0[a], k1));
+          d[a][1] = s1[a];
+          d[a][2] = times_i(cscale(s0[a], k3));
+        }
+        const double2 theta = cadd(cadd(d[0][0], d[1][1]), d[2][2]);
+        if (GROUP == 0) {
+          ba = cadd(Ca[e], make_double2(2 * mu * d[0][0].x - th * theta.x, 2 * mu * d[0][0].y - th * theta.y));
+          bb = cadd(Cb[e], cscale(cadd(d[0][1], d[1][0]), mu));
+          bc = cadd(Cc[e], cscale(cadd(d[0][2], d[2][0]), mu));
+        } else {
+          ba = cadd(Ca[e], make_double2(2 * mu * d[1][1].x - th * theta.x, 2 * mu * d[1][1].y - th * theta.y));
+          bb = cadd(Cb[e], cscale(cadd(d[1][2], d[2][1]), mu));
+          bc = cadd(Cc[e], make_double2(2 * mu * d[2][2].x - th * theta.x, 2 * mu * d[2][2].y - th * theta.y));
+        }
       }
 #pragma unroll
       for (int m = 0; m < LB; ++m) {
@@ -1719,13 +1831,65 @@ __device__ __forceinline__ void flux_body(const DevPlan& P, const unsigned bx, c
     }
   }
 }
-template <int GROUP, int W, int LB>
+template <int GROUP, int W, int LB, bool VARMU>
 __global__ void __launch_bounds__(kThreads) k_flux(DevPlan P, const double2* __restrict__ Ca,
                                   const double2* __restrict__ Cb, const double2* __restrict__ Cc,
                                   const double2* __restrict__ u1, const double2* __restrict__ u2,
                                   const double2* __restrict__ u3, double2* Ta, double2* Tb, double2* Tc, double2* RO,
                                   double2* RP, const double2* __restrict__ rhov) {
-  flux_body<GROUP, W, LB>(P, blockIdx.x, Ca, Cb, Cc, u1, u2, u3, Ta, Tb, Tc, RO, RP, rhov);
+  flux_body<GROUP, W, LB, VARMU>(P, blockIdx.x, Ca, Cb, Cc, u1, u2, u3, Ta, Tb, Tc, RO, RP, rhov);
+}
+
+// column kernel (variable viscosity): the rate-of-strain values S_ij = d_j u_i + d_i u_j - 2/3 theta
+// delta_ij (i <= j) at the Greville points from the projected velocity u_hat (i k1, d/dy, i k3), for the
+// physical-grid product tau_ij = mu(z) S_ij
+struct SixPtr {
+  double2* v[6];
+};
+template <int W>
+__device__ __forceinline__ void strain_body(const DevPlan& P, const unsigned bx, const double2* __restrict__ u1,
+                                            const double2* __restrict__ u2, const double2* __restrict__ u3,
+                                            const SixPtr& S) {
+  const int nl = P.nl, nn = P.nn, n2 = P.n2;
+  const size_t ncol = size_t(nn) * nl;
+  const size_t c = size_t(bx) * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const double k1 = P.k1[c % nl], k3 = P.k3[c / nl];
+  RowWin<W> w1, w2, w3;
+  w1.init(u1, ncol, c, n2);
+  w2.init(u2, ncol, c, n2);
+  w3.init(u3, ncol, c, n2);
+  for (int i = 0; i < n2; ++i) {
+    const int lo = P.ev_lo[i];
+    w1.advance(u1, ncol, c, n2, lo);
+    w2.advance(u2, ncol, c, n2, lo);
+    w3.advance(u3, ncol, c, n2, lo);
+    const auto e0 = P.ev_w + size_t(i) * kMaxW;
+    const auto e1 = P.ev_w + (size_t(n2) + i) * kMaxW;
+    const double2 s0[3] = {w1.dot(e0), w2.dot(e0), w3.dot(e0)};
+    const double2 s1[3] = {w1.dot(e1), w2.dot(e1), w3.dot(e1)};
+    double2 d[3][3];  // d u_a / d x_b at tau_i
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      d[a][0] = times_i(cscale(s0[a], k1));
+      d[a][1] = s1[a];
+      d[a][2] = times_i(cscale(s0[a], k3));
+    }
+    const double2 th = cscale(cadd(cadd(d[0][0], d[1][1]), d[2][2]), 2.0 / 3.0);
+    const size_t e = size_t(i) * ncol + c;
+    S.v[0][e] = csub(cscale(d[0][0], 2.0), th);
+    S.v[1][e] = cadd(d[0][1], d[1][0]);
+    S.v[2][e] = cadd(d[0][2], d[2][0]);
+    S.v[3][e] = csub(cscale(d[1][1], 2.0), th);
+    S.v[4][e] = cadd(d[1][2], d[2][1]);
+    S.v[5][e] = csub(cscale(d[2][2], 2.0), th);
+  }
+}
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_strain(DevPlan P, const double2* __restrict__ u1,
+                                                     const double2* __restrict__ u2,
+                                                     const double2* __restrict__ u3, SixPtr S) {
+  strain_body<W>(P, blockIdx.x, u1, u2, u3, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -2745,19 +2909,35 @@ struct JobMc : ColumnJob {
   }
 };
 
-template <int GROUP, int W, int LB>
+struct FluxArgs {
+  const double2 *Ca, *Cb, *Cc, *u1, *u2, *u3;
+  double2 *Ta, *Tb, *Tc, *RO, *RP;
+  const double2* rhov;
+};
+template <int GROUP, int W, int LB, bool VARMU = false>
 struct JobFlux : ColumnJob {
-  struct Args {
-    const double2 *Ca, *Cb, *Cc, *u1, *u2, *u3;
-    double2 *Ta, *Tb, *Tc, *RO, *RP;
-    const double2* rhov;
-  };
+  using Args = FluxArgs;
   __device__ static void run(const DevPlan& P, unsigned bx, unsigned, unsigned, const Args& A) {
-    flux_body<GROUP, W, LB>(P, bx, A.Ca, A.Cb, A.Cc, A.u1, A.u2, A.u3, A.Ta, A.Tb, A.Tc, A.RO, A.RP, A.rhov);
+    flux_body<GROUP, W, LB, VARMU>(P, bx, A.Ca, A.Cb, A.Cc, A.u1, A.u2, A.u3, A.Ta, A.Tb, A.Tc, A.RO, A.RP,
+                                   A.rhov);
   }
   static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
-    hipLaunchKernelGGL((k_flux<GROUP, W, LB>), g, dim3(kThreads), lds, s, P, A.Ca, A.Cb, A.Cc, A.u1, A.u2, A.u3,
+    hipLaunchKernelGGL((k_flux<GROUP, W, LB, VARMU>), g, dim3(kThreads), lds, s, P, A.Ca, A.Cb, A.Cc, A.u1, A.u2, A.u3,
                        A.Ta, A.Tb, A.Tc, A.RO, A.RP, A.rhov);
+  }
+};
+
+template <int W>
+struct JobStrain : ColumnJob {
+  struct Args {
+    const double2 *u1, *u2, *u3;
+    SixPtr S;
+  };
+  __device__ static void run(const DevPlan& P, unsigned bx, unsigned, unsigned, const Args& A) {
+    strain_body<W>(P, bx, A.u1, A.u2, A.u3, A.S);
+  }
+  static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& A) {
+    hipLaunchKernelGGL((k_strain<W>), g, dim3(kThreads), lds, s, P, A.u1, A.u2, A.u3, A.S);
   }
 };
 
@@ -3142,6 +3322,11 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   D.rho_h = cfg->rho_h;
   D.inv_rlrh = 1.0 / (cfg->rho_l * cfg->rho_h);
   D.drho = cfg->rho_h - cfg->rho_l;
+  for (int k = 0; k < 3; ++k) {
+    D.mu_z[k] = cfg->mu_z[k];
+    D.rq_z[k] = cfg->rhoD_z[k];
+  }
+  D.rq_form = cfg->rhoD_form;
   std::vector<int> lo;
   std::vector<double> w;
   RowTable ev[kNumEv] = {H.E[0], H.E[1], H.E[2], H.F0};
@@ -3484,7 +3669,7 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
   double2* obuf = c.at<double2>(p->ws.off_obuf);
   double* aux = c.at<double>(p->ws.off_aux);
   // physical aux fields each phase writes (R_z) or reads (L, rho_t)
-  const double naux = (PH == PH_RZ) ? 4.0 : (PH == PH_L) ? 3.0 : (PH == PH_RHOT) ? 1.0 : 0.0;
+  const double naux = (PH == PH_RZ || PH == PH_RZV) ? 4.0 : (PH == PH_L) ? 3.0 : (PH == PH_RHOT) ? 1.0 : 0.0;
   const int lg = p->lgz, bg = p->bgx;
   const size_t lds_z = size_t(lg) * M3 * sizeof(double2);
   const size_t lds_x = size_t(bg) * H.hx * sizeof(double2);
@@ -3513,8 +3698,9 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
       }
     }
     {
-      constexpr int xcls = (PH == PH_RZ) ? KC_XPASS_RZ : (PH == PH_L) ? KC_XPASS_L : (PH == PH_RHOT) ? KC_XPASS_RHOT
-                           : (PH == PH_VEL) ? KC_XPASS_VEL : KC_XPASS_IO;
+      constexpr int xcls = (PH == PH_RZ || PH == PH_RZV) ? KC_XPASS_RZ : (PH == PH_L) ? KC_XPASS_L
+                           : (PH == PH_RHOT) ? KC_XPASS_RHOT : (PH == PH_VEL || PH == PH_TAU) ? KC_XPASS_VEL
+                           : KC_XPASS_IO;
       ProfScope ps(p, xcls, c.s, nb * ((nin + nout) * zplane + naux * double(M3) * H.cfg.m1 * 8.0));
       if (xr) {
 #define CALLX(N) launch_xpass_t<PH, N>(c, zbuf, obuf, phys_out, phys_in, j0, nb, aux)
@@ -3616,6 +3802,12 @@ static void zfilter(const Ctx& c, const double2* in, const double2* add, double2
   }
   const size_t ps_ = size_t(M3) * H.nl;
   col<JobWall>(c, dim3(unsigned((ps_ + kThreads - 1) / kThreads)), 0, {out});
+}
+
+// transport laws that depend on z
+static bool var_mu(const lmvd_config& c) { return c.mu_z[0] != 0.0 || c.mu_z[1] != 0.0 || c.mu_z[2] != 0.0; }
+static bool var_rhod(const lmvd_config& c) {
+  return c.rhoD_form != 0 || c.rhoD_z[0] != 0.0 || c.rhoD_z[1] != 0.0 || c.rhoD_z[2] != 0.0;
 }
 
 static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void* workspace, hipStream_t s,
@@ -3743,16 +3935,14 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   // the register x-pass forms d z / d x from the z line and takes z from zbuf slot 6, where it stays for
   // the u, rho, C_ij pass when all planes are one batch; the generic x-pass takes them as inputs
   const bool xr = p->use_reg && xreg_size(H.cfg.m1, H.nl);
-  if (xr)
-    st = plane_phase<PH_RZ>(c,
-                            {ev(vzl, EV_IDENT), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT),
-                             ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT), ev(vz0, EV_IDENT)},
-                            {vals[0]});
-  else
-    st = plane_phase<PH_RZ>(c,
-                            {ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT),
-                             ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)},
-                            {vals[0]});
+  {
+    const std::vector<EvalIn> rin =
+        xr ? std::vector<EvalIn>{ev(vzl, EV_IDENT), ev(vmd1, EV_IDENT), ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT),
+                                 ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT), ev(vz0, EV_IDENT)}
+           : std::vector<EvalIn>{ev(vzl, EV_IDENT), ev(vz0, EV_IDENT), ev(vz0, EV_IDENT, MU_IK1), ev(vmd1, EV_IDENT),
+                                 ev(vz1, EV_IDENT), ev(vc2d, EV_IDENT), ev(vz3, EV_IDENT), ev(vmd3, EV_IDENT)};
+    st = var_rhod(H.cfg) ? plane_phase<PH_RZV>(c, rin, {vals[0]}) : plane_phase<PH_RZ>(c, rin, {vals[0]});
+  }
   if (st != LMVD_OK) return st;
   proj(c, 2, vals[0], rz);
   // The iterates before the last one are used only through their values at tau.  With all planes in
@@ -3829,24 +4019,55 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     col<JobProj3>(c, dim3((n + kThreads - 1) / kThreads, 3), 0, {0, ProjBatch{{vals[0], vals[1], vals[2]}, {u[0], u[1],
                   u[2]}}, n});
   }
+  const bool narrow = H.p <= 8 && H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
+  const bool varmu = var_mu(H.cfg);
+  if (varmu) {
+    // mu = mu(z): tau_ij = mu(z) S_ij on the physical grid.  The S_ij values at tau come from u_hat and go
+    // to the R_z inputs' buffers (dead by now); z is still in zbuf slot 6 when all planes are one batch
+    // on the register x-pass, else transformed again; the tau_ij values land in T, which the flux
+    // kernels read and then overwrite.
+    double2* S[6] = {vz1, vzl, vz3, vmd1, vmd3, vc2d};
+    {
+      const int n = int(ncol);
+      const dim3 grid((n + kThreads - 1) / kThreads);
+      ProfScope ps(p, KC_FLUX, s, 16.0 * nB * 9.0);
+      const SixPtr sp{{S[0], S[1], S[2], S[3], S[4], S[5]}};
+      if (narrow) col<JobStrain<8>>(c, grid, 0, {u[0], u[1], u[2], sp});
+      else col<JobStrain<kMaxW>>(c, grid, 0, {u[0], u[1], u[2], sp});
+    }
+    std::vector<EvalIn> tin;
+    for (int q = 0; q < 6; ++q) tin.push_back(ev(S[q], EV_IDENT));
+    if (!(xr && p->pb == H.n2)) {
+      EvalIn zin = ev(vz0, EV_IDENT);
+      zin.slot = 6;
+      tin.push_back(zin);
+    }
+    st = plane_phase<PH_TAU>(c, tin, {T[0], T[1], T[2], T[3], T[4], T[5]});
+    if (st != LMVD_OK) return st;
+  }
   // fluxes and their share of the RHS values at tau (RO: Omega2, RP: phi2)
   double2* RO = vals[0];
   double2* RP = vals[1];
   {
     const int n = int(ncol);
     const dim3 grid((n + kThreads - 1) / kThreads);
-    // per group: C_ij and u_hat in, L-sweep intermediates out and back, RHS values out (group 1 also
-    // reads them and rho)
+    // per group: C_ij and u_hat (or tau_ij values) in, L-sweep intermediates out and back, RHS values out
+    // (group 1 also reads them and rho)
     ProfScope ps(p, KC_FLUX, s, 16.0 * nB * 31.0);
-    const bool narrow = H.p <= 8 && H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
-    if (narrow) {
-      col<JobFlux<0, 8, 6>>(c, grid, 0, {cv[0], cv[1], cv[2], u[0], u[1], u[2], T[0], T[1], T[2], RO, RP, rhov});
-      col<JobFlux<1, 8, 6>>(c, grid, 0, {cv[3], cv[4], cv[5], u[0], u[1], u[2], T[3], T[4], T[5], RO, RP, rhov});
+    const FluxArgs fa{cv[0], cv[1], cv[2], u[0], u[1], u[2], T[0], T[1], T[2], RO, RP, rhov};
+    const FluxArgs fb{cv[3], cv[4], cv[5], u[0], u[1], u[2], T[3], T[4], T[5], RO, RP, rhov};
+    if (narrow && varmu) {
+      col<JobFlux<0, 8, 6, true>>(c, grid, 0, fa);
+      col<JobFlux<1, 8, 6, true>>(c, grid, 0, fb);
+    } else if (narrow) {
+      col<JobFlux<0, 8, 6>>(c, grid, 0, fa);
+      col<JobFlux<1, 8, 6>>(c, grid, 0, fb);
+    } else if (varmu) {
+      col<JobFlux<0, kMaxW, kMaxBand, true>>(c, grid, 0, fa);
+      col<JobFlux<1, kMaxW, kMaxBand, true>>(c, grid, 0, fb);
     } else {
-      col<JobFlux<0, kMaxW, kMaxBand>>(c, grid, 0,
-                                       {cv[0], cv[1], cv[2], u[0], u[1], u[2], T[0], T[1], T[2], RO, RP, rhov});
-      col<JobFlux<1, kMaxW, kMaxBand>>(c, grid, 0,
-                                       {cv[3], cv[4], cv[5], u[0], u[1], u[2], T[3], T[4], T[5], RO, RP, rhov});
+      col<JobFlux<0, kMaxW, kMaxBand>>(c, grid, 0, fa);
+      col<JobFlux<1, kMaxW, kMaxBand>>(c, grid, 0, fb);
     }
   }
   // RHS and RK2

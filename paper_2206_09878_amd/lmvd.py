@@ -33,6 +33,7 @@ class Config(ctypes.Structure):
         ("rho_l", ctypes.c_double), ("rho_h", ctypes.c_double),
         ("beta_n", ctypes.c_double), ("beta_p", ctypes.c_double),
         ("kf", ctypes.c_int32), ("plane_batch", ctypes.c_int32),
+        ("mu_z", ctypes.c_double * 3), ("rhoD_z", ctypes.c_double * 3), ("rhoD_form", ctypes.c_int32),
     ]
 
 
@@ -111,7 +112,8 @@ def make_config(w, plane_batch: int = 0):
     bp = np.ascontiguousarray(w.breakpoints, dtype=np.float64)
     c = Config(w.n1, w.n3, w.n2, w.order, w.m1, w.m3, w.L1, w.L2, w.L3,
                bp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), w.dt, w.mu, w.rhoD, w.g,
-               w.rho_l, w.rho_h, w.beta_n, w.beta_p, w.kf, plane_batch)
+               w.rho_l, w.rho_h, w.beta_n, w.beta_p, w.kf, plane_batch,
+               (ctypes.c_double * 3)(*w.mu_z), (ctypes.c_double * 3)(*w.rhoD_z), w.rhoD_form)
     c._bp = bp
     return c
 
