@@ -18,6 +18,7 @@ oracle baseline.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -164,7 +165,8 @@ def cpu_baseline(full, n=128, n2=129):
     inp = make_inputs(w, seed=2)
     st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
     cfg = Config(w.n1, w.n3, w.n2, w.order, w.m1, w.m3, w.L1, w.L2, w.L3, w.breakpoints, w.dt, w.mu,
-                 w.rhoD, w.g, w.rho_l, w.rho_h, w.beta_n, w.beta_p, w.kf)
+                 w.rhoD, w.g, w.rho_l, w.rho_h, w.beta_n, w.beta_p, w.kf, tuple(w.mu_z), tuple(w.rhoD_z),
+                 w.rhoD_form)
     op = OPlan(cfg)
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
@@ -191,6 +193,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rt512")
     ap.add_argument("--plane-batch", type=int, default=0)
+    ap.add_argument("--transport", choices=["constant", "variable"], default="constant",
+                    help="variable: mu(z) = mu (1 + z/2 - 0.3 z^2 + 0.2 z^3), rho D_z = f(z) rhoD (1 + 0.4 z + "
+                         "0.1 z^2 - 0.05 z^3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-class", choices=names, default=None,
                     help="time this kernel class instead of detecting the dominant one")
@@ -230,6 +235,9 @@ def main():
         print(json.dumps(bench_batch(args)), flush=True)
         return
     w = workload(args.workload)
+    if args.transport == "variable":
+        w = dataclasses.replace(w, mu_z=(0.5 * w.mu, -0.3 * w.mu, 0.2 * w.mu),
+                                rhoD_z=(0.4 * w.rhoD, 0.1 * w.rhoD, -0.05 * w.rhoD), rhoD_form=1)
     plan = Plan(w, plane_batch=args.plane_batch)
     stepper = Stepper(plan, make_inputs(w, seed=2, stage=0), stage=0)
     for _ in range(args.warmup):
@@ -282,7 +290,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: Rayleigh-Taylor At=0.925, {w.n1}x{w.n2}x{w.n3} modes, "
                                f"{w.m1}x{w.m3} dealiased x-z grid, k_f={w.kf}, stages n/' alternating",
-                   "kf": w.kf, "plane_batch": args.plane_batch or w.n2},
+                   "kf": w.kf, "plane_batch": args.plane_batch or w.n2, "transport": args.transport},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel_class": names[dom], "kernel": kernel_symbol(names[dom], w),

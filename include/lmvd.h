@@ -49,7 +49,9 @@
  * M3 <= 1024 and M1/2 <= 768, N1/2 <= M1/2, N3-1 <= M3, order <= 9, n2 <= 4096).  LMVD_ENOMEM:
  * host or device allocation failed in lmvd_plan_create.  LMVD_EHIP: a HIP
  * call failed.  LMVD_ENUMERIC: a factorisation without pivoting met a
- * near-zero pivot at plan creation.
+ * near-zero pivot at plan creation.  LMVD_ENONFINITE: with check_finite set,
+ * an output of lmvd_substep holds a NaN or an infinity (the outputs are
+ * written all the same).
  */
 #ifndef LMVD_H
 #define LMVD_H
@@ -69,7 +71,8 @@ typedef enum {
   LMVD_ENOMEM = -2,
   LMVD_EHIP = -3,
   LMVD_EUNSUPPORTED = -4,
-  LMVD_ENUMERIC = -5
+  LMVD_ENUMERIC = -5,
+  LMVD_ENONFINITE = -6
 } lmvd_status;
 
 /* Problem definition.  Symbols follow the paper. */
@@ -99,6 +102,10 @@ typedef struct {
   double mu_z[3];
   double rhoD_z[3];
   int32_t rhoD_form;
+  /* 1: lmvd_substep scans its outputs (z_out, phi2_out, omega2_out, the plane means, zt) for NaN
+   * and infinity and returns LMVD_ENONFINITE if it finds one.  The scan synchronises the stream
+   * (a diagnostic for long runs, not for timed loops); a plan with it set cannot enter a graph. */
+  int32_t check_finite;
 } lmvd_config;
 
 /* Arguments of one substep.  All pointers are device pointers.  Pointers that

@@ -252,12 +252,12 @@ struct Op<PH_RZV> {  // R_z = (1/rho)(-m^d . grad z + rho D(z) lap z + (rho D)'(
   }
 };
 template <>
-struct Op<PH_TAU> {  // tau_ij = mu(z) S_ij; inputs S11, S12, S13, S22, S23, S33, z
-  static constexpr int NIN = 7, NOUT = 6;
+struct Op<PH_TAU> {  // tau = mu(z) S for three strain components; inputs S_a, S_b, S_c, z
+  static constexpr int NIN = 4, NOUT = 3;
   __device__ static void apply(const DevPlan& P, const double* x, double* y, double*, size_t) {
-    const double mu = mu_of(P, x[6]);
+    const double mu = mu_of(P, x[3]);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) y[q] = mu * x[q];
+    for (int q = 0; q < 3; ++q) y[q] = mu * x[q];
   }
 };
 template <>
@@ -1022,31 +1022,31 @@ struct Pair<PH_RZV> {
     return make_double2(s[1] * s[0], 0.0);
   }
 };
-// inputs (zbuf slots) S11, S12, S13, S22, S23, S33 and z in slot 6 -> tau_ij = mu(z) S_ij (fields 0..5)
+// inputs (zbuf slots) S_a, S_b, S_c in slots 0..2 and z in slot 6 -> tau = mu(z) S (fields 0..2); run
+// once per group of three strain components, so that four doubles of state per point stay in registers
 template <>
 struct Pair<PH_TAU> {
-  static constexpr int NP = 4, NQ = 3, NST = 7;
-  // pairs (z, S11), (S12, S13), (S22, S23), (S33)
-  __device__ static constexpr int fa(int i) { return i == 0 ? 6 : 2 * i - 1; }
-  __device__ static constexpr int fb(int i) { return i == 0 ? 0 : i == 3 ? -1 : 2 * i; }
+  static constexpr int NP = 2, NQ = 2, NST = 4;
+  // pairs (z, S_a), (S_b, S_c)
+  __device__ static constexpr int fa(int i) { return i == 0 ? 6 : 1; }
+  __device__ static constexpr int fb(int i) { return i == 0 ? 0 : 2; }
   __device__ static constexpr bool dxa(int) { return false; }
-  __device__ static constexpr int ga(int q) { return 2 * q; }
-  __device__ static constexpr int gb(int q) { return 2 * q + 1; }
+  __device__ static constexpr int ga(int q) { return q == 0 ? 0 : 2; }
+  __device__ static constexpr int gb(int q) { return q == 0 ? 1 : -1; }
   template <int I>
   __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y, double*, size_t) {
     if constexpr (I == 0) {
       s[0] = mu_of(P, x);
       s[1] = s[0] * y;
-    } else if constexpr (I == 3) {
-      s[6] = s[0] * x;
     } else {
-      s[2 * I] = s[0] * x;
-      s[2 * I + 1] = s[0] * y;
+      s[2] = s[0] * x;
+      s[3] = s[0] * y;
     }
   }
   template <int Q>
   __device__ __forceinline__ static double2 out(const DevPlan&, const double* s) {
-    return make_double2(s[2 * Q + 1], s[2 * Q + 2]);
+    if constexpr (Q == 0) return make_double2(s[1], s[2]);
+    else return make_double2(s[3], 0.0);
   }
 };
 template <>
@@ -3182,6 +3182,7 @@ struct lmvd_plan_s {
   double* fac = nullptr;    // A(k) factors (plan memory), filled on first use
   bool fac_ready = false;
   int fac_la = 7, fac_ua = 7;  // instantiated band of the factor kernels
+  unsigned* finite_flag = nullptr;  // device word of the non-finite scan
 };
 
 namespace lmvd {
@@ -3395,6 +3396,15 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
     p->allocs.push_back(d);
     p->fac = static_cast<double*>(d);
     D.fac = p->fac;
+  }
+  {
+    void* d = nullptr;
+    if (hipMalloc(&d, 256) != hipSuccess) {
+      lmvd_plan_destroy(p);
+      return LMVD_ENOMEM;
+    }
+    p->allocs.push_back(d);
+    p->finite_flag = static_cast<unsigned*>(d);
   }
   const double* tw = nullptr;
   UP_OR_FAIL(H.fz.tw, &tw);
@@ -4023,9 +4033,10 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   const bool varmu = var_mu(H.cfg);
   if (varmu) {
     // mu = mu(z): tau_ij = mu(z) S_ij on the physical grid.  The S_ij values at tau come from u_hat and go
-    // to the R_z inputs' buffers (dead by now); z is still in zbuf slot 6 when all planes are one batch
-    // on the register x-pass, else transformed again; the tau_ij values land in T, which the flux
-    // kernels read and then overwrite.
+    // to the R_z inputs' buffers (dead by now).  Two physical passes, one per group of three components
+    // (the two flux groups); z is still in zbuf slot 6 when all planes are one batch on the register
+    // x-pass, else transformed again.  The tau_ij values land in T, which the flux kernels read and then
+    // overwrite.
     double2* S[6] = {vz1, vzl, vz3, vmd1, vmd3, vc2d};
     {
       const int n = int(ncol);
@@ -4035,15 +4046,16 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
       if (narrow) col<JobStrain<8>>(c, grid, 0, {u[0], u[1], u[2], sp});
       else col<JobStrain<kMaxW>>(c, grid, 0, {u[0], u[1], u[2], sp});
     }
-    std::vector<EvalIn> tin;
-    for (int q = 0; q < 6; ++q) tin.push_back(ev(S[q], EV_IDENT));
-    if (!(xr && p->pb == H.n2)) {
-      EvalIn zin = ev(vz0, EV_IDENT);
-      zin.slot = 6;
-      tin.push_back(zin);
+    for (int grp = 0; grp < 2; ++grp) {
+      std::vector<EvalIn> tin{ev(S[3 * grp], EV_IDENT), ev(S[3 * grp + 1], EV_IDENT), ev(S[3 * grp + 2], EV_IDENT)};
+      if (!(xr && p->pb == H.n2)) {
+        EvalIn zin = ev(vz0, EV_IDENT);
+        if (xr) zin.slot = 6;  // the register x-pass reads z from slot 6, the generic one from slot 3
+        tin.push_back(zin);
+      }
+      st = plane_phase<PH_TAU>(c, tin, {T[3 * grp], T[3 * grp + 1], T[3 * grp + 2]});
+      if (st != LMVD_OK) return st;
     }
-    st = plane_phase<PH_TAU>(c, tin, {T[0], T[1], T[2], T[3], T[4], T[5]});
-    if (st != LMVD_OK) return st;
   }
   // fluxes and their share of the RHS values at tau (RO: Omega2, RP: phi2)
   double2* RO = vals[0];
@@ -4151,6 +4163,7 @@ const char* lmvd_status_string(lmvd_status s) {
     case LMVD_EHIP: return "HIP error";
     case LMVD_EUNSUPPORTED: return "unsupported size";
     case LMVD_ENUMERIC: return "numerical failure (pivot)";
+    case LMVD_ENONFINITE: return "non-finite value in the substep's outputs";
   }
   return "unknown status";
 }
@@ -4179,6 +4192,33 @@ lmvd_status lmvd_sizes(lmvd_plan plan, size_t* se, size_t* ss, size_t* wb) {
   return LMVD_OK;
 }
 
+namespace lmvd {
+// non-finite scan of n doubles: one lane per wavefront that saw a NaN or an infinity sets the flag
+__global__ void __launch_bounds__(kThreads) k_nonfinite(const double* __restrict__ x, size_t n, unsigned* flag) {
+  bool bad = false;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (__any(bad) && (threadIdx.x % 64) == 0) atomicOr(flag, 1u);
+}
+__global__ void k_clear_flag(unsigned* flag) {
+  if (threadIdx.x == 0) flag[0] = 0u;
+}
+static lmvd_status scan_outputs(lmvd_plan_s* p, const lmvd_substep_args* a, hipStream_t s) {
+  const size_t nS = 2 * size_t(p->H.nn) * p->H.nl * p->H.n2, n2 = size_t(p->H.n2);
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, s, p->finite_flag);
+  const std::pair<const void*, size_t> f[] = {{a->z_out, nS}, {a->phi2_out, nS}, {a->omega2_out, nS},
+                                              {a->m1bar_out, n2}, {a->m3bar_out, n2}, {a->zt, nS}};
+  for (const auto& q : f)
+    if (q.first)
+      hipLaunchKernelGGL(k_nonfinite, dim3(1024), dim3(kThreads), 0, s, static_cast<const double*>(q.first),
+                         q.second, p->finite_flag);
+  unsigned h = 0;
+  if (hipMemcpyAsync(&h, p->finite_flag, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return LMVD_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return LMVD_EHIP;
+  return h ? LMVD_ENONFINITE : LMVD_OK;
+}
+}  // namespace lmvd
+
 lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* a, void* workspace, void* stream) {
   const lmvd_status ck = lmvd::check_substep_args(plan, a, workspace);
   if (ck != LMVD_OK) return ck;
@@ -4192,7 +4232,9 @@ lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* a, void* works
                        reinterpret_cast<const double2*>(static_cast<char*>(workspace) + plan->ws.off_mpar),
                        static_cast<double2*>(a->mc[0]), static_cast<double2*>(a->mc[2]));
   }
-  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+  if (hipGetLastError() != hipSuccess) return LMVD_EHIP;
+  if (plan->H.cfg.check_finite) return lmvd::scan_outputs(plan, a, s);
+  return LMVD_OK;
 }
 
 struct lmvd_graph_s {
@@ -4338,7 +4380,7 @@ lmvd_status lmvd_graph_create(const lmvd_plan* plans, const lmvd_substep_args* a
   const int dev = plans[0] ? plans[0]->device : 0;
   for (int i = 0; i < count; ++i) {
     lmvd_plan p = plans[i];
-    if (!p || p->device != dev || p->prof.cls >= 0) return LMVD_EINVAL;
+    if (!p || p->device != dev || p->prof.cls >= 0 || p->H.cfg.check_finite) return LMVD_EINVAL;
     for (int k = 0; k < nsub; ++k) {
       const lmvd_substep_args* a = &args[size_t(i) * nsub + k];
       const lmvd_status ck = lmvd::check_substep_args(p, a, workspaces[i]);

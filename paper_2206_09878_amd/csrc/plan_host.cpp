@@ -237,6 +237,7 @@ lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& H, std::string
   }
   if (cfg.kf < 0 || cfg.plane_batch < 0) { msg = "kf and plane_batch must be >= 0"; return LMVD_EINVAL; }
   if (cfg.rhoD_form != 0 && cfg.rhoD_form != 1) { msg = "rhoD_form must be 0 or 1"; return LMVD_EINVAL; }
+  if (cfg.check_finite != 0 && cfg.check_finite != 1) { msg = "check_finite must be 0 or 1"; return LMVD_EINVAL; }
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(cfg.mu_z[k]) || !std::isfinite(cfg.rhoD_z[k])) {
       msg = "transport-law coefficients must be finite";

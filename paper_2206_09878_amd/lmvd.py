@@ -34,6 +34,7 @@ class Config(ctypes.Structure):
         ("beta_n", ctypes.c_double), ("beta_p", ctypes.c_double),
         ("kf", ctypes.c_int32), ("plane_batch", ctypes.c_int32),
         ("mu_z", ctypes.c_double * 3), ("rhoD_z", ctypes.c_double * 3), ("rhoD_form", ctypes.c_int32),
+        ("check_finite", ctypes.c_int32),
     ]
 
 
@@ -106,14 +107,14 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def make_config(w, plane_batch: int = 0):
+def make_config(w, plane_batch: int = 0, check_finite: bool = False):
     """ctypes Config from a workload (paper_2206_09878_amd.workloads.Workload).
     The returned object keeps its breakpoint buffer alive."""
     bp = np.ascontiguousarray(w.breakpoints, dtype=np.float64)
     c = Config(w.n1, w.n3, w.n2, w.order, w.m1, w.m3, w.L1, w.L2, w.L3,
                bp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), w.dt, w.mu, w.rhoD, w.g,
                w.rho_l, w.rho_h, w.beta_n, w.beta_p, w.kf, plane_batch,
-               (ctypes.c_double * 3)(*w.mu_z), (ctypes.c_double * 3)(*w.rhoD_z), w.rhoD_form)
+               (ctypes.c_double * 3)(*w.mu_z), (ctypes.c_double * 3)(*w.rhoD_z), w.rhoD_form, int(check_finite))
     c._bp = bp
     return c
 
@@ -134,11 +135,11 @@ def host_tables(w):
 class Plan:
     """A plan plus its workspace on the current GPU."""
 
-    def __init__(self, w, plane_batch: int = 0):
+    def __init__(self, w, plane_batch: int = 0, check_finite: bool = False):
         import torch
         self.torch = torch
         self.w = w
-        self.cfg = make_config(w, plane_batch)
+        self.cfg = make_config(w, plane_batch, check_finite)
         h = ctypes.c_void_p()
         _check(library().lmvd_plan_create(ctypes.byref(self.cfg), ctypes.byref(h)), "lmvd_plan_create")
         self.handle = h

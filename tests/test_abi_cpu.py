@@ -33,6 +33,38 @@ def test_status_strings():
     lib = lmvd.library()
     assert lib.lmvd_status_string(0) == b"ok"
     assert b"invalid" in lib.lmvd_status_string(-1)
+    assert b"non-finite" in lib.lmvd_status_string(-6)
+
+
+def test_config_layout_matches_the_header(tmp_path):
+    """The ctypes mirror of lmvd_config has the C struct's size and field offsets (gcc, host only)."""
+    import subprocess
+    fields = [f[0] for f in lmvd.Config._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lmvd.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(lmvd_config));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(lmvd_config, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(lmvd.Config)
+    assert got[1:] == [getattr(lmvd.Config, f).offset for f in fields]
+
+
+@pytest.mark.parametrize("change", ["rhoD_form", "check_finite", "mu_z_nan", "rhoD_z_inf"])
+def test_plan_create_rejects_bad_transport_laws_and_flags(change):
+    cfg = lmvd.make_config(workload("small"))
+    if change == "rhoD_form":
+        cfg.rhoD_form = 2
+    elif change == "check_finite":
+        cfg.check_finite = 3
+    elif change == "mu_z_nan":
+        cfg.mu_z[1] = float("nan")
+    else:
+        cfg.rhoD_z[0] = float("inf")
+    h = ctypes.c_void_p()
+    assert lmvd.library().lmvd_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
 
 
 @pytest.mark.parametrize("name,n,n2", [("small", None, None), ("small", 16, 25), ("mixing128", 48, 65)])
