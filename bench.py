@@ -118,9 +118,6 @@ def bench_batch(args, count=64, nsub=4):
     from paper_2206_09878_amd.workloads import batch_workloads, make_inputs
     ws = batch_workloads(count)
     st = [Stepper(Plan(w), make_inputs(w, seed=w.extra["seed"], stage=0), stage=0) for w in ws]
-    t0 = time.perf_counter()
-    g = GraphBatch(st, nsub=nsub)
-    build_s = time.perf_counter() - t0
 
     def eager():
         for s in st:
@@ -135,6 +132,17 @@ def bench_batch(args, count=64, nsub=4):
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
+    # the graph with the default z tile, then with the tiles the graph autotuner picks (its tries
+    # advance the instances like warm-up launches)
+    t0 = time.perf_counter()
+    g = GraphBatch(st, nsub=nsub)
+    build_s = time.perf_counter() - t0
+    for _ in range(max(args.warmup, 1)):
+        g.launch()
+    t_default = timed(g.launch, args.steps)
+    t0 = time.perf_counter()
+    tiles, _ = g.autotune(launches=3)
+    tune_s = time.perf_counter() - t0
     for _ in range(max(args.warmup, 1)):
         g.launch()
         eager()
@@ -152,7 +160,10 @@ def bench_batch(args, count=64, nsub=4):
             "grid_point_substeps_per_s": pts / tg,
             "one_by_one": {"value": subs / te, "ms_per_step": 1e3 * te / args.steps,
                            "grid_point_substeps_per_s": pts / te},
-            "graph_speedup": te / tg, "graph_build_s": build_s}
+            "graph_speedup": te / tg, "graph_build_s": build_s,
+            "autotune": {"z_tile_divisors": {str(d): tiles.count(d) for d in sorted(set(tiles))},
+                         "tune_s": tune_s, "default_tile_value": subs / t_default,
+                         "speedup_over_default_tile": t_default / tg}}
 
 
 def cpu_baseline(full, n=128, n2=129):

@@ -205,6 +205,33 @@ lmvd_status lmvd_graph_destroy(lmvd_graph graph);
  * instance.  Both give the results of the plain path. */
 lmvd_status lmvd_graph_grouped(lmvd_graph graph, int32_t* grouped);
 
+/* ---- tile autotuner ----
+ * Chooses the tile of the register z-transform kernels of a plan with M3 < 768: T = M3/12 threads per
+ * z line and 256/(T D) lines per block, D in {1, 2, 4}.  Fewer lines per block leave fewer idle lanes
+ * when N1/2 is small.  With force = 0 it times the inverse and forward z transforms of three fields over
+ * the plan's plane batch for each D (a warm-up, then 5 repetitions, HIP events on the stream) on the
+ * caller's workspace, whose contents it overwrites, and keeps the fastest; force = 1, 2 or 4 sets D
+ * without timing.  Plans without such kernels (M3 = 768, or a size without a register plan) keep D = 1.
+ * zdiv (host) receives the choice; times_ms (host, optional, 3 doubles) the mean time of one repetition
+ * for D = 1, 2, 4 (-1 where not timed).  The choice holds for every later call on the plan, graphs
+ * captured afterwards included; results do not depend on it.  Synchronises the stream; not during
+ * graph capture or a profile (LMVD_EINVAL). */
+lmvd_status lmvd_autotune(lmvd_plan plan, void* workspace, void* stream, int32_t force, int32_t* zdiv,
+                          double* times_ms);
+
+/* The same tile choice made for a batch by timing the graph itself: instances run side by side in a
+ * graph, where a tile that is faster alone can be slower.  Takes the arguments of lmvd_graph_create
+ * (same rules) and a stream; sets D = 1 on every plan with a choice, then, one z-transform size at a
+ * time, tries D = 2 and 4 for all plans of that size and keeps a divisor that makes the graph at least
+ * 1 % faster.  Each try captures the graph, launches it once, times `launches` launches (1..100) with
+ * HIP events and destroys it, so every try ADVANCES EVERY INSTANCE by (1 + launches) * nsub substeps:
+ * call it where warm-up launches would go.  zdivs (host, optional, count entries) receives each plan's
+ * divisor, ms_per_launch (host, optional) the best time per launch.  Graphs captured afterwards use the
+ * choice.  Synchronises the stream. */
+lmvd_status lmvd_graph_autotune(const lmvd_plan* plans, const lmvd_substep_args* args, void* const* workspaces,
+                                int32_t count, int32_t nsub, void* stream, int32_t launches, int32_t* zdivs,
+                                double* ms_per_launch);
+
 /* ---- operator entry points (same conventions), one per stage of the path ----
  * They expose the steps of the substep individually for verification. */
 

@@ -609,11 +609,14 @@ LMVD_LINEPLAN(36, 3, 12, 3, 1, 1, 12)
 LMVD_LINEPLAN(24, 2, 12, 2, 1, 1, 12)
 #undef LMVD_LINEPLAN
 
-// lines per block and LDS line stride (doubles) of the z kernels (lines = l, lane-fastest)
-template <int N>
+// lines per block and LDS line stride (doubles) of the z kernels (lines = l, lane-fastest).  D divides
+// the block: LG = 256 / (T D) lines of T threads.  Fewer lines per block leave fewer idle lanes when the
+// plan has few l-lines (small N1); the tile autotuner picks D per plan by timing.
+template <int N, int D = 1>
 struct ZShape {
   static constexpr int T = LinePlan<N>::T;
-  static constexpr int LG = kThreads / T;
+  static constexpr int LG = kThreads / T / D;
+  static_assert(LG >= 1, "z tile divisor too large for this transform");
   static constexpr int BASE = N + N / LinePlan<N>::PAD;
   // 8 lines: stride = 2 mod 32 keeps two neighbouring threads of each of the
   // 8 lines on distinct banks; otherwise an odd stride
@@ -644,10 +647,10 @@ LMVD_XPLAN(48, 4, 12, 4, 1, 1, 12)
 // grid (ceil(nl/LG), planes, nin), block LG*T (line index lane-fastest).
 // EXACT: nn = 2N/3 - 1 (3/2 grid), so the zero-padded positions are known
 // at compile time.
-template <int N, bool EXACT>
+template <int N, bool EXACT, int D = 1>
 __device__ __forceinline__ void zinv_r_body(const DevPlan& P, const unsigned bx, const unsigned by, const unsigned bz, const EvalArgs& A, double2* __restrict__ zbuf, int j0, int pb) {
   using LP = LinePlan<N>;
-  using ZS = ZShape<N>;
+  using ZS = ZShape<N, D>;
   constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL;
   constexpr int NNX = 2 * N / 3 - 1, H3X = (NNX + 1) / 2, PADX = N - NNX;
   extern __shared__ double lds_d[];
@@ -688,16 +691,16 @@ __device__ __forceinline__ void zinv_r_body(const DevPlan& P, const unsigned bx,
       for (int r = 0; r < RL; ++r) out[size_t(tl + T * c + r * (N / RL)) * nl] = v[c * RL + r];
   }
 }
-template <int N, bool EXACT>
+template <int N, bool EXACT, int D>
 __global__ void __launch_bounds__(kThreads) k_zinv_r(DevPlan P, EvalArgs A, double2* __restrict__ zbuf, int j0, int pb) {
-  zinv_r_body<N, EXACT>(P, blockIdx.x, blockIdx.y, blockIdx.z, A, zbuf, j0, pb);
+  zinv_r_body<N, EXACT, D>(P, blockIdx.x, blockIdx.y, blockIdx.z, A, zbuf, j0, pb);
 }
 
 // forward z-FFT of size N = m3 and truncation to the retained n.
-template <int N>
+template <int N, int D = 1>
 __device__ __forceinline__ void zfwd_r_body(const DevPlan& P, const unsigned bx, const unsigned by, const unsigned bz, const double2* __restrict__ obuf, const OutPtrs& V, int j0, int pb) {
   using LP = LinePlan<N>;
-  using ZS = ZShape<N>;
+  using ZS = ZShape<N, D>;
   constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL;
   extern __shared__ double lds_d[];
   const int tid = threadIdx.x;
@@ -722,9 +725,9 @@ __device__ __forceinline__ void zfwd_r_body(const DevPlan& P, const unsigned bx,
       }
   }
 }
-template <int N>
+template <int N, int D>
 __global__ void __launch_bounds__(kThreads) k_zfwd_r(DevPlan P, const double2* __restrict__ obuf, OutPtrs V, int j0, int pb) {
-  zfwd_r_body<N>(P, blockIdx.x, blockIdx.y, blockIdx.z, obuf, V, j0, pb);
+  zfwd_r_body<N, D>(P, blockIdx.x, blockIdx.y, blockIdx.z, obuf, V, j0, pb);
 }
 
 // z kernels with one 64-thread group per line (12 points per thread) and 8
@@ -894,12 +897,12 @@ __global__ void __launch_bounds__(kZWThreads) k_zfilt_w(DevPlan P, const double2
                                                        const double2* __restrict__ add, double2* __restrict__ out) {
   zfilt_w_body<N>(P, blockIdx.x, blockIdx.y, in, add, out);
 }
-template <int N>
+template <int N, int D = 1>
 __device__ __forceinline__ void zfilt_r_body(const DevPlan& P, const unsigned bx, const unsigned by,
                                              const double2* __restrict__ in, const double2* __restrict__ add,
                                              double2* __restrict__ out) {
   using LP = LinePlan<N>;
-  using ZS = ZShape<N>;
+  using ZS = ZShape<N, D>;
   constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL, EL = E / RL;
   extern __shared__ double lds_d[];
   const int tid = threadIdx.x;
@@ -932,10 +935,10 @@ __device__ __forceinline__ void zfilt_r_body(const DevPlan& P, const unsigned bx
       }
   }
 }
-template <int N>
+template <int N, int D>
 __global__ void __launch_bounds__(kThreads) k_zfilt_r(DevPlan P, const double2* __restrict__ in,
                                                      const double2* __restrict__ add, double2* __restrict__ out) {
-  zfilt_r_body<N>(P, blockIdx.x, blockIdx.y, in, add, out);
+  zfilt_r_body<N, D>(P, blockIdx.x, blockIdx.y, in, add, out);
 }
 
 // Wall planes of the filtered iterate: the Neumann projection's values at the
@@ -2974,34 +2977,34 @@ struct JobRhsMean : ColumnJob {
 };
 
 // plane jobs (register-FFT kernels; block shape fixed by the transform size)
-template <int N, bool EXACT>
+template <int N, bool EXACT, int D = 1>
 struct JobZinvR {
-  static constexpr int kBound = kThreads, kBlock = ZShape<N>::LG * ZShape<N>::T, kMinBlocks = 0;
+  static constexpr int kBound = kThreads, kBlock = ZShape<N, D>::LG * ZShape<N, D>::T, kMinBlocks = 0;
   struct Args {
     EvalArgs A;
     double2* zbuf;
     int j0, pb;
   };
   __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned bz, const Args& a) {
-    zinv_r_body<N, EXACT>(P, bx, by, bz, a.A, a.zbuf, a.j0, a.pb);
+    zinv_r_body<N, EXACT, D>(P, bx, by, bz, a.A, a.zbuf, a.j0, a.pb);
   }
   static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
-    hipLaunchKernelGGL((k_zinv_r<N, EXACT>), g, dim3(kBlock), lds, s, P, a.A, a.zbuf, a.j0, a.pb);
+    hipLaunchKernelGGL((k_zinv_r<N, EXACT, D>), g, dim3(kBlock), lds, s, P, a.A, a.zbuf, a.j0, a.pb);
   }
 };
-template <int N>
+template <int N, int D = 1>
 struct JobZfwdR {
-  static constexpr int kBound = kThreads, kBlock = ZShape<N>::LG * ZShape<N>::T, kMinBlocks = 0;
+  static constexpr int kBound = kThreads, kBlock = ZShape<N, D>::LG * ZShape<N, D>::T, kMinBlocks = 0;
   struct Args {
     const double2* obuf;
     OutPtrs V;
     int j0, pb;
   };
   __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned bz, const Args& a) {
-    zfwd_r_body<N>(P, bx, by, bz, a.obuf, a.V, a.j0, a.pb);
+    zfwd_r_body<N, D>(P, bx, by, bz, a.obuf, a.V, a.j0, a.pb);
   }
   static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
-    hipLaunchKernelGGL(k_zfwd_r<N>, g, dim3(kBlock), lds, s, P, a.obuf, a.V, a.j0, a.pb);
+    hipLaunchKernelGGL((k_zfwd_r<N, D>), g, dim3(kBlock), lds, s, P, a.obuf, a.V, a.j0, a.pb);
   }
 };
 template <int N, bool EXACT>
@@ -3081,15 +3084,15 @@ struct JobZfiltW {
     hipLaunchKernelGGL(k_zfilt_w<N>, g, dim3(kBlock), lds, s, P, a.in, a.add, a.out);
   }
 };
-template <int N>
+template <int N, int D = 1>
 struct JobZfiltR {
-  static constexpr int kBound = kThreads, kBlock = ZShape<N>::LG * ZShape<N>::T, kMinBlocks = 0;
+  static constexpr int kBound = kThreads, kBlock = ZShape<N, D>::LG * ZShape<N, D>::T, kMinBlocks = 0;
   using Args = typename JobZfiltW<N>::Args;
   __device__ static void run(const DevPlan& P, unsigned bx, unsigned by, unsigned, const Args& a) {
-    zfilt_r_body<N>(P, bx, by, a.in, a.add, a.out);
+    zfilt_r_body<N, D>(P, bx, by, a.in, a.add, a.out);
   }
   static void launch(dim3 g, size_t lds, hipStream_t s, const DevPlan& P, const Args& a) {
-    hipLaunchKernelGGL(k_zfilt_r<N>, g, dim3(kBlock), lds, s, P, a.in, a.add, a.out);
+    hipLaunchKernelGGL((k_zfilt_r<N, D>), g, dim3(kBlock), lds, s, P, a.in, a.add, a.out);
   }
 };
 struct JobWall : ColumnJob {
@@ -3183,6 +3186,7 @@ struct lmvd_plan_s {
   bool fac_ready = false;
   int fac_la = 7, fac_ua = 7;  // instantiated band of the factor kernels
   unsigned* finite_flag = nullptr;  // device word of the non-finite scan
+  int zdiv = 1;     // z tile divisor of the register z kernels below 768 points (lmvd_autotune)
 };
 
 namespace lmvd {
@@ -3578,6 +3582,14 @@ static EvalIn ev(const void* a, int kind, int ma = MU_ONE, const void* b = nullp
   return e;
 }
 
+// z tile divisor (1, 2 or 4; anything else is 1) as a compile-time constant
+template <typename F>
+static void ztile_dispatch(int zdiv, F&& f) {
+  if (zdiv == 4) f(std::integral_constant<int, 4>{});
+  else if (zdiv == 2) f(std::integral_constant<int, 2>{});
+  else f(std::integral_constant<int, 1>{});
+}
+
 // register-FFT launches for the specialised sizes
 template <int N>
 static void launch_zinv_t(const Ctx& c, const EvalArgs& A, double2* zbuf, int j0, int nb, int nin) {
@@ -3592,11 +3604,15 @@ static void launch_zinv_t(const Ctx& c, const EvalArgs& A, double2* zbuf, int j0
     else col<JobZinvW<N, false>>(c, g, lds, {A, zbuf, j0, p->pb});
     return;
   }
-  using ZS = ZShape<N>;
-  const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nin);
-  const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
-  if (exact) col<JobZinvR<N, true>>(c, g, lds, {A, zbuf, j0, p->pb});
-  else col<JobZinvR<N, false>>(c, g, lds, {A, zbuf, j0, p->pb});
+  auto go = [&](auto dv) {
+    constexpr int D = decltype(dv)::value;
+    using ZS = ZShape<N, D>;
+    const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nin);
+    const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
+    if (exact) col<JobZinvR<N, true, D>>(c, g, lds, {A, zbuf, j0, p->pb});
+    else col<JobZinvR<N, false, D>>(c, g, lds, {A, zbuf, j0, p->pb});
+  };
+  ztile_dispatch(p->zdiv, go);
 }
 template <int N>
 static void launch_zfwd_t(const Ctx& c, const double2* obuf, const OutPtrs& V, int j0, int nb, int nout) {
@@ -3609,10 +3625,14 @@ static void launch_zfwd_t(const Ctx& c, const double2* obuf, const OutPtrs& V, i
     col<JobZfwdW<N>>(c, g, lds, {obuf, V, j0, p->pb});
     return;
   }
-  using ZS = ZShape<N>;
-  const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nout);
-  const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
-  col<JobZfwdR<N>>(c, g, lds, {obuf, V, j0, p->pb});
+  auto go = [&](auto dv) {
+    constexpr int D = decltype(dv)::value;
+    using ZS = ZShape<N, D>;
+    const dim3 g((p->H.nl + ZS::LG - 1) / ZS::LG, nb, nout);
+    const size_t lds = size_t(ZS::LG) * ZS::STRIDE * sizeof(double);
+    col<JobZfwdR<N, D>>(c, g, lds, {obuf, V, j0, p->pb});
+  };
+  ztile_dispatch(p->zdiv, go);
 }
 template <int PH, int N>
 static void launch_xpass_t(const Ctx& c, const double2* zbuf, double2* obuf, double* phys_out,
@@ -3798,8 +3818,12 @@ static void zfilter(const Ctx& c, const double2* in, const double2* add, double2
     col<JobZfiltW<768>>(c, dim3((H.nl + ZP::LG - 1) / ZP::LG, n2), lds, {in, add, out});
   } else {
 #define LMVD_ZF(N)                                                                                      \
-  col<JobZfiltR<N>>(c, dim3((H.nl + ZShape<N>::LG - 1) / ZShape<N>::LG, n2),                           \
-                    size_t(ZShape<N>::LG) * ZShape<N>::STRIDE * sizeof(double), {in, add, out})
+  ztile_dispatch(p->zdiv, [&](auto dv) {                                                              \
+    constexpr int D = decltype(dv)::value;                                                            \
+    using ZS = ZShape<N, D>;                                                                          \
+    col<JobZfiltR<N, D>>(c, dim3((H.nl + ZS::LG - 1) / ZS::LG, n2), size_t(ZS::LG) * ZS::STRIDE * sizeof(double), \
+                         {in, add, out});                                                             \
+  })
     switch (M3) {
       case 192: LMVD_ZF(192); break;
       case 144: LMVD_ZF(144); break;
@@ -4441,6 +4465,151 @@ lmvd_status lmvd_graph_destroy(lmvd_graph g) {
   if (g->arena) (void)hipFree(g->arena);
   delete g;
   return LMVD_OK;
+}
+
+lmvd_status lmvd_graph_autotune(const lmvd_plan* plans, const lmvd_substep_args* args, void* const* workspaces,
+                                int32_t count, int32_t nsub, void* stream, int32_t launches, int32_t* zdivs,
+                                double* ms_per_launch) {
+  if (!plans || !args || !workspaces || count < 1 || nsub < 1 || launches < 1 || launches > 100)
+    return LMVD_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (!plans[i]) return LMVD_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(plans[0]->device) != hipSuccess) return LMVD_EHIP;
+  auto tileable = [](lmvd_plan p) { return p->use_reg && zreg_size(p->H.cfg.m3) && p->H.cfg.m3 != 768; };
+  std::vector<int> sizes;
+  for (int i = 0; i < count; ++i) {
+    if (!tileable(plans[i])) continue;
+    plans[i]->zdiv = 1;
+    if (std::find(sizes.begin(), sizes.end(), plans[i]->H.cfg.m3) == sizes.end()) sizes.push_back(plans[i]->H.cfg.m3);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return LMVD_EHIP;
+  }
+  // one measurement: capture the graph with the current tiles, one warm-up launch, then `launches` timed
+  auto measure = [&](double& ms) -> lmvd_status {
+    lmvd_graph g = nullptr;
+    lmvd_status st = lmvd_graph_create(plans, args, workspaces, count, nsub, &g);
+    if (st != LMVD_OK) return st;
+    st = lmvd_graph_launch(g, stream);
+    if (st == LMVD_OK && hipEventRecord(e0, s) != hipSuccess) st = LMVD_EHIP;
+    for (int r = 0; r < launches && st == LMVD_OK; ++r) st = lmvd_graph_launch(g, stream);
+    float t = 0.0f;
+    if (st == LMVD_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+      st = LMVD_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess && st == LMVD_OK) st = LMVD_EHIP;
+    (void)lmvd_graph_destroy(g);
+    ms = double(t) / launches;
+    return st;
+  };
+  double best = 0.0;
+  lmvd_status st = measure(best);
+  // coordinate descent over the transform sizes present: one divisor per size, kept when it is at least
+  // 1 % faster than the best so far
+  for (size_t k = 0; k < sizes.size() && st == LMVD_OK; ++k) {
+    int cur = 1;
+    for (int d : {2, 4}) {
+      for (int i = 0; i < count; ++i)
+        if (tileable(plans[i]) && plans[i]->H.cfg.m3 == sizes[k]) plans[i]->zdiv = d;
+      double t = 0.0;
+      st = measure(t);
+      if (st != LMVD_OK) break;
+      if (t < 0.99 * best) {
+        best = t;
+        cur = d;
+      }
+    }
+    for (int i = 0; i < count; ++i)
+      if (tileable(plans[i]) && plans[i]->H.cfg.m3 == sizes[k]) plans[i]->zdiv = cur;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (zdivs)
+    for (int i = 0; i < count; ++i) zdivs[i] = plans[i]->zdiv;
+  if (ms_per_launch) *ms_per_launch = best;
+  return st;
+}
+
+lmvd_status lmvd_autotune(lmvd_plan plan, void* workspace, void* stream, int32_t force, int32_t* zdiv,
+                          double* times_ms) {
+  if (!plan || !workspace || !zdiv) return LMVD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
+  if (force != 0 && force != 1 && force != 2 && force != 4) return LMVD_EINVAL;
+  if (plan->prof.cls >= 0) return LMVD_EINVAL;
+  if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
+  const HostTables& H = plan->H;
+  const int M3 = H.cfg.m3;
+  const int cand[3] = {1, 2, 4};
+  if (times_ms)
+    for (int i = 0; i < 3; ++i) times_ms[i] = -1.0;
+  // only the register z kernels below 768 points have a tile choice
+  if (!(plan->use_reg && zreg_size(M3) && M3 != 768)) {
+    plan->zdiv = 1;
+    *zdiv = 1;
+    return LMVD_OK;
+  }
+  if (force) {
+    plan->zdiv = force;
+    *zdiv = force;
+    return LMVD_OK;
+  }
+  // time the inverse and forward z transforms of three fields over the plan's plane batch, on the
+  // workspace's own value and staging buffers (their contents do not matter for the timing)
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ctx c{plan, static_cast<char*>(workspace), s};
+  const Workspace& W = plan->ws;
+  EvalArgs A{};
+  OutPtrs V{};
+  for (int f = 0; f < 3; ++f) {
+    A.in[f] = ev(c.at<double2>(W.off_vals[f]), EV_IDENT);
+    A.in[f].slot = f;
+    V.v[f] = c.at<double2>(W.off_vals[3 + f]);
+  }
+  double2* zbuf = c.at<double2>(W.off_zbuf);
+  double2* obuf = c.at<double2>(W.off_obuf);
+  const int nb = std::min(plan->pb, H.n2);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return LMVD_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return LMVD_EHIP;
+  }
+  const int saved = plan->zdiv;
+  int best = 1;
+  float best_ms = 0.0f;
+  lmvd_status st = LMVD_OK;
+  for (int i = 0; i < 3 && st == LMVD_OK; ++i) {
+    plan->zdiv = cand[i];
+    auto pass = [&]() {
+#define CALLZ(N) launch_zinv_t<N>(c, A, zbuf, 0, nb, 3)
+      LMVD_ZSWITCH(M3, CALLZ)
+#undef CALLZ
+#define CALLF(N) launch_zfwd_t<N>(c, obuf, V, 0, nb, 3)
+      LMVD_ZSWITCH(M3, CALLF)
+#undef CALLF
+    };
+    pass();  // warm-up
+    float ms = 0.0f;
+    if (hipEventRecord(e0, s) != hipSuccess) st = LMVD_EHIP;
+    for (int r = 0; r < 5 && st == LMVD_OK; ++r) pass();
+    if (st == LMVD_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = LMVD_EHIP;
+    if (st == LMVD_OK && hipGetLastError() != hipSuccess) st = LMVD_EHIP;
+    if (times_ms) times_ms[i] = ms / 5.0;
+    if (i == 0 || ms < best_ms) {
+      best = cand[i];
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan->zdiv = (st == LMVD_OK) ? best : saved;
+  *zdiv = plan->zdiv;
+  return st;
 }
 
 lmvd_status lmvd_to_physical(lmvd_plan plan, const void* values, double* phys, void* workspace, void* stream) {

@@ -57,7 +57,8 @@ class SubstepArgs(ctypes.Structure):
 EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_sizes", "lmvd_substep",
            "lmvd_to_physical", "lmvd_to_spectral", "lmvd_project", "lmvd_evaluate", "lmvd_md", "lmvd_mc",
            "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop", "lmvd_graph_create",
-           "lmvd_graph_launch", "lmvd_graph_destroy", "lmvd_graph_grouped"]
+           "lmvd_graph_launch", "lmvd_graph_destroy", "lmvd_graph_grouped", "lmvd_autotune",
+           "lmvd_graph_autotune"]
 
 
 def library():
@@ -90,6 +91,9 @@ def library():
         lib.lmvd_graph_launch.argtypes = [vp, vp]
         lib.lmvd_graph_destroy.argtypes = [vp]
         lib.lmvd_graph_grouped.argtypes = [vp, ctypes.POINTER(i32)]
+        lib.lmvd_autotune.argtypes = [vp, vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+        lib.lmvd_graph_autotune.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(SubstepArgs), ctypes.POINTER(vp), i32,
+                                            i32, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
         for name in EXPORTS:
             if name != "lmvd_status_string":
                 getattr(lib, name).restype = ctypes.c_int
@@ -159,6 +163,15 @@ class Plan:
                 self.handle = None
         except Exception:
             pass
+
+    def autotune(self, force: int = 0):
+        """Pick the z-transform tile by timing (force = 0) or set it (1, 2, 4); see lmvd_autotune.
+        Returns (divisor, per-candidate ms or -1)."""
+        z = ctypes.c_int32()
+        t = (ctypes.c_double * 3)()
+        _check(library().lmvd_autotune(self.handle, _ptr(self.ws), self._stream(), force, ctypes.byref(z), t),
+               "lmvd_autotune")
+        return z.value, list(t)
 
     # -- helpers ---------------------------------------------------------------
     def _stream(self):
@@ -353,6 +366,25 @@ class GraphBatch:
         _check(library().lmvd_graph_create(plans, args, ws, n, nsub, ctypes.byref(h)), "lmvd_graph_create")
         self.handle = h
         self.nsub = nsub
+        self._args, self._plans, self._ws = args, plans, ws
+
+    def autotune(self, launches: int = 3):
+        """Pick the z tiles by timing this graph (lmvd_graph_autotune) and capture it again with them.
+        Advances every instance like warm-up launches.  Returns (divisor per instance, ms per launch)."""
+        n = len(self.steppers)
+        torch = self.steppers[0].p.torch
+        z = (ctypes.c_int32 * n)()
+        ms = ctypes.c_double()
+        library().lmvd_graph_destroy(self.handle)
+        self.handle = None
+        _check(library().lmvd_graph_autotune(self._plans, self._args, self._ws, n, self.nsub,
+                                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), launches, z,
+                                             ctypes.byref(ms)), "lmvd_graph_autotune")
+        h = ctypes.c_void_p()
+        _check(library().lmvd_graph_create(self._plans, self._args, self._ws, n, self.nsub, ctypes.byref(h)),
+               "lmvd_graph_create")
+        self.handle = h
+        return list(z), ms.value
 
     @property
     def grouped(self) -> bool:
