@@ -260,6 +260,38 @@ lmvd_status lmvd_md(lmvd_plan plan, const void* phi2, const void* omega2,
 lmvd_status lmvd_mc(lmvd_plan plan, const void* rhot, void* m1, void* m2, void* m3,
                     void* workspace, void* stream);
 
+/* Steps 4 and 5 of the substep alone (Algorithm time_advanceDNS): the right-hand sides of Omega2, phi2
+ * (eqs. om and phi, with the body force -rho g delta_i2) and of the plane means (eq. mean_m1m3) for a
+ * given z (S-field, B) and momentum m = (m1 in B, m2 in B*, m3 in B): values at the Greville points,
+ * u = m/rho, rho and C_ij = -m_i m_j/rho on the 3/2 grid, u_hat, T_ij = C_ij + tau_ij (with mu(z) when
+ * the plan has it) projected, N_i, and the Dirichlet (Omega2, phi2) and Neumann (means) projections.
+ * The same kernels as lmvd_substep, without the RK2 update.  Outputs: rhs_phi2, rhs_omega2 (S-fields,
+ * (0,0) mode zero), rhs_m1, rhs_m3 ([n2]); all device pointers, 16-byte aligned; workspace as for
+ * lmvd_substep (256-byte aligned, contents overwritten).  Asynchronous. */
+lmvd_status lmvd_rhs(lmvd_plan plan, const void* z, const void* m1, const void* m2, const void* m3, void* rhs_phi2,
+                     void* rhs_omega2, double* rhs_m1, double* rhs_m3, void* workspace, void* stream);
+
+/* ---- adjoints of the linear operators (for gradients through the substep's building blocks) ----
+ * Transposes in the real inner products <a, b> = sum Re(conj(a) b) over every stored entry of an
+ * S-field and <f, g> = sum f g over a physical field, so that <A x, y> = <x, A^T y>.  With them the
+ * operators can sit behind automatic differentiation (the binding's autograd module).
+ *
+ * lmvd_to_physical_adjoint: transpose of lmvd_to_physical (eq. disc_f on the 3/2 grid) on S-fields
+ * with a Hermitian l = 0 column (the inputs lmvd_to_physical accepts; its output has one too): the
+ * forward transform of phys times M1 M3, and times 2 for l > 0 (the real field takes c_l with its
+ * conjugate partner at -l).  phys [n2][M3][M1] in, values out
+ * (S-field); workspace as for lmvd_to_spectral.
+ * lmvd_evaluate_adjoint: E_d^T (or F_0^T with star = 1): values at tau (n2 rows) in, coefficients out
+ * (n2 rows, n2 + 1 with star); values and coeffs must not alias.
+ * lmvd_project_adjoint: transpose of lmvd_project for the same kind: R A^{-T} with A = LU the kind's
+ * collocation matrix (App. C) and R the end-row replacement (kinds 1, 2); coeffs in, values out,
+ * not aliased.  All device pointers; asynchronous. */
+lmvd_status lmvd_to_physical_adjoint(lmvd_plan plan, const double* phys, void* values, void* workspace,
+                                     void* stream);
+lmvd_status lmvd_evaluate_adjoint(lmvd_plan plan, int32_t deriv, int32_t star, const void* values, void* coeffs,
+                                  void* stream);
+lmvd_status lmvd_project_adjoint(lmvd_plan plan, int32_t kind, const void* coeffs, void* values, void* stream);
+
 /* Timing hook for measurements: while active, every launch of one kernel
  * class is bracketed by two HIP events recorded on the stream it is launched
  * on.  Classes (one kernel each):

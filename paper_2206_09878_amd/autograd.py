@@ -1,0 +1,63 @@
+"""Automatic differentiation through the linear building blocks of the substep.
+
+Each operator is a torch.autograd.Function whose forward is the library's
+operator and whose backward is its transpose (lmvd_*_adjoint), so gradients of
+real losses follow PyTorch's convention for complex inputs (dL/dRe + i dL/dIm).
+
+    from paper_2206_09878_amd.autograd import to_physical, evaluate, project
+    loss = (to_physical(plan, evaluate(plan, 0, project(plan, 0, v))) * w).sum()
+    loss.backward()          # v.grad through P^T, E_0^T and the transposed transform
+
+The operators are linear, so their backward needs no saved state.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class _ToPhysical(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, values):
+        ctx.plan = plan
+        return plan.to_physical(values.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return None, ctx.plan.to_physical_adjoint(g.contiguous())
+
+
+class _Evaluate(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, deriv, star, coeffs):
+        ctx.plan, ctx.deriv, ctx.star = plan, deriv, star
+        return plan.evaluate(deriv, coeffs.contiguous(), star=star)
+
+    @staticmethod
+    def backward(ctx, g):
+        return None, None, None, ctx.plan.evaluate_adjoint(ctx.deriv, g.contiguous(), star=ctx.star)
+
+
+class _Project(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, kind, values):
+        ctx.plan, ctx.kind = plan, kind
+        return plan.project(kind, values.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return None, None, ctx.plan.project_adjoint(ctx.kind, g.contiguous())
+
+
+def to_physical(plan, values):
+    """Values at the Greville points (S-field) -> physical field on the 3/2 grid, differentiable."""
+    return _ToPhysical.apply(plan, values)
+
+
+def evaluate(plan, deriv, coeffs, star=False):
+    """E_deriv (or F_0 with star) applied to B (B*) coefficients, differentiable."""
+    return _Evaluate.apply(plan, deriv, star, coeffs)
+
+
+def project(plan, kind, values):
+    """Values -> coefficients (kind 0 plain, 1 Dirichlet, 2 Neumann rows), differentiable."""
+    return _Project.apply(plan, kind, values)

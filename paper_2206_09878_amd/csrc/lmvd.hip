@@ -2699,6 +2699,7 @@ __device__ __forceinline__ void rhs_fluct_body(const DevPlan& P, const unsigned 
     ro[0] = xo;
     if (rphi_out) rphi_out[e] = xp;
     if (rom_out) rom_out[e] = xo;
+    if (stage > 1) continue;  // right-hand sides only
     const double2 p0 = phi[e], o0 = om[e];
     if (stage == 0) {
       phi_out[e] = fma2(0.5 * P.dt, xp, p0);
@@ -2785,7 +2786,7 @@ __device__ __forceinline__ void rhs_mean_body(const DevPlan& P, const unsigned b
     const double* rprev = comp == 0 ? r1p : r3p;
     double* mo = comp == 0 ? m1o : m3o;
     if (ro) ro[i] = x;
-    mo[i] = (stage == 0) ? m[i] + 0.5 * P.dt * x : m[i] + P.dt * (x - 0.5 * rprev[i]);
+    if (stage <= 1) mo[i] = (stage == 0) ? m[i] + 0.5 * P.dt * x : m[i] + P.dt * (x - 0.5 * rprev[i]);
   }
 }
 __global__ void __launch_bounds__(256) k_rhs_mean(DevPlan P, const double2* __restrict__ T12,
@@ -3142,6 +3143,95 @@ __global__ void k_evaluate(DevPlan P, int kind, const double2* __restrict__ src,
   const int j = int(e / ncol);
   const size_t col = e - size_t(j) * ncol;
   dst[e] = eval_at(P, kind, src, j, col, ncol, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// adjoints (transposes in the real inner products <a, b> = sum Re(conj(a) b) of S-fields and
+// sum f g of physical fields) of evaluation, projection and the inverse transform
+
+// E_d^T per column: values at tau (n2 rows) -> coefficients (n2 rows, n2 + 1 for F0); the rows a value
+// row reaches start at a nondecreasing position, so finished rows leave a register window in order
+__global__ void __launch_bounds__(kThreads) k_evaluate_t(DevPlan P, int kind, const double2* __restrict__ src,
+                                                        double2* __restrict__ dst) {
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int n2 = P.n2, rows = (kind == EV_F0) ? n2 + 1 : n2;
+  double2 acc[kMaxW];
+#pragma unroll
+  for (int q = 0; q < kMaxW; ++q) acc[q] = zero2();
+  int base = 0;
+  for (int j = 0; j < n2; ++j) {
+    const int lo = P.ev_lo[kind * n2 + j];
+    while (base < lo) {
+      if (base < rows) dst[size_t(base) * ncol + c] = acc[0];
+#pragma unroll
+      for (int q = 0; q < kMaxW - 1; ++q) acc[q] = acc[q + 1];
+      acc[kMaxW - 1] = zero2();
+      ++base;
+    }
+    const auto w = P.ev_w + (size_t(kind) * n2 + j) * kMaxW;
+    const double2 v = src[size_t(j) * ncol + c];
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q)
+      if (lo + q < rows) acc[q] = fma2(w[q], v, acc[q]);
+  }
+  while (base < rows) {
+    dst[size_t(base) * ncol + c] = acc[0];
+#pragma unroll
+    for (int q = 0; q < kMaxW - 1; ++q) acc[q] = acc[q + 1];
+    acc[kMaxW - 1] = zero2();
+    ++base;
+  }
+}
+
+// (A^{-1} R)^T = R A^{-T} per column, A = L U of the projection `kind`: U^T z = y ascending, L^T x = z
+// descending (x in out), then the end rows zeroed for the Dirichlet / Neumann kinds
+__global__ void __launch_bounds__(kThreads) k_project_t(DevPlan P, int kind, const double2* __restrict__ in,
+                                                       double2* __restrict__ out) {
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int n2 = P.n2;
+  const auto L = P.lu_l + size_t(kind) * n2 * kMaxBand;
+  const auto U = P.lu_u + size_t(kind) * n2 * (kMaxBand + 1);
+  const auto Ui = P.lu_uinv + size_t(kind) * n2;
+  double2 ring[kMaxBand];
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+  for (int i = 0; i < n2; ++i) {  // ring[q] = z_{i-1-q}; U_{i-1-q, i} is entry q+1 of row i-1-q
+    double2 b = in[size_t(i) * ncol + c];
+#pragma unroll
+    for (int q = 0; q < kMaxBand; ++q)
+      if (i - 1 - q >= 0) b = fma2(-U[(i - 1 - q) * (kMaxBand + 1) + q + 1], ring[q], b);
+    const double2 z = cscale(b, Ui[i]);
+#pragma unroll
+    for (int q = kMaxBand - 1; q > 0; --q) ring[q] = ring[q - 1];
+    ring[0] = z;
+    out[size_t(i) * ncol + c] = z;
+  }
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+  for (int i = n2 - 1; i >= 0; --i) {  // ring[m] = x_{i+1+m}; L_{i+1+m, i} is multiplier m of row i+1+m
+    double2 x = out[size_t(i) * ncol + c];
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m)
+      if (i + 1 + m < n2) x = fma2(-L[(i + 1 + m) * kMaxBand + m], ring[m], x);
+#pragma unroll
+    for (int m = kMaxBand - 1; m > 0; --m) ring[m] = ring[m - 1];
+    ring[0] = x;
+    out[size_t(i) * ncol + c] = (kind != 0 && (i == 0 || i == n2 - 1)) ? zero2() : x;
+  }
+}
+
+// the inverse transform's transpose from the forward one: times M1 M3, and 2 for l > 0 (a real field
+// takes c_l and its conjugate partner -l; the l = 0 column enters through its real part)
+__global__ void __launch_bounds__(kThreads) k_scale_modes(DevPlan P, double2* __restrict__ v) {
+  const size_t ncol = size_t(P.nn) * P.nl;
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= ncol * P.n2) return;
+  const int l = int(e % size_t(P.nl));
+  v[e] = cscale(v[e], double(P.m1) * double(P.m3) * (l == 0 ? 1.0 : 2.0));
 }
 
 // ---------------------------------------------------------------------------
@@ -3844,6 +3934,131 @@ static bool var_rhod(const lmvd_config& c) {
   return c.rhoD_form != 0 || c.rhoD_z[0] != 0.0 || c.rhoD_z[1] != 0.0 || c.rhoD_z[2] != 0.0;
 }
 
+// Steps 4 and 5 of the substep (Algorithm time_advanceDNS), shared by lmvd_substep and lmvd_rhs: from the
+// momentum values at tau (vm1, vm3 from B, vm2 from B*) and the z values (vz0; with zres, z is still in
+// zbuf slot 6 from the R_z phase), u = m/rho, rho and C_ij = -m_i m_j/rho on the physical grid, u_hat by
+// interpolation, T_ij = C_ij + tau_ij projected with the RHS of Omega2 and phi2 emitted at tau (eqs. om,
+// phi with the body force), the Dirichlet / Neumann projections of the RHS (eq. mean_m1m3 for the means)
+// and the RK2 update of phi2, Omega2 and the means (a->stage 0 or 1; 2: right-hand sides only).
+static lmvd_status rhs_phase(const Ctx& c, const lmvd_substep_args* a, const double2* vz0, const double2* vm1,
+                             const double2* vm2, const double2* vm3, bool zres) {
+  lmvd_plan_s* p = c.p;
+  const HostTables& H = p->H;
+  const Workspace& W = p->ws;
+  hipStream_t s = c.s;
+  const size_t ncol = ncols(p);
+  const size_t nB = ncol * H.n2;
+  const bool xr = p->use_reg && xreg_size(H.cfg.m1, H.nl);
+  double2* vals[kMaxOut];
+  for (int g = 0; g < kMaxOut; ++g) vals[g] = c.at<double2>(W.off_vals[g]);
+  double2* u[3];
+  for (int i = 0; i < 3; ++i) u[i] = c.at<double2>(W.off_u[i]);
+  double2* T[6];
+  for (int i = 0; i < 6; ++i) T[i] = c.at<double2>(W.off_T[i]);
+  double2* rhov = c.at<double2>(W.off_rhov);
+  double2* vz1 = c.at<double2>(W.off_vz1);
+  double2* vzl = c.at<double2>(W.off_vzl);
+  double2* vz3 = c.at<double2>(W.off_vz3);
+  double2* vmd1 = c.at<double2>(W.off_vmd1);
+  double2* vmd3 = c.at<double2>(W.off_vmd3);
+  double2* vc2d = c.at<double2>(W.off_vc2d);
+  const double2* phi2 = static_cast<const double2*>(a->phi2);
+  const double2* om2 = static_cast<const double2*>(a->omega2);
+  lmvd_status st;
+  double2* cv[6] = {vals[4], vals[5], vals[6], vals[7], vals[8], vals[9]};
+  const std::vector<double2*> vel_out{vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]};
+  if (zres) {  // z still in zbuf slot 6
+    st = plane_phase<PH_VEL>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)}, vel_out);
+  } else if (xr) {
+    EvalIn zin = ev(vz0, EV_IDENT);
+    zin.slot = 6;
+    st = plane_phase<PH_VEL>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT), zin}, vel_out);
+  } else {
+    st = plane_phase<PH_VEL>(c, {ev(vz0, EV_IDENT), ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
+                             vel_out);
+  }
+  if (st != LMVD_OK) return st;
+  {
+    const int n = int(ncol);
+    ProfScope ps(p, KC_PROJ, s, 3 * 4.0 * 16.0 * nB);
+    col<JobProj3>(c, dim3((n + kThreads - 1) / kThreads, 3), 0, {0, ProjBatch{{vals[0], vals[1], vals[2]}, {u[0], u[1],
+                  u[2]}}, n});
+  }
+  const bool narrow = H.p <= 8 && H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
+  const bool varmu = var_mu(H.cfg);
+  if (varmu) {
+    // mu = mu(z): tau_ij = mu(z) S_ij on the physical grid.  The S_ij values at tau come from u_hat and go
+    // to the R_z inputs' buffers (dead by now).  Two physical passes, one per group of three components
+    // (the two flux groups); z is still in zbuf slot 6 when all planes are one batch on the register
+    // x-pass, else transformed again.  The tau_ij values land in T, which the flux kernels read and then
+    // overwrite.
+    double2* S[6] = {vz1, vzl, vz3, vmd1, vmd3, vc2d};
+    {
+      const int n = int(ncol);
+      const dim3 grid((n + kThreads - 1) / kThreads);
+      ProfScope ps(p, KC_FLUX, s, 16.0 * nB * 9.0);
+      const SixPtr sp{{S[0], S[1], S[2], S[3], S[4], S[5]}};
+      if (narrow) col<JobStrain<8>>(c, grid, 0, {u[0], u[1], u[2], sp});
+      else col<JobStrain<kMaxW>>(c, grid, 0, {u[0], u[1], u[2], sp});
+    }
+    for (int grp = 0; grp < 2; ++grp) {
+      std::vector<EvalIn> tin{ev(S[3 * grp], EV_IDENT), ev(S[3 * grp + 1], EV_IDENT), ev(S[3 * grp + 2], EV_IDENT)};
+      if (!zres) {
+        EvalIn zin = ev(vz0, EV_IDENT);
+        if (xr) zin.slot = 6;  // the register x-pass reads z from slot 6, the generic one from slot 3
+        tin.push_back(zin);
+      }
+      st = plane_phase<PH_TAU>(c, tin, {T[3 * grp], T[3 * grp + 1], T[3 * grp + 2]});
+      if (st != LMVD_OK) return st;
+    }
+  }
+  // fluxes and their share of the RHS values at tau (RO: Omega2, RP: phi2)
+  double2* RO = vals[0];
+  double2* RP = vals[1];
+  {
+    const int n = int(ncol);
+    const dim3 grid((n + kThreads - 1) / kThreads);
+    // per group: C_ij and u_hat (or tau_ij values) in, L-sweep intermediates out and back, RHS values out
+    // (group 1 also reads them and rho)
+    ProfScope ps(p, KC_FLUX, s, 16.0 * nB * 31.0);
+    const FluxArgs fa{cv[0], cv[1], cv[2], u[0], u[1], u[2], T[0], T[1], T[2], RO, RP, rhov};
+    const FluxArgs fb{cv[3], cv[4], cv[5], u[0], u[1], u[2], T[3], T[4], T[5], RO, RP, rhov};
+    if (narrow && varmu) {
+      col<JobFlux<0, 8, 6, true>>(c, grid, 0, fa);
+      col<JobFlux<1, 8, 6, true>>(c, grid, 0, fb);
+    } else if (narrow) {
+      col<JobFlux<0, 8, 6>>(c, grid, 0, fa);
+      col<JobFlux<1, 8, 6>>(c, grid, 0, fb);
+    } else if (varmu) {
+      col<JobFlux<0, kMaxW, kMaxBand, true>>(c, grid, 0, fa);
+      col<JobFlux<1, kMaxW, kMaxBand, true>>(c, grid, 0, fb);
+    } else {
+      col<JobFlux<0, kMaxW, kMaxBand>>(c, grid, 0, fa);
+      col<JobFlux<1, kMaxW, kMaxBand>>(c, grid, 0, fb);
+    }
+  }
+  // RHS and RK2
+  {
+    const int n = int(ncol);
+    {
+      ProfScope ps(p, KC_RHS, s, 16.0 * nB * (a->stage ? 12.0 : 10.0) + 16.0 * nB * (a->rhs_phi2 ? 2 : 0));
+      col<JobRhsFluct>(c, dim3((n + kThreads - 1) / kThreads), 0,
+                       {RO, RP, phi2, om2, static_cast<const double2*>(a->rhs_phi2_prev),
+                        static_cast<const double2*>(a->rhs_omega2_prev), static_cast<double2*>(a->phi2_out),
+                        static_cast<double2*>(a->omega2_out), static_cast<double2*>(a->rhs_phi2),
+                        static_cast<double2*>(a->rhs_omega2), c.at<double2>(W.off_yphi), c.at<double2>(W.off_yom),
+                        a->stage});
+    }
+    {
+      ProfScope ps(p, KC_RHS, s, 16.0 * 2 * H.n2 + 8.0 * H.n2 * (a->stage ? 8.0 : 6.0));
+      col<JobRhsMean>(c, dim3(1), size_t(2) * H.n2 * sizeof(double),
+                      {T[1], T[4], a->m1bar, a->m3bar, a->rhs_m1_prev, a->rhs_m3_prev, a->m1bar_out, a->m3bar_out,
+                       a->rhs_m1, a->rhs_m3, a->stage});
+    }
+  }
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
 static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void* workspace, hipStream_t s,
                                Recorder* rec = nullptr) {
   const HostTables& H = p->H;
@@ -4031,100 +4246,9 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]});
   if (st != LMVD_OK) return st;
   mc_step(true);  // m = m^d + m^c values
-  // 4./5. velocities, density, fluxes
-  // u = m/rho, rho and C_ij = -m_i m_j/rho on the physical grid; u_hat by interpolation;
-  // T_ij = C_ij + tau_ij(u_hat) projected
-  double2* cv[6] = {vals[4], vals[5], vals[6], vals[7], vals[8], vals[9]};
-  const std::vector<double2*> vel_out{vals[0], vals[1], vals[2], rhov, cv[0], cv[1], cv[2], cv[3], cv[4], cv[5]};
-  if (xr && p->pb == H.n2) {  // z still in zbuf slot 6
-    st = plane_phase<PH_VEL>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)}, vel_out);
-  } else if (xr) {
-    EvalIn zin = ev(vz0, EV_IDENT);
-    zin.slot = 6;
-    st = plane_phase<PH_VEL>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT), zin}, vel_out);
-  } else {
-    st = plane_phase<PH_VEL>(c, {ev(vz0, EV_IDENT), ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)},
-                             vel_out);
-  }
+  // 4./5. velocities, density, fluxes, right-hand sides and the RK2 update
+  st = rhs_phase(c, a, vz0, vm1, vm2, vm3, xr && p->pb == H.n2);
   if (st != LMVD_OK) return st;
-  {
-    const int n = int(ncol);
-    ProfScope ps(p, KC_PROJ, s, 3 * 4.0 * 16.0 * nB);
-    col<JobProj3>(c, dim3((n + kThreads - 1) / kThreads, 3), 0, {0, ProjBatch{{vals[0], vals[1], vals[2]}, {u[0], u[1],
-                  u[2]}}, n});
-  }
-  const bool narrow = H.p <= 8 && H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
-  const bool varmu = var_mu(H.cfg);
-  if (varmu) {
-    // mu = mu(z): tau_ij = mu(z) S_ij on the physical grid.  The S_ij values at tau come from u_hat and go
-    // to the R_z inputs' buffers (dead by now).  Two physical passes, one per group of three components
-    // (the two flux groups); z is still in zbuf slot 6 when all planes are one batch on the register
-    // x-pass, else transformed again.  The tau_ij values land in T, which the flux kernels read and then
-    // overwrite.
-    double2* S[6] = {vz1, vzl, vz3, vmd1, vmd3, vc2d};
-    {
-      const int n = int(ncol);
-      const dim3 grid((n + kThreads - 1) / kThreads);
-      ProfScope ps(p, KC_FLUX, s, 16.0 * nB * 9.0);
-      const SixPtr sp{{S[0], S[1], S[2], S[3], S[4], S[5]}};
-      if (narrow) col<JobStrain<8>>(c, grid, 0, {u[0], u[1], u[2], sp});
-      else col<JobStrain<kMaxW>>(c, grid, 0, {u[0], u[1], u[2], sp});
-    }
-    for (int grp = 0; grp < 2; ++grp) {
-      std::vector<EvalIn> tin{ev(S[3 * grp], EV_IDENT), ev(S[3 * grp + 1], EV_IDENT), ev(S[3 * grp + 2], EV_IDENT)};
-      if (!(xr && p->pb == H.n2)) {
-        EvalIn zin = ev(vz0, EV_IDENT);
-        if (xr) zin.slot = 6;  // the register x-pass reads z from slot 6, the generic one from slot 3
-        tin.push_back(zin);
-      }
-      st = plane_phase<PH_TAU>(c, tin, {T[3 * grp], T[3 * grp + 1], T[3 * grp + 2]});
-      if (st != LMVD_OK) return st;
-    }
-  }
-  // fluxes and their share of the RHS values at tau (RO: Omega2, RP: phi2)
-  double2* RO = vals[0];
-  double2* RP = vals[1];
-  {
-    const int n = int(ncol);
-    const dim3 grid((n + kThreads - 1) / kThreads);
-    // per group: C_ij and u_hat (or tau_ij values) in, L-sweep intermediates out and back, RHS values out
-    // (group 1 also reads them and rho)
-    ProfScope ps(p, KC_FLUX, s, 16.0 * nB * 31.0);
-    const FluxArgs fa{cv[0], cv[1], cv[2], u[0], u[1], u[2], T[0], T[1], T[2], RO, RP, rhov};
-    const FluxArgs fb{cv[3], cv[4], cv[5], u[0], u[1], u[2], T[3], T[4], T[5], RO, RP, rhov};
-    if (narrow && varmu) {
-      col<JobFlux<0, 8, 6, true>>(c, grid, 0, fa);
-      col<JobFlux<1, 8, 6, true>>(c, grid, 0, fb);
-    } else if (narrow) {
-      col<JobFlux<0, 8, 6>>(c, grid, 0, fa);
-      col<JobFlux<1, 8, 6>>(c, grid, 0, fb);
-    } else if (varmu) {
-      col<JobFlux<0, kMaxW, kMaxBand, true>>(c, grid, 0, fa);
-      col<JobFlux<1, kMaxW, kMaxBand, true>>(c, grid, 0, fb);
-    } else {
-      col<JobFlux<0, kMaxW, kMaxBand>>(c, grid, 0, fa);
-      col<JobFlux<1, kMaxW, kMaxBand>>(c, grid, 0, fb);
-    }
-  }
-  // RHS and RK2
-  {
-    const int n = int(ncol);
-    {
-      ProfScope ps(p, KC_RHS, s, 16.0 * nB * (a->stage ? 12.0 : 10.0) + 16.0 * nB * (a->rhs_phi2 ? 2 : 0));
-      col<JobRhsFluct>(c, dim3((n + kThreads - 1) / kThreads), 0,
-                       {RO, RP, phi2, om2, static_cast<const double2*>(a->rhs_phi2_prev),
-                        static_cast<const double2*>(a->rhs_omega2_prev), static_cast<double2*>(a->phi2_out),
-                        static_cast<double2*>(a->omega2_out), static_cast<double2*>(a->rhs_phi2),
-                        static_cast<double2*>(a->rhs_omega2), c.at<double2>(W.off_yphi), c.at<double2>(W.off_yom),
-                        a->stage});
-    }
-    {
-      ProfScope ps(p, KC_RHS, s, 16.0 * 2 * H.n2 + 8.0 * H.n2 * (a->stage ? 8.0 : 6.0));
-      col<JobRhsMean>(c, dim3(1), size_t(2) * H.n2 * sizeof(double),
-                      {T[1], T[4], a->m1bar, a->m3bar, a->rhs_m1_prev, a->rhs_m3_prev, a->m1bar_out, a->m3bar_out,
-                       a->rhs_m1, a->rhs_m3, a->stage});
-    }
-  }
   // optional diagnostics (never in a recorded substep)
   if (!rec) {
     const size_t sB = nB * 16, sS = ncol * (H.n2 + 1) * 16;
@@ -4640,6 +4764,65 @@ lmvd_status lmvd_evaluate(lmvd_plan plan, int32_t deriv, int32_t star, const voi
                      static_cast<hipStream_t>(stream), plan->D, kind, static_cast<const double2*>(coeffs),
                      static_cast<double2*>(values));
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_evaluate_adjoint(lmvd_plan plan, int32_t deriv, int32_t star, const void* values, void* coeffs,
+                                  void* stream) {
+  if (!plan || !values || !coeffs || deriv < 0 || deriv > 2 || (star && deriv != 0) || values == coeffs)
+    return LMVD_EINVAL;
+  const size_t ncol = size_t(plan->H.nn) * plan->H.nl;
+  hipLaunchKernelGGL(k_evaluate_t, dim3((ncol + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     static_cast<hipStream_t>(stream), plan->D, star ? int(EV_F0) : deriv,
+                     static_cast<const double2*>(values), static_cast<double2*>(coeffs));
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_project_adjoint(lmvd_plan plan, int32_t kind, const void* coeffs, void* values, void* stream) {
+  if (!plan || !coeffs || !values || kind < 0 || kind > 2 || coeffs == values) return LMVD_EINVAL;
+  const size_t ncol = size_t(plan->H.nn) * plan->H.nl;
+  hipLaunchKernelGGL(k_project_t, dim3((ncol + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     static_cast<hipStream_t>(stream), plan->D, int(kind), static_cast<const double2*>(coeffs),
+                     static_cast<double2*>(values));
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_to_physical_adjoint(lmvd_plan plan, const double* phys, void* values, void* workspace,
+                                     void* stream) {
+  const lmvd_status st = lmvd_to_spectral(plan, phys, values, workspace, stream);
+  if (st != LMVD_OK) return st;
+  const size_t n = size_t(plan->H.nn) * plan->H.nl * plan->H.n2;
+  hipLaunchKernelGGL(k_scale_modes, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     static_cast<hipStream_t>(stream), plan->D, static_cast<double2*>(values));
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_rhs(lmvd_plan plan, const void* z, const void* m1, const void* m2, const void* m3, void* rhs_phi2,
+                     void* rhs_omega2, double* rhs_m1, double* rhs_m3, void* workspace, void* stream) {
+  if (!plan || !z || !m1 || !m2 || !m3 || !rhs_phi2 || !rhs_omega2 || !rhs_m1 || !rhs_m3 || !workspace)
+    return LMVD_EINVAL;
+  for (const void* q : {z, m1, m2, m3, static_cast<const void*>(rhs_phi2), static_cast<const void*>(rhs_omega2),
+                        static_cast<const void*>(rhs_m1), static_cast<const void*>(rhs_m3)})
+    if (!aligned(q)) return LMVD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
+  if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ctx c{plan, static_cast<char*>(workspace), s};
+  const Workspace& W = plan->ws;
+  double2* vz0 = c.at<double2>(W.off_vz0);
+  double2* vm[3] = {c.at<double2>(W.off_vm1c), c.at<double2>(W.off_vm2c), c.at<double2>(W.off_vm3c)};
+  const size_t n = size_t(plan->H.nn) * plan->H.nl * plan->H.n2;
+  const dim3 g((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_evaluate, g, dim3(kThreads), 0, s, plan->D, int(EV_E0), static_cast<const double2*>(z), vz0);
+  hipLaunchKernelGGL(k_evaluate, g, dim3(kThreads), 0, s, plan->D, int(EV_E0), static_cast<const double2*>(m1), vm[0]);
+  hipLaunchKernelGGL(k_evaluate, g, dim3(kThreads), 0, s, plan->D, int(EV_F0), static_cast<const double2*>(m2), vm[1]);
+  hipLaunchKernelGGL(k_evaluate, g, dim3(kThreads), 0, s, plan->D, int(EV_E0), static_cast<const double2*>(m3), vm[2]);
+  lmvd_substep_args a{};
+  a.stage = 2;  // right-hand sides only
+  a.rhs_phi2 = rhs_phi2;
+  a.rhs_omega2 = rhs_omega2;
+  a.rhs_m1 = rhs_m1;
+  a.rhs_m3 = rhs_m3;
+  return rhs_phase(c, &a, vz0, vm[0], vm[1], vm[2], false);
 }
 
 lmvd_status lmvd_md(lmvd_plan plan, const void* phi2, const void* omega2, const double* m1bar, const double* m3bar,

@@ -58,7 +58,8 @@ EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_
            "lmvd_to_physical", "lmvd_to_spectral", "lmvd_project", "lmvd_evaluate", "lmvd_md", "lmvd_mc",
            "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop", "lmvd_graph_create",
            "lmvd_graph_launch", "lmvd_graph_destroy", "lmvd_graph_grouped", "lmvd_autotune",
-           "lmvd_graph_autotune"]
+           "lmvd_graph_autotune", "lmvd_rhs", "lmvd_to_physical_adjoint", "lmvd_evaluate_adjoint",
+           "lmvd_project_adjoint"]
 
 
 def library():
@@ -82,6 +83,10 @@ def library():
         lib.lmvd_evaluate.argtypes = [vp, i32, i32, vp, vp, vp]
         lib.lmvd_md.argtypes = [vp] * 8 + [vp, vp]
         lib.lmvd_mc.argtypes = [vp] * 7
+        lib.lmvd_rhs.argtypes = [vp] * 11
+        lib.lmvd_to_physical_adjoint.argtypes = [vp] * 5
+        lib.lmvd_evaluate_adjoint.argtypes = [vp, i32, i32, vp, vp, vp]
+        lib.lmvd_project_adjoint.argtypes = [vp, i32, vp, vp, vp]
         lib.lmvd_host_tables.argtypes = [ctypes.POINTER(Config), vp, vp, vp, vp, vp]
         lib.lmvd_profile_start.argtypes = [vp, i32, i32]
         lib.lmvd_profile_stop.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
@@ -275,6 +280,25 @@ class Plan:
                "lmvd_evaluate")
         return out
 
+    # transposes (lmvd_*_adjoint): <A x, y> = <x, A^T y> in the real inner products
+    def to_physical_adjoint(self, phys):
+        out = self.empty()
+        _check(library().lmvd_to_physical_adjoint(self.handle, _ptr(phys), _ptr(out), _ptr(self.ws), self._stream()),
+               "lmvd_to_physical_adjoint")
+        return out
+
+    def evaluate_adjoint(self, deriv, values, star=False):
+        out = self.empty(star)
+        _check(library().lmvd_evaluate_adjoint(self.handle, deriv, int(star), _ptr(values), _ptr(out),
+                                               self._stream()), "lmvd_evaluate_adjoint")
+        return out
+
+    def project_adjoint(self, kind, coeffs):
+        out = self.empty()
+        _check(library().lmvd_project_adjoint(self.handle, kind, _ptr(coeffs), _ptr(out), self._stream()),
+               "lmvd_project_adjoint")
+        return out
+
     def md(self, phi2, omega2, m1bar, m3bar):
         m1, m2, m3 = self.empty(), self.empty(True), self.empty()
         _check(library().lmvd_md(self.handle, _ptr(phi2), _ptr(omega2), _ptr(m1bar), _ptr(m3bar), _ptr(m1),
@@ -286,6 +310,16 @@ class Plan:
         _check(library().lmvd_mc(self.handle, _ptr(rhot), _ptr(m1), _ptr(m2), _ptr(m3), _ptr(self.ws),
                                  self._stream()), "lmvd_mc")
         return m1, m2, m3
+
+    def rhs(self, z, m1, m2, m3):
+        """Right-hand sides of phi2, Omega2 and the plane means for z and m (lmvd_rhs)."""
+        torch = self.torch
+        rp, ro = self.empty(), self.empty()
+        r1 = torch.empty(self.w.n2, dtype=torch.float64, device="cuda")
+        r3 = torch.empty(self.w.n2, dtype=torch.float64, device="cuda")
+        _check(library().lmvd_rhs(self.handle, _ptr(z), _ptr(m1), _ptr(m2), _ptr(m3), _ptr(rp), _ptr(ro), _ptr(r1),
+                                  _ptr(r3), _ptr(self.ws), self._stream()), "lmvd_rhs")
+        return {"phi2": rp, "omega2": ro, "m1bar": r1, "m3bar": r3}
 
 
 class Stepper:

@@ -1,0 +1,129 @@
+"""Adjoints of the linear operators (lmvd_to_physical_adjoint,
+lmvd_evaluate_adjoint, lmvd_project_adjoint) and automatic differentiation
+through them (paper_2206_09878_amd.autograd), through the C ABI:
+
+  * <A x, y> = <x, A^T y> in the real inner products for the inverse transform
+    (register and generic kernels), E_0, E_1, E_2, F_0 and the three
+    projections, on random S-fields with a Hermitian l = 0 column (the inputs
+    the library accepts);
+  * E_d^T and the projections' transposes equal the oracle's dense transposes
+    column by column (1e-12);
+  * the gradient of a real loss through project -> evaluate -> to_physical
+    matches central finite differences (eps = 1e-6) on 16 random directions.
+"""
+import numpy as np
+import pytest
+
+from oracle.lmvd import Plan as OPlan
+from paper_2206_09878_amd.workloads import workload
+from tests.conftest import oracle_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def rdot(torch, a, b):
+    return float(torch.sum(torch.view_as_real(a) * torch.view_as_real(b)).item()) if a.is_complex() \
+        else float(torch.sum(a * b).item())
+
+
+def crand(torch, shape, seed):
+    """Random S-field whose l = 0 column is Hermitian (f(0, -n) = conj f(0, n)), as the library's
+    inputs must be."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    re = torch.randn(shape, dtype=torch.float64, device="cuda", generator=g)
+    im = torch.randn(shape, dtype=torch.float64, device="cuda", generator=g)
+    c = torch.complex(re, im)
+    nn = shape[1]
+    c[:, 0, 0] = c[:, 0, 0].real.to(c.dtype)
+    for n in range(1, (nn + 1) // 2 + 1):
+        if nn - n > n - 1:
+            c[:, nn - n, 0] = torch.conj(c[:, n, 0])
+    return c
+
+
+def plan_of(n, n2):
+    from paper_2206_09878_amd.lmvd import Plan
+    return Plan(workload("small", n=n, n2=n2))
+
+
+@pytest.mark.parametrize("n,n2", [(32, 33), (24, 25)])     # register and generic transform kernels
+def test_transform_transpose(torch, n, n2):
+    p = plan_of(n, n2)
+    w = p.w
+    c = crand(torch, w.shape, 1)
+    g = torch.randn((w.n2, w.m3, w.m1), dtype=torch.float64, device="cuda")
+    lhs = rdot(torch, p.to_physical(c), g)
+    rhs = rdot(torch, c, p.to_physical_adjoint(g))
+    torch.cuda.synchronize()
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs) + 1e-12
+
+
+@pytest.mark.parametrize("deriv,star", [(0, False), (1, False), (2, False), (0, True)])
+def test_evaluate_transpose(torch, deriv, star):
+    p = plan_of(32, 33)
+    w = p.w
+    c = crand(torch, w.shape_star if star else w.shape, 2)
+    v = crand(torch, w.shape, 3)
+    lhs = rdot(torch, p.evaluate(deriv, c, star=star), v)
+    ct = p.evaluate_adjoint(deriv, v, star=star)
+    rhs = rdot(torch, c, ct)
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+    # against the oracle's dense matrix, column by column
+    op = OPlan(oracle_config(w))
+    M = op.sp.F[0] if star else op.sp.E[deriv]
+    ref = np.tensordot(M.T, v.cpu().numpy(), axes=(1, 0))
+    got = ct.cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_project_transpose(torch, kind):
+    p = plan_of(32, 33)
+    w = p.w
+    v = crand(torch, w.shape, 4)
+    y = crand(torch, w.shape, 5)
+    lhs = rdot(torch, p.project(kind, v), y)
+    vt = p.project_adjoint(kind, y)
+    rhs = rdot(torch, v, vt)
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+    op = OPlan(oracle_config(w))
+    A = (op.P_plain, op.P_D, op.P_N)[kind]
+    yy = y.cpu().numpy()
+    ref = np.linalg.solve(A.T, yy.reshape(w.n2, -1)).reshape(yy.shape)
+    if kind:
+        ref[0] = 0.0
+        ref[-1] = 0.0
+    got = vt.cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_gradient_matches_central_differences(torch):
+    """Loss = sum(W * to_physical(E_1 P_N v)): its gradient by autograd (the
+    adjoint chain) against (L(v + eps d) - L(v - eps d)) / (2 eps) on 16 random
+    directions d, eps = 1e-6."""
+    from paper_2206_09878_amd.autograd import evaluate, project, to_physical
+    p = plan_of(32, 33)
+    w = p.w
+    Wt = torch.randn((w.n2, w.m3, w.m1), dtype=torch.float64, device="cuda")
+
+    def loss(v):
+        return torch.sum(Wt * to_physical(p, evaluate(p, 1, project(p, 2, v))))
+
+    v = crand(torch, w.shape, 6).requires_grad_(True)
+    L = loss(v)
+    L.backward()
+    grad = v.grad.detach()
+    eps = 1e-6
+    with torch.no_grad():
+        for k in range(16):
+            d = crand(torch, w.shape, 100 + k)
+            fd = (loss(v + eps * d) - loss(v - eps * d)).item() / (2 * eps)
+            an = rdot(torch, grad, d)
+            assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (k, fd, an)

@@ -221,6 +221,31 @@ def test_substep_mixing_layer_full_size(torch):
     check_pair(got, ref, rhs_tol=rhs_tolerances(w, 0, 1, ref=ref))
 
 
+@pytest.mark.parametrize("name,n,n2,laws", [("small", None, None, False), ("small", 24, 33, True),
+                                             ("mixing128", 64, 65, False)])
+def test_rhs_entry_point(torch, name, n, n2, laws):
+    """lmvd_rhs (steps 4 and 5 alone) from the oracle's own z and m = m^d + m^c
+    of a substep, against that substep's RHS: row a9 in isolation.  The 36-point
+    case runs the generic x-pass with variable transport laws."""
+    import dataclasses
+    w = workload(name, n=n, n2=n2)
+    if laws:
+        w = dataclasses.replace(w, mu_z=(0.5 * w.mu, -0.3 * w.mu, 0.2 * w.mu),
+                                rhoD_z=(0.4 * w.rhoD, 0.0, 0.0), rhoD_form=1)
+    print("lmvd_rhs", name, (w.n1, w.n2, w.n3), "laws", laws, flush=True)
+    inp = make_inputs(w, seed=8, stage=0)
+    st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
+    ref = substep(OPlan(oracle_config(w)), st, 0, hist=inp["hist"], diagnostics=True)
+    md, mc = ref["diag"]["md"], ref["diag"]["mc"]
+    p = gplan(w)
+    got = p.rhs(p.to_dev(st["z"]), *[p.to_dev(md[i] + mc[i]) for i in range(3)])
+    torch.cuda.synchronize()
+    tol = rhs_tolerances(w, 0, 8, ref=ref)
+    for k in ("phi2", "omega2", "m1bar", "m3bar"):
+        e = rel(host(got[k]), ref["rhs"][k])
+        assert e < tol[k], (k, e, tol[k])
+
+
 def test_trajectory_three_substeps_small(torch):
     """Config 0 trajectory: substeps n, ', n, each side free-running on its own
     outputs (history rotation, stored RHS and z_t between the stages), from the
