@@ -292,6 +292,22 @@ lmvd_status lmvd_evaluate_adjoint(lmvd_plan plan, int32_t deriv, int32_t star, c
                                   void* stream);
 lmvd_status lmvd_project_adjoint(lmvd_plan plan, int32_t kind, const void* coeffs, void* values, void* stream);
 
+/* Transpose of lmvd_md, the map (phi2, Omega2, <m>1, <m>3) -> (m1, m2, m3) of eqs. phi_poisson,
+ * bc_both and md_recon, in the same inner products (the plane means as plain real vectors): from the
+ * adjoints m1, m3 (S-fields, B) and m2 (B*) it writes the adjoints phi2, omega2 (S-fields) and m1bar,
+ * m3bar ([n2]).  A(k)^{-T} uses the plan's A(k) factors (computed first if needed).  Per column the
+ * adjoint of the Robin rows is zero and the (0,0) column maps to the plane means only.  workspace as
+ * for lmvd_substep (one (n2+1)-row scratch field).  Device pointers, asynchronous. */
+lmvd_status lmvd_md_adjoint(lmvd_plan plan, const void* m1, const void* m2, const void* m3, void* phi2,
+                           void* omega2, double* m1bar, double* m3bar, void* workspace, void* stream);
+
+/* Transpose of lmvd_mc, the map rho_t (B coefficients) -> (m1, m2, m3) of eqs. COM_fourier, CF_fourier,
+ * mc_recon and mc_mean: from the adjoints m1, m3 (B) and m2 (B*) it writes the adjoint rhot (S-field,
+ * B).  The (0,0) column transposes the plane-mean system (D* rows and the top condition).  workspace and
+ * factors as for lmvd_md_adjoint.  Device pointers, asynchronous. */
+lmvd_status lmvd_mc_adjoint(lmvd_plan plan, const void* m1, const void* m2, const void* m3, void* rhot,
+                           void* workspace, void* stream);
+
 /* Timing hook for measurements: while active, every launch of one kernel
  * class is bracketed by two HIP events recorded on the stream it is launched
  * on.  Classes (one kernel each):

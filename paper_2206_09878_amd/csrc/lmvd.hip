@@ -3224,6 +3224,179 @@ __global__ void __launch_bounds__(kThreads) k_project_t(DevPlan P, int kind, con
   }
 }
 
+constexpr int kFacMax = 9;  // band of the factor rows (a_lower, a_upper <= 8)
+// psi = A(k)^{-T} b in place in scr (n2 + 1 rows of column c), A = U L from the plan's factors of pair
+// fac (U unit upper: the multipliers; L: entries left of the diagonal and the inverse diagonal):
+// L^T w = b descending, then U^T psi = w ascending
+__device__ __forceinline__ void solve_At(const DevPlan& P, const double* fac, int npairs, double2* scr, size_t c,
+                                         size_t ncol) {
+  const int N = P.n2 + 1;
+  // L^T w = b (descending): ring[q] = w_{i+1+q}; L_{i+1+q, i} is left entry q of row i+1+q
+  double2 ring[kFacMax];
+#pragma unroll
+  for (int q = 0; q < kFacMax; ++q) ring[q] = zero2();
+  for (int i = N - 1; i >= 0; --i) {
+    double2 b = scr[size_t(i) * ncol + c];
+#pragma unroll
+    for (int q = 0; q < kFacMax; ++q) {
+      const int row = i + 1 + q;
+      if (row < N && q < P.fac_ns[row]) b = fma2(-fac[size_t(P.fac_off[row] + P.fac_nm[row] + q) * npairs], ring[q], b);
+    }
+    const double2 w = cscale(b, fac[size_t(P.fac_off[i] + P.fac_nm[i] + P.fac_ns[i]) * npairs]);
+#pragma unroll
+    for (int q = kFacMax - 1; q > 0; --q) ring[q] = ring[q - 1];
+    ring[0] = w;
+    scr[size_t(i) * ncol + c] = w;
+  }
+  // U^T psi = w (ascending): ring[m] = psi_{i-1-m}; U_{i-1-m, i} is multiplier m of row i-1-m
+#pragma unroll
+  for (int q = 0; q < kFacMax; ++q) ring[q] = zero2();
+  for (int i = 0; i < N; ++i) {
+    double2 x = scr[size_t(i) * ncol + c];
+#pragma unroll
+    for (int m = 0; m < kFacMax; ++m) {
+      const int row = i - 1 - m;
+      if (row >= 0 && m < P.fac_nm[row]) x = fma2(-fac[size_t(P.fac_off[row] + m) * npairs], ring[m], x);
+    }
+#pragma unroll
+    for (int m = kFacMax - 1; m > 0; --m) ring[m] = ring[m - 1];
+    ring[0] = x;
+    scr[size_t(i) * ncol + c] = x;
+  }
+}
+
+// out (n2 rows of column c) = (add ? out : 0) + sum over the interior tau* rows i of G_g[i, :]^T scale psi_i
+// (g = 0: G0, 1: G1); the rows each tau* row reaches start at a nondecreasing position, so finished rows
+// leave a register window in order
+__device__ __forceinline__ void scatter_Gt(const DevPlan& P, int g, const double2* scr, double scale, double2* out,
+                                           size_t c, size_t ncol, bool add) {
+  const int n2 = P.n2, N = n2 + 1;
+  double2 acc[kMaxW];
+#pragma unroll
+  for (int q = 0; q < kMaxW; ++q) acc[q] = zero2();
+  int base = 0;
+  for (int i = 1; i < n2; ++i) {
+    const int lo = P.gs_lo[g * N + i];
+    while (base < lo) {
+      const size_t e = size_t(base) * ncol + c;
+      out[e] = add ? cadd(out[e], acc[0]) : acc[0];
+#pragma unroll
+      for (int q = 0; q < kMaxW - 1; ++q) acc[q] = acc[q + 1];
+      acc[kMaxW - 1] = zero2();
+      ++base;
+    }
+    const double2 psi = cscale(scr[size_t(i) * ncol + c], scale);
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q)
+      if (lo + q < n2) acc[q] = fma2(P.gs_w[(size_t(g) * N + i) * kMaxW + q], psi, acc[q]);
+  }
+  while (base < n2) {
+    const size_t e = size_t(base) * ncol + c;
+    out[e] = add ? cadd(out[e], acc[0]) : acc[0];
+#pragma unroll
+    for (int q = 0; q < kMaxW - 1; ++q) acc[q] = acc[q + 1];
+    acc[kMaxW - 1] = zero2();
+    ++base;
+  }
+}
+
+// transpose of the m^d map (phi2, Omega2, <m>1, <m>3) -> (m1, m2, m3) coefficients (eqs. phi_poisson,
+// bc_both, md_recon).  Per column: the adjoints of D = D* c and of Omega2 from the m1, m3 adjoints (the
+// multipliers i k1 / k^2, i k3 / k^2 conjugated), c_bar = m2_bar + D*^T D_bar, psi = A(k)^{-T} c_bar with
+// the plan's factors A = U L (U unit upper: the multipliers, L: entries left of the diagonal and the
+// inverse diagonal) as L^T w = c_bar descending and U^T psi = w ascending, then phi2_bar = G0^T psi over
+// the interior tau* rows (the Robin rows carry no phi2).  psi goes through scr (n2 + 1 rows).
+__global__ void __launch_bounds__(kThreads) k_md_t(DevPlan P, const double2* __restrict__ a1,
+                                                  const double2* __restrict__ a2, const double2* __restrict__ a3,
+                                                  double2* __restrict__ phi_t, double2* __restrict__ om_t,
+                                                  double* __restrict__ m1bar_t, double* __restrict__ m3bar_t,
+                                                  double2* __restrict__ scr) {
+  const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
+  const size_t ncol = size_t(nn) * nl;
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int l = int(c % size_t(nl)), ni = int(c / size_t(nl));
+  const double k1 = P.k1[l], k3 = P.k3[ni], ksq = k1 * k1 + k3 * k3;
+  if (ksq == 0.0) {  // (0,0): m1 = <m>1, m3 = <m>3, m2 = 0; phi2, Omega2 do not enter
+    for (int i = 0; i < n2; ++i) {
+      m1bar_t[i] = a1[size_t(i) * ncol].x;
+      m3bar_t[i] = a3[size_t(i) * ncol].x;
+      phi_t[size_t(i) * ncol] = zero2();
+      om_t[size_t(i) * ncol] = zero2();
+    }
+    return;
+  }
+  const double iksq = 1.0 / ksq;
+  const int half = (nn + 1) / 2, npairs = nl * half;
+  const int pp = ni < half ? ni : nn - ni;
+  const double* fac = P.fac + size_t(pp) * nl + l;
+  // c_bar = m2_bar + D*^T D_bar; Omega2_bar
+  double2 dprev = zero2();
+  for (int r = 0; r < N; ++r) {
+    double2 db = zero2();
+    if (r < n2) {
+      const double2 m1 = a1[size_t(r) * ncol + c], m3 = a3[size_t(r) * ncol + c];
+      db = cscale(times_i(make_double2(-(k1 * m1.x + k3 * m3.x), -(k1 * m1.y + k3 * m3.y))), iksq);
+      om_t[size_t(r) * ncol + c] = cscale(times_i(make_double2(k3 * m1.x - k1 * m3.x, k3 * m1.y - k1 * m3.y)), iksq);
+    }
+    double2 cb = a2[size_t(r) * ncol + c];
+    if (r >= 1) cb = fma2(P.dstar[r - 1], dprev, cb);
+    if (r < n2) cb = fma2(-P.dstar[r], db, cb);
+    scr[size_t(r) * ncol + c] = cb;
+    dprev = db;
+  }
+  solve_At(P, fac, npairs, scr, c, ncol);
+  scatter_Gt(P, 0, scr, 1.0, phi_t, c, ncol, false);
+}
+
+// transpose of the m^c map rho_t (B coefficients) -> (m1, m2, m3) (eqs. COM_fourier, CF_fourier, mc_recon,
+// mc_mean): m_par_bar = (k1 m1_bar + k3 m3_bar) / k; rho_t_bar = D_bar = (-i/k) m_par_bar; c_bar = m2_bar +
+// D*^T D_bar; psi = A(k)^{-T} c_bar; rho_t_bar -= G1^T psi over the interior rows.  The (0,0) column solves
+// the transposed mean system [D*; top row]^T psi = m2_bar by one ascending recurrence, rho_t_bar = -psi.
+__global__ void __launch_bounds__(kThreads) k_mc_t(DevPlan P, const double2* __restrict__ a1,
+                                                  const double2* __restrict__ a2, const double2* __restrict__ a3,
+                                                  double2* __restrict__ rho_t, double2* __restrict__ scr) {
+  const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
+  const size_t ncol = size_t(nn) * nl;
+  const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int l = int(c % size_t(nl)), ni = int(c / size_t(nl));
+  const double k1 = P.k1[l], k3 = P.k3[ni], ksq = k1 * k1 + k3 * k3;
+  if (ksq == 0.0) {
+    // psi_0 = -b_0 / d_0; psi_r = (d_{r-1} psi_{r-1} - b_r) / d_r (r < n2); rho_t_bar_r = -psi_r
+    double2 prev = zero2();
+    for (int r = 0; r < n2; ++r) {
+      double2 b = a2[size_t(r) * ncol];
+      if (r >= 1) b = make_double2(P.dstar[r - 1] * prev.x - b.x, P.dstar[r - 1] * prev.y - b.y);
+      else b = make_double2(-b.x, -b.y);
+      prev = cscale(b, 1.0 / P.dstar[r]);
+      rho_t[size_t(r) * ncol] = make_double2(-prev.x, -prev.y);
+    }
+    return;
+  }
+  const double ik = 1.0 / sqrt(ksq);
+  const int half = (nn + 1) / 2, npairs = nl * half;
+  const int pp = ni < half ? ni : nn - ni;
+  const double* fac = P.fac + size_t(pp) * nl + l;
+  double2 dprev = zero2();
+  for (int r = 0; r < N; ++r) {
+    double2 db = zero2();
+    if (r < n2) {
+      const double2 m1 = a1[size_t(r) * ncol + c], m3 = a3[size_t(r) * ncol + c];
+      const double2 mp = make_double2((k1 * m1.x + k3 * m3.x) * ik, (k1 * m1.y + k3 * m3.y) * ik);
+      db = cscale(make_double2(mp.y, -mp.x), ik);  // (-i/k) m_par_bar
+      rho_t[size_t(r) * ncol + c] = db;
+    }
+    double2 cb = a2[size_t(r) * ncol + c];
+    if (r >= 1) cb = fma2(P.dstar[r - 1], dprev, cb);
+    if (r < n2) cb = fma2(-P.dstar[r], db, cb);
+    scr[size_t(r) * ncol + c] = cb;
+    dprev = db;
+  }
+  solve_At(P, fac, npairs, scr, c, ncol);
+  scatter_Gt(P, 1, scr, -1.0, rho_t, c, ncol, true);  // rho_t_bar -= G1^T psi
+}
+
 // the inverse transform's transpose from the forward one: times M1 M3, and 2 for l > 0 (a real field
 // takes c_l and its conjugate partner -l; the l = 0 column enters through its real part)
 __global__ void __launch_bounds__(kThreads) k_scale_modes(DevPlan P, double2* __restrict__ v) {
@@ -4783,6 +4956,37 @@ lmvd_status lmvd_project_adjoint(lmvd_plan plan, int32_t kind, const void* coeff
   hipLaunchKernelGGL(k_project_t, dim3((ncol + kThreads - 1) / kThreads), dim3(kThreads), 0,
                      static_cast<hipStream_t>(stream), plan->D, int(kind), static_cast<const double2*>(coeffs),
                      static_cast<double2*>(values));
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_md_adjoint(lmvd_plan plan, const void* m1, const void* m2, const void* m3, void* phi2,
+                           void* omega2, double* m1bar, double* m3bar, void* workspace, void* stream) {
+  if (!plan || !m1 || !m2 || !m3 || !phi2 || !omega2 || !m1bar || !m3bar || !workspace) return LMVD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
+  if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lmvd::ensure_factors(plan, s);
+  const size_t ncol = size_t(plan->H.nn) * plan->H.nl;
+  double2* scr = reinterpret_cast<double2*>(static_cast<char*>(workspace) + plan->ws.off_yt);
+  hipLaunchKernelGGL(k_md_t, dim3((ncol + kThreads - 1) / kThreads), dim3(kThreads), 0, s, plan->D,
+                     static_cast<const double2*>(m1), static_cast<const double2*>(m2),
+                     static_cast<const double2*>(m3), static_cast<double2*>(phi2), static_cast<double2*>(omega2),
+                     m1bar, m3bar, scr);
+  return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_mc_adjoint(lmvd_plan plan, const void* m1, const void* m2, const void* m3, void* rhot,
+                           void* workspace, void* stream) {
+  if (!plan || !m1 || !m2 || !m3 || !rhot || !workspace) return LMVD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
+  if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lmvd::ensure_factors(plan, s);
+  const size_t ncol = size_t(plan->H.nn) * plan->H.nl;
+  double2* scr = reinterpret_cast<double2*>(static_cast<char*>(workspace) + plan->ws.off_yt);
+  hipLaunchKernelGGL(k_mc_t, dim3((ncol + kThreads - 1) / kThreads), dim3(kThreads), 0, s, plan->D,
+                     static_cast<const double2*>(m1), static_cast<const double2*>(m2),
+                     static_cast<const double2*>(m3), static_cast<double2*>(rhot), scr);
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
 }
 

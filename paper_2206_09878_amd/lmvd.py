@@ -59,7 +59,7 @@ EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_
            "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop", "lmvd_graph_create",
            "lmvd_graph_launch", "lmvd_graph_destroy", "lmvd_graph_grouped", "lmvd_autotune",
            "lmvd_graph_autotune", "lmvd_rhs", "lmvd_to_physical_adjoint", "lmvd_evaluate_adjoint",
-           "lmvd_project_adjoint"]
+           "lmvd_project_adjoint", "lmvd_md_adjoint", "lmvd_mc_adjoint"]
 
 
 def library():
@@ -87,6 +87,8 @@ def library():
         lib.lmvd_to_physical_adjoint.argtypes = [vp] * 5
         lib.lmvd_evaluate_adjoint.argtypes = [vp, i32, i32, vp, vp, vp]
         lib.lmvd_project_adjoint.argtypes = [vp, i32, vp, vp, vp]
+        lib.lmvd_md_adjoint.argtypes = [vp] * 10
+        lib.lmvd_mc_adjoint.argtypes = [vp] * 7
         lib.lmvd_host_tables.argtypes = [ctypes.POINTER(Config), vp, vp, vp, vp, vp]
         lib.lmvd_profile_start.argtypes = [vp, i32, i32]
         lib.lmvd_profile_stop.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
@@ -297,6 +299,23 @@ class Plan:
         out = self.empty()
         _check(library().lmvd_project_adjoint(self.handle, kind, _ptr(coeffs), _ptr(out), self._stream()),
                "lmvd_project_adjoint")
+        return out
+
+    def md_adjoint(self, m1, m2, m3):
+        """Transpose of md: adjoints of (m1, m2, m3) -> adjoints of (phi2, Omega2, <m>1, <m>3)."""
+        torch = self.torch
+        phi, om = self.empty(), self.empty()
+        b1 = torch.empty(self.w.n2, dtype=torch.float64, device="cuda")
+        b3 = torch.empty(self.w.n2, dtype=torch.float64, device="cuda")
+        _check(library().lmvd_md_adjoint(self.handle, _ptr(m1), _ptr(m2), _ptr(m3), _ptr(phi), _ptr(om), _ptr(b1),
+                                         _ptr(b3), _ptr(self.ws), self._stream()), "lmvd_md_adjoint")
+        return phi, om, b1, b3
+
+    def mc_adjoint(self, m1, m2, m3):
+        """Transpose of mc: adjoints of (m1, m2, m3) -> adjoint of rho_t (B coefficients)."""
+        out = self.empty()
+        _check(library().lmvd_mc_adjoint(self.handle, _ptr(m1), _ptr(m2), _ptr(m3), _ptr(out), _ptr(self.ws),
+                                         self._stream()), "lmvd_mc_adjoint")
         return out
 
     def md(self, phi2, omega2, m1bar, m3bar):

@@ -127,3 +127,73 @@ def test_gradient_matches_central_differences(torch):
             fd = (loss(v + eps * d) - loss(v - eps * d)).item() / (2 * eps)
             an = rdot(torch, grad, d)
             assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (k, fd, an)
+
+
+@pytest.mark.parametrize("n,n2", [(32, 33), (48, 49)])
+def test_md_transpose(torch, n, n2):
+    """<md(x), y> = <x, md^T(y)> for x = (phi2, Omega2, <m>1, <m>3) and y = (m1, m2 in B*, m3); and
+    md^T against the oracle's m^d written as a dense real matrix on one column."""
+    p = plan_of(n, n2)
+    w = p.w
+    phi, om = crand(torch, w.shape, 7), crand(torch, w.shape, 8)
+    b1 = torch.randn(w.n2, dtype=torch.float64, device="cuda")
+    b3 = torch.randn(w.n2, dtype=torch.float64, device="cuda")
+    y1, y2, y3 = crand(torch, w.shape, 9), crand(torch, w.shape_star, 10), crand(torch, w.shape, 11)
+    m1, m2, m3 = p.md(phi, om, b1, b3)
+    lhs = rdot(torch, m1, y1) + rdot(torch, m2, y2) + rdot(torch, m3, y3)
+    tp, to, t1, t3 = p.md_adjoint(y1, y2, y3)
+    rhs = rdot(torch, phi, tp) + rdot(torch, om, to) + rdot(torch, b1, t1) + rdot(torch, b3, t3)
+    torch.cuda.synchronize()
+    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs)), (lhs, rhs)
+    # one column (l, n) = (3, 2) through the oracle, as a dense matrix of phi2 -> m2 (real and imaginary
+    # unit inputs): its transpose applied to y2's column equals phi2_bar's column (from the m2 part)
+    from oracle.lmvd import divergence_free_momentum
+    op = OPlan(oracle_config(w))
+    ni, l = 2, 3
+    z = np.zeros(w.shape, dtype=complex)
+    zb = np.zeros(w.n2)
+    y2c = y2.cpu().numpy()[:, ni, l]
+    cols = []
+    for k in range(2 * w.n2):
+        e = np.zeros(w.shape, dtype=complex)
+        e[k % w.n2, ni, l] = 1.0 if k < w.n2 else 1j
+        cols.append(divergence_free_momentum(op, e, z, zb, zb)[1][:, ni, l])
+    A = np.array(cols).T                                   # m2 column (complex) <- (Re, Im) of phi2 column
+    Ar = np.vstack([A.real, A.imag])                       # real form
+    g = Ar.T @ np.concatenate([y2c.real, y2c.imag])
+    zero = torch.zeros_like(y1)
+    tp2 = p.md_adjoint(zero, y2, zero)[0].cpu().numpy()[:, ni, l]
+    assert np.abs(tp2 - (g[:w.n2] + 1j * g[w.n2:])).max() < 1e-10 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("n,n2", [(32, 33), (48, 49)])
+def test_mc_transpose(torch, n, n2):
+    """<mc(rho_t), y> = <rho_t, mc^T(y)> (the (0,0) column with its plane-mean system included), and
+    mc^T against the oracle's m^c written as a dense real matrix on one column and on the mean column."""
+    p = plan_of(n, n2)
+    w = p.w
+    r = crand(torch, w.shape, 12)
+    y1, y2, y3 = crand(torch, w.shape, 13), crand(torch, w.shape_star, 14), crand(torch, w.shape, 15)
+    m1, m2, m3 = p.mc(r)
+    lhs = rdot(torch, m1, y1) + rdot(torch, m2, y2) + rdot(torch, m3, y3)
+    rt = p.mc_adjoint(y1, y2, y3)
+    rhs = rdot(torch, r, rt)
+    torch.cuda.synchronize()
+    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs)), (lhs, rhs)
+    from oracle.lmvd import curl_free_momentum
+    op = OPlan(oracle_config(w))
+    ys = [y.cpu().numpy() for y in (y1, y2, y3)]
+    got = rt.cpu().numpy()
+    for ni, l in ((2, 3), (0, 0)):
+        cols = []
+        for k in range(2 * w.n2):
+            e = np.zeros(w.shape, dtype=complex)
+            e[k % w.n2, ni, l] = 1.0 if k < w.n2 else 1j
+            out = curl_free_momentum(op, e)
+            cols.append(np.concatenate([out[0][:, ni, l], out[1][:, ni, l], out[2][:, ni, l]]))
+        A = np.array(cols).T
+        Ar = np.vstack([A.real, A.imag])
+        yc = np.concatenate([ys[0][:, ni, l], ys[1][:, ni, l], ys[2][:, ni, l]])
+        g = Ar.T @ np.concatenate([yc.real, yc.imag])
+        ref = g[:w.n2] + 1j * g[w.n2:]
+        assert np.abs(got[:, ni, l] - ref).max() < 1e-10 * np.abs(ref).max(), (ni, l)
