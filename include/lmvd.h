@@ -288,6 +288,10 @@ lmvd_status lmvd_rhs(lmvd_plan plan, const void* z, const void* m1, const void* 
  * not aliased.  All device pointers; asynchronous. */
 lmvd_status lmvd_to_physical_adjoint(lmvd_plan plan, const double* phys, void* values, void* workspace,
                                      void* stream);
+/* Transpose of lmvd_to_spectral (same contract): the inverse transform of values / (M1 M3 w_l), w_0 = 1,
+ * w_l = 2.  values (S-field) in, phys out; workspace as for lmvd_to_physical. */
+lmvd_status lmvd_to_spectral_adjoint(lmvd_plan plan, const void* values, double* phys, void* workspace,
+                                     void* stream);
 lmvd_status lmvd_evaluate_adjoint(lmvd_plan plan, int32_t deriv, int32_t star, const void* values, void* coeffs,
                                   void* stream);
 lmvd_status lmvd_project_adjoint(lmvd_plan plan, int32_t kind, const void* coeffs, void* values, void* stream);

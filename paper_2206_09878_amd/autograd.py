@@ -4,7 +4,7 @@ Each operator is a torch.autograd.Function whose forward is the library's
 operator and whose backward is its transpose (lmvd_*_adjoint), so gradients of
 real losses follow PyTorch's convention for complex inputs (dL/dRe + i dL/dIm).
 
-    from paper_2206_09878_amd.autograd import to_physical, evaluate, project
+    from paper_2206_09878_amd.autograd import to_physical, to_spectral, evaluate, project, mc
     loss = (to_physical(plan, evaluate(plan, 0, project(plan, 0, v))) * w).sum()
     loss.backward()          # v.grad through P^T, E_0^T and the transposed transform
 
@@ -24,6 +24,29 @@ class _ToPhysical(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         return None, ctx.plan.to_physical_adjoint(g.contiguous())
+
+
+class _ToSpectral(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, phys):
+        ctx.plan = plan
+        return plan.to_spectral(phys.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return None, ctx.plan.to_spectral_adjoint(g.contiguous())
+
+
+class _Mc(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, rhot):
+        ctx.plan = plan
+        return plan.mc(rhot.contiguous())
+
+    @staticmethod
+    def backward(ctx, g1, g2, g3):
+        z = lambda g, star: g.contiguous() if g is not None else ctx.plan.empty(star).zero_()
+        return None, ctx.plan.mc_adjoint(z(g1, False), z(g2, True), z(g3, False))
 
 
 class _Evaluate(torch.autograd.Function):
@@ -51,6 +74,16 @@ class _Project(torch.autograd.Function):
 def to_physical(plan, values):
     """Values at the Greville points (S-field) -> physical field on the 3/2 grid, differentiable."""
     return _ToPhysical.apply(plan, values)
+
+
+def to_spectral(plan, phys):
+    """Physical field on the 3/2 grid -> values at the Greville points (S-field), differentiable."""
+    return _ToSpectral.apply(plan, phys)
+
+
+def mc(plan, rhot):
+    """m^c = (m1, m2 in B*, m3) from the B coefficients of rho_t, differentiable."""
+    return _Mc.apply(plan, rhot)
 
 
 def evaluate(plan, deriv, coeffs, star=False):

@@ -3399,12 +3399,15 @@ __global__ void __launch_bounds__(kThreads) k_mc_t(DevPlan P, const double2* __r
 
 // the inverse transform's transpose from the forward one: times M1 M3, and 2 for l > 0 (a real field
 // takes c_l and its conjugate partner -l; the l = 0 column enters through its real part)
-__global__ void __launch_bounds__(kThreads) k_scale_modes(DevPlan P, double2* __restrict__ v) {
+// (inv = 1: the forward transform's transpose divides instead, before an inverse transform)
+__global__ void __launch_bounds__(kThreads) k_scale_modes(DevPlan P, const double2* __restrict__ src,
+                                                         double2* __restrict__ v, int inv) {
   const size_t ncol = size_t(P.nn) * P.nl;
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= ncol * P.n2) return;
   const int l = int(e % size_t(P.nl));
-  v[e] = cscale(v[e], double(P.m1) * double(P.m3) * (l == 0 ? 1.0 : 2.0));
+  const double f = double(P.m1) * double(P.m3) * (l == 0 ? 1.0 : 2.0);
+  v[e] = cscale(src[e], inv ? 1.0 / f : f);
 }
 
 // ---------------------------------------------------------------------------
@@ -4996,8 +4999,22 @@ lmvd_status lmvd_to_physical_adjoint(lmvd_plan plan, const double* phys, void* v
   if (st != LMVD_OK) return st;
   const size_t n = size_t(plan->H.nn) * plan->H.nl * plan->H.n2;
   hipLaunchKernelGGL(k_scale_modes, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                     static_cast<hipStream_t>(stream), plan->D, static_cast<double2*>(values));
+                     static_cast<hipStream_t>(stream), plan->D, static_cast<const double2*>(values),
+                     static_cast<double2*>(values), 0);
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
+}
+
+lmvd_status lmvd_to_spectral_adjoint(lmvd_plan plan, const void* values, double* phys, void* workspace,
+                                     void* stream) {
+  if (!plan || !values || !phys || !workspace) return LMVD_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
+  // the scaled copy goes to a value field of the workspace that the inverse transform does not use
+  double2* tmp = reinterpret_cast<double2*>(static_cast<char*>(workspace) + plan->ws.off_vals[kMaxOut - 1]);
+  const size_t n = size_t(plan->H.nn) * plan->H.nl * plan->H.n2;
+  hipLaunchKernelGGL(k_scale_modes, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     static_cast<hipStream_t>(stream), plan->D, static_cast<const double2*>(values), tmp, 1);
+  if (hipGetLastError() != hipSuccess) return LMVD_EHIP;
+  return lmvd_to_physical(plan, tmp, phys, workspace, stream);
 }
 
 lmvd_status lmvd_rhs(lmvd_plan plan, const void* z, const void* m1, const void* m2, const void* m3, void* rhs_phi2,

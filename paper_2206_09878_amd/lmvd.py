@@ -59,7 +59,7 @@ EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_
            "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop", "lmvd_graph_create",
            "lmvd_graph_launch", "lmvd_graph_destroy", "lmvd_graph_grouped", "lmvd_autotune",
            "lmvd_graph_autotune", "lmvd_rhs", "lmvd_to_physical_adjoint", "lmvd_evaluate_adjoint",
-           "lmvd_project_adjoint", "lmvd_md_adjoint", "lmvd_mc_adjoint"]
+           "lmvd_project_adjoint", "lmvd_md_adjoint", "lmvd_mc_adjoint", "lmvd_to_spectral_adjoint"]
 
 
 def library():
@@ -89,6 +89,7 @@ def library():
         lib.lmvd_project_adjoint.argtypes = [vp, i32, vp, vp, vp]
         lib.lmvd_md_adjoint.argtypes = [vp] * 10
         lib.lmvd_mc_adjoint.argtypes = [vp] * 7
+        lib.lmvd_to_spectral_adjoint.argtypes = [vp] * 5
         lib.lmvd_host_tables.argtypes = [ctypes.POINTER(Config), vp, vp, vp, vp, vp]
         lib.lmvd_profile_start.argtypes = [vp, i32, i32]
         lib.lmvd_profile_stop.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
@@ -287,6 +288,13 @@ class Plan:
         out = self.empty()
         _check(library().lmvd_to_physical_adjoint(self.handle, _ptr(phys), _ptr(out), _ptr(self.ws), self._stream()),
                "lmvd_to_physical_adjoint")
+        return out
+
+    def to_spectral_adjoint(self, values):
+        w = self.w
+        out = self.torch.empty((w.n2, w.m3, w.m1), dtype=self.torch.float64, device="cuda")
+        _check(library().lmvd_to_spectral_adjoint(self.handle, _ptr(values), _ptr(out), _ptr(self.ws), self._stream()),
+               "lmvd_to_spectral_adjoint")
         return out
 
     def evaluate_adjoint(self, deriv, values, star=False):

@@ -1,6 +1,7 @@
 """Adjoints of the linear operators (lmvd_to_physical_adjoint,
-lmvd_evaluate_adjoint, lmvd_project_adjoint) and automatic differentiation
-through them (paper_2206_09878_amd.autograd), through the C ABI:
+lmvd_to_spectral_adjoint, lmvd_evaluate_adjoint, lmvd_project_adjoint,
+lmvd_md_adjoint, lmvd_mc_adjoint) and automatic differentiation through them
+(paper_2206_09878_amd.autograd), through the C ABI:
 
   * <A x, y> = <x, A^T y> in the real inner products for the inverse transform
     (register and generic kernels), E_0, E_1, E_2, F_0 and the three
@@ -9,7 +10,10 @@ through them (paper_2206_09878_amd.autograd), through the C ABI:
   * E_d^T and the projections' transposes equal the oracle's dense transposes
     column by column (1e-12);
   * the gradient of a real loss through project -> evaluate -> to_physical
-    matches central finite differences (eps = 1e-6) on 16 random directions.
+    matches central finite differences (eps = 1e-6) on 16 random directions;
+  * m^d and m^c transposes against dot products and the oracle's dense maps;
+  * one fixed-point iteration composed from the differentiable operators has
+    the gradient of central differences.
 """
 import numpy as np
 import pytest
@@ -62,6 +66,10 @@ def test_transform_transpose(torch, n, n2):
     lhs = rdot(torch, p.to_physical(c), g)
     rhs = rdot(torch, c, p.to_physical_adjoint(g))
     torch.cuda.synchronize()
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs) + 1e-12
+    # the forward transform's transpose
+    lhs = rdot(torch, p.to_spectral(g), c)
+    rhs = rdot(torch, g, p.to_spectral_adjoint(c))
     assert abs(lhs - rhs) < 1e-12 * abs(lhs) + 1e-12
 
 
@@ -197,3 +205,46 @@ def test_mc_transpose(torch, n, n2):
         g = Ar.T @ np.concatenate([yc.real, yc.imag])
         ref = g[:w.n2] + 1j * g[w.n2:]
         assert np.abs(got[:, ni, l] - ref).max() < 1e-10 * np.abs(ref).max(), (ni, l)
+
+
+def test_fixed_point_iteration_gradient(torch):
+    """The building blocks compose under autograd: one fixed-point iteration z_t -> L(z) z_t (eq. y_k,
+    Section 4.3), written with the differentiable operators and torch's pointwise products (rho_t =
+    f'(z) z_t on the grid, m^c, g . m^c with g = -grad z / rho, the Neumann projection), has a gradient
+    (the adjoint chain: P_N^T, the transforms' transposes, m^c^T, E^T) that matches central differences
+    on 16 random directions."""
+    from paper_2206_09878_amd.autograd import evaluate, mc, project, to_physical, to_spectral
+    from paper_2206_09878_amd.workloads import make_inputs
+    p = plan_of(32, 33)
+    w = p.w
+    z = p.to_dev(make_inputs(w, seed=60, stage=0)["z"])
+    k1 = torch.as_tensor(np.asarray(OPlan(oracle_config(w)).k1), device="cuda")
+    k3 = torch.as_tensor(np.asarray(OPlan(oracle_config(w)).k3), device="cuda")
+    with torch.no_grad():
+        v0 = p.evaluate(0, z)
+        zp = p.to_physical(v0)
+        rho = w.rho_l * w.rho_h / (w.rho_h - (w.rho_h - w.rho_l) * zp)
+        fp = rho * rho * (w.rho_h - w.rho_l) / (w.rho_l * w.rho_h)
+        g1 = -p.to_physical((1j * k1)[None, None, :] * v0) / rho
+        g2 = -p.to_physical(p.evaluate(1, z)) / rho
+        g3 = -p.to_physical((1j * k3)[None, :, None] * v0) / rho
+    W = crand(torch, w.shape, 61)
+
+    def loss(zt):
+        rt = project(p, 0, to_spectral(p, fp * to_physical(p, evaluate(p, 0, zt))))
+        m1, m2, m3 = mc(p, rt)
+        Lp = g1 * to_physical(p, evaluate(p, 0, m1)) + g2 * to_physical(p, evaluate(p, 0, m2, star=True)) \
+            + g3 * to_physical(p, evaluate(p, 0, m3))
+        out = project(p, 2, to_spectral(p, Lp))
+        return torch.sum(torch.view_as_real(W) * torch.view_as_real(out))
+
+    zt = crand(torch, w.shape, 62).requires_grad_(True)
+    loss(zt).backward()
+    grad = zt.grad.detach()
+    eps = 1e-6
+    with torch.no_grad():
+        for k in range(16):
+            d = crand(torch, w.shape, 200 + k)
+            fd = (loss(zt + eps * d) - loss(zt - eps * d)).item() / (2 * eps)
+            an = rdot(torch, grad, d)
+            assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (k, fd, an)
