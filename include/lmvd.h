@@ -163,7 +163,12 @@ lmvd_status lmvd_sizes(lmvd_plan plan, size_t* sfield_elems, size_t* sfield_star
 
 /* One substep (Algorithm time_advanceDNS) on `stream` (a hipStream_t; NULL =
  * the null stream).  Asynchronous.  Not reentrant: one plan must not run on two
- * streams at once, and concurrent calls must use distinct workspaces. */
+ * streams at once, and concurrent calls must use distinct workspaces.  It
+ * allocates nothing, issues no memset and does not synchronise (unless the plan
+ * sets check_finite), so a caller may capture it in a HIP graph.  The plan's
+ * A(k) factors are computed by the first call on the plan: make one call (or
+ * lmvd_graph_create) before a capture, or the capture records that work too.
+ * The timing hook must be off while capturing. */
 lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* args, void* workspace,
                          void* stream);
 
