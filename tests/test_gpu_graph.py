@@ -124,3 +124,34 @@ def test_graph_rejects_bad_arguments(torch):
     h = ctypes.c_void_p()
     assert library().lmvd_graph_create(plans, arr, wsp, 1, 1, ctypes.byref(h)) != 0
     assert library().lmvd_graph_create(plans, arr, wsp, 0, 1, ctypes.byref(h)) != 0
+
+
+def test_substeps_captured_in_a_caller_graph(torch):
+    """lmvd_substep allocates, memsets and synchronises nothing, so a caller can capture it: four
+    substeps captured with torch.cuda.graph, replayed three times with eager work and synchronisations
+    in between, equal the same substeps run eagerly, bit for bit, after every replay."""
+    ws = batch_workloads(count=1, seed=5000)
+    (a,), (b,) = steppers(ws), steppers(ws)
+    a.substep()                      # first call: the plan's A(k) factors, outside the capture
+    b.substep()
+    for _ in range(3):               # back to the start of the history-ring period
+        a.substep()
+        b.substep()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(4):
+                a.substep()
+    torch.cuda.synchronize()
+    for replay in range(3):
+        g.replay()
+        for _ in range(4):
+            b.substep()
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 16, device="cuda").sum()   # unrelated eager work between replays
+        for ta, tb in zip(state_tensors(a), state_tensors(b)):
+            assert torch.equal(ta, tb), replay
+        assert torch.isfinite(junk)
