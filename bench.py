@@ -287,7 +287,7 @@ def main():
     traffic = counter_traffic(names[dom], w)
     model = substep_model_bytes(w, w.kf)
     out = {
-        "metric": "RK substeps/s at 512x385x512 FP64",
+        "metric": f"RK substeps/s at {w.n1}x{w.n2}x{w.n3} FP64",
         "value": value,
         "unit": "substeps/s",
         "n_gpus": 1,
