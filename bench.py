@@ -59,6 +59,10 @@ def source_digest() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
+KIND = {"rt512": "Rayleigh-Taylor At=0.925, multimode interface", "mixing128": "temporal mixing layer",
+        "adjoint96": "temporal mixing layer", "small": "broadband random fields"}
+
+
 def counter_traffic(cls: str, w):
     """HBM bytes per launch of `cls` from the committed rocprofv3 counter summary, or None when
     there is none for this class and workload or the kernel source changed since it was taken."""
@@ -299,8 +303,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: Rayleigh-Taylor At=0.925, {w.n1}x{w.n2}x{w.n3} modes, "
-                               f"{w.m1}x{w.m3} dealiased x-z grid, k_f={w.kf}, stages n/' alternating",
+        "config": {"workload": f"{w.name}: {KIND.get(w.name, 'synthetic fields')}, density ratio "
+                               f"{w.rho_h / w.rho_l:.2f}, {w.n1}x{w.n2}x{w.n3} modes, {w.m1}x{w.m3} dealiased x-z "
+                               f"grid, k_f={w.kf}, stages n/' alternating",
                    "kf": w.kf, "plane_batch": args.plane_batch or w.n2, "transport": args.transport},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
