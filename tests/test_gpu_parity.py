@@ -97,14 +97,15 @@ def test_md_mc(torch, name, n, n2):
         assert rel(host(g), r) < TOL
 
 
-def run_pair(w, stage, seed=0, kf=None, guess_mode=0, plane_batch=0, tile=0):
-    """One substep on the GPU and in the oracle from the same inputs (tile: force the z tile divisor)."""
+def run_pair(w, stage, seed=0, kf=None, guess_mode=0, plane_batch=0, tile=0, inputs=None):
+    """One substep on the GPU and in the oracle from the same inputs (tile: force the z tile divisor;
+    inputs: a dict like make_inputs' instead of the seeded one)."""
     import torch
     p = gplan(w, plane_batch=plane_batch)
     if tile:
         assert p.autotune(force=tile)[0] == tile
     op = OPlan(oracle_config(w))
-    inp = make_inputs(w, seed=seed, stage=stage)
+    inp = make_inputs(w, seed=seed, stage=stage) if inputs is None else inputs
     st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
     kw = {}
     if stage == 1:
