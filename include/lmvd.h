@@ -46,8 +46,9 @@
  * the ABI.  LMVD_EINVAL: bad configuration, null or misaligned (not 16-byte)
  * pointer, or a bad argument value.  LMVD_EUNSUPPORTED: a grid size outside
  * what the kernels handle (M1/2 and M3 must be products of 2s and 3s with
- * M3 <= 1024 and M1/2 <= 768, N1/2 <= M1/2, N3-1 <= M3, order <= 8 (the band
- * of A(k), built on order + 1 for m2, must stay within 8), n2 <= 4096).  LMVD_ENOMEM:
+ * M3 <= 1024 and M1/2 <= 768, N1/2 <= M1/2, N3-1 <= M3, order <= 9, n2 <= 4096,
+ * and a band of A(k) (built on order + 1 for m2) within 8, which order 9 keeps
+ * only for some breakpoint distributions).  LMVD_ENOMEM:
  * host or device allocation failed in lmvd_plan_create.  LMVD_EHIP: a HIP
  * call failed.  LMVD_ENUMERIC: a factorisation without pivoting met a
  * near-zero pivot at plan creation.  LMVD_ENONFINITE: with check_finite set,
@@ -80,7 +81,7 @@ typedef enum {
 typedef struct {
   int32_t n1, n3;        /* Fourier modes, even; retained |l| <= n1/2-1, |n| <= n3/2-1 (eq. disc_f) */
   int32_t n2;            /* number of B coefficients (order-p B-splines); m2 uses n2+1 of order p+1 */
-  int32_t order;         /* p (App. C); 3 <= p <= 8                                                  */
+  int32_t order;         /* p (App. C); 3 <= p <= 9 (9: see LMVD_EUNSUPPORTED)                      */
   int32_t m1, m3;        /* physical x1, x3 grid; 3/2 rule: m = 3n/2; m1 >= n1, m3 >= n3            */
   double L1, L2, L3;     /* domain [0,L1] x [-L2/2, L2/2] x [0,L3] (Section 4)                        */
   const double* breakpoints; /* host array of n2-order+2 strictly increasing values, ends -+L2/2     */

@@ -105,3 +105,14 @@ def test_bad_breakpoints_rejected():
     cfg.breakpoints = bp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     h = ctypes.c_void_p()
     assert lmvd.library().lmvd_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+
+
+@pytest.mark.parametrize("n1,n3,n2,order", [(32, 32, 4097, 8), (32, 1024, 33, 8)])
+def test_plan_create_rejects_sizes_beyond_the_kernels(n1, n3, n2, order):
+    """n2 above 4096 (plane-mean kernel LDS) and M3 above 1024 (z transforms): LMVD_EUNSUPPORTED from
+    the host checks, before any allocation."""
+    import dataclasses
+    w = dataclasses.replace(workload("small"), n1=n1, n3=n3, n2=n2, m1=3 * n1 // 2, m3=3 * n3 // 2, order=order)
+    cfg = lmvd.make_config(w)
+    h = ctypes.c_void_p()
+    assert lmvd.library().lmvd_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == -4
