@@ -236,7 +236,7 @@ def main():
         print(json.dumps({"copy_bytes_per_dispatch": 8 * n, "dispatches": 3}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs the substep on one GPU only; sharding across GPUs is a design, "
+        print("bench.py: the substep runs on one GPU only; sharding across GPUs is designed, not implemented "
               "not a run. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
