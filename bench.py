@@ -236,8 +236,8 @@ def main():
         print(json.dumps({"copy_bytes_per_dispatch": 8 * n, "dispatches": 3}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: the substep runs on one GPU only; sharding across GPUs is designed, not implemented "
-              "not a run. Use --gpus 1.", file=sys.stderr)
+        print("bench.py: the substep runs on one GPU only; sharding across GPUs is designed, not implemented. "
+              "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
