@@ -373,6 +373,35 @@ class Stepper:
             self.zt.copy_(dev(inputs["zt_prev"]))
         self.zt_next = plan.empty()
 
+    # -- checkpoint / resume ------------------------------------------------------
+    def save(self, path):
+        """Write everything the next substeps read (z and its history ring, phi2, Omega2, the plane
+        means, the stage, and at stage ' the stored stage-n RHS and z_t) to a numpy .npz file."""
+        torch = self.p.torch
+        torch.cuda.synchronize()
+        host = lambda t: t.detach().cpu().numpy()
+        arrs = {"stage": np.array(self.stage), "z": host(self.z), "phi2": host(self.phi2),
+                "omega2": host(self.omega2), "m1bar": host(self.m1bar), "m3bar": host(self.m3bar),
+                "zt": host(self.zt)}
+        for i, h in enumerate(self.hist):
+            arrs[f"hist{i}"] = host(h)
+        for k, v in self.rhs.items():
+            arrs[f"rhs_{k}"] = host(v)
+        np.savez(path, **arrs)
+
+    @classmethod
+    def load(cls, plan, path):
+        """A Stepper on `plan` resumed from a file written by save(); the plan must have the same sizes."""
+        with np.load(path) as d:
+            if d["z"].shape != tuple(plan.shape):
+                raise LmvdError(f"checkpoint shape {d['z'].shape} does not match the plan's {tuple(plan.shape)}")
+            stage = int(d["stage"])
+            inputs = {k: d[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
+            inputs["hist"] = [d[f"hist{i}"] for i in range(3)]
+            inputs["rhs_prev"] = {k: d[f"rhs_{k}"] for k in ("phi2", "omega2", "m1bar", "m3bar")}
+            inputs["zt_prev"] = d["zt"]
+        return cls(plan, inputs, stage=stage)
+
     def next_args(self, kf=-1):
         """Argument struct of the next substep; advances the state bookkeeping
         (history ring, stage) without launching anything."""

@@ -155,3 +155,24 @@ def test_substeps_captured_in_a_caller_graph(torch):
         for ta, tb in zip(state_tensors(a), state_tensors(b)):
             assert torch.equal(ta, tb), replay
         assert torch.isfinite(junk)
+
+
+@pytest.mark.parametrize("split", [3, 4])
+def test_checkpoint_resume_is_bit_identical(torch, tmp_path, split):
+    """Stepper.save after `split` substeps (stage ' or n next), Stepper.load on a fresh plan, then the
+    remaining substeps: the same bits as the uninterrupted run."""
+    from paper_2206_09878_amd.lmvd import Plan, Stepper
+    (w,) = batch_workloads(count=1, seed=5100)
+    (a,) = steppers([w])
+    for _ in range(split):
+        a.substep()
+    path = str(tmp_path / "state.npz")
+    a.save(path)
+    b = Stepper.load(Plan(w), path)
+    assert b.stage == a.stage
+    for _ in range(8 - split):
+        a.substep()
+        b.substep()
+    torch.cuda.synchronize()
+    for k in ("z", "phi2", "omega2", "m1bar", "m3bar"):
+        assert torch.equal(a.state()[k], b.state()[k]), k
