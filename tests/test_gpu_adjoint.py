@@ -248,3 +248,71 @@ def test_fixed_point_iteration_gradient(torch):
             fd = (loss(zt + eps * d) - loss(zt - eps * d)).item() / (2 * eps)
             an = rdot(torch, grad, d)
             assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (k, fd, an)
+
+
+def test_rhs_gradient_through_the_operators(torch):
+    """Steps 4 and 5 (RHS of phi2, eq. phi with the body force) written with the differentiable
+    operators and torch's pointwise products: u = m/rho, T_ij = -m_i m_j/rho + tau_ij on the 3/2 grid,
+    T_hat, N_i, RHS_phi2 = -k^2 N2 - d/dy(i k1 N1 + i k3 N3) + k^2 g rho, Dirichlet projection.  Its value
+    equals lmvd_rhs (the native kernels) and its gradient in m1 matches central differences."""
+    from paper_2206_09878_amd.autograd import evaluate, project, to_physical, to_spectral
+    from paper_2206_09878_amd.workloads import make_inputs
+    p = plan_of(32, 33)
+    w = p.w
+    op = OPlan(oracle_config(w))
+    ik1 = torch.as_tensor(1j * np.asarray(op.k1), device="cuda")[None, None, :]
+    ik3 = torch.as_tensor(1j * np.asarray(op.k3), device="cuda")[None, :, None]
+    ksq = torch.as_tensor(np.asarray(op.ksq), device="cuda")[None]
+    inp = make_inputs(w, seed=80, stage=0)
+    z = p.to_dev(inp["z"])
+    m1, m2, m3 = p.md(p.to_dev(inp["phi2"]), p.to_dev(inp["omega2"]), p.to_dev(inp["m1bar"]),
+                      p.to_dev(inp["m3bar"]))
+    mu, g = w.mu, w.g
+    with torch.no_grad():
+        zp = p.to_physical(p.evaluate(0, z))
+        rho = w.rho_l * w.rho_h / (w.rho_h - (w.rho_h - w.rho_l) * zp)
+
+    def rhs_phi(m1_):
+        mp = [to_physical(p, evaluate(p, 0, m1_)), to_physical(p, evaluate(p, 0, m2, star=True)),
+              to_physical(p, evaluate(p, 0, m3))]
+        uh = [project(p, 0, to_spectral(p, x / rho)) for x in mp]
+        d = []
+        for ui in uh:
+            v0 = evaluate(p, 0, ui)
+            d.append([to_physical(p, ik1 * v0), to_physical(p, evaluate(p, 1, ui)), to_physical(p, ik3 * v0)])
+        theta = d[0][0] + d[1][1] + d[2][2]
+        Th = {}
+        for i, j in ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)):
+            t = -mp[i] * mp[j] / rho + mu * (d[i][j] + d[j][i])
+            if i == j:
+                t = t - (2.0 / 3.0) * mu * theta
+            Th[(i, j)] = Th[(j, i)] = project(p, 0, to_spectral(p, t))
+        N = [ik1 * evaluate(p, 0, Th[(i, 0)]) + evaluate(p, 1, Th[(i, 1)]) + ik3 * evaluate(p, 0, Th[(i, 2)])
+             for i in range(3)]
+        dN = [ik1 * evaluate(p, 1, Th[(i, 0)]) + evaluate(p, 2, Th[(i, 1)]) + ik3 * evaluate(p, 1, Th[(i, 2)])
+              for i in range(3)]
+        R = -ksq * N[1] - (ik1 * dN[0] + ik3 * dN[2]) + ksq * g * to_spectral(p, rho)
+        mask = torch.ones_like(R)
+        mask[:, 0, 0] = 0.0
+        return project(p, 1, R * mask)
+
+    with torch.no_grad():
+        native = p.rhs(z, m1, m2, m3)["phi2"]
+        composed = rhs_phi(m1)
+    torch.cuda.synchronize()
+    err = (composed - native).abs().max().item() / native.abs().max().item()
+    print("composed vs native RHS_phi2", err, flush=True)
+    assert err < 1e-10
+    W = crand(torch, w.shape, 81)
+    loss = lambda x: torch.sum(torch.view_as_real(W) * torch.view_as_real(rhs_phi(x)))
+    x = m1.clone().requires_grad_(True)
+    loss(x).backward()
+    grad = x.grad.detach()
+    scale = m1.abs().max().item()
+    eps = 1e-6 * scale
+    with torch.no_grad():
+        for k in range(16):
+            dvec = crand(torch, w.shape, 300 + k)
+            fd = (loss(m1 + eps * dvec) - loss(m1 - eps * dvec)).item() / (2 * eps)
+            an = rdot(torch, grad, dvec)
+            assert abs(fd - an) < 1e-5 * max(1.0, abs(an)), (k, fd, an)
