@@ -4,7 +4,7 @@ Each operator is a torch.autograd.Function whose forward is the library's
 operator and whose backward is its transpose (lmvd_*_adjoint), so gradients of
 real losses follow PyTorch's convention for complex inputs (dL/dRe + i dL/dIm).
 
-    from paper_2206_09878_amd.autograd import to_physical, to_spectral, evaluate, project, mc
+    from paper_2206_09878_amd.autograd import to_physical, to_spectral, evaluate, project, md, mc
     loss = (to_physical(plan, evaluate(plan, 0, project(plan, 0, v))) * w).sum()
     loss.backward()          # v.grad through P^T, E_0^T and the transposed transform
 
@@ -49,6 +49,19 @@ class _Mc(torch.autograd.Function):
         return None, ctx.plan.mc_adjoint(z(g1, False), z(g2, True), z(g3, False))
 
 
+class _Md(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, phi2, omega2, m1bar, m3bar):
+        ctx.plan = plan
+        return plan.md(phi2.contiguous(), omega2.contiguous(), m1bar.contiguous(), m3bar.contiguous())
+
+    @staticmethod
+    def backward(ctx, g1, g2, g3):
+        z = lambda g, star: g.contiguous() if g is not None else ctx.plan.empty(star).zero_()
+        tp, to, t1, t3 = ctx.plan.md_adjoint(z(g1, False), z(g2, True), z(g3, False))
+        return None, tp, to, t1, t3
+
+
 class _Evaluate(torch.autograd.Function):
     @staticmethod
     def forward(ctx, plan, deriv, star, coeffs):
@@ -79,6 +92,11 @@ def to_physical(plan, values):
 def to_spectral(plan, phys):
     """Physical field on the 3/2 grid -> values at the Greville points (S-field), differentiable."""
     return _ToSpectral.apply(plan, phys)
+
+
+def md(plan, phi2, omega2, m1bar, m3bar):
+    """m^d = (m1, m2 in B*, m3) from (phi2, Omega2, <m>1, <m>3), differentiable."""
+    return _Md.apply(plan, phi2, omega2, m1bar, m3bar)
 
 
 def mc(plan, rhot):

@@ -316,3 +316,129 @@ def test_rhs_gradient_through_the_operators(torch):
             fd = (loss(m1 + eps * dvec) - loss(m1 - eps * dvec)).item() / (2 * eps)
             an = rdot(torch, grad, dvec)
             assert abs(fd - an) < 1e-5 * max(1.0, abs(an)), (k, fd, an)
+
+
+def composed_substep(torch, p, op, st, hist):
+    """One stage-n substep (Algorithm time_advanceDNS, in the oracle's order) written with the
+    differentiable operators and torch's pointwise products; returns the new state and z_t."""
+    from paper_2206_09878_amd.autograd import evaluate, mc, md, project, to_physical, to_spectral
+    w = p.w
+    ik1 = torch.as_tensor(1j * np.asarray(op.k1), device="cuda")[None, None, :]
+    ik3 = torch.as_tensor(1j * np.asarray(op.k3), device="cuda")[None, :, None]
+    ksq = torch.as_tensor(np.asarray(op.ksq), device="cuda")[None]
+    phys = lambda v: to_physical(p, v)
+    spec = lambda x: to_spectral(p, x)
+    phi2, om2, z, m1bar, m3bar = st
+    # 1. m^d
+    md1, md2, md3 = md(p, phi2, om2, m1bar, m3bar)
+    # 2. R_z and the fields fixed during the substep
+    Vz = evaluate(p, 0, z)
+    zp = phys(Vz)
+    z1, z2, z3 = phys(ik1 * Vz), phys(evaluate(p, 1, z)), phys(ik3 * Vz)
+    lap = phys(evaluate(p, 2, z) - ksq * Vz)
+    rho = w.rho_l * w.rho_h / (w.rho_h - (w.rho_h - w.rho_l) * zp)
+    fp = rho * rho * (w.rho_h - w.rho_l) / (w.rho_l * w.rho_h)
+    mdp = [phys(evaluate(p, 0, md1)), phys(evaluate(p, 0, md2, star=True)), phys(evaluate(p, 0, md3))]
+    Rz = project(p, 2, spec((-(mdp[0] * z1 + mdp[1] * z2 + mdp[2] * z3) + w.rhoD * lap) / rho))
+    # BDF-like guess, stage n with beta^n = 0: dt z_t = 2 z - 2 z^{n-1,'}
+    zt = (2.0 * z - 2.0 * hist[0]) / w.dt
+
+    def mc_of(zt_):
+        return mc(p, project(p, 0, spec(fp * phys(evaluate(p, 0, zt_)))))
+
+    # 3. fixed-point iterations
+    for _ in range(w.kf):
+        c1, c2, c3 = mc_of(zt)
+        L = -(z1 * phys(evaluate(p, 0, c1)) + z2 * phys(evaluate(p, 0, c2, star=True))
+              + z3 * phys(evaluate(p, 0, c3))) / rho
+        zt = project(p, 2, spec(L)) + Rz
+    c1, c2, c3 = mc_of(zt)
+    m = [md1 + c1, md2 + c2, md3 + c3]
+    # 4./5. fluxes and right-hand sides
+    mp = [phys(evaluate(p, 0, m[0])), phys(evaluate(p, 0, m[1], star=True)), phys(evaluate(p, 0, m[2]))]
+    uh = [project(p, 0, spec(x / rho)) for x in mp]
+    d = []
+    for ui in uh:
+        v0 = evaluate(p, 0, ui)
+        d.append([phys(ik1 * v0), phys(evaluate(p, 1, ui)), phys(ik3 * v0)])
+    theta = d[0][0] + d[1][1] + d[2][2]
+    Th = {}
+    for i, j in ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)):
+        t = -mp[i] * mp[j] / rho + w.mu * (d[i][j] + d[j][i])
+        if i == j:
+            t = t - (2.0 / 3.0) * w.mu * theta
+        Th[(i, j)] = Th[(j, i)] = project(p, 0, spec(t))
+    N = [ik1 * evaluate(p, 0, Th[(i, 0)]) + evaluate(p, 1, Th[(i, 1)]) + ik3 * evaluate(p, 0, Th[(i, 2)])
+         for i in range(3)]
+    dN = [ik1 * evaluate(p, 1, Th[(i, 0)]) + evaluate(p, 2, Th[(i, 1)]) + ik3 * evaluate(p, 1, Th[(i, 2)])
+          for i in range(3)]
+    mask = torch.ones_like(Vz)
+    mask[:, 0, 0] = 0.0
+    R_phi = project(p, 1, mask * (-ksq * N[1] - (ik1 * dN[0] + ik3 * dN[2]) + ksq * w.g * spec(rho)))
+    R_om = project(p, 1, mask * (ik3 * N[0] - ik1 * N[2]))
+    col = 1.0 - mask                                  # the (0,0) column alone
+
+    def mean_rhs(T):
+        return project(p, 2, col * evaluate(p, 1, T).real.to(Vz.dtype))[:, 0, 0].real
+
+    R1, R3 = mean_rhs(Th[(0, 1)]), mean_rhs(Th[(2, 1)])
+    h = 0.5 * w.dt
+    return dict(z=z + h * zt, phi2=phi2 + h * R_phi, omega2=om2 + h * R_om, m1bar=m1bar + h * R1,
+                m3bar=m3bar + h * R3, zt=zt)
+
+
+def test_substep_gradient_through_the_operators(torch):
+    """The whole stage-n substep composed from the differentiable operators equals lmvd_substep (the
+    native kernels) on every output, and the gradient of a real objective of its outputs with respect
+    to the input z (through rho(z), R_z, the guess, the fixed point, m^c, the fluxes and RK2) matches
+    Richardson-extrapolated central differences on 16 random directions."""
+    from paper_2206_09878_amd.workloads import make_inputs
+    p = plan_of(32, 33)
+    w = p.w
+    op = OPlan(oracle_config(w))
+    inp = make_inputs(w, seed=90, stage=0)
+    st = [p.to_dev(inp[k]) for k in ("phi2", "omega2", "z", "m1bar", "m3bar")]
+    hist = [p.to_dev(h) for h in inp["hist"]]
+    with torch.no_grad():
+        ref = composed_substep(torch, p, op, st, hist)
+    # the native substep from the same inputs
+    d = [x.clone() for x in st]
+    z_out, zt = p.empty(), p.empty()
+    rhs = {"phi2": p.empty(), "omega2": p.empty(),
+           "m1bar": torch.empty(w.n2, dtype=torch.float64, device="cuda"),
+           "m3bar": torch.empty(w.n2, dtype=torch.float64, device="cuda")}
+    p.substep(0, d[0], d[1], d[2], d[3], d[4], z_out=z_out, hist=hist, rhs_out=rhs, zt_out=zt)
+    torch.cuda.synchronize()
+    native = dict(phi2=d[0], omega2=d[1], z=z_out, m1bar=d[3], m3bar=d[4], zt=zt)
+    for k, v in native.items():
+        e = (ref[k] - v).abs().max().item() / max(v.abs().max().item(), 1e-300)
+        print("composed vs native", k, e, flush=True)
+        assert e < 1e-9, (k, e)
+    W = {k: (crand(torch, w.shape, 91 + i) if k in ("z", "phi2", "omega2") else
+             torch.randn(w.n2, dtype=torch.float64, device="cuda")) for i, k in enumerate(("z", "phi2", "omega2",
+                                                                                         "m1bar", "m3bar"))}
+
+    def loss(z):
+        out = composed_substep(torch, p, op, [st[0], st[1], z, st[3], st[4]], hist)
+        tot = 0.0
+        for k, wk in W.items():
+            o = out[k]
+            tot = tot + (torch.sum(torch.view_as_real(wk) * torch.view_as_real(o)) if o.is_complex()
+                         else torch.sum(wk * o))
+        return tot
+
+    z0 = st[2].clone().requires_grad_(True)
+    loss(z0).backward()
+    grad = z0.grad.detach()
+    # central differences at eps and eps/2, Richardson-extrapolated: the objective has large third
+    # derivatives (the guess carries 1/dt), so plain central differences carry a visible O(eps^2) term
+    eps = 1e-6 * st[2].abs().max().item()
+    with torch.no_grad():
+        for k in range(16):
+            dvec = crand(torch, w.shape, 400 + k)
+            c = lambda e: (loss(st[2] + e * dvec) - loss(st[2] - e * dvec)).item() / (2 * e)
+            f1, f2 = c(eps), c(0.5 * eps)
+            fd = (4.0 * f2 - f1) / 3.0
+            an = rdot(torch, grad, dvec)
+            print("direction", k, "central", f1, "extrapolated", fd, "adjoint", an, flush=True)
+            assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (k, f1, fd, an)
