@@ -318,9 +318,10 @@ def test_rhs_gradient_through_the_operators(torch):
             assert abs(fd - an) < 1e-5 * max(1.0, abs(an)), (k, fd, an)
 
 
-def composed_substep(torch, p, op, st, hist):
-    """One stage-n substep (Algorithm time_advanceDNS, in the oracle's order) written with the
-    differentiable operators and torch's pointwise products; returns the new state and z_t."""
+def composed_substep(torch, p, op, st, hist, stage=0, prev=None):
+    """One substep (Algorithm time_advanceDNS, in the oracle's order) written with the differentiable
+    operators and torch's pointwise products; returns the new state, this stage's RHS and z_t.
+    Stage ' takes prev = (RHS, z_t) of stage n."""
     from paper_2206_09878_amd.autograd import evaluate, mc, md, project, to_physical, to_spectral
     w = p.w
     ik1 = torch.as_tensor(1j * np.asarray(op.k1), device="cuda")[None, None, :]
@@ -340,8 +341,10 @@ def composed_substep(torch, p, op, st, hist):
     fp = rho * rho * (w.rho_h - w.rho_l) / (w.rho_l * w.rho_h)
     mdp = [phys(evaluate(p, 0, md1)), phys(evaluate(p, 0, md2, star=True)), phys(evaluate(p, 0, md3))]
     Rz = project(p, 2, spec((-(mdp[0] * z1 + mdp[1] * z2 + mdp[2] * z3) + w.rhoD * lap) / rho))
-    # BDF-like guess, stage n with beta^n = 0: dt z_t = 2 z - 2 z^{n-1,'}
-    zt = (2.0 * z - 2.0 * hist[0]) / w.dt
+    # BDF-like guess (eq. dzdt_guesses, beta^n = 0, beta' = -4): dt z_t = a . (z, h1, h2, h3)
+    bp = w.beta_p
+    a = (2.0, -2.0, 0.0, 0.0) if stage == 0 else (4.0 + bp, -(5.0 + 2.0 * bp), bp, 1.0)
+    zt = (a[0] * z + a[1] * hist[0] + a[2] * hist[1] + a[3] * hist[2]) / w.dt
 
     def mc_of(zt_):
         return mc(p, project(p, 0, spec(fp * phys(evaluate(p, 0, zt_)))))
@@ -382,9 +385,18 @@ def composed_substep(torch, p, op, st, hist):
         return project(p, 2, col * evaluate(p, 1, T).real.to(Vz.dtype))[:, 0, 0].real
 
     R1, R3 = mean_rhs(Th[(0, 1)]), mean_rhs(Th[(2, 1)])
-    h = 0.5 * w.dt
-    return dict(z=z + h * zt, phi2=phi2 + h * R_phi, omega2=om2 + h * R_om, m1bar=m1bar + h * R1,
-                m3bar=m3bar + h * R3, zt=zt)
+    R = dict(phi2=R_phi, omega2=R_om, m1bar=R1, m3bar=R3)
+    X = dict(phi2=phi2, omega2=om2, m1bar=m1bar, m3bar=m3bar)
+    if stage == 0:
+        out = {k: X[k] + 0.5 * w.dt * R[k] for k in X}
+        out["z"] = z + 0.5 * w.dt * zt
+    else:
+        Rp, ztp = prev
+        out = {k: X[k] + w.dt * (R[k] - 0.5 * Rp[k]) for k in X}
+        out["z"] = z + w.dt * (zt - 0.5 * ztp)
+    out["zt"] = zt
+    out["rhs"] = R
+    return out
 
 
 def test_substep_gradient_through_the_operators(torch):
@@ -442,3 +454,64 @@ def test_substep_gradient_through_the_operators(torch):
             an = rdot(torch, grad, dvec)
             print("direction", k, "central", f1, "extrapolated", fd, "adjoint", an, flush=True)
             assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (k, f1, fd, an)
+
+
+def test_multistep_gradient_with_checkpoints(torch):
+    """The adjoint workload's pattern at 32 x 33 x 32: 4 RK steps (8 substeps, stages n and ' with
+    the z history ring) composed from the differentiable operators, checkpointed every 2 RK steps
+    (torch.utils.checkpoint recomputes each segment's forward in the backward pass); objective the
+    kinetic energy of m^d at the final time, (1/2) mean |m^d|^2 / rho on the 3/2 grid; gradient with
+    respect to the initial z.  The checkpointed gradient equals the one kept in memory, and matches
+    Richardson-extrapolated central differences on 4 random directions."""
+    from torch.utils.checkpoint import checkpoint
+
+    from paper_2206_09878_amd.autograd import evaluate, md, to_physical
+    from paper_2206_09878_amd.workloads import make_inputs
+    p = plan_of(32, 33)
+    w = p.w
+    op = OPlan(oracle_config(w))
+    inp = make_inputs(w, seed=95, stage=0)
+    st0 = [p.to_dev(inp[k]) for k in ("phi2", "omega2", "z", "m1bar", "m3bar")]
+    hist0 = [p.to_dev(h) for h in inp["hist"]]
+
+    def rk_step(phi2, om2, z, m1bar, m3bar, h1, h2, h3):
+        a = composed_substep(torch, p, op, [phi2, om2, z, m1bar, m3bar], [h1, h2, h3], stage=0)
+        zp = a["z"]
+        b = composed_substep(torch, p, op, [a["phi2"], a["omega2"], zp, a["m1bar"], a["m3bar"]], [z, h1, h2],
+                             stage=1, prev=(a["rhs"], a["zt"]))
+        # history for the next stage n: z^{n,'}, z^n, z^{n-1,'}
+        return b["phi2"], b["omega2"], b["z"], b["m1bar"], b["m3bar"], zp, z, h1
+
+    def objective(z0, ckpt):
+        carry = (st0[0], st0[1], z0, st0[3], st0[4], *hist0)
+        for seg in range(2):
+            def segment(*c):
+                for _ in range(2):
+                    c = rk_step(*c)
+                return c
+            carry = checkpoint(segment, *carry, use_reentrant=False) if ckpt else segment(*carry)
+        phi2, om2, z, m1bar, m3bar = carry[:5]
+        m1, m2, m3 = md(p, phi2, om2, m1bar, m3bar)
+        zp = to_physical(p, evaluate(p, 0, z))
+        rho = w.rho_l * w.rho_h / (w.rho_h - (w.rho_h - w.rho_l) * zp)
+        ke = sum(to_physical(p, evaluate(p, 0, m, star=(i == 1))) ** 2 for i, m in enumerate((m1, m2, m3)))
+        return 0.5 * torch.mean(ke / rho)
+
+    grads = []
+    for ckpt in (True, False):
+        z0 = st0[2].clone().requires_grad_(True)
+        objective(z0, ckpt).backward()
+        grads.append(z0.grad.detach())
+    diff = (grads[0] - grads[1]).abs().max().item() / grads[1].abs().max().item()
+    print("checkpointed vs stored gradient", diff, flush=True)
+    assert diff < 1e-12
+    eps = 1e-6 * st0[2].abs().max().item()
+    with torch.no_grad():
+        for k in range(4):
+            dvec = crand(torch, w.shape, 500 + k)
+            c = lambda e: (objective(st0[2] + e * dvec, False) - objective(st0[2] - e * dvec, False)).item() / (2 * e)
+            f1, f2 = c(eps), c(0.5 * eps)
+            fd = (4.0 * f2 - f1) / 3.0
+            an = rdot(torch, grads[0], dvec)
+            print("direction", k, "central", f1, "extrapolated", fd, "adjoint", an, flush=True)
+            assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12 * abs(f1) + 1e-300), (k, f1, fd, an)
