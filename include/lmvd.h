@@ -38,8 +38,8 @@
  *
  * Ownership.  Every state, output and workspace buffer is device memory owned
  * by the caller.  A plan owns only its constant tables, among them the
- * factors of A(k) for every (l, |n|) pair, which the first lmvd_substep of
- * the plan computes on its stream.  lmvd_substep allocates nothing, does not
+ * factors of A(k) for every (l, |n|) pair, which lmvd_plan_create computes
+ * and checks (lmvd_factor_check).  lmvd_substep allocates nothing, does not
  * synchronise the host and only enqueues work on the given stream.
  *
  * Errors.  Every entry point returns an lmvd_status; no exceptions cross
@@ -51,7 +51,8 @@
  * only for some breakpoint distributions).  LMVD_ENOMEM:
  * host or device allocation failed in lmvd_plan_create.  LMVD_EHIP: a HIP
  * call failed.  LMVD_ENUMERIC: a factorisation without pivoting met a
- * near-zero pivot at plan creation.  LMVD_ENONFINITE: with check_finite set,
+ * near-zero pivot or excessive growth at plan creation (the shared
+ * projections on the host, A(k) for every (l, |n|) pair on the device).  LMVD_ENONFINITE: with check_finite set,
  * an output of lmvd_substep holds a NaN or an infinity (the outputs are
  * written all the same).
  */
@@ -153,8 +154,9 @@ typedef struct {
 const char* lmvd_status_string(lmvd_status s);
 
 /* Build the plan: host tables (knots, Greville points, collocation and
- * derivative matrices, no-pivot LU of the shared projections, FFT twiddles)
- * and their upload to the current device.  Host-synchronous. */
+ * derivative matrices, no-pivot LU of the shared projections, FFT twiddles),
+ * their upload to the current device, and the checked A(k) factors of every
+ * (l, |n|) pair (computed on the device).  Host-synchronous. */
 lmvd_status lmvd_plan_create(const lmvd_config* cfg, lmvd_plan* out);
 lmvd_status lmvd_plan_destroy(lmvd_plan plan);
 
@@ -167,9 +169,8 @@ lmvd_status lmvd_sizes(lmvd_plan plan, size_t* sfield_elems, size_t* sfield_star
  * the null stream).  Asynchronous.  Not reentrant: one plan must not run on two
  * streams at once, and concurrent calls must use distinct workspaces.  It
  * allocates nothing, issues no memset and does not synchronise (unless the plan
- * sets check_finite), so a caller may capture it in a HIP graph.  The plan's
- * A(k) factors are computed by the first call on the plan: make one call (or
- * lmvd_graph_create) before a capture, or the capture records that work too.
+ * sets check_finite), so a caller may capture it in a HIP graph, the first
+ * call on a plan included (the A(k) factors are made at plan creation).
  * The timing hook must be off while capturing. */
 lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* args, void* workspace,
                          void* stream);
@@ -193,8 +194,7 @@ lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* args, void* wo
  * allocated, at the same addresses, while the graph exists.  A sequence of
  * args whose pointers repeat after nsub substeps (a history ring of period
  * nsub, with the stages alternating) makes repeated launches keep advancing
- * the simulations.  Computes each plan's A(k) factors first if needed
- * (synchronously).  No plan may have its timing hook active.  Host-synchronous;
+ * the simulations.  No plan may have its timing hook active.  Host-synchronous;
  * launches nothing else.  Errors: LMVD_EINVAL for bad arguments, LMVD_EHIP if
  * capture or instantiation fails (nothing is left allocated).
  * lmvd_graph_launch: asynchronous on `stream`; launches of one graph, and of
@@ -306,7 +306,7 @@ lmvd_status lmvd_project_adjoint(lmvd_plan plan, int32_t kind, const void* coeff
 /* Transpose of lmvd_md, the map (phi2, Omega2, <m>1, <m>3) -> (m1, m2, m3) of eqs. phi_poisson,
  * bc_both and md_recon, in the same inner products (the plane means as plain real vectors): from the
  * adjoints m1, m3 (S-fields, B) and m2 (B*) it writes the adjoints phi2, omega2 (S-fields) and m1bar,
- * m3bar ([n2]).  A(k)^{-T} uses the plan's A(k) factors (computed first if needed).  Per column the
+ * m3bar ([n2]).  A(k)^{-T} uses the plan's A(k) factors.  Per column the
  * adjoint of the Robin rows is zero and the (0,0) column maps to the plane means only.  workspace as
  * for lmvd_substep (one (n2+1)-row scratch field).  Device pointers, asynchronous. */
 lmvd_status lmvd_md_adjoint(lmvd_plan plan, const void* m1, const void* m2, const void* m3, void* phi2,
@@ -339,6 +339,25 @@ lmvd_status lmvd_mc_adjoint(lmvd_plan plan, const void* m1, const void* m2, cons
  * solve; re-reads through the caches are not counted. */
 lmvd_status lmvd_profile_start(lmvd_plan plan, int32_t cls, int32_t max_launches);
 lmvd_status lmvd_profile_stop(lmvd_plan plan, double* total_ms, int64_t* launches, double* alg_bytes);
+
+/* ---- the no-pivot factorisation of A(k) ----
+ * The m^d and m^c solves use one factorisation of A(k) = E*_2 - k^2 E*_0 with the Robin rows (eqs.
+ * phi_poisson, bc_both) per (l, |n|) pair, eliminated from the last row upwards without pivoting, made
+ * and checked by lmvd_plan_create for every pair of the grid: with s the largest magnitude of row i of
+ * A(k), the pivot of the row must reach 1e-12 s and no entry of the eliminated row may exceed
+ * growth_max s (1e4 at plan creation); a NaN fails too.  A plan whose factors fail is not created
+ * (LMVD_ENUMERIC).
+ * lmvd_factor_check: the result of that check for a plan (growth_max = 0), or the factorisation made
+ * and checked again with another growth_max > 0 (synchronous; the factors are the same, so the plan stays
+ * usable; the new result replaces the old).  Outputs (host, optional): the largest growth, the smallest
+ * pivot ratio, the number of rows that failed.  Returns LMVD_ENUMERIC if any row failed.
+ * lmvd_factor_check_host: the same elimination and check on the host for every distinct nonzero k^2 of
+ * the configuration's grid (no GPU; for validating a configuration before a plan); distinct_k receives
+ * the number of k^2 checked. */
+lmvd_status lmvd_factor_check(lmvd_plan plan, double growth_max, double* max_growth, double* min_pivot_ratio,
+                              int64_t* bad_rows);
+lmvd_status lmvd_factor_check_host(const lmvd_config* cfg, double growth_max, double* max_growth,
+                                   double* min_pivot_ratio, int64_t* bad_rows, int64_t* distinct_k);
 
 /* Host-only view of the plan's y-discretisation (for inspection; no GPU use):
  * Greville points tau [n2] and tau* [n2+1], and the dense matrices

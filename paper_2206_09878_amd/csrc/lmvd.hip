@@ -2088,8 +2088,15 @@ __global__ void __launch_bounds__(kThreads) k_solveA(DevPlan P, const double2* _
 // entries left of the diagonal and 1/pivot (nm_i, ns_i: the structure of A,
 // from the plan), at fac[(fac_off[i] + slot) * npairs + t].  A(k) = E*_2 - k^2 E*_0 at interior tau*, Robin rows
 // k m2 - m2' (bottom), k m2 + m2' (top) (eqs. phi_poisson, bc_both).
+// Every row is checked as it is eliminated: with s the largest magnitude of the row of A, the pivot must
+// reach kPivotMin s and no entry of the eliminated row may exceed growth_max s (a row that fails, or
+// holds a NaN, counts in stats[0]); stats[1] and stats[2] receive the largest growth and the smallest
+// pivot ratio of all pairs (bit patterns of positive floats, which order like the values).
+constexpr double kPivotMin = 1e-12;
+constexpr double kGrowthMax = 1e4;  // default growth limit of the check at plan creation
 template <int LA, int UA>
-__global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __restrict__ fac) {
+__global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __restrict__ fac, double growth_max,
+                                                        unsigned* __restrict__ stats) {
   const int nl = P.nl, nn = P.nn, n2 = P.n2, N = n2 + 1;
   const int npairs = nl * ((nn + 1) / 2);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2111,6 +2118,8 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
   const auto ew = P.es_w;
   double piv[UA][LA];  // entries left of the diagonal of pivot rows i+1 .. i+UA
   double pinv[UA];
+  unsigned bad = 0;
+  double gmax = 0.0, rmin = 1.0 / 0.0;
 #pragma unroll
   for (int m = 0; m < UA; ++m) {
     pinv[m] = 0.0;
@@ -2137,6 +2146,9 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
     }
     const int nm = P.fac_nm[i], ns = P.fac_ns[i];
     double* f = fac + size_t(P.fac_off[i]) * npairs + t;
+    double rs = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) rs = fmax(rs, fabs(a[w]));
     // eliminate columns i+UA .. i+1 with pivot rows i+UA .. i+1 (farthest first)
 #pragma unroll
     for (int m = UA; m >= 1; --m) {
@@ -2145,6 +2157,13 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
       for (int q = 1; q <= LA; ++q) a[LA + m - q] -= lm * piv[m - 1][q - 1];
       if (m <= nm) f[size_t(m - 1) * npairs] = lm;
     }
+    double big = 0.0;
+#pragma unroll
+    for (int w = 0; w <= LA; ++w) big = fmax(big, fabs(a[w]));
+    const double growth = big / rs, ratio = fabs(a[LA]) / rs;
+    if (!(ratio >= kPivotMin) || !(growth <= growth_max)) ++bad;
+    gmax = fmax(gmax, growth);
+    rmin = fmin(rmin, ratio);
     const double dinv = 1.0 / a[LA];
 #pragma unroll
     for (int q = 1; q <= LA; ++q)
@@ -2160,6 +2179,9 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
 #pragma unroll
     for (int q = 1; q <= LA; ++q) piv[0][q - 1] = a[LA - q];
   }
+  if (bad) atomicAdd(&stats[0], bad);
+  atomicMax(&stats[1], __float_as_uint(float(fmin(gmax, 3.0e38))));
+  atomicMin(&stats[2], __float_as_uint(float(rmin)));
 }
 
 // ---------------------------------------------------------------------------
@@ -3448,10 +3470,11 @@ struct lmvd_plan_s {
   int bgx = 1;      // z-lines per x-pass block
   int device = 0;
   bool use_reg = true;  // register-FFT kernels for the specialised sizes
-  double* fac = nullptr;    // A(k) factors (plan memory), filled on first use
-  bool fac_ready = false;
+  double* fac = nullptr;    // A(k) factors (plan memory), computed and checked at plan creation
   int fac_la = 7, fac_ua = 7;  // instantiated band of the factor kernels
-  unsigned* finite_flag = nullptr;  // device word of the non-finite scan
+  double fac_growth = 0.0, fac_pivot = 0.0;  // largest growth, smallest pivot ratio of the check
+  int64_t fac_bad = 0;      // rows that failed the check
+  unsigned* finite_flag = nullptr;  // device words: the non-finite scan (0), the factor check (16..18)
   int zdiv = 1;     // z tile divisor of the register z kernels below 768 points (lmvd_autotune)
 };
 
@@ -3547,6 +3570,8 @@ static void choose_shapes(lmvd_plan_s* p) {
   bg = std::min(bg, M3);
   p->bgx = bg;
 }
+
+static lmvd_status factor_and_check(lmvd_plan_s* p, double growth_max);
 
 static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::string& msg) {
   if (!cfg || !out) return LMVD_EINVAL;
@@ -3687,6 +3712,12 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   D.xtw = reinterpret_cast<const double2*>(tw);
 #undef UP_TABLE
 #undef UP_OR_FAIL
+  st = factor_and_check(p, kGrowthMax);
+  if (st != LMVD_OK) {
+    if (st == LMVD_ENUMERIC) msg = "A(k) fails the pivot check without pivoting";
+    lmvd_plan_destroy(p);
+    return st;
+  }
   layout_workspace(p);
   *out = p;
   return LMVD_OK;
@@ -4058,16 +4089,28 @@ static void solveA(const Ctx& c, const double2* in1, const double2* in2, const d
                        o3, uscr);
 }
 
-// the plan's A(k) factors, computed on the stream of the first substep that needs them
-static void ensure_factors(lmvd_plan_s* p, hipStream_t s) {
-  if (p->fac_ready) return;
+// The plan's A(k) factors for every (l, |n|) pair, with the check of every pivot (k_factor_ul), run on
+// the null stream and waited for.  LMVD_ENUMERIC when a row fails the check.
+static lmvd_status factor_and_check(lmvd_plan_s* p, double growth_max) {
   const int npairs = p->H.nl * ((p->H.nn + 1) / 2);
   const dim3 g((npairs + kThreads - 1) / kThreads);
+  unsigned* stats = p->finite_flag + 16;
+  const unsigned init[4] = {0u, 0u, 0x7f800000u, 0u};  // count, max growth (0), min ratio (+inf)
+  HIP_OK(hipMemcpy(stats, init, sizeof(init), hipMemcpyHostToDevice));
   if (p->fac_la == 7)
-    hipLaunchKernelGGL((k_factor_ul<7, 7>), g, dim3(kThreads), 0, s, p->D, p->fac);
+    hipLaunchKernelGGL((k_factor_ul<7, 7>), g, dim3(kThreads), 0, nullptr, p->D, p->fac, growth_max, stats);
   else
-    hipLaunchKernelGGL((k_factor_ul<8, 8>), g, dim3(kThreads), 0, s, p->D, p->fac);
-  p->fac_ready = true;
+    hipLaunchKernelGGL((k_factor_ul<8, 8>), g, dim3(kThreads), 0, nullptr, p->D, p->fac, growth_max, stats);
+  HIP_OK(hipGetLastError());
+  unsigned h[4];
+  HIP_OK(hipMemcpy(h, stats, sizeof(h), hipMemcpyDeviceToHost));
+  float gf, rf;
+  std::memcpy(&gf, &h[1], 4);
+  std::memcpy(&rf, &h[2], 4);
+  p->fac_bad = h[0];
+  p->fac_growth = gf;
+  p->fac_pivot = rf;
+  return h[0] ? LMVD_ENUMERIC : LMVD_OK;
 }
 
 // out = filter(in) + add on all planes, then the wall planes of out (see k_zfilt_w, k_wall)
@@ -4279,7 +4322,6 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   const dim3 cgrid((unsigned)((ncol + kThreads - 1) / kThreads));
   // m^c values (and, for the final iterate, m = m^d + m^c and the coefficients) from the rho_t values
   auto mc_step = [&](bool final_it) {
-    ensure_factors(p, s);
     const int nth = 2 * H.nl * ((H.nn + 1) / 2);
     const dim3 g((nth + kThreads - 1) / kThreads);
     // values in, L-sweep intermediate out and back, 3 value fields out, A(k) sweep intermediate out and back,
@@ -4332,7 +4374,6 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
                         gdst, vzt};
   // 1. m^d and its values at tau, the values of z (fixed during the substep) and the guess
   if (H.p == 8) {
-    ensure_factors(p, s);
     const int nth = 2 * H.nl * ((H.nn + 1) / 2);
     const bool diag = a->md[0] || a->md[1] || a->md[2];
     // m^d: phi2, Omega2 in, 3 value fields out, A(k) sweep intermediate out and back, factors once per
@@ -4722,11 +4763,6 @@ lmvd_status lmvd_graph_create(const lmvd_plan* plans, const lmvd_substep_args* a
   std::vector<hipEvent_t> ev(count + 1, nullptr);
   lmvd_status st = LMVD_OK;
   if (hipStreamCreateWithFlags(&origin, hipStreamNonBlocking) != hipSuccess) st = LMVD_EHIP;
-  // the A(k) factors are plan state computed on first use: outside the graph
-  if (st == LMVD_OK) {
-    for (int i = 0; i < count; ++i) lmvd::ensure_factors(plans[i], origin);
-    if (hipStreamSynchronize(origin) != hipSuccess) st = LMVD_EHIP;
-  }
   for (int i = 0; i < count && st == LMVD_OK; ++i)
     if (hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) != hipSuccess) st = LMVD_EHIP;
   for (int i = 0; i <= count && st == LMVD_OK; ++i)
@@ -4968,7 +5004,6 @@ lmvd_status lmvd_md_adjoint(lmvd_plan plan, const void* m1, const void* m2, cons
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
   if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  lmvd::ensure_factors(plan, s);
   const size_t ncol = size_t(plan->H.nn) * plan->H.nl;
   double2* scr = reinterpret_cast<double2*>(static_cast<char*>(workspace) + plan->ws.off_yt);
   hipLaunchKernelGGL(k_md_t, dim3((ncol + kThreads - 1) / kThreads), dim3(kThreads), 0, s, plan->D,
@@ -4984,7 +5019,6 @@ lmvd_status lmvd_mc_adjoint(lmvd_plan plan, const void* m1, const void* m2, cons
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
   if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  lmvd::ensure_factors(plan, s);
   const size_t ncol = size_t(plan->H.nn) * plan->H.nl;
   double2* scr = reinterpret_cast<double2*>(static_cast<char*>(workspace) + plan->ws.off_yt);
   hipLaunchKernelGGL(k_mc_t, dim3((ncol + kThreads - 1) / kThreads), dim3(kThreads), 0, s, plan->D,
@@ -5098,6 +5132,36 @@ lmvd_status lmvd_profile_stop(lmvd_plan plan, double* total_ms, int64_t* launche
   f.cls = -1;
   f.used = 0;
   return LMVD_OK;
+}
+
+lmvd_status lmvd_factor_check(lmvd_plan plan, double growth_max, double* max_growth, double* min_pivot_ratio,
+                              int64_t* bad_rows) {
+  if (!plan || !(growth_max >= 0.0)) return LMVD_EINVAL;
+  if (growth_max > 0.0) {
+    if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
+    const lmvd_status st = lmvd::factor_and_check(plan, growth_max);
+    if (st != LMVD_OK && st != LMVD_ENUMERIC) return st;
+  }
+  if (max_growth) *max_growth = plan->fac_growth;
+  if (min_pivot_ratio) *min_pivot_ratio = plan->fac_pivot;
+  if (bad_rows) *bad_rows = plan->fac_bad;
+  return plan->fac_bad ? LMVD_ENUMERIC : LMVD_OK;
+}
+
+lmvd_status lmvd_factor_check_host(const lmvd_config* cfg, double growth_max, double* max_growth,
+                                   double* min_pivot_ratio, int64_t* bad_rows, int64_t* distinct_k) {
+  if (!cfg || !(growth_max > 0.0)) return LMVD_EINVAL;
+  HostTables H;
+  std::string msg;
+  lmvd_status st = build_host_tables(*cfg, H, msg);
+  if (st != LMVD_OK) return st;
+  FactorCheck fc;
+  st = factor_check_host(H, growth_max, fc);
+  if (max_growth) *max_growth = fc.max_growth;
+  if (min_pivot_ratio) *min_pivot_ratio = fc.min_pivot_ratio;
+  if (bad_rows) *bad_rows = fc.bad_rows;
+  if (distinct_k) *distinct_k = fc.distinct_k;
+  return st;
 }
 
 lmvd_status lmvd_host_tables(const lmvd_config* cfg, double* tau, double* tau_star, double* E0, double* E1,

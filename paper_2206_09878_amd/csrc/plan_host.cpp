@@ -465,3 +465,57 @@ lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& H, std::string
 }
 
 }  // namespace lmvd
+
+namespace lmvd {
+
+// The bottom-up no-pivot elimination of A(k) (rows n2 .. 0) for every distinct k^2 = k1^2 + k3^2 of the
+// grid, with the row check of the device factorisation: s = largest magnitude of row i of A; the pivot
+// must reach 1e-12 s and the eliminated row may not exceed growth_max s.
+lmvd_status factor_check_host(const HostTables& H, double growth_max, FactorCheck& out) {
+  const int n2 = H.n2, N = n2 + 1, LA = H.a_lower, UA = H.a_upper, W = LA + UA + 1;
+  std::vector<double> ks;
+  for (int l = 0; l < H.nl; ++l)
+    for (int n = 0; n < (H.nn + 1) / 2; ++n) ks.push_back(H.k1[l] * H.k1[l] + H.k3[n] * H.k3[n]);
+  std::sort(ks.begin(), ks.end());
+  ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+  out = FactorCheck{};
+  out.min_pivot_ratio = INFINITY;
+  std::vector<double> piv(size_t(UA) * LA), pinv(UA), a(W);
+  for (double ksq : ks) {
+    if (ksq == 0.0) continue;
+    ++out.distinct_k;
+    const double k = std::sqrt(ksq);
+    std::fill(piv.begin(), piv.end(), 0.0);
+    std::fill(pinv.begin(), pinv.end(), 0.0);
+    for (int i = N - 1; i >= 0; --i) {
+      const bool robin = (i == 0 || i == n2);
+      const double sg = (i == 0) ? -1.0 : 1.0;
+      double rs = 0.0;
+      for (int w = 0; w < W; ++w) {
+        const int col = i - LA + w;
+        a[w] = robin ? k * H.Es[0].at(i, col) + sg * H.Es[1].at(i, col)
+                     : H.Es[2].at(i, col) - ksq * H.Es[0].at(i, col);
+        rs = std::max(rs, std::fabs(a[w]));
+      }
+      for (int m = UA; m >= 1; --m) {
+        const double lm = a[LA + m] * pinv[m - 1];
+        for (int q = 1; q <= LA; ++q) a[LA + m - q] -= lm * piv[size_t(m - 1) * LA + q - 1];
+      }
+      double big = 0.0;
+      for (int w = 0; w <= LA; ++w) big = std::max(big, std::fabs(a[w]));
+      const double growth = big / rs, ratio = std::fabs(a[LA]) / rs;
+      if (!(ratio >= 1e-12) || !(growth <= growth_max)) ++out.bad_rows;
+      if (growth > out.max_growth) out.max_growth = growth;
+      if (ratio < out.min_pivot_ratio) out.min_pivot_ratio = ratio;
+      for (int m = UA - 1; m > 0; --m) {
+        pinv[m] = pinv[m - 1];
+        for (int q = 0; q < LA; ++q) piv[size_t(m) * LA + q] = piv[size_t(m - 1) * LA + q];
+      }
+      pinv[0] = 1.0 / a[LA];
+      for (int q = 1; q <= LA; ++q) piv[q - 1] = a[LA - q];
+    }
+  }
+  return out.bad_rows ? LMVD_ENUMERIC : LMVD_OK;
+}
+
+}  // namespace lmvd

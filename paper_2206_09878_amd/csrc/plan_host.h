@@ -90,6 +90,15 @@ struct HostTables {
 // Build all host tables.  Returns LMVD_OK or an error with `msg` set.
 lmvd_status build_host_tables(const lmvd_config& cfg, HostTables& out, std::string& msg);
 
+// Result of the pivot check of the A(k) elimination over every distinct k of a grid.
+struct FactorCheck {
+  double max_growth = 0.0;       // largest entry of an eliminated row over the row's largest entry in A
+  double min_pivot_ratio = 0.0;  // smallest pivot over the row's largest entry in A
+  int64_t bad_rows = 0;          // rows with a pivot below 1e-12 of the row or growth above the limit
+  int64_t distinct_k = 0;        // nonzero k^2 checked
+};
+lmvd_status factor_check_host(const HostTables& H, double growth_max, FactorCheck& out);
+
 // Dense copy of a row table (row-major rows x cols).
 std::vector<double> dense(const RowTable& r);
 

@@ -59,7 +59,8 @@ EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_
            "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop", "lmvd_graph_create",
            "lmvd_graph_launch", "lmvd_graph_destroy", "lmvd_graph_grouped", "lmvd_autotune",
            "lmvd_graph_autotune", "lmvd_rhs", "lmvd_to_physical_adjoint", "lmvd_evaluate_adjoint",
-           "lmvd_project_adjoint", "lmvd_md_adjoint", "lmvd_mc_adjoint", "lmvd_to_spectral_adjoint"]
+           "lmvd_project_adjoint", "lmvd_md_adjoint", "lmvd_mc_adjoint", "lmvd_to_spectral_adjoint",
+           "lmvd_factor_check", "lmvd_factor_check_host"]
 
 
 def library():
@@ -91,6 +92,9 @@ def library():
         lib.lmvd_mc_adjoint.argtypes = [vp] * 7
         lib.lmvd_to_spectral_adjoint.argtypes = [vp] * 5
         lib.lmvd_host_tables.argtypes = [ctypes.POINTER(Config), vp, vp, vp, vp, vp]
+        pd, p64 = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
+        lib.lmvd_factor_check.argtypes = [vp, ctypes.c_double, pd, pd, p64]
+        lib.lmvd_factor_check_host.argtypes = [ctypes.POINTER(Config), ctypes.c_double, pd, pd, p64, p64]
         lib.lmvd_profile_start.argtypes = [vp, i32, i32]
         lib.lmvd_profile_stop.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_double)]
@@ -144,6 +148,19 @@ def host_tables(w):
     return tau, taus, E
 
 
+def factor_check_host(w, growth_max: float = 1e4):
+    """Pivot check of the A(k) elimination for every distinct k of the workload's grid, on the host
+    (lmvd_factor_check_host).  Returns (status, max growth, min pivot ratio, failed rows, distinct k)."""
+    cfg = make_config(w)
+    g, r = ctypes.c_double(), ctypes.c_double()
+    bad, nk = ctypes.c_int64(), ctypes.c_int64()
+    st = library().lmvd_factor_check_host(ctypes.byref(cfg), growth_max, ctypes.byref(g), ctypes.byref(r),
+                                          ctypes.byref(bad), ctypes.byref(nk))
+    if st not in (0, -5):
+        _check(st, "lmvd_factor_check_host")
+    return st, g.value, r.value, bad.value, nk.value
+
+
 class Plan:
     """A plan plus its workspace on the current GPU."""
 
@@ -171,6 +188,15 @@ class Plan:
                 self.handle = None
         except Exception:
             pass
+
+    def factor_check(self, growth_max: float = 0.0):
+        """The A(k) pivot check of plan creation (growth_max = 0), or made again with another limit
+        (lmvd_factor_check).  Returns (status, max growth, min pivot ratio, failed rows)."""
+        g, r, bad = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        st = library().lmvd_factor_check(self.handle, growth_max, ctypes.byref(g), ctypes.byref(r), ctypes.byref(bad))
+        if st not in (0, -5):
+            _check(st, "lmvd_factor_check")
+        return st, g.value, r.value, bad.value
 
     def autotune(self, force: int = 0):
         """Pick the z-transform tile by timing (force = 0) or set it (1, 2, 4); see lmvd_autotune.

@@ -116,3 +116,26 @@ def test_plan_create_rejects_sizes_beyond_the_kernels(n1, n3, n2, order):
     cfg = lmvd.make_config(w)
     h = ctypes.c_void_p()
     assert lmvd.library().lmvd_plan_create(ctypes.byref(cfg), ctypes.byref(h)) == -4
+
+
+@pytest.mark.parametrize("name", ["small", "mixing128", "rt512"])
+def test_factor_check_host_passes_on_the_workload_grids(name):
+    """Every distinct k of the grid (27,239 at 512x385x512 with its clustered knots) passes the pivot
+    check of the A(k) elimination; the growth stays near 1 and the pivots far from zero."""
+    from paper_2206_09878_amd.lmvd import factor_check_host
+    w = workload(name)
+    st, growth, pivot, bad, nk = factor_check_host(w)
+    assert st == 0 and bad == 0
+    assert nk > (w.n1 // 2) * (w.n3 // 2) // 4
+    assert 1.0 <= growth < 2.0 and pivot > 1e-2
+
+
+def test_factor_check_host_fires_below_the_growth_it_sees():
+    """A growth limit below the growth the elimination reaches makes rows fail (LMVD_ENUMERIC): the check
+    is live."""
+    from paper_2206_09878_amd.lmvd import factor_check_host
+    w = workload("small")
+    st, growth, _, _, _ = factor_check_host(w)
+    assert st == 0
+    st, _, _, bad, _ = factor_check_host(w, growth_max=0.5 * (1.0 + growth))
+    assert st == -5 and bad > 0

@@ -183,3 +183,22 @@ def test_inverse_transform_direct_sums_and_round_trip(full):
         val = float(np.sum(wl[None, :] * (V[j] * ph).real))
         worst = max(worst, abs(P[j, b, a] - val) / np.abs(V[j]).sum())
     assert worst < 1e-13, worst
+
+
+def test_every_pivot_of_the_plan_passes_the_device_check(full):
+    """Plan creation factored A(k) for all 65,536 (l, |n|) pairs and checked every row on the device; the
+    largest growth and smallest pivot ratio agree with the host elimination over the distinct k. Made again
+    with a growth limit below what the elimination reaches, the check fails rows (LMVD_ENUMERIC) and leaves
+    the plan usable."""
+    from paper_2206_09878_amd.lmvd import factor_check_host
+    p, w = full["plan"], full["w"]
+    st, growth, pivot, bad = p.factor_check()
+    assert st == 0 and bad == 0
+    hst, hgrowth, hpivot, hbad, _ = factor_check_host(w)
+    assert hst == 0
+    print(f"device: growth {growth:.6g}, pivot ratio {pivot:.6g}; host: {hgrowth:.6g}, {hpivot:.6g}")
+    assert abs(growth - hgrowth) < 1e-6 * hgrowth and abs(pivot - hpivot) < 1e-6 * hpivot
+    st, _, _, bad = p.factor_check(0.5 * (1.0 + growth))
+    assert st == -5 and bad > 0
+    st, _, _, bad = p.factor_check(1e4)
+    assert st == 0 and bad == 0

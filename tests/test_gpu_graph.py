@@ -132,7 +132,7 @@ def test_substeps_captured_in_a_caller_graph(torch):
     in between, equal the same substeps run eagerly, bit for bit, after every replay."""
     ws = batch_workloads(count=1, seed=5000)
     (a,), (b,) = steppers(ws), steppers(ws)
-    a.substep()                      # first call: the plan's A(k) factors, outside the capture
+    a.substep()
     b.substep()
     for _ in range(3):               # back to the start of the history-ring period
         a.substep()
