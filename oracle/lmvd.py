@@ -169,11 +169,16 @@ class Plan:
         result is zero.
         """
         out = np.zeros_like(R)
-        ksq = self.ksq
-        for val in np.unique(ksq):
+        ksq = self.ksq.ravel()
+        vals, inv = np.unique(ksq, return_inverse=True)
+        order = np.argsort(inv, kind="stable")         # columns of each k^2 together, in row-major order
+        bounds = np.searchsorted(inv[order], np.arange(len(vals) + 1))
+        nl = self.ksq.shape[1]
+        for g, val in enumerate(vals):
             if val == 0.0:
                 continue
-            idx = np.nonzero(ksq == val)
+            flat = order[bounds[g]:bounds[g + 1]]
+            idx = (flat // nl, flat % nl)
             A = self.A_of_k(np.sqrt(val))
             out[:, idx[0], idx[1]] = banded_solve(A, R[:, idx[0], idx[1]])
         return out
