@@ -338,7 +338,7 @@ lmvd_status lmvd_mc_adjoint(lmvd_plan plan, const void* m1, const void* m2, cons
  * once, factor tables, and the stored intermediate of a two-sweep banded
  * solve; re-reads through the caches are not counted. */
 lmvd_status lmvd_profile_start(lmvd_plan plan, int32_t cls, int32_t max_launches);
-lmvd_status lmvd_profile_stop(lmvd_plan plan, double* total_ms, int64_t* launches, double* alg_bytes);
+lmvd_status lmvd_profile_stop(lmvd_plan plan, double* total_ms, int64_t* launches, double* compulsory_bytes);
 
 /* ---- the no-pivot factorisation of A(k) ----
  * The m^d and m^c solves use one factorisation of A(k) = E*_2 - k^2 E*_0 with the Robin rows (eqs.

@@ -3456,7 +3456,7 @@ struct lmvd_prof {
   int cls = -1;                 // kernel class being timed, -1 = off
   std::vector<hipEvent_t> ev;   // start/stop pairs
   int used = 0;                 // pairs recorded
-  double bytes = 0.0;           // algorithmic bytes of the recorded launches
+  double bytes = 0.0;           // compulsory bytes of the recorded launches
 };
 
 struct lmvd_plan_s {
@@ -5114,7 +5114,7 @@ lmvd_status lmvd_profile_start(lmvd_plan plan, int32_t cls, int32_t max_launches
   return LMVD_OK;
 }
 
-lmvd_status lmvd_profile_stop(lmvd_plan plan, double* total_ms, int64_t* launches, double* alg_bytes) {
+lmvd_status lmvd_profile_stop(lmvd_plan plan, double* total_ms, int64_t* launches, double* compulsory_bytes) {
   if (!plan) return LMVD_EINVAL;
   lmvd_prof& f = plan->prof;
   double tot = 0.0;
@@ -5126,7 +5126,7 @@ lmvd_status lmvd_profile_stop(lmvd_plan plan, double* total_ms, int64_t* launche
   }
   if (total_ms) *total_ms = tot;
   if (launches) *launches = f.used;
-  if (alg_bytes) *alg_bytes = f.bytes;
+  if (compulsory_bytes) *compulsory_bytes = f.bytes;
   for (hipEvent_t e : f.ev) (void)hipEventDestroy(e);
   f.ev.clear();
   f.cls = -1;

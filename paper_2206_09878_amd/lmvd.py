@@ -278,7 +278,7 @@ class Plan:
         _check(library().lmvd_profile_start(self.handle, cls, max_launches), "lmvd_profile_start")
 
     def profile_stop(self):
-        """(total_ms, launches, algorithmic_bytes) of the timed kernel class."""
+        """(total_ms, launches, compulsory_bytes) of the timed kernel class."""
         ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         _check(library().lmvd_profile_stop(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
                "lmvd_profile_stop")

@@ -183,6 +183,23 @@ def _random_modes(rng, w: Workload, amp_of_kappa, profile):
     return _hermitian_l0(f)
 
 
+def broadband_momentum(w: Workload, seed: int, amp: float = 1e-3, kmax: int = 32):
+    """(phi2, Omega2) coefficient arrays with k^-5/3 amplitudes for 1 <= kappa <= kmax, a Gaussian
+    profile across the channel (zero at the walls) and random complex normal entries: a broadband m^d to
+    add to states that have none (the Rayleigh-Taylor initial state), so that every product of the
+    substep is non-trivial."""
+    rng = np.random.default_rng(seed)
+    n, l, kap = _mode_grid(w)
+    a = np.where((kap >= 1) & (kap <= kmax), np.maximum(kap, 1.0) ** (-5.0 / 3.0), 0.0)
+    prof = np.exp(-np.linspace(-2.0, 2.0, w.n2) ** 2)
+    prof[0] = prof[-1] = 0.0
+
+    def field():
+        xi = rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape)
+        return _hermitian_l0(amp * xi * a[None] * prof[:, None, None])
+    return field(), field()
+
+
 def make_inputs(w: Workload, seed: int = 0, stage: int = 0) -> dict:
     """Seeded inputs of one substep.
 

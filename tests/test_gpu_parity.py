@@ -97,21 +97,24 @@ def test_md_mc(torch, name, n, n2):
         assert rel(host(g), r) < TOL
 
 
-def run_pair(w, stage, seed=0, kf=None, guess_mode=0, plane_batch=0, tile=0, inputs=None):
-    """One substep on the GPU and in the oracle from the same inputs (tile: force the z tile divisor;
-    inputs: a dict like make_inputs' instead of the seeded one)."""
-    import torch
-    p = gplan(w, plane_batch=plane_batch)
-    if tile:
-        assert p.autotune(force=tile)[0] == tile
+def oracle_substep(w, stage, inp, kf=None, guess_mode=0):
+    """The oracle's substep (with diagnostics) from the inputs of make_inputs' form."""
     op = OPlan(oracle_config(w))
-    inp = make_inputs(w, seed=seed, stage=stage) if inputs is None else inputs
     st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
     kw = {}
     if stage == 1:
         kw = dict(rhs_prev=inp["rhs_prev"], zt_prev=inp["zt_prev"])
-    ref = substep(op, st, stage, hist=inp["hist"], kf=kf, guess="zero" if guess_mode else "bdf",
-                  diagnostics=True, **kw)
+    return substep(op, st, stage, hist=inp["hist"], kf=kf, guess="zero" if guess_mode else "bdf",
+                   diagnostics=True, **kw)
+
+
+def gpu_substep(w, stage, inp, kf=None, guess_mode=0, plane_batch=0, tile=0):
+    """The same substep through lmvd_substep, with the m^d and m^c diagnostics; host copies."""
+    import torch
+    p = gplan(w, plane_batch=plane_batch)
+    if tile:
+        assert p.autotune(force=tile)[0] == tile
+    st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
     d = {k: p.to_dev(v) for k, v in st.items()}
     hist = [p.to_dev(h) for h in inp["hist"]]
     z_out = p.empty()
@@ -128,9 +131,17 @@ def run_pair(w, stage, seed=0, kf=None, guess_mode=0, plane_batch=0, tile=0, inp
         args["zt_prev"] = p.to_dev(inp["zt_prev"])
     p.substep(stage, d["phi2"], d["omega2"], d["z"], d["m1bar"], d["m3bar"], **args)
     torch.cuda.synchronize()
-    got = dict(phi2=host(d["phi2"]), omega2=host(d["omega2"]), z=host(z_out), m1bar=host(d["m1bar"]),
-               m3bar=host(d["m3bar"]), zt=host(zt), rhs={k: host(v) for k, v in rhs.items()},
-               md=[host(x) for x in md], mc=[host(x) for x in mc])
+    return dict(phi2=host(d["phi2"]), omega2=host(d["omega2"]), z=host(z_out), m1bar=host(d["m1bar"]),
+                m3bar=host(d["m3bar"]), zt=host(zt), rhs={k: host(v) for k, v in rhs.items()},
+                md=[host(x) for x in md], mc=[host(x) for x in mc])
+
+
+def run_pair(w, stage, seed=0, kf=None, guess_mode=0, plane_batch=0, tile=0, inputs=None):
+    """One substep on the GPU and in the oracle from the same inputs (tile: force the z tile divisor;
+    inputs: a dict like make_inputs' instead of the seeded one)."""
+    inp = make_inputs(w, seed=seed, stage=stage) if inputs is None else inputs
+    ref = oracle_substep(w, stage, inp, kf=kf, guess_mode=guess_mode)
+    got = gpu_substep(w, stage, inp, kf=kf, guess_mode=guess_mode, plane_batch=plane_batch, tile=tile)
     return got, ref
 
 
@@ -154,11 +165,11 @@ class scipy_fft_in_oracle:
         self.F.np = self.np
 
 
-def rhs_tolerances(w, stage, seed, kf=None, ref=None):
+def rhs_tolerances(w, stage, seed, kf=None, ref=None, inputs=None):
     """Per-field bound for the stage RHS outputs: 1e-11, or 4x the oracle's own
     numpy-vs-scipy FFT spread where derivatives amplify rounding more."""
     op = OPlan(oracle_config(w))
-    inp = make_inputs(w, seed=seed, stage=stage)
+    inp = make_inputs(w, seed=seed, stage=stage) if inputs is None else inputs
     st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
     kw = dict(rhs_prev=inp["rhs_prev"], zt_prev=inp["zt_prev"]) if stage == 1 else {}
     with scipy_fft_in_oracle():
@@ -180,6 +191,7 @@ def check_pair(got, ref, tol=TOL, rhs_tol=None):
     if rhs_tol:
         for k, v in rhs_tol.items():
             tols["rhs_" + k] = v
+    print("  " + ", ".join(f"{k} {v:.1e}/{tols[k]:.0e}" for k, v in errs.items()), flush=True)
     bad = {k: (v, tols[k]) for k, v in errs.items() if not v < tols[k]}
     assert not bad, (bad, errs)
     return errs
@@ -270,46 +282,12 @@ def test_trajectory_three_substeps_small(torch):
     assert all(v < TOL for v in errs.values()), errs
 
 
-def plane_batch_substep(w, plane_batch, seed, stage):
-    """One substep on the GPU only (no diagnostics), returning the host outputs."""
-    import torch
-    p = gplan(w, plane_batch=plane_batch)
-    inp = make_inputs(w, seed=seed, stage=stage)
-    d = {k: p.to_dev(inp[k]) for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
-    hist = [p.to_dev(h) for h in inp["hist"]]
-    z_out, zt = p.empty(), p.empty()
-    rhs = {"phi2": p.empty(), "omega2": p.empty(),
-           "m1bar": torch.empty(w.n2, dtype=torch.float64, device="cuda"),
-           "m3bar": torch.empty(w.n2, dtype=torch.float64, device="cuda")}
-    kw = dict(z_out=z_out, hist=hist, rhs_out=rhs, zt_out=zt)
-    if stage == 1:
-        kw["rhs_prev"] = {k: p.to_dev(v) for k, v in inp["rhs_prev"].items()}
-        kw["zt_prev"] = p.to_dev(inp["zt_prev"])
-    p.substep(stage, d["phi2"], d["omega2"], d["z"], d["m1bar"], d["m3bar"], **kw)
-    torch.cuda.synchronize()
-    out = {k: host(v) for k, v in d.items()}
-    out.update(z_out=host(z_out), zt=host(zt), **{"rhs_" + k: host(v) for k, v in rhs.items()})
-    return out
-
-
-@pytest.mark.parametrize("name,n,n2,stage", [("rt512", 512, 33, 0), ("mixing128", 64, 65, 1)])
-def test_filtered_iterates_match_spectral_path(torch, name, n, n2, stage):
-    """All planes in one batch: the fixed-point iterates before the last are
-    z-filtered on the 3/2 grid with the wall planes from the Neumann
-    projection's wall-row weights.  A plane batch below n2 takes the spectral
-    path (forward transform, projection, values, inverse transform).  The two
-    agree to rounding on every output (768-point filter kernel at rt512 sizes;
-    the register kernels of the smaller sizes are also covered by the oracle
-    parity tests above)."""
-    w = workload(name, n=n, n2=n2)
-    a = plane_batch_substep(w, 0, seed=9, stage=stage)
-    b = plane_batch_substep(w, n2 - 1, seed=9, stage=stage)
-    errs = {k: rel(a[k], b[k]) for k in a}
-    print("filtered vs spectral:", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
-    # The iterate and the state agree to rounding.  RHS_phi2 (and phi2 = phi2 + dt/2 RHS_phi2) of the
-    # Rayleigh-Taylor state, where m^d = 0, is a small remainder of much larger terms: the oracle itself,
-    # run with numpy's and then scipy's FFT at 512x33x512 (seed 9, stage n), disagrees by 1.7e-9 there
-    # and by 4.0e-12 in RHS_Omega2; the bounds below are about 6x and 2.5x those spreads.
-    tol = {"phi2": 1e-8, "rhs_phi2": 1e-8, "omega2": 1e-11, "rhs_omega2": 1e-11}
-    bad = {k: v for k, v in errs.items() if not v < tol.get(k, 1e-12)}
-    assert not bad, errs
+@pytest.mark.parametrize("plane_batch", [0, 64])
+def test_filtered_and_spectral_iterates_against_oracle(torch, plane_batch):
+    """64x65x64, stage ': all planes in one batch (the fixed-point iterates before the last are
+    z-filtered on the 3/2 grid, wall planes from the Neumann projection's wall-row weights) and a plane
+    batch of n2 - 1 (the spectral path: forward transform, projection, values, inverse transform), each
+    against the oracle.  The 768-point filter kernel is covered the same way at 512 x 17 x 512."""
+    w = workload("mixing128", n=64, n2=65)
+    got, ref = run_pair(w, 1, seed=9, plane_batch=plane_batch)
+    check_pair(got, ref, rhs_tol=rhs_tolerances(w, 1, 9, ref=ref))
