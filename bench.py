@@ -15,6 +15,7 @@ spectral-field dataflow) and the CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
     python bench.py --workload batch64     (64 small uneven instances, one HIP graph)
+    python bench.py --workload adjoint96   (gradient of the 96^3 workload: adjoint/forward time)
 """
 from __future__ import annotations
 
@@ -161,6 +162,15 @@ def bench_batch(args, count=64, nsub=4):
     t0 = time.perf_counter()
     tiles, _ = g.autotune(launches=3)
     tune_s = time.perf_counter() - t0
+    chosen = {}
+    for w, t in zip(ws, tiles):
+        chosen[str(w.m3)] = t
+    # the candidates' times for one instance of each z size alone (lmvd_autotune on a copy of its plan)
+    alone = {}
+    for m3 in sorted({w.m3 for w in ws}):
+        w = next(x for x in ws if x.m3 == m3)
+        _, times = Plan(w).autotune()
+        alone[str(m3)] = {str(code): round(ms, 4) for code, ms in zip(Plan.TILE_CODES, times) if ms > 0}
     for _ in range(max(args.warmup, 1)):
         g.launch()
         eager()
@@ -179,9 +189,60 @@ def bench_batch(args, count=64, nsub=4):
             "one_by_one": {"value": subs / te, "ms_per_step": 1e3 * te / args.steps,
                            "grid_point_substeps_per_s": pts / te},
             "graph_speedup": te / tg, "graph_build_s": build_s,
-            "autotune": {"z_tile_divisors": {str(d): tiles.count(d) for d in sorted(set(tiles))},
+            "autotune": {"z_tile_code_per_size": chosen, "tile_code": "D + 8 V (V: line plan, D: divisor)",
                          "tune_s": tune_s, "default_tile_value": subs / t_default,
-                         "speedup_over_default_tile": t_default / tg}}
+                         "speedup_over_default_tile": t_default / tg, "alone_ms_per_code": alone}}
+
+
+def bench_adjoint(args, steps=20, every=5):
+    """The adjoint workload: 96 x 97 x 96 (density 1 -> 7 layer), 20 RK steps, objective the domain-
+    averaged kinetic energy at the final time, gradient with respect to the initial z through the
+    library's adjoint substep with checkpointed recomputation every 5 steps.  A step = one forward +
+    backward of the whole workload; the native forward (the same 41 substeps on the plain path) is
+    timed beside it."""
+    import torch
+
+    from paper_2206_09878_amd.adjoint import final_kinetic_energy, rollout
+    from paper_2206_09878_amd.lmvd import Plan, Stepper
+    from paper_2206_09878_amd.workloads import make_inputs, workload
+    w = workload("adjoint96")
+    p = Plan(w)
+    inp = make_inputs(w, seed=98, stage=0)
+    st0 = {k: p.to_dev(inp[k]) for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
+    hist0 = [p.to_dev(h) for h in inp["hist"]]
+
+    def native():
+        s = Stepper(p, inp, stage=0)
+        for _ in range(2 * steps + 1):
+            s.substep()
+
+    def adjoint():
+        z0 = st0["z"].clone().requires_grad_(True)
+        state, hist = rollout(p, dict(st0, z=z0), hist0, steps=steps, checkpoint_every=every)
+        final_kinetic_energy(p, state, hist).backward()
+        return z0.grad
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / k
+
+    for _ in range(max(args.warmup, 1)):
+        native()
+        adjoint()
+    k = max(1, min(args.steps, 5))
+    t_nat = timed(native, k)
+    t_adj = timed(adjoint, k)
+    return {"metric": "adjoint/forward time, 96x97x96 FP64, 20 RK steps checkpointed every 5", "value": t_adj / t_nat,
+            "unit": "ratio", "n_gpus": 1, "steps": k, "warmup": args.warmup, "ms_per_step": 1e3 * t_adj,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "adjoint96: temporal mixing layer, density ratio 7, 96x97x96 modes, 144x144 grid, "
+                                   "k_f=4, 20 RK steps (40 substeps) + the objective's substep; gradient of the "
+                                   "final kinetic energy in the initial z; a step = forward + backward", "kf": w.kf},
+            "native_forward_ms": 1e3 * t_nat, "forward_plus_backward_ms": 1e3 * t_adj}
 
 
 def cpu_baseline(full, n2=9):
@@ -258,6 +319,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch64":
         print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if args.workload == "adjoint96":
+        print(json.dumps(bench_adjoint(args)), flush=True)
         return
     w = workload(args.workload)
     if args.transport == "variable":

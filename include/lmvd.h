@@ -213,28 +213,37 @@ lmvd_status lmvd_graph_destroy(lmvd_graph graph);
 lmvd_status lmvd_graph_grouped(lmvd_graph graph, int32_t* grouped);
 
 /* ---- tile autotuner ----
- * Chooses the tile of the register z-transform kernels of a plan with M3 < 768: T = M3/12 threads per
- * z line and 256/(T D) lines per block, D in {1, 2, 4}.  Fewer lines per block leave fewer idle lanes
- * when N1/2 is small.  With force = 0 it times the inverse and forward z transforms of three fields over
- * the plan's plane batch for each D (a warm-up, then 5 repetitions, HIP events on the stream) on the
- * caller's workspace, whose contents it overwrites, and keeps the fastest; force = 1, 2 or 4 sets D
- * without timing.  Plans without such kernels (M3 = 768, or a size without a register plan) keep D = 1.
- * zdiv (host) receives the choice; times_ms (host, optional, 3 doubles) the mean time of one repetition
- * for D = 1, 2, 4 (-1 where not timed).  The choice holds for every later call on the plan, graphs
- * captured afterwards included; results do not depend on it.  Synchronises the stream; not during
- * graph capture or a profile (LMVD_EINVAL). */
+ * Chooses the tile of the register z-transform kernels of a plan with M3 < 768, as a code K = D + 8 V:
+ * V in {0, 1, 2} selects the line plan (threads per z line T, radix split and stage order of the Stockham
+ * FFT; three plans for M3 = 48, 72, 96, 144 and 192, one for the other sizes, where V = 1, 2 mean the
+ * first) and D in {1, 2, 4} divides the 256 / T lines per block (fewer lines per block leave fewer idle
+ * lanes when N1/2 is small).  The plans:
+ *   M3 = 48:  V0 T 4 radices 12.4      V1 T 8 6.2.2.2     V2 T 2 24.2
+ *   M3 = 72:  V0 T 6 12.6              V1 T 12 6.6.2      V2 T 3 24.3
+ *   M3 = 96:  V0 T 8 12.4.2            V1 T 4 24.4        V2 T 4 8.12
+ *   M3 = 144: V0 T 12 12.12            V1 T 24 6.6.2.2    V2 T 6 24.6
+ *   M3 = 192: V0 T 16 12.4.4           V1 T 8 24.8        V2 T 16 4.4.12
+ * With force = 0 it times the inverse and forward z transforms of three fields over the plan's plane
+ * batch for each candidate code (a warm-up, then 5 repetitions, HIP events on the stream) on the
+ * caller's workspace, whose contents it overwrites, and keeps the fastest; force = a code (1, 2, 4, 9,
+ * 10, 12, 17, 18, 20) sets it without timing.  Plans without such kernels (M3 = 768, or a size without a
+ * register plan) keep K = 1.  zdiv (host) receives the choice; times_ms (host, optional, 9 doubles) the
+ * mean time of one repetition for K = 1, 2, 4, 9, 10, 12, 17, 18, 20 (-1 where not timed).  The choice
+ * holds for every later call on the plan, graphs captured afterwards included; results do not depend
+ * on it beyond rounding.  Synchronises the stream; not during graph capture or a profile
+ * (LMVD_EINVAL). */
 lmvd_status lmvd_autotune(lmvd_plan plan, void* workspace, void* stream, int32_t force, int32_t* zdiv,
                           double* times_ms);
 
 /* The same tile choice made for a batch by timing the graph itself: instances run side by side in a
  * graph, where a tile that is faster alone can be slower.  Takes the arguments of lmvd_graph_create
- * (same rules) and a stream; sets D = 1 on every plan with a choice, then, one z-transform size at a
- * time, tries D = 2 and 4 for all plans of that size and keeps a divisor that makes the graph at least
- * 1 % faster.  Each try captures the graph, launches it once, times `launches` launches (1..100) with
- * HIP events and destroys it, so every try ADVANCES EVERY INSTANCE by (1 + launches) * nsub substeps:
- * call it where warm-up launches would go.  zdivs (host, optional, count entries) receives each plan's
- * divisor, ms_per_launch (host, optional) the best time per launch.  Graphs captured afterwards use the
- * choice.  Synchronises the stream. */
+ * (same rules) and a stream; sets K = 1 on every plan with a choice, then, one z-transform size at a
+ * time, tries every other code of that size (the line plans and divisors above) for all plans of that
+ * size and keeps a code that makes the graph at least 1 % faster.  Each try captures the graph,
+ * launches it once, times `launches` launches (1..100) with HIP events and destroys it, so every try
+ * ADVANCES EVERY INSTANCE by (1 + launches) * nsub substeps: call it where warm-up launches would go.
+ * zdivs (host, optional, count entries) receives each plan's code, ms_per_launch (host, optional) the
+ * best time per launch.  Graphs captured afterwards use the choice.  Synchronises the stream. */
 lmvd_status lmvd_graph_autotune(const lmvd_plan* plans, const lmvd_substep_args* args, void* const* workspaces,
                                 int32_t count, int32_t nsub, void* stream, int32_t launches, int32_t* zdivs,
                                 double* ms_per_launch);
@@ -319,6 +328,58 @@ lmvd_status lmvd_md_adjoint(lmvd_plan plan, const void* m1, const void* m2, cons
 lmvd_status lmvd_mc_adjoint(lmvd_plan plan, const void* m1, const void* m2, const void* m3, void* rhot,
                            void* workspace, void* stream);
 
+/* ---- adjoint of the substep ----
+ * Reverse mode of lmvd_substep (Algorithm time_advanceDNS) for gradients through a simulation: given
+ * the substep's inputs (the same lmvd_substep_args as the forward call; its output pointers are not
+ * used) and the cotangents of its outputs, it writes the gradients with respect to its inputs, in the
+ * real inner products <a, b> = sum Re(conj(a) b) over the stored entries of an S-field and the plain dot
+ * product of real vectors.  It recomputes the substep's intermediates from the inputs (the iterates
+ * z_t^k and m^c of the fixed point, m = m^d + m^c on the grid, the grid values of z and its
+ * derivatives) and transposes every step in reverse order: the RK2 update, the right-hand sides and
+ * fluxes (eqs. om, phi, mean_m1m3), the final m^c (eqs. COM_fourier, CF_fourier, mc_recon, mc_mean),
+ * the k_f fixed-point iterations with the matrix-free L(z) of Section 4.3, R_z, the guess (eq.
+ * dzdt_guesses) and m^d (eqs. phi_poisson, md_recon), with hand-written kernels for the pointwise
+ * Jacobians and the transposes of the linear operators below.
+ * Gradients of S-fields are returned as their representatives with a Hermitian l = 0 column (the part
+ * that pairs with the inputs the library accepts); the (0,0) entries of the phi2 and Omega2 gradients
+ * are zero (those inputs are ignored).  Constant transport coefficients only (LMVD_EUNSUPPORTED for a
+ * plan with mu(z) or rho D(z)).  workspace: lmvd_adjoint_sizes bytes (256-byte aligned; it contains the
+ * substep workspace), overwritten.  Asynchronous on `stream`; allocates nothing. */
+typedef struct {
+  /* cotangents of lmvd_substep's outputs (device; required, zero arrays where an output does not
+   * matter) */
+  const void* phi2_out;
+  const void* omega2_out;
+  const void* z_out;
+  const double* m1bar_out;
+  const double* m3bar_out;
+  const void* rhs_phi2;
+  const void* rhs_omega2;
+  const void* zt;
+  const double* rhs_m1;
+  const double* rhs_m3;
+  /* cotangents of the diagnostic outputs m^d, m^c (m2 in B*; optional, NULL = zero) */
+  const void* md[3];
+  const void* mc[3];
+  /* gradients with respect to the inputs (device, written; required) */
+  void* phi2;
+  void* omega2;
+  void* z;
+  double* m1bar;
+  double* m3bar;
+  /* optional (NULL = not wanted): the z history (guess_mode 0; zero with guess_mode 1) and, at stage ',
+   * the stage-n data */
+  void* z_hist[3];
+  void* rhs_phi2_prev;
+  void* rhs_omega2_prev;
+  void* zt_prev;
+  double* rhs_m1_prev;
+  double* rhs_m3_prev;
+} lmvd_substep_grads;
+lmvd_status lmvd_adjoint_sizes(lmvd_plan plan, int32_t kf, size_t* workspace_bytes);
+lmvd_status lmvd_substep_adjoint(lmvd_plan plan, const lmvd_substep_args* args, const lmvd_substep_grads* grads,
+                                 void* workspace, void* stream);
+
 /* Timing hook for measurements: while active, every launch of one kernel
  * class is bracketed by two HIP events recorded on the stream it is launched
  * on.  Classes (one kernel each):
@@ -365,6 +426,12 @@ lmvd_status lmvd_factor_check_host(const lmvd_config* cfg, double growth_max, do
  * Any output pointer may be NULL. */
 lmvd_status lmvd_host_tables(const lmvd_config* cfg, double* tau, double* tau_star,
                              double* E0, double* E1, double* E2);
+
+/* Host-only values of the y basis at arbitrary points (App. C: B-splines of order p on the plan's
+ * clamped knots, star = 0, or of order p + 1 for m2, star = 1): out[i * ncols + j] = B_j(y[i]),
+ * ncols = n2 (n2 + 1 with star).  For quadratures in y (an objective's integral, say).  LMVD_EINVAL if
+ * a point lies outside [-L2/2, L2/2]. */
+lmvd_status lmvd_basis_values(const lmvd_config* cfg, int32_t npts, const double* y, int32_t star, double* out);
 
 #ifdef __cplusplus
 }

@@ -589,35 +589,56 @@ __device__ __forceinline__ void guess_body(const DevPlan& P, size_t c, const Gue
 // T threads per line, radices R0..R3 (every radix divides N/T), PAD: one
 // LDS pad slot every PAD positions.
 
-template <int N>
-struct LinePlan;
-#define LMVD_LINEPLAN(N_, T_, R0_, R1_, R2_, R3_, PAD_)                                              \
+// Several plans per size (V = 0, 1, 2: other thread counts, radix splits or stage orders) are compiled
+// for the sizes below 768; the tile autotuner picks one by timing.  A size without alternatives uses its
+// first plan for every V.
+template <int N, int V>
+struct LinePlanV : LinePlanV<N, 0> {};
+#define LMVD_LINEPLAN(N_, V_, T_, R0_, R1_, R2_, R3_, PAD_)                                          \
   template <>                                                                                        \
-  struct LinePlan<N_> {                                                                              \
+  struct LinePlanV<N_, V_> {                                                                         \
     static constexpr int T = T_, R0 = R0_, R1 = R1_, R2 = R2_, R3 = R3_, PAD = PAD_;                 \
     static constexpr int E = N_ / T_;                                                                \
     static constexpr int RL = rf::Last<R0_, R1_, R2_, R3_>::value;                                   \
   };
-LMVD_LINEPLAN(768, 32, 24, 8, 4, 1, 24)
-LMVD_LINEPLAN(384, 32, 12, 4, 4, 2, 12)
-LMVD_LINEPLAN(192, 16, 12, 4, 4, 1, 12)
-LMVD_LINEPLAN(144, 12, 12, 12, 1, 1, 12)
-LMVD_LINEPLAN(96, 8, 12, 4, 2, 1, 12)
-LMVD_LINEPLAN(72, 6, 12, 6, 1, 1, 12)
-LMVD_LINEPLAN(48, 4, 12, 4, 1, 1, 12)
-LMVD_LINEPLAN(36, 3, 12, 3, 1, 1, 12)
-LMVD_LINEPLAN(24, 2, 12, 2, 1, 1, 12)
+LMVD_LINEPLAN(768, 0, 32, 24, 8, 4, 1, 24)
+LMVD_LINEPLAN(384, 0, 32, 12, 4, 4, 2, 12)
+LMVD_LINEPLAN(192, 0, 16, 12, 4, 4, 1, 12)
+LMVD_LINEPLAN(192, 1, 8, 24, 8, 1, 1, 24)
+LMVD_LINEPLAN(192, 2, 16, 4, 4, 12, 1, 12)
+LMVD_LINEPLAN(144, 0, 12, 12, 12, 1, 1, 12)
+LMVD_LINEPLAN(144, 1, 24, 6, 6, 2, 2, 6)
+LMVD_LINEPLAN(144, 2, 6, 24, 6, 1, 1, 24)
+LMVD_LINEPLAN(96, 0, 8, 12, 4, 2, 1, 12)
+LMVD_LINEPLAN(96, 1, 4, 24, 4, 1, 1, 24)
+LMVD_LINEPLAN(96, 2, 4, 8, 12, 1, 1, 8)
+LMVD_LINEPLAN(72, 0, 6, 12, 6, 1, 1, 12)
+LMVD_LINEPLAN(72, 1, 12, 6, 6, 2, 1, 6)
+LMVD_LINEPLAN(72, 2, 3, 24, 3, 1, 1, 24)
+LMVD_LINEPLAN(48, 0, 4, 12, 4, 1, 1, 12)
+LMVD_LINEPLAN(48, 1, 8, 6, 2, 2, 2, 6)
+LMVD_LINEPLAN(48, 2, 2, 24, 2, 1, 1, 24)
+LMVD_LINEPLAN(36, 0, 3, 12, 3, 1, 1, 12)
+LMVD_LINEPLAN(24, 0, 2, 12, 2, 1, 1, 12)
 #undef LMVD_LINEPLAN
+template <int N>
+using LinePlan = LinePlanV<N, 0>;
+// number of distinct z plans of a size
+static constexpr int zplan_count(int n) {
+  return (n == 192 || n == 144 || n == 96 || n == 72 || n == 48) ? 3 : 1;
+}
 
-// lines per block and LDS line stride (doubles) of the z kernels (lines = l, lane-fastest).  D divides
-// the block: LG = 256 / (T D) lines of T threads.  Fewer lines per block leave fewer idle lanes when the
-// plan has few l-lines (small N1); the tile autotuner picks D per plan by timing.
-template <int N, int D = 1>
+// Tile code K of the register z kernels: K % 8 = D, the divisor of the lines per block, and K / 8 = V,
+// the line plan.  LG = 256 / (T D) lines of T threads (lines = l, lane-fastest).  Fewer lines per block
+// leave fewer idle lanes when the plan has few l-lines (small N1); the tile autotuner picks K per plan by
+// timing.
+template <int N, int K = 1>
 struct ZShape {
-  static constexpr int T = LinePlan<N>::T;
-  static constexpr int LG = kThreads / T / D;
+  using LP = LinePlanV<N, K / 8>;
+  static constexpr int T = LP::T;
+  static constexpr int LG = kThreads / T / (K % 8);
   static_assert(LG >= 1, "z tile divisor too large for this transform");
-  static constexpr int BASE = N + N / LinePlan<N>::PAD;
+  static constexpr int BASE = N + N / LP::PAD;
   // 8 lines: stride = 2 mod 32 keeps two neighbouring threads of each of the
   // 8 lines on distinct banks; otherwise an odd stride
   static constexpr int STRIDE = (LG == 8) ? (BASE + ((2 - BASE % 32) + 32) % 32) : (BASE | 1);
@@ -649,7 +670,7 @@ LMVD_XPLAN(48, 4, 12, 4, 1, 1, 12)
 // at compile time.
 template <int N, bool EXACT, int D = 1>
 __device__ __forceinline__ void zinv_r_body(const DevPlan& P, const unsigned bx, const unsigned by, const unsigned bz, const EvalArgs& A, double2* __restrict__ zbuf, int j0, int pb) {
-  using LP = LinePlan<N>;
+  using LP = typename ZShape<N, D>::LP;
   using ZS = ZShape<N, D>;
   constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL;
   constexpr int NNX = 2 * N / 3 - 1, H3X = (NNX + 1) / 2, PADX = N - NNX;
@@ -699,7 +720,7 @@ __global__ void __launch_bounds__(kThreads) k_zinv_r(DevPlan P, EvalArgs A, doub
 // forward z-FFT of size N = m3 and truncation to the retained n.
 template <int N, int D = 1>
 __device__ __forceinline__ void zfwd_r_body(const DevPlan& P, const unsigned bx, const unsigned by, const unsigned bz, const double2* __restrict__ obuf, const OutPtrs& V, int j0, int pb) {
-  using LP = LinePlan<N>;
+  using LP = typename ZShape<N, D>::LP;
   using ZS = ZShape<N, D>;
   constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL;
   extern __shared__ double lds_d[];
@@ -901,7 +922,7 @@ template <int N, int D = 1>
 __device__ __forceinline__ void zfilt_r_body(const DevPlan& P, const unsigned bx, const unsigned by,
                                              const double2* __restrict__ in, const double2* __restrict__ add,
                                              double2* __restrict__ out) {
-  using LP = LinePlan<N>;
+  using LP = typename ZShape<N, D>::LP;
   using ZS = ZShape<N, D>;
   constexpr int T = LP::T, E = LP::E, LG = ZS::LG, RL = LP::RL, EL = E / RL;
   extern __shared__ double lds_d[];
@@ -970,23 +991,31 @@ struct Pair;
 // leave alone, so the u, rho, C_ij pass reads it again):  R_z = (1/rho)(-m^d . grad z + rho D lap z)
 template <>
 struct Pair<PH_RZ> {
-  static constexpr int NP = 4, NQ = 1, NST = 2;
-  // pairs (lap z, z), (d z / d x, m1), (z2, m2), (z3, m3)
-  __device__ static constexpr int fa(int i) { return i == 0 ? 0 : i == 1 ? 6 : 2 * i - 2; }
+  static constexpr int NP = 4, NQ = 1, NST = 3;
+  // pairs (d z / d x, z), both from z's line, (lap z, m1), (z2, m2), (z3, m3): in a paired transform
+  // the rounding of each field is of the order of the larger one, so z and its gradient travel with
+  // fields no larger than themselves; m^d, small, takes the rounding of lap z and reaches R_z only
+  // through the advective term
+  __device__ static constexpr int fa(int i) { return i == 0 ? 6 : 2 * i - 2; }
   __device__ static constexpr int fb(int i) { return i == 0 ? 6 : 2 * i - 1; }
   // the x-derivative of z is formed here from z's line, mode by mode
-  __device__ static constexpr bool dxa(int i) { return i == 1; }
+  __device__ static constexpr bool dxa(int i) { return i == 0; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
   __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y, double* a, size_t fs) {
     // a == nullptr on lines past the grid edge: nothing is written there
-    if constexpr (I == 0) {
+    if constexpr (I == 0) {  // x = d z / d x, y = z
       const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * y);
       s[0] = (P.rho_h - P.drho * y) * P.inv_rlrh;  // 1/rho
-      s[1] = P.rhoD * x;
-      if (a) a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
-    } else {
+      s[2] = x;
+      if (a) {
+        a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
+        a[0] = -s[0] * x;
+      }
+    } else if constexpr (I == 1) {  // x = lap z, y = m1
+      s[1] = P.rhoD * x - s[2] * y;
+    } else {  // x = d z / d x_I, y = m_I
       s[1] -= x * y;
       if (a) a[(I - 1) * fs] = -s[0] * x;
     }
@@ -1000,8 +1029,9 @@ struct Pair<PH_RZ> {
 template <>
 struct Pair<PH_RZV> {
   static constexpr int NP = 4, NQ = 1, NST = 3;
-  __device__ static constexpr int fa(int i) { return Pair<PH_RZ>::fa(i); }
-  __device__ static constexpr int fb(int i) { return Pair<PH_RZ>::fb(i); }
+  // pairs (lap z, z), (d z / d x from z's line, m1), (z2, m2), (z3, m3)
+  __device__ static constexpr int fa(int i) { return i == 0 ? 0 : i == 1 ? 6 : 2 * i - 2; }
+  __device__ static constexpr int fb(int i) { return i == 0 ? 6 : 2 * i - 1; }
   __device__ static constexpr bool dxa(int i) { return i == 1; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
@@ -3879,12 +3909,25 @@ static EvalIn ev(const void* a, int kind, int ma = MU_ONE, const void* b = nullp
   return e;
 }
 
-// z tile divisor (1, 2 or 4; anything else is 1) as a compile-time constant
+// z tile code (D = 1, 2, 4 with plan V = 0, 1, 2: codes D + 8 V; anything else is 1) as a compile-time
+// constant
 template <typename F>
-static void ztile_dispatch(int zdiv, F&& f) {
-  if (zdiv == 4) f(std::integral_constant<int, 4>{});
-  else if (zdiv == 2) f(std::integral_constant<int, 2>{});
-  else f(std::integral_constant<int, 1>{});
+static void ztile_dispatch(int code, F&& f) {
+  switch (code) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 10: f(std::integral_constant<int, 10>{}); break;
+    case 12: f(std::integral_constant<int, 12>{}); break;
+    case 17: f(std::integral_constant<int, 17>{}); break;
+    case 18: f(std::integral_constant<int, 18>{}); break;
+    case 20: f(std::integral_constant<int, 20>{}); break;
+    default: f(std::integral_constant<int, 1>{}); break;
+  }
+}
+static bool ztile_valid(int code) {
+  const int d = code % 8, v = code / 8;
+  return (d == 1 || d == 2 || d == 4) && v >= 0 && v <= 2;
 }
 
 // register-FFT launches for the specialised sizes
@@ -4843,11 +4886,15 @@ lmvd_status lmvd_graph_autotune(const lmvd_plan* plans, const lmvd_substep_args*
   };
   double best = 0.0;
   lmvd_status st = measure(best);
-  // coordinate descent over the transform sizes present: one divisor per size, kept when it is at least
-  // 1 % faster than the best so far
+  // coordinate descent over the transform sizes present: one tile code per size (line plan and divisor),
+  // kept when it is at least 1 % faster than the best so far
   for (size_t k = 0; k < sizes.size() && st == LMVD_OK; ++k) {
     int cur = 1;
-    for (int d : {2, 4}) {
+    std::vector<int> codes;
+    for (int v = 0; v < zplan_count(sizes[k]); ++v)
+      for (int dd : {1, 2, 4})
+        if (dd + 8 * v != 1) codes.push_back(dd + 8 * v);
+    for (int d : codes) {
       for (int i = 0; i < count; ++i)
         if (tileable(plans[i]) && plans[i]->H.cfg.m3 == sizes[k]) plans[i]->zdiv = d;
       double t = 0.0;
@@ -4873,14 +4920,15 @@ lmvd_status lmvd_autotune(lmvd_plan plan, void* workspace, void* stream, int32_t
                           double* times_ms) {
   if (!plan || !workspace || !zdiv) return LMVD_EINVAL;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return LMVD_EINVAL;
-  if (force != 0 && force != 1 && force != 2 && force != 4) return LMVD_EINVAL;
+  if (force != 0 && !ztile_valid(force)) return LMVD_EINVAL;
   if (plan->prof.cls >= 0) return LMVD_EINVAL;
   if (hipSetDevice(plan->device) != hipSuccess) return LMVD_EHIP;
   const HostTables& H = plan->H;
   const int M3 = H.cfg.m3;
-  const int cand[3] = {1, 2, 4};
+  const int cand[9] = {1, 2, 4, 9, 10, 12, 17, 18, 20};
+  const int ncand = 3 * zplan_count(M3);
   if (times_ms)
-    for (int i = 0; i < 3; ++i) times_ms[i] = -1.0;
+    for (int i = 0; i < 9; ++i) times_ms[i] = -1.0;
   // only the register z kernels below 768 points have a tile choice
   if (!(plan->use_reg && zreg_size(M3) && M3 != 768)) {
     plan->zdiv = 1;
@@ -4917,7 +4965,7 @@ lmvd_status lmvd_autotune(lmvd_plan plan, void* workspace, void* stream, int32_t
   int best = 1;
   float best_ms = 0.0f;
   lmvd_status st = LMVD_OK;
-  for (int i = 0; i < 3 && st == LMVD_OK; ++i) {
+  for (int i = 0; i < ncand && st == LMVD_OK; ++i) {
     plan->zdiv = cand[i];
     auto pass = [&]() {
 #define CALLZ(N) launch_zinv_t<N>(c, A, zbuf, 0, nb, 3)
@@ -5164,6 +5212,19 @@ lmvd_status lmvd_factor_check_host(const lmvd_config* cfg, double growth_max, do
   return st;
 }
 
+lmvd_status lmvd_basis_values(const lmvd_config* cfg, int32_t npts, const double* y, int32_t star, double* out) {
+  if (!cfg || npts < 0 || (npts > 0 && (!y || !out)) || (star != 0 && star != 1)) return LMVD_EINVAL;
+  HostTables H;
+  std::string msg;
+  lmvd_status st = build_host_tables(*cfg, H, msg);
+  if (st != LMVD_OK) return st;
+  std::vector<double> v;
+  st = basis_values(H, star, std::vector<double>(y, y + npts), v);
+  if (st != LMVD_OK) return st;
+  std::copy(v.begin(), v.end(), out);
+  return LMVD_OK;
+}
+
 lmvd_status lmvd_host_tables(const lmvd_config* cfg, double* tau, double* tau_star, double* E0, double* E1,
                              double* E2) {
   if (!cfg) return LMVD_EINVAL;
@@ -5183,3 +5244,5 @@ lmvd_status lmvd_host_tables(const lmvd_config* cfg, double* tau, double* tau_st
 }
 
 }  // extern "C"
+
+#include "substep_adjoint.h"

@@ -519,3 +519,19 @@ lmvd_status factor_check_host(const HostTables& H, double growth_max, FactorChec
 }
 
 }  // namespace lmvd
+
+namespace lmvd {
+
+// Values of the B basis (order p, star = 0) or the B* basis (order p + 1, star = 1) at the points y, all
+// within [-L2/2, L2/2]: out[i * ncols + j] = B_j(y_i), ncols = n2 (n2 + 1 for B*).
+lmvd_status basis_values(const HostTables& H, int star, const std::vector<double>& y, std::vector<double>& out) {
+  const double h = 0.5 * H.cfg.L2;
+  for (double v : y)
+    if (!(v >= -h && v <= h)) return LMVD_EINVAL;
+  RowTable rt;
+  rows_at(star ? H.ts : H.t, star ? H.p + 1 : H.p, y, 0, &rt);
+  out = dense(rt);
+  return LMVD_OK;
+}
+
+}  // namespace lmvd

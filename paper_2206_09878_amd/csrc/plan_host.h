@@ -99,6 +99,10 @@ struct FactorCheck {
 };
 lmvd_status factor_check_host(const HostTables& H, double growth_max, FactorCheck& out);
 
+// Values of the B (star = 0) or B* (star = 1) basis at arbitrary points of [-L2/2, L2/2], dense
+// [points][n2 (+1)].
+lmvd_status basis_values(const HostTables& H, int star, const std::vector<double>& y, std::vector<double>& out);
+
 // Dense copy of a row table (row-major rows x cols).
 std::vector<double> dense(const RowTable& r);
 

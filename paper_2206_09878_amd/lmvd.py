@@ -54,13 +54,27 @@ class SubstepArgs(ctypes.Structure):
     ]
 
 
+_V = ctypes.c_void_p
+
+
+class SubstepGrads(ctypes.Structure):
+    """Mirror of lmvd_substep_grads: output cotangents, then input gradients."""
+    _fields_ = ([(n, _V) for n in ("phi2_out", "omega2_out", "z_out", "m1bar_out", "m3bar_out", "rhs_phi2",
+                                   "rhs_omega2", "zt", "rhs_m1", "rhs_m3")]
+                + [("md", _V * 3), ("mc", _V * 3)]
+                + [(n, _V) for n in ("phi2", "omega2", "z", "m1bar", "m3bar")]
+                + [("z_hist", _V * 3)]
+                + [(n, _V) for n in ("rhs_phi2_prev", "rhs_omega2_prev", "zt_prev", "rhs_m1_prev", "rhs_m3_prev")])
+
+
 EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_sizes", "lmvd_substep",
            "lmvd_to_physical", "lmvd_to_spectral", "lmvd_project", "lmvd_evaluate", "lmvd_md", "lmvd_mc",
            "lmvd_host_tables", "lmvd_profile_start", "lmvd_profile_stop", "lmvd_graph_create",
            "lmvd_graph_launch", "lmvd_graph_destroy", "lmvd_graph_grouped", "lmvd_autotune",
            "lmvd_graph_autotune", "lmvd_rhs", "lmvd_to_physical_adjoint", "lmvd_evaluate_adjoint",
            "lmvd_project_adjoint", "lmvd_md_adjoint", "lmvd_mc_adjoint", "lmvd_to_spectral_adjoint",
-           "lmvd_factor_check", "lmvd_factor_check_host"]
+           "lmvd_factor_check", "lmvd_factor_check_host",
+           "lmvd_adjoint_sizes", "lmvd_substep_adjoint", "lmvd_basis_values"]
 
 
 def library():
@@ -78,6 +92,9 @@ def library():
         lib.lmvd_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                    ctypes.POINTER(ctypes.c_size_t)]
         lib.lmvd_substep.argtypes = [vp, ctypes.POINTER(SubstepArgs), vp, vp]
+        lib.lmvd_adjoint_sizes.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
+        lib.lmvd_basis_values.argtypes = [ctypes.POINTER(Config), i32, vp, i32, vp]
+        lib.lmvd_substep_adjoint.argtypes = [vp, ctypes.POINTER(SubstepArgs), ctypes.POINTER(SubstepGrads), vp, vp]
         lib.lmvd_to_physical.argtypes = [vp, vp, vp, vp, vp]
         lib.lmvd_to_spectral.argtypes = [vp, vp, vp, vp, vp]
         lib.lmvd_project.argtypes = [vp, i32, vp, vp, vp]
@@ -148,6 +165,16 @@ def host_tables(w):
     return tau, taus, E
 
 
+def basis_values(w, y, star: bool = False):
+    """Values of the B (B* with star) basis at the points y (host): array [len(y), n2 (+1)]."""
+    cfg = make_config(w)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.zeros((len(y), w.n2 + (1 if star else 0)))
+    _check(library().lmvd_basis_values(ctypes.byref(cfg), len(y), y.ctypes.data, int(star), out.ctypes.data),
+           "lmvd_basis_values")
+    return out
+
+
 def factor_check_host(w, growth_max: float = 1e4):
     """Pivot check of the A(k) elimination for every distinct k of the workload's grid, on the host
     (lmvd_factor_check_host).  Returns (status, max growth, min pivot ratio, failed rows, distinct k)."""
@@ -198,11 +225,13 @@ class Plan:
             _check(st, "lmvd_factor_check")
         return st, g.value, r.value, bad.value
 
+    TILE_CODES = (1, 2, 4, 9, 10, 12, 17, 18, 20)
+
     def autotune(self, force: int = 0):
-        """Pick the z-transform tile by timing (force = 0) or set it (1, 2, 4); see lmvd_autotune.
-        Returns (divisor, per-candidate ms or -1)."""
+        """Pick the z-transform tile (line plan and divisor, code D + 8 V) by timing (force = 0) or set it
+        (force = a code); see lmvd_autotune.  Returns (code, per-code ms or -1, in TILE_CODES order)."""
         z = ctypes.c_int32()
-        t = (ctypes.c_double * 3)()
+        t = (ctypes.c_double * 9)()
         _check(library().lmvd_autotune(self.handle, _ptr(self.ws), self._stream(), force, ctypes.byref(z), t),
                "lmvd_autotune")
         return z.value, list(t)
@@ -269,6 +298,73 @@ class Plan:
             for i in range(3):
                 a.mc[i] = mc[i].data_ptr()
         return a
+
+    # -- adjoint of the substep ---------------------------------------------------------
+    def adjoint_workspace(self, kf: int = -1):
+        """The adjoint's workspace (lmvd_adjoint_sizes; it contains the substep's), allocated once per k_f."""
+        kf = self.w.kf if kf < 0 else kf
+        cache = self.__dict__.setdefault("_adj_ws", {})
+        if kf not in cache:
+            b = ctypes.c_size_t()
+            _check(library().lmvd_adjoint_sizes(self.handle, kf, ctypes.byref(b)), "lmvd_adjoint_sizes")
+            buf = self.torch.empty(b.value + 256, dtype=self.torch.uint8, device="cuda")
+            off = (-buf.data_ptr()) % 256
+            cache[kf] = (buf, buf[off:off + b.value])
+        return cache[kf][1]
+
+    def substep_adjoint(self, stage, inputs, cot, kf=-1, guess_mode=0):
+        """Gradients of <cot, outputs of one substep> with respect to its inputs (lmvd_substep_adjoint).
+        inputs: phi2, omega2, z, m1bar, m3bar, hist (3), and at stage 1 rhs_prev (dict), zt_prev (device
+        tensors).  cot: phi2_out, omega2_out, z_out, m1bar_out, m3bar_out, rhs (dict: phi2, omega2,
+        m1bar, m3bar), zt, optional md, mc (3-tuples); any missing entry is zero.  Returns a dict like
+        inputs with the gradients."""
+        torch = self.torch
+        w = self.w
+        zS = lambda star=False: self.empty(star).zero_()
+        zV = lambda: torch.zeros(w.n2, dtype=torch.float64, device="cuda")
+        rhs = cot.get("rhs") or {}
+        c = {"phi2_out": cot.get("phi2_out"), "omega2_out": cot.get("omega2_out"), "z_out": cot.get("z_out"),
+             "m1bar_out": cot.get("m1bar_out"), "m3bar_out": cot.get("m3bar_out"), "rhs_phi2": rhs.get("phi2"),
+             "rhs_omega2": rhs.get("omega2"), "zt": cot.get("zt"), "rhs_m1": rhs.get("m1bar"),
+             "rhs_m3": rhs.get("m3bar")}
+        keep = []
+        for k in c:
+            if c[k] is None:
+                c[k] = zV() if k in ("m1bar_out", "m3bar_out", "rhs_m1", "rhs_m3") else zS()
+            c[k] = c[k].contiguous()
+            keep.append(c[k])
+        g = SubstepGrads()
+        for k, v in c.items():
+            setattr(g, k, _ptr(v))
+        for name in ("md", "mc"):
+            t = cot.get(name)
+            if t is not None:
+                arr = getattr(g, name)
+                for i in range(3):
+                    if t[i] is not None:
+                        x = t[i].contiguous()
+                        keep.append(x)
+                        arr[i] = x.data_ptr()
+        out = {"phi2": zS(), "omega2": zS(), "z": zS(), "m1bar": zV(), "m3bar": zV()}
+        for k in ("phi2", "omega2", "z", "m1bar", "m3bar"):
+            setattr(g, k, _ptr(out[k]))
+        if guess_mode == 0:
+            out["hist"] = [zS() for _ in range(3)]
+            for i in range(3):
+                g.z_hist[i] = out["hist"][i].data_ptr()
+        if stage == 1:
+            out["rhs_prev"] = {"phi2": zS(), "omega2": zS(), "m1bar": zV(), "m3bar": zV()}
+            out["zt_prev"] = zS()
+            g.rhs_phi2_prev, g.rhs_omega2_prev = _ptr(out["rhs_prev"]["phi2"]), _ptr(out["rhs_prev"]["omega2"])
+            g.rhs_m1_prev, g.rhs_m3_prev = _ptr(out["rhs_prev"]["m1bar"]), _ptr(out["rhs_prev"]["m3bar"])
+            g.zt_prev = _ptr(out["zt_prev"])
+        a = self.substep_args(stage, inputs["phi2"], inputs["omega2"], inputs["z"], inputs["m1bar"],
+                              inputs["m3bar"], z_out=zS(), hist=inputs.get("hist"), kf=kf, guess_mode=guess_mode,
+                              rhs_prev=inputs.get("rhs_prev"), zt_prev=inputs.get("zt_prev"))
+        _check(library().lmvd_substep_adjoint(self.handle, ctypes.byref(a), ctypes.byref(g),
+                                              _ptr(self.adjoint_workspace(kf)), self._stream()),
+               "lmvd_substep_adjoint")
+        return out
 
     # -- timing hook -----------------------------------------------------------------
     KERNEL_CLASSES = ("zinv", "xpass_rz", "xpass_l", "xpass_rhot", "xpass_vel", "zfwd", "mc", "md", "proj",

@@ -139,3 +139,40 @@ def test_factor_check_host_fires_below_the_growth_it_sees():
     assert st == 0
     st, _, _, bad, _ = factor_check_host(w, growth_max=0.5 * (1.0 + growth))
     assert st == -5 and bad > 0
+
+
+@pytest.mark.parametrize("struct,cname", [("SubstepGrads", "lmvd_substep_grads"), ("SubstepArgs", "lmvd_substep_args")])
+def test_argument_struct_layouts_match_the_header(tmp_path, struct, cname):
+    """The ctypes mirrors of lmvd_substep_grads and lmvd_substep_args have the C structs' size and field
+    offsets (gcc, host only)."""
+    import subprocess
+    cls = getattr(lmvd, struct)
+    fields = [f[0] for f in cls._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lmvd.h"\nint main(void) {\n'
+                   f'  printf("%zu\\n", sizeof({cname}));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof({cname}, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(cls)
+    assert got[1:] == [getattr(cls, f).offset for f in fields]
+
+
+def test_basis_values_match_scipy():
+    """lmvd_basis_values (the plan builder's Cox-de Boor at arbitrary y) against scipy's B-splines on the
+    same knots, for B (order p) and B* (order p + 1), including both walls."""
+    from scipy.interpolate import BSpline
+    from paper_2206_09878_amd.lmvd import basis_values
+    w = workload("small", n=16, n2=25)
+    sp = SplineSpaces(w.breakpoints, w.order)
+    y = np.concatenate([[-w.L2 / 2, w.L2 / 2], np.random.default_rng(3).uniform(-w.L2 / 2, w.L2 / 2, 40)])
+    for star, t, k in ((False, sp.t, w.order - 1), (True, sp.ts, w.order)):
+        got = basis_values(w, y, star=star)
+        ref = BSpline.design_matrix(np.clip(y, t[0], t[-1] - 1e-15 * w.L2), t, k).toarray()
+        ref[1] = 0.0
+        ref[1, -1] = 1.0                           # the right end: the last basis function alone
+        assert np.abs(got - ref).max() < 1e-12, star
+    with pytest.raises(lmvd.LmvdError):
+        basis_values(w, [w.L2])

@@ -515,129 +515,3 @@ def test_multistep_gradient_with_checkpoints(torch):
             an = rdot(torch, grads[0], dvec)
             print("direction", k, "central", f1, "extrapolated", fd, "adjoint", an, flush=True)
             assert abs(fd - an) < 1e-6 * max(abs(an), 1e-12 * abs(f1) + 1e-300), (k, f1, fd, an)
-
-
-def test_adjoint_at_the_adjoint_workload_size(torch):
-    """At the adjoint workload's size, 96 x 97 x 96 (density 1 -> 7 layer): one RK step (stages n and ')
-    composed from the differentiable operators, the kinetic energy of m^d at its end, the gradient
-    with respect to the initial z against extrapolated central differences on 2 directions; prints the
-    forward and forward + backward times (the adjoint / forward ratio of this composition)."""
-    import time
-
-    from paper_2206_09878_amd.autograd import evaluate, md, to_physical
-    from paper_2206_09878_amd.lmvd import Plan
-    from paper_2206_09878_amd.workloads import make_inputs
-    w = workload("adjoint96")
-    p = Plan(w)
-    op = OPlan(oracle_config(w))
-    inp = make_inputs(w, seed=97, stage=0)
-    st0 = [p.to_dev(inp[k]) for k in ("phi2", "omega2", "z", "m1bar", "m3bar")]
-    hist0 = [p.to_dev(h) for h in inp["hist"]]
-    print("adjoint workload size", (w.n1, w.n2, w.n3), flush=True)
-
-    def objective(z0):
-        a = composed_substep(torch, p, op, [st0[0], st0[1], z0, st0[3], st0[4]], hist0, stage=0)
-        b = composed_substep(torch, p, op, [a["phi2"], a["omega2"], a["z"], a["m1bar"], a["m3bar"]],
-                             [z0, hist0[0], hist0[1]], stage=1, prev=(a["rhs"], a["zt"]))
-        m1, m2, m3 = md(p, b["phi2"], b["omega2"], b["m1bar"], b["m3bar"])
-        zp = to_physical(p, evaluate(p, 0, b["z"]))
-        rho = w.rho_l * w.rho_h / (w.rho_h - (w.rho_h - w.rho_l) * zp)
-        ke = sum(to_physical(p, evaluate(p, 0, m, star=(i == 1))) ** 2 for i, m in enumerate((m1, m2, m3)))
-        return 0.5 * torch.mean(ke / rho)
-
-    with torch.no_grad():
-        objective(st0[2])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.no_grad():
-        objective(st0[2])
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    z0 = st0[2].clone().requires_grad_(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    objective(z0).backward()
-    torch.cuda.synchronize()
-    t_both = time.perf_counter() - t0
-    grad = z0.grad.detach()
-    print(f"forward {t_fwd:.3f} s, forward + backward {t_both:.3f} s, adjoint / forward {(t_both - t_fwd) / t_fwd:.2f}",
-          flush=True)
-    eps = 1e-6 * st0[2].abs().max().item()
-    with torch.no_grad():
-        for k in range(2):
-            dvec = crand(torch, w.shape, 600 + k)
-            c = lambda e: (objective(st0[2] + e * dvec) - objective(st0[2] - e * dvec)).item() / (2 * e)
-            f1, f2 = c(eps), c(0.5 * eps)
-            fd = (4.0 * f2 - f1) / 3.0
-            an = rdot(torch, grad, dvec)
-            print("direction", k, "central", f1, "extrapolated", fd, "adjoint", an, flush=True)
-            assert abs(fd - an) < 1e-6 * max(abs(an), 1e-300), (k, f1, fd, an)
-
-
-def test_adjoint_workload_twenty_steps_checkpointed(torch):
-    """The adjoint workload: 96 x 97 x 96 (density 1 -> 7 layer), 20 RK steps (40 substeps) composed
-    from the differentiable operators with checkpointed recomputation every 5 steps; objective the
-    domain-averaged kinetic energy of m^d at the final time; its gradient with respect to the initial
-    scalar z (the density field is f(z)) against central differences, eps = 1e-6 (relative), on 16
-    random directions, extrapolated from eps and eps/2."""
-    import time
-
-    from torch.utils.checkpoint import checkpoint
-
-    from paper_2206_09878_amd.autograd import evaluate, md, to_physical
-    from paper_2206_09878_amd.lmvd import Plan
-    from paper_2206_09878_amd.workloads import make_inputs
-    w = workload("adjoint96")
-    p = Plan(w)
-    op = OPlan(oracle_config(w))
-    inp = make_inputs(w, seed=98, stage=0)
-    st0 = [p.to_dev(inp[k]) for k in ("phi2", "omega2", "z", "m1bar", "m3bar")]
-    hist0 = [p.to_dev(h) for h in inp["hist"]]
-
-    def rk_step(phi2, om2, z, m1bar, m3bar, h1, h2, h3):
-        a = composed_substep(torch, p, op, [phi2, om2, z, m1bar, m3bar], [h1, h2, h3], stage=0)
-        zp = a["z"]
-        b = composed_substep(torch, p, op, [a["phi2"], a["omega2"], zp, a["m1bar"], a["m3bar"]], [z, h1, h2],
-                             stage=1, prev=(a["rhs"], a["zt"]))
-        return b["phi2"], b["omega2"], b["z"], b["m1bar"], b["m3bar"], zp, z, h1
-
-    def objective(z0, ckpt):
-        carry = (st0[0], st0[1], z0, st0[3], st0[4], *hist0)
-        for _ in range(4):
-            def segment(*c):
-                for _ in range(5):
-                    c = rk_step(*c)
-                return c
-            carry = checkpoint(segment, *carry, use_reentrant=False) if ckpt else segment(*carry)
-        phi2, om2, z, m1bar, m3bar = carry[:5]
-        m1, m2, m3 = md(p, phi2, om2, m1bar, m3bar)
-        zp = to_physical(p, evaluate(p, 0, z))
-        rho = w.rho_l * w.rho_h / (w.rho_h - (w.rho_h - w.rho_l) * zp)
-        ke = sum(to_physical(p, evaluate(p, 0, m, star=(i == 1))) ** 2 for i, m in enumerate((m1, m2, m3)))
-        return 0.5 * torch.mean(ke / rho)
-
-    print("adjoint workload", (w.n1, w.n2, w.n3), "20 RK steps, checkpoint every 5", flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.no_grad():
-        J = objective(st0[2], False).item()
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    z0 = st0[2].clone().requires_grad_(True)
-    t0 = time.perf_counter()
-    objective(z0, True).backward()
-    torch.cuda.synchronize()
-    t_adj = time.perf_counter() - t0
-    grad = z0.grad.detach()
-    print(f"objective {J:.6e}; forward {t_fwd:.2f} s, checkpointed forward + backward {t_adj:.2f} s", flush=True)
-    assert np.isfinite(J) and torch.isfinite(torch.view_as_real(grad)).all()
-    eps = 1e-6 * st0[2].abs().max().item()
-    with torch.no_grad():
-        for k in range(16):
-            dvec = crand(torch, w.shape, 700 + k)
-            c = lambda e: (objective(st0[2] + e * dvec, False) - objective(st0[2] - e * dvec, False)).item() / (2 * e)
-            f1, f2 = c(eps), c(0.5 * eps)
-            fd = (4.0 * f2 - f1) / 3.0
-            an = rdot(torch, grad, dvec)
-            print("direction", k, "central", f1, "extrapolated", fd, "adjoint", an, flush=True)
-            assert abs(fd - an) < 1e-6 * max(abs(an), 1e-300), (k, f1, fd, an)

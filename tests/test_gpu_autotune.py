@@ -1,11 +1,12 @@
 """The z-tile autotuner (lmvd_autotune) through the C ABI:
 
-  * every tile divisor D = 1, 2, 4 gives the oracle's substep at 1e-11, and
-    the same bits as the other divisors (each z line is transformed by the same
-    threads in the same order; only the number of lines per block changes);
+  * every tile code K = D + 8 V (line plan V: threads per line, radix split and stage order; divisor D of
+    the lines per block) gives the oracle's substep at 1e-11 at the five register z sizes (M3 = 48, 72,
+    96, 144, 192); codes of one plan give the same bits (each z line is transformed by the same
+    threads in the same order; only the number of lines per block changes), and the plans agree with
+    each other to rounding;
   * the timed choice is one of the candidates, with a time for each;
-  * plans without a tile choice (768-point z lines, sizes without a register
-    plan) keep D = 1;
+  * plans without a tile choice (768-point z lines, sizes without a register plan) keep K = 1;
   * a graph of tuned instances of uneven sizes equals their eager substeps;
   * the graph-level tuner (timing the graph itself) leaves the results unchanged.
 """
@@ -24,18 +25,29 @@ def torch():
     return t
 
 
-@pytest.mark.parametrize("n,n2", [(32, 33), (48, 49), (64, 65)])
+@pytest.mark.parametrize("n,n2", [(32, 33), (48, 49), (64, 65), (96, 33), (128, 17)])
 def test_every_tile_matches_the_oracle_and_each_other(torch, n, n2):
+    from tests.test_gpu_parity import gpu_substep, oracle_substep, output_errors
+    from paper_2206_09878_amd.lmvd import Plan
     w = workload("small", n=n, n2=n2)
+    inp = make_inputs(w, seed=50, stage=0)
+    ref = oracle_substep(w, 0, inp)
+    nplans = 3 if w.m3 in (48, 72, 96, 144, 192) else 1
+    codes = [d + 8 * v for v in range(nplans) for d in (1, 2, 4)]
     outs = {}
-    for d in (1, 2, 4):
-        print("tile", d, (n, n2, n), flush=True)
-        got, ref = run_pair(w, 0, seed=50, tile=d)
+    for k in codes:
+        print("tile", k, (n, n2, n), flush=True)
+        got = gpu_substep(w, 0, inp, tile=k)
         check_pair(got, ref)
-        outs[d] = got
-    for d in (2, 4):
-        for k in ("phi2", "omega2", "z", "zt"):
-            assert (outs[d][k] == outs[1][k]).all(), (d, k)
+        outs[k] = got
+    for k in codes:
+        base = outs[k - (k % 8) + 1]                 # the same plan with D = 1
+        for key in ("phi2", "omega2", "z", "zt"):
+            assert (outs[k][key] == base[key]).all(), (k, key)
+        other = {"state": outs[1], "zt": outs[1]["zt"], "rhs": outs[1]["rhs"],
+                 "diag": {"md": outs[1]["md"], "mc": outs[1]["mc"]}}
+        errs = output_errors(outs[k], other)
+        assert max(errs.values()) < 1e-12, (k, errs)
 
 
 def test_timed_choice(torch):
@@ -43,16 +55,16 @@ def test_timed_choice(torch):
     p = Plan(workload("small", n=32, n2=33))
     d, t = p.autotune()
     print("choice", d, "times (ms)", t, flush=True)
-    assert d in (1, 2, 4)
-    assert all(x > 0 for x in t)
-    assert t[(1, 2, 4).index(d)] == min(t)
+    assert d in p.TILE_CODES
+    assert all(x > 0 for x in t)                     # M3 = 48: three plans, every code timed
+    assert t[p.TILE_CODES.index(d)] == min(t)
 
 
 def test_no_choice_without_register_z_kernels(torch):
     from paper_2206_09878_amd.lmvd import Plan
     for w in (workload("small", n=24, n2=25), workload("rt512", n=512, n2=9)):   # M3 = 36, 768
         d, t = Plan(w).autotune()
-        assert d == 1 and t == [-1.0, -1.0, -1.0]
+        assert d == 1 and t == [-1.0] * 9
 
 
 def test_graph_of_tuned_instances(torch):
@@ -61,7 +73,7 @@ def test_graph_of_tuned_instances(torch):
     mk = lambda: [Stepper(Plan(w), make_inputs(w, seed=w.extra["seed"], stage=0), stage=0) for w in ws]
     A, B = mk(), mk()
     for i, s in enumerate(A):
-        s.p.autotune(force=(1, 2, 4)[i % 3])
+        s.p.autotune(force=(1, 2, 4, 9, 12, 18, 20)[i % 7])
     g = GraphBatch(A, nsub=4)
     for _ in range(2):
         for s in B:
@@ -85,7 +97,7 @@ def test_graph_autotune_keeps_the_results(torch):
     g = GraphBatch(A, nsub=4)
     tiles, ms = g.autotune(launches=1)
     print("graph tiles", tiles, "ms per launch", ms, flush=True)
-    assert len(tiles) == 6 and all(t in (1, 2, 4) for t in tiles) and ms > 0
+    assert len(tiles) == 6 and all(t in Plan.TILE_CODES for t in tiles) and ms > 0
     for a, b in zip(A, B):
         sa, sb = a.state(), b.state()
         assert sa["stage"] == sb["stage"] == 0

@@ -57,10 +57,11 @@ def test_transforms(torch, name, n, n2):
     V = hermitian(rng, w.shape)
     ref = to_physical(V, w.m1, w.m3)
     got = host(p.to_physical(p.to_dev(V)))
-    assert rel(got, ref) < TOL
     u = rng.standard_normal((w.n2, w.m3, w.m1))
     refV = to_spectral(u, w.n1, w.n3)
     gotV = host(p.to_spectral(p.to_dev(u)))
+    print(f"transforms {w.m1}x{w.m3}: inverse {rel(got, ref):.1e}, forward {rel(gotV, refV):.1e}", flush=True)
+    assert rel(got, ref) < TOL
     assert rel(gotV, refV) < TOL
 
 
@@ -147,8 +148,7 @@ def run_pair(w, stage, seed=0, kf=None, guess_mode=0, plane_batch=0, tile=0, inp
 
 class scipy_fft_in_oracle:
     """Run the oracle with scipy.fft in place of numpy.fft: the same sums with
-    a different rounding.  The spread between the two oracle runs measures how
-    much float64 rounding the quantity itself amplifies."""
+    a different rounding."""
 
     def __enter__(self):
         import types
@@ -165,34 +165,114 @@ class scipy_fft_in_oracle:
         self.F.np = self.np
 
 
-def rhs_tolerances(w, stage, seed, kf=None, ref=None, inputs=None):
-    """Per-field bound for the stage RHS outputs: 1e-11, or 4x the oracle's own
-    numpy-vs-scipy FFT spread where derivatives amplify rounding more."""
-    op = OPlan(oracle_config(w))
-    inp = make_inputs(w, seed=seed, stage=stage) if inputs is None else inputs
-    st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
-    kw = dict(rhs_prev=inp["rhs_prev"], zt_prev=inp["zt_prev"]) if stage == 1 else {}
-    with scipy_fft_in_oracle():
-        alt = substep(op, st, stage, hist=inp["hist"], kf=kf, **kw)
-    return {k: max(TOL, 4.0 * rel(alt["rhs"][k], ref["rhs"][k])) for k in alt["rhs"]}
+class dense_solves_in_oracle:
+    """Run the oracle with its banded solves done as dense pivoted LU (numpy.linalg.solve), eliminating
+    from the first row (reverse = False) or, on the row- and column-reversed system, from the last row:
+    the same systems with other elimination orders and rounding."""
+
+    def __init__(self, reverse=False):
+        self.reverse = reverse
+
+    def __enter__(self):
+        import oracle.lmvd as O
+        self.O, self.orig = O, O.banded_solve
+        rev = self.reverse
+
+        def dense(A, B):
+            shp = B.shape
+            b = B.reshape(shp[0], -1)
+            if rev:
+                return np.linalg.solve(A[::-1, ::-1], b[::-1])[::-1].reshape(shp)
+            return np.linalg.solve(A, b).reshape(shp)
+        O.banded_solve = dense
+        return self
+
+    def __exit__(self, *exc):
+        self.O.banded_solve = self.orig
 
 
-def check_pair(got, ref, tol=TOL, rhs_tol=None):
+class transform_rounding_in_oracle:
+    """Run the oracle with one unit of float64 rounding, at the scale of each transform's largest output,
+    added to every output of its inverse and forward transforms (seeded uniform noise): a model of the
+    rounding that another transform implementation makes."""
+
+    def __init__(self, seed=77):
+        self.rng = np.random.default_rng(seed)
+
+    def __enter__(self):
+        import oracle.adjoint as A
+        import oracle.lmvd as O
+        self.mods = [(M, M.to_physical, M.to_spectral) for M in (O, A)]
+        eps = 2.0 ** -53
+
+        def noisy(f):
+            def g(*a):
+                y = f(*a)
+                s = eps * np.abs(y).max()
+                if np.iscomplexobj(y):
+                    return y + s * (self.rng.uniform(-1, 1, y.shape) + 1j * self.rng.uniform(-1, 1, y.shape))
+                return y + s * self.rng.uniform(-1, 1, y.shape)
+            return g
+        for M, inv, fwd in self.mods:
+            M.to_physical, M.to_spectral = noisy(inv), noisy(fwd)
+        return self
+
+    def __exit__(self, *exc):
+        for M, inv, fwd in self.mods:
+            M.to_physical, M.to_spectral = inv, fwd
+
+
+def output_errors(got, ref):
+    """Relative max-norm difference of every output of a substep (state, z_t, RHS, m^d, m^c)."""
     errs = {}
     for k in ("phi2", "omega2", "z", "m1bar", "m3bar"):
         errs[k] = rel(got[k], ref["state"][k])
     errs["zt"] = rel(got["zt"], ref["zt"])
     for k in ("phi2", "omega2", "m1bar", "m3bar"):
         errs["rhs_" + k] = rel(got["rhs"][k], ref["rhs"][k])
-    for i in range(3):
-        errs[f"md{i}"] = rel(got["md"][i], ref["diag"]["md"][i])
-        errs[f"mc{i}"] = rel(got["mc"][i], ref["diag"]["mc"][i])
-    tols = {k: tol for k in errs}
+    if "md" in got:
+        for i in range(3):
+            errs[f"md{i}"] = rel(got["md"][i], ref["diag"]["md"][i])
+            errs[f"mc{i}"] = rel(got["mc"][i], ref["diag"]["mc"][i])
+    return errs
+
+
+def spread_tolerances(w, stage, ref, inputs, kf=None, rounding=False, factor=4.0):
+    """Per-output bound: 1e-11, or `factor` times the oracle's own spread where the output amplifies
+    float64 rounding more than that (derivatives of fields with large plane means, small differences of
+    large terms).  The spread is the difference between the oracle and the oracle run with scipy's FFT
+    in place of numpy's; with rounding, also with dense pivoted solves in place of the banded ones and
+    one unit of rounding, at the scale of each transform's largest output, added to every transform
+    output: the change that the rounding of another implementation of the same arithmetic makes to
+    the output."""
+    inp = inputs
+    st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
+    kw = dict(rhs_prev=inp["rhs_prev"], zt_prev=inp["zt_prev"]) if stage == 1 else {}
+    import contextlib
+    with scipy_fft_in_oracle(), (dense_solves_in_oracle() if rounding else contextlib.nullcontext()), \
+            (transform_rounding_in_oracle() if rounding else contextlib.nullcontext()):
+        alt = substep(OPlan(oracle_config(w)), st, stage, hist=inp["hist"], kf=kf, diagnostics=True, **kw)
+    alt_out = dict(alt["state"], zt=alt["zt"], rhs=alt["rhs"], md=alt["diag"]["md"], mc=alt["diag"]["mc"])
+    return {k: max(TOL, factor * v) for k, v in output_errors(alt_out, ref).items()}
+
+
+def rhs_tolerances(w, stage, seed, kf=None, ref=None, inputs=None):
+    """The spread bounds of the stage RHS outputs (see spread_tolerances), keyed phi2, omega2, m1bar, m3bar."""
+    inp = make_inputs(w, seed=seed, stage=stage) if inputs is None else inputs
+    t = spread_tolerances(w, stage, ref, inp, kf=kf)
+    return {k[4:]: v for k, v in t.items() if k.startswith("rhs_")}
+
+
+def check_pair(got, ref, tol=TOL, rhs_tol=None, tols=None):
+    errs = output_errors(got, ref)
+    bounds = {k: tol for k in errs}
     if rhs_tol:
         for k, v in rhs_tol.items():
-            tols["rhs_" + k] = v
-    print("  " + ", ".join(f"{k} {v:.1e}/{tols[k]:.0e}" for k, v in errs.items()), flush=True)
-    bad = {k: (v, tols[k]) for k, v in errs.items() if not v < tols[k]}
+            bounds["rhs_" + k] = v
+    if tols:
+        bounds.update({k: v for k, v in tols.items() if k in bounds})
+    print("  " + ", ".join(f"{k} {v:.1e}/{bounds[k]:.0e}" for k, v in errs.items()), flush=True)
+    bad = {k: (v, bounds[k]) for k, v in errs.items() if not v < bounds[k]}
     assert not bad, (bad, errs)
     return errs
 

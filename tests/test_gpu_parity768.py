@@ -11,14 +11,23 @@ Both stages, each from the same inputs:
   * all planes in one batch, as the benchmark launches it: the fixed-point iterates before the last
     stay on the grid (768-point z filter and wall planes);
   * plane batches of 5 (17 = 5 + 5 + 5 + 2, a ragged tail): the spectral path.
+Plane-mean momenta are added to the recipe's state as well (a jet in x1, a shear in x3), so that the
+mean equations are not a small residual of the fluctuations' products.
 Every output is compared element by element with the oracle (relative max-norm per field), each error
-printed beside its bound: 1e-11, and for the stage RHS max(1e-11, 4 x the oracle's own numpy-vs-scipy
-FFT spread)."""
+printed beside its bound: max(1e-11, 16 x the oracle's own rounding spread of that output), the spread
+being the oracle against the oracle run with scipy's FFT, dense pivoted solves and one unit of rounding
+(at the scale of each transform's largest output) added to every transform output; the factor 16 covers
+the several units of rounding of the library's radix-12 transforms and its other elimination order.
+The spread exceeds 1e-11 only where the output takes high derivatives of a field with a large plane
+mean: the synthetic z history gives a plane-mean mass flux <m2^c> of order 3 through the light fluid
+(rho = 0.039), so T_22 has a plane mean near 1.5e3, whose float64 rounding (1e-13 in every mode) times
+k^2 (up to 5e6) sits in RHS_phi2 at about 1e-8 of its largest entry, and so in phi2 = phi2 + dt/2
+RHS_phi2."""
 import numpy as np
 import pytest
 
-from paper_2206_09878_amd.workloads import broadband_momentum, make_inputs, workload
-from tests.test_gpu_parity import check_pair, gpu_substep, oracle_substep, rhs_tolerances
+from paper_2206_09878_amd.workloads import broadband_momentum, make_inputs, sample_points, workload
+from tests.test_gpu_parity import check_pair, gpu_substep, oracle_substep, spread_tolerances
 
 pytestmark = pytest.mark.gpu
 
@@ -33,10 +42,15 @@ def reference(stage):
         inp = make_inputs(w, seed=12 + stage, stage=stage)
         phi2, omega2 = broadband_momentum(w, seed=40 + stage)
         inp["phi2"], inp["omega2"] = phi2, omega2
+        # plane-mean momenta (a jet in x1, a shear in x3), so that the mean equations carry a stress of
+        # their own and not only the small residual of the fluctuations' products
+        y = sample_points(w.n2, w.L2, w.gamma)
+        inp["m1bar"] = 0.05 * np.exp(-y ** 2)
+        inp["m3bar"] = -0.03 * y * np.exp(-y ** 2)
         print(f"oracle rt512 recipe {w.n1}x{w.n2}x{w.n3}, M={w.m1}, ratio {w.rho_h / w.rho_l:.2f}, stage {stage}",
               flush=True)
         ref = oracle_substep(w, stage, inp)
-        tol = rhs_tolerances(w, stage, None, ref=ref, inputs=inp)
+        tol = spread_tolerances(w, stage, ref, inp, rounding=True, factor=16.0)
         _REF[stage] = (w, inp, ref, tol)
     return _REF[stage]
 
@@ -52,4 +66,4 @@ def test_rt768_substep_against_oracle(stage, plane_batch):
     assert np.abs(ref["diag"]["md"][0]).max() > 1e-6 and np.abs(ref["diag"]["mc"][1]).max() > 1e-6
     print(f"GPU stage {stage}, plane batch {plane_batch or w.n2}", flush=True)
     got = gpu_substep(w, stage, inp, plane_batch=plane_batch)
-    check_pair(got, ref, rhs_tol=tol)
+    check_pair(got, ref, tols=tol)
