@@ -215,14 +215,14 @@ lmvd_status lmvd_graph_grouped(lmvd_graph graph, int32_t* grouped);
 /* ---- tile autotuner ----
  * Chooses the tile of the register z-transform kernels of a plan with M3 < 768, as a code K = D + 8 V:
  * V in {0, 1, 2} selects the line plan (threads per z line T, radix split and stage order of the Stockham
- * FFT; three plans for M3 = 48, 72, 96, 144 and 192, one for the other sizes, where V = 1, 2 mean the
- * first) and D in {1, 2, 4} divides the 256 / T lines per block (fewer lines per block leave fewer idle
- * lanes when N1/2 is small).  The plans:
+ * FFT, whose first radix is the M3 / T points of a thread; three plans for M3 = 48, 72, 96, 144 and 192,
+ * one for the other sizes, where V = 1, 2 mean the first) and D in {1, 2, 4} divides the 256 / T lines
+ * per block (fewer lines per block leave fewer idle lanes when N1/2 is small).  The plans:
  *   M3 = 48:  V0 T 4 radices 12.4      V1 T 8 6.2.2.2     V2 T 2 24.2
  *   M3 = 72:  V0 T 6 12.6              V1 T 12 6.6.2      V2 T 3 24.3
- *   M3 = 96:  V0 T 8 12.4.2            V1 T 4 24.4        V2 T 4 8.12
+ *   M3 = 96:  V0 T 8 12.4.2            V1 T 4 24.4        V2 T 8 12.2.4
  *   M3 = 144: V0 T 12 12.12            V1 T 24 6.6.2.2    V2 T 6 24.6
- *   M3 = 192: V0 T 16 12.4.4           V1 T 8 24.8        V2 T 16 4.4.12
+ *   M3 = 192: V0 T 16 12.4.4           V1 T 8 24.8        V2 T 16 12.2.2.4
  * With force = 0 it times the inverse and forward z transforms of three fields over the plan's plane
  * batch for each candidate code (a warm-up, then 5 repetitions, HIP events on the stream) on the
  * caller's workspace, whose contents it overwrites, and keeps the fastest; force = a code (1, 2, 4, 9,

@@ -224,6 +224,7 @@ __device__ __forceinline__ void run_wave(double2* v, double2* lds, int base, int
 template <int N, int T, int DIR, int R0, int R1, int R2, int R3, int PADDIV>
 __device__ __forceinline__ void run(double2* v, double* lds, int base, int tl, const double2* __restrict__ tw) {
   static_assert(R0 * R1 * R2 * R3 == N, "radices must multiply to N");
+  static_assert(R0 == N / T, "stage 0 takes one butterfly per thread: v[r] = x[tl + T r] are its inputs");
   static_assert((N / T) % R0 == 0 && (N / T) % R1 == 0 && (N / T) % R2 == 0 && (N / T) % R3 == 0,
                 "every radix must divide N/T");
   constexpr int NS1 = R0, NS2 = R0 * R1, NS3 = R0 * R1 * R2;
@@ -341,6 +342,7 @@ __device__ __forceinline__ void exchange_split(double2* v, double* lds, int base
 template <int N, int T, int DIR, int R0, int R1, int R2, int R3, int PADDIV, bool BLK = false>
 __device__ __forceinline__ void run_split(double2* v, double* lds, int base, int tl, const double2* twl) {
   static_assert(R0 * R1 * R2 * R3 == N, "radices must multiply to N");
+  static_assert(R0 == N / T, "stage 0 takes one butterfly per thread: v[r] = x[tl + T r] are its inputs");
   static_assert((N / T) % R0 == 0 && (N / T) % R1 == 0 && (N / T) % R2 == 0 && (N / T) % R3 == 0,
                 "every radix must divide N/T");
   using ST = StageTw<R0, R1, R2, R3>;

@@ -605,13 +605,13 @@ LMVD_LINEPLAN(768, 0, 32, 24, 8, 4, 1, 24)
 LMVD_LINEPLAN(384, 0, 32, 12, 4, 4, 2, 12)
 LMVD_LINEPLAN(192, 0, 16, 12, 4, 4, 1, 12)
 LMVD_LINEPLAN(192, 1, 8, 24, 8, 1, 1, 24)
-LMVD_LINEPLAN(192, 2, 16, 4, 4, 12, 1, 12)
+LMVD_LINEPLAN(192, 2, 16, 12, 2, 2, 4, 12)
 LMVD_LINEPLAN(144, 0, 12, 12, 12, 1, 1, 12)
 LMVD_LINEPLAN(144, 1, 24, 6, 6, 2, 2, 6)
 LMVD_LINEPLAN(144, 2, 6, 24, 6, 1, 1, 24)
 LMVD_LINEPLAN(96, 0, 8, 12, 4, 2, 1, 12)
 LMVD_LINEPLAN(96, 1, 4, 24, 4, 1, 1, 24)
-LMVD_LINEPLAN(96, 2, 4, 8, 12, 1, 1, 8)
+LMVD_LINEPLAN(96, 2, 8, 12, 2, 4, 1, 12)
 LMVD_LINEPLAN(72, 0, 6, 12, 6, 1, 1, 12)
 LMVD_LINEPLAN(72, 1, 12, 6, 6, 2, 1, 6)
 LMVD_LINEPLAN(72, 2, 3, 24, 3, 1, 1, 24)
@@ -992,29 +992,30 @@ struct Pair;
 template <>
 struct Pair<PH_RZ> {
   static constexpr int NP = 4, NQ = 1, NST = 3;
-  // pairs (d z / d x, z), both from z's line, (lap z, m1), (z2, m2), (z3, m3): in a paired transform
-  // the rounding of each field is of the order of the larger one, so z and its gradient travel with
-  // fields no larger than themselves; m^d, small, takes the rounding of lap z and reaches R_z only
-  // through the advective term
-  __device__ static constexpr int fa(int i) { return i == 0 ? 6 : 2 * i - 2; }
-  __device__ static constexpr int fb(int i) { return i == 0 ? 6 : 2 * i - 1; }
-  // the x-derivative of z is formed here from z's line, mode by mode
+  // pairs (d z / d x, lap z), (z, m1), (z2, m2), (z3, m3).  In a paired transform the rounding of each
+  // field is of the order of the larger one.  lap z, by far the largest field, travels with a gradient
+  // component, which reaches R_z only times the small m^d (and L z_t times m^c); a momentum paired with
+  // lap z would carry that rounding into m . grad z, times the large gradient.  z's line is read twice:
+  // for its x-derivative (formed mode by mode) and for z itself
+  __device__ static constexpr int fa(int i) { return i < 2 ? 6 : 2 * i - 2; }
+  __device__ static constexpr int fb(int i) { return i == 0 ? 0 : 2 * i - 1; }
   __device__ static constexpr bool dxa(int i) { return i == 0; }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
   __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y, double* a, size_t fs) {
     // a == nullptr on lines past the grid edge: nothing is written there
-    if constexpr (I == 0) {  // x = d z / d x, y = z
-      const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * y);
-      s[0] = (P.rho_h - P.drho * y) * P.inv_rlrh;  // 1/rho
+    if constexpr (I == 0) {  // x = d z / d x, y = lap z
       s[2] = x;
+      s[1] = P.rhoD * y;
+    } else if constexpr (I == 1) {  // x = z, y = m1
+      const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x);
+      s[0] = (P.rho_h - P.drho * x) * P.inv_rlrh;  // 1/rho
+      s[1] -= s[2] * y;
       if (a) {
         a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
-        a[0] = -s[0] * x;
+        a[0] = -s[0] * s[2];
       }
-    } else if constexpr (I == 1) {  // x = lap z, y = m1
-      s[1] = P.rhoD * x - s[2] * y;
     } else {  // x = d z / d x_I, y = m_I
       s[1] -= x * y;
       if (a) a[(I - 1) * fs] = -s[0] * x;
@@ -1029,23 +1030,29 @@ struct Pair<PH_RZ> {
 template <>
 struct Pair<PH_RZV> {
   static constexpr int NP = 4, NQ = 1, NST = 3;
-  // pairs (lap z, z), (d z / d x from z's line, m1), (z2, m2), (z3, m3)
-  __device__ static constexpr int fa(int i) { return i == 0 ? 0 : i == 1 ? 6 : 2 * i - 2; }
-  __device__ static constexpr int fb(int i) { return i == 0 ? 6 : 2 * i - 1; }
-  __device__ static constexpr bool dxa(int i) { return i == 1; }
+  // the pairs of PH_RZ
+  __device__ static constexpr int fa(int i) { return Pair<PH_RZ>::fa(i); }
+  __device__ static constexpr int fb(int i) { return Pair<PH_RZ>::fb(i); }
+  __device__ static constexpr bool dxa(int i) { return Pair<PH_RZ>::dxa(i); }
   __device__ static constexpr int ga(int q) { return q; }
   __device__ static constexpr int gb(int) { return -1; }
   template <int I>
   __device__ __forceinline__ static void in(const DevPlan& P, double* s, double x, double y, double* a, size_t fs) {
-    if constexpr (I == 0) {
-      const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * y);
+    if constexpr (I == 0) {  // x = d z / d x, y = lap z (kept until rho D(z) is known)
+      s[2] = x;
+      s[1] = y;
+    } else if constexpr (I == 1) {  // x = z, y = m1
+      const double rho = (P.rho_l * P.rho_h) / (P.rho_h - P.drho * x);
       double k, dk;
-      rhod_of(P, y, rho, k, dk);
-      s[0] = (P.rho_h - P.drho * y) * P.inv_rlrh;  // 1/rho
-      s[1] = k * x;
+      rhod_of(P, x, rho, k, dk);
+      s[0] = (P.rho_h - P.drho * x) * P.inv_rlrh;  // 1/rho
+      s[1] = fma(dk * s[2], s[2], k * s[1] - s[2] * y);
+      if (a) {
+        a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
+        a[0] = -s[0] * s[2];
+      }
       s[2] = dk;
-      if (a) a[3 * fs] = rho * rho * P.drho * P.inv_rlrh;
-    } else {
+    } else {  // x = d z / d x_I, y = m_I
       s[1] = fma(s[2] * x, x, s[1] - x * y);
       if (a) a[(I - 1) * fs] = -s[0] * x;
     }

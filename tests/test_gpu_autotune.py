@@ -1,10 +1,11 @@
 """The z-tile autotuner (lmvd_autotune) through the C ABI:
 
   * every tile code K = D + 8 V (line plan V: threads per line, radix split and stage order; divisor D of
-    the lines per block) gives the oracle's substep at 1e-11 at the five register z sizes (M3 = 48, 72,
-    96, 144, 192); codes of one plan give the same bits (each z line is transformed by the same
-    threads in the same order; only the number of lines per block changes), and the plans agree with
-    each other to rounding;
+    the lines per block) gives the oracle's substep at the five register z sizes (M3 = 48, 72, 96, 144,
+    192), each output within 1e-11 or 4 x the oracle's own FFT-rounding spread where that is larger
+    (the stage RHS at 128 x 17 x 128, whose k^2-weighted mean-shear flux amplifies rounding); codes of one
+    plan give the same bits (each z line is transformed by the same threads in the same order; only the
+    number of lines per block changes), and the plans agree with each other within the same bounds;
   * the timed choice is one of the candidates, with a time for each;
   * plans without a tile choice (768-point z lines, sizes without a register plan) keep K = 1;
   * a graph of tuned instances of uneven sizes equals their eager substeps;
@@ -27,18 +28,18 @@ def torch():
 
 @pytest.mark.parametrize("n,n2", [(32, 33), (48, 49), (64, 65), (96, 33), (128, 17)])
 def test_every_tile_matches_the_oracle_and_each_other(torch, n, n2):
-    from tests.test_gpu_parity import gpu_substep, oracle_substep, output_errors
-    from paper_2206_09878_amd.lmvd import Plan
+    from tests.test_gpu_parity import gpu_substep, oracle_substep, output_errors, spread_tolerances
     w = workload("small", n=n, n2=n2)
     inp = make_inputs(w, seed=50, stage=0)
     ref = oracle_substep(w, 0, inp)
+    tol = spread_tolerances(w, 0, ref, inp)
     nplans = 3 if w.m3 in (48, 72, 96, 144, 192) else 1
     codes = [d + 8 * v for v in range(nplans) for d in (1, 2, 4)]
     outs = {}
     for k in codes:
         print("tile", k, (n, n2, n), flush=True)
         got = gpu_substep(w, 0, inp, tile=k)
-        check_pair(got, ref)
+        check_pair(got, ref, tols=tol)
         outs[k] = got
     for k in codes:
         base = outs[k - (k % 8) + 1]                 # the same plan with D = 1
@@ -47,7 +48,8 @@ def test_every_tile_matches_the_oracle_and_each_other(torch, n, n2):
         other = {"state": outs[1], "zt": outs[1]["zt"], "rhs": outs[1]["rhs"],
                  "diag": {"md": outs[1]["md"], "mc": outs[1]["mc"]}}
         errs = output_errors(outs[k], other)
-        assert max(errs.values()) < 1e-12, (k, errs)
+        bad = {key: (v, tol[key]) for key, v in errs.items() if not v < tol[key]}
+        assert not bad, (k, bad)
 
 
 def test_timed_choice(torch):
@@ -72,8 +74,11 @@ def test_graph_of_tuned_instances(torch):
     ws = batch_workloads(count=5, seed=4000)
     mk = lambda: [Stepper(Plan(w), make_inputs(w, seed=w.extra["seed"], stage=0), stage=0) for w in ws]
     A, B = mk(), mk()
-    for i, s in enumerate(A):
-        s.p.autotune(force=(1, 2, 4, 9, 12, 18, 20)[i % 7])
+    # the eager twins run the same line plans (plans differ from each other in rounding)
+    for i, (a, b) in enumerate(zip(A, B)):
+        k = (1, 2, 4, 9, 12, 18, 20)[i % 7]
+        a.p.autotune(force=k)
+        b.p.autotune(force=k - k % 8 + 1)
     g = GraphBatch(A, nsub=4)
     for _ in range(2):
         for s in B:
@@ -98,6 +103,8 @@ def test_graph_autotune_keeps_the_results(torch):
     tiles, ms = g.autotune(launches=1)
     print("graph tiles", tiles, "ms per launch", ms, flush=True)
     assert len(tiles) == 6 and all(t in Plan.TILE_CODES for t in tiles) and ms > 0
+    for t, b in zip(tiles, B):
+        b.p.autotune(force=t - t % 8 + 1)     # the same line plan, divisor 1
     for a, b in zip(A, B):
         sa, sb = a.state(), b.state()
         assert sa["stage"] == sb["stage"] == 0
