@@ -175,6 +175,19 @@ lmvd_status lmvd_sizes(lmvd_plan plan, size_t* sfield_elems, size_t* sfield_star
 lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* args, void* workspace,
                          void* stream);
 
+/* ---- allocation-free substep ----
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): lmvd_substep with the workspace taken from a fixed array of device
+ * memory that the library holds on every GPU it runs on (64 MiB, lmvd_noalloc_capacity), instead of a
+ * caller buffer.  Same arguments, results and asynchrony as lmvd_substep; it calls no hipMalloc, hipFree
+ * or other allocating routine.  Plans whose workspace (lmvd_sizes) exceeds the array are rejected with
+ * LMVD_EUNSUPPORTED before anything is launched (64 MiB holds for example 32 x 97 x 32 or
+ * 48 x 33 x 48).  Every call on a GPU uses that GPU's one array, whose contents the previous call left
+ * there (a substep writes every workspace byte it reads, so nothing is carried between calls): calls that
+ * overlap on one GPU (two streams, or two host threads) race and must not be made. */
+lmvd_status lmvd_substep_noalloc(lmvd_plan plan, const lmvd_substep_args* args, void* stream);
+lmvd_status lmvd_noalloc_capacity(size_t* bytes);
+
 /* ---- many independent simulations in one HIP graph ----
  * For small problems, where one substep is a few dozen short launches, the
  * substeps of many independent instances (each its own plan, workspace and

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -3610,6 +3611,32 @@ static void choose_shapes(lmvd_plan_s* p) {
 
 static lmvd_status factor_and_check(lmvd_plan_s* p, double growth_max);
 
+// Workspace of lmvd_substep_noalloc: one array in device memory per GPU, held until the process ends.
+// In host code `scratch` is only a host-side stand-in for the symbol; its device address on each GPU
+// comes from hipGetSymbolAddress (resolve_scratch, at plan creation with the plan's device current) and
+// only that address is handed to kernels.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+static void* scratch_ptr[kMaxDevices] = {};
+static std::mutex scratch_mu;
+
+static lmvd_status resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return LMVD_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_ptr[device]) return LMVD_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LMVD_EHIP;
+  scratch_ptr[device] = ptr;
+  return LMVD_OK;
+}
+
+static void* device_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return scratch_ptr[device];
+}
+
 static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::string& msg) {
   if (!cfg || !out) return LMVD_EINVAL;
   lmvd_plan_s* p = new (std::nothrow) lmvd_plan_s();
@@ -3636,6 +3663,12 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
     return LMVD_EUNSUPPORTED;
   }
   if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
+  st = resolve_scratch(p->device);
+  if (st != LMVD_OK) {
+    msg = "device address of the allocation-free workspace";
+    delete p;
+    return st;
+  }
   p->pb = (cfg->plane_batch > 0) ? std::min(cfg->plane_batch, H.n2) : H.n2;
   choose_shapes(p);
   DevPlan& D = p->D;
@@ -4649,6 +4682,20 @@ lmvd_status lmvd_substep(lmvd_plan plan, const lmvd_substep_args* a, void* works
   }
   if (hipGetLastError() != hipSuccess) return LMVD_EHIP;
   if (plan->H.cfg.check_finite) return lmvd::scan_outputs(plan, a, s);
+  return LMVD_OK;
+}
+
+lmvd_status lmvd_substep_noalloc(lmvd_plan plan, const lmvd_substep_args* a, void* stream) {
+  if (!plan || !a) return LMVD_EINVAL;
+  if (plan->ws.bytes > lmvd::kNoAllocBytes) return LMVD_EUNSUPPORTED;
+  void* ws = lmvd::device_scratch(plan->device);
+  if (!ws) return LMVD_EHIP;
+  return lmvd_substep(plan, a, ws, stream);
+}
+
+lmvd_status lmvd_noalloc_capacity(size_t* bytes) {
+  if (!bytes) return LMVD_EINVAL;
+  *bytes = lmvd::kNoAllocBytes;
   return LMVD_OK;
 }
 

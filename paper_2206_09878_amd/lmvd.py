@@ -73,7 +73,7 @@ EXPORTS = ["lmvd_status_string", "lmvd_plan_create", "lmvd_plan_destroy", "lmvd_
            "lmvd_graph_launch", "lmvd_graph_destroy", "lmvd_graph_grouped", "lmvd_autotune",
            "lmvd_graph_autotune", "lmvd_rhs", "lmvd_to_physical_adjoint", "lmvd_evaluate_adjoint",
            "lmvd_project_adjoint", "lmvd_md_adjoint", "lmvd_mc_adjoint", "lmvd_to_spectral_adjoint",
-           "lmvd_factor_check", "lmvd_factor_check_host",
+           "lmvd_factor_check", "lmvd_factor_check_host", "lmvd_substep_noalloc", "lmvd_noalloc_capacity",
            "lmvd_adjoint_sizes", "lmvd_substep_adjoint", "lmvd_basis_values"]
 
 
@@ -92,6 +92,8 @@ def library():
         lib.lmvd_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                    ctypes.POINTER(ctypes.c_size_t)]
         lib.lmvd_substep.argtypes = [vp, ctypes.POINTER(SubstepArgs), vp, vp]
+        lib.lmvd_substep_noalloc.argtypes = [vp, ctypes.POINTER(SubstepArgs), vp]
+        lib.lmvd_noalloc_capacity.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
         lib.lmvd_adjoint_sizes.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
         lib.lmvd_basis_values.argtypes = [ctypes.POINTER(Config), i32, vp, i32, vp]
         lib.lmvd_substep_adjoint.argtypes = [vp, ctypes.POINTER(SubstepArgs), ctypes.POINTER(SubstepGrads), vp, vp]
