@@ -36,6 +36,9 @@ constexpr int kMaxIn = 8;
 constexpr int kMaxOut = 10;
 constexpr int kNumAux = 4;   // physical-grid fields fixed during a substep
 constexpr int kPre = 3;      // rows loaded ahead by the sequential column sweeps
+// k_mc, at two waves per SIMD, hides the HBM latency only with its loads issued well ahead: row values
+// kPreMc rows ahead, factor rows kFacPre rows ahead, the input values of the emitted rows kValPre ahead
+constexpr int kPreMc = 8, kFacPre = 3, kValPre = 4;
 constexpr int kThreads = 256;
 constexpr int kZMaxE = 12;    // elements per thread in the z-FFT kernels
 constexpr int kXSlots = 3;    // complex slots per thread per line set in k_xpass
@@ -2280,19 +2283,19 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
   const double ik = mean ? 0.0 : 1.0 / sqrt(ksq);
   const double* fac = P.fac + (active ? pr : 0);
   const McLds lay{n2, N, LB};
-  // 1. ascending sweep of the interpolation projection (rows loaded kPre ahead)
+  // 1. ascending sweep of the interpolation projection (rows loaded kPreMc ahead)
   if (active) {
     double2 ring[LB];
 #pragma unroll
     for (int m = 0; m < LB; ++m) ring[m] = zero2();
-    double2 pf[kPre];
+    double2 pf[kPreMc];
 #pragma unroll
-    for (int d = 0; d < kPre; ++d) pf[d] = (d < n2) ? vals[size_t(d) * ncol + c] : zero2();
+    for (int d = 0; d < kPreMc; ++d) pf[d] = (d < n2) ? vals[size_t(d) * ncol + c] : zero2();
     for (int i = 0; i < n2; ++i) {
       double2 b = pf[0];
 #pragma unroll
-      for (int d = 0; d < kPre - 1; ++d) pf[d] = pf[d + 1];
-      if (i + kPre < n2) pf[kPre - 1] = vals[size_t(i + kPre) * ncol + c];
+      for (int d = 0; d < kPreMc - 1; ++d) pf[d] = pf[d + 1];
+      if (i + kPreMc < n2) pf[kPreMc - 1] = vals[size_t(i + kPreMc) * ncol + c];
 #pragma unroll
       for (int m = 0; m < LB; ++m) b = fma2(-P.lu_l[i * kMaxBand + m], ring[m], b);
       yp[size_t(i) * ncol + c] = b;
@@ -2347,25 +2350,29 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
       for (int m = 0; m < UA; ++m) yr[m] = zero2();
       double2 cm = zero2();  // mean column: c_{j+1}
       yt[size_t(n2) * ncol + c] = zero2();  // Robin row n2: r = 0, nothing above it
-      // multipliers of the next row of the bottom-up sweep (rows n2-1, n2-2, ..., 0 in turn)
+      // multipliers of the rows of the bottom-up sweep (rows n2-1, n2-2, ..., 0 in turn): fm[d] holds
+      // those of row inext - d, so each row's are loaded kFacPre - 1 rows before they are used
       int inext = n2 - 1;
-      double fm[UA];
-      auto load_mult = [&](int row) {
-        const int nm = nm_(row), off = of_(row);
+      double fm[kFacPre][UA];
+      auto load_mult = [&](double (&dst)[UA], int row) {
+        const int nm = row >= 0 ? nm_(row) : 0, off = row >= 0 ? of_(row) : 0;
 #pragma unroll
-        for (int m = 0; m < UA; ++m) fm[m] = (m < nm) ? fac[(size_t(off) + m) * npairs] : 0.0;
+        for (int m = 0; m < UA; ++m) dst[m] = (m < nm) ? fac[(size_t(off) + m) * npairs] : 0.0;
       };
 #pragma unroll
-      for (int m = 0; m < UA; ++m) fm[m] = 0.0;
-      if (!mean) load_mult(inext);
-      double2 pf[kPre];  // rows j-1 .. j-kPre of the L-sweep result, loaded ahead
+      for (int d = 0; d < kFacPre; ++d) {
 #pragma unroll
-      for (int d = 0; d < kPre; ++d) pf[d] = (n2 - 1 - d >= 0) ? yp[size_t(n2 - 1 - d) * ncol + c] : zero2();
+        for (int m = 0; m < UA; ++m) fm[d][m] = 0.0;
+        if (!mean) load_mult(fm[d], inext - d);
+      }
+      double2 pf[kPreMc];  // rows j-1 .. j-kPreMc of the L-sweep result, loaded ahead
+#pragma unroll
+      for (int d = 0; d < kPreMc; ++d) pf[d] = (n2 - 1 - d >= 0) ? yp[size_t(n2 - 1 - d) * ncol + c] : zero2();
       for (int j = n2 - 1; j >= 0; --j) {
         double2 y = pf[0];
 #pragma unroll
-        for (int d = 0; d < kPre - 1; ++d) pf[d] = pf[d + 1];
-        if (j - kPre >= 0) pf[kPre - 1] = yp[size_t(j - kPre) * ncol + c];
+        for (int d = 0; d < kPreMc - 1; ++d) pf[d] = pf[d + 1];
+        if (j - kPreMc >= 0) pf[kPreMc - 1] = yp[size_t(j - kPreMc) * ncol + c];
 #pragma unroll
         for (int q = 0; q < LB; ++q) y = fma2(-U_(j, q), win[q], y);
         const double2 x = cscale(y, Ui_(j));
@@ -2385,9 +2392,13 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
 #pragma unroll
           for (int q = 0; q < kMaxW; ++q) r = fma2(-G_(i, q), win[q], r);
 #pragma unroll
-          for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
+          for (int m = 0; m < UA; ++m) r = fma2(-fm[0][m], yr[m], r);
           --inext;
-          load_mult(inext);
+#pragma unroll
+          for (int d = 0; d < kFacPre - 1; ++d)
+#pragma unroll
+            for (int m = 0; m < UA; ++m) fm[d][m] = fm[d + 1][m];
+          load_mult(fm[kFacPre - 1], inext - (kFacPre - 1));
           yt[size_t(i) * ncol + c] = r;
 #pragma unroll
           for (int m = UA - 1; m > 0; --m) yr[m] = yr[m - 1];
@@ -2397,7 +2408,7 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
       if (!mean) {  // Robin row 0 (inext == 0): r = 0
         double2 r = zero2();
 #pragma unroll
-        for (int m = 0; m < UA; ++m) r = fma2(-fm[m], yr[m], r);
+        for (int m = 0; m < UA; ++m) r = fma2(-fm[0][m], yr[m], r);
         yt[c] = r;
       }
     }
@@ -2439,29 +2450,42 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
       double2 cw[kMaxW];  // c_i, c_{i-1}, ...
 #pragma unroll
       for (int q = 0; q < kMaxW; ++q) cw[q] = zero2();
-      // entries left of the diagonal (fs[0 .. LA-1]) and 1/pivot (fs[LA]) of a row
-      double fs[LA + 1];
-      auto load_sub = [&](int row) {
-        const int nm = nm_(row), ns = ns_(row), off = of_(row);
+      // entries left of the diagonal (fs[.][0 .. LA-1]) and 1/pivot (fs[.][LA]) of rows i .. i+kFacPre-1
+      double fs[kFacPre][LA + 1];
+      auto load_sub = [&](double (&dst)[LA + 1], int row) {
+        const bool ok = row < N;
+        const int nm = ok ? nm_(row) : 0, ns = ok ? ns_(row) : 0, off = ok ? of_(row) : 0;
 #pragma unroll
-        for (int q = 0; q < LA; ++q) fs[q] = (q < ns) ? fac[(size_t(off) + nm + q) * npairs] : 0.0;
-        fs[LA] = fac[(size_t(off) + nm + ns) * npairs];
+        for (int q = 0; q < LA; ++q) dst[q] = (ok && q < ns) ? fac[(size_t(off) + nm + q) * npairs] : 0.0;
+        dst[LA] = ok ? fac[(size_t(off) + nm + ns) * npairs] : 0.0;
       };
 #pragma unroll
-      for (int q = 0; q <= LA; ++q) fs[q] = 0.0;
-      double2 pf[kPre];  // rows i .. i+kPre-1 of the A(k) forward-sweep result, loaded ahead
+      for (int d = 0; d < kFacPre; ++d) {
 #pragma unroll
-      for (int d = 0; d < kPre; ++d) pf[d] = (d < N) ? yt[size_t(d) * ncol + c] : zero2();
-      if (!mean) load_sub(0);
+        for (int q = 0; q <= LA; ++q) fs[d][q] = 0.0;
+        if (!mean) load_sub(fs[d], d);
+      }
+      double2 pf[kPreMc];  // rows i .. i+kPreMc-1 of the A(k) forward-sweep result, loaded ahead
+#pragma unroll
+      for (int d = 0; d < kPreMc; ++d) pf[d] = (d < N) ? yt[size_t(d) * ncol + c] : zero2();
+      // input values of the next rows to emit (tau rows are emitted in ascending order, each once)
+      int enext = 0;
+      double2 vq[kValPre];
+#pragma unroll
+      for (int d = 0; d < kValPre; ++d) vq[d] = (!mean && d < n2) ? vals[size_t(d) * ncol + c] : zero2();
       for (int i = 0; i < N; ++i) {
         double2 x = pf[0];
 #pragma unroll
-        for (int d = 0; d < kPre - 1; ++d) pf[d] = pf[d + 1];
-        if (i + kPre < N) pf[kPre - 1] = yt[size_t(i + kPre) * ncol + c];
+        for (int d = 0; d < kPreMc - 1; ++d) pf[d] = pf[d + 1];
+        if (i + kPreMc < N) pf[kPreMc - 1] = yt[size_t(i + kPreMc) * ncol + c];
         double fc[LA + 1];
 #pragma unroll
-        for (int q = 0; q <= LA; ++q) fc[q] = fs[q];
-        if (i + 1 < N && !mean) load_sub(i + 1);
+        for (int q = 0; q <= LA; ++q) fc[q] = fs[0][q];
+#pragma unroll
+        for (int d = 0; d < kFacPre - 1; ++d)
+#pragma unroll
+          for (int q = 0; q <= LA; ++q) fs[d][q] = fs[d + 1][q];
+        if (!mean) load_sub(fs[kFacPre - 1], i + kFacPre);
         if (!mean) {
 #pragma unroll
           for (int q = 0; q < LA; ++q) x = fma2(-fc[q], cw[q], x);
@@ -2491,9 +2515,14 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
           const size_t o = size_t(row) * ncol + c;
           double2 m1 = zero2(), m3 = zero2();
           if (!mean) {
-            const double2 mp = cscale(times_i(cadd(vals[o], f1)), ik);
+            // row == enext: its input value is vq[0]
+            const double2 mp = cscale(times_i(cadd(vq[0], f1)), ik);
             m1 = cscale(mp, k1 * ik);
             m3 = cscale(mp, k3 * ik);
+#pragma unroll
+            for (int d = 0; d < kValPre - 1; ++d) vq[d] = vq[d + 1];
+            ++enext;
+            vq[kValPre - 1] = (enext + kValPre - 1 < n2) ? vals[size_t(enext + kValPre - 1) * ncol + c] : zero2();
           }
           if (d1) {
             m1 = cadd(m1, d1[o]);
