@@ -659,7 +659,7 @@ struct XPlan;
     static constexpr int BG = kThreads / T_;                     /* lines per block */               \
     static constexpr int STRIDE = ((N_ + N_ / PAD_) + 1) / 2 * 2; /* doubles per line, even */        \
   };
-LMVD_XPLAN(768, 64, 12, 4, 4, 4, 64)
+LMVD_XPLAN(768, 64, 12, 4, 4, 4, 48)
 LMVD_XPLAN(192, 16, 12, 4, 4, 1, 12)
 LMVD_XPLAN(144, 12, 12, 12, 1, 1, 12)
 LMVD_XPLAN(96, 8, 12, 4, 2, 1, 12)
@@ -700,6 +700,7 @@ __device__ __forceinline__ void zinv_r_body(const DevPlan& P, const unsigned bx,
       const int ni = pos < h3 ? pos : pos - pad;
       val = src[size_t(ni) * nl];
       if (in.b) val = cadd(val, in.b[size_t(j) * ncol + size_t(ni) * nl + l]);
+      if (in.ma == MU_IK3) val = apply_mult(MU_IK3, 0.0, P.k3[ni], val);
     }
     v[r] = val;
   }
@@ -812,6 +813,14 @@ __device__ __forceinline__ void zinv_w_body(const DevPlan& P, const unsigned bx,
       const int pos = tl + T * r;
       const bool ok = lok && (pos < h3 || pos >= h3 + pad);
       v[r] = ok ? (hasb ? cadd(xa[r], xb[r]) : xa[r]) : zero2();
+    }
+    if (in.ma == MU_IK3) {  // i k3 of each point's z mode (zero-padded points stay zero)
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const int pos = tl + T * r;
+        const bool ok = lok && (pos < h3 || pos >= h3 + pad);
+        if (ok) v[r] = apply_mult(MU_IK3, 0.0, P.k3[pos < h3 ? pos : pos - pad], v[r]);
+      }
     }
   };
   if (in.b) load(std::true_type{});
@@ -2237,6 +2246,9 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
 //   3. ascending back substitution for c (the B* coefficients of m2); every
 //      tau row whose F0/F1 band is complete emits the values
 //        m2 = F0 c,  m_par = (i/k)(rho_t + F1 c),  m1 = (k1/k) m_par,  m3 = (k3/k) m_par
+//      or, without V3 (an iterate whose m^c is used only by L z_t), m2 and the potential
+//      psi = (rho_t + F1 c) / k^2 in V1, of which m1 = i k1 psi and m3 = i k3 psi (the inverse z
+//      transform applies the factors), so one value field less is written and read
 //      (F1 = E0 D*, so F1 c = E0 D* c and E0 rho_t is the input value itself).
 // Plane mean (k = 0): D* c = -<rho_t>, c_top = 0, m1 = m3 = 0.
 // With d1 (final iterate) the m^d values are added and the coefficients
@@ -2516,9 +2528,14 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
           double2 m1 = zero2(), m3 = zero2();
           if (!mean) {
             // row == enext: its input value is vq[0]
-            const double2 mp = cscale(times_i(cadd(vq[0], f1)), ik);
-            m1 = cscale(mp, k1 * ik);
-            m3 = cscale(mp, k3 * ik);
+            const double2 sum = cadd(vq[0], f1);  // rho_t + F1 c
+            if (V3) {
+              const double2 mp = cscale(times_i(sum), ik);
+              m1 = cscale(mp, k1 * ik);
+              m3 = cscale(mp, k3 * ik);
+            } else {
+              m1 = cscale(sum, ik * ik);  // psi: m1 = i k1 psi, m3 = i k3 psi
+            }
 #pragma unroll
             for (int d = 0; d < kValPre - 1; ++d) vq[d] = vq[d + 1];
             ++enext;
@@ -2531,7 +2548,7 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
           }
           V1[o] = m1;
           V2[o] = m2;
-          V3[o] = m3;
+          if (V3) V3[o] = m3;
         }
       }
     }
@@ -4116,9 +4133,10 @@ static lmvd_status plane_phase(const Ctx& c, const std::vector<EvalIn>& ins, con
     const int nb = std::min(p->pb, H.n2 - j0);
     const double zplane = double(M3) * nl * 16.0, splane = double(ncols(p)) * 16.0;
     const double nin = double(ins.size()), nout = double(outs.size());
-    bool inputs_plain = true;  // the register z kernel takes values with multiplier 1 or i k1 only
+    bool inputs_plain = true;  // the register z kernels take values with multiplier 1, i k1 or i k3 only
     for (const EvalIn& e : ins)
-      if (e.kind != EV_IDENT || (e.ma != MU_ONE && e.ma != MU_IK1) || (e.b && e.mb != MU_ONE)) inputs_plain = false;
+      if (e.kind != EV_IDENT || (e.ma != MU_ONE && e.ma != MU_IK1 && e.ma != MU_IK3) || (e.b && e.mb != MU_ONE))
+        inputs_plain = false;
     const bool zr = p->use_reg && zreg_size(M3) && inputs_plain, xr = p->use_reg && xreg_size(H.cfg.m1, nl);
     if (!ins.empty() && zinv) {
       double terms = 0;
@@ -4436,10 +4454,11 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   auto mc_step = [&](bool final_it) {
     const int nth = 2 * H.nl * ((H.nn + 1) / 2);
     const dim3 g((nth + kThreads - 1) / kThreads);
-    // values in, L-sweep intermediate out and back, 3 value fields out, A(k) sweep intermediate out and back,
-    // the factors once per pair; the final iterate also reads m^d values and writes rho_t, m_par, c2
+    // values in, L-sweep intermediate out and back, 2 value fields out (psi, m2; the final iterate 3), A(k)
+    // sweep intermediate out and back, the factors once per pair; the final iterate also reads m^d values and
+    // writes rho_t, m_par, c2
     ProfScope ps(p, KC_MC, s,
-                 16.0 * nB * (final_it ? 11.0 : 6.0) + 16.0 * ncol * (H.n2 + 1) * (final_it ? 3.0 : 2.0) +
+                 16.0 * nB * (final_it ? 11.0 : 5.0) + 16.0 * ncol * (H.n2 + 1) * (final_it ? 3.0 : 2.0) +
                      8.0 * H.fac_slots * (nth / 2));
     const bool narrow = H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
     double2* yp = c.at<double2>(W.off_yp);
@@ -4447,7 +4466,8 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
 #define LMVD_MC(LA_, LB_, ST_)                                                                               \
   col<JobMc<LA_, LA_, LB_, ST_>>(c, g, ST_ ? lay.bytes() : 0,                                                \
                                  {vals[0], yp, yt, final_it ? vmd1 : nullptr, final_it ? vc2d : nullptr,     \
-                                  final_it ? vmd3 : nullptr, vm1, vm2, vm3, final_it ? rhot : nullptr,       \
+                                  final_it ? vmd3 : nullptr, vm1, vm2, final_it ? vm3 : nullptr,             \
+                                  final_it ? rhot : nullptr,                                                 \
                                   final_it ? c2c : nullptr, final_it ? mpar : nullptr})
     // the staged tables must leave room for two blocks per compute unit
     const McLds lay{H.n2, H.n2 + 1, narrow ? 6 : kMaxBand};
@@ -4549,10 +4569,10 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
     const bool last = (it == kf - 1);
     st = plane_phase<PH_RHOT>(c, {ev(vzt, EV_IDENT)}, {vals[0]}, nullptr, nullptr, !zt_filtered);
     if (st != LMVD_OK) return st;
-    mc_step(false);
+    mc_step(false);  // psi in vm1, m2 in vm2
     const bool filt = elide && !last;
-    st = plane_phase<PH_L>(c, {ev(vm1, EV_IDENT), ev(vm2, EV_IDENT), ev(vm3, EV_IDENT)}, {vals[0]}, nullptr,
-                           nullptr, true, !filt);
+    st = plane_phase<PH_L>(c, {ev(vm1, EV_IDENT, MU_IK1), ev(vm2, EV_IDENT), ev(vm1, EV_IDENT, MU_IK3)}, {vals[0]},
+                           nullptr, nullptr, true, !filt);
     if (st != LMVD_OK) return st;
     zt_filtered = filt;
     if (filt) {
