@@ -780,7 +780,9 @@ __device__ __forceinline__ void zinv_w_body(const DevPlan& P, const unsigned bx,
   double2* twl = reinterpret_cast<double2*>(lds_d + LG * ZP::STRIDE);
   const int tid = threadIdx.x;
   const int ll = tid % LG, tl = tid / LG;
-  const int f = bz, jj = by, j = j0 + jj, l = bx * LG + ll;
+  // grid (fields, l groups, planes): the fields of one l group and plane are dispatched together, so
+  // fields that read the same input (i k1 psi and i k3 psi) find it in the memory-side cache
+  const int f = bx, jj = bz, j = j0 + jj, l = by * LG + ll;
   const int nn = EXACT ? NNX : P.nn, nl = P.nl;
   const int h3 = EXACT ? H3X : (nn + 1) / 2, pad = EXACT ? PADX : N - nn;
   rf::fill_stage_tw<N, ZP::R0, ZP::R1, ZP::R2, ZP::R3>(twl, P.fz.tw, tid, kZWThreads);
@@ -4023,7 +4025,7 @@ static void launch_zinv_t(const Ctx& c, const EvalArgs& A, double2* zbuf, int j0
   const bool exact = p->H.nn == 2 * N / 3 - 1;
   if constexpr (N == 768) {
     using ZP = ZPlanW<N>;
-    const dim3 g((p->H.nl + ZP::LG - 1) / ZP::LG, nb, nin);
+    const dim3 g(nin, (p->H.nl + ZP::LG - 1) / ZP::LG, nb);
     const size_t lds = size_t(ZP::LG) * ZP::STRIDE * sizeof(double) +
                        size_t(rf::StageTw<ZP::R0, ZP::R1, ZP::R2, ZP::R3>::SIZE) * sizeof(double2);
     if (exact) col<JobZinvW<N, true>>(c, g, lds, {A, zbuf, j0, p->pb});
