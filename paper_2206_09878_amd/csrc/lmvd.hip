@@ -854,7 +854,8 @@ __device__ __forceinline__ void zfwd_w_body(const DevPlan& P, const unsigned bx,
   double2* twl = reinterpret_cast<double2*>(lds_d + LG * ZP::STRIDE);
   const int tid = threadIdx.x;
   const int ll = tid % LG, tl = tid / LG;
-  const int g = bz, jj = by, l = bx * LG + ll;
+  // grid (fields, l groups, planes), as the inverse kernel
+  const int g = bx, jj = bz, l = by * LG + ll;
   const int nn = P.nn, nl = P.nl, h3 = (nn + 1) / 2, pad = N - nn;
   rf::fill_stage_tw<N, ZP::R0, ZP::R1, ZP::R2, ZP::R3>(twl, P.fz.tw, tid, kZWThreads);
   const bool lok = l < nl;
@@ -4047,7 +4048,7 @@ static void launch_zfwd_t(const Ctx& c, const double2* obuf, const OutPtrs& V, i
   lmvd_plan_s* p = c.p;
   if constexpr (N == 768) {
     using ZP = ZPlanW<N>;
-    const dim3 g((p->H.nl + ZP::LG - 1) / ZP::LG, nb, nout);
+    const dim3 g(nout, (p->H.nl + ZP::LG - 1) / ZP::LG, nb);
     const size_t lds = size_t(ZP::LG) * ZP::STRIDE * sizeof(double) +
                        size_t(rf::StageTw<ZP::R0, ZP::R1, ZP::R2, ZP::R3>::SIZE) * sizeof(double2);
     col<JobZfwdW<N>>(c, g, lds, {obuf, V, j0, p->pb});
