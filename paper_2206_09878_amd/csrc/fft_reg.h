@@ -130,10 +130,18 @@ __device__ __forceinline__ void stage(double2* v, int tl, const double2* __restr
   }
 }
 
-// LDS addressing of position p of the line owned by this thread group
+// LDS addressing of position p of the line owned by this thread group: PADDIV > 0 inserts one pad slot
+// every PADDIV positions; PADDIV = -(100 K + M) permutes positions within aligned blocks instead,
+// p ^ ((p >> K) & M), which spreads strided accesses over the banks at no extra LDS and with a shift,
+// a mask and an exclusive or per address (no division)
 template <int PADDIV>
 __device__ __forceinline__ int padded(int p) {
-  return PADDIV > 0 ? int(unsigned(p) + unsigned(p) / unsigned(PADDIV)) : p;
+  if constexpr (PADDIV < 0) {
+    constexpr unsigned K = unsigned(-PADDIV) / 100u, M = unsigned(-PADDIV) % 100u;
+    return int(unsigned(p) ^ ((unsigned(p) >> K) & M));
+  } else {
+    return PADDIV > 0 ? int(unsigned(p) + unsigned(p) / unsigned(PADDIV)) : p;
+  }
 }
 
 // Move stage outputs (radix Ra, span NSa) to the next stage's inputs (radix Rb)

@@ -591,7 +591,7 @@ __device__ __forceinline__ void guess_body(const DevPlan& P, size_t c, const Gue
 // ---------------------------------------------------------------------------
 // Register-FFT plane kernels for the sizes of the workloads.  Line size N,
 // T threads per line, radices R0..R3 (every radix divides N/T), PAD: one
-// LDS pad slot every PAD positions.
+// LDS pad slot every PAD positions (PAD < 0: the permutation of rf::padded).
 
 // Several plans per size (V = 0, 1, 2: other thread counts, radix splits or stage orders) are compiled
 // for the sizes below 768; the tile autotuner picks one by timing.  A size without alternatives uses its
@@ -657,9 +657,10 @@ struct XPlan;
     static constexpr int E = N_ / T_;                                                                \
     static constexpr int RL = rf::Last<R0_, R1_, R2_, R3_>::value;                                   \
     static constexpr int BG = kThreads / T_;                     /* lines per block */               \
-    static constexpr int STRIDE = ((N_ + N_ / PAD_) + 1) / 2 * 2; /* doubles per line, even */        \
+    static constexpr int STRIDE = PAD_ < 0 ? N_ : ((N_ + N_ / PAD_) + 1) / 2 * 2; /* doubles per line */ \
+    static_assert(PAD_ > 0 || N_ % ((-PAD_) % 100 + 1) == 0, "the permutation must stay within the line");   \
   };
-LMVD_XPLAN(768, 64, 12, 4, 4, 4, 48)
+LMVD_XPLAN(768, 64, 12, 4, 4, 4, -231)  // LDS positions p ^ ((p >> 2) & 31)
 LMVD_XPLAN(192, 16, 12, 4, 4, 1, 12)
 LMVD_XPLAN(144, 12, 12, 12, 1, 1, 12)
 LMVD_XPLAN(96, 8, 12, 4, 2, 1, 12)
