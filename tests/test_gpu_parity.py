@@ -362,6 +362,34 @@ def test_trajectory_three_substeps_small(torch):
     assert all(v < TOL for v in errs.values()), errs
 
 
+def test_trajectory_drift_curve_small(torch):
+    """Config 0 drift curve: 20 RK steps (40 substeps), each side free-running on its own outputs from
+    the same seeded state and synthetic history.  After every step the relative max-norm difference of
+    each state field is printed; the first step is within 1e-11, and the whole curve within 1e-10 (a
+    bound on the growth of the two implementations' rounding along the trajectory)."""
+    from oracle.lmvd import Integrator
+    from paper_2206_09878_amd.lmvd import Stepper
+    w = workload("small")
+    p = gplan(w)
+    op = OPlan(oracle_config(w))
+    inp = make_inputs(w, seed=0, stage=0)
+    st = {k: inp[k] for k in ("phi2", "omega2", "z", "m1bar", "m3bar")}
+    it = Integrator(op, st, hist=inp["hist"])
+    s = Stepper(p, inp, stage=0)
+    curve = []
+    for step in range(20):
+        ref = it.step()
+        s.substep()
+        s.substep()
+        torch.cuda.synchronize()
+        got = dict(phi2=host(s.phi2), omega2=host(s.omega2), z=host(s.z), m1bar=host(s.m1bar), m3bar=host(s.m3bar))
+        errs = {k: rel(got[k], ref[k]) for k in got}
+        curve.append(max(errs.values()))
+        print(f"step {step + 1:2d}: " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
+    assert curve[0] < TOL, curve
+    assert max(curve) < 1e-10, curve
+
+
 @pytest.mark.parametrize("plane_batch", [0, 64])
 def test_filtered_and_spectral_iterates_against_oracle(torch, plane_batch):
     """64x65x64, stage ': all planes in one batch (the fixed-point iterates before the last are
