@@ -3259,40 +3259,35 @@ __global__ void k_evaluate(DevPlan P, int kind, const double2* __restrict__ src,
 // adjoints (transposes in the real inner products <a, b> = sum Re(conj(a) b) of S-fields and
 // sum f g of physical fields) of evaluation, projection and the inverse transform
 
-// E_d^T per column: values at tau (n2 rows) -> coefficients (n2 rows, n2 + 1 for F0); the rows a value
-// row reaches start at a nondecreasing position, so finished rows leave a register window in order
+// E_d^T: values at tau (n2 rows) -> coefficients (n2 rows, n2 + 1 for F0), one thread per (coefficient row,
+// column), grid (ceil(ncol / 256), rows).  Coefficient row i gathers the value rows j whose band
+// [lo_j, lo_j + kMaxW) holds it; lo_j is nondecreasing, so they are one range [ja, jb], found by binary
+// search on the (uniform) row table, and summed in ascending j.
 __global__ void __launch_bounds__(kThreads) k_evaluate_t(DevPlan P, int kind, const double2* __restrict__ src,
                                                         double2* __restrict__ dst) {
   const size_t ncol = size_t(P.nn) * P.nl;
   const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= ncol) return;
+  const int i = int(blockIdx.y);
   const int n2 = P.n2, rows = (kind == EV_F0) ? n2 + 1 : n2;
-  double2 acc[kMaxW];
-#pragma unroll
-  for (int q = 0; q < kMaxW; ++q) acc[q] = zero2();
-  int base = 0;
-  for (int j = 0; j < n2; ++j) {
-    const int lo = P.ev_lo[kind * n2 + j];
-    while (base < lo) {
-      if (base < rows) dst[size_t(base) * ncol + c] = acc[0];
-#pragma unroll
-      for (int q = 0; q < kMaxW - 1; ++q) acc[q] = acc[q + 1];
-      acc[kMaxW - 1] = zero2();
-      ++base;
-    }
-    const auto w = P.ev_w + (size_t(kind) * n2 + j) * kMaxW;
-    const double2 v = src[size_t(j) * ncol + c];
-#pragma unroll
-    for (int q = 0; q < kMaxW; ++q)
-      if (lo + q < rows) acc[q] = fma2(w[q], v, acc[q]);
+  if (c >= ncol || i >= rows) return;
+  const cptr<int> lo = P.ev_lo + size_t(kind) * n2;
+  // ja: first j with lo_j + kMaxW - 1 >= i;  jb: last j with lo_j <= i
+  int a0 = 0, a1 = n2;
+  while (a0 < a1) {
+    const int m = (a0 + a1) >> 1;
+    if (lo[m] + kMaxW - 1 < i) a0 = m + 1; else a1 = m;
   }
-  while (base < rows) {
-    dst[size_t(base) * ncol + c] = acc[0];
-#pragma unroll
-    for (int q = 0; q < kMaxW - 1; ++q) acc[q] = acc[q + 1];
-    acc[kMaxW - 1] = zero2();
-    ++base;
+  int b0 = a0, b1 = n2;
+  while (b0 < b1) {
+    const int m = (b0 + b1) >> 1;
+    if (lo[m] <= i) b0 = m + 1; else b1 = m;
   }
+  double2 acc = zero2();
+  for (int j = a0; j < b0; ++j) {
+    const int q = i - lo[j];
+    acc = fma2(P.ev_w[(size_t(kind) * n2 + j) * kMaxW + q], src[size_t(j) * ncol + c], acc);
+  }
+  dst[size_t(i) * ncol + c] = acc;
 }
 
 // (A^{-1} R)^T = R A^{-T} per column, A = L U of the projection `kind`: U^T z = y ascending, L^T x = z
@@ -5138,7 +5133,8 @@ lmvd_status lmvd_evaluate_adjoint(lmvd_plan plan, int32_t deriv, int32_t star, c
   if (!plan || !values || !coeffs || deriv < 0 || deriv > 2 || (star && deriv != 0) || values == coeffs)
     return LMVD_EINVAL;
   const size_t ncol = size_t(plan->H.nn) * plan->H.nl;
-  hipLaunchKernelGGL(k_evaluate_t, dim3((ncol + kThreads - 1) / kThreads), dim3(kThreads), 0,
+  const int rows = star ? plan->H.n2 + 1 : plan->H.n2;
+  hipLaunchKernelGGL(k_evaluate_t, dim3(unsigned((ncol + kThreads - 1) / kThreads), unsigned(rows)), dim3(kThreads), 0,
                      static_cast<hipStream_t>(stream), plan->D, star ? int(EV_F0) : deriv,
                      static_cast<const double2*>(values), static_cast<double2*>(coeffs));
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;

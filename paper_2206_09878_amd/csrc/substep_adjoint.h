@@ -290,7 +290,8 @@ static lmvd_status fwd_t(const AdjCtx& a, double2* vals, double* phys) {
   return plane_phase<PH_TOPHYS>(a.c, {ev(vals, EV_IDENT)}, {}, phys, nullptr);
 }
 static void eval_t(const AdjCtx& a, int kind, const double2* vals, double2* coeffs) {
-  hipLaunchKernelGGL(k_evaluate_t, a.gC, dim3(kThreads), 0, a.c.s, a.c.p->D, kind, vals, coeffs);
+  const dim3 g(a.gC.x, unsigned(kind == EV_F0 ? a.c.p->H.n2 + 1 : a.c.p->H.n2));
+  hipLaunchKernelGGL(k_evaluate_t, g, dim3(kThreads), 0, a.c.s, a.c.p->D, kind, vals, coeffs);
 }
 static void proj_t(const AdjCtx& a, int kind, const double2* coeffs, double2* vals) {
   hipLaunchKernelGGL(k_project_t, a.gC, dim3(kThreads), 0, a.c.s, a.c.p->D, kind, coeffs, vals);
