@@ -3336,33 +3336,74 @@ constexpr int kFacMax = 9;  // band of the factor rows (a_lower, a_upper <= 8)
 __device__ __forceinline__ void solve_At(const DevPlan& P, const double* fac, int npairs, double2* scr, size_t c,
                                          size_t ncol) {
   const int N = P.n2 + 1;
+  // The operands of a step (the value row and the factor entries it needs) are loaded kFacPre steps
+  // ahead into register rings: at two waves per SIMD or fewer the HBM latency is otherwise exposed at
+  // every step of the chain.
   // L^T w = b (descending): ring[q] = w_{i+1+q}; L_{i+1+q, i} is left entry q of row i+1+q
+  auto load_lt = [&](double (&e)[kFacMax + 1], int i) {
+#pragma unroll
+    for (int q = 0; q < kFacMax; ++q) {
+      const int row = i + 1 + q;
+      e[q] = (i >= 0 && row < N && q < P.fac_ns[row]) ? fac[size_t(P.fac_off[row] + P.fac_nm[row] + q) * npairs] : 0.0;
+    }
+    e[kFacMax] = (i >= 0) ? fac[size_t(P.fac_off[i] + P.fac_nm[i] + P.fac_ns[i]) * npairs] : 0.0;
+  };
+  double fr[kFacPre][kFacMax + 1];
+  double2 pv[kFacPre];
+#pragma unroll
+  for (int d = 0; d < kFacPre; ++d) {
+    load_lt(fr[d], N - 1 - d);
+    pv[d] = (N - 1 - d >= 0) ? scr[size_t(N - 1 - d) * ncol + c] : zero2();
+  }
   double2 ring[kFacMax];
 #pragma unroll
   for (int q = 0; q < kFacMax; ++q) ring[q] = zero2();
   for (int i = N - 1; i >= 0; --i) {
-    double2 b = scr[size_t(i) * ncol + c];
+    double2 b = pv[0];
 #pragma unroll
-    for (int q = 0; q < kFacMax; ++q) {
-      const int row = i + 1 + q;
-      if (row < N && q < P.fac_ns[row]) b = fma2(-fac[size_t(P.fac_off[row] + P.fac_nm[row] + q) * npairs], ring[q], b);
+    for (int q = 0; q < kFacMax; ++q) b = fma2(-fr[0][q], ring[q], b);
+    const double2 w = cscale(b, fr[0][kFacMax]);
+#pragma unroll
+    for (int d = 0; d < kFacPre - 1; ++d) {
+      pv[d] = pv[d + 1];
+#pragma unroll
+      for (int q = 0; q <= kFacMax; ++q) fr[d][q] = fr[d + 1][q];
     }
-    const double2 w = cscale(b, fac[size_t(P.fac_off[i] + P.fac_nm[i] + P.fac_ns[i]) * npairs]);
+    load_lt(fr[kFacPre - 1], i - kFacPre);
+    pv[kFacPre - 1] = (i - kFacPre >= 0) ? scr[size_t(i - kFacPre) * ncol + c] : zero2();
 #pragma unroll
     for (int q = kFacMax - 1; q > 0; --q) ring[q] = ring[q - 1];
     ring[0] = w;
     scr[size_t(i) * ncol + c] = w;
   }
   // U^T psi = w (ascending): ring[m] = psi_{i-1-m}; U_{i-1-m, i} is multiplier m of row i-1-m
-#pragma unroll
-  for (int q = 0; q < kFacMax; ++q) ring[q] = zero2();
-  for (int i = 0; i < N; ++i) {
-    double2 x = scr[size_t(i) * ncol + c];
+  auto load_ut = [&](double (&e)[kFacMax + 1], int i) {
 #pragma unroll
     for (int m = 0; m < kFacMax; ++m) {
       const int row = i - 1 - m;
-      if (row >= 0 && m < P.fac_nm[row]) x = fma2(-fac[size_t(P.fac_off[row] + m) * npairs], ring[m], x);
+      e[m] = (i < N && row >= 0 && m < P.fac_nm[row]) ? fac[size_t(P.fac_off[row] + m) * npairs] : 0.0;
     }
+    e[kFacMax] = 0.0;
+  };
+#pragma unroll
+  for (int d = 0; d < kFacPre; ++d) {
+    load_ut(fr[d], d);
+    pv[d] = (d < N) ? scr[size_t(d) * ncol + c] : zero2();
+  }
+#pragma unroll
+  for (int q = 0; q < kFacMax; ++q) ring[q] = zero2();
+  for (int i = 0; i < N; ++i) {
+    double2 x = pv[0];
+#pragma unroll
+    for (int m = 0; m < kFacMax; ++m) x = fma2(-fr[0][m], ring[m], x);
+#pragma unroll
+    for (int d = 0; d < kFacPre - 1; ++d) {
+      pv[d] = pv[d + 1];
+#pragma unroll
+      for (int q = 0; q <= kFacMax; ++q) fr[d][q] = fr[d + 1][q];
+    }
+    load_ut(fr[kFacPre - 1], i + kFacPre);
+    pv[kFacPre - 1] = (i + kFacPre < N) ? scr[size_t(i + kFacPre) * ncol + c] : zero2();
 #pragma unroll
     for (int m = kFacMax - 1; m > 0; --m) ring[m] = ring[m - 1];
     ring[0] = x;
@@ -3380,6 +3421,9 @@ __device__ __forceinline__ void scatter_Gt(const DevPlan& P, int g, const double
 #pragma unroll
   for (int q = 0; q < kMaxW; ++q) acc[q] = zero2();
   int base = 0;
+  double2 pf[kPreMc];  // psi rows 1, 2, ... loaded ahead
+#pragma unroll
+  for (int d = 0; d < kPreMc; ++d) pf[d] = (1 + d < n2) ? scr[size_t(1 + d) * ncol + c] : zero2();
   for (int i = 1; i < n2; ++i) {
     const int lo = P.gs_lo[g * N + i];
     while (base < lo) {
@@ -3390,7 +3434,10 @@ __device__ __forceinline__ void scatter_Gt(const DevPlan& P, int g, const double
       acc[kMaxW - 1] = zero2();
       ++base;
     }
-    const double2 psi = cscale(scr[size_t(i) * ncol + c], scale);
+    const double2 psi = cscale(pf[0], scale);
+#pragma unroll
+    for (int d = 0; d < kPreMc - 1; ++d) pf[d] = pf[d + 1];
+    if (i + kPreMc < n2) pf[kPreMc - 1] = scr[size_t(i + kPreMc) * ncol + c];
 #pragma unroll
     for (int q = 0; q < kMaxW; ++q)
       if (lo + q < n2) acc[q] = fma2(P.gs_w[(size_t(g) * N + i) * kMaxW + q], psi, acc[q]);
