@@ -4454,6 +4454,34 @@ static lmvd_status rhs_phase(const Ctx& c, const lmvd_substep_args* a, const dou
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
 }
 
+// Fused m^c (k_mc) of one set of rho_t values at tau, on the workspace's two sweep scratch fields: V1, V2, V3
+// receive the m^c values (V3 null: psi in V1, see mc_body); with d1..d3 the m^d values are added and rhoc, c2,
+// mparc receive the coefficients.
+static void launch_mc(const Ctx& c, const double2* vals, const double2* d1, const double2* d2, const double2* d3,
+                      double2* V1, double2* V2, double2* V3, double2* rhoc, double2* c2, double2* mparc) {
+  lmvd_plan_s* p = c.p;
+  const HostTables& H = p->H;
+  const int nth = 2 * H.nl * ((H.nn + 1) / 2);
+  const dim3 g((nth + kThreads - 1) / kThreads);
+  const bool narrow = H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
+  double2* yp = c.at<double2>(p->ws.off_yp);
+  double2* yt = c.at<double2>(p->ws.off_yt);
+  // the staged tables must leave room for two blocks per compute unit
+  const McLds lay{H.n2, H.n2 + 1, narrow ? 6 : kMaxBand};
+  const bool stage = lay.bytes() <= 72 * 1024;
+#define LMVD_MC(LA_, LB_, ST_) \
+  col<JobMc<LA_, LA_, LB_, ST_>>(c, g, ST_ ? lay.bytes() : 0, {vals, yp, yt, d1, d2, d3, V1, V2, V3, rhoc, c2, mparc})
+  if (p->fac_la == 7 && narrow && stage)
+    LMVD_MC(7, 6, true);
+  else if (p->fac_la == 7 && narrow)
+    LMVD_MC(7, 6, false);
+  else if (p->fac_la == 7)
+    LMVD_MC(7, kMaxBand, false);
+  else
+    LMVD_MC(8, kMaxBand, false);
+#undef LMVD_MC
+}
+
 static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void* workspace, hipStream_t s,
                                Recorder* rec = nullptr) {
   const HostTables& H = p->H;
@@ -4498,35 +4526,16 @@ static lmvd_status run_substep(lmvd_plan_s* p, const lmvd_substep_args* a, void*
   const dim3 cgrid((unsigned)((ncol + kThreads - 1) / kThreads));
   // m^c values (and, for the final iterate, m = m^d + m^c and the coefficients) from the rho_t values
   auto mc_step = [&](bool final_it) {
-    const int nth = 2 * H.nl * ((H.nn + 1) / 2);
-    const dim3 g((nth + kThreads - 1) / kThreads);
     // values in, L-sweep intermediate out and back, 2 value fields out (psi, m2; the final iterate 3), A(k)
     // sweep intermediate out and back, the factors once per pair; the final iterate also reads m^d values and
     // writes rho_t, m_par, c2
+    const int nth = 2 * H.nl * ((H.nn + 1) / 2);
     ProfScope ps(p, KC_MC, s,
                  16.0 * nB * (final_it ? 11.0 : 5.0) + 16.0 * ncol * (H.n2 + 1) * (final_it ? 3.0 : 2.0) +
                      8.0 * H.fac_slots * (nth / 2));
-    const bool narrow = H.proj[0].lower <= 6 && H.proj[0].upper <= 6;
-    double2* yp = c.at<double2>(W.off_yp);
-    double2* yt = c.at<double2>(W.off_yt);
-#define LMVD_MC(LA_, LB_, ST_)                                                                               \
-  col<JobMc<LA_, LA_, LB_, ST_>>(c, g, ST_ ? lay.bytes() : 0,                                                \
-                                 {vals[0], yp, yt, final_it ? vmd1 : nullptr, final_it ? vc2d : nullptr,     \
-                                  final_it ? vmd3 : nullptr, vm1, vm2, final_it ? vm3 : nullptr,             \
-                                  final_it ? rhot : nullptr,                                                 \
-                                  final_it ? c2c : nullptr, final_it ? mpar : nullptr})
-    // the staged tables must leave room for two blocks per compute unit
-    const McLds lay{H.n2, H.n2 + 1, narrow ? 6 : kMaxBand};
-    const bool stage = lay.bytes() <= 72 * 1024;
-    if (p->fac_la == 7 && narrow && stage)
-      LMVD_MC(7, 6, true);
-    else if (p->fac_la == 7 && narrow)
-      LMVD_MC(7, 6, false);
-    else if (p->fac_la == 7)
-      LMVD_MC(7, kMaxBand, false);
-    else
-      LMVD_MC(8, kMaxBand, false);
-#undef LMVD_MC
+    launch_mc(c, vals[0], final_it ? vmd1 : nullptr, final_it ? vc2d : nullptr, final_it ? vmd3 : nullptr, vm1, vm2,
+              final_it ? vm3 : nullptr, final_it ? rhot : nullptr, final_it ? c2c : nullptr,
+              final_it ? mpar : nullptr);
   };
   auto values = [&](const double2* a1, double2* v1, const double2* a2, double2* v2, const double2* a3, double2* v3) {
     ProfScope ps(p, KC_VALUES, s, 16.0 * nB * ((a1 ? 2 : 0) + (a2 ? 2 : 0) + (a3 ? 2 : 0)));

@@ -392,7 +392,8 @@ static lmvd_status run_substep_adjoint(lmvd_plan_s* p, const lmvd_substep_args* 
     for (int h = 0; h < 3; ++h) axpy(a, cS(fa->z_hist[h]), ztc, co[h + 1] / dt);
   }
   // fixed-point iterations; the grid values of every iterate's z_t and m^c are kept
-  auto rhot_of = [&](const double2* zt, double* ztphys) -> lmvd_status {
+  // rho_t values at tau (in t1) of an iterate, its z_t kept on the grid
+  auto rhot_vals = [&](const double2* zt, double* ztphys) -> lmvd_status {
     lmvd_status r = to_phys(a, zt, EV_E0, ztphys);
     if (r != LMVD_OK) return r;
     AdjPointArgs A{};
@@ -400,17 +401,15 @@ static lmvd_status run_substep_adjoint(lmvd_plan_s* p, const lmvd_substep_args* 
     A.zt = ztphys;
     A.out[0] = pt[0];
     pointwise(AP_RHOT, A);
-    r = to_vals(a, pt[0], t1);
-    if (r != LMVD_OK) return r;
-    proj(a.c, 0, t1, rhot);
-    return LMVD_OK;
+    return to_vals(a, pt[0], t1);
   };
   for (int k = 0; k < kf; ++k) {
-    ADJ_OK(rhot_of(ztc, ztp(k)));
-    mc_of(a, rhot, mc1, mc2, mc3);
-    ADJ_OK(to_phys(a, mc1, EV_E0, mcp(k, 0)));
-    ADJ_OK(to_phys(a, mc2, EV_F0, mcp(k, 1)));
-    ADJ_OK(to_phys(a, mc3, EV_E0, mcp(k, 2)));
+    // m^c values at tau by the substep's fused kernel (mc1, mc2, mc3 hold values here), then on the grid
+    ADJ_OK(rhot_vals(ztc, ztp(k)));
+    launch_mc(a.c, t1, nullptr, nullptr, nullptr, mc1, mc2, mc3, nullptr, nullptr, nullptr);
+    ADJ_OK(to_phys(a, mc1, EV_IDENT, mcp(k, 0)));
+    ADJ_OK(to_phys(a, mc2, EV_IDENT, mcp(k, 1)));
+    ADJ_OK(to_phys(a, mc3, EV_IDENT, mcp(k, 2)));
     AdjPointArgs A{};
     A.zp = zp;
     for (int i = 0; i < 3; ++i) A.g[i] = gz[i], A.m[i] = mcp(k, i);
@@ -421,8 +420,9 @@ static lmvd_status run_substep_adjoint(lmvd_plan_s* p, const lmvd_substep_args* 
     axpy(a, rz, ztn);
     std::swap(ztc, ztn);
   }
-  // final m^c and m = m^d + m^c on the grid
-  ADJ_OK(rhot_of(ztc, ztp(kf)));
+  // final m^c (coefficients) and m = m^d + m^c on the grid
+  ADJ_OK(rhot_vals(ztc, ztp(kf)));
+  proj(a.c, 0, t1, rhot);
   mc_of(a, rhot, mc1, mc2, mc3);
   double2 *m1 = a.S(L.m1), *m2 = a.S(L.m2), *m3 = a.S(L.m3);
   axpy(a, md1, m1, 1.0, AM_ONE, false);
