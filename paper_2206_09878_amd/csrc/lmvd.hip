@@ -37,8 +37,15 @@ constexpr int kMaxOut = 10;
 constexpr int kNumAux = 4;   // physical-grid fields fixed during a substep
 constexpr int kPre = 3;      // rows loaded ahead by the sequential column sweeps
 // k_mc, at two waves per SIMD, hides the HBM latency only with its loads issued well ahead: row values
-// kPreMc rows ahead, factor rows kFacPre rows ahead, the input values of the emitted rows kValPre ahead
-constexpr int kPreMc = 8, kFacPre = 3, kValPre = 4;
+// kPreMc rows ahead, factor rows kFacPre rows ahead, the input values of the emitted rows kValPre ahead.
+// A regular stream (one row per step of its sweep) is read through a ring whose slot d serves the steps
+// d (mod depth): the sweep runs in blocks of `depth` steps, unrolled, and each step consumes its slot,
+// then refills it with an unconditional load (row index clamped into range); consuming before the load
+// is issued lets the load take the slot's register. A ring that shifts its
+// entries instead (slot 0 consumed, slot d+1 copied to slot d) copies each load's destination one step
+// after issuing it, and the copy waits for the load, so such a ring hides one step of latency at most.
+// Sweep 2 (descending) reads kPreMc2 rows ahead; sweep 3 reads the rows and the factor rows kPreMc3 ahead.
+constexpr int kPreMc = 8, kFacPre = 3, kValPre = 4, kPreMc2 = 4, kPreMc3 = 4;
 constexpr int kThreads = 256;
 constexpr int kZMaxE = 12;    // elements per thread in the z-FFT kernels
 constexpr int kXSlots = 3;    // complex slots per thread per line set in k_xpass
@@ -2304,21 +2311,29 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
     double2 ring[LB];
 #pragma unroll
     for (int m = 0; m < LB; ++m) ring[m] = zero2();
-    double2 pf[kPreMc];
-#pragma unroll
-    for (int d = 0; d < kPreMc; ++d) pf[d] = (d < n2) ? vals[size_t(d) * ncol + c] : zero2();
-    for (int i = 0; i < n2; ++i) {
-      double2 b = pf[0];
-#pragma unroll
-      for (int d = 0; d < kPreMc - 1; ++d) pf[d] = pf[d + 1];
-      if (i + kPreMc < n2) pf[kPreMc - 1] = vals[size_t(i + kPreMc) * ncol + c];
+    auto step = [&](int i, double2 b) __attribute__((always_inline)) {
 #pragma unroll
       for (int m = 0; m < LB; ++m) b = fma2(-P.lu_l[i * kMaxBand + m], ring[m], b);
       yp[size_t(i) * ncol + c] = b;
 #pragma unroll
       for (int m = LB - 1; m > 0; --m) ring[m] = ring[m - 1];
       ring[0] = b;
+    };
+    double2 pf[kPreMc];  // slot d: the next row i = d (mod kPreMc)
+#pragma unroll
+    for (int d = 0; d < kPreMc; ++d) pf[d] = vals[size_t(min(d, n2 - 1)) * ncol + c];
+    const int nfull = n2 - n2 % kPreMc;
+    for (int i0 = 0; i0 < nfull; i0 += kPreMc) {
+#pragma unroll
+      for (int d = 0; d < kPreMc; ++d) {
+        const int i = i0 + d;
+        step(i, pf[d]);
+        pf[d] = vals[size_t(min(i + kPreMc, n2 - 1)) * ncol + c];
+      }
     }
+#pragma unroll
+    for (int d = 0; d < kPreMc; ++d)
+      if (nfull + d < n2) step(nfull + d, pf[d]);
   }
   // 2. descending sweep: rho_t coefficients, r = -G1 rho_t, bottom-up forward sweep of A(k)
   {
@@ -2381,14 +2396,7 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
         for (int m = 0; m < UA; ++m) fm[d][m] = 0.0;
         if (!mean) load_mult(fm[d], inext - d);
       }
-      double2 pf[kPreMc];  // rows j-1 .. j-kPreMc of the L-sweep result, loaded ahead
-#pragma unroll
-      for (int d = 0; d < kPreMc; ++d) pf[d] = (n2 - 1 - d >= 0) ? yp[size_t(n2 - 1 - d) * ncol + c] : zero2();
-      for (int j = n2 - 1; j >= 0; --j) {
-        double2 y = pf[0];
-#pragma unroll
-        for (int d = 0; d < kPreMc - 1; ++d) pf[d] = pf[d + 1];
-        if (j - kPreMc >= 0) pf[kPreMc - 1] = yp[size_t(j - kPreMc) * ncol + c];
+      auto step = [&](int j, double2 y) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < LB; ++q) y = fma2(-U_(j, q), win[q], y);
         const double2 x = cscale(y, Ui_(j));
@@ -2399,7 +2407,7 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
         if (mean) {
           cm = make_double2(cm.x + x.x / ds_(j), cm.y + x.y / ds_(j));
           yt[size_t(j) * ncol + c] = cm;
-          continue;
+          return;
         }
         const int first = gf_(j), cnt = gc_(j);
         for (int e = cnt - 1; e >= 0; --e) {
@@ -2420,7 +2428,23 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
           for (int m = UA - 1; m > 0; --m) yr[m] = yr[m - 1];
           yr[0] = r;
         }
+      };
+      // step t of the sweep is row j = n2 - 1 - t of the L-sweep result; slot d serves t = d (mod kPreMc2)
+      double2 pf[kPreMc2];
+#pragma unroll
+      for (int d = 0; d < kPreMc2; ++d) pf[d] = yp[size_t(max(n2 - 1 - d, 0)) * ncol + c];
+      const int nfull = n2 - n2 % kPreMc2;
+      for (int t0 = 0; t0 < nfull; t0 += kPreMc2) {
+#pragma unroll
+        for (int d = 0; d < kPreMc2; ++d) {
+          const int j = n2 - 1 - (t0 + d);
+          step(j, pf[d]);
+          pf[d] = yp[size_t(max(j - kPreMc2, 0)) * ncol + c];
+        }
       }
+#pragma unroll
+      for (int d = 0; d < kPreMc2; ++d)
+        if (nfull + d < n2) step(n2 - 1 - (nfull + d), pf[d]);
       if (!mean) {  // Robin row 0 (inext == 0): r = 0
         double2 r = zero2();
 #pragma unroll
@@ -2466,46 +2490,26 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
       double2 cw[kMaxW];  // c_i, c_{i-1}, ...
 #pragma unroll
       for (int q = 0; q < kMaxW; ++q) cw[q] = zero2();
-      // entries left of the diagonal (fs[.][0 .. LA-1]) and 1/pivot (fs[.][LA]) of rows i .. i+kFacPre-1
-      double fs[kFacPre][LA + 1];
+      // entries left of the diagonal (raw[0 .. LA-1], those past the row's count masked at use) and
+      // 1/pivot (raw[LA]) of a factor row, read unconditionally at an in-range address
       auto load_sub = [&](double (&dst)[LA + 1], int row) {
-        const bool ok = row < N;
-        const int nm = ok ? nm_(row) : 0, ns = ok ? ns_(row) : 0, off = ok ? of_(row) : 0;
+        row = min(row, N - 1);
+        const int nm = nm_(row), ns = ns_(row), off = of_(row);
 #pragma unroll
-        for (int q = 0; q < LA; ++q) dst[q] = (ok && q < ns) ? fac[(size_t(off) + nm + q) * npairs] : 0.0;
-        dst[LA] = ok ? fac[(size_t(off) + nm + ns) * npairs] : 0.0;
+        for (int q = 0; q < LA; ++q) dst[q] = fac[(size_t(off) + nm + min(q, ns)) * npairs];
+        dst[LA] = fac[(size_t(off) + nm + ns) * npairs];
       };
-#pragma unroll
-      for (int d = 0; d < kFacPre; ++d) {
-#pragma unroll
-        for (int q = 0; q <= LA; ++q) fs[d][q] = 0.0;
-        if (!mean) load_sub(fs[d], d);
-      }
-      double2 pf[kPreMc];  // rows i .. i+kPreMc-1 of the A(k) forward-sweep result, loaded ahead
-#pragma unroll
-      for (int d = 0; d < kPreMc; ++d) pf[d] = (d < N) ? yt[size_t(d) * ncol + c] : zero2();
       // input values of the next rows to emit (tau rows are emitted in ascending order, each once)
       int enext = 0;
       double2 vq[kValPre];
 #pragma unroll
       for (int d = 0; d < kValPre; ++d) vq[d] = (!mean && d < n2) ? vals[size_t(d) * ncol + c] : zero2();
-      for (int i = 0; i < N; ++i) {
-        double2 x = pf[0];
-#pragma unroll
-        for (int d = 0; d < kPreMc - 1; ++d) pf[d] = pf[d + 1];
-        if (i + kPreMc < N) pf[kPreMc - 1] = yt[size_t(i + kPreMc) * ncol + c];
-        double fc[LA + 1];
-#pragma unroll
-        for (int q = 0; q <= LA; ++q) fc[q] = fs[0][q];
-#pragma unroll
-        for (int d = 0; d < kFacPre - 1; ++d)
-#pragma unroll
-          for (int q = 0; q <= LA; ++q) fs[d][q] = fs[d + 1][q];
-        if (!mean) load_sub(fs[kFacPre - 1], i + kFacPre);
+      auto step = [&](int i, double2 x, const double (&fr)[LA + 1]) __attribute__((always_inline)) {
         if (!mean) {
+          const int ns = ns_(i);
 #pragma unroll
-          for (int q = 0; q < LA; ++q) x = fma2(-fc[q], cw[q], x);
-          x = cscale(x, fc[LA]);
+          for (int q = 0; q < LA; ++q) x = fma2(-(q < ns ? fr[q] : 0.0), cw[q], x);
+          x = cscale(x, fr[LA]);
         }
 #pragma unroll
         for (int q = kMaxW - 1; q > 0; --q) cw[q] = cw[q - 1];
@@ -2554,7 +2558,28 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
           V2[o] = m2;
           if (V3) V3[o] = m3;
         }
+      };
+      // slot d serves rows i = d (mod kPreMc3): the A(k) forward-sweep result and the factor row
+      double2 pf[kPreMc3];
+      double fs[kPreMc3][LA + 1];
+#pragma unroll
+      for (int d = 0; d < kPreMc3; ++d) {
+        pf[d] = yt[size_t(min(d, N - 1)) * ncol + c];
+        load_sub(fs[d], d);
       }
+      const int nfull = N - N % kPreMc3;
+      for (int i0 = 0; i0 < nfull; i0 += kPreMc3) {
+#pragma unroll
+        for (int d = 0; d < kPreMc3; ++d) {
+          const int i = i0 + d;
+          step(i, pf[d], fs[d]);
+          pf[d] = yt[size_t(min(i + kPreMc3, N - 1)) * ncol + c];
+          load_sub(fs[d], i + kPreMc3);
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < kPreMc3; ++d)
+        if (nfull + d < N) step(nfull + d, pf[d], fs[d]);
     }
   }
 }
@@ -3290,22 +3315,37 @@ __global__ void __launch_bounds__(kThreads) k_evaluate_t(DevPlan P, int kind, co
   dst[size_t(i) * ncol + c] = acc;
 }
 
+// Independent transposed projections of one kind in one launch, blockIdx.y picking the job. A job may
+// run in place (in == out): each thread owns one column and reads every row of it before writing it.
+constexpr int kProjTJobs = 8;
+struct ProjTJobs {
+  const double2* in[kProjTJobs];
+  double2* out[kProjTJobs];
+};
+// Rows of the sweep loaded this many steps ahead of the dependent chain: at the small sizes this
+// kernel runs at, a few waves per CU wait on every row's HBM latency otherwise. The sweeps run in
+// blocks of kProjTPre steps, unrolled, so that step d of a block consumes slot d of the ring and then
+// refills it, unconditionally (the row index clamped to the sweep's last row): a load's destination
+// is then never copied or merged before it is consumed, either of which makes the wave wait for it.
+constexpr int kProjTPre = 4;
+
 // (A^{-1} R)^T = R A^{-T} per column, A = L U of the projection `kind`: U^T z = y ascending, L^T x = z
 // descending (x in out), then the end rows zeroed for the Dirichlet / Neumann kinds
-__global__ void __launch_bounds__(kThreads) k_project_t(DevPlan P, int kind, const double2* __restrict__ in,
-                                                       double2* __restrict__ out) {
+__global__ void __launch_bounds__(kThreads) k_project_t(DevPlan P, int kind, ProjTJobs J) {
   const size_t ncol = size_t(P.nn) * P.nl;
   const size_t c = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
+  const double2* in = J.in[blockIdx.y];
+  double2* out = J.out[blockIdx.y];
   const int n2 = P.n2;
   const auto L = P.lu_l + size_t(kind) * n2 * kMaxBand;
   const auto U = P.lu_u + size_t(kind) * n2 * (kMaxBand + 1);
   const auto Ui = P.lu_uinv + size_t(kind) * n2;
+  const int nfull = n2 - n2 % kProjTPre;  // steps run in whole blocks; the rest from the ring alone
   double2 ring[kMaxBand];
-#pragma unroll
-  for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
-  for (int i = 0; i < n2; ++i) {  // ring[q] = z_{i-1-q}; U_{i-1-q, i} is entry q+1 of row i-1-q
-    double2 b = in[size_t(i) * ncol + c];
+  double2 pv[kProjTPre];  // slot d: the next row of the sweep whose index is d (mod kProjTPre) from its start
+  // U^T z = y: ring[q] = z_{i-1-q}; U_{i-1-q, i} is entry q+1 of row i-1-q
+  auto up = [&](int i, double2 b) {
 #pragma unroll
     for (int q = 0; q < kMaxBand; ++q)
       if (i - 1 - q >= 0) b = fma2(-U[(i - 1 - q) * (kMaxBand + 1) + q + 1], ring[q], b);
@@ -3314,11 +3354,9 @@ __global__ void __launch_bounds__(kThreads) k_project_t(DevPlan P, int kind, con
     for (int q = kMaxBand - 1; q > 0; --q) ring[q] = ring[q - 1];
     ring[0] = z;
     out[size_t(i) * ncol + c] = z;
-  }
-#pragma unroll
-  for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
-  for (int i = n2 - 1; i >= 0; --i) {  // ring[m] = x_{i+1+m}; L_{i+1+m, i} is multiplier m of row i+1+m
-    double2 x = out[size_t(i) * ncol + c];
+  };
+  // L^T x = z: ring[m] = x_{i+1+m}; L_{i+1+m, i} is multiplier m of row i+1+m
+  auto down = [&](int i, double2 x) {
 #pragma unroll
     for (int m = 0; m < kMaxBand; ++m)
       if (i + 1 + m < n2) x = fma2(-L[(i + 1 + m) * kMaxBand + m], ring[m], x);
@@ -3326,7 +3364,38 @@ __global__ void __launch_bounds__(kThreads) k_project_t(DevPlan P, int kind, con
     for (int m = kMaxBand - 1; m > 0; --m) ring[m] = ring[m - 1];
     ring[0] = x;
     out[size_t(i) * ncol + c] = (kind != 0 && (i == 0 || i == n2 - 1)) ? zero2() : x;
+  };
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+#pragma unroll
+  for (int d = 0; d < kProjTPre; ++d) pv[d] = in[size_t(min(d, n2 - 1)) * ncol + c];
+  for (int i0 = 0; i0 < nfull; i0 += kProjTPre) {
+#pragma unroll
+    for (int d = 0; d < kProjTPre; ++d) {
+      const int i = i0 + d;
+      up(i, pv[d]);
+      pv[d] = in[size_t(min(i + kProjTPre, n2 - 1)) * ncol + c];
+    }
   }
+#pragma unroll
+  for (int d = 0; d < kProjTPre; ++d)
+    if (nfull + d < n2) up(nfull + d, pv[d]);
+#pragma unroll
+  for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+  // descending over z (written above by this thread): step d of a block is row n2 - 1 - (i0 + d)
+#pragma unroll
+  for (int d = 0; d < kProjTPre; ++d) pv[d] = out[size_t(max(n2 - 1 - d, 0)) * ncol + c];
+  for (int i0 = 0; i0 < nfull; i0 += kProjTPre) {
+#pragma unroll
+    for (int d = 0; d < kProjTPre; ++d) {
+      const int i = n2 - 1 - (i0 + d);
+      down(i, pv[d]);
+      pv[d] = out[size_t(max(i - kProjTPre, 0)) * ncol + c];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < kProjTPre; ++d)
+    if (nfull + d < n2) down(n2 - 1 - (nfull + d), pv[d]);
 }
 
 constexpr int kFacMax = 9;  // band of the factor rows (a_lower, a_upper <= 8)
@@ -5199,9 +5268,11 @@ lmvd_status lmvd_evaluate_adjoint(lmvd_plan plan, int32_t deriv, int32_t star, c
 lmvd_status lmvd_project_adjoint(lmvd_plan plan, int32_t kind, const void* coeffs, void* values, void* stream) {
   if (!plan || !coeffs || !values || kind < 0 || kind > 2 || coeffs == values) return LMVD_EINVAL;
   const size_t ncol = size_t(plan->H.nn) * plan->H.nl;
+  ProjTJobs J{};
+  J.in[0] = static_cast<const double2*>(coeffs);
+  J.out[0] = static_cast<double2*>(values);
   hipLaunchKernelGGL(k_project_t, dim3((ncol + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                     static_cast<hipStream_t>(stream), plan->D, int(kind), static_cast<const double2*>(coeffs),
-                     static_cast<double2*>(values));
+                     static_cast<hipStream_t>(stream), plan->D, int(kind), J);
   return hipGetLastError() == hipSuccess ? LMVD_OK : LMVD_EHIP;
 }
 

@@ -293,8 +293,14 @@ static void eval_t(const AdjCtx& a, int kind, const double2* vals, double2* coef
   const dim3 g(a.gC.x, unsigned(kind == EV_F0 ? a.c.p->H.n2 + 1 : a.c.p->H.n2));
   hipLaunchKernelGGL(k_evaluate_t, g, dim3(kThreads), 0, a.c.s, a.c.p->D, kind, vals, coeffs);
 }
+// R A^{-T} of `kind` for n independent (coeffs, vals) pairs in one launch; a pair may be in place
+static void proj_t_n(const AdjCtx& a, int kind, int n, const double2* const* coeffs, double2* const* vals) {
+  ProjTJobs J{};
+  for (int j = 0; j < n; ++j) J.in[j] = coeffs[j], J.out[j] = vals[j];
+  hipLaunchKernelGGL(k_project_t, dim3(a.gC.x, unsigned(n)), dim3(kThreads), 0, a.c.s, a.c.p->D, kind, J);
+}
 static void proj_t(const AdjCtx& a, int kind, const double2* coeffs, double2* vals) {
-  hipLaunchKernelGGL(k_project_t, a.gC, dim3(kThreads), 0, a.c.s, a.c.p->D, kind, coeffs, vals);
+  proj_t_n(a, kind, 1, &coeffs, &vals);
 }
 // coeffs_bar (+)= E_kind^T Inv^T(phys_bar), through the two scratch fields t, u
 static lmvd_status phys_to_coef_t(const AdjCtx& a, const double* physb, int kind, double2* coefb, double2* t,
@@ -482,8 +488,11 @@ static lmvd_status run_substep_adjoint(lmvd_plan_s* p, const lmvd_substep_args* 
   double2* tb[6];
   for (int i = 0; i < 6; ++i) tb[i] = a.S(L.tb[i]);
   double2* ub[3] = {a.S(L.ub[0]), a.S(L.ub[1]), a.S(L.ub[2])};
-  proj_t(a, 1, rphb, t1);   // v_bar of R_phi
-  proj_t(a, 1, romb, t2);   // v_bar of R_Omega
+  {  // v_bar of R_phi into t1, of R_Omega into t2
+    const double2* in[2] = {rphb, romb};
+    double2* out[2] = {t1, t2};
+    proj_t_n(a, 1, 2, in, out);
+  }
   axpy(a, t1, nb[1], -1.0, AM_KSQ, false, false, true);
   axpy(a, t1, dnb[0], 1.0, AM_IK1, false, false, true);
   axpy(a, t1, dnb[2], 1.0, AM_IK3, false, false, true);
@@ -536,11 +545,9 @@ static lmvd_status run_substep_adjoint(lmvd_plan_s* p, const lmvd_substep_args* 
     hipLaunchKernelGGL(k_adj_meancol, dim3(unsigned((n2 + 63) / 64)), dim3(64), 0, s, p->D, 0, t2, tmpv);
     axpy(a, t2, tb[q == 0 ? 1 : 4]);
   }
-  // T_hat = P0^{-1} (values of T): V_ab = P0^T T_hat_bar (in place through t1)
-  for (int q = 0; q < 6; ++q) {
-    proj_t(a, 0, tb[q], t1);
-    axpy(a, t1, tb[q], 1.0, AM_ONE, false);
-  }
+  // T_hat = P0^{-1} (values of T): V_ab = P0^T T_hat_bar, the six in place in one launch
+  static_assert(kProjTJobs >= 6, "six stress components per launch");
+  proj_t_n(a, 0, 6, tb, tb);
   // viscous part, formed spectrally from u_hat: s_ab = mu (D_b u_a + D_a u_b) - 2/3 mu delta_ab sum_c D_c u_c,
   // D_0 = i k1 E0, D_1 = E1, D_2 = i k3 E0
   const double mu = H.cfg.mu;
@@ -571,10 +578,8 @@ static lmvd_status run_substep_adjoint(lmvd_plan_s* p, const lmvd_substep_args* 
   for (int c = 0; c < 3; ++c) add_Dt(c, t4, -2.0 / 3.0 * mu, ub[c]);
   // convective part on the grid: T_bar_ab = Fwd^T V_ab; u_bar = Fwd^T P0^T u_hat_bar
   for (int q = 0; q < 6; ++q) ADJ_OK(fwd_t(a, tb[q], pt[q]));
-  for (int i = 0; i < 3; ++i) {
-    proj_t(a, 0, ub[i], t1);
-    ADJ_OK(fwd_t(a, t1, pt[6 + i]));
-  }
+  proj_t_n(a, 0, 3, ub, ub);  // u_hat_bar -> P0^T u_hat_bar in place (ub is not read again)
+  for (int i = 0; i < 3; ++i) ADJ_OK(fwd_t(a, ub[i], pt[6 + i]));
   double* zpb = a.Ph(L.zpb);
   double* gb[3] = {a.Ph(L.gb[0]), a.Ph(L.gb[1]), a.Ph(L.gb[2])};
   double* lapb = a.Ph(L.lapb);
