@@ -1606,6 +1606,9 @@ __global__ void __launch_bounds__(kThreads, 2) k_xpair_w2(DevPlan P, const doubl
 // (kind 0 interpolation, 1 Dirichlet rows, 2 Neumann rows).  One thread per
 // column; forward sweep stores L^{-1} b in `out`, backward sweep overwrites it.
 
+// Rows read this many steps ahead of the sweeps' dependent chains (see the m^c kernel's rings).
+constexpr int kProjPre = 4;
+
 template <int EPI>
 __device__ __forceinline__ void proj_body(const DevPlan& P, int c, int kind, const double2* in, double2* out,
                                           const double2* __restrict__ add, const double2* __restrict__ z,
@@ -1613,21 +1616,40 @@ __device__ __forceinline__ void proj_body(const DevPlan& P, int c, int kind, con
                                           double2* __restrict__ vals_out, double2* __restrict__ vals_out1,
                                           int stage, int ncol) {
   if (c >= ncol) return;
+  constexpr int D = kProjPre;
   const int n2 = P.n2;
+  const int nfull = n2 - n2 % D;
   const auto L = P.lu_l + size_t(kind) * n2 * kMaxBand;
   const auto U = P.lu_u + size_t(kind) * n2 * (kMaxBand + 1);
   const auto Ui = P.lu_uinv + size_t(kind) * n2;
   double2 ring[kMaxBand];
 #pragma unroll
   for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
-  for (int i = 0; i < n2; ++i) {
-    double2 b = (kind != 0 && (i == 0 || i == n2 - 1)) ? zero2() : in[size_t(i) * ncol + c];
+  // ascending L sweep; slot d of pv holds the next input row i = d (mod D)
+  auto fwd = [&](int i, double2 b) __attribute__((always_inline)) {
+    if (kind != 0 && (i == 0 || i == n2 - 1)) b = zero2();
 #pragma unroll
     for (int m = 0; m < kMaxBand; ++m) b = fma2(-L[i * kMaxBand + m], ring[m], b);
     out[size_t(i) * ncol + c] = b;
 #pragma unroll
     for (int m = kMaxBand - 1; m > 0; --m) ring[m] = ring[m - 1];
     ring[0] = b;
+  };
+  {
+    double2 pv[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) pv[d] = in[size_t(min(d, n2 - 1)) * ncol + c];
+    for (int i0 = 0; i0 < nfull; i0 += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int i = i0 + d;
+        fwd(i, pv[d]);
+        pv[d] = in[size_t(min(i + D, n2 - 1)) * ncol + c];
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      if (nfull + d < n2) fwd(nfull + d, pv[d]);
   }
 #pragma unroll
   for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
@@ -1635,8 +1657,23 @@ __device__ __forceinline__ void proj_body(const DevPlan& P, int c, int kind, con
   double2 win[kMaxW];
 #pragma unroll
   for (int q = 0; q < kMaxW; ++q) win[q] = zero2();
-  for (int i = n2 - 1; i >= 0; --i) {
-    double2 y = out[size_t(i) * ncol + c];
+  // descending U sweep; the rows it reads (the L-sweep result, and for the fixed-point epilogues the
+  // added field, z and the previous stage's z_t) come through rings of D slots like the ascending one
+  const double2* ztp = (stage != 0) ? zt_prev : z;  // read unconditionally, used at stage 1 only
+  struct Rows {
+    double2 y, a, z0, zp;
+  };
+  auto load = [&](Rows& r, int i) __attribute__((always_inline)) {
+    const size_t e = size_t(i) * ncol + c;
+    r.y = out[e];
+    if (EPI != EPI_STORE) r.a = add[e];
+    if (EPI == EPI_ADD_ZUPDATE) {
+      r.z0 = z[e];
+      r.zp = ztp[e];
+    }
+  };
+  auto bwd = [&](int i, const Rows& r) __attribute__((always_inline)) {
+    double2 y = r.y;
 #pragma unroll
     for (int q = 0; q < kMaxBand; ++q) y = fma2(-U[i * (kMaxBand + 1) + q + 1], ring[q], y);
     const double2 x = cscale(y, Ui[i]);
@@ -1644,7 +1681,7 @@ __device__ __forceinline__ void proj_body(const DevPlan& P, int c, int kind, con
     for (int q = kMaxBand - 1; q > 0; --q) ring[q] = ring[q - 1];
     ring[0] = x;
     const size_t e = size_t(i) * ncol + c;
-    const double2 fin = (EPI == EPI_STORE) ? x : cadd(x, add[e]);
+    const double2 fin = (EPI == EPI_STORE) ? x : cadd(x, r.a);
     // a non-final fixed-point iterate (EPI_ADD) is consumed only through its emitted values
     if (EPI != EPI_ADD) out[e] = fin;
     if (vals_out) {
@@ -1667,20 +1704,33 @@ __device__ __forceinline__ void proj_body(const DevPlan& P, int c, int kind, con
         }
       }
     }
-    if (EPI != EPI_STORE) {
+    if (EPI == EPI_ADD_ZUPDATE) {
       const double2 zt = fin;
-      if (EPI == EPI_ADD_ZUPDATE) {
-        const double2 z0 = z[e];
-        double2 zn;
-        if (stage == 0) {
-          zn = fma2(0.5 * P.dt, zt, z0);
-        } else {
-          const double2 dz = make_double2(zt.x - 0.5 * zt_prev[e].x, zt.y - 0.5 * zt_prev[e].y);
-          zn = fma2(P.dt, dz, z0);
-        }
-        z_out[e] = zn;
+      double2 zn;
+      if (stage == 0) {
+        zn = fma2(0.5 * P.dt, zt, r.z0);
+      } else {
+        const double2 dz = make_double2(zt.x - 0.5 * r.zp.x, zt.y - 0.5 * r.zp.y);
+        zn = fma2(P.dt, dz, r.z0);
+      }
+      z_out[e] = zn;
+    }
+  };
+  {
+    Rows pr[D];  // slot d: step t = d (mod D) of the sweep, row i = n2 - 1 - t
+#pragma unroll
+    for (int d = 0; d < D; ++d) load(pr[d], max(n2 - 1 - d, 0));
+    for (int t0 = 0; t0 < nfull; t0 += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int i = n2 - 1 - (t0 + d);
+        bwd(i, pr[d]);
+        load(pr[d], max(i - D, 0));
       }
     }
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      if (nfull + d < n2) bwd(n2 - 1 - (nfull + d), pr[d]);
   }
 }
 
@@ -2788,15 +2838,15 @@ __device__ __forceinline__ void rhs_fluct_body(const DevPlan& P, const unsigned 
   const auto L = P.lu_l + size_t(1) * n2 * kMaxBand;
   const auto U = P.lu_u + size_t(1) * n2 * (kMaxBand + 1);
   const auto Ui = P.lu_uinv + size_t(1) * n2;
+  constexpr int D = kProjPre;
+  const int nfull = n2 - n2 % D;
   double2 rp[kMaxBand], ro[kMaxBand];
 #pragma unroll
   for (int m = 0; m < kMaxBand; ++m) rp[m] = ro[m] = zero2();
-  for (int i = 0; i < n2; ++i) {
-    double2 bp = zero2(), bo = zero2();
-    if (i > 0 && i < n2 - 1) {
-      bp = RP[size_t(i) * ncol + c];
-      bo = RO[size_t(i) * ncol + c];
-    }
+  // ascending L sweep over the interior rows (Dirichlet end rows zero); rows come through rings of D
+  // slots, slot d serving the steps i = d (mod D), each consumed before its refill is issued
+  auto fwd = [&](int i, double2 bp, double2 bo) __attribute__((always_inline)) {
+    if (i == 0 || i == n2 - 1) bp = bo = zero2();
 #pragma unroll
     for (int m = 0; m < kMaxBand; ++m) {
       const double lm = L[i * kMaxBand + m];
@@ -2812,12 +2862,51 @@ __device__ __forceinline__ void rhs_fluct_body(const DevPlan& P, const unsigned 
     }
     rp[0] = bp;
     ro[0] = bo;
+  };
+  {
+    double2 pp[D], po[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      pp[d] = RP[size_t(min(d, n2 - 1)) * ncol + c];
+      po[d] = RO[size_t(min(d, n2 - 1)) * ncol + c];
+    }
+    for (int i0 = 0; i0 < nfull; i0 += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int i = i0 + d;
+        fwd(i, pp[d], po[d]);
+        pp[d] = RP[size_t(min(i + D, n2 - 1)) * ncol + c];
+        po[d] = RO[size_t(min(i + D, n2 - 1)) * ncol + c];
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      if (nfull + d < n2) fwd(nfull + d, pp[d], po[d]);
   }
 #pragma unroll
   for (int m = 0; m < kMaxBand; ++m) rp[m] = ro[m] = zero2();
-  for (int i = n2 - 1; i >= 0; --i) {
+  // descending U sweep and the RK2 update; the state and the previous stage's right-hand sides are
+  // read unconditionally (from the state itself when the stage does not use them)
+  const bool upd = stage <= 1;
+  const double2* phr = upd ? phi : yphi;
+  const double2* omr = upd ? om : yom;
+  const double2* ppr = stage == 1 ? rphi_prev : phr;
+  const double2* opr = stage == 1 ? rom_prev : omr;
+  struct Rows {
+    double2 yp, yo, p0, o0, pp, op;
+  };
+  auto load = [&](Rows& r, int i) __attribute__((always_inline)) {
     const size_t e = size_t(i) * ncol + c;
-    double2 yp = yphi[e], yo = yom[e];
+    r.yp = yphi[e];
+    r.yo = yom[e];
+    r.p0 = phr[e];
+    r.o0 = omr[e];
+    r.pp = ppr[e];
+    r.op = opr[e];
+  };
+  auto bwd = [&](int i, const Rows& r) __attribute__((always_inline)) {
+    const size_t e = size_t(i) * ncol + c;
+    double2 yp = r.yp, yo = r.yo;
 #pragma unroll
     for (int q = 0; q < kMaxBand; ++q) {
       const double u = U[i * (kMaxBand + 1) + q + 1];
@@ -2834,16 +2923,30 @@ __device__ __forceinline__ void rhs_fluct_body(const DevPlan& P, const unsigned 
     ro[0] = xo;
     if (rphi_out) rphi_out[e] = xp;
     if (rom_out) rom_out[e] = xo;
-    if (stage > 1) continue;  // right-hand sides only
-    const double2 p0 = phi[e], o0 = om[e];
+    if (!upd) return;  // right-hand sides only
     if (stage == 0) {
-      phi_out[e] = fma2(0.5 * P.dt, xp, p0);
-      om_out[e] = fma2(0.5 * P.dt, xo, o0);
+      phi_out[e] = fma2(0.5 * P.dt, xp, r.p0);
+      om_out[e] = fma2(0.5 * P.dt, xo, r.o0);
     } else {
-      const double2 pp = rphi_prev[e], op = rom_prev[e];
-      phi_out[e] = fma2(P.dt, make_double2(xp.x - 0.5 * pp.x, xp.y - 0.5 * pp.y), p0);
-      om_out[e] = fma2(P.dt, make_double2(xo.x - 0.5 * op.x, xo.y - 0.5 * op.y), o0);
+      phi_out[e] = fma2(P.dt, make_double2(xp.x - 0.5 * r.pp.x, xp.y - 0.5 * r.pp.y), r.p0);
+      om_out[e] = fma2(P.dt, make_double2(xo.x - 0.5 * r.op.x, xo.y - 0.5 * r.op.y), r.o0);
     }
+  };
+  {
+    Rows pr[D];  // slot d: step t = d (mod D), row i = n2 - 1 - t
+#pragma unroll
+    for (int d = 0; d < D; ++d) load(pr[d], max(n2 - 1 - d, 0));
+    for (int t0 = 0; t0 < nfull; t0 += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int i = n2 - 1 - (t0 + d);
+        bwd(i, pr[d]);
+        load(pr[d], max(i - D, 0));
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      if (nfull + d < n2) bwd(n2 - 1 - (nfull + d), pr[d]);
   }
 }
 __global__ void __launch_bounds__(kThreads) k_rhs_fluct(DevPlan P, const double2* __restrict__ RO,
