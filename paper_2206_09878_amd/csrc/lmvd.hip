@@ -3502,85 +3502,104 @@ __global__ void __launch_bounds__(kThreads) k_project_t(DevPlan P, int kind, Pro
 }
 
 constexpr int kFacMax = 9;  // band of the factor rows (a_lower, a_upper <= 8)
+constexpr int kScatPre = 4;  // psi rows read ahead by scatter_Gt
 // psi = A(k)^{-T} b in place in scr (n2 + 1 rows of column c), A = U L from the plan's factors of pair
 // fac (U unit upper: the multipliers; L: entries left of the diagonal and the inverse diagonal):
 // L^T w = b descending, then U^T psi = w ascending
 __device__ __forceinline__ void solve_At(const DevPlan& P, const double* fac, int npairs, double2* scr, size_t c,
                                          size_t ncol) {
   const int N = P.n2 + 1;
-  // The operands of a step (the value row and the factor entries it needs) are loaded kFacPre steps
-  // ahead into register rings: at two waves per SIMD or fewer the HBM latency is otherwise exposed at
-  // every step of the chain.
+  // The operands of a step (the value row and the factor entries it needs) are loaded D = kFacPre steps
+  // ahead: at two waves per SIMD or fewer the HBM latency is otherwise exposed at every step of the
+  // chain. The sweeps run in unrolled blocks of D steps; step d of a block consumes ring slot d and then
+  // refills it with unconditional loads at in-range addresses (entries outside a row's band are masked
+  // where they are used), so a load keeps its register until its use.
+  constexpr int D = kFacPre;
+  const int nfull = N - N % D;
+  double fr[D][kFacMax + 1];
+  double2 pv[D];
+  double2 ring[kFacMax];
   // L^T w = b (descending): ring[q] = w_{i+1+q}; L_{i+1+q, i} is left entry q of row i+1+q
-  auto load_lt = [&](double (&e)[kFacMax + 1], int i) {
+  auto load_lt = [&](double (&e)[kFacMax + 1], int i) __attribute__((always_inline)) {
+    i = max(i, 0);
+#pragma unroll
+    for (int q = 0; q < kFacMax; ++q) {
+      const int row = min(i + 1 + q, N - 1);
+      e[q] = fac[size_t(P.fac_off[row] + P.fac_nm[row] + min(q, P.fac_ns[row])) * npairs];
+    }
+    e[kFacMax] = fac[size_t(P.fac_off[i] + P.fac_nm[i] + P.fac_ns[i]) * npairs];
+  };
+  auto step_lt = [&](int i, double2 b, const double (&e)[kFacMax + 1]) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < kFacMax; ++q) {
       const int row = i + 1 + q;
-      e[q] = (i >= 0 && row < N && q < P.fac_ns[row]) ? fac[size_t(P.fac_off[row] + P.fac_nm[row] + q) * npairs] : 0.0;
+      const bool in = row < N && q < P.fac_ns[min(row, N - 1)];
+      b = fma2(-(in ? e[q] : 0.0), ring[q], b);
     }
-    e[kFacMax] = (i >= 0) ? fac[size_t(P.fac_off[i] + P.fac_nm[i] + P.fac_ns[i]) * npairs] : 0.0;
-  };
-  double fr[kFacPre][kFacMax + 1];
-  double2 pv[kFacPre];
-#pragma unroll
-  for (int d = 0; d < kFacPre; ++d) {
-    load_lt(fr[d], N - 1 - d);
-    pv[d] = (N - 1 - d >= 0) ? scr[size_t(N - 1 - d) * ncol + c] : zero2();
-  }
-  double2 ring[kFacMax];
-#pragma unroll
-  for (int q = 0; q < kFacMax; ++q) ring[q] = zero2();
-  for (int i = N - 1; i >= 0; --i) {
-    double2 b = pv[0];
-#pragma unroll
-    for (int q = 0; q < kFacMax; ++q) b = fma2(-fr[0][q], ring[q], b);
-    const double2 w = cscale(b, fr[0][kFacMax]);
-#pragma unroll
-    for (int d = 0; d < kFacPre - 1; ++d) {
-      pv[d] = pv[d + 1];
-#pragma unroll
-      for (int q = 0; q <= kFacMax; ++q) fr[d][q] = fr[d + 1][q];
-    }
-    load_lt(fr[kFacPre - 1], i - kFacPre);
-    pv[kFacPre - 1] = (i - kFacPre >= 0) ? scr[size_t(i - kFacPre) * ncol + c] : zero2();
+    const double2 w = cscale(b, e[kFacMax]);
 #pragma unroll
     for (int q = kFacMax - 1; q > 0; --q) ring[q] = ring[q - 1];
     ring[0] = w;
     scr[size_t(i) * ncol + c] = w;
+  };
+#pragma unroll
+  for (int q = 0; q < kFacMax; ++q) ring[q] = zero2();
+#pragma unroll
+  for (int d = 0; d < D; ++d) {  // step t = d (mod D) is row i = N - 1 - t
+    load_lt(fr[d], N - 1 - d);
+    pv[d] = scr[size_t(max(N - 1 - d, 0)) * ncol + c];
   }
+  for (int t0 = 0; t0 < nfull; t0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int i = N - 1 - (t0 + d);
+      step_lt(i, pv[d], fr[d]);
+      load_lt(fr[d], i - D);
+      pv[d] = scr[size_t(max(i - D, 0)) * ncol + c];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (nfull + d < N) step_lt(N - 1 - (nfull + d), pv[d], fr[d]);
   // U^T psi = w (ascending): ring[m] = psi_{i-1-m}; U_{i-1-m, i} is multiplier m of row i-1-m
-  auto load_ut = [&](double (&e)[kFacMax + 1], int i) {
+  auto load_ut = [&](double (&e)[kFacMax + 1], int i) __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m < kFacMax; ++m) {
+      const int row = min(max(i - 1 - m, 0), N - 1);
+      e[m] = fac[size_t(P.fac_off[row] + min(m, max(P.fac_nm[row] - 1, 0))) * npairs];
+    }
+  };
+  auto step_ut = [&](int i, double2 x, const double (&e)[kFacMax + 1]) __attribute__((always_inline)) {
 #pragma unroll
     for (int m = 0; m < kFacMax; ++m) {
       const int row = i - 1 - m;
-      e[m] = (i < N && row >= 0 && m < P.fac_nm[row]) ? fac[size_t(P.fac_off[row] + m) * npairs] : 0.0;
+      const bool in = row >= 0 && m < P.fac_nm[max(row, 0)];
+      x = fma2(-(in ? e[m] : 0.0), ring[m], x);
     }
-    e[kFacMax] = 0.0;
-  };
-#pragma unroll
-  for (int d = 0; d < kFacPre; ++d) {
-    load_ut(fr[d], d);
-    pv[d] = (d < N) ? scr[size_t(d) * ncol + c] : zero2();
-  }
-#pragma unroll
-  for (int q = 0; q < kFacMax; ++q) ring[q] = zero2();
-  for (int i = 0; i < N; ++i) {
-    double2 x = pv[0];
-#pragma unroll
-    for (int m = 0; m < kFacMax; ++m) x = fma2(-fr[0][m], ring[m], x);
-#pragma unroll
-    for (int d = 0; d < kFacPre - 1; ++d) {
-      pv[d] = pv[d + 1];
-#pragma unroll
-      for (int q = 0; q <= kFacMax; ++q) fr[d][q] = fr[d + 1][q];
-    }
-    load_ut(fr[kFacPre - 1], i + kFacPre);
-    pv[kFacPre - 1] = (i + kFacPre < N) ? scr[size_t(i + kFacPre) * ncol + c] : zero2();
 #pragma unroll
     for (int m = kFacMax - 1; m > 0; --m) ring[m] = ring[m - 1];
     ring[0] = x;
     scr[size_t(i) * ncol + c] = x;
+  };
+#pragma unroll
+  for (int q = 0; q < kFacMax; ++q) ring[q] = zero2();
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    load_ut(fr[d], d);
+    pv[d] = scr[size_t(min(d, N - 1)) * ncol + c];
   }
+  for (int i0 = 0; i0 < nfull; i0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int i = i0 + d;
+      step_ut(i, pv[d], fr[d]);
+      load_ut(fr[d], i + D);
+      pv[d] = scr[size_t(min(i + D, N - 1)) * ncol + c];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (nfull + d < N) step_ut(nfull + d, pv[d], fr[d]);
 }
 
 // out (n2 rows of column c) = (add ? out : 0) + sum over the interior tau* rows i of G_g[i, :]^T scale psi_i
@@ -3593,35 +3612,45 @@ __device__ __forceinline__ void scatter_Gt(const DevPlan& P, int g, const double
 #pragma unroll
   for (int q = 0; q < kMaxW; ++q) acc[q] = zero2();
   int base = 0;
-  double2 pf[kPreMc];  // psi rows 1, 2, ... loaded ahead
-#pragma unroll
-  for (int d = 0; d < kPreMc; ++d) pf[d] = (1 + d < n2) ? scr[size_t(1 + d) * ncol + c] : zero2();
-  for (int i = 1; i < n2; ++i) {
-    const int lo = P.gs_lo[g * N + i];
-    while (base < lo) {
-      const size_t e = size_t(base) * ncol + c;
-      out[e] = add ? cadd(out[e], acc[0]) : acc[0];
-#pragma unroll
-      for (int q = 0; q < kMaxW - 1; ++q) acc[q] = acc[q + 1];
-      acc[kMaxW - 1] = zero2();
-      ++base;
-    }
-    const double2 psi = cscale(pf[0], scale);
-#pragma unroll
-    for (int d = 0; d < kPreMc - 1; ++d) pf[d] = pf[d + 1];
-    if (i + kPreMc < n2) pf[kPreMc - 1] = scr[size_t(i + kPreMc) * ncol + c];
-#pragma unroll
-    for (int q = 0; q < kMaxW; ++q)
-      if (lo + q < n2) acc[q] = fma2(P.gs_w[(size_t(g) * N + i) * kMaxW + q], psi, acc[q]);
-  }
-  while (base < n2) {
+  // the row that leaves the window next, read one row ahead (from scr, valid and unused, without add)
+  const double2* osrc = add ? out : scr;
+  double2 onext = osrc[c];
+  auto flush = [&]() __attribute__((always_inline)) {
     const size_t e = size_t(base) * ncol + c;
-    out[e] = add ? cadd(out[e], acc[0]) : acc[0];
+    const double2 o = add ? cadd(onext, acc[0]) : acc[0];
+    onext = osrc[size_t(min(base + 1, n2 - 1)) * ncol + c];
+    out[e] = o;
 #pragma unroll
     for (int q = 0; q < kMaxW - 1; ++q) acc[q] = acc[q + 1];
     acc[kMaxW - 1] = zero2();
     ++base;
+  };
+  auto step = [&](int i, double2 pr) __attribute__((always_inline)) {
+    const int lo = P.gs_lo[g * N + i];
+    while (base < lo) flush();
+    const double2 psi = cscale(pr, scale);
+#pragma unroll
+    for (int q = 0; q < kMaxW; ++q)
+      if (lo + q < n2) acc[q] = fma2(P.gs_w[(size_t(g) * N + i) * kMaxW + q], psi, acc[q]);
+  };
+  // psi rows 1 .. n2 - 1 through a ring like solve_At's: step t is row i = 1 + t, slot t mod kScatPre
+  constexpr int D = kScatPre;
+  const int nsteps = n2 - 1, nfull = nsteps - nsteps % D;
+  double2 pf[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) pf[d] = scr[size_t(min(1 + d, n2 - 1)) * ncol + c];
+  for (int t0 = 0; t0 < nfull; t0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int i = 1 + t0 + d;
+      step(i, pf[d]);
+      pf[d] = scr[size_t(min(i + D, n2 - 1)) * ncol + c];
+    }
   }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (nfull + d < nsteps) step(1 + nfull + d, pf[d]);
+  while (base < n2) flush();
 }
 
 // transpose of the m^d map (phi2, Omega2, <m>1, <m>3) -> (m1, m2, m3) coefficients (eqs. phi_poisson,
