@@ -35,17 +35,17 @@ namespace lmvd {
 constexpr int kMaxIn = 8;
 constexpr int kMaxOut = 10;
 constexpr int kNumAux = 4;   // physical-grid fields fixed during a substep
-constexpr int kPre = 3;      // rows loaded ahead by the sequential column sweeps
-// k_mc, at two waves per SIMD, hides the HBM latency only with its loads issued well ahead: row values
-// kPreMc rows ahead, factor rows kFacPre rows ahead, the input values of the emitted rows kValPre ahead.
-// A regular stream (one row per step of its sweep) is read through a ring whose slot d serves the steps
-// d (mod depth): the sweep runs in blocks of `depth` steps, unrolled, and each step consumes its slot,
-// then refills it with an unconditional load (row index clamped into range); consuming before the load
-// is issued lets the load take the slot's register. A ring that shifts its
-// entries instead (slot 0 consumed, slot d+1 copied to slot d) copies each load's destination one step
-// after issuing it, and the copy waits for the load, so such a ring hides one step of latency at most.
-// Sweep 2 (descending) reads kPreMc2 rows ahead; sweep 3 reads the rows and the factor rows kPreMc3 ahead.
-constexpr int kPreMc = 8, kFacPre = 3, kValPre = 4, kPreMc2 = 4, kPreMc3 = 4;
+// The column sweeps run one thread per column, a dependent chain of row steps each; at two waves per
+// SIMD they hide the HBM latency only with their loads issued well ahead of use. A regular stream (one
+// row per step of its sweep) is read through a ring whose slot d serves the steps d (mod depth): the
+// sweep runs in blocks of `depth` steps, unrolled, and each step consumes its slot, then refills it with
+// an unconditional load (row index clamped into range); consuming before the load is issued lets the
+// load take the slot's register. A ring that shifts its entries instead (slot 0 consumed, slot d+1
+// copied to slot d) copies each load's destination one step after issuing it, and the copy waits for
+// the load, so such a ring hides one step of latency at most. Depths: the m^c sweeps read kPreMc
+// (sweep 1), kPreMc2 (sweep 2) and kPreMc3 (sweep 3, rows and factor rows) steps ahead, the transposed
+// A(k) solve kFacPre.
+constexpr int kPreMc = 8, kFacPre = 3, kPreMc2 = 4, kPreMc3 = 4;
 constexpr int kThreads = 256;
 constexpr int kZMaxE = 12;    // elements per thread in the z-FFT kernels
 constexpr int kXSlots = 3;    // complex slots per thread per line set in k_xpass
@@ -2549,12 +2549,16 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
         for (int q = 0; q < LA; ++q) dst[q] = fac[(size_t(off) + nm + min(q, ns)) * npairs];
         dst[LA] = fac[(size_t(off) + nm + ns) * npairs];
       };
-      // input values of the next rows to emit (tau rows are emitted in ascending order, each once)
-      int enext = 0;
-      double2 vq[kValPre];
-#pragma unroll
-      for (int d = 0; d < kValPre; ++d) vq[d] = (!mean && d < n2) ? vals[size_t(d) * ncol + c] : zero2();
-      auto step = [&](int i, double2 x, const double (&fr)[LA + 1]) __attribute__((always_inline)) {
+      // operands of the next tau row to emit (rows are emitted in ascending order, each once), read one
+      // emission ahead: its input value and, for the final iterate, its m^d values
+      double2 ev = vals[c], e1 = zero2(), e2 = zero2(), e3 = zero2();
+      if (d1) {
+        e1 = d1[c];
+        e2 = d2[c];
+        e3 = d3[c];
+      }
+      // rh: rho_t coefficient of row i - 1 (final iterate only), read with the step's other rows
+      auto step = [&](int i, double2 x, const double (&fr)[LA + 1], double2 rh) __attribute__((always_inline)) {
         if (!mean) {
           const int ns = ns_(i);
 #pragma unroll
@@ -2570,7 +2574,7 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
             const size_t e = size_t(i - 1) * ncol + c;
             const double ds = ds_(i - 1);
             const double2 dc = make_double2(ds * (cw[0].x - cw[1].x), ds * (cw[0].y - cw[1].y));
-            mparc[e] = mean ? zero2() : cscale(times_i(cadd(rhoc[e], dc)), ik);
+            mparc[e] = mean ? zero2() : cscale(times_i(cadd(rh, dc)), ik);
           }
         }
         const int first = af_(i), cnt = ac_(i);
@@ -2585,8 +2589,7 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
           const size_t o = size_t(row) * ncol + c;
           double2 m1 = zero2(), m3 = zero2();
           if (!mean) {
-            // row == enext: its input value is vq[0]
-            const double2 sum = cadd(vq[0], f1);  // rho_t + F1 c
+            const double2 sum = cadd(ev, f1);  // rho_t + F1 c
             if (V3) {
               const double2 mp = cscale(times_i(sum), ik);
               m1 = cscale(mp, k1 * ik);
@@ -2594,15 +2597,20 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
             } else {
               m1 = cscale(sum, ik * ik);  // psi: m1 = i k1 psi, m3 = i k3 psi
             }
-#pragma unroll
-            for (int d = 0; d < kValPre - 1; ++d) vq[d] = vq[d + 1];
-            ++enext;
-            vq[kValPre - 1] = (enext + kValPre - 1 < n2) ? vals[size_t(enext + kValPre - 1) * ncol + c] : zero2();
           }
           if (d1) {
-            m1 = cadd(m1, d1[o]);
-            m2 = cadd(m2, d2[o]);
-            m3 = cadd(m3, d3[o]);
+            m1 = cadd(m1, e1);
+            m2 = cadd(m2, e2);
+            m3 = cadd(m3, e3);
+          }
+          {  // the next emitted row is row + 1
+            const size_t on = size_t(min(row + 1, n2 - 1)) * ncol + c;
+            ev = vals[on];
+            if (d1) {
+              e1 = d1[on];
+              e2 = d2[on];
+              e3 = d3[on];
+            }
           }
           V1[o] = m1;
           V2[o] = m2;
@@ -2610,26 +2618,28 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
         }
       };
       // slot d serves rows i = d (mod kPreMc3): the A(k) forward-sweep result and the factor row
-      double2 pf[kPreMc3];
+      double2 pf[kPreMc3], prh[kPreMc3];
       double fs[kPreMc3][LA + 1];
 #pragma unroll
       for (int d = 0; d < kPreMc3; ++d) {
         pf[d] = yt[size_t(min(d, N - 1)) * ncol + c];
         load_sub(fs[d], d);
+        prh[d] = c2 ? rhoc[size_t(max(d - 1, 0)) * ncol + c] : zero2();
       }
       const int nfull = N - N % kPreMc3;
       for (int i0 = 0; i0 < nfull; i0 += kPreMc3) {
 #pragma unroll
         for (int d = 0; d < kPreMc3; ++d) {
           const int i = i0 + d;
-          step(i, pf[d], fs[d]);
+          step(i, pf[d], fs[d], prh[d]);
           pf[d] = yt[size_t(min(i + kPreMc3, N - 1)) * ncol + c];
           load_sub(fs[d], i + kPreMc3);
+          if (c2) prh[d] = rhoc[size_t(min(i + kPreMc3 - 1, n2 - 1)) * ncol + c];
         }
       }
 #pragma unroll
       for (int d = 0; d < kPreMc3; ++d)
-        if (nfull + d < N) step(nfull + d, pf[d], fs[d]);
+        if (nfull + d < N) step(nfull + d, pf[d], fs[d], prh[d]);
     }
   }
 }
