@@ -2431,21 +2431,25 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
       for (int m = 0; m < UA; ++m) yr[m] = zero2();
       double2 cm = zero2();  // mean column: c_{j+1}
       yt[size_t(n2) * ncol + c] = zero2();  // Robin row n2: r = 0, nothing above it
-      // multipliers of the rows of the bottom-up sweep (rows n2-1, n2-2, ..., 0 in turn): fm[d] holds
-      // those of row inext - d, so each row's are loaded kFacPre - 1 rows before they are used
+      // multipliers of the next row of the bottom-up sweep (rows n2-1, n2-2, ..., 0 in turn), raw (the
+      // entries past the row's count are masked where they are used): the rows are emitted a variable
+      // number per step, so they are read one emission ahead, each row's as soon as the previous one's
+      // have been used
       int inext = n2 - 1;
-      double fm[kFacPre][UA];
-      auto load_mult = [&](double (&dst)[UA], int row) {
-        const int nm = row >= 0 ? nm_(row) : 0, off = row >= 0 ? of_(row) : 0;
+      double fm[UA];
+      auto load_mult = [&](int row) __attribute__((always_inline)) {
+        row = max(row, 0);
+        const int nm = nm_(row), off = of_(row);
 #pragma unroll
-        for (int m = 0; m < UA; ++m) dst[m] = (m < nm) ? fac[(size_t(off) + m) * npairs] : 0.0;
+        for (int m = 0; m < UA; ++m) fm[m] = fac[(size_t(off) + min(m, max(nm - 1, 0))) * npairs];
       };
+      auto mult = [&](int row, double2 r) __attribute__((always_inline)) {
+        const int nm = nm_(row);
 #pragma unroll
-      for (int d = 0; d < kFacPre; ++d) {
-#pragma unroll
-        for (int m = 0; m < UA; ++m) fm[d][m] = 0.0;
-        if (!mean) load_mult(fm[d], inext - d);
-      }
+        for (int m = 0; m < UA; ++m) r = fma2(-(m < nm ? fm[m] : 0.0), yr[m], r);
+        return r;
+      };
+      load_mult(inext);
       auto step = [&](int j, double2 y) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < LB; ++q) y = fma2(-U_(j, q), win[q], y);
@@ -2465,14 +2469,9 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
           double2 r = zero2();
 #pragma unroll
           for (int q = 0; q < kMaxW; ++q) r = fma2(-G_(i, q), win[q], r);
-#pragma unroll
-          for (int m = 0; m < UA; ++m) r = fma2(-fm[0][m], yr[m], r);
+          r = mult(i, r);
           --inext;
-#pragma unroll
-          for (int d = 0; d < kFacPre - 1; ++d)
-#pragma unroll
-            for (int m = 0; m < UA; ++m) fm[d][m] = fm[d + 1][m];
-          load_mult(fm[kFacPre - 1], inext - (kFacPre - 1));
+          load_mult(inext);
           yt[size_t(i) * ncol + c] = r;
 #pragma unroll
           for (int m = UA - 1; m > 0; --m) yr[m] = yr[m - 1];
@@ -2495,12 +2494,7 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
 #pragma unroll
       for (int d = 0; d < kPreMc2; ++d)
         if (nfull + d < n2) step(n2 - 1 - (nfull + d), pf[d]);
-      if (!mean) {  // Robin row 0 (inext == 0): r = 0
-        double2 r = zero2();
-#pragma unroll
-        for (int m = 0; m < UA; ++m) r = fma2(-fm[0][m], yr[m], r);
-        yt[c] = r;
-      }
+      if (!mean) yt[c] = mult(0, zero2());  // Robin row 0 (inext == 0): r = 0
     }
   }
   // 3. ascending back substitution and emission of the values at tau
