@@ -91,9 +91,10 @@ def test_evaluate_transpose(torch, deriv, star):
     assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n,n2", [(32, 33), (16, 14), (16, 15), (16, 16), (16, 19)])  # row counts mod 4
 @pytest.mark.parametrize("kind", [0, 1, 2])
-def test_project_transpose(torch, kind):
-    p = plan_of(32, 33)
+def test_project_transpose(torch, kind, n, n2):
+    p = plan_of(n, n2)
     w = p.w
     v = crand(torch, w.shape, 4)
     y = crand(torch, w.shape, 5)
@@ -137,7 +138,7 @@ def test_gradient_matches_central_differences(torch):
             assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (k, fd, an)
 
 
-@pytest.mark.parametrize("n,n2", [(32, 33), (48, 49)])
+@pytest.mark.parametrize("n,n2", [(32, 33), (48, 49), (16, 14), (16, 19)])
 def test_md_transpose(torch, n, n2):
     """<md(x), y> = <x, md^T(y)> for x = (phi2, Omega2, <m>1, <m>3) and y = (m1, m2 in B*, m3); and
     md^T against the oracle's m^d written as a dense real matrix on one column."""
@@ -174,7 +175,7 @@ def test_md_transpose(torch, n, n2):
     assert np.abs(tp2 - (g[:w.n2] + 1j * g[w.n2:])).max() < 1e-10 * np.abs(g).max()
 
 
-@pytest.mark.parametrize("n,n2", [(32, 33), (48, 49)])
+@pytest.mark.parametrize("n,n2", [(32, 33), (48, 49), (16, 14), (16, 19)])
 def test_mc_transpose(torch, n, n2):
     """<mc(rho_t), y> = <rho_t, mc^T(y)> (the (0,0) column with its plane-mean system included), and
     mc^T against the oracle's m^c written as a dense real matrix on one column and on the mean column."""

@@ -65,7 +65,7 @@ def test_transforms(torch, name, n, n2):
     assert rel(gotV, refV) < TOL
 
 
-@pytest.mark.parametrize("name,n,n2", [("small", None, None), ("small", 48, 49)])
+@pytest.mark.parametrize("name,n,n2", [("small", None, None), ("small", 48, 49), ("small", 16, 14), ("small", 16, 19)])
 def test_evaluate_and_project(torch, name, n, n2):
     w = workload(name, n=n, n2=n2)
     p = gplan(w)
@@ -281,6 +281,19 @@ def check_pair(got, ref, tol=TOL, rhs_tol=None, tols=None):
 def test_substep_small(torch, stage):
     w = workload("small")
     got, ref = run_pair(w, stage)
+    check_pair(got, ref)
+
+
+# Row counts of every residue mod 8: the column sweeps run their rows (n2, or n2 + 1 for the B* sweeps)
+# in unrolled blocks of 4 or 8 steps and then a tail of the remaining steps.
+ROWS = [12, 13, 14, 15, 16, 18, 19, 20, 22]
+
+
+@pytest.mark.parametrize("n2", ROWS)
+@pytest.mark.parametrize("stage", [0, 1])
+def test_substep_row_counts(torch, n2, stage):
+    w = workload("small", n=16, n2=n2)
+    got, ref = run_pair(w, stage, seed=40 + n2)
     check_pair(got, ref)
 
 

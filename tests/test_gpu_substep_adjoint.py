@@ -83,7 +83,7 @@ def flat(g):
 
 
 CASES = [(32, 33, 0, 0, 4, 0), (32, 33, 1, 0, 4, 0), (32, 33, 0, 1, 1, 0), (24, 25, 1, 0, 4, 7),
-         (24, 25, 0, 1, 4, 7)]
+         (24, 25, 0, 1, 4, 7), (16, 14, 1, 0, 4, 0), (16, 19, 0, 0, 4, 0)]  # the last two: other row counts
 
 
 @pytest.mark.parametrize("n,n2,stage,guess_mode,kf,plane_batch", CASES)
