@@ -317,12 +317,6 @@ static lmvd_status phys_to_coef_t(const AdjCtx& a, const double* physb, int kind
   axpy(a, u, coefb, 1.0, AM_ONE, true, star);
   return LMVD_OK;
 }
-// m^c coefficients from rho_t coefficients (eqs. COM_fourier, CF_fourier, mc_recon, mc_mean)
-static void mc_of(const AdjCtx& a, const double2* rhot, double2* m1, double2* m2, double2* m3) {
-  double2* mpar = a.c.at<double2>(a.c.p->ws.off_mpar);
-  solveA<1>(a.c, rhot, nullptr, nullptr, nullptr, m2, mpar, nullptr);
-  hipLaunchKernelGGL(k_mc13, a.gS, dim3(kThreads), 0, a.c.s, a.c.p->D, mpar, m1, m3);
-}
 static void mc_t(const AdjCtx& a, const double2* m1b, const double2* m2b, const double2* m3b, double2* rhotb) {
   double2* scr = a.c.at<double2>(a.c.p->ws.off_yt);
   hipLaunchKernelGGL(k_mc_t, a.gC, dim3(kThreads), 0, a.c.s, a.c.p->D, m1b, m2b, m3b, rhotb, scr);
@@ -361,8 +355,20 @@ static lmvd_status run_substep_adjoint(lmvd_plan_s* p, const lmvd_substep_args* 
   };
 
   // ---- forward recomputation ----
-  // m^d (eqs. phi_poisson, md_recon)
-  solveA<0>(a.c, cS(fa->phi2), cS(fa->omega2), fa->m1bar, fa->m3bar, md2, md1, md3);
+  // m^d coefficients (eqs. phi_poisson, md_recon): the substep's own m^d job with the plan's factors, its
+  // values at tau written to scratch, where the substep runs it; else the solve with the LU formed per call
+  if (H.p == 8) {
+    const int nth = 2 * H.nl * ((H.nn + 1) / 2);
+    const MdArgs margs{cS(fa->phi2), cS(fa->omega2), fa->m1bar, fa->m3bar, a.c.at<double2>(p->ws.off_yt),
+                       t2, t3, t4, md2, md1, md3};
+    const dim3 gm((unsigned(nth) + kThreads - 1) / kThreads, 1);  // job 0 only
+    if (p->fac_la == 7)
+      col<JobPrologue<7, 7, 8>>(a.c, gm, 0, {1, margs, ValuesZArgs{}, GuessArgs{}});
+    else
+      col<JobPrologue<8, 8, 8>>(a.c, gm, 0, {1, margs, ValuesZArgs{}, GuessArgs{}});
+  } else {
+    solveA<0>(a.c, cS(fa->phi2), cS(fa->omega2), fa->m1bar, fa->m3bar, md2, md1, md3);
+  }
   // z and its derivatives on the grid
   ADJ_OK(to_phys(a, z, EV_E0, zp));
   ADJ_OK(to_phys(a, z, EV_E0, gz[0], MU_IK1));
@@ -426,10 +432,15 @@ static lmvd_status run_substep_adjoint(lmvd_plan_s* p, const lmvd_substep_args* 
     axpy(a, rz, ztn);
     std::swap(ztc, ztn);
   }
-  // final m^c (coefficients) and m = m^d + m^c on the grid
+  // final m^c coefficients (eqs. COM_fourier, CF_fourier, mc_recon, mc_mean) by the substep's fused kernel in
+  // its final-iterate form (rho_t coefficients, c and m_par; its values at tau go to scratch), then
+  // m1 = (k1/k) m_par, m3 = (k3/k) m_par; and m = m^d + m^c on the grid
   ADJ_OK(rhot_vals(ztc, ztp(kf)));
-  proj(a.c, 0, t1, rhot);
-  mc_of(a, rhot, mc1, mc2, mc3);
+  {
+    double2* mpar = a.c.at<double2>(p->ws.off_mpar);
+    launch_mc(a.c, t1, nullptr, nullptr, nullptr, t2, t3, t4, rhot, mc2, mpar);
+    hipLaunchKernelGGL(k_mc13, a.gS, dim3(kThreads), 0, s, p->D, mpar, mc1, mc3);
+  }
   double2 *m1 = a.S(L.m1), *m2 = a.S(L.m2), *m3 = a.S(L.m3);
   axpy(a, md1, m1, 1.0, AM_ONE, false);
   axpy(a, mc1, m1);
