@@ -79,6 +79,8 @@ struct DevPlan {
   cptr<double> lu_l;      // [3][n2][kMaxBand]
   cptr<double> lu_u;      // [3][n2][kMaxBand+1]
   cptr<double> lu_uinv;   // [3][n2]
+  cptr<double> lu_ut;     // [3][n2][kMaxBand+1] row i: U_{i-1-q, i} (q < kMaxBand, 0 above row 0), then 1/U_ii
+  cptr<double> lu_lt;     // [3][n2][kMaxBand]   row i: L_{i+1+m, i} (0 below the last row)
   const double* k1;        // [nl]
   const double* k3;        // [nn]
   cptr<int> emit_first;   // [n2] first E0 row whose band starts at row i
@@ -3445,28 +3447,27 @@ __global__ void __launch_bounds__(kThreads) k_project_t(DevPlan P, int kind, Pro
   const double2* in = J.in[blockIdx.y];
   double2* out = J.out[blockIdx.y];
   const int n2 = P.n2;
-  const auto L = P.lu_l + size_t(kind) * n2 * kMaxBand;
-  const auto U = P.lu_u + size_t(kind) * n2 * (kMaxBand + 1);
-  const auto Ui = P.lu_uinv + size_t(kind) * n2;
+  // the factors by columns: row i holds the band entries step i reads (zero outside the matrix, where
+  // the ring holds zeros as well, so every term can be formed)
+  const auto UT = P.lu_ut + size_t(kind) * n2 * (kMaxBand + 1);
+  const auto LT = P.lu_lt + size_t(kind) * n2 * kMaxBand;
   const int nfull = n2 - n2 % kProjTPre;  // steps run in whole blocks; the rest from the ring alone
   double2 ring[kMaxBand];
   double2 pv[kProjTPre];  // slot d: the next row of the sweep whose index is d (mod kProjTPre) from its start
-  // U^T z = y: ring[q] = z_{i-1-q}; U_{i-1-q, i} is entry q+1 of row i-1-q
+  // U^T z = y: ring[q] = z_{i-1-q}; U_{i-1-q, i} is entry q of row i of UT, 1/U_ii its last
   auto up = [&](int i, double2 b) {
 #pragma unroll
-    for (int q = 0; q < kMaxBand; ++q)
-      if (i - 1 - q >= 0) b = fma2(-U[(i - 1 - q) * (kMaxBand + 1) + q + 1], ring[q], b);
-    const double2 z = cscale(b, Ui[i]);
+    for (int q = 0; q < kMaxBand; ++q) b = fma2(-UT[i * (kMaxBand + 1) + q], ring[q], b);
+    const double2 z = cscale(b, UT[i * (kMaxBand + 1) + kMaxBand]);
 #pragma unroll
     for (int q = kMaxBand - 1; q > 0; --q) ring[q] = ring[q - 1];
     ring[0] = z;
     out[size_t(i) * ncol + c] = z;
   };
-  // L^T x = z: ring[m] = x_{i+1+m}; L_{i+1+m, i} is multiplier m of row i+1+m
+  // L^T x = z: ring[m] = x_{i+1+m}; L_{i+1+m, i} is entry m of row i of LT
   auto down = [&](int i, double2 x) {
 #pragma unroll
-    for (int m = 0; m < kMaxBand; ++m)
-      if (i + 1 + m < n2) x = fma2(-L[(i + 1 + m) * kMaxBand + m], ring[m], x);
+    for (int m = 0; m < kMaxBand; ++m) x = fma2(-LT[i * kMaxBand + m], ring[m], x);
 #pragma unroll
     for (int m = kMaxBand - 1; m > 0; --m) ring[m] = ring[m - 1];
     ring[0] = x;
@@ -4031,6 +4032,24 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   UP_TABLE(L, D.lu_l);
   UP_TABLE(U, D.lu_u);
   UP_TABLE(Ui, D.lu_uinv);
+  // the same factors by columns, for the transposed sweeps: what a step of U^T z = y or L^T x = z reads
+  // is one contiguous row (one scalar-load batch per step instead of one load per band row)
+  {
+    const int n2 = H.n2;
+    std::vector<double> UT(size_t(3) * n2 * (kMaxBand + 1), 0.0), LT(size_t(3) * n2 * kMaxBand, 0.0);
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < n2; ++i) {
+        double* ut = &UT[(size_t(k) * n2 + i) * (kMaxBand + 1)];
+        double* lt = &LT[(size_t(k) * n2 + i) * kMaxBand];
+        for (int q = 0; q < kMaxBand; ++q) {
+          if (i - 1 - q >= 0) ut[q] = U[(size_t(k) * n2 + i - 1 - q) * (kMaxBand + 1) + q + 1];
+          if (i + 1 + q < n2) lt[q] = L[(size_t(k) * n2 + i + 1 + q) * kMaxBand + q];
+        }
+        ut[kMaxBand] = Ui[size_t(k) * n2 + i];
+      }
+    UP_TABLE(UT, D.lu_ut);
+    UP_TABLE(LT, D.lu_lt);
+  }
   UP_OR_FAIL(H.k1, &D.k1);
   UP_OR_FAIL(H.k3, &D.k3);
   UP_TABLE(H.emit_first, D.emit_first);
