@@ -94,6 +94,11 @@ struct DevPlan {
   cptr<int> fac_nm;       // [n2+1] multipliers of row i (rows i+1 .. i+nm)
   cptr<int> fac_ns;       // [n2+1] entries of row i left of its diagonal
   cptr<int> fac_off;      // [n2+1] first slot of row i
+  // by columns, for the transposed A(k) solve (slot -1: no entry): step i of L^T w = b reads the left
+  // entry q of row i+1+q (q < kFacMax) and then the inverse pivot of row i; step i of U^T psi = w reads
+  // multiplier m of row i-1-m
+  cptr<int> fac_lt;       // [n2+1][kFacMax+1]
+  cptr<int> fac_ut;       // [n2+1][kFacMax]
   FftDev fz, fx;
   const double2* xtw;      // [hx] exp(-2 pi i k / m1)
   cptr<double> wall_w;    // weights of the wall rows of E0 P_N (interior values -> wall values)
@@ -3524,23 +3529,17 @@ __device__ __forceinline__ void solve_At(const DevPlan& P, const double* fac, in
   double fr[D][kFacMax + 1];
   double2 pv[D];
   double2 ring[kFacMax];
-  // L^T w = b (descending): ring[q] = w_{i+1+q}; L_{i+1+q, i} is left entry q of row i+1+q
+  // L^T w = b (descending): ring[q] = w_{i+1+q}; L_{i+1+q, i} is left entry q of row i+1+q, at the slot
+  // the plan's column table gives (-1: none; slot 0 is read instead and masked at use)
   auto load_lt = [&](double (&e)[kFacMax + 1], int i) __attribute__((always_inline)) {
-    i = max(i, 0);
+    const auto sl = P.fac_lt + size_t(max(i, 0)) * (kFacMax + 1);
 #pragma unroll
-    for (int q = 0; q < kFacMax; ++q) {
-      const int row = min(i + 1 + q, N - 1);
-      e[q] = fac[size_t(P.fac_off[row] + P.fac_nm[row] + min(q, P.fac_ns[row])) * npairs];
-    }
-    e[kFacMax] = fac[size_t(P.fac_off[i] + P.fac_nm[i] + P.fac_ns[i]) * npairs];
+    for (int q = 0; q <= kFacMax; ++q) e[q] = fac[size_t(max(sl[q], 0)) * npairs];
   };
   auto step_lt = [&](int i, double2 b, const double (&e)[kFacMax + 1]) __attribute__((always_inline)) {
+    const auto sl = P.fac_lt + size_t(i) * (kFacMax + 1);
 #pragma unroll
-    for (int q = 0; q < kFacMax; ++q) {
-      const int row = i + 1 + q;
-      const bool in = row < N && q < P.fac_ns[min(row, N - 1)];
-      b = fma2(-(in ? e[q] : 0.0), ring[q], b);
-    }
+    for (int q = 0; q < kFacMax; ++q) b = fma2(-(sl[q] >= 0 ? e[q] : 0.0), ring[q], b);
     const double2 w = cscale(b, e[kFacMax]);
 #pragma unroll
     for (int q = kFacMax - 1; q > 0; --q) ring[q] = ring[q - 1];
@@ -3566,21 +3565,17 @@ __device__ __forceinline__ void solve_At(const DevPlan& P, const double* fac, in
 #pragma unroll
   for (int d = 0; d < D; ++d)
     if (nfull + d < N) step_lt(N - 1 - (nfull + d), pv[d], fr[d]);
-  // U^T psi = w (ascending): ring[m] = psi_{i-1-m}; U_{i-1-m, i} is multiplier m of row i-1-m
+  // U^T psi = w (ascending): ring[m] = psi_{i-1-m}; U_{i-1-m, i} is multiplier m of row i-1-m, at the
+  // slot of the plan's column table
   auto load_ut = [&](double (&e)[kFacMax + 1], int i) __attribute__((always_inline)) {
+    const auto sl = P.fac_ut + size_t(min(i, N - 1)) * kFacMax;
 #pragma unroll
-    for (int m = 0; m < kFacMax; ++m) {
-      const int row = min(max(i - 1 - m, 0), N - 1);
-      e[m] = fac[size_t(P.fac_off[row] + min(m, max(P.fac_nm[row] - 1, 0))) * npairs];
-    }
+    for (int m = 0; m < kFacMax; ++m) e[m] = fac[size_t(max(sl[m], 0)) * npairs];
   };
   auto step_ut = [&](int i, double2 x, const double (&e)[kFacMax + 1]) __attribute__((always_inline)) {
+    const auto sl = P.fac_ut + size_t(i) * kFacMax;
 #pragma unroll
-    for (int m = 0; m < kFacMax; ++m) {
-      const int row = i - 1 - m;
-      const bool in = row >= 0 && m < P.fac_nm[max(row, 0)];
-      x = fma2(-(in ? e[m] : 0.0), ring[m], x);
-    }
+    for (int m = 0; m < kFacMax; ++m) x = fma2(-(sl[m] >= 0 ? e[m] : 0.0), ring[m], x);
 #pragma unroll
     for (int m = kFacMax - 1; m > 0; --m) ring[m] = ring[m - 1];
     ring[0] = x;
@@ -4062,6 +4057,21 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   UP_TABLE(H.fac_nm, D.fac_nm);
   UP_TABLE(H.fac_ns, D.fac_ns);
   UP_TABLE(H.fac_off, D.fac_off);
+  {
+    const int N = H.n2 + 1;
+    std::vector<int32_t> lt(size_t(N) * (kFacMax + 1), -1), ut(size_t(N) * kFacMax, -1);
+    for (int i = 0; i < N; ++i) {
+      for (int q = 0; q < kFacMax; ++q) {
+        const int r = i + 1 + q;
+        if (r < N && q < H.fac_ns[r]) lt[size_t(i) * (kFacMax + 1) + q] = H.fac_off[r] + H.fac_nm[r] + q;
+        const int u = i - 1 - q;
+        if (u >= 0 && q < H.fac_nm[u]) ut[size_t(i) * kFacMax + q] = H.fac_off[u] + q;
+      }
+      lt[size_t(i) * (kFacMax + 1) + kFacMax] = H.fac_off[i] + H.fac_nm[i] + H.fac_ns[i];
+    }
+    UP_TABLE(lt, D.fac_lt);
+    UP_TABLE(ut, D.fac_ut);
+  }
   UP_TABLE(H.wall_w, D.wall_w);
   D.wall_k0 = H.wall_k0;
   D.wall_k1 = H.wall_k1;
