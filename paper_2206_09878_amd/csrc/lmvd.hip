@@ -1632,17 +1632,28 @@ __device__ __forceinline__ void proj_body(const DevPlan& P, int c, int kind, con
   double2 ring[kMaxBand];
 #pragma unroll
   for (int m = 0; m < kMaxBand; ++m) ring[m] = zero2();
+  // band rows of the next step, read while the current step runs (scalar loads, one row ahead)
+  double cnx[kMaxBand + 1];
+  auto load_l = [&](int i) __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) cnx[m] = L[min(i, n2 - 1) * kMaxBand + m];
+  };
   // ascending L sweep; slot d of pv holds the next input row i = d (mod D)
   auto fwd = [&](int i, double2 b) __attribute__((always_inline)) {
+    double lc[kMaxBand];
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) lc[m] = cnx[m];
+    load_l(i + 1);
     if (kind != 0 && (i == 0 || i == n2 - 1)) b = zero2();
 #pragma unroll
-    for (int m = 0; m < kMaxBand; ++m) b = fma2(-L[i * kMaxBand + m], ring[m], b);
+    for (int m = 0; m < kMaxBand; ++m) b = fma2(-lc[m], ring[m], b);
     out[size_t(i) * ncol + c] = b;
 #pragma unroll
     for (int m = kMaxBand - 1; m > 0; --m) ring[m] = ring[m - 1];
     ring[0] = b;
   };
   {
+    load_l(0);
     double2 pv[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) pv[d] = in[size_t(min(d, n2 - 1)) * ncol + c];
@@ -1679,11 +1690,21 @@ __device__ __forceinline__ void proj_body(const DevPlan& P, int c, int kind, con
       r.zp = ztp[e];
     }
   };
+  auto load_u = [&](int i) __attribute__((always_inline)) {
+    i = max(i, 0);
+#pragma unroll
+    for (int q = 0; q < kMaxBand; ++q) cnx[q] = U[i * (kMaxBand + 1) + q + 1];
+    cnx[kMaxBand] = Ui[i];
+  };
   auto bwd = [&](int i, const Rows& r) __attribute__((always_inline)) {
+    double uc[kMaxBand + 1];
+#pragma unroll
+    for (int q = 0; q <= kMaxBand; ++q) uc[q] = cnx[q];
+    load_u(i - 1);
     double2 y = r.y;
 #pragma unroll
-    for (int q = 0; q < kMaxBand; ++q) y = fma2(-U[i * (kMaxBand + 1) + q + 1], ring[q], y);
-    const double2 x = cscale(y, Ui[i]);
+    for (int q = 0; q < kMaxBand; ++q) y = fma2(-uc[q], ring[q], y);
+    const double2 x = cscale(y, uc[kMaxBand]);
 #pragma unroll
     for (int q = kMaxBand - 1; q > 0; --q) ring[q] = ring[q - 1];
     ring[0] = x;
@@ -1724,6 +1745,7 @@ __device__ __forceinline__ void proj_body(const DevPlan& P, int c, int kind, con
     }
   };
   {
+    load_u(n2 - 1);
     Rows pr[D];  // slot d: step t = d (mod D) of the sweep, row i = n2 - 1 - t
 #pragma unroll
     for (int d = 0; d < D; ++d) load(pr[d], max(n2 - 1 - d, 0));
@@ -2368,9 +2390,19 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
     double2 ring[LB];
 #pragma unroll
     for (int m = 0; m < LB; ++m) ring[m] = zero2();
-    auto step = [&](int i, double2 b) __attribute__((always_inline)) {
+    double lnx[LB];  // band row of the next step, read one row ahead (scalar loads)
+    auto load_l = [&](int i) __attribute__((always_inline)) {
 #pragma unroll
-      for (int m = 0; m < LB; ++m) b = fma2(-P.lu_l[i * kMaxBand + m], ring[m], b);
+      for (int m = 0; m < LB; ++m) lnx[m] = P.lu_l[min(i, n2 - 1) * kMaxBand + m];
+    };
+    load_l(0);
+    auto step = [&](int i, double2 b) __attribute__((always_inline)) {
+      double lc[LB];
+#pragma unroll
+      for (int m = 0; m < LB; ++m) lc[m] = lnx[m];
+      load_l(i + 1);
+#pragma unroll
+      for (int m = 0; m < LB; ++m) b = fma2(-lc[m], ring[m], b);
       yp[size_t(i) * ncol + c] = b;
 #pragma unroll
       for (int m = LB - 1; m > 0; --m) ring[m] = ring[m - 1];
@@ -2856,13 +2888,22 @@ __device__ __forceinline__ void rhs_fluct_body(const DevPlan& P, const unsigned 
   for (int m = 0; m < kMaxBand; ++m) rp[m] = ro[m] = zero2();
   // ascending L sweep over the interior rows (Dirichlet end rows zero); rows come through rings of D
   // slots, slot d serving the steps i = d (mod D), each consumed before its refill is issued
+  // the band row of the next step is read while the current step runs (scalar loads, one row ahead)
+  double lnx[kMaxBand];
+  auto load_l = [&](int i) __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) lnx[m] = L[min(i, n2 - 1) * kMaxBand + m];
+  };
   auto fwd = [&](int i, double2 bp, double2 bo) __attribute__((always_inline)) {
+    double lc[kMaxBand];
+#pragma unroll
+    for (int m = 0; m < kMaxBand; ++m) lc[m] = lnx[m];
+    load_l(i + 1);
     if (i == 0 || i == n2 - 1) bp = bo = zero2();
 #pragma unroll
     for (int m = 0; m < kMaxBand; ++m) {
-      const double lm = L[i * kMaxBand + m];
-      bp = fma2(-lm, rp[m], bp);
-      bo = fma2(-lm, ro[m], bo);
+      bp = fma2(-lc[m], rp[m], bp);
+      bo = fma2(-lc[m], ro[m], bo);
     }
     yphi[size_t(i) * ncol + c] = bp;
     yom[size_t(i) * ncol + c] = bo;
@@ -2875,6 +2916,7 @@ __device__ __forceinline__ void rhs_fluct_body(const DevPlan& P, const unsigned 
     ro[0] = bo;
   };
   {
+    load_l(0);
     double2 pp[D], po[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -2915,16 +2957,26 @@ __device__ __forceinline__ void rhs_fluct_body(const DevPlan& P, const unsigned 
     r.pp = ppr[e];
     r.op = opr[e];
   };
+  double unx[kMaxBand + 1];  // U row and inverse pivot of the next step, one row ahead
+  auto load_u = [&](int i) __attribute__((always_inline)) {
+    i = max(i, 0);
+#pragma unroll
+    for (int q = 0; q < kMaxBand; ++q) unx[q] = U[i * (kMaxBand + 1) + q + 1];
+    unx[kMaxBand] = Ui[i];
+  };
   auto bwd = [&](int i, const Rows& r) __attribute__((always_inline)) {
     const size_t e = size_t(i) * ncol + c;
+    double uc[kMaxBand + 1];
+#pragma unroll
+    for (int q = 0; q <= kMaxBand; ++q) uc[q] = unx[q];
+    load_u(i - 1);
     double2 yp = r.yp, yo = r.yo;
 #pragma unroll
     for (int q = 0; q < kMaxBand; ++q) {
-      const double u = U[i * (kMaxBand + 1) + q + 1];
-      yp = fma2(-u, rp[q], yp);
-      yo = fma2(-u, ro[q], yo);
+      yp = fma2(-uc[q], rp[q], yp);
+      yo = fma2(-uc[q], ro[q], yo);
     }
-    const double2 xp = cscale(yp, Ui[i]), xo = cscale(yo, Ui[i]);
+    const double2 xp = cscale(yp, uc[kMaxBand]), xo = cscale(yo, uc[kMaxBand]);
 #pragma unroll
     for (int q = kMaxBand - 1; q > 0; --q) {
       rp[q] = rp[q - 1];
@@ -2944,6 +2996,7 @@ __device__ __forceinline__ void rhs_fluct_body(const DevPlan& P, const unsigned 
     }
   };
   {
+    load_u(n2 - 1);
     Rows pr[D];  // slot d: step t = d (mod D), row i = n2 - 1 - t
 #pragma unroll
     for (int d = 0; d < D; ++d) load(pr[d], max(n2 - 1 - d, 0));
