@@ -85,8 +85,7 @@ struct DevPlan {
   const double* k3;        // [nn]
   cptr<int> emit_first;   // [n2] first E0 row whose band starts at row i
   cptr<int> emit_cnt;     // [n2] number of such rows
-  cptr<int> g1e_first;    // [n2] first interior tau* row whose G1 band starts at B row j
-  cptr<int> g1e_cnt;      // [n2]
+  cptr<int> g1e_cnt;      // [n2] interior tau* rows whose G1 band starts at B row j (emitted in descending row order)
   cptr<int> asc_first;    // [n2+1] first tau row whose last F0/F1 column is B* row j
   cptr<int> asc_cnt;      // [n2+1]
   cptr<double> asc_w;     // [2][n2][kMaxW] F0, F1 weights of c_{last - q}
@@ -2345,12 +2344,12 @@ __global__ void __launch_bounds__(kThreads) k_factor_ul(DevPlan P, double* __res
 // c2 = c, mparc = (i/k)(rho_t + D* c) and rhoc = rho_t are written.
 // LDS layout of the tables a sweep of k_mc reads (doubles, then ints), per
 // phase; phase 2: U rows of the interpolation (LB), 1/pivots, G1 rows,
-// G1 emission starts and counts, factor row counts and offsets; phase 3:
+// G1 emission counts, factor row counts and offsets; phase 3:
 // F0/F1 emission weights, emission starts and counts, factor row structure.
 struct McLds {
   int n2, N, lb;
   __host__ __device__ int p2_doubles() const { return n2 * lb + n2 + N * kMaxW + n2; }
-  __host__ __device__ int p2_ints() const { return 2 * n2 + 2 * N; }
+  __host__ __device__ int p2_ints() const { return n2 + 2 * N; }
   __host__ __device__ int p3_doubles() const { return 2 * n2 * kMaxW + n2; }
   __host__ __device__ int p3_ints() const { return 2 * N + 3 * N; }
   __host__ __device__ size_t bytes() const {
@@ -2430,8 +2429,7 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
     double* sui = su + n2 * LB;         // [n2]
     double* sg = sui + n2;              // [N][kMaxW] G1 rows
     double* sds = sg + N * kMaxW;       // [n2] dstar
-    int* sgf = reinterpret_cast<int*>(sds + n2);  // [n2] G1 emission starts
-    int* sgc = sgf + n2;                // [n2]
+    int* sgc = reinterpret_cast<int*>(sds + n2);  // [n2] G1 emission counts
     int* snm = sgc + n2;                // [N]
     int* sof = snm + N;                 // [N]
     if constexpr (STAGE) {
@@ -2439,7 +2437,6 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
       for (int e = threadIdx.x; e < n2; e += blockDim.x) {
         sui[e] = P.lu_uinv[e];
         sds[e] = P.dstar[e];
-        sgf[e] = P.g1e_first[e];
         sgc[e] = P.g1e_cnt[e];
       }
       for (int e = threadIdx.x; e < N * kMaxW; e += blockDim.x) sg[e] = P.gs_w[size_t(N) * kMaxW + e];
@@ -2457,7 +2454,6 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
       if constexpr (STAGE) return sg[i * kMaxW + q]; else return P.gs_w[(size_t(N) + i) * kMaxW + q];
     };
     auto ds_ = [&](int j) -> double { if constexpr (STAGE) return sds[j]; else return P.dstar[j]; };
-    auto gf_ = [&](int j) -> int { if constexpr (STAGE) return sgf[j]; else return P.g1e_first[j]; };
     auto gc_ = [&](int j) -> int { if constexpr (STAGE) return sgc[j]; else return P.g1e_cnt[j]; };
     auto nm_ = [&](int r) -> int { if constexpr (STAGE) return snm[r]; else return P.fac_nm[r]; };
     auto of_ = [&](int r) -> int { if constexpr (STAGE) return sof[r]; else return P.fac_off[r]; };
@@ -2489,10 +2485,33 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
         return r;
       };
       load_mult(inext);
-      auto step = [&](int j, double2 y) __attribute__((always_inline)) {
+      // the next step's U row, inverse pivot and emission count, and the G1 weights of the next row to
+      // emit, are read while the current step (emission) runs: the table reads are not on the chain
+      double nu[LB + 1], ng[kMaxW];
+      int ncnt;
+      auto load_row = [&](int j) __attribute__((always_inline)) {
+        j = max(j, 0);
 #pragma unroll
-        for (int q = 0; q < LB; ++q) y = fma2(-U_(j, q), win[q], y);
-        const double2 x = cscale(y, Ui_(j));
+        for (int q = 0; q < LB; ++q) nu[q] = U_(j, q);
+        nu[LB] = Ui_(j);
+        ncnt = gc_(j);
+      };
+      auto load_g = [&](int i) __attribute__((always_inline)) {
+        i = max(i, 0);
+#pragma unroll
+        for (int q = 0; q < kMaxW; ++q) ng[q] = G_(i, q);
+      };
+      load_row(n2 - 1);
+      load_g(n2 - 1);
+      auto step = [&](int j, double2 y) __attribute__((always_inline)) {
+        double uc[LB + 1];
+#pragma unroll
+        for (int q = 0; q <= LB; ++q) uc[q] = nu[q];
+        const int cnt = ncnt;
+        load_row(j - 1);
+#pragma unroll
+        for (int q = 0; q < LB; ++q) y = fma2(-uc[q], win[q], y);
+        const double2 x = cscale(y, uc[LB]);
 #pragma unroll
         for (int q = kMaxW - 1; q > 0; --q) win[q] = win[q - 1];
         win[0] = x;
@@ -2502,12 +2521,16 @@ __device__ __forceinline__ void mc_body(const DevPlan& P, const unsigned bx, con
           yt[size_t(j) * ncol + c] = cm;
           return;
         }
-        const int first = gf_(j), cnt = gc_(j);
-        for (int e = cnt - 1; e >= 0; --e) {
-          const int i = first + e;  // == inext
+        // rows are emitted in descending order, each once: the row is inext
+        for (int e = 0; e < cnt; ++e) {
+          const int i = inext;
+          double gw[kMaxW];
+#pragma unroll
+          for (int q = 0; q < kMaxW; ++q) gw[q] = ng[q];
+          load_g(i - 1);
           double2 r = zero2();
 #pragma unroll
-          for (int q = 0; q < kMaxW; ++q) r = fma2(-G_(i, q), win[q], r);
+          for (int q = 0; q < kMaxW; ++q) r = fma2(-gw[q], win[q], r);
           r = mult(i, r);
           --inext;
           load_mult(inext);
@@ -4102,7 +4125,6 @@ static lmvd_status create_plan(const lmvd_config* cfg, lmvd_plan* out, std::stri
   UP_OR_FAIL(H.k3, &D.k3);
   UP_TABLE(H.emit_first, D.emit_first);
   UP_TABLE(H.emit_cnt, D.emit_cnt);
-  UP_TABLE(H.g1e_first, D.g1e_first);
   UP_TABLE(H.g1e_cnt, D.g1e_cnt);
   UP_TABLE(H.asc_first, D.asc_first);
   UP_TABLE(H.asc_cnt, D.asc_cnt);
