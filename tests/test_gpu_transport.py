@@ -11,6 +11,7 @@ FFT-rounding spread where that is larger), on:
   * the register x-pass with plane batches (z transformed again);
   * the generic x-pass (M = 36) with ragged plane batches;
   * a mid size (64 x 65 x 64, M = 96);
+  * row counts n2 = 14 and 19 (16 x n2 x 16), whose unrolled column sweeps end in longer tails;
   * each law alone (only mu(z), only rho D(z), both forms of rho D);
   * the grouped HIP graph of two such instances, equal to eager substeps bit
     for bit.
@@ -66,6 +67,11 @@ def test_variable_transport_generic_path_ragged_batches(torch):
 
 def test_variable_transport_mid_size(torch):
     check(with_laws(workload("mixing128", n=64, n2=65)), 0, seed=24)
+
+
+@pytest.mark.parametrize("n2,stage", [(14, 1), (19, 0)])
+def test_variable_transport_row_counts(torch, n2, stage):
+    check(with_laws(workload("small", n=16, n2=n2)), stage, seed=25 + n2)
 
 
 @pytest.mark.parametrize("mu,rhod,form", [(True, False, 0), (False, True, 0), (False, True, 1)])
