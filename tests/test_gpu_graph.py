@@ -10,6 +10,8 @@ through the C ABI.
     one-branch-per-instance form of the graph, with the same bit-for-bit result.
   * The entry point rejects diagnostic outputs and a period that breaks the
     history ring.
+  * Instances at row counts 14, 19 and 22 (other tails of the unrolled column
+    sweeps) are bit for bit equal to their eager substeps as well.
 """
 import ctypes
 
@@ -61,6 +63,30 @@ def test_graph_replays_equal_eager_substeps(torch):
                 assert torch.equal(ta, tb), (launch, i)
         # the state keeps moving: the next launch starts from a new state
         assert np.isfinite(host(A[0].z)).all()
+
+
+def test_graph_row_counts(torch):
+    """Instances whose row counts (n2 = 14, 19, 22) end the unrolled column sweeps in other tails than
+    the batch's n2 = 2^k + 1, grouped in one graph, equal the same substeps run one by one, bit for bit."""
+    from paper_2206_09878_amd.lmvd import GraphBatch, Plan, Stepper
+    from paper_2206_09878_amd.workloads import workload
+    ws = [workload("small", n=16, n2=n2) for n2 in (14, 19, 22)]
+
+    def make():
+        return [Stepper(Plan(w), make_inputs(w, seed=60 + w.n2, stage=0), stage=0) for w in ws]
+
+    A, B = make(), make()
+    g = GraphBatch(A, nsub=4)
+    print("row-count instances:", [(w.n1, w.n2, w.n3) for w in ws], "grouped", g.grouped, flush=True)
+    for launch in range(2):
+        for s in B:
+            for _ in range(4):
+                s.substep()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(A, B)):
+            for ta, tb in zip(state_tensors(a), state_tensors(b)):
+                assert torch.equal(ta, tb), (launch, i)
 
 
 def test_graph_eight_substeps_per_launch(torch):
